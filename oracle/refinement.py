@@ -1,0 +1,345 @@
+"""Dense FP64 oracle of iterative refinement, localized inverse factorization
+and recursive inverse Cholesky, with the paper's leaf-block truncation.
+
+Test infrastructure only (see the package docstring).
+
+Conventions
+-----------
+* Matrices are real symmetric; the conjugate transpose of the paper is the
+  plain transpose here.
+* Block grid: b x b blocks from the matrix origin; a sub-problem always starts
+  on a block boundary, so its blocks are blocks of the global grid.  The last
+  block row/column may be partial.
+* Truncation (Sec. 5): after every matrix-matrix product and after every leaf
+  (base) factorization, blocks whose Frobenius norm is below tau are set to
+  zero; a block whose norm equals tau is kept.  S itself is truncated the same
+  way before it is factorized.  Sums, differences and scalings are not
+  truncated.  tau = 0 truncates nothing.
+* m: the refinement order (the paper uses m = 4).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+class NoConvergence(RuntimeError):
+    pass
+
+
+class NotPositiveDefinite(RuntimeError):
+    pass
+
+
+# ----------------------------------------------------------------------------
+# basic pieces
+# ----------------------------------------------------------------------------
+
+def coefficients(m: int) -> list[float]:
+    """b_0 = 1, b_k = (2k - 1) / (2k) * b_{k-1} (eq. refinement_nonlocal)."""
+    b = [1.0]
+    for k in range(1, m + 1):
+        b.append((2 * k - 1) / (2 * k) * b[-1])
+    return b
+
+
+def block_norms(X: np.ndarray, b: int) -> np.ndarray:
+    """Frobenius norm of every b x b block of X (partial edge blocks included)."""
+    r, c = X.shape
+    nbr, nbc = (r + b - 1) // b, (c + b - 1) // b
+    P = np.zeros((nbr * b, nbc * b))
+    P[:r, :c] = X
+    T = P.reshape(nbr, b, nbc, b)
+    return np.sqrt(np.einsum("ikjl,ikjl->ij", T, T))
+
+
+def truncate(X: np.ndarray, b: int, tau: float) -> np.ndarray:
+    """Zero every b x b block of X whose Frobenius norm is < tau (Sec. 5)."""
+    if tau <= 0.0:
+        return X
+    keep = block_norms(X, b) >= tau
+    mask = np.repeat(np.repeat(keep, b, axis=0), b, axis=1)[: X.shape[0], : X.shape[1]]
+    return np.where(mask, X, 0.0)
+
+
+def mult(A: np.ndarray, B: np.ndarray, b: int, tau: float) -> np.ndarray:
+    """A matrix-matrix product followed by truncation."""
+    return truncate(A @ B, b, tau)
+
+
+def gershgorin_bound(S: np.ndarray) -> float:
+    """Gershgorin upper bound of the spectral radius: max_i sum_j |S_ij|
+    (Sec. 2.2, scaling of the identity start)."""
+    return float(np.max(np.sum(np.abs(S), axis=1)))
+
+
+def start_scale(S: np.ndarray, mode: str, value: float | None = None) -> float:
+    """Scale c of the start Z_0 = c I (Sec. 2.2).
+
+    * ``"sqrt2_over_gersh"``: c = sqrt(2 / beta), beta the Gershgorin bound
+      (the paper's choice);
+    * ``"inv_sqrt_gersh"``: c = 1 / sqrt(beta);
+    * ``"inv_sqrt_lmax"``: c = 1 / sqrt(value), value = lambda_max;
+    * ``"optimal"``: c = sqrt(2 / (lambda_min + lambda_max)) from eigvalsh;
+    * ``"given"``: c = value.
+    """
+    if mode == "sqrt2_over_gersh":
+        return math.sqrt(2.0 / gershgorin_bound(S))
+    if mode == "inv_sqrt_gersh":
+        return 1.0 / math.sqrt(gershgorin_bound(S))
+    if mode == "inv_sqrt_lmax":
+        return 1.0 / math.sqrt(value)
+    if mode == "optimal":
+        ev = np.linalg.eigvalsh(S)
+        return math.sqrt(2.0 / (ev[0] + ev[-1]))
+    if mode == "given":
+        return float(value)
+    raise ValueError(mode)
+
+
+def inverse_cholesky(S: np.ndarray) -> np.ndarray:
+    """Upper-triangular Z with Z^T S Z = I: S = U^T U (Cholesky), Z = U^{-1}.
+    This is the leaf factorization S^{-1} = Z Z^T of Alg. 1 and Alg. 2."""
+    try:
+        L = np.linalg.cholesky(S)
+    except np.linalg.LinAlgError as e:
+        raise NotPositiveDefinite(str(e)) from e
+    U = L.T
+    n = S.shape[0]
+    return np.linalg.solve(U, np.eye(n)) if n else np.zeros((0, 0))
+
+
+def split_point(rows: int, b: int) -> int:
+    """Rows of the leading part A when a range of ``rows`` rows is split: the
+    range's ceil(nb/2) leading blocks, nb = ceil(rows / b)."""
+    nb = (rows + b - 1) // b
+    return ((nb + 1) // 2) * b
+
+
+# ----------------------------------------------------------------------------
+# refinement
+# ----------------------------------------------------------------------------
+
+@dataclass
+class RefineInfo:
+    iterations: int = 0
+    norms: list = field(default_factory=list)     # ||delta_k||_F, k = 1..iterations
+    stagnated: bool = False
+
+
+def stop_now(k: int, e: float, e_prev: float | None, m: int, stop: str, tol: float) -> bool:
+    """Stop decision after delta_k has been formed (k >= 1).
+
+    ``"paper"``: stop when ||delta_k||_F > ||delta_{k-1}||_F^{m+1}, first tested
+    at k = 2 (the error record starts at the largest real value and its
+    (m+1)-th power), or when delta_k = 0.  ``"tol"``: stop when
+    ||delta_k||_F <= tol, or when the norm stops decreasing.  A norm that grows
+    while >= 1 means divergence.
+    """
+    if not math.isfinite(e):
+        raise NoConvergence(f"non-finite ||delta|| at iteration {k}")
+    if e_prev is not None and e > e_prev and e >= 1.0:
+        raise NoConvergence(f"||delta|| grew from {e_prev:g} to {e:g} at iteration {k}")
+    if stop == "paper":
+        if e == 0.0:
+            return True
+        return e_prev is not None and e > e_prev ** (m + 1)
+    if stop == "tol":
+        if e <= tol:
+            return True
+        return e_prev is not None and e >= e_prev
+    raise ValueError(stop)
+
+
+def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_iter=100, info=None):
+    """Localized iterative refinement (eq. refinement_local; Alg. 2 repeat loop).
+
+    Each iteration, with T_k the Horner terms of sum_{k=1}^m b_k delta^k:
+        T = b_{m-1} I + b_m delta
+        T = b_k I + delta T          (k = m-2, ..., 1; product truncated)
+        q = delta T                  (truncated)
+        M = Z q                      (truncated)
+        Z' = Z + M
+        SM = S M                     (truncated)
+        delta' = delta - Z'^T SM - SM^T Z      (each product truncated;
+                                                M^T S is formed as (SM)^T)
+    Returns (Z, RefineInfo).
+    """
+    info = info if info is not None else RefineInfo()
+    bk = coefficients(m)
+    n = S.shape[0]
+    I = np.eye(n)
+    Z, delta = Z0.copy(), delta0.copy()
+    if not np.any(delta):
+        return Z, info
+    e_prev = None
+    for k in range(1, max_iter + 1):
+        if m == 1:
+            q = bk[1] * delta
+        else:
+            T = bk[m - 1] * I + bk[m] * delta
+            for j in range(m - 2, 0, -1):
+                T = bk[j] * I + mult(delta, T, b, tau)
+            q = mult(delta, T, b, tau)
+        M = mult(Z, q, b, tau)
+        Z_new = Z + M
+        SM = mult(S, M, b, tau)
+        X1 = mult(Z_new.T, SM, b, tau)
+        X2 = mult(SM.T, Z, b, tau)
+        delta = delta - X1 - X2
+        Z = Z_new
+        e = float(np.sqrt(np.sum(delta * delta)))
+        info.norms.append(e)
+        info.iterations = k
+        if stop_now(k, e, e_prev, m, stop, tol):
+            if stop == "tol" and e > tol:
+                info.stagnated = True
+            return Z, info
+        e_prev = e
+    raise NoConvergence(f"no convergence in {max_iter} iterations")
+
+
+def nonlocal_refinement(S, Z0, b, tau, m=4, iterations=None, stop="paper", tol=0.0, max_iter=100):
+    """Regular (non-localized) refinement, eq. refinement_nonlocal:
+    delta_i = I - (Z_i^T S) Z_i, Z_{i+1} = Z_i P_i with
+    P_i = sum_{k=0}^m b_k delta_i^k in Horner form (every product truncated).
+    With ``iterations`` given, exactly that many steps are taken.
+    Returns (Z, RefineInfo)."""
+    bk = coefficients(m)
+    n = S.shape[0]
+    I = np.eye(n)
+    info = RefineInfo()
+    Z = Z0.copy()
+    delta = I - mult(mult(Z.T, S, b, tau), Z, b, tau)
+    if iterations is None and not np.any(delta):
+        return Z, info
+    e_prev = None
+    for k in range(1, (iterations if iterations is not None else max_iter) + 1):
+        P = bk[m] * I
+        for j in range(m - 1, -1, -1):
+            P = bk[j] * I + mult(delta, P, b, tau)
+        Z = mult(Z, P, b, tau)
+        delta = I - mult(mult(Z.T, S, b, tau), Z, b, tau)
+        e = float(np.sqrt(np.sum(delta * delta)))
+        info.norms.append(e)
+        info.iterations = k
+        if iterations is None and stop_now(k, e, e_prev, m, stop, tol):
+            return Z, info
+        e_prev = e
+    if iterations is None:
+        raise NoConvergence(f"no convergence in {max_iter} iterations")
+    return Z, info
+
+
+# ----------------------------------------------------------------------------
+# the three methods
+# ----------------------------------------------------------------------------
+
+def irsi(S, b, tau, m=4, start="sqrt2_over_gersh", start_value=None, stop="paper", tol=0.0,
+         max_iter=100, truncate_input=True):
+    """Iterative refinement from a scaled identity (IRSI, Sec. 2.2):
+    Z_0 = c I, delta_0 = I - c^2 S (a scaling, no product), then localized
+    refinement.  Returns (Z, RefineInfo, c)."""
+    St = truncate(S, b, tau) if truncate_input else S
+    c = start_scale(St, start, start_value)
+    n = S.shape[0]
+    Z0 = c * np.eye(n)
+    delta0 = np.eye(n) - (c * c) * St
+    Z, info = localized_refinement(St, Z0, delta0, b, tau, m, stop, tol, max_iter)
+    return Z, info, c
+
+
+@dataclass
+class LifNode:
+    lo: int                      # first row (multiple of b)
+    hi: int                      # one past the last row
+    depth: int
+    children: tuple = ()
+    info: RefineInfo | None = None
+    delta0_norm2: float = 0.0    # ||delta_0||_2 of this node's refinement
+
+
+def lif_plan(n: int, b: int, base_rows: int) -> LifNode:
+    """Binary split tree: a range is split at ceil(nb/2) blocks while it has
+    more than ``base_rows`` rows."""
+    def build(lo, hi, depth):
+        node = LifNode(lo, hi, depth)
+        if hi - lo > base_rows:
+            h = lo + split_point(hi - lo, b)
+            node.children = (build(lo, h, depth + 1), build(h, hi, depth + 1))
+        return node
+    return build(0, n, 0)
+
+
+def lif(S, b, tau, m=4, base_rows=4096, stop="paper", tol=0.0, max_iter=100, truncate_input=True,
+        plan=None):
+    """Localized inverse factorization (Alg. 2) with an inverse Cholesky leaf.
+
+    For a node with children A (leading rows) and C:
+        Z_A = lif(A), Z_C = lif(C), Z_0 = diag(Z_A, Z_C),
+        X = (Z_A^T B) Z_C (each product truncated),
+        delta_0 = -[[0, X], [X^T, 0]],
+        then localized refinement of Z_0 on the node's S.
+    Returns (Z, plan) with per-node RefineInfo stored in the plan.
+    """
+    St = truncate(S, b, tau) if truncate_input else S
+    plan = plan if plan is not None else lif_plan(S.shape[0], b, base_rows)
+
+    def rec(node):
+        Sn = St[node.lo:node.hi, node.lo:node.hi]
+        if not node.children:
+            return truncate(inverse_cholesky(Sn), b, tau)
+        a, c = node.children
+        ZA = rec(a)
+        ZC = rec(c)
+        h = a.hi - a.lo
+        B = Sn[:h, h:]
+        X = mult(mult(ZA.T, B, b, tau), ZC, b, tau)
+        rows = node.hi - node.lo
+        Z0 = np.zeros((rows, rows))
+        Z0[:h, :h] = ZA
+        Z0[h:, h:] = ZC
+        delta0 = np.zeros((rows, rows))
+        delta0[:h, h:] = -X
+        delta0[h:, :h] = -X.T
+        node.delta0_norm2 = float(np.linalg.norm(delta0, 2)) if rows <= 4000 else float("nan")
+        node.info = RefineInfo()
+        Z, _ = localized_refinement(Sn, Z0, delta0, b, tau, m, stop, tol, max_iter, node.info)
+        return Z
+
+    return rec(plan), plan
+
+
+def rinch(S, b, tau, base_rows=4096, truncate_input=True):
+    """Recursive inverse Cholesky (Alg. 1), split as in ``lif_plan``:
+        Z00 = rinch(S00); R = Z00^T S01; Q = S11 - R^T R; Z11 = rinch(Q);
+        Z01 = -(Z00 R) Z11; Z10 = 0.
+    Every product is truncated, and so is every leaf result."""
+    St = truncate(S, b, tau) if truncate_input else S
+
+    def rec(Sn):
+        rows = Sn.shape[0]
+        if rows <= base_rows:
+            return truncate(inverse_cholesky(Sn), b, tau)
+        h = split_point(rows, b)
+        S00, S01, S11 = Sn[:h, :h], Sn[:h, h:], Sn[h:, h:]
+        Z00 = rec(S00)
+        R = mult(Z00.T, S01, b, tau)
+        Q = S11 - mult(R.T, R, b, tau)
+        Z11 = rec(Q)
+        Z01 = -mult(mult(Z00, R, b, tau), Z11, b, tau)
+        Z = np.zeros((rows, rows))
+        Z[:h, :h] = Z00
+        Z[:h, h:] = Z01
+        Z[h:, h:] = Z11
+        return Z
+
+    return rec(St)
+
+
+def true_residual(S, Z) -> float:
+    """||I - Z^T S Z||_F, untruncated (Table 1's error measure)."""
+    R = np.eye(S.shape[0]) - Z.T @ S @ Z
+    return float(np.sqrt(np.sum(R * R)))
