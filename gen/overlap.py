@@ -15,7 +15,7 @@ Everything here is seeded and deterministic.  The recipe:
 * S_ij = (2 sqrt(a_i a_j) / (a_i + a_j))^{3/2} exp(-a_i a_j r^2 / (a_i + a_j)),
   so diag(S) = 1;
 * atoms sorted by a 63-bit Morton code (21 bits per axis over the bounding
-  box, stable sort), each atom keeping its functions in listed order;
+  cube, stable sort), each atom keeping its functions in listed order;
 * the matrix is cut into b x b blocks (row-major), the last block row/column
   zero-padded when b does not divide n; only blocks holding an element above
   ``elem_eps`` are listed, both (i, j) and (j, i) of the symmetric pattern.
@@ -93,10 +93,11 @@ def _random_rotations(rng: np.random.Generator, count: int) -> np.ndarray:
 
 def _morton_order(points: np.ndarray) -> np.ndarray:
     """Stable argsort of points by a 63-bit Morton code, 21 bits per axis over
-    the bounding box; ties keep generation order."""
+    the bounding cube (one scale for all axes, so a long thin system is
+    ordered along its length); ties keep generation order."""
     lo = points.min(axis=0)
-    span = points.max(axis=0) - lo
-    span[span == 0] = 1.0
+    span = float(np.max(points.max(axis=0) - lo))
+    span = span if span > 0 else 1.0
     q = np.floor((points - lo) / span * ((1 << 21) - 1)).astype(np.uint64)
     q = np.minimum(q, np.uint64((1 << 21) - 1))
 

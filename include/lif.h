@@ -1,0 +1,170 @@
+/*
+ * lif.h -- C ABI of the MI355X (gfx950) inverse-factorization library.
+ *
+ * Computes Z with S^{-1} = Z Z^T for a block-sparse symmetric positive
+ * definite S (Artemov, Rudberg, Rubensson, "Parallelization and scalability
+ * analysis of inverse factorization using the Chunks and Tasks programming
+ * model", Sec. 2), by
+ *   - iterative refinement from a scaled identity (IRSI, Sec. 2.2,
+ *     eq. refinement_local with the start Z_0 = c I), and
+ *   - localized inverse factorization (LIF, Alg. 2) with an inverse Cholesky
+ *     leaf factorization.
+ * Every matrix-matrix product, and every leaf factorization, is followed by
+ * truncation: b x b blocks with Frobenius norm < tau are removed (Sec. 5).
+ * S itself is truncated the same way when the handle is created.
+ *
+ * Matrices cross the boundary as block lists (lif_blocks): row-major b x b
+ * FP64 blocks with int32 block coordinates sorted by (row, col), no
+ * duplicates, entries at scalar indices >= n equal to zero.  A symmetric
+ * matrix lists both (i, j) and (j, i).
+ *
+ * Errors: every call returns a lif_status; nothing throws or exits.  The
+ * message of the last failure on a handle is read with lif_last_error.
+ * After an error the handle may still be destroyed, and caller outputs are
+ * left untouched.
+ *
+ * Streams: all device work of a handle is queued on the hipStream_t given in
+ * lif_opts.stream (NULL = the null stream).  Calls return once their results
+ * are complete; the stopping rule needs host-visible norms every iteration.
+ * A handle is not re-entrant; separate handles are independent.
+ */
+#ifndef LIF_H
+#define LIF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lif_handle_s* lif_handle;
+
+/* status codes */
+#define LIF_OK                 0
+#define LIF_ERR_INVALID        1  /* malformed input or options */
+#define LIF_ERR_NOT_PD         2  /* a leaf Cholesky met a non-positive pivot */
+#define LIF_ERR_NO_CONVERGENCE 3  /* ||delta||_F non-finite, growing past 1, or max_iter reached */
+#define LIF_ERR_OUT_OF_MEMORY  4  /* device memory above mem_cap_bytes or hipMalloc failed */
+#define LIF_ERR_HIP            5  /* a HIP runtime call failed */
+#define LIF_ERR_STATE          6  /* call order (e.g. lif_get_Z before a factorization) */
+typedef int32_t lif_status;
+
+/* lif_opts.prec: arithmetic of the products that form the correction M */
+#define LIF_FP64        0  /* everything FP64 */
+#define LIF_MIXED_FP32  1  /* M products with FP32 inputs, FP32 accumulation; delta and ||delta|| FP64 */
+#define LIF_MIXED_BF16  2  /* M products with BF16 inputs, FP32 accumulation; delta and ||delta|| FP64 */
+
+/* lif_opts.stop: stopping rule of the refinement */
+#define LIF_STOP_PAPER  0  /* stop when ||delta_k||_F > ||delta_{k-1}||_F^{m+1} (Sec. 2.2), first tested at k = 2 */
+#define LIF_STOP_TOL    1  /* stop when ||delta_k||_F <= tol, or when it stops decreasing */
+
+/* lif_opts.start: scale c of the IRSI start Z_0 = c I (Sec. 2.2) */
+#define LIF_START_SQRT2_OVER_GERSH 0  /* c = sqrt(2 / beta), beta the Gershgorin bound of S */
+#define LIF_START_INV_SQRT_GERSH   1  /* c = 1 / sqrt(beta) */
+#define LIF_START_INV_SQRT_LMAX    2  /* c = 1 / sqrt(start_value), start_value = lambda_max(S) */
+#define LIF_START_GIVEN            3  /* c = start_value */
+
+typedef struct {
+  int64_t n;             /* matrix dimension (> 0) */
+  int32_t b;             /* block size: 32 or 64 */
+  int64_t nnzb;          /* number of listed blocks */
+  const int32_t* brow;   /* [nnzb] block row, sorted with bcol, in [0, nb), nb = ceil(n/b) */
+  const int32_t* bcol;   /* [nnzb] block column */
+  const double* vals;    /* [nnzb * b * b] row-major blocks */
+  int32_t on_device;     /* 1: the three arrays are device pointers, 0: host pointers */
+} lif_blocks;
+
+typedef struct {
+  int32_t m;              /* refinement order, 1..8 (the paper uses 4) */
+  double tau;             /* block truncation threshold, >= 0 (0 = none) */
+  int32_t prec;           /* LIF_FP64 / LIF_MIXED_FP32 / LIF_MIXED_BF16 */
+  int32_t stop;           /* LIF_STOP_PAPER / LIF_STOP_TOL */
+  double tol;             /* target ||delta||_F for LIF_STOP_TOL */
+  int32_t max_iter;       /* per refinement; exceeding it is LIF_ERR_NO_CONVERGENCE */
+  int64_t base_rows;      /* LIF recursion stops at ranges of <= base_rows rows (>= b) */
+  int32_t start;          /* LIF_START_* (IRSI only) */
+  double start_value;     /* lambda_max or c, see LIF_START_* */
+  int32_t checkpoint;     /* 1: keep per-iteration Z for lif_backward */
+  uint64_t mem_cap_bytes; /* device memory the handle may hold (0 = no cap) */
+  void* stream;           /* hipStream_t for all work (NULL = null stream) */
+  int32_t timing;         /* 1: time every leaf-GEMM launch with HIP events */
+} lif_opts;
+
+typedef struct {
+  int32_t iterations_top;    /* refinement iterations of the top-level problem */
+  int32_t levels;            /* LIF levels with refinement (0 for IRSI) */
+  int32_t iterations_total;  /* sum over all refinements of all nodes */
+  int32_t stagnated;         /* 1 if LIF_STOP_TOL ended on a non-decreasing norm above tol */
+  double start_scale;        /* c of the IRSI start */
+  double delta_tracked;      /* ||delta||_F of the top-level problem when it stopped */
+  double flops_leaf_gemm;    /* 2 b^3 per block product, summed over all products */
+  double seconds_total;      /* wall time of the call */
+  double seconds_leaf_gemm;  /* summed leaf-GEMM kernel time (timing = 1) */
+  int64_t leaf_gemm_launches;/* number of leaf-GEMM launches */
+  int64_t products_total;    /* block products over all products */
+  int64_t nnzb_Z;            /* blocks of the result */
+  int32_t n_norms;           /* entries used in norms[] */
+  double norms[64];          /* ||delta_k||_F of the top-level problem, k = 1.. */
+} lif_info;
+
+/* Fills *o with the defaults: m = 4, tau = 0, FP64, paper stopping rule,
+ * tol = 1e-10, max_iter = 100, base_rows = 4096, start = SQRT2_OVER_GERSH,
+ * checkpoint = 0, no cap, null stream, timing = 0. */
+lif_status lif_opts_default(lif_opts* o);
+
+/* Validates S and copies it into library-owned device memory (the caller may
+ * free its arrays on return), truncates it at o->tau.  Checks: n > 0,
+ * b in {32, 64}, sorted unique in-range blocks, symmetric block pattern,
+ * zero padding, options in range (LIF_ERR_INVALID otherwise).  The options
+ * are copied.  On success *out owns all device memory of the problem. */
+lif_status lif_create(const lif_blocks* S, const lif_opts* o, lif_handle* out);
+
+/* Iterative refinement (eq. refinement_local).  Z0 == NULL: IRSI, start
+ * Z_0 = c I, delta_0 = I - c^2 S (Sec. 2.2).  Otherwise Z0 (same n and b)
+ * is the start and delta_0 = I - Z0^T S Z0 (products truncated).  The result
+ * replaces the handle's Z.  info may be NULL. */
+lif_status lif_refine(lif_handle h, const lif_blocks* Z0, lif_info* info);
+
+/* Localized inverse factorization (Alg. 2): ranges of more than base_rows
+ * rows split at ceil(nb/2) blocks; leaves factorized by inverse Cholesky
+ * (S_leaf = U^T U, Z_leaf = U^{-1}); each level of the recursion is corrected
+ * by localized refinement from diag(Z_A, Z_C) with
+ * delta_0 = -[[0, X], [X^T, 0]], X = (Z_A^T B) Z_C.  All nodes of one depth are
+ * processed together.  A non-positive leaf pivot gives LIF_ERR_NOT_PD. */
+lif_status lif_localized(lif_handle h, lif_info* info);
+
+/* Copies the handle's Z out as a block list.  Two-phase: with brow == NULL
+ * only *nnzb is written; otherwise the arrays (capacity *nnzb blocks, host or
+ * device per on_device) receive the blocks in (row, col) order.
+ * LIF_ERR_STATE before a factorization, LIF_ERR_INVALID if the capacity is
+ * too small. */
+lif_status lif_get_Z(lif_handle h, int64_t* nnzb, int32_t* brow, int32_t* bcol, double* vals,
+                     int32_t on_device);
+
+/* ||I - Z^T S Z||_F of the handle's Z in FP64 with no truncation (Table 1's
+ * error measure), against the truncated S the handle factorized. */
+lif_status lif_residual(lif_handle h, double* out);
+
+/* C = op(A) op(B) truncated at tau: the block-sparse product of Sec. 4 with
+ * the leaf truncation of Sec. 5, on the handle's stream and memory.  op is
+ * the identity (trans = 0) or the transpose (trans = 1).  A and B must have
+ * the handle's n and b.  Two-phase output like lif_get_Z (the product is
+ * recomputed on the second call); *products receives the number of block
+ * products (may be NULL). */
+lif_status lif_multiply(lif_handle h, const lif_blocks* A, int32_t transA, const lif_blocks* B,
+                        int32_t transB, double tau, int64_t* nnzb, int32_t* brow, int32_t* bcol,
+                        double* vals, int32_t on_device, int64_t* products);
+
+/* Releases the handle and all its device memory.  NULL is ignored. */
+void lif_destroy(lif_handle h);
+
+/* Message of the last failed call on h ("" if none); valid until the next
+ * call on h.  With h == NULL: the last lif_create failure of this thread. */
+const char* lif_last_error(lif_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIF_H */

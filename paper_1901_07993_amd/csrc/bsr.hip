@@ -1,0 +1,447 @@
+// Block-CSR utility kernels: row pointers, block norms, truncation and
+// compaction (Sec. 5: blocks with Frobenius norm < tau are removed), pattern
+// union with scaled sums (matrix addition / scaling, identity terms),
+// filters that cut level- and coupling-parts out of a matrix, transposition,
+// the Gershgorin bound (Sec. 2.2) and segmented norm sums.
+//
+// These passes stream over HBM; each block is handled by one workgroup with
+// coalesced 16-byte accesses, index work by one thread per block row.
+#include "common.h"
+
+namespace lif {
+
+namespace {
+
+constexpr int kWG = 256;
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ inline double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Fixed-order block sum of one double per thread (256 threads): wave sums,
+// then the 4 wave totals added in order by thread 0.  Deterministic.
+__device__ inline double block_sum_256(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  return r;
+}
+
+__global__ void k_row_ptr_from_rows(const int* __restrict__ brow, int64_t nnzb, int nb, int* __restrict__ rp) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e > nnzb) return;
+  int prev = (e == 0) ? -1 : brow[e - 1];
+  int cur = (e == nnzb) ? nb : brow[e];
+  for (int r = prev + 1; r <= cur; ++r) rp[r] = (int)e;
+}
+
+__global__ __launch_bounds__(kWG) void k_block_sumsq(const double* __restrict__ val, int64_t nnzb, int bb,
+                                                     double* __restrict__ out, int take_sqrt) {
+  __shared__ double sh[4];
+  const int64_t e = blockIdx.x;
+  const double2* p = reinterpret_cast<const double2*>(val + e * (int64_t)bb);
+  double s = 0.0;
+  for (int i = threadIdx.x; i < bb / 2; i += kWG) {
+    double2 v = p[i];
+    s += v.x * v.x + v.y * v.y;
+  }
+  double r = block_sum_256(s, sh);
+  if (threadIdx.x == 0) out[e] = take_sqrt ? sqrt(r) : r;
+}
+
+__global__ void k_keep_counts(const int* __restrict__ rp, const double* __restrict__ norms, double tau, int nb,
+                              int* __restrict__ counts) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  int cnt = 0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) cnt += (norms[e] >= tau) ? 1 : 0;
+  counts[i] = cnt;
+}
+
+__global__ void k_compact_index(const int* __restrict__ rp, const int* __restrict__ col,
+                                const double* __restrict__ norms, double tau, const int* __restrict__ nrp,
+                                int nb, int* __restrict__ ncol, int* __restrict__ src) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  int o = nrp[i];
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    if (norms[e] >= tau) {
+      ncol[o] = col[e];
+      src[o] = e;
+      ++o;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_gather_blocks(const double* __restrict__ val, const int* __restrict__ src,
+                                                       int bb, double* __restrict__ out) {
+  const int64_t e = blockIdx.x;
+  const double2* s = reinterpret_cast<const double2*>(val + (int64_t)src[e] * bb);
+  double2* d = reinterpret_cast<double2*>(out + e * (int64_t)bb);
+  for (int i = threadIdx.x; i < bb / 2; i += kWG) d[i] = s[i];
+}
+
+// Gershgorin: row_max[i] = max over the b scalar rows of block row i of
+// sum_j |S_rj|.  One workgroup per block row; each wave takes scalar rows
+// w, w+4, ... and reads them 64 doubles at a time.
+__global__ __launch_bounds__(kWG) void k_gershgorin(const int* __restrict__ rp, const double* __restrict__ val,
+                                                    int b, double* __restrict__ row_max) {
+  __shared__ double sh[4];
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double best = 0.0;
+  for (int r = w; r < b; r += 4) {
+    double s = 0.0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+      const double* row = val + (int64_t)e * b * b + (int64_t)r * b;
+      for (int cc = lane; cc < b; cc += 64) s += fabs(row[cc]);
+    }
+    s = wave_sum(s);
+    best = fmax(best, s);
+  }
+  if (lane == 0) sh[w] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) row_max[i] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+__global__ __launch_bounds__(1024) void k_max_reduce(const double* __restrict__ in, int count, double* __restrict__ out) {
+  __shared__ double sh[16];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < count; i += 1024) m = fmax(m, in[i]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int k = 0; k < 16; ++k) r = fmax(r, sh[k]);
+    out[0] = r;
+  }
+}
+
+// Union of the sorted column lists of A's and B's row i, plus column i when
+// diag_on[i] is set.  A or B may be absent (null pointers).
+__device__ inline int union_row(const int* ra, const int* ca, const int* rb, const int* cb,
+                                const unsigned char* diag_on, int i, int* cc, int* ia, int* ib,
+                                unsigned char* id) {
+  int pa = ra ? ra[i] : 0, ea = ra ? ra[i + 1] : 0;
+  int pb = rb ? rb[i] : 0, eb = rb ? rb[i + 1] : 0;
+  bool dg = diag_on && diag_on[i];
+  int o = 0;
+  while (pa < ea || pb < eb || dg) {
+    int xa = pa < ea ? ca[pa] : INT_MAX;
+    int xb = pb < eb ? cb[pb] : INT_MAX;
+    int xd = dg ? i : INT_MAX;
+    int x = min(xa, min(xb, xd));
+    if (cc) {
+      cc[o] = x;
+      ia[o] = (xa == x) ? pa : -1;
+      ib[o] = (xb == x) ? pb : -1;
+      id[o] = (xd == x) ? 1 : 0;
+    }
+    if (xa == x) ++pa;
+    if (xb == x) ++pb;
+    if (xd == x) dg = false;
+    ++o;
+  }
+  return o;
+}
+
+__global__ void k_union_counts(const int* ra, const int* ca, const int* rb, const int* cb,
+                               const unsigned char* diag_on, int nb, int* counts) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  counts[i] = union_row(ra, ca, rb, cb, diag_on, i, nullptr, nullptr, nullptr, nullptr);
+}
+
+__global__ void k_union_fill(const int* ra, const int* ca, const int* rb, const int* cb,
+                             const unsigned char* diag_on, const int* rc, int nb, int* cc, int* ia, int* ib,
+                             unsigned char* id) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  int o = rc[i];
+  union_row(ra, ca, rb, cb, diag_on, i, cc + o, ia + o, ib + o, id + o);
+}
+
+// out = alpha A[ia] + beta B[ib] + gamma I (diagonal entries of real rows only)
+__global__ __launch_bounds__(kWG) void k_axpby_values(double alpha, const double* __restrict__ va,
+                                                      const int* __restrict__ ia, double beta,
+                                                      const double* __restrict__ vb, const int* __restrict__ ib,
+                                                      double gamma, const unsigned char* __restrict__ id,
+                                                      const int* __restrict__ row_of, int b, int64_t n,
+                                                      double* __restrict__ out) {
+  const int64_t e = blockIdx.x;
+  const int bb = b * b;
+  const int xa = ia[e], xb = ib[e];
+  const bool dg = id[e] != 0;
+  const int64_t row0 = (int64_t)row_of[e] * b;
+  const double2* pa = xa >= 0 ? reinterpret_cast<const double2*>(va + (int64_t)xa * bb) : nullptr;
+  const double2* pb = xb >= 0 ? reinterpret_cast<const double2*>(vb + (int64_t)xb * bb) : nullptr;
+  double2* po = reinterpret_cast<double2*>(out + e * (int64_t)bb);
+  for (int q = threadIdx.x; q < bb / 2; q += kWG) {
+    double2 r = make_double2(0.0, 0.0);
+    if (pa) {
+      double2 v = pa[q];
+      r.x = alpha * v.x;
+      r.y = alpha * v.y;
+    }
+    if (pb) {
+      double2 v = pb[q];
+      r.x += beta * v.x;
+      r.y += beta * v.y;
+    }
+    if (dg) {
+      const int lin = 2 * q;
+      const int rr = lin / b, c0 = lin % b;
+      if (row0 + rr < n) {
+        if (c0 == rr) r.x += gamma;
+        if (c0 + 1 == rr) r.y += gamma;
+      }
+    }
+    po[q] = r;
+  }
+}
+
+__global__ void k_block_row_of(const int* __restrict__ rp, int nb, int* __restrict__ row_of) {
+  int i = blockIdx.x;
+  for (int e = rp[i] + threadIdx.x; e < rp[i + 1]; e += blockDim.x) row_of[e] = i;
+}
+
+// Filter predicates on per-block-row labels of the row (rlab) and of the
+// column (clab):
+//   mode 0: rlab[i] >= 0 && rlab[i] == clab[j]            (same group)
+//   mode 1: rlab[i] >= 0, rlab[i] even, clab[j] == rlab[i] + 1
+//           (labels 2 g + side: leading part A to trailing part C of group g)
+//   mode 2: rlab[i] >= 0                                   (rows of active groups)
+__device__ inline bool keep_pred(int mode, int li, int lj) {
+  if (li < 0) return false;
+  if (mode == 0) return li == lj;
+  if (mode == 1) return ((li & 1) == 0) && lj == li + 1;
+  return true;
+}
+
+__global__ void k_filter_counts(const int* __restrict__ rp, const int* __restrict__ col, const int* __restrict__ rlab,
+                                const int* __restrict__ clab, int mode, int nb, int* __restrict__ counts) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  int li = rlab[i];
+  int cnt = 0;
+  if (li >= 0)
+    for (int e = rp[i]; e < rp[i + 1]; ++e) cnt += keep_pred(mode, li, clab[col[e]]) ? 1 : 0;
+  counts[i] = cnt;
+}
+
+__global__ void k_filter_fill(const int* __restrict__ rp, const int* __restrict__ col, const int* __restrict__ rlab,
+                              const int* __restrict__ clab, int mode, const int* __restrict__ nrp, int nb,
+                              int* __restrict__ ncol, int* __restrict__ src) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  int li = rlab[i];
+  if (li < 0) return;
+  int o = nrp[i];
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    if (keep_pred(mode, li, clab[col[e]])) {
+      ncol[o] = col[e];
+      src[o] = e;
+      ++o;
+    }
+  }
+}
+
+__global__ void k_transpose_counts(const int* __restrict__ col, int64_t nnzb, int* __restrict__ counts) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnzb) atomicAdd(&counts[col[e]], 1);
+}
+
+__global__ void k_transpose_fill(const int* __restrict__ rp, const int* __restrict__ col, const int* __restrict__ tptr,
+                                 int nb, int* __restrict__ cursor, int* __restrict__ tcol, int* __restrict__ tsrc) {
+  int i = blockIdx.x;
+  for (int e = rp[i] + threadIdx.x; e < rp[i + 1]; e += blockDim.x) {
+    int j = col[e];
+    int pos = tptr[j] + atomicAdd(&cursor[j], 1);
+    tcol[pos] = i;
+    tsrc[pos] = e;
+  }
+}
+
+// Sort each transposed row by its (distinct) column keys: every element's
+// rank is the number of smaller keys in its segment, and it is written to
+// that rank of the output arrays.  Keys are staged in LDS when the segment
+// fits (4096 entries), else read from HBM.  Out of place, so any segment
+// length is handled.
+constexpr int kSortLds = 4096;
+__global__ __launch_bounds__(kWG) void k_transpose_sort(const int* __restrict__ tptr, const int* __restrict__ icol,
+                                                        const int* __restrict__ isrc, int* __restrict__ ocol,
+                                                        int* __restrict__ osrc) {
+  __shared__ int key[kSortLds];
+  const int j = blockIdx.x;
+  const int lo = tptr[j], len = tptr[j + 1] - tptr[j];
+  const bool staged = len <= kSortLds;
+  if (staged) {
+    for (int t = threadIdx.x; t < len; t += kWG) key[t] = icol[lo + t];
+    __syncthreads();
+  }
+  const int* keys = staged ? key : icol + lo;
+  for (int t = threadIdx.x; t < len; t += kWG) {
+    const int k = keys[t];
+    int r = 0;
+    for (int u = 0; u < len; ++u) r += (keys[u] < k) ? 1 : 0;
+    ocol[lo + r] = k;
+    osrc[lo + r] = isrc[lo + t];
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_transpose_blocks(const double* __restrict__ val, const int* __restrict__ src,
+                                                          int b, double* __restrict__ out) {
+  __shared__ double t[64 * 65];
+  const int64_t e = blockIdx.x;
+  const double* s = val + (int64_t)src[e] * b * b;
+  double* d = out + e * (int64_t)b * b;
+  for (int q = threadIdx.x; q < b * b; q += kWG) {
+    int r = q / b, cc = q % b;
+    t[r * 65 + cc] = s[q];
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < b * b; q += kWG) {
+    int r = q / b, cc = q % b;
+    d[q] = t[cc * 65 + r];
+  }
+}
+
+// out[s] = sum of sumsq[e] over the blocks of block rows [rlo[s], rhi[s])
+__global__ __launch_bounds__(kWG) void k_segment_sum(const double* __restrict__ sumsq, const int* __restrict__ rp,
+                                                     const int* __restrict__ rlo, const int* __restrict__ rhi,
+                                                     double* __restrict__ out) {
+  __shared__ double sh[4];
+  const int s = blockIdx.x;
+  const int lo = rp[rlo[s]], hi = rp[rhi[s]];
+  double v = 0.0;
+  for (int e = lo + threadIdx.x; e < hi; e += kWG) v += sumsq[e];
+  double r = block_sum_256(v, sh);
+  if (threadIdx.x == 0) out[s] = r;
+}
+
+__global__ void k_fill_i32(int* p, int value, int64_t count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = value;
+}
+
+inline unsigned grid1(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+#define LIF_LAUNCH(...)                   \
+  do {                                    \
+    hipLaunchKernelGGL(__VA_ARGS__);      \
+    LIF_HIP(hipGetLastError());           \
+  } while (0)
+
+void launch_row_ptr_from_rows(Ctx& c, const int* brow, int64_t nnzb, int nb, int* row_ptr) {
+  LIF_LAUNCH(k_row_ptr_from_rows, dim3(grid1(nnzb + 1, 256)), dim3(256), 0, c.stream, brow, nnzb, nb, row_ptr);
+}
+
+void launch_block_sumsq(Ctx& c, const double* val, int64_t nnzb, int b, double* out, bool take_sqrt) {
+  if (nnzb == 0) return;
+  LIF_LAUNCH(k_block_sumsq, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, val, nnzb, b * b, out, take_sqrt ? 1 : 0);
+}
+
+void launch_keep_counts(Ctx& c, const int* row_ptr, const double* norms, double tau, int nb, int* counts) {
+  LIF_LAUNCH(k_keep_counts, dim3(grid1(nb, 256)), dim3(256), 0, c.stream, row_ptr, norms, tau, nb, counts);
+}
+
+void launch_compact_index(Ctx& c, const int* row_ptr, const int* col, const double* norms, double tau,
+                          const int* new_row_ptr, int nb, int* new_col, int* src) {
+  LIF_LAUNCH(k_compact_index, dim3(grid1(nb, 256)), dim3(256), 0, c.stream, row_ptr, col, norms, tau, new_row_ptr,
+             nb, new_col, src);
+}
+
+void launch_gather_blocks(Ctx& c, const double* val, const int* src, int64_t nnzb, int b, double* out) {
+  if (nnzb == 0) return;
+  LIF_LAUNCH(k_gather_blocks, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, val, src, b * b, out);
+}
+
+void launch_gershgorin(Ctx& c, const int* row_ptr, const double* val, int nb, int b, double* row_max) {
+  LIF_LAUNCH(k_gershgorin, dim3(nb), dim3(kWG), 0, c.stream, row_ptr, val, b, row_max);
+}
+
+void launch_max_reduce(Ctx& c, const double* in, int count, double* out) {
+  LIF_LAUNCH(k_max_reduce, dim3(1), dim3(1024), 0, c.stream, in, count, out);
+}
+
+void launch_union_counts(Ctx& c, const int* ra, const int* ca, const int* rb, const int* cb,
+                         const unsigned char* diag_on, int nb, int* counts) {
+  LIF_LAUNCH(k_union_counts, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, ra, ca, rb, cb, diag_on, nb, counts);
+}
+
+void launch_union_fill(Ctx& c, const int* ra, const int* ca, const int* rb, const int* cb,
+                       const unsigned char* diag_on, const int* rc, int nb, int* cc, int* ia, int* ib,
+                       unsigned char* id) {
+  LIF_LAUNCH(k_union_fill, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, ra, ca, rb, cb, diag_on, rc, nb, cc, ia,
+             ib, id);
+}
+
+void launch_axpby_values(Ctx& c, double alpha, const double* va, const int* ia, double beta, const double* vb,
+                         const int* ib, double gamma, const unsigned char* id, const int* row_of, int64_t nnzb,
+                         int b, int64_t n, double* out) {
+  if (nnzb == 0) return;
+  LIF_LAUNCH(k_axpby_values, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, alpha, va, ia, beta, vb, ib, gamma, id,
+             row_of, b, n, out);
+}
+
+void launch_block_row_of(Ctx& c, const int* row_ptr, int nb, int64_t nnzb, int* row_of) {
+  if (nnzb == 0) return;
+  LIF_LAUNCH(k_block_row_of, dim3(nb), dim3(64), 0, c.stream, row_ptr, nb, row_of);
+}
+
+void launch_filter_counts(Ctx& c, const int* row_ptr, const int* col, const int* rlab, const int* clab, int mode,
+                          int nb, int* counts) {
+  LIF_LAUNCH(k_filter_counts, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, row_ptr, col, rlab, clab, mode, nb,
+             counts);
+}
+
+void launch_filter_fill(Ctx& c, const int* row_ptr, const int* col, const int* rlab, const int* clab, int mode,
+                        const int* new_row_ptr, int nb, int* new_col, int* src) {
+  LIF_LAUNCH(k_filter_fill, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, row_ptr, col, rlab, clab, mode,
+             new_row_ptr, nb, new_col, src);
+}
+
+void launch_transpose_counts(Ctx& c, const int* col, int64_t nnzb, int* counts) {
+  if (nnzb == 0) return;
+  LIF_LAUNCH(k_transpose_counts, dim3(grid1(nnzb, 256)), dim3(256), 0, c.stream, col, nnzb, counts);
+}
+
+void launch_transpose_fill(Ctx& c, const int* row_ptr, const int* col, const int* tptr, int nb, int* cursor,
+                           int* tcol, int* tsrc) {
+  LIF_LAUNCH(k_transpose_fill, dim3(nb), dim3(64), 0, c.stream, row_ptr, col, tptr, nb, cursor, tcol, tsrc);
+}
+
+void launch_transpose_sort(Ctx& c, const int* tptr, int nb, const int* icol, const int* isrc, int* ocol,
+                           int* osrc) {
+  LIF_LAUNCH(k_transpose_sort, dim3(nb), dim3(kWG), 0, c.stream, tptr, icol, isrc, ocol, osrc);
+}
+
+void launch_transpose_blocks(Ctx& c, const double* val, const int* src, int64_t nnzb, int b, double* out) {
+  if (nnzb == 0) return;
+  LIF_LAUNCH(k_transpose_blocks, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, val, src, b, out);
+}
+
+void launch_segment_sum(Ctx& c, const double* sumsq, const int* row_ptr, const int* rlo, const int* rhi, int nseg,
+                        double* out) {
+  if (nseg == 0) return;
+  LIF_LAUNCH(k_segment_sum, dim3(nseg), dim3(kWG), 0, c.stream, sumsq, row_ptr, rlo, rhi, out);
+}
+
+void launch_fill_i32(Ctx& c, int* p, int value, int64_t count) {
+  if (count == 0) return;
+  LIF_LAUNCH(k_fill_i32, dim3(grid1(count, 256)), dim3(256), 0, c.stream, p, value, count);
+}
+
+}  // namespace lif

@@ -1,0 +1,243 @@
+// Internal declarations of the inverse-factorization library: device memory
+// pool, RAII device buffers, the device block-CSR matrix and the launchers of
+// every kernel.  Host code only; kernels live in the *.hip files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/lif.h"
+
+namespace lif {
+
+struct Error : std::runtime_error {
+  int status;
+  Error(int s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define LIF_HIP(x)                                                                         \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess)                                                                  \
+      throw ::lif::Error(LIF_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+#define LIF_REQUIRE(cond, status, msg)          \
+  do {                                          \
+    if (!(cond)) throw ::lif::Error((status), (msg)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Device memory pool: caches freed allocations by exact rounded size so the
+// refinement loop does not call hipMalloc/hipFree once warm.  All memory of a
+// handle goes through one pool, which enforces the handle's byte cap.
+// ---------------------------------------------------------------------------
+class Pool {
+ public:
+  explicit Pool(uint64_t cap) : cap_(cap) {}
+  ~Pool() { release_all(); }
+  void* alloc(size_t bytes);
+  void free(void* p);
+  void trim();            // return cached (unused) memory to HIP
+  uint64_t in_use() const { return in_use_; }
+  uint64_t reserved() const { return reserved_; }
+  uint64_t peak() const { return peak_; }
+
+ private:
+  static size_t round(size_t bytes);
+  void release_all();
+  uint64_t cap_;
+  uint64_t in_use_ = 0, reserved_ = 0, peak_ = 0;
+  std::multimap<size_t, void*> cache_;
+  std::map<void*, size_t> live_;
+};
+
+template <typename T>
+class DBuf {
+ public:
+  DBuf() = default;
+  DBuf(Pool* pool, size_t n) : pool_(pool), n_(n) {
+    p_ = n ? static_cast<T*>(pool->alloc(n * sizeof(T))) : nullptr;
+  }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : pool_(o.pool_), p_(o.p_), n_(o.n_) { o.p_ = nullptr; o.n_ = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      reset();
+      pool_ = o.pool_; p_ = o.p_; n_ = o.n_;
+      o.p_ = nullptr; o.n_ = 0;
+    }
+    return *this;
+  }
+  ~DBuf() { reset(); }
+  void reset() {
+    if (p_ && pool_) pool_->free(p_);
+    p_ = nullptr;
+    n_ = 0;
+  }
+  T* get() const { return p_; }
+  size_t size() const { return n_; }
+
+ private:
+  Pool* pool_ = nullptr;
+  T* p_ = nullptr;
+  size_t n_ = 0;
+};
+
+// ---------------------------------------------------------------------------
+// Device block-CSR matrix: nb block rows, row_ptr[nb+1], col[nnzb] sorted
+// within each row, val[nnzb][b][b] row-major FP64 blocks.
+// ---------------------------------------------------------------------------
+struct Bsr {
+  int64_t n = 0;
+  int b = 0;
+  int nb = 0;
+  int64_t nnzb = 0;
+  DBuf<int> row_ptr;
+  DBuf<int> col;
+  DBuf<double> val;
+};
+
+// Per-call statistics.
+struct Stats {
+  double flops = 0;
+  int64_t products = 0;
+  int64_t gemm_launches = 0;
+  double gemm_ms = 0;
+};
+
+// Execution context shared by all operations of a handle.
+struct Ctx {
+  hipStream_t stream = nullptr;
+  Pool* pool = nullptr;
+  Stats stats;
+  bool timing = false;
+  int b = 64;
+  int64_t n = 0;
+  int nb = 0;
+  // pinned host staging for small device->host reads
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  // per-block-row flags, all set (identity on every row)
+  DBuf<unsigned char> ones;
+  // events around leaf-GEMM launches (timing mode), resolved at flush_timing()
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+  std::vector<hipEvent_t> ev_free;
+
+  hipEvent_t take_event();
+  void flush_timing();
+  void sync() { LIF_HIP(hipStreamSynchronize(stream)); }
+  // copy `bytes` from device `src` through the pinned buffer; synchronizes
+  void d2h(void* dst, const void* src, size_t bytes);
+  // two small reads with one synchronization (each at most 64 bytes)
+  void d2h2(void* d0, const void* s0, size_t b0, void* d1, const void* s1, size_t b1);
+  ~Ctx();
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip files).  All enqueue on ctx.stream.
+// ---------------------------------------------------------------------------
+
+// scan.hip
+// out[0] = 0, out[i+1] = out[i] + in[i] for i < count (int32 or int64 input)
+void scan_exclusive_i32(Ctx& c, const int* in, int* out, int count);
+void scan_exclusive_i64(Ctx& c, const int64_t* in, int64_t* out, int count);
+
+// bsr.hip
+void launch_row_ptr_from_rows(Ctx& c, const int* brow, int64_t nnzb, int nb, int* row_ptr);
+void launch_block_sumsq(Ctx& c, const double* val, int64_t nnzb, int b, double* out, bool take_sqrt);
+void launch_keep_counts(Ctx& c, const int* row_ptr, const double* norms, double tau, int nb, int* counts);
+void launch_compact_index(Ctx& c, const int* row_ptr, const int* col, const double* norms, double tau,
+                          const int* new_row_ptr, int nb, int* new_col, int* src);
+void launch_gather_blocks(Ctx& c, const double* val, const int* src, int64_t nnzb, int b, double* out);
+void launch_gershgorin(Ctx& c, const int* row_ptr, const double* val, int nb, int b, double* row_max);
+void launch_max_reduce(Ctx& c, const double* in, int count, double* out);
+void launch_union_counts(Ctx& c, const int* ra, const int* ca, const int* rb, const int* cb,
+                         const unsigned char* diag_on, int nb, int* counts);
+void launch_union_fill(Ctx& c, const int* ra, const int* ca, const int* rb, const int* cb,
+                       const unsigned char* diag_on, const int* rc, int nb, int* cc, int* ia, int* ib,
+                       unsigned char* id);
+void launch_axpby_values(Ctx& c, double alpha, const double* va, const int* ia, double beta,
+                         const double* vb, const int* ib, double gamma, const unsigned char* id,
+                         const int* row_of, int64_t nnzb, int b, int64_t n, double* out);
+void launch_block_row_of(Ctx& c, const int* row_ptr, int nb, int64_t nnzb, int* row_of);
+void launch_filter_counts(Ctx& c, const int* row_ptr, const int* col, const int* rlab, const int* clab,
+                          int mode, int nb, int* counts);
+void launch_filter_fill(Ctx& c, const int* row_ptr, const int* col, const int* rlab, const int* clab,
+                        int mode, const int* new_row_ptr, int nb, int* new_col, int* src);
+void launch_transpose_counts(Ctx& c, const int* col, int64_t nnzb, int* counts);
+void launch_transpose_fill(Ctx& c, const int* row_ptr, const int* col, const int* tptr, int nb,
+                           int* cursor, int* tcol, int* tsrc);
+void launch_transpose_sort(Ctx& c, const int* tptr, int nb, const int* icol, const int* isrc, int* ocol,
+                           int* osrc);
+void launch_transpose_blocks(Ctx& c, const double* val, const int* src, int64_t nnzb, int b, double* out);
+void launch_segment_sum(Ctx& c, const double* sumsq, const int* row_ptr, const int* rlo, const int* rhi, int nseg,
+                        double* out);
+void launch_fill_i32(Ctx& c, int* p, int value, int64_t count);
+
+// spgemm.hip
+// Symbolic phase.  opA given as CSR (row ptr, col, value index) of op(A);
+// B as CSR of op(B) with value index.  Writes per-row output and product
+// counts.
+void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* brp, const int* bcol,
+                           int nb, int* cnt_c, int64_t* cnt_p);
+void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp,
+                          const int* bcol, const int* bidx, int nb, const int* crp,
+                          const int64_t* prp, int* ccol, int64_t* seg, int2* pairs);
+// Numeric phase: C_blk = sum over its segment of op(A_a) op(B_b).
+void launch_numeric(Ctx& c, const double* A, const double* B, bool ta, bool tb, const int64_t* seg,
+                    const int2* pairs, int64_t nnzc, int b, double* C, double* norms);
+
+// chol.hip -- batched leaf inverse Cholesky on packed upper tile grids
+void launch_chol_scatter(Ctx& c, const int* row_of, const int* col, const double* val, int64_t nnzb, int b,
+                         const int* base_of_row, const int* blk0, const int* nbb, const int64_t* tile0, double* U);
+void launch_chol_pad(Ctx& c, int nbase, const int* nbb, const int* rows, const int64_t* tile0, int b, double* M,
+                     double value);
+void launch_potrf(Ctx& c, int k, int nbase, const int* nbb, const int* blk0, const int64_t* tile0, int b, double* U,
+                  double* Z, int* err);
+void launch_trsm(Ctx& c, int k, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b, double* U,
+                 const double* Z);
+void launch_update(Ctx& c, int k, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b, double* U);
+void launch_trinv(Ctx& c, int j, int nbase, const int* nbb, const int64_t* tile0, int b, const double* U, double* Z);
+
+// ---------------------------------------------------------------------------
+// Block-sparse operations (ops.cpp): allocate outputs, run the kernels,
+// read back the sizes they need.
+// ---------------------------------------------------------------------------
+struct CsrView {          // CSR of op(A): row ptr, column, index of the stored block
+  const int* rp = nullptr;
+  const int* col = nullptr;
+  const int* idx = nullptr;  // null: identity (block e of A)
+  DBuf<int> own_rp, own_col, own_idx;
+};
+
+template <typename T>
+void h2d(Ctx& c, T* dst, const T* src, size_t count) {
+  if (count) LIF_HIP(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, c.stream));
+}
+
+Bsr bsr_empty(Ctx& c, int64_t n, int b);
+Bsr bsr_from_blocks(Ctx& c, const lif_blocks& in);
+void bsr_to_blocks(Ctx& c, const Bsr& A, int32_t* brow, int32_t* bcol, double* vals, bool on_device);
+DBuf<double> block_norms(Ctx& c, const Bsr& A);
+Bsr truncate(Ctx& c, Bsr&& A, const double* norms, double tau);
+CsrView transpose_view(Ctx& c, const Bsr& A);
+Bsr transpose(Ctx& c, const Bsr& A);
+Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau);
+// alpha A + beta B + gamma I on the block rows with diag_on set (A or B may be null)
+Bsr axpby(Ctx& c, double alpha, const Bsr* A, double beta, const Bsr* B, double gamma,
+          const unsigned char* diag_on);
+Bsr filter(Ctx& c, const Bsr& A, const int* rlab, const int* clab, int mode);
+double gershgorin(Ctx& c, const Bsr& A);
+std::vector<double> node_sumsq(Ctx& c, const Bsr& A, const int* rlo, const int* rhi, int nseg);
+Bsr copy(Ctx& c, const Bsr& A);
+
+}  // namespace lif

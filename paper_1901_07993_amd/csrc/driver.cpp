@@ -1,0 +1,411 @@
+// Refinement and localized-recursion drivers (host code).
+#include "driver.h"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+namespace lif {
+
+namespace {
+
+// Coefficients of eq. refinement_nonlocal: b_0 = 1, b_k = (2k-1)/(2k) b_{k-1}.
+std::vector<double> coefficients(int m) {
+  std::vector<double> b(m + 1);
+  b[0] = 1.0;
+  for (int k = 1; k <= m; ++k) b[k] = b[k - 1] * (2.0 * k - 1.0) / (2.0 * k);
+  return b;
+}
+
+// Stopping decision after delta_k of one problem has been formed.
+//   paper rule (Sec. 2.2): stop when e_k > e_{k-1}^{m+1}; the error record
+//     starts at the largest real value and its (m+1)-th power, so the first
+//     real comparison is k = 2; delta_k = 0 also stops.
+//   tol rule: stop when e_k <= tol or when e_k >= e_{k-1} (no progress).
+// A norm that grows while >= 1 is divergence (the start was not a
+// contraction); a non-finite norm likewise.
+enum class Step { Continue, Stop, Diverged };
+
+Step stop_decision(int k, double e, double e_prev, bool has_prev, int m, int stop, double tol, bool* stagnated) {
+  if (!std::isfinite(e)) return Step::Diverged;
+  if (has_prev && e > e_prev && e >= 1.0) return Step::Diverged;
+  if (stop == LIF_STOP_PAPER) {
+    if (e == 0.0) return Step::Stop;
+    if (has_prev && e > std::pow(e_prev, m + 1)) return Step::Stop;
+    return Step::Continue;
+  }
+  if (e <= tol) return Step::Stop;
+  if (has_prev && e >= e_prev) {
+    *stagnated = true;
+    return Step::Stop;
+  }
+  return Step::Continue;
+}
+
+struct NodeState {
+  bool active = true;
+  bool has_prev = false;
+  double e_prev = 0.0;
+  double e = 0.0;
+  int iterations = 0;
+  bool stagnated = false;
+  std::vector<double> norms;
+};
+
+// A set of independent problems refined together: node s owns block rows
+// [rlo[s], rhi[s]).  S is the matching block-diagonal part of the matrix.
+struct Batch {
+  std::vector<int> rlo, rhi;
+  int nb = 0;
+};
+
+void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, const Opts& o,
+                  std::vector<NodeState>& st, int max_iter) {
+  const int nn = (int)bt.rlo.size();
+  const int nb = bt.nb;
+  const std::vector<double> bk = coefficients(o.m);
+  st.assign(nn, NodeState());
+  DBuf<int> d_rlo(c.pool, nn), d_rhi(c.pool, nn);
+  h2d(c, d_rlo.get(), bt.rlo.data(), nn);
+  h2d(c, d_rhi.get(), bt.rhi.data(), nn);
+
+  {  // problems whose delta_0 is exactly zero need no iteration
+    std::vector<double> ss = node_sumsq(c, delta, d_rlo.get(), d_rhi.get(), nn);
+    for (int s = 0; s < nn; ++s)
+      if (ss[s] == 0.0) st[s].active = false;
+  }
+
+  std::vector<int> rowlab(nb);
+  std::vector<unsigned char> diag(nb);
+  DBuf<int> d_rowlab(c.pool, nb);
+  DBuf<unsigned char> d_diag(c.pool, nb);
+  bool labels_dirty = true;
+  bool all_active = true;
+
+  for (int k = 1;; ++k) {
+    int n_active = 0;
+    for (auto& s : st) n_active += s.active ? 1 : 0;
+    if (n_active == 0) break;
+    if (k > max_iter)
+      throw Error(LIF_ERR_NO_CONVERGENCE, "refinement did not stop within max_iter = " + std::to_string(max_iter) +
+                                              " iterations");
+    if (labels_dirty) {
+      std::fill(rowlab.begin(), rowlab.end(), -1);
+      all_active = true;
+      for (int s = 0; s < nn; ++s) {
+        if (!st[s].active) {
+          all_active = false;
+          continue;
+        }
+        for (int i = bt.rlo[s]; i < bt.rhi[s]; ++i) rowlab[i] = s;
+      }
+      for (int i = 0; i < nb; ++i) diag[i] = rowlab[i] >= 0 ? 1 : 0;
+      h2d(c, d_rowlab.get(), rowlab.data(), nb);
+      h2d(c, d_diag.get(), diag.data(), nb);
+      labels_dirty = false;
+    }
+    // delta restricted to the problems still iterating
+    Bsr dfilt;
+    const bool restrict_rows = !all_active;
+    if (restrict_rows) dfilt = filter(c, delta, d_rowlab.get(), nullptr, 2);
+    const Bsr& da = restrict_rows ? dfilt : delta;
+
+    // M = Z sum_{k=1}^m b_k delta^k, Horner form, every product truncated
+    Bsr q;
+    if (o.m == 1) {
+      q = axpby(c, bk[1], &da, 0.0, nullptr, 0.0, nullptr);
+    } else {
+      Bsr T = axpby(c, bk[o.m], &da, 0.0, nullptr, bk[o.m - 1], d_diag.get());
+      for (int j = o.m - 2; j >= 1; --j) {
+        Bsr P = spgemm(c, da, false, T, false, o.tau);
+        T = axpby(c, 1.0, &P, 0.0, nullptr, bk[j], d_diag.get());
+      }
+      q = spgemm(c, da, false, T, false, o.tau);
+    }
+    Bsr M = spgemm(c, Z, false, q, false, o.tau);
+    q = Bsr();
+    Bsr Znew = axpby(c, 1.0, &Z, 1.0, &M, 0.0, nullptr);
+    // delta_{k+1} = delta_k - Z_{k+1}^T (S M) - (S M)^T Z_k   (M^T S = (S M)^T)
+    Bsr SM = spgemm(c, S, false, M, false, o.tau);
+    M = Bsr();
+    Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau);
+    Bsr X2 = spgemm(c, SM, true, Z, false, o.tau);
+    SM = Bsr();
+    Bsr t = axpby(c, 1.0, &delta, -1.0, &X1, 0.0, nullptr);
+    X1 = Bsr();
+    delta = axpby(c, 1.0, &t, -1.0, &X2, 0.0, nullptr);
+    t = Bsr();
+    X2 = Bsr();
+    Z = std::move(Znew);
+
+    std::vector<double> ss = node_sumsq(c, delta, d_rlo.get(), d_rhi.get(), nn);
+    for (int s = 0; s < nn; ++s) {
+      NodeState& ns = st[s];
+      if (!ns.active) continue;
+      const double e = std::sqrt(ss[s]);
+      ns.iterations = k;
+      ns.norms.push_back(e);
+      const Step d = stop_decision(k, e, ns.e_prev, ns.has_prev, o.m, o.stop, o.tol, &ns.stagnated);
+      if (d == Step::Diverged)
+        throw Error(LIF_ERR_NO_CONVERGENCE, "refinement diverged: ||delta||_F = " + std::to_string(e) +
+                                                " at iteration " + std::to_string(k) + " of problem " +
+                                                std::to_string(s));
+      ns.e = e;
+      if (d == Step::Stop) {
+        ns.active = false;
+        labels_dirty = true;
+      } else {
+        ns.e_prev = e;
+        ns.has_prev = true;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+const unsigned char* all_rows_on(Ctx& c) {
+  if (!c.ones.get()) {
+    c.ones = DBuf<unsigned char>(c.pool, c.nb);
+    LIF_HIP(hipMemsetAsync(c.ones.get(), 1, c.nb, c.stream));
+  }
+  return c.ones.get();
+}
+
+Plan make_plan(int64_t n, int b, int64_t base_rows) {
+  Plan p;
+  struct Item {
+    int64_t lo, hi;
+    int depth, parent;
+    bool left;
+  };
+  std::vector<Item> stack{{0, n, 0, -1, false}};
+  while (!stack.empty()) {
+    Item it = stack.back();
+    stack.pop_back();
+    const int id = (int)p.nodes.size();
+    p.nodes.push_back(PlanNode{it.lo, it.hi, it.depth});
+    if (it.parent >= 0) {
+      if (it.left)
+        p.nodes[it.parent].left = id;
+      else
+        p.nodes[it.parent].right = id;
+    }
+    p.max_depth = std::max(p.max_depth, it.depth);
+    if (it.hi - it.lo > base_rows) {
+      const int64_t nbr = (it.hi - it.lo + b - 1) / b;
+      const int64_t h = it.lo + ((nbr + 1) / 2) * b;
+      stack.push_back({h, it.hi, it.depth + 1, id, false});
+      stack.push_back({it.lo, h, it.depth + 1, id, true});
+    }
+  }
+  return p;
+}
+
+Bsr run_irsi(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info) {
+  double cs = 0.0;
+  if (o.start == LIF_START_GIVEN) {
+    cs = o.start_value;
+  } else if (o.start == LIF_START_INV_SQRT_LMAX) {
+    cs = 1.0 / std::sqrt(o.start_value);
+  } else {
+    const double beta = gershgorin(c, S);
+    cs = (o.start == LIF_START_SQRT2_OVER_GERSH) ? std::sqrt(2.0 / beta) : 1.0 / std::sqrt(beta);
+  }
+  LIF_REQUIRE(std::isfinite(cs) && cs > 0.0, LIF_ERR_INVALID, "start scale is not a positive finite number");
+  info.start_scale = cs;
+  const unsigned char* on = all_rows_on(c);
+  Bsr Z = axpby(c, 0.0, nullptr, 0.0, nullptr, cs, on);
+  Bsr delta = axpby(c, -cs * cs, &S, 0.0, nullptr, 1.0, on);
+  Batch bt;
+  bt.nb = S.nb;
+  bt.rlo = {0};
+  bt.rhi = {S.nb};
+  std::vector<NodeState> st;
+  refine_batch(c, S, Z, std::move(delta), bt, o, st, o.max_iter);
+  info.iterations_top = st[0].iterations;
+  info.iterations_total = st[0].iterations;
+  info.stagnated = st[0].stagnated;
+  info.delta_top = st[0].e;
+  info.norms_top = st[0].norms;
+  return Z;
+}
+
+Bsr run_refine_from(Ctx& c, const Bsr& S, Bsr&& Z0, const Opts& o, RunInfo& info) {
+  const unsigned char* on = all_rows_on(c);
+  Bsr SZ = spgemm(c, S, false, Z0, false, o.tau);
+  Bsr ZSZ = spgemm(c, Z0, true, SZ, false, o.tau);
+  SZ = Bsr();
+  Bsr delta = axpby(c, -1.0, &ZSZ, 0.0, nullptr, 1.0, on);
+  Batch bt;
+  bt.nb = S.nb;
+  bt.rlo = {0};
+  bt.rhi = {S.nb};
+  std::vector<NodeState> st;
+  Bsr Z = std::move(Z0);
+  refine_batch(c, S, Z, std::move(delta), bt, o, st, o.max_iter);
+  info.iterations_top = st[0].iterations;
+  info.iterations_total = st[0].iterations;
+  info.stagnated = st[0].stagnated;
+  info.delta_top = st[0].e;
+  info.norms_top = st[0].norms;
+  return Z;
+}
+
+Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int64_t, int64_t>>& ranges,
+                          double tau) {
+  const int b = S.b, nb = S.nb;
+  const int nbase = (int)ranges.size();
+  std::vector<int> blk0(nbase), nbbv(nbase), rowsv(nbase), base_of_row(nb, -1);
+  std::vector<int64_t> tile0(nbase);
+  int64_t tiles = 0;
+  int max_nbb = 0;
+  for (int s = 0; s < nbase; ++s) {
+    blk0[s] = (int)(ranges[s].first / b);
+    rowsv[s] = (int)(ranges[s].second - ranges[s].first);
+    nbbv[s] = (rowsv[s] + b - 1) / b;
+    tile0[s] = tiles;
+    tiles += (int64_t)nbbv[s] * (nbbv[s] + 1) / 2;
+    max_nbb = std::max(max_nbb, nbbv[s]);
+    for (int i = 0; i < nbbv[s]; ++i) base_of_row[blk0[s] + i] = s;
+  }
+  DBuf<int> d_blk0(c.pool, nbase), d_nbb(c.pool, nbase), d_rows(c.pool, nbase), d_bor(c.pool, nb),
+      d_err(c.pool, nbase);
+  DBuf<int64_t> d_tile0(c.pool, nbase);
+  h2d(c, d_blk0.get(), blk0.data(), nbase);
+  h2d(c, d_nbb.get(), nbbv.data(), nbase);
+  h2d(c, d_rows.get(), rowsv.data(), nbase);
+  h2d(c, d_bor.get(), base_of_row.data(), nb);
+  h2d(c, d_tile0.get(), tile0.data(), nbase);
+  launch_fill_i32(c, d_err.get(), std::numeric_limits<int>::max(), nbase);
+
+  const size_t tile_doubles = (size_t)b * b;
+  DBuf<double> U(c.pool, (size_t)tiles * tile_doubles);
+  Bsr Z;
+  Z.n = S.n;
+  Z.b = b;
+  Z.nb = nb;
+  Z.val = DBuf<double>(c.pool, (size_t)tiles * tile_doubles);
+  LIF_HIP(hipMemsetAsync(U.get(), 0, (size_t)tiles * tile_doubles * sizeof(double), c.stream));
+  LIF_HIP(hipMemsetAsync(Z.val.get(), 0, (size_t)tiles * tile_doubles * sizeof(double), c.stream));
+  {
+    DBuf<int> rowof(c.pool, (size_t)std::max<int64_t>(S.nnzb, 1));
+    launch_block_row_of(c, S.row_ptr.get(), nb, S.nnzb, rowof.get());
+    launch_chol_scatter(c, rowof.get(), S.col.get(), S.val.get(), S.nnzb, b, d_bor.get(), d_blk0.get(), d_nbb.get(),
+                        d_tile0.get(), U.get());
+  }
+  launch_chol_pad(c, nbase, d_nbb.get(), d_rows.get(), d_tile0.get(), b, U.get(), 1.0);
+  for (int k = 0; k < max_nbb; ++k) {
+    launch_potrf(c, k, nbase, d_nbb.get(), d_blk0.get(), d_tile0.get(), b, U.get(), Z.val.get(), d_err.get());
+    launch_trsm(c, k, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), Z.val.get());
+    launch_update(c, k, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get());
+  }
+  for (int j = 1; j < max_nbb; ++j) launch_trinv(c, j, nbase, d_nbb.get(), d_tile0.get(), b, U.get(), Z.val.get());
+  launch_chol_pad(c, nbase, d_nbb.get(), d_rows.get(), d_tile0.get(), b, Z.val.get(), 0.0);
+  std::vector<int> err(nbase);
+  c.d2h(err.data(), d_err.get(), nbase * sizeof(int));
+  for (int s = 0; s < nbase; ++s)
+    if (err[s] != std::numeric_limits<int>::max())
+      throw Error(LIF_ERR_NOT_PD, "leaf " + std::to_string(s) + " (rows " + std::to_string(ranges[s].first) + ".." +
+                                      std::to_string(ranges[s].second) + "): non-positive pivot at row " +
+                                      std::to_string(err[s]));
+  // block-CSR view of the packed tiles: row I of leaf s holds columns I..end
+  std::vector<int> rp(nb + 1, 0), col;
+  col.reserve((size_t)tiles);
+  for (int I = 0; I < nb; ++I) {
+    const int s = base_of_row[I];
+    if (s >= 0) {
+      const int end = blk0[s] + nbbv[s];
+      for (int J = I; J < end; ++J) col.push_back(J);
+    }
+    rp[I + 1] = (int)col.size();
+  }
+  LIF_REQUIRE((int64_t)col.size() == tiles, LIF_ERR_INVALID, "leaf ranges do not cover whole block rows");
+  Z.nnzb = tiles;
+  Z.row_ptr = DBuf<int>(c.pool, nb + 1);
+  Z.col = DBuf<int>(c.pool, (size_t)tiles);
+  h2d(c, Z.row_ptr.get(), rp.data(), nb + 1);
+  h2d(c, Z.col.get(), col.data(), (size_t)tiles);
+  if (tau > 0.0) {
+    DBuf<double> nrm = block_norms(c, Z);
+    return truncate(c, std::move(Z), nrm.get(), tau);
+  }
+  c.sync();  // host vectors rp/col go out of scope
+  return Z;
+}
+
+Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info) {
+  const int b = S.b, nb = S.nb;
+  const Plan plan = make_plan(S.n, b, o.base_rows);
+  std::vector<std::pair<int64_t, int64_t>> leaves;
+  for (const auto& nd : plan.nodes)
+    if (nd.left < 0) leaves.emplace_back(nd.lo, nd.hi);
+  std::sort(leaves.begin(), leaves.end());
+  Bsr Z = leaf_inverse_cholesky(c, S, leaves, o.tau);
+  info.levels = 0;
+  info.iterations_total = 0;
+  for (int d = plan.max_depth - 1; d >= 0; --d) {
+    std::vector<int> ids;
+    for (int i = 0; i < (int)plan.nodes.size(); ++i)
+      if (plan.nodes[i].depth == d && plan.nodes[i].left >= 0) ids.push_back(i);
+    if (ids.empty()) continue;
+    std::sort(ids.begin(), ids.end(), [&](int a, int x) { return plan.nodes[a].lo < plan.nodes[x].lo; });
+    const int nn = (int)ids.size();
+    Batch bt;
+    bt.nb = nb;
+    std::vector<int> lab(nb, -1), side(nb, -1);
+    for (int s = 0; s < nn; ++s) {
+      const PlanNode& nd = plan.nodes[ids[s]];
+      const int r0 = (int)(nd.lo / b), r1 = (int)((nd.hi + b - 1) / b);
+      const int rm = (int)(plan.nodes[nd.left].hi / b);
+      bt.rlo.push_back(r0);
+      bt.rhi.push_back(r1);
+      for (int i = r0; i < r1; ++i) {
+        lab[i] = s;
+        side[i] = 2 * s + (i >= rm ? 1 : 0);
+      }
+    }
+    DBuf<int> d_lab(c.pool, nb), d_side(c.pool, nb);
+    h2d(c, d_lab.get(), lab.data(), nb);
+    h2d(c, d_side.get(), side.data(), nb);
+    // the level's diagonal problems, and the couplings B of each split
+    Bsr S_lvl = filter(c, S, d_lab.get(), d_lab.get(), 0);
+    Bsr S_up = filter(c, S, d_side.get(), d_side.get(), 1);
+    // delta_0 = -[[0, X], [X^T, 0]], X = (Z_A^T B) Z_C
+    Bsr W = spgemm(c, Z, true, S_up, false, o.tau);
+    S_up = Bsr();
+    Bsr X = spgemm(c, W, false, Z, false, o.tau);
+    W = Bsr();
+    Bsr Xt = transpose(c, X);
+    Bsr delta0 = axpby(c, -1.0, &X, -1.0, &Xt, 0.0, nullptr);
+    X = Bsr();
+    Xt = Bsr();
+    std::vector<NodeState> st;
+    refine_batch(c, S_lvl, Z, std::move(delta0), bt, o, st, o.max_iter);
+    info.levels += 1;
+    for (auto& ns : st) info.iterations_total += ns.iterations;
+    if (d == 0) {
+      info.iterations_top = st[0].iterations;
+      info.stagnated = st[0].stagnated;
+      info.delta_top = st[0].e;
+      info.norms_top = st[0].norms;
+    }
+    c.sync();  // label vectors go out of scope
+  }
+  return Z;
+}
+
+double residual(Ctx& c, const Bsr& S, const Bsr& Z) {
+  Bsr SZ = spgemm(c, S, false, Z, false, 0.0);
+  Bsr ZSZ = spgemm(c, Z, true, SZ, false, 0.0);
+  SZ = Bsr();
+  Bsr R = axpby(c, -1.0, &ZSZ, 0.0, nullptr, 1.0, all_rows_on(c));
+  std::vector<int> lo{0}, hi{S.nb};
+  DBuf<int> d_lo(c.pool, 1), d_hi(c.pool, 1);
+  h2d(c, d_lo.get(), lo.data(), 1);
+  h2d(c, d_hi.get(), hi.data(), 1);
+  std::vector<double> ss = node_sumsq(c, R, d_lo.get(), d_hi.get(), 1);
+  return std::sqrt(ss[0]);
+}
+
+}  // namespace lif

@@ -1,0 +1,66 @@
+// Drivers of the three refinement-based computations: IRSI (Sec. 2.2),
+// localized inverse factorization (Alg. 2) with a batched inverse Cholesky
+// leaf, and the untruncated residual ||I - Z^T S Z||_F (Table 1).
+#pragma once
+
+#include "common.h"
+
+namespace lif {
+
+struct Opts {
+  int m = 4;
+  double tau = 0.0;
+  int prec = LIF_FP64;
+  int stop = LIF_STOP_PAPER;
+  double tol = 1e-10;
+  int max_iter = 100;
+  int64_t base_rows = 4096;
+  int start = LIF_START_SQRT2_OVER_GERSH;
+  double start_value = 0.0;
+  bool checkpoint = false;
+};
+
+// One node of the split tree: scalar rows [lo, hi), lo a multiple of b.
+struct PlanNode {
+  int64_t lo, hi;
+  int depth;
+  int left = -1, right = -1;  // children (indices into the plan), -1 for a leaf
+};
+
+struct Plan {
+  std::vector<PlanNode> nodes;  // nodes[0] is the root
+  int max_depth = 0;
+};
+
+// Split rule: a range of more than base_rows rows is split after its
+// ceil(nb/2) leading blocks.
+Plan make_plan(int64_t n, int b, int64_t base_rows);
+
+struct RunInfo {
+  int iterations_top = 0;
+  int levels = 0;
+  int iterations_total = 0;
+  bool stagnated = false;
+  double start_scale = 0.0;
+  double delta_top = 0.0;
+  std::vector<double> norms_top;
+};
+
+// Identity-like helpers on the context: a per-block-row flag array with
+// every row set.
+const unsigned char* all_rows_on(Ctx& c);
+
+// IRSI: Z_0 = c I, delta_0 = I - c^2 S.
+Bsr run_irsi(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info);
+// Refinement from a given start: delta_0 = I - Z0^T S Z0 (products truncated).
+Bsr run_refine_from(Ctx& c, const Bsr& S, Bsr&& Z0, const Opts& o, RunInfo& info);
+// Localized inverse factorization.
+Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info);
+// Batched leaf factorization of the diagonal ranges [lo_k, hi_k) of S:
+// block-diagonal upper-triangular Z with Z_k^T S_k Z_k = I, truncated at tau.
+Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int64_t, int64_t>>& ranges,
+                          double tau);
+// ||I - Z^T S Z||_F with untruncated products.
+double residual(Ctx& c, const Bsr& S, const Bsr& Z);
+
+}  // namespace lif

@@ -1,0 +1,137 @@
+// Device memory pool and execution context.
+#include "common.h"
+
+namespace lif {
+
+size_t Pool::round(size_t bytes) {
+  // 256-byte granularity below 1 MiB, 1 MiB above: keeps reuse high for the
+  // repeated, similarly sized buffers of the refinement loop.
+  if (bytes < (1u << 20)) return (bytes + 255) & ~size_t(255);
+  return (bytes + (1u << 20) - 1) & ~size_t((1u << 20) - 1);
+}
+
+void* Pool::alloc(size_t bytes) {
+  size_t r = round(bytes);
+  auto it = cache_.find(r);
+  if (it != cache_.end()) {
+    void* p = it->second;
+    cache_.erase(it);
+    live_[p] = r;
+    in_use_ += r;
+    if (in_use_ > peak_) peak_ = in_use_;
+    return p;
+  }
+  if (cap_ && reserved_ + r > cap_) trim();
+  if (cap_ && reserved_ + r > cap_)
+    throw Error(LIF_ERR_OUT_OF_MEMORY, "device memory cap exceeded: need " + std::to_string(r) +
+                                           " more bytes with " + std::to_string(reserved_) +
+                                           " held, cap " + std::to_string(cap_));
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, r);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    trim();
+    e = hipMalloc(&p, r);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(LIF_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(r) + " bytes failed");
+    }
+  }
+  reserved_ += r;
+  live_[p] = r;
+  in_use_ += r;
+  if (in_use_ > peak_) peak_ = in_use_;
+  return p;
+}
+
+void Pool::free(void* p) {
+  auto it = live_.find(p);
+  if (it == live_.end()) return;
+  in_use_ -= it->second;
+  cache_.emplace(it->second, p);
+  live_.erase(it);
+}
+
+void Pool::trim() {
+  if (cache_.empty()) return;
+  // memory in the cache may still be read by queued kernels of the stream
+  // that freed it; wait for the device before giving it back
+  (void)hipDeviceSynchronize();
+  for (auto& kv : cache_) {
+    (void)hipFree(kv.second);
+    reserved_ -= kv.first;
+  }
+  cache_.clear();
+}
+
+void Pool::release_all() {
+  (void)hipDeviceSynchronize();
+  for (auto& kv : cache_) (void)hipFree(kv.second);
+  for (auto& kv : live_) (void)hipFree(kv.first);
+  cache_.clear();
+  live_.clear();
+  reserved_ = in_use_ = 0;
+}
+
+hipEvent_t Ctx::take_event() {
+  if (!ev_free.empty()) {
+    hipEvent_t e = ev_free.back();
+    ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  LIF_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void Ctx::flush_timing() {
+  if (ev_pending.empty()) return;
+  LIF_HIP(hipStreamSynchronize(stream));
+  for (auto& pr : ev_pending) {
+    float ms = 0.f;
+    LIF_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+    stats.gemm_ms += ms;
+    ev_free.push_back(pr.first);
+    ev_free.push_back(pr.second);
+  }
+  ev_pending.clear();
+}
+
+void Ctx::d2h(void* dst, const void* src, size_t bytes) {
+  if (bytes > pinned_bytes) {
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+    size_t want = bytes < 4096 ? 4096 : bytes;
+    LIF_HIP(hipHostMalloc(&pinned, want, hipHostMallocDefault));
+    pinned_bytes = want;
+  }
+  LIF_HIP(hipMemcpyAsync(pinned, src, bytes, hipMemcpyDeviceToHost, stream));
+  LIF_HIP(hipStreamSynchronize(stream));
+  std::memcpy(dst, pinned, bytes);
+}
+
+void Ctx::d2h2(void* d0, const void* s0, size_t b0, void* d1, const void* s1, size_t b1) {
+  if (pinned_bytes < 128) {
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+    LIF_HIP(hipHostMalloc(&pinned, 4096, hipHostMallocDefault));
+    pinned_bytes = 4096;
+  }
+  char* p = static_cast<char*>(pinned);
+  LIF_HIP(hipMemcpyAsync(p, s0, b0, hipMemcpyDeviceToHost, stream));
+  LIF_HIP(hipMemcpyAsync(p + 64, s1, b1, hipMemcpyDeviceToHost, stream));
+  LIF_HIP(hipStreamSynchronize(stream));
+  std::memcpy(d0, p, b0);
+  std::memcpy(d1, p + 64, b1);
+}
+
+Ctx::~Ctx() {
+  for (auto& pr : ev_pending) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  for (auto e : ev_free) (void)hipEventDestroy(e);
+  if (pinned) (void)hipHostFree(pinned);
+}
+
+}  // namespace lif

@@ -1,0 +1,329 @@
+// Block-sparse matrix-matrix product C = op(A) op(B) on b x b dense blocks:
+// the sparse multiplication that dominates all three methods of the paper
+// (Sec. 2, Sec. 4), with zero blocks skipped as the quad-tree skips null
+// children.
+//
+// Symbolic phase (integer, HBM-bound): one workgroup per block row i of C.
+// The output columns of row i are collected in an LDS bitmap over the nb
+// block columns; their number and the number of block products are counted.
+// After a host-side prefix sum the fill pass writes C's sorted column list,
+// a segment pointer per output block, and the (a, b) block-index pairs of
+// each output block in ascending inner index k -- so every output block is
+// summed in the same order on every run (no atomics on values).
+//
+// Numeric phase (FP64 MFMA): one workgroup per output block.  For each pair
+// of its segment the two b x b operand blocks are staged through LDS (k-major
+// layout so MFMA fragments are contiguous 16-double rows), with the next
+// pair's blocks prefetched into registers while the current one is
+// multiplied.  v_mfma_f64_16x16x4f64 accumulates the whole segment in
+// registers; the block is written once, together with its Frobenius norm
+// (fixed-order FP64 reduction) for the truncation pass.
+#include "common.h"
+#include "tile_mma.h"
+
+namespace lif {
+
+namespace {
+
+constexpr int kSymWG = 256;
+
+// ---------------------------------------------------------------------------
+// symbolic
+// ---------------------------------------------------------------------------
+
+__device__ inline void build_row_bitmap(const int* __restrict__ arp, const int* __restrict__ acol,
+                                        const int* __restrict__ brp, const int* __restrict__ bcol, int i,
+                                        unsigned* bm, int nwords, int64_t* pcount) {
+  for (int w = threadIdx.x; w < nwords; w += kSymWG) bm[w] = 0u;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t p = 0;
+  for (int e = arp[i] + wave; e < arp[i + 1]; e += kSymWG / 64) {
+    const int k = acol[e];
+    const int lo = brp[k], hi = brp[k + 1];
+    if (lane == 0) p += hi - lo;
+    for (int f = lo + lane; f < hi; f += 64) {
+      const int j = bcol[f];
+      atomicOr(&bm[j >> 5], 1u << (j & 31));
+    }
+  }
+  if (pcount) *pcount = p;
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kSymWG) void k_symbolic_count(const int* __restrict__ arp, const int* __restrict__ acol,
+                                                           const int* __restrict__ brp, const int* __restrict__ bcol,
+                                                           int nb, int* __restrict__ cnt_c,
+                                                           int64_t* __restrict__ cnt_p) {
+  extern __shared__ unsigned smem[];
+  __shared__ int64_t red_p[kSymWG];
+  __shared__ int red_c[kSymWG];
+  const int i = blockIdx.x;
+  const int nwords = (nb + 31) >> 5;
+  unsigned* bm = smem;
+  int64_t p = 0;
+  build_row_bitmap(arp, acol, brp, bcol, i, bm, nwords, &p);
+  int c = 0;
+  for (int w = threadIdx.x; w < nwords; w += kSymWG) c += __popc(bm[w]);
+  red_p[threadIdx.x] = p;
+  red_c[threadIdx.x] = c;
+  __syncthreads();
+  for (int s = kSymWG / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      red_p[threadIdx.x] += red_p[threadIdx.x + s];
+      red_c[threadIdx.x] += red_c[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    cnt_c[i] = red_c[0];
+    cnt_p[i] = red_p[0];
+  }
+}
+
+// LDS layout of the fill pass: bitmap[nwords] | word_prefix[nwords] | cursor[nb]
+__global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict__ arp, const int* __restrict__ acol,
+                                                          const int* __restrict__ aidx, const int* __restrict__ brp,
+                                                          const int* __restrict__ bcol, const int* __restrict__ bidx,
+                                                          int nb, const int* __restrict__ crp,
+                                                          const int64_t* __restrict__ prp, int* __restrict__ ccol,
+                                                          int64_t* __restrict__ seg, int2* __restrict__ pairs) {
+  extern __shared__ unsigned smem[];
+  __shared__ int scan_tmp[kSymWG];
+  const int i = blockIdx.x;
+  const int nwords = (nb + 31) >> 5;
+  unsigned* bm = smem;
+  int* wp = reinterpret_cast<int*>(smem + nwords);
+  int* cur = wp + nwords;
+  build_row_bitmap(arp, acol, brp, bcol, i, bm, nwords, nullptr);
+
+  // exclusive prefix of word popcounts: contiguous chunks per thread
+  const int chunk = (nwords + kSymWG - 1) / kSymWG;
+  const int w0 = min(nwords, (int)threadIdx.x * chunk), w1 = min(nwords, w0 + chunk);
+  int s = 0;
+  for (int w = w0; w < w1; ++w) s += __popc(bm[w]);
+  scan_tmp[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < kSymWG; off <<= 1) {
+    int v = (threadIdx.x >= off) ? scan_tmp[threadIdx.x - off] : 0;
+    __syncthreads();
+    scan_tmp[threadIdx.x] += v;
+    __syncthreads();
+  }
+  const int ncols = scan_tmp[kSymWG - 1];
+  int run = threadIdx.x ? scan_tmp[threadIdx.x - 1] : 0;
+  for (int w = w0; w < w1; ++w) {
+    wp[w] = run;
+    run += __popc(bm[w]);
+  }
+  __syncthreads();
+
+  // output columns in ascending order; zero the per-output product counters
+  const int cbase = crp[i];
+  for (int w = threadIdx.x; w < nwords; w += kSymWG) {
+    unsigned bits = bm[w];
+    int r = wp[w];
+    while (bits) {
+      const int bit = __ffs(bits) - 1;
+      ccol[cbase + r] = (w << 5) + bit;
+      cur[r] = 0;
+      ++r;
+      bits &= bits - 1;
+    }
+  }
+  __syncthreads();
+
+  // products per output block
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int e = arp[i] + wave; e < arp[i + 1]; e += kSymWG / 64) {
+    const int k = acol[e];
+    for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
+      const int j = bcol[f];
+      const int r = wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u));
+      atomicAdd(&cur[r], 1);
+    }
+  }
+  __syncthreads();
+
+  // exclusive scan of the per-output counts -> segment starts
+  const int c0 = min(ncols, (int)threadIdx.x * ((ncols + kSymWG - 1) / kSymWG));
+  const int c1 = min(ncols, c0 + (ncols + kSymWG - 1) / kSymWG);
+  int t = 0;
+  for (int r = c0; r < c1; ++r) t += cur[r];
+  __syncthreads();
+  scan_tmp[threadIdx.x] = t;
+  __syncthreads();
+  for (int off = 1; off < kSymWG; off <<= 1) {
+    int v = (threadIdx.x >= off) ? scan_tmp[threadIdx.x - off] : 0;
+    __syncthreads();
+    scan_tmp[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t prow = prp[i];
+  int acc = threadIdx.x ? scan_tmp[threadIdx.x - 1] : 0;
+  for (int r = c0; r < c1; ++r) {
+    const int cnt = cur[r];
+    seg[cbase + r] = prow + acc;
+    cur[r] = acc;
+    acc += cnt;
+  }
+  __syncthreads();
+
+  // pairs in ascending k within each output block: the A row is walked in
+  // order; within one k every output column occurs at most once
+  for (int e = arp[i]; e < arp[i + 1]; ++e) {
+    const int k = acol[e];
+    const int a = aidx ? aidx[e] : e;
+    for (int f = brp[k] + threadIdx.x; f < brp[k + 1]; f += kSymWG) {
+      const int j = bcol[f];
+      const int r = wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u));
+      const int pos = cur[r];
+      pairs[prow + pos] = make_int2(a, bidx ? bidx[f] : f);
+      cur[r] = pos + 1;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// numeric
+// ---------------------------------------------------------------------------
+
+__device__ inline int64_t xcd_remap(int64_t wg, int64_t total) {
+  // the dispatcher deals workgroups round-robin to the 8 XCDs; give each XCD
+  // a contiguous run of output blocks (they share A blocks of one row and B
+  // blocks of neighbouring columns in that XCD's L2)
+  const int64_t x = wg & 7, l = wg >> 3;
+  const int64_t q = total >> 3, r = total & 7;
+  return x * q + (x < r ? x : r) + l;
+}
+
+template <int B, bool TA, bool TB>
+__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const double* __restrict__ A,
+                                                                     const double* __restrict__ Bm,
+                                                                     const int64_t* __restrict__ seg,
+                                                                     const int2* __restrict__ pairs, int64_t nnzc,
+                                                                     double* __restrict__ C,
+                                                                     double* __restrict__ norms) {
+  using Cfg = TileCfg<B>;
+  __shared__ double As[Cfg::LDS_DOUBLES];
+  __shared__ double Bs[Cfg::LDS_DOUBLES];
+  __shared__ double red[Cfg::WAVES];
+  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+  if (blk >= nnzc) return;
+  const int64_t p0 = seg[blk], p1 = seg[blk + 1];
+  const Frag f = frag_coords<B>();
+
+  v4d acc[2][2];
+  acc_zero(acc);
+  double2 ra[Cfg::V2], rbv[Cfg::V2];
+  {
+    const int2 pr = pairs[p0];
+    tile_load<B>(A + (int64_t)pr.x * B * B, ra);
+    tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
+  }
+  for (int64_t p = p0; p < p1; ++p) {
+    __syncthreads();
+    // op(A) = A needs LDS row k = column k of the block (transposing store);
+    // op(A) = A^T has it as row k already.  For B the other way round.
+    tile_store<B>(As, ra, TA);
+    tile_store<B>(Bs, rbv, !TB);
+    __syncthreads();
+    if (p + 1 < p1) {
+      const int2 pr = pairs[p + 1];
+      tile_load<B>(A + (int64_t)pr.x * B * B, ra);
+      tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
+    }
+    tile_mma<B>(As, Bs, f, acc);
+  }
+
+  // epilogue: write the block, FP64 sum of squares in a fixed order
+  double* Cb = C + blk * B * B;
+  double ss = 0.0;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double v = acc[ti][tj][r];
+        Cb[acc_row(f, ti, r) * B + acc_col(f, tj)] = v;
+        ss += v * v;
+      }
+  for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+  if (f.lane == 0) red[f.wave] = ss;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < Cfg::WAVES; ++w) t += red[w];
+    norms[blk] = sqrt(t);
+  }
+}
+
+template <int B>
+void launch_numeric_b(Ctx& c, const double* A, const double* Bm, bool ta, bool tb, const int64_t* seg,
+                      const int2* pairs, int64_t nnzc, double* C, double* norms) {
+  using Cfg = TileCfg<B>;
+  dim3 grid((unsigned)nnzc), block(Cfg::THREADS);
+  if (!ta && !tb)
+    hipLaunchKernelGGL((k_numeric_f64<B, false, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, nnzc, C, norms);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((k_numeric_f64<B, true, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, nnzc, C, norms);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((k_numeric_f64<B, false, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, nnzc, C, norms);
+  else
+    hipLaunchKernelGGL((k_numeric_f64<B, true, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, nnzc, C, norms);
+  LIF_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+size_t symbolic_lds_bytes(int nb, bool fill) {
+  const size_t nwords = (size_t)(nb + 31) / 32;
+  return fill ? nwords * 8 + (size_t)nb * 4 : nwords * 4;
+}
+
+static void allow_lds(const void* fn, size_t bytes) {
+  if (bytes > 48 * 1024)
+    LIF_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* brp, const int* bcol, int nb,
+                           int* cnt_c, int64_t* cnt_p) {
+  allow_lds((const void*)k_symbolic_count, symbolic_lds_bytes(nb, false));
+  hipLaunchKernelGGL(k_symbolic_count, dim3(nb), dim3(kSymWG), symbolic_lds_bytes(nb, false), c.stream, arp, acol,
+                     brp, bcol, nb, cnt_c, cnt_p);
+  LIF_HIP(hipGetLastError());
+}
+
+void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp, const int* bcol,
+                          const int* bidx, int nb, const int* crp, const int64_t* prp, int* ccol, int64_t* seg,
+                          int2* pairs) {
+  allow_lds((const void*)k_symbolic_fill, symbolic_lds_bytes(nb, true));
+  hipLaunchKernelGGL(k_symbolic_fill, dim3(nb), dim3(kSymWG), symbolic_lds_bytes(nb, true), c.stream, arp, acol,
+                     aidx, brp, bcol, bidx, nb, crp, prp, ccol, seg, pairs);
+  LIF_HIP(hipGetLastError());
+}
+
+void launch_numeric(Ctx& c, const double* A, const double* B, bool ta, bool tb, const int64_t* seg,
+                    const int2* pairs, int64_t nnzc, int b, double* C, double* norms) {
+  if (nnzc == 0) return;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c.timing) {
+    e0 = c.take_event();
+    e1 = c.take_event();
+    LIF_HIP(hipEventRecord(e0, c.stream));
+  }
+  if (b == 64)
+    launch_numeric_b<64>(c, A, B, ta, tb, seg, pairs, nnzc, C, norms);
+  else
+    launch_numeric_b<32>(c, A, B, ta, tb, seg, pairs, nnzc, C, norms);
+  if (c.timing) {
+    LIF_HIP(hipEventRecord(e1, c.stream));
+    c.ev_pending.emplace_back(e0, e1);
+  }
+  c.stats.gemm_launches += 1;
+}
+
+}  // namespace lif

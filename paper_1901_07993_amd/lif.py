@@ -1,0 +1,244 @@
+"""ctypes binding of the C ABI in include/lif.h (argument marshalling only).
+
+Every computation runs in the HIP library ``liblif.so``; if it is missing or
+cannot be loaded, ``load()`` raises -- there is no other code path.
+
+Matrices are passed as block lists: any object with attributes ``n``, ``b``,
+``brow``, ``bcol``, ``vals`` (numpy arrays: host; torch CUDA tensors: device).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int32, c_int64, c_uint64, c_void_p
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblif.so")
+
+OK, ERR_INVALID, ERR_NOT_PD, ERR_NO_CONVERGENCE, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_STATE = range(7)
+FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
+STOP_PAPER, STOP_TOL = 0, 1
+START_SQRT2_OVER_GERSH, START_INV_SQRT_GERSH, START_INV_SQRT_LMAX, START_GIVEN = 0, 1, 2, 3
+
+_STATUS_NAMES = {1: "LIF_ERR_INVALID", 2: "LIF_ERR_NOT_PD", 3: "LIF_ERR_NO_CONVERGENCE",
+                 4: "LIF_ERR_OUT_OF_MEMORY", 5: "LIF_ERR_HIP", 6: "LIF_ERR_STATE"}
+
+EXPORTED = ("lif_opts_default", "lif_create", "lif_refine", "lif_localized", "lif_get_Z", "lif_residual",
+            "lif_multiply", "lif_destroy", "lif_last_error")
+
+
+class LifError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Blocks(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("b", c_int32), ("nnzb", c_int64), ("brow", c_void_p), ("bcol", c_void_p),
+                ("vals", c_void_p), ("on_device", c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("m", c_int32), ("tau", c_double), ("prec", c_int32), ("stop", c_int32), ("tol", c_double),
+                ("max_iter", c_int32), ("base_rows", c_int64), ("start", c_int32), ("start_value", c_double),
+                ("checkpoint", c_int32), ("mem_cap_bytes", c_uint64), ("stream", c_void_p), ("timing", c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iterations_top", c_int32), ("levels", c_int32), ("iterations_total", c_int32),
+                ("stagnated", c_int32), ("start_scale", c_double), ("delta_tracked", c_double),
+                ("flops_leaf_gemm", c_double), ("seconds_total", c_double), ("seconds_leaf_gemm", c_double),
+                ("leaf_gemm_launches", c_int64), ("products_total", c_int64), ("nnzb_Z", c_int64),
+                ("n_norms", c_int32), ("norms", c_double * 64)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "norms"}
+        d["norms"] = [self.norms[i] for i in range(self.n_norms)]
+        return d
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads liblif.so (built by ``paper_1901_07993_amd.build``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.lif_opts_default.argtypes = [POINTER(Opts)]
+    lib.lif_create.argtypes = [POINTER(Blocks), POINTER(Opts), POINTER(c_void_p)]
+    lib.lif_refine.argtypes = [c_void_p, POINTER(Blocks), POINTER(Info)]
+    lib.lif_localized.argtypes = [c_void_p, POINTER(Info)]
+    lib.lif_get_Z.argtypes = [c_void_p, POINTER(c_int64), c_void_p, c_void_p, c_void_p, c_int32]
+    lib.lif_residual.argtypes = [c_void_p, POINTER(c_double)]
+    lib.lif_multiply.argtypes = [c_void_p, POINTER(Blocks), c_int32, POINTER(Blocks), c_int32, c_double,
+                                 POINTER(c_int64), c_void_p, c_void_p, c_void_p, c_int32, POINTER(c_int64)]
+    lib.lif_destroy.argtypes = [c_void_p]
+    lib.lif_destroy.restype = None
+    lib.lif_last_error.argtypes = [c_void_p]
+    lib.lif_last_error.restype = c_char_p
+    for name in EXPORTED:
+        if name not in ("lif_destroy", "lif_last_error"):
+            getattr(lib, name).restype = c_int32
+    _lib = lib
+    return lib
+
+
+@dataclass
+class HostBlocks:
+    n: int
+    b: int
+    brow: np.ndarray
+    bcol: np.ndarray
+    vals: np.ndarray
+
+    @property
+    def nnzb(self) -> int:
+        return int(self.brow.shape[0])
+
+    @property
+    def nb(self) -> int:
+        return (self.n + self.b - 1) // self.b
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _marshal(M):
+    """(Blocks struct, keep-alive list) for a block list on host or device."""
+    keep = []
+    if _is_torch(M.vals):
+        import torch
+        assert M.vals.is_cuda, "torch block lists must live on the GPU"
+        brow = M.brow.to(torch.int32).contiguous()
+        bcol = M.bcol.to(torch.int32).contiguous()
+        vals = M.vals.to(torch.float64).contiguous()
+        keep += [brow, bcol, vals]
+        st = Blocks(int(M.n), int(M.b), int(brow.shape[0]), brow.data_ptr(), bcol.data_ptr(), vals.data_ptr(), 1)
+    else:
+        brow = np.ascontiguousarray(M.brow, dtype=np.int32)
+        bcol = np.ascontiguousarray(M.bcol, dtype=np.int32)
+        vals = np.ascontiguousarray(M.vals, dtype=np.float64)
+        keep += [brow, bcol, vals]
+        st = Blocks(int(M.n), int(M.b), int(brow.shape[0]), brow.ctypes.data, bcol.ctypes.data, vals.ctypes.data, 0)
+    return st, keep
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:  # noqa: BLE001 - no torch GPU: the null stream
+        pass
+    return ctypes.c_void_p(0)
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    load().lif_opts_default(byref(o))
+    for k, v in kw.items():
+        if k == "stream":
+            o.stream = v
+        else:
+            setattr(o, k, v)
+    return o
+
+
+class Factorization:
+    """One inverse-factorization problem: S (block list) and options.
+
+    Keyword options mirror ``lif_opts``: m, tau, prec, stop, tol, max_iter,
+    base_rows, start, start_value, checkpoint, mem_cap_bytes, timing.
+    """
+
+    def __init__(self, S, **opts):
+        lib = load()
+        if "stream" not in opts:
+            opts["stream"] = _current_stream()
+        self._opts = default_opts(**opts)
+        st, keep = _marshal(S)
+        h = c_void_p()
+        rc = lib.lif_create(byref(st), byref(self._opts), byref(h))
+        del keep
+        if rc != OK:
+            raise LifError(rc, lib.lif_last_error(None).decode())
+        self._h = h
+        self.n, self.b = int(S.n), int(S.b)
+
+    def _check(self, rc):
+        if rc != OK:
+            raise LifError(rc, load().lif_last_error(self._h).decode())
+
+    def refine(self, Z0=None) -> dict:
+        info = Info()
+        if Z0 is None:
+            self._check(load().lif_refine(self._h, None, byref(info)))
+        else:
+            st, keep = _marshal(Z0)
+            self._check(load().lif_refine(self._h, byref(st), byref(info)))
+            del keep
+        return info.as_dict()
+
+    def localized(self) -> dict:
+        info = Info()
+        self._check(load().lif_localized(self._h, byref(info)))
+        return info.as_dict()
+
+    def get_Z(self) -> HostBlocks:
+        lib = load()
+        nnzb = c_int64(0)
+        self._check(lib.lif_get_Z(self._h, byref(nnzb), None, None, None, 0))
+        k = nnzb.value
+        brow = np.empty(k, np.int32)
+        bcol = np.empty(k, np.int32)
+        vals = np.empty((k, self.b, self.b), np.float64)
+        self._check(lib.lif_get_Z(self._h, byref(nnzb), brow.ctypes.data, bcol.ctypes.data, vals.ctypes.data, 0))
+        return HostBlocks(self.n, self.b, brow, bcol, vals)
+
+    def residual(self) -> float:
+        out = c_double(0.0)
+        self._check(load().lif_residual(self._h, byref(out)))
+        return out.value
+
+    def multiply(self, A, transA: bool, B, transB: bool, tau: float = 0.0):
+        """C = op(A) op(B) truncated at tau; returns (HostBlocks, products)."""
+        lib = load()
+        sa, ka = _marshal(A)
+        sb, kb = _marshal(B)
+        nnzb = c_int64(0)
+        prods = c_int64(0)
+        self._check(lib.lif_multiply(self._h, byref(sa), int(transA), byref(sb), int(transB), float(tau), byref(nnzb),
+                                     None, None, None, 0, byref(prods)))
+        k = nnzb.value
+        brow = np.empty(k, np.int32)
+        bcol = np.empty(k, np.int32)
+        vals = np.empty((k, self.b, self.b), np.float64)
+        self._check(lib.lif_multiply(self._h, byref(sa), int(transA), byref(sb), int(transB), float(tau), byref(nnzb),
+                                     brow.ctypes.data, bcol.ctypes.data, vals.ctypes.data, 0, byref(prods)))
+        del ka, kb
+        return HostBlocks(self.n, self.b, brow, bcol, vals), prods.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lif_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

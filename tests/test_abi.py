@@ -1,0 +1,94 @@
+"""The C-ABI library: it loads, exports every entry point include/lif.h
+declares, its structs have the layout the binding assumes, and host-side
+validation rejects malformed input without touching a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1901_07993_amd import lif
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lif.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(lif.LIB_PATH), reason="liblif.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lif_[A-Za-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_functions()
+    assert set(names) == set(lif.EXPORTED)
+    out = subprocess.run(["nm", "-D", "--defined-only", lif.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (lif_\w+)", out))
+    assert set(names) <= exported
+    lib = lif.load()
+    for n in names:
+        assert hasattr(lib, n)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lif.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(lif_blocks), sizeof(lif_opts),'
+                   ' sizeof(lif_info), offsetof(lif_opts, stream), offsetof(lif_info, norms),'
+                   ' offsetof(lif_blocks, on_device)); return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    want = [ctypes.sizeof(lif.Blocks), ctypes.sizeof(lif.Opts), ctypes.sizeof(lif.Info), lif.Opts.stream.offset,
+            lif.Info.norms.offset, lif.Blocks.on_device.offset]
+    assert got == want
+
+
+def test_default_options():
+    o = lif.default_opts()
+    assert (o.m, o.tau, o.prec, o.stop, o.max_iter, o.base_rows) == (4, 0.0, 0, 0, 100, 4096)
+    assert o.tol == 1e-10 and o.timing == 0
+
+
+def _blocks(n, b, rows, cols, vals=None):
+    nnzb = len(rows)
+    v = np.zeros((nnzb, b, b)) if vals is None else vals
+    return lif.HostBlocks(n, b, np.array(rows, np.int32), np.array(cols, np.int32), v)
+
+
+@pytest.mark.parametrize("case,msg", [
+    (dict(n=64, b=16, rows=[0], cols=[0]), "b must be 32 or 64"),
+    (dict(n=128, b=64, rows=[1, 0], cols=[1, 0]), "not sorted"),
+    (dict(n=128, b=64, rows=[0, 0], cols=[0, 0]), "not sorted"),
+    (dict(n=128, b=64, rows=[0, 0, 1], cols=[0, 1, 1]), "not symmetric"),
+    (dict(n=128, b=64, rows=[0, 2], cols=[0, 2]), "out of range"),
+    (dict(n=0, b=64, rows=[], cols=[]), "n must be > 0"),
+])
+def test_invalid_inputs_rejected_on_host(case, msg):
+    S = _blocks(**case)
+    with pytest.raises(lif.LifError) as ei:
+        lif.Factorization(S)
+    assert ei.value.status == lif.ERR_INVALID and msg in str(ei.value)
+
+
+def test_nonzero_padding_rejected():
+    v = np.zeros((1, 64, 64))
+    v[0, 63, 63] = 1.0
+    S = _blocks(100, 64, [1], [1], None)
+    S.vals = np.concatenate([v])
+    with pytest.raises(lif.LifError) as ei:
+        lif.Factorization(S)
+    assert "beyond n" in str(ei.value)
+
+
+@pytest.mark.parametrize("opt,val", [("m", 0), ("m", 9), ("tau", -1.0), ("prec", 7), ("stop", 3),
+                                     ("max_iter", 0), ("base_rows", 16), ("start", 9)])
+def test_invalid_options_rejected(opt, val):
+    S = _blocks(64, 64, [0], [0], np.eye(64)[None])
+    with pytest.raises(lif.LifError) as ei:
+        lif.Factorization(S, **{opt: val})
+    assert ei.value.status == lif.ERR_INVALID

