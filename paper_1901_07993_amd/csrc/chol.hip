@@ -17,6 +17,10 @@
 //   Z_ij = -(sum_{k=i}^{j-1} Z_ik U_kj) Z_jj, i < j
 // Tile products run on FP64 MFMA (tile_mma.h).  Padded rows of the last
 // leaf carry a unit diagonal during the factorization and are zeroed after.
+// A byte per packed tile records whether the tile of S / U can be nonzero:
+// tiles outside S's pattern stay zero unless an update reaches them, and
+// products with a zero U tile are skipped, so a banded S costs a banded
+// Cholesky (the inverse itself fills the upper triangle).
 #include "common.h"
 #include "tile_mma.h"
 
@@ -32,7 +36,8 @@ __global__ __launch_bounds__(256) void k_chol_scatter(const int* __restrict__ ro
                                                       const double* __restrict__ val, int b,
                                                       const int* __restrict__ base_of_row,
                                                       const int* __restrict__ blk0, const int* __restrict__ nbbv,
-                                                      const int64_t* __restrict__ tile0, double* __restrict__ U) {
+                                                      const int64_t* __restrict__ tile0, double* __restrict__ U,
+                                                      unsigned char* __restrict__ nz) {
   const int64_t e = blockIdx.x;
   const int I = row_of[e], J = col[e];
   const int s = base_of_row[I];
@@ -42,6 +47,7 @@ __global__ __launch_bounds__(256) void k_chol_scatter(const int* __restrict__ ro
   const double2* src = reinterpret_cast<const double2*>(val + e * (int64_t)b * b);
   double2* dst = reinterpret_cast<double2*>(U + t * (int64_t)b * b);
   for (int q = threadIdx.x; q < b * b / 2; q += 256) dst[q] = src[q];
+  if (threadIdx.x == 0) nz[t] = 1;
 }
 
 // set (pad = 1) or clear (pad = 0) the diagonal of padded rows of the last tile
@@ -54,14 +60,23 @@ __global__ void k_chol_pad(int nbase, const int* __restrict__ nbbv, const int* _
   for (int r = real + threadIdx.x; r < b; r += blockDim.x) M[t * b * b + (int64_t)r * b + r] = value;
 }
 
+// Cholesky of the diagonal tile (k, k) and the inverse of its factor, in LDS.
+// G = 256 / B threads share a column and split its dot products by residue
+// of the summation index, reducing with lane shuffles (they sit in one wave).
+//   rows of U, top to bottom: s_c = T[j][c] - sum_{i<j} U[i][j] U[i][c],
+//     U[j][j] = sqrt(s_j), U[j][c] = s_c / U[j][j]        (2 barriers per row)
+//   columns of W = U^{-1}, independently: W[c][c] = 1 / U[c][c],
+//     W[r][c] = -sum_{q=r+1}^{c} U[r][q] W[q][c] / U[r][r], r = c-1 .. 0;
+//     the lane owning residue r % G writes W[r][c], and each lane only reads
+//     the W entries of its own residue, so no barrier is needed.
 template <int B>
 __global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nbbv, const int* __restrict__ blk0,
                                                const int64_t* __restrict__ tile0, double* __restrict__ U,
                                                double* __restrict__ Z, int* __restrict__ err) {
   constexpr int L = B + 1;
+  constexpr int G = 256 / B;
   __shared__ double T[B * L];
   __shared__ double W[B * L];
-  __shared__ double piv_inv;
   const int s = blockIdx.x;
   const int nbb = nbbv[s];
   if (k >= nbb) return;
@@ -69,43 +84,46 @@ __global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nb
   double* g = U + t * B * B;
   for (int q = threadIdx.x; q < B * B; q += 256) T[(q / B) * L + (q % B)] = g[q];
   __syncthreads();
+  __shared__ double piv;
+  const int c = threadIdx.x / G, gi = threadIdx.x % G;
   for (int j = 0; j < B; ++j) {
-    if (threadIdx.x == 0) {
-      double d = T[j * L + j];
-      if (!(d > 0.0)) {
-        atomicMin(&err[s], (blk0[s] + k) * B + j);
-        d = 1.0;
-      }
-      const double p = sqrt(d);
-      T[j * L + j] = p;
-      piv_inv = 1.0 / p;
+    double v = 0.0;
+    if (c >= j) {
+      double acc = 0.0;
+      for (int i = gi; i < j; i += G) acc += T[i * L + j] * T[i * L + c];
+      for (int off = 1; off < G; off <<= 1) acc += __shfl_xor(acc, off, 64);
+      v = T[j * L + c] - acc;
+      if (c == j && gi == 0) piv = v;
     }
-    __syncthreads();
-    for (int c = j + 1 + threadIdx.x; c < B; c += 256) T[j * L + c] *= piv_inv;
-    __syncthreads();
-    const int m = B - j - 1;
-    for (int q = threadIdx.x; q < m * m; q += 256) {
-      const int r = j + 1 + q / m, c = j + 1 + q % m;
-      if (c >= r) T[r * L + c] -= T[j * L + r] * T[j * L + c];
+    __syncthreads();  // pivot visible; every read of row j's old values done
+    double d = piv;
+    if (!(d > 0.0)) {
+      if (threadIdx.x == 0) atomicMin(&err[s], (blk0[s] + k) * B + j);
+      d = 1.0;
     }
-    __syncthreads();
+    const double p = sqrt(d);
+    if (gi == 0 && c >= j) T[j * L + c] = (c == j) ? p : v / p;
+    __syncthreads();  // row j of U final before the next row reads it
   }
-  // inverse of the upper factor, one column per thread (back substitution)
-  for (int c = threadIdx.x; c < B; c += 256) {
-    for (int r = 0; r < B; ++r) W[r * L + c] = 0.0;
-    W[c * L + c] = 1.0 / T[c * L + c];
+  for (int r = gi; r < B; r += G) W[r * L + c] = 0.0;
+  {
+    const double wcc = 1.0 / T[c * L + c];
+    if (c % G == gi) W[c * L + c] = wcc;
     for (int r = c - 1; r >= 0; --r) {
       double acc = 0.0;
-      for (int q = r + 1; q <= c; ++q) acc += T[r * L + q] * W[q * L + c];
-      W[r * L + c] = -acc / T[r * L + r];
+      // q in (r, c] with q % G == gi
+      int q0 = r + 1 + ((gi - (r + 1) % G) + G) % G;
+      for (int q = q0; q <= c; q += G) acc += T[r * L + q] * W[q * L + c];
+      for (int off = 1; off < G; off <<= 1) acc += __shfl_xor(acc, off, 64);
+      if (r % G == gi) W[r * L + c] = -acc / T[r * L + r];
     }
   }
   __syncthreads();
   double* gz = Z + t * B * B;
   for (int q = threadIdx.x; q < B * B; q += 256) {
-    const int r = q / B, c = q % B;
-    g[q] = (c >= r) ? T[r * L + c] : 0.0;
-    gz[q] = W[r * L + c];
+    const int r = q / B, cc = q % B;
+    g[q] = (cc >= r) ? T[r * L + cc] : 0.0;
+    gz[q] = (cc >= r) ? W[r * L + cc] : 0.0;
   }
 }
 
@@ -113,14 +131,15 @@ __global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nb
 template <int B>
 __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trsm(int k, const int* __restrict__ nbbv,
                                                               const int64_t* __restrict__ tile0,
-                                                              double* __restrict__ U, const double* __restrict__ Z) {
+                                                              double* __restrict__ U, const double* __restrict__ Z,
+                                                              const unsigned char* __restrict__ nz) {
   using Cfg = TileCfg<B>;
   __shared__ double As[Cfg::LDS_DOUBLES];
   __shared__ double Bs[Cfg::LDS_DOUBLES];
   const int s = blockIdx.y;
   const int nbb = nbbv[s];
   const int j = k + 1 + blockIdx.x;
-  if (j >= nbb) return;
+  if (j >= nbb || !nz[packed_tile(tile0[s], nbb, k, j)]) return;
   const Frag f = frag_coords<B>();
   double2 reg[Cfg::V2];
   tile_load<B>(Z + packed_tile(tile0[s], nbb, k, k) * B * B, reg);
@@ -153,7 +172,7 @@ __device__ inline void tri_decode(int64_t t, int& ip, int& jp) {
 template <int B>
 __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_update(int k, const int* __restrict__ nbbv,
                                                                 const int64_t* __restrict__ tile0,
-                                                                double* __restrict__ U) {
+                                                                double* __restrict__ U, unsigned char* __restrict__ nz) {
   using Cfg = TileCfg<B>;
   __shared__ double As[Cfg::LDS_DOUBLES];
   __shared__ double Bs[Cfg::LDS_DOUBLES];
@@ -165,6 +184,7 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_update(int k, const int
   int ip, jp;
   tri_decode(t, ip, jp);
   const int i = k + 1 + ip, j = k + 1 + jp;
+  if (!nz[packed_tile(tile0[s], nbb, k, i)] || !nz[packed_tile(tile0[s], nbb, k, j)]) return;
   const Frag f = frag_coords<B>();
   double2 reg[Cfg::V2];
   tile_load<B>(U + packed_tile(tile0[s], nbb, k, i) * B * B, reg);
@@ -185,6 +205,7 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_update(int k, const int
         const int idx = acc_row(f, ti, r) * B + acc_col(f, tj);
         g[idx] -= acc[ti][tj][r];
       }
+  if (threadIdx.x == 0) nz[packed_tile(tile0[s], nbb, i, j)] = 1;
 }
 
 // Z_ij = -(sum_{k=i}^{j-1} Z_ik U_kj) Z_jj for i = blockIdx.x < j
@@ -192,7 +213,8 @@ template <int B>
 __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, const int* __restrict__ nbbv,
                                                                const int64_t* __restrict__ tile0,
                                                                const double* __restrict__ U,
-                                                               double* __restrict__ Z) {
+                                                               double* __restrict__ Z,
+                                                               const unsigned char* __restrict__ nz) {
   using Cfg = TileCfg<B>;
   __shared__ double As[Cfg::LDS_DOUBLES];
   __shared__ double Bs[Cfg::LDS_DOUBLES];
@@ -205,7 +227,10 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, const int*
   v4d acc[2][2];
   acc_zero(acc);
   double2 ra[Cfg::V2], rb[Cfg::V2];
+  int used = 0;
   for (int k = i; k < j; ++k) {
+    if (!nz[packed_tile(t0, nbb, k, j)]) continue;  // U_kj = 0
+    ++used;
     tile_load<B>(Z + packed_tile(t0, nbb, i, k) * B * B, ra);
     tile_load<B>(U + packed_tile(t0, nbb, k, j) * B * B, rb);
     __syncthreads();
@@ -214,6 +239,7 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, const int*
     __syncthreads();
     tile_mma<B>(As, Bs, f, acc);
   }
+  if (used == 0) return;  // Z_ij = 0 (the buffer starts zeroed)
   __syncthreads();
   // W (accumulators) becomes the A operand: LDS row c holds column c of W
 #pragma unroll
@@ -245,10 +271,11 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, const int*
   } while (0)
 
 void launch_chol_scatter(Ctx& c, const int* row_of, const int* col, const double* val, int64_t nnzb, int b,
-                         const int* base_of_row, const int* blk0, const int* nbb, const int64_t* tile0, double* U) {
+                         const int* base_of_row, const int* blk0, const int* nbb, const int64_t* tile0, double* U,
+                         unsigned char* nz) {
   if (nnzb == 0) return;
   LIF_LAUNCH(k_chol_scatter, dim3((unsigned)nnzb), dim3(256), 0, c.stream, row_of, col, val, b, base_of_row, blk0,
-             nbb, tile0, U);
+             nbb, tile0, U, nz);
 }
 
 void launch_chol_pad(Ctx& c, int nbase, const int* nbb, const int* rows, const int64_t* tile0, int b, double* M,
@@ -265,32 +292,34 @@ void launch_potrf(Ctx& c, int k, int nbase, const int* nbb, const int* blk0, con
 }
 
 void launch_trsm(Ctx& c, int k, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b, double* U,
-                 const double* Z) {
+                 const double* Z, const unsigned char* nz) {
   if (max_nbb - k - 1 <= 0) return;
   dim3 grid(max_nbb - k - 1, nbase);
   if (b == 64)
-    LIF_LAUNCH(k_trsm<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, k, nbb, tile0, U, Z);
+    LIF_LAUNCH(k_trsm<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, k, nbb, tile0, U, Z, nz);
   else
-    LIF_LAUNCH(k_trsm<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, k, nbb, tile0, U, Z);
+    LIF_LAUNCH(k_trsm<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, k, nbb, tile0, U, Z, nz);
 }
 
-void launch_update(Ctx& c, int k, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b, double* U) {
+void launch_update(Ctx& c, int k, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b, double* U,
+                   unsigned char* nz) {
   const int64_t m = max_nbb - k - 1;
   if (m <= 0) return;
   dim3 grid((unsigned)(m * (m + 1) / 2), nbase);
   if (b == 64)
-    LIF_LAUNCH(k_update<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, k, nbb, tile0, U);
+    LIF_LAUNCH(k_update<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, k, nbb, tile0, U, nz);
   else
-    LIF_LAUNCH(k_update<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, k, nbb, tile0, U);
+    LIF_LAUNCH(k_update<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, k, nbb, tile0, U, nz);
 }
 
-void launch_trinv(Ctx& c, int j, int nbase, const int* nbb, const int64_t* tile0, int b, const double* U, double* Z) {
+void launch_trinv(Ctx& c, int j, int nbase, const int* nbb, const int64_t* tile0, int b, const double* U, double* Z,
+                  const unsigned char* nz) {
   if (j <= 0) return;
   dim3 grid(j, nbase);
   if (b == 64)
-    LIF_LAUNCH(k_trinv<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, j, nbb, tile0, U, Z);
+    LIF_LAUNCH(k_trinv<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, j, nbb, tile0, U, Z, nz);
   else
-    LIF_LAUNCH(k_trinv<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, j, nbb, tile0, U, Z);
+    LIF_LAUNCH(k_trinv<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, j, nbb, tile0, U, Z, nz);
 }
 
 }  // namespace lif

@@ -198,15 +198,18 @@ void launch_numeric(Ctx& c, const double* A, const double* B, bool ta, bool tb, 
 
 // chol.hip -- batched leaf inverse Cholesky on packed upper tile grids
 void launch_chol_scatter(Ctx& c, const int* row_of, const int* col, const double* val, int64_t nnzb, int b,
-                         const int* base_of_row, const int* blk0, const int* nbb, const int64_t* tile0, double* U);
+                         const int* base_of_row, const int* blk0, const int* nbb, const int64_t* tile0, double* U,
+                         unsigned char* nz);
 void launch_chol_pad(Ctx& c, int nbase, const int* nbb, const int* rows, const int64_t* tile0, int b, double* M,
                      double value);
 void launch_potrf(Ctx& c, int k, int nbase, const int* nbb, const int* blk0, const int64_t* tile0, int b, double* U,
                   double* Z, int* err);
 void launch_trsm(Ctx& c, int k, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b, double* U,
-                 const double* Z);
-void launch_update(Ctx& c, int k, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b, double* U);
-void launch_trinv(Ctx& c, int j, int nbase, const int* nbb, const int64_t* tile0, int b, const double* U, double* Z);
+                 const double* Z, const unsigned char* nz);
+void launch_update(Ctx& c, int k, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b, double* U,
+                   unsigned char* nz);
+void launch_trinv(Ctx& c, int j, int nbase, const int* nbb, const int64_t* tile0, int b, const double* U, double* Z,
+                  const unsigned char* nz);
 
 // ---------------------------------------------------------------------------
 // Block-sparse operations (ops.cpp): allocate outputs, run the kernels,

@@ -278,6 +278,8 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   h2d(c, d_bor.get(), base_of_row.data(), nb);
   h2d(c, d_tile0.get(), tile0.data(), nbase);
   launch_fill_i32(c, d_err.get(), std::numeric_limits<int>::max(), nbase);
+  DBuf<unsigned char> nz(c.pool, (size_t)tiles);
+  LIF_HIP(hipMemsetAsync(nz.get(), 0, (size_t)tiles, c.stream));
 
   const size_t tile_doubles = (size_t)b * b;
   DBuf<double> U(c.pool, (size_t)tiles * tile_doubles);
@@ -292,15 +294,16 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
     DBuf<int> rowof(c.pool, (size_t)std::max<int64_t>(S.nnzb, 1));
     launch_block_row_of(c, S.row_ptr.get(), nb, S.nnzb, rowof.get());
     launch_chol_scatter(c, rowof.get(), S.col.get(), S.val.get(), S.nnzb, b, d_bor.get(), d_blk0.get(), d_nbb.get(),
-                        d_tile0.get(), U.get());
+                        d_tile0.get(), U.get(), nz.get());
   }
   launch_chol_pad(c, nbase, d_nbb.get(), d_rows.get(), d_tile0.get(), b, U.get(), 1.0);
   for (int k = 0; k < max_nbb; ++k) {
     launch_potrf(c, k, nbase, d_nbb.get(), d_blk0.get(), d_tile0.get(), b, U.get(), Z.val.get(), d_err.get());
-    launch_trsm(c, k, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), Z.val.get());
-    launch_update(c, k, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get());
+    launch_trsm(c, k, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), Z.val.get(), nz.get());
+    launch_update(c, k, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), nz.get());
   }
-  for (int j = 1; j < max_nbb; ++j) launch_trinv(c, j, nbase, d_nbb.get(), d_tile0.get(), b, U.get(), Z.val.get());
+  for (int j = 1; j < max_nbb; ++j)
+    launch_trinv(c, j, nbase, d_nbb.get(), d_tile0.get(), b, U.get(), Z.val.get(), nz.get());
   launch_chol_pad(c, nbase, d_nbb.get(), d_rows.get(), d_tile0.get(), b, Z.val.get(), 0.0);
   std::vector<int> err(nbase);
   c.d2h(err.data(), d_err.get(), nbase * sizeof(int));
@@ -326,12 +329,10 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   Z.col = DBuf<int>(c.pool, (size_t)tiles);
   h2d(c, Z.row_ptr.get(), rp.data(), nb + 1);
   h2d(c, Z.col.get(), col.data(), (size_t)tiles);
-  if (tau > 0.0) {
-    DBuf<double> nrm = block_norms(c, Z);
-    return truncate(c, std::move(Z), nrm.get(), tau);
-  }
-  c.sync();  // host vectors rp/col go out of scope
-  return Z;
+  // leaf truncation (Sec. 5); exactly-zero tiles of the triangle are dropped
+  // as well (the smallest positive double as threshold at tau = 0)
+  DBuf<double> nrm = block_norms(c, Z);
+  return truncate(c, std::move(Z), nrm.get(), std::max(tau, std::numeric_limits<double>::denorm_min()));
 }
 
 Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info) {

@@ -223,6 +223,32 @@ def test_leaf_only_is_inverse_cholesky():
     assert np.max(np.abs(Z - Zo)) <= 1e-12 * np.max(np.abs(Zo))
 
 
+@pytest.mark.parametrize("b", [32, 64])
+def test_leaf_fill_in_outside_pattern(b):
+    # arrowhead S: dense first block row/column plus the block diagonal; the
+    # Cholesky factor fills the whole upper triangle beyond S's pattern
+    n = 9 * b - 5
+    nb = 9
+    rng = np.random.default_rng(12)
+    D = np.zeros((n, n))
+    A = rng.standard_normal((b, n)) * 0.1
+    D[:b, :] = A
+    D[:, :b] = A.T
+    for i in range(nb):
+        lo, hi = i * b, min(n, (i + 1) * b)
+        Q = rng.standard_normal((hi - lo, hi - lo)) * 0.1
+        D[lo:hi, lo:hi] = Q @ Q.T + np.eye(hi - lo) * (b * 0.2)
+    D = 0.5 * (D + D.T)
+    assert np.linalg.eigvalsh(D)[0] > 0
+    S = dense_to_blocks(D, b)
+    say(f"case leaf fill-in arrowhead b={b} n={n}")
+    with lif.Factorization(dev(S), base_rows=n) as f:
+        f.localized()
+        Z = blocks_to_dense(f.get_Z())
+    Zo = R.inverse_cholesky(D)
+    assert np.max(np.abs(Z - Zo)) <= 1e-12 * np.max(np.abs(Zo))
+
+
 def test_lif_chain_matches_oracle():
     S, cfg = config_matrix(1, count=150)   # n = 3000 chain, b = 64
     D = blocks_to_dense(S)

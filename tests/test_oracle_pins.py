@@ -313,7 +313,7 @@ def test_truncation_threshold_is_strict():
 
 
 def test_truncated_methods_order_and_floor(water100):
-    # Sec. 5.5: RINCH most accurate, IRSI least, LIF in between (tau > 0)
+    # Sec. 5.4 (Table 1): RINCH most accurate, IRSI least, LIF in between (tau > 0)
     D, _ = water100
     tau = 1e-5
     Dt = R.truncate(D, 32, tau)
