@@ -149,7 +149,9 @@ lif_status lif_residual(lif_handle h, double* out);
 /* C = op(A) op(B) truncated at tau: the block-sparse product of Sec. 4 with
  * the leaf truncation of Sec. 5, on the handle's stream and memory.  op is
  * the identity (trans = 0) or the transpose (trans = 1).  A and B must have
- * the handle's n and b.  Two-phase output like lif_get_Z (the product is
+ * the handle's n and b.  The product uses the handle's opts.prec: FP64, or
+ * inputs rounded to FP32 / BF16 (round to nearest even; BF16 via FP32) with
+ * FP32 accumulation and an FP64 result.  Two-phase output like lif_get_Z (the product is
  * recomputed on the second call); *products receives the number of block
  * products (may be NULL). */
 lif_status lif_multiply(lif_handle h, const lif_blocks* A, int32_t transA, const lif_blocks* B,

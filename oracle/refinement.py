@@ -64,9 +64,33 @@ def truncate(X: np.ndarray, b: int, tau: float) -> np.ndarray:
     return np.where(mask, X, 0.0)
 
 
-def mult(A: np.ndarray, B: np.ndarray, b: int, tau: float) -> np.ndarray:
-    """A matrix-matrix product followed by truncation."""
-    return truncate(A @ B, b, tau)
+def round_to(X: np.ndarray, prec: str) -> np.ndarray:
+    """Input rounding of the precision form (values returned as FP64).
+
+    ``"fp32"``: round to nearest even FP32.  ``"bf16"``: round to FP32 first,
+    then to BF16 by round to nearest even on the 32-bit pattern (add 0x7FFF
+    plus the lowest kept bit, drop the low 16 bits); infinities and NaN keep
+    their high half.  ``"fp64"``: unchanged.
+    """
+    if prec == "fp64":
+        return X
+    f = np.asarray(X, dtype=np.float64).astype(np.float32)
+    if prec == "fp32":
+        return f.astype(np.float64)
+    if prec != "bf16":
+        raise ValueError(prec)
+    u = f.view(np.uint32).astype(np.uint64)
+    special = (u & 0x7F800000) == 0x7F800000
+    rounded = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    kept = np.where(special, (u >> 16) << 16, rounded) & 0xFFFFFFFF
+    return kept.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def mult(A: np.ndarray, B: np.ndarray, b: int, tau: float, prec: str = "fp64") -> np.ndarray:
+    """A matrix-matrix product followed by truncation.  With ``prec`` fp32 or
+    bf16 the inputs are rounded first (the precision form: reduced-precision
+    inputs, the products of the rounded values summed, FP64 result)."""
+    return truncate(round_to(A, prec) @ round_to(B, prec), b, tau)
 
 
 def gershgorin_bound(S: np.ndarray) -> float:
@@ -153,7 +177,8 @@ def stop_now(k: int, e: float, e_prev: float | None, m: int, stop: str, tol: flo
     raise ValueError(stop)
 
 
-def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_iter=100, info=None):
+def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_iter=100, info=None,
+                         prec="fp64"):
     """Localized iterative refinement (eq. refinement_local; Alg. 2 repeat loop).
 
     Each iteration, with T_k the Horner terms of sum_{k=1}^m b_k delta^k:
@@ -165,6 +190,8 @@ def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_
         SM = S M                     (truncated)
         delta' = delta - Z'^T SM - SM^T Z      (each product truncated;
                                                 M^T S is formed as (SM)^T)
+    ``prec`` applies to the products that form M (delta T and Z q); the
+    delta-update products stay FP64.
     Returns (Z, RefineInfo).
     """
     info = info if info is not None else RefineInfo()
@@ -181,9 +208,9 @@ def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_
         else:
             T = bk[m - 1] * I + bk[m] * delta
             for j in range(m - 2, 0, -1):
-                T = bk[j] * I + mult(delta, T, b, tau)
-            q = mult(delta, T, b, tau)
-        M = mult(Z, q, b, tau)
+                T = bk[j] * I + mult(delta, T, b, tau, prec)
+            q = mult(delta, T, b, tau, prec)
+        M = mult(Z, q, b, tau, prec)
         Z_new = Z + M
         SM = mult(S, M, b, tau)
         X1 = mult(Z_new.T, SM, b, tau)
@@ -238,7 +265,7 @@ def nonlocal_refinement(S, Z0, b, tau, m=4, iterations=None, stop="paper", tol=0
 # ----------------------------------------------------------------------------
 
 def irsi(S, b, tau, m=4, start="sqrt2_over_gersh", start_value=None, stop="paper", tol=0.0,
-         max_iter=100, truncate_input=True):
+         max_iter=100, truncate_input=True, prec="fp64"):
     """Iterative refinement from a scaled identity (IRSI, Sec. 2.2):
     Z_0 = c I, delta_0 = I - c^2 S (a scaling, no product), then localized
     refinement.  Returns (Z, RefineInfo, c)."""
@@ -247,7 +274,7 @@ def irsi(S, b, tau, m=4, start="sqrt2_over_gersh", start_value=None, stop="paper
     n = S.shape[0]
     Z0 = c * np.eye(n)
     delta0 = np.eye(n) - (c * c) * St
-    Z, info = localized_refinement(St, Z0, delta0, b, tau, m, stop, tol, max_iter)
+    Z, info = localized_refinement(St, Z0, delta0, b, tau, m, stop, tol, max_iter, prec=prec)
     return Z, info, c
 
 
@@ -274,7 +301,7 @@ def lif_plan(n: int, b: int, base_rows: int) -> LifNode:
 
 
 def lif(S, b, tau, m=4, base_rows=4096, stop="paper", tol=0.0, max_iter=100, truncate_input=True,
-        plan=None):
+        plan=None, prec="fp64"):
     """Localized inverse factorization (Alg. 2) with an inverse Cholesky leaf.
 
     For a node with children A (leading rows) and C:
@@ -306,7 +333,7 @@ def lif(S, b, tau, m=4, base_rows=4096, stop="paper", tol=0.0, max_iter=100, tru
         delta0[h:, :h] = -X.T
         node.delta0_norm2 = float(np.linalg.norm(delta0, 2)) if rows <= 4000 else float("nan")
         node.info = RefineInfo()
-        Z, _ = localized_refinement(Sn, Z0, delta0, b, tau, m, stop, tol, max_iter, node.info)
+        Z, _ = localized_refinement(Sn, Z0, delta0, b, tau, m, stop, tol, max_iter, node.info, prec=prec)
         return Z
 
     return rec(plan), plan

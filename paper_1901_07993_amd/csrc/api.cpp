@@ -27,7 +27,8 @@ thread_local std::string g_create_error;
 void validate_opts(const lif_opts& o) {
   LIF_REQUIRE(o.m >= 1 && o.m <= 8, LIF_ERR_INVALID, "opts.m must be in 1..8");
   LIF_REQUIRE(std::isfinite(o.tau) && o.tau >= 0.0, LIF_ERR_INVALID, "opts.tau must be finite and >= 0");
-  LIF_REQUIRE(o.prec == LIF_FP64, LIF_ERR_INVALID, "opts.prec: only LIF_FP64 is available in this build");
+  LIF_REQUIRE(o.prec == LIF_FP64 || o.prec == LIF_MIXED_FP32 || o.prec == LIF_MIXED_BF16, LIF_ERR_INVALID,
+              "opts.prec is invalid");
   LIF_REQUIRE(o.stop == LIF_STOP_PAPER || o.stop == LIF_STOP_TOL, LIF_ERR_INVALID, "opts.stop is invalid");
   LIF_REQUIRE(std::isfinite(o.tol) && o.tol >= 0.0, LIF_ERR_INVALID, "opts.tol must be finite and >= 0");
   LIF_REQUIRE(o.max_iter >= 1 && o.max_iter <= 10000, LIF_ERR_INVALID, "opts.max_iter must be in 1..10000");
@@ -320,7 +321,7 @@ lif_status lif_multiply(lif_handle h, const lif_blocks* A, int32_t transA, const
     reset_stats(h);
     Bsr a = bsr_from_blocks(h->ctx, *A);
     Bsr b = bsr_from_blocks(h->ctx, *B);
-    Bsr C = spgemm(h->ctx, a, transA != 0, b, transB != 0, tau);
+    Bsr C = spgemm(h->ctx, a, transA != 0, b, transB != 0, tau, h->opts.prec);
     if (products) *products = h->ctx.stats.products;
     st = copy_out(h, C, nnzb, brow, bcol, vals, on_device);
     h->ctx.sync();

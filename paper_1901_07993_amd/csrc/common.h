@@ -109,6 +109,7 @@ struct Bsr {
 // Per-call statistics.
 struct Stats {
   double flops = 0;
+  double flops_lowp = 0;  // part of flops done with FP32/BF16 inputs
   int64_t products = 0;
   int64_t gemm_launches = 0;
   double gemm_ms = 0;
@@ -192,9 +193,13 @@ void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* b
 void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp,
                           const int* bcol, const int* bidx, int nb, const int* crp,
                           const int64_t* prp, int* ccol, int64_t* seg, int2* pairs);
-// Numeric phase: C_blk = sum over its segment of op(A_a) op(B_b).
-void launch_numeric(Ctx& c, const double* A, const double* B, bool ta, bool tb, const int64_t* seg,
+// Numeric phase: C_blk = sum over its segment of op(A_a) op(B_b), in FP64
+// (prec = LIF_FP64) or with FP32 / BF16 inputs and FP32 accumulation.
+void launch_numeric(Ctx& c, int prec, const double* A, const double* B, bool ta, bool tb, const int64_t* seg,
                     const int2* pairs, int64_t nnzc, int b, double* C, double* norms);
+// spgemm_mixed.hip
+void launch_numeric_mixed(Ctx& c, int prec, const double* A, const double* Bm, bool ta, bool tb,
+                          const int64_t* seg, const int2* pairs, int64_t nnzc, int b, double* C, double* norms);
 
 // chol.hip -- batched leaf inverse Cholesky on packed upper tile grids
 void launch_chol_scatter(Ctx& c, const int* row_of, const int* col, const double* val, int64_t nnzb, int b,
@@ -234,7 +239,7 @@ DBuf<double> block_norms(Ctx& c, const Bsr& A);
 Bsr truncate(Ctx& c, Bsr&& A, const double* norms, double tau);
 CsrView transpose_view(Ctx& c, const Bsr& A);
 Bsr transpose(Ctx& c, const Bsr& A);
-Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau);
+Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec = LIF_FP64);
 // alpha A + beta B + gamma I on the block rows with diag_on set (A or B may be null)
 Bsr axpby(Ctx& c, double alpha, const Bsr* A, double beta, const Bsr* B, double gamma,
           const unsigned char* diag_on);

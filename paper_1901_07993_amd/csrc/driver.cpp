@@ -110,19 +110,21 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
     if (restrict_rows) dfilt = filter(c, delta, d_rowlab.get(), nullptr, 2);
     const Bsr& da = restrict_rows ? dfilt : delta;
 
-    // M = Z sum_{k=1}^m b_k delta^k, Horner form, every product truncated
+    // M = Z sum_{k=1}^m b_k delta^k, Horner form, every product truncated;
+    // these products run in the requested input precision (FP32 accumulation
+    // when reduced), the delta-update below always in FP64
     Bsr q;
     if (o.m == 1) {
       q = axpby(c, bk[1], &da, 0.0, nullptr, 0.0, nullptr);
     } else {
       Bsr T = axpby(c, bk[o.m], &da, 0.0, nullptr, bk[o.m - 1], d_diag.get());
       for (int j = o.m - 2; j >= 1; --j) {
-        Bsr P = spgemm(c, da, false, T, false, o.tau);
+        Bsr P = spgemm(c, da, false, T, false, o.tau, o.prec);
         T = axpby(c, 1.0, &P, 0.0, nullptr, bk[j], d_diag.get());
       }
-      q = spgemm(c, da, false, T, false, o.tau);
+      q = spgemm(c, da, false, T, false, o.tau, o.prec);
     }
-    Bsr M = spgemm(c, Z, false, q, false, o.tau);
+    Bsr M = spgemm(c, Z, false, q, false, o.tau, o.prec);
     q = Bsr();
     Bsr Znew = axpby(c, 1.0, &Z, 1.0, &M, 0.0, nullptr);
     // delta_{k+1} = delta_k - Z_{k+1}^T (S M) - (S M)^T Z_k   (M^T S = (S M)^T)

@@ -148,7 +148,7 @@ Bsr transpose(Ctx& c, const Bsr& A) {
   return T;
 }
 
-Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau) {
+Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec) {
   LIF_REQUIRE(A.nb == B.nb && A.b == B.b, LIF_ERR_INVALID, "spgemm: operand shapes differ");
   const int nb = A.nb;
   Bsr C;
@@ -190,9 +190,12 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau) {
   }
   C.val = DBuf<double>(c.pool, (size_t)nnzc * C.b * C.b);
   DBuf<double> nrm(c.pool, (size_t)nnzc);
-  launch_numeric(c, A.val.get(), B.val.get(), ta, tb, seg.get(), pairs.get(), nnzc, C.b, C.val.get(), nrm.get());
+  launch_numeric(c, prec, A.val.get(), B.val.get(), ta, tb, seg.get(), pairs.get(), nnzc, C.b, C.val.get(),
+                 nrm.get());
   c.stats.products += P;
-  c.stats.flops += 2.0 * (double)C.b * C.b * C.b * (double)P;
+  const double fl = 2.0 * (double)C.b * C.b * C.b * (double)P;
+  c.stats.flops += fl;
+  if (prec != LIF_FP64) c.stats.flops_lowp += fl;
   return truncate(c, std::move(C), nrm.get(), tau);
 }
 

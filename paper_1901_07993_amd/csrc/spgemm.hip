@@ -306,7 +306,7 @@ void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* ai
   LIF_HIP(hipGetLastError());
 }
 
-void launch_numeric(Ctx& c, const double* A, const double* B, bool ta, bool tb, const int64_t* seg,
+void launch_numeric(Ctx& c, int prec, const double* A, const double* B, bool ta, bool tb, const int64_t* seg,
                     const int2* pairs, int64_t nnzc, int b, double* C, double* norms) {
   if (nnzc == 0) return;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -315,7 +315,9 @@ void launch_numeric(Ctx& c, const double* A, const double* B, bool ta, bool tb, 
     e1 = c.take_event();
     LIF_HIP(hipEventRecord(e0, c.stream));
   }
-  if (b == 64)
+  if (prec != LIF_FP64)
+    launch_numeric_mixed(c, prec, A, B, ta, tb, seg, pairs, nnzc, b, C, norms);
+  else if (b == 64)
     launch_numeric_b<64>(c, A, B, ta, tb, seg, pairs, nnzc, C, norms);
   else
     launch_numeric_b<32>(c, A, B, ta, tb, seg, pairs, nnzc, C, norms);

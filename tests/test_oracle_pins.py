@@ -434,3 +434,47 @@ def test_planted_truncation_comparison_is_caught(monkeypatch):
         np.repeat(np.repeat(R.block_norms(X, b) > tau, b, 0), b, 1)[:X.shape[0], :X.shape[1]], X, 0.0))
     with pytest.raises(AssertionError):
         test_truncation_threshold_is_strict()
+
+
+# ----------------------------------------------------------------------------
+# precision form: input rounding
+# ----------------------------------------------------------------------------
+
+def test_bf16_and_fp32_rounding_by_hand():
+    # BF16 keeps 8 significant bits (7 stored); ties go to the even pattern
+    one = 1.0
+    cases = [
+        (1.0 + 2.0 ** -8, 1.0),                   # exact tie, 1.0 is even
+        (1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -6),   # tie between 1+2^-7 (odd) and 1+2^-6 (even)
+        (1.0 + 2.0 ** -8 + 2.0 ** -20, 1.0 + 2.0 ** -7),  # just above the tie
+        (-(1.0 + 2.0 ** -8), -1.0),
+        (3.0, 3.0), (0.0, 0.0),
+        (2.0 ** -130, 2.0 ** -130),               # FP32 subnormal, representable in BF16
+    ]
+    got = R.round_to(np.array([c[0] for c in cases]), "bf16")
+    assert np.array_equal(got, np.array([c[1] for c in cases]))
+    assert np.isinf(R.round_to(np.array([np.inf]), "bf16"))[0]
+    assert np.isnan(R.round_to(np.array([np.nan]), "bf16"))[0]
+    # FP32: 24 significant bits
+    x = np.array([1.0 + 2.0 ** -24, 1.0 + 3 * 2.0 ** -24, 0.1])
+    assert np.array_equal(R.round_to(x, "fp32"), np.array([1.0, 1.0 + 2.0 ** -22, float(np.float32(0.1))]))
+    assert R.round_to(np.array([one]), "fp64")[0] == one
+
+
+def test_mixed_refinement_reaches_fp64_accuracy(water100):
+    # the refinement wins back the accuracy lost in the correction products:
+    # with FP64 delta updates the tracked delta is the true residual, and TOL
+    # stopping reaches 1e-10 for FP32 and BF16 inputs.  The factor reached is
+    # an inverse factor (Z^T S Z = I) within O(u_in) of the FP64 one, u_in the
+    # unit roundoff of the inputs: inexact corrections move Z along the set of
+    # inverse factors, which the residual does not see.
+    D, lam = water100
+    Z64, i64, _ = R.irsi(D, 32, 0.0, start="inv_sqrt_lmax", start_value=lam[-1], stop="tol", tol=1e-10)
+    for prec, u_in in (("fp32", 2.0 ** -24), ("bf16", 2.0 ** -8)):
+        Z, info, _ = R.irsi(D, 32, 0.0, start="inv_sqrt_lmax", start_value=lam[-1], stop="tol", tol=1e-10,
+                            prec=prec)
+        assert info.norms[-1] <= 1e-10 and not info.stagnated
+        assert abs(R.true_residual(D, Z) - info.norms[-1]) <= 1e-12
+        assert info.iterations >= i64.iterations
+        dev = np.linalg.norm(Z - Z64) / np.linalg.norm(Z64)
+        assert 0.01 * u_in < dev <= 10 * u_in
