@@ -72,6 +72,19 @@ def cpu_baseline() -> dict:
             "sample_seconds": dt, "numpy_threads_hint": cores, "np_version": np.__version__}
 
 
+def rel_diff(A, B) -> float:
+    """||A - B||_F / ||B||_F of two block lists (host arrays)."""
+    import numpy as np
+    ia = {(int(r), int(c)): k for k, (r, c) in enumerate(zip(A.brow, A.bcol))}
+    ib = {(int(r), int(c)): k for k, (r, c) in enumerate(zip(B.brow, B.bcol))}
+    num = 0.0
+    for key in set(ia) | set(ib):
+        a = A.vals[ia[key]] if key in ia else 0.0
+        b = B.vals[ib[key]] if key in ib else 0.0
+        num += float(np.sum((a - b) ** 2))
+    return (num / float(np.sum(B.vals ** 2))) ** 0.5
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +93,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--count", type=int, default=5000, help="chain residues (5000 = the full workload)")
     ap.add_argument("--no-residual", action="store_true", help="skip the untruncated residual after timing")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 / BF16 runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
@@ -98,28 +112,47 @@ def main():
     S, cfg = config_matrix(1, count=args.count)
     Sd = type("DevBlocks", (), dict(n=S.n, b=S.b, brow=torch.from_numpy(S.brow).cuda(),
                                     bcol=torch.from_numpy(S.bcol).cuda(), vals=torch.from_numpy(S.vals).cuda()))
-    f = lif.Factorization(Sd, tau=cfg["tau"], base_rows=4096, stop=lif.STOP_PAPER, timing=1)
-    torch.cuda.synchronize()
-    for w in range(args.warmup):
-        info = f.localized()
-        print(f"# warmup {w}: {info['seconds_total']:.3f} s, top iterations {info['iterations_top']}",
-              file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    infos = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        infos.append(f.localized())
-        print(f"# step {k}: {infos[-1]['seconds_total']:.3f} s", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) / args.steps * 1e3
+    def run(prec, stop, tol):
+        f = lif.Factorization(Sd, tau=cfg["tau"], base_rows=4096, stop=stop, tol=tol, prec=prec, timing=1)
+        torch.cuda.synchronize()
+        for w in range(args.warmup):
+            info = f.localized()
+            print(f"# prec {prec} warmup {w}: {info['seconds_total']:.3f} s, top iterations {info['iterations_top']}",
+                  file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        infos = []
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            infos.append(f.localized())
+            print(f"# prec {prec} step {k}: {infos[-1]['seconds_total']:.3f} s", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res = None if args.no_residual else f.residual()
+        Z = None if args.no_residual else f.get_Z()
+        f.close()
+        return (t1 - t0) / args.steps, infos, res, Z
+
+    step_s, infos, res, Z64 = run(lif.FP64, lif.STOP_PAPER, 1e-10)
+    ms = step_s * 1e3
     flops = sum(i["flops_leaf_gemm"] for i in infos)
     gemm_s = sum(i["seconds_leaf_gemm"] for i in infos)
     launches = sum(i["leaf_gemm_launches"] for i in infos)
-    res = None if args.no_residual else f.residual()
     last = infos[-1]
     achieved = flops / gemm_s / 1e12 if gemm_s > 0 else 0.0
     traffic = measured_traffic()
+    mixed = {}
+    if not args.no_mixed:
+        for name, prec in (("fp32", lif.MIXED_FP32), ("bf16", lif.MIXED_BF16)):
+            s_m, inf_m, res_m, Zm = run(prec, lif.STOP_TOL, 1e-10)
+            fl = sum(i["flops_leaf_gemm"] for i in inf_m)
+            gs = sum(i["seconds_leaf_gemm"] for i in inf_m)
+            mixed[name] = {"s_per_factorization": s_m, "speedup_vs_fp64": step_s / s_m,
+                           "leaf_gemm_gflops": fl / gs / 1e9 if gs > 0 else None,
+                           "iterations_top": inf_m[-1]["iterations_top"],
+                           "iterations_total": inf_m[-1]["iterations_total"],
+                           "stagnated": inf_m[-1]["stagnated"], "delta_tracked": inf_m[-1]["delta_tracked"],
+                           "residual": res_m,
+                           "rel_diff_vs_fp64_Z": None if Zm is None else rel_diff(Zm, Z64)}
     out = {
         "metric": METRIC,
         "value": ms / 1e3,
@@ -147,6 +180,7 @@ def main():
         "iterations_total": last["iterations_total"],
         "nnzb_Z": last["nnzb_Z"],
         "products_per_step": last["products_total"],
+        "mixed": mixed,
         "roofline": {"bound": "mfma", "kernel": "k_numeric_f64 (leaf GEMM, v_mfma_f64_16x16x4f64)",
                      "achieved": achieved, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
@@ -155,7 +189,6 @@ def main():
                      "launches_per_step": launches / args.steps,
                      "traffic": traffic},
     }
-    f.close()
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

@@ -147,7 +147,7 @@ void fill_info(lif_handle h, const RunInfo& ri, double seconds, lif_info* info) 
   info->seconds_leaf_gemm = h->ctx.stats.gemm_ms * 1e-3;
   info->leaf_gemm_launches = h->ctx.stats.gemm_launches;
   info->products_total = h->ctx.stats.products;
-  info->nnzb_Z = h->has_Z ? h->Z.nnzb : 0;
+  info->nnzb_Z = h->has_Z ? exact_nnzb(h->ctx, h->Z) : 0;
   info->n_norms = (int32_t)std::min<size_t>(64, ri.norms_top.size());
   for (int k = 0; k < info->n_norms; ++k) info->norms[k] = ri.norms_top[k];
 }
@@ -160,15 +160,16 @@ void reset_stats(lif_handle h) {
 lif_status copy_out(lif_handle h, const Bsr& A, int64_t* nnzb, int32_t* brow, int32_t* bcol, double* vals,
                     int32_t on_device) {
   LIF_REQUIRE(nnzb != nullptr, LIF_ERR_INVALID, "nnzb is null");
+  const int64_t have = exact_nnzb(h->ctx, A);
   if (brow == nullptr) {
-    *nnzb = A.nnzb;
+    *nnzb = have;
     return LIF_OK;
   }
-  LIF_REQUIRE(*nnzb >= A.nnzb, LIF_ERR_INVALID,
-              "output capacity " + std::to_string(*nnzb) + " < " + std::to_string(A.nnzb) + " blocks");
-  LIF_REQUIRE(A.nnzb == 0 || (bcol && vals), LIF_ERR_INVALID, "null output array");
+  LIF_REQUIRE(*nnzb >= have, LIF_ERR_INVALID,
+              "output capacity " + std::to_string(*nnzb) + " < " + std::to_string(have) + " blocks");
+  LIF_REQUIRE(have == 0 || (bcol && vals), LIF_ERR_INVALID, "null output array");
   bsr_to_blocks(h->ctx, A, brow, bcol, vals, on_device != 0);
-  *nnzb = A.nnzb;
+  *nnzb = have;
   return LIF_OK;
 }
 
@@ -229,7 +230,7 @@ lif_status lif_create(const lif_blocks* S, const lif_opts* o, lif_handle* out) {
     Bsr S0 = bsr_from_blocks(c, *S);
     DBuf<double> nrm = block_norms(c, S0);
     h->S = truncate(c, std::move(S0), nrm.get(), p.tau);
-    c.sync();
+    exact_nnzb(c, h->S);
   } catch (const Error& e) {
     g_create_error = e.what();
     delete h;

@@ -45,9 +45,11 @@ __global__ void k_row_ptr_from_rows(const int* __restrict__ brow, int64_t nnzb, 
 }
 
 __global__ __launch_bounds__(kWG) void k_block_sumsq(const double* __restrict__ val, int64_t nnzb, int bb,
-                                                     double* __restrict__ out, int take_sqrt) {
+                                                     double* __restrict__ out, int take_sqrt,
+                                                     const int* __restrict__ live) {
   __shared__ double sh[4];
   const int64_t e = blockIdx.x;
+  if (live && e >= *live) return;
   const double2* p = reinterpret_cast<const double2*>(val + e * (int64_t)bb);
   double s = 0.0;
   for (int i = threadIdx.x; i < bb / 2; i += kWG) {
@@ -83,8 +85,9 @@ __global__ void k_compact_index(const int* __restrict__ rp, const int* __restric
 }
 
 __global__ __launch_bounds__(kWG) void k_gather_blocks(const double* __restrict__ val, const int* __restrict__ src,
-                                                       int bb, double* __restrict__ out) {
+                                                       int bb, double* __restrict__ out, const int* __restrict__ live) {
   const int64_t e = blockIdx.x;
+  if (live && e >= *live) return;
   const double2* s = reinterpret_cast<const double2*>(val + (int64_t)src[e] * bb);
   double2* d = reinterpret_cast<double2*>(out + e * (int64_t)bb);
   for (int i = threadIdx.x; i < bb / 2; i += kWG) d[i] = s[i];
@@ -127,76 +130,93 @@ __global__ __launch_bounds__(1024) void k_max_reduce(const double* __restrict__ 
   }
 }
 
-// Union of the sorted column lists of A's and B's row i, plus column i when
-// diag_on[i] is set.  A or B may be absent (null pointers).
-__device__ inline int union_row(const int* ra, const int* ca, const int* rb, const int* cb,
-                                const unsigned char* diag_on, int i, int* cc, int* ia, int* ib,
-                                unsigned char* id) {
-  int pa = ra ? ra[i] : 0, ea = ra ? ra[i + 1] : 0;
-  int pb = rb ? rb[i] : 0, eb = rb ? rb[i + 1] : 0;
+// Union of the sorted column lists of up to three operands' row i, plus
+// column i when diag_on[i] is set.  Absent operands have null pointers.
+struct Src3 {
+  const int* rp[3];
+  const int* col[3];
+};
+
+__device__ inline int union_row(const Src3& S, const unsigned char* diag_on, int i, int* cc, int* ix,
+                                int64_t stride, unsigned char* id) {
+  int p[3], e[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    p[t] = S.rp[t] ? S.rp[t][i] : 0;
+    e[t] = S.rp[t] ? S.rp[t][i + 1] : 0;
+  }
   bool dg = diag_on && diag_on[i];
   int o = 0;
-  while (pa < ea || pb < eb || dg) {
-    int xa = pa < ea ? ca[pa] : INT_MAX;
-    int xb = pb < eb ? cb[pb] : INT_MAX;
-    int xd = dg ? i : INT_MAX;
-    int x = min(xa, min(xb, xd));
+  while (p[0] < e[0] || p[1] < e[1] || p[2] < e[2] || dg) {
+    int x = dg ? i : INT_MAX;
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+      if (p[t] < e[t]) x = min(x, S.col[t][p[t]]);
     if (cc) {
       cc[o] = x;
-      ia[o] = (xa == x) ? pa : -1;
-      ib[o] = (xb == x) ? pb : -1;
-      id[o] = (xd == x) ? 1 : 0;
+      id[o] = (dg && x == i) ? 1 : 0;
     }
-    if (xa == x) ++pa;
-    if (xb == x) ++pb;
-    if (xd == x) dg = false;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const bool hit = p[t] < e[t] && S.col[t][p[t]] == x;
+      if (cc) ix[t * stride + o] = hit ? p[t] : -1;
+      if (hit) ++p[t];
+    }
+    if (dg && x == i) dg = false;
     ++o;
   }
   return o;
 }
 
-__global__ void k_union_counts(const int* ra, const int* ca, const int* rb, const int* cb,
-                               const unsigned char* diag_on, int nb, int* counts) {
+__global__ void k_union_counts(Src3 S, const unsigned char* diag_on, int nb, int* counts) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
-  counts[i] = union_row(ra, ca, rb, cb, diag_on, i, nullptr, nullptr, nullptr, nullptr);
+  counts[i] = union_row(S, diag_on, i, nullptr, nullptr, 0, nullptr);
 }
 
-__global__ void k_union_fill(const int* ra, const int* ca, const int* rb, const int* cb,
-                             const unsigned char* diag_on, const int* rc, int nb, int* cc, int* ia, int* ib,
-                             unsigned char* id) {
+// ix holds three index arrays of length stride (one per source), -1 = absent
+__global__ void k_union_fill(Src3 S, const unsigned char* diag_on, const int* rc, int nb, int* cc, int* ix,
+                             int64_t stride, unsigned char* id) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
   int o = rc[i];
-  union_row(ra, ca, rb, cb, diag_on, i, cc + o, ia + o, ib + o, id + o);
+  union_row(S, diag_on, i, cc + o, ix + o, stride, id + o);
 }
 
-// out = alpha A[ia] + beta B[ib] + gamma I (diagonal entries of real rows only)
-__global__ __launch_bounds__(kWG) void k_axpby_values(double alpha, const double* __restrict__ va,
-                                                      const int* __restrict__ ia, double beta,
-                                                      const double* __restrict__ vb, const int* __restrict__ ib,
+struct Val3 {
+  const double* v[3];
+  double coef[3];
+};
+
+// out = sum_t coef_t src_t[ix_t] + gamma I (diagonal entries of real rows only)
+__global__ __launch_bounds__(kWG) void k_axpby_values(Val3 V, const int* __restrict__ ix, int64_t stride,
                                                       double gamma, const unsigned char* __restrict__ id,
                                                       const int* __restrict__ row_of, int b, int64_t n,
-                                                      double* __restrict__ out) {
+                                                      double* __restrict__ out, const int* __restrict__ live) {
   const int64_t e = blockIdx.x;
+  if (live && e >= *live) return;
   const int bb = b * b;
-  const int xa = ia[e], xb = ib[e];
+  const double2* src[3];
+  double cf[3];
+  int ns = 0;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const int x = V.v[t] ? ix[t * stride + e] : -1;
+    if (x >= 0) {
+      src[ns] = reinterpret_cast<const double2*>(V.v[t] + (int64_t)x * bb);
+      cf[ns] = V.coef[t];
+      ++ns;
+    }
+  }
   const bool dg = id[e] != 0;
   const int64_t row0 = (int64_t)row_of[e] * b;
-  const double2* pa = xa >= 0 ? reinterpret_cast<const double2*>(va + (int64_t)xa * bb) : nullptr;
-  const double2* pb = xb >= 0 ? reinterpret_cast<const double2*>(vb + (int64_t)xb * bb) : nullptr;
   double2* po = reinterpret_cast<double2*>(out + e * (int64_t)bb);
   for (int q = threadIdx.x; q < bb / 2; q += kWG) {
     double2 r = make_double2(0.0, 0.0);
-    if (pa) {
-      double2 v = pa[q];
-      r.x = alpha * v.x;
-      r.y = alpha * v.y;
-    }
-    if (pb) {
-      double2 v = pb[q];
-      r.x += beta * v.x;
-      r.y += beta * v.y;
+    for (int t = 0; t < ns; ++t) {
+      const double2 v = src[t][q];
+      r.x += cf[t] * v.x;
+      r.y += cf[t] * v.y;
     }
     if (dg) {
       const int lin = 2 * q;
@@ -256,9 +276,11 @@ __global__ void k_filter_fill(const int* __restrict__ rp, const int* __restrict_
   }
 }
 
-__global__ void k_transpose_counts(const int* __restrict__ col, int64_t nnzb, int* __restrict__ counts) {
+__global__ void k_transpose_counts(const int* __restrict__ col, int64_t nnzb, int* __restrict__ counts,
+                                   const int* __restrict__ live) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < nnzb) atomicAdd(&counts[col[e]], 1);
+  const int64_t lim = live ? min(nnzb, (int64_t)*live) : nnzb;
+  if (e < lim) atomicAdd(&counts[col[e]], 1);
 }
 
 __global__ void k_transpose_fill(const int* __restrict__ rp, const int* __restrict__ col, const int* __restrict__ tptr,
@@ -300,9 +322,11 @@ __global__ __launch_bounds__(kWG) void k_transpose_sort(const int* __restrict__ 
 }
 
 __global__ __launch_bounds__(kWG) void k_transpose_blocks(const double* __restrict__ val, const int* __restrict__ src,
-                                                          int b, double* __restrict__ out) {
+                                                          int b, double* __restrict__ out,
+                                                          const int* __restrict__ live) {
   __shared__ double t[64 * 65];
   const int64_t e = blockIdx.x;
+  if (live && e >= *live) return;
   const double* s = val + (int64_t)src[e] * b * b;
   double* d = out + e * (int64_t)b * b;
   for (int q = threadIdx.x; q < b * b; q += kWG) {
@@ -348,9 +372,11 @@ void launch_row_ptr_from_rows(Ctx& c, const int* brow, int64_t nnzb, int nb, int
   LIF_LAUNCH(k_row_ptr_from_rows, dim3(grid1(nnzb + 1, 256)), dim3(256), 0, c.stream, brow, nnzb, nb, row_ptr);
 }
 
-void launch_block_sumsq(Ctx& c, const double* val, int64_t nnzb, int b, double* out, bool take_sqrt) {
+void launch_block_sumsq(Ctx& c, const double* val, int64_t nnzb, int b, double* out, bool take_sqrt,
+                        const int* live) {
   if (nnzb == 0) return;
-  LIF_LAUNCH(k_block_sumsq, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, val, nnzb, b * b, out, take_sqrt ? 1 : 0);
+  LIF_LAUNCH(k_block_sumsq, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, val, nnzb, b * b, out, take_sqrt ? 1 : 0,
+             live);
 }
 
 void launch_keep_counts(Ctx& c, const int* row_ptr, const double* norms, double tau, int nb, int* counts) {
@@ -363,9 +389,10 @@ void launch_compact_index(Ctx& c, const int* row_ptr, const int* col, const doub
              nb, new_col, src);
 }
 
-void launch_gather_blocks(Ctx& c, const double* val, const int* src, int64_t nnzb, int b, double* out) {
+void launch_gather_blocks(Ctx& c, const double* val, const int* src, int64_t nnzb, int b, double* out,
+                          const int* live) {
   if (nnzb == 0) return;
-  LIF_LAUNCH(k_gather_blocks, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, val, src, b * b, out);
+  LIF_LAUNCH(k_gather_blocks, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, val, src, b * b, out, live);
 }
 
 void launch_gershgorin(Ctx& c, const int* row_ptr, const double* val, int nb, int b, double* row_max) {
@@ -376,24 +403,37 @@ void launch_max_reduce(Ctx& c, const double* in, int count, double* out) {
   LIF_LAUNCH(k_max_reduce, dim3(1), dim3(1024), 0, c.stream, in, count, out);
 }
 
-void launch_union_counts(Ctx& c, const int* ra, const int* ca, const int* rb, const int* cb,
-                         const unsigned char* diag_on, int nb, int* counts) {
-  LIF_LAUNCH(k_union_counts, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, ra, ca, rb, cb, diag_on, nb, counts);
+void launch_union3(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on, int nb,
+                   int* counts) {
+  Src3 S;
+  for (int t = 0; t < 3; ++t) {
+    S.rp[t] = rp[t];
+    S.col[t] = col[t];
+  }
+  LIF_LAUNCH(k_union_counts, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, S, diag_on, nb, counts);
 }
 
-void launch_union_fill(Ctx& c, const int* ra, const int* ca, const int* rb, const int* cb,
-                       const unsigned char* diag_on, const int* rc, int nb, int* cc, int* ia, int* ib,
-                       unsigned char* id) {
-  LIF_LAUNCH(k_union_fill, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, ra, ca, rb, cb, diag_on, rc, nb, cc, ia,
-             ib, id);
+void launch_union3_fill(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on,
+                        const int* rc, int nb, int* cc, int* ix, int64_t stride, unsigned char* id) {
+  Src3 S;
+  for (int t = 0; t < 3; ++t) {
+    S.rp[t] = rp[t];
+    S.col[t] = col[t];
+  }
+  LIF_LAUNCH(k_union_fill, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, S, diag_on, rc, nb, cc, ix, stride, id);
 }
 
-void launch_axpby_values(Ctx& c, double alpha, const double* va, const int* ia, double beta, const double* vb,
-                         const int* ib, double gamma, const unsigned char* id, const int* row_of, int64_t nnzb,
-                         int b, int64_t n, double* out) {
+void launch_axpby3_values(Ctx& c, const double* const v[3], const double coef[3], const int* ix, int64_t stride,
+                          double gamma, const unsigned char* id, const int* row_of, int64_t nnzb, int b, int64_t n,
+                          double* out, const int* live) {
   if (nnzb == 0) return;
-  LIF_LAUNCH(k_axpby_values, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, alpha, va, ia, beta, vb, ib, gamma, id,
-             row_of, b, n, out);
+  Val3 V;
+  for (int t = 0; t < 3; ++t) {
+    V.v[t] = v[t];
+    V.coef[t] = coef[t];
+  }
+  LIF_LAUNCH(k_axpby_values, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, V, ix, stride, gamma, id, row_of, b, n,
+             out, live);
 }
 
 void launch_block_row_of(Ctx& c, const int* row_ptr, int nb, int64_t nnzb, int* row_of) {
@@ -413,9 +453,9 @@ void launch_filter_fill(Ctx& c, const int* row_ptr, const int* col, const int* r
              new_row_ptr, nb, new_col, src);
 }
 
-void launch_transpose_counts(Ctx& c, const int* col, int64_t nnzb, int* counts) {
+void launch_transpose_counts(Ctx& c, const int* col, int64_t nnzb, int* counts, const int* live) {
   if (nnzb == 0) return;
-  LIF_LAUNCH(k_transpose_counts, dim3(grid1(nnzb, 256)), dim3(256), 0, c.stream, col, nnzb, counts);
+  LIF_LAUNCH(k_transpose_counts, dim3(grid1(nnzb, 256)), dim3(256), 0, c.stream, col, nnzb, counts, live);
 }
 
 void launch_transpose_fill(Ctx& c, const int* row_ptr, const int* col, const int* tptr, int nb, int* cursor,
@@ -428,9 +468,10 @@ void launch_transpose_sort(Ctx& c, const int* tptr, int nb, const int* icol, con
   LIF_LAUNCH(k_transpose_sort, dim3(nb), dim3(kWG), 0, c.stream, tptr, icol, isrc, ocol, osrc);
 }
 
-void launch_transpose_blocks(Ctx& c, const double* val, const int* src, int64_t nnzb, int b, double* out) {
+void launch_transpose_blocks(Ctx& c, const double* val, const int* src, int64_t nnzb, int b, double* out,
+                             const int* live) {
   if (nnzb == 0) return;
-  LIF_LAUNCH(k_transpose_blocks, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, val, src, b, out);
+  LIF_LAUNCH(k_transpose_blocks, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, val, src, b, out, live);
 }
 
 void launch_segment_sum(Ctx& c, const double* sumsq, const int* row_ptr, const int* rlo, const int* rhi, int nseg,

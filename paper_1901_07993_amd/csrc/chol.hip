@@ -89,8 +89,17 @@ __global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nb
   for (int j = 0; j < B; ++j) {
     double v = 0.0;
     if (c >= j) {
-      double acc = 0.0;
-      for (int i = gi; i < j; i += G) acc += T[i * L + j] * T[i * L + c];
+      // four independent partial sums keep several LDS reads in flight
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int i = gi;
+      for (; i + 3 * G < j; i += 4 * G) {
+        a0 += T[i * L + j] * T[i * L + c];
+        a1 += T[(i + G) * L + j] * T[(i + G) * L + c];
+        a2 += T[(i + 2 * G) * L + j] * T[(i + 2 * G) * L + c];
+        a3 += T[(i + 3 * G) * L + j] * T[(i + 3 * G) * L + c];
+      }
+      for (; i < j; i += G) a0 += T[i * L + j] * T[i * L + c];
+      double acc = (a0 + a1) + (a2 + a3);
       for (int off = 1; off < G; off <<= 1) acc += __shfl_xor(acc, off, 64);
       v = T[j * L + c] - acc;
       if (c == j && gi == 0) piv = v;
@@ -106,16 +115,27 @@ __global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nb
     __syncthreads();  // row j of U final before the next row reads it
   }
   for (int r = gi; r < B; r += G) W[r * L + c] = 0.0;
+  // reciprocal pivots once, so the column sweeps multiply instead of divide
+  __shared__ double rdiag[B];
+  for (int r = threadIdx.x; r < B; r += 256) rdiag[r] = 1.0 / T[r * L + r];
+  __syncthreads();
   {
-    const double wcc = 1.0 / T[c * L + c];
-    if (c % G == gi) W[c * L + c] = wcc;
+    if (c % G == gi) W[c * L + c] = rdiag[c];
     for (int r = c - 1; r >= 0; --r) {
-      double acc = 0.0;
-      // q in (r, c] with q % G == gi
-      int q0 = r + 1 + ((gi - (r + 1) % G) + G) % G;
-      for (int q = q0; q <= c; q += G) acc += T[r * L + q] * W[q * L + c];
+      // q in (r, c] with q % G == gi, four independent partial sums
+      const int q0 = r + 1 + ((gi - (r + 1) % G) + G) % G;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int q = q0;
+      for (; q + 3 * G <= c; q += 4 * G) {
+        a0 += T[r * L + q] * W[q * L + c];
+        a1 += T[r * L + q + G] * W[(q + G) * L + c];
+        a2 += T[r * L + q + 2 * G] * W[(q + 2 * G) * L + c];
+        a3 += T[r * L + q + 3 * G] * W[(q + 3 * G) * L + c];
+      }
+      for (; q <= c; q += G) a0 += T[r * L + q] * W[q * L + c];
+      double acc = (a0 + a1) + (a2 + a3);
       for (int off = 1; off < G; off <<= 1) acc += __shfl_xor(acc, off, 64);
-      if (r % G == gi) W[r * L + c] = -acc / T[r * L + r];
+      if (r % G == gi) W[r * L + c] = -acc * rdiag[r];
     }
   }
   __syncthreads();
@@ -227,19 +247,29 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, const int*
   v4d acc[2][2];
   acc_zero(acc);
   double2 ra[Cfg::V2], rb[Cfg::V2];
-  int used = 0;
-  for (int k = i; k < j; ++k) {
-    if (!nz[packed_tile(t0, nbb, k, j)]) continue;  // U_kj = 0
-    ++used;
-    tile_load<B>(Z + packed_tile(t0, nbb, i, k) * B * B, ra);
-    tile_load<B>(U + packed_tile(t0, nbb, k, j) * B * B, rb);
+  // k with U_kj != 0, visited in ascending order; the next pair's tiles are
+  // loaded into registers while the current one is multiplied
+  auto next_k = [&](int k) {
+    while (k < j && !nz[packed_tile(t0, nbb, k, j)]) ++k;
+    return k;
+  };
+  int k = next_k(i);
+  if (k >= j) return;  // Z_ij = 0 (the buffer starts zeroed)
+  tile_load<B>(Z + packed_tile(t0, nbb, i, k) * B * B, ra);
+  tile_load<B>(U + packed_tile(t0, nbb, k, j) * B * B, rb);
+  while (k < j) {
     __syncthreads();
     tile_store<B>(As, ra, false);  // op(A) = Z_ik
     tile_store<B>(Bs, rb, true);
     __syncthreads();
+    const int kn = next_k(k + 1);
+    if (kn < j) {
+      tile_load<B>(Z + packed_tile(t0, nbb, i, kn) * B * B, ra);
+      tile_load<B>(U + packed_tile(t0, nbb, kn, j) * B * B, rb);
+    }
     tile_mma<B>(As, Bs, f, acc);
+    k = kn;
   }
-  if (used == 0) return;  // Z_ij = 0 (the buffer starts zeroed)
   __syncthreads();
   // W (accumulators) becomes the A operand: LDS row c holds column c of W
 #pragma unroll

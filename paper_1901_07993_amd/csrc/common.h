@@ -96,14 +96,23 @@ class DBuf {
 // Device block-CSR matrix: nb block rows, row_ptr[nb+1], col[nnzb] sorted
 // within each row, val[nnzb][b][b] row-major FP64 blocks.
 // ---------------------------------------------------------------------------
+//
+// The block count may be known only on the device (row_ptr[nb]): operations
+// that cannot grow a matrix beyond a host-known bound (truncation, filters,
+// sums) allocate that bound as capacity and leave nnzb = -1, so they need no
+// device-to-host read.  Kernels that run over blocks take the device count
+// and skip the tail of the capacity.
 struct Bsr {
   int64_t n = 0;
   int b = 0;
   int nb = 0;
-  int64_t nnzb = 0;
+  mutable int64_t nnzb = 0;  // exact block count, or -1 while only the device knows it
+  int64_t cap = 0;           // blocks allocated in col and val (>= the count)
   DBuf<int> row_ptr;
   DBuf<int> col;
   DBuf<double> val;
+  int64_t bound() const { return nnzb >= 0 ? nnzb : cap; }
+  const int* live() const { return row_ptr.get() + nb; }  // device-side count
 };
 
 // Per-call statistics.
@@ -138,8 +147,13 @@ struct Ctx {
   void sync() { LIF_HIP(hipStreamSynchronize(stream)); }
   // copy `bytes` from device `src` through the pinned buffer; synchronizes
   void d2h(void* dst, const void* src, size_t bytes);
-  // two small reads with one synchronization (each at most 64 bytes)
-  void d2h2(void* d0, const void* s0, size_t b0, void* d1, const void* s1, size_t b1);
+  // several small reads (at most 64 bytes each) with one synchronization
+  struct Read {
+    void* dst;
+    const void* src;
+    size_t bytes;
+  };
+  void d2h_batch(const std::vector<Read>& reads);
   ~Ctx();
 };
 
@@ -154,32 +168,34 @@ void scan_exclusive_i64(Ctx& c, const int64_t* in, int64_t* out, int count);
 
 // bsr.hip
 void launch_row_ptr_from_rows(Ctx& c, const int* brow, int64_t nnzb, int nb, int* row_ptr);
-void launch_block_sumsq(Ctx& c, const double* val, int64_t nnzb, int b, double* out, bool take_sqrt);
+void launch_block_sumsq(Ctx& c, const double* val, int64_t nnzb, int b, double* out, bool take_sqrt,
+                        const int* live);
 void launch_keep_counts(Ctx& c, const int* row_ptr, const double* norms, double tau, int nb, int* counts);
 void launch_compact_index(Ctx& c, const int* row_ptr, const int* col, const double* norms, double tau,
                           const int* new_row_ptr, int nb, int* new_col, int* src);
-void launch_gather_blocks(Ctx& c, const double* val, const int* src, int64_t nnzb, int b, double* out);
+void launch_gather_blocks(Ctx& c, const double* val, const int* src, int64_t nnzb, int b, double* out,
+                          const int* live);
 void launch_gershgorin(Ctx& c, const int* row_ptr, const double* val, int nb, int b, double* row_max);
 void launch_max_reduce(Ctx& c, const double* in, int count, double* out);
-void launch_union_counts(Ctx& c, const int* ra, const int* ca, const int* rb, const int* cb,
-                         const unsigned char* diag_on, int nb, int* counts);
-void launch_union_fill(Ctx& c, const int* ra, const int* ca, const int* rb, const int* cb,
-                       const unsigned char* diag_on, const int* rc, int nb, int* cc, int* ia, int* ib,
-                       unsigned char* id);
-void launch_axpby_values(Ctx& c, double alpha, const double* va, const int* ia, double beta,
-                         const double* vb, const int* ib, double gamma, const unsigned char* id,
-                         const int* row_of, int64_t nnzb, int b, int64_t n, double* out);
+void launch_union3(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on, int nb,
+                   int* counts);
+void launch_union3_fill(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on,
+                        const int* rc, int nb, int* cc, int* ix, int64_t stride, unsigned char* id);
+void launch_axpby3_values(Ctx& c, const double* const v[3], const double coef[3], const int* ix, int64_t stride,
+                          double gamma, const unsigned char* id, const int* row_of, int64_t nnzb, int b, int64_t n,
+                          double* out, const int* live);
 void launch_block_row_of(Ctx& c, const int* row_ptr, int nb, int64_t nnzb, int* row_of);
 void launch_filter_counts(Ctx& c, const int* row_ptr, const int* col, const int* rlab, const int* clab,
                           int mode, int nb, int* counts);
 void launch_filter_fill(Ctx& c, const int* row_ptr, const int* col, const int* rlab, const int* clab,
                         int mode, const int* new_row_ptr, int nb, int* new_col, int* src);
-void launch_transpose_counts(Ctx& c, const int* col, int64_t nnzb, int* counts);
+void launch_transpose_counts(Ctx& c, const int* col, int64_t nnzb, int* counts, const int* live);
 void launch_transpose_fill(Ctx& c, const int* row_ptr, const int* col, const int* tptr, int nb,
                            int* cursor, int* tcol, int* tsrc);
 void launch_transpose_sort(Ctx& c, const int* tptr, int nb, const int* icol, const int* isrc, int* ocol,
                            int* osrc);
-void launch_transpose_blocks(Ctx& c, const double* val, const int* src, int64_t nnzb, int b, double* out);
+void launch_transpose_blocks(Ctx& c, const double* val, const int* src, int64_t nnzb, int b, double* out,
+                             const int* live);
 void launch_segment_sum(Ctx& c, const double* sumsq, const int* row_ptr, const int* rlo, const int* rhi, int nseg,
                         double* out);
 void launch_fill_i32(Ctx& c, int* p, int value, int64_t count);
@@ -243,9 +259,13 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
 // alpha A + beta B + gamma I on the block rows with diag_on set (A or B may be null)
 Bsr axpby(Ctx& c, double alpha, const Bsr* A, double beta, const Bsr* B, double gamma,
           const unsigned char* diag_on);
+// alpha A + beta B + kappa C in one pass (any may be null)
+Bsr axpby3(Ctx& c, double alpha, const Bsr* A, double beta, const Bsr* B, double kappa, const Bsr* C);
 Bsr filter(Ctx& c, const Bsr& A, const int* rlab, const int* clab, int mode);
 double gershgorin(Ctx& c, const Bsr& A);
 std::vector<double> node_sumsq(Ctx& c, const Bsr& A, const int* rlo, const int* rhi, int nseg);
 Bsr copy(Ctx& c, const Bsr& A);
+// exact block count (reads it from the device when only the device knows it)
+int64_t exact_nnzb(Ctx& c, const Bsr& A);
 
 }  // namespace lif

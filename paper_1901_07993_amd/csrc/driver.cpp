@@ -133,10 +133,8 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
     Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau);
     Bsr X2 = spgemm(c, SM, true, Z, false, o.tau);
     SM = Bsr();
-    Bsr t = axpby(c, 1.0, &delta, -1.0, &X1, 0.0, nullptr);
+    delta = axpby3(c, 1.0, &delta, -1.0, &X1, -1.0, &X2);
     X1 = Bsr();
-    delta = axpby(c, 1.0, &t, -1.0, &X2, 0.0, nullptr);
-    t = Bsr();
     X2 = Bsr();
     Z = std::move(Znew);
 
@@ -293,9 +291,10 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   LIF_HIP(hipMemsetAsync(U.get(), 0, (size_t)tiles * tile_doubles * sizeof(double), c.stream));
   LIF_HIP(hipMemsetAsync(Z.val.get(), 0, (size_t)tiles * tile_doubles * sizeof(double), c.stream));
   {
-    DBuf<int> rowof(c.pool, (size_t)std::max<int64_t>(S.nnzb, 1));
-    launch_block_row_of(c, S.row_ptr.get(), nb, S.nnzb, rowof.get());
-    launch_chol_scatter(c, rowof.get(), S.col.get(), S.val.get(), S.nnzb, b, d_bor.get(), d_blk0.get(), d_nbb.get(),
+    const int64_t snz = exact_nnzb(c, S);
+    DBuf<int> rowof(c.pool, (size_t)std::max<int64_t>(snz, 1));
+    launch_block_row_of(c, S.row_ptr.get(), nb, snz, rowof.get());
+    launch_chol_scatter(c, rowof.get(), S.col.get(), S.val.get(), snz, b, d_bor.get(), d_blk0.get(), d_nbb.get(),
                         d_tile0.get(), U.get(), nz.get());
   }
   launch_chol_pad(c, nbase, d_nbb.get(), d_rows.get(), d_tile0.get(), b, U.get(), 1.0);
@@ -327,6 +326,7 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   }
   LIF_REQUIRE((int64_t)col.size() == tiles, LIF_ERR_INVALID, "leaf ranges do not cover whole block rows");
   Z.nnzb = tiles;
+  Z.cap = tiles;
   Z.row_ptr = DBuf<int>(c.pool, nb + 1);
   Z.col = DBuf<int>(c.pool, (size_t)tiles);
   h2d(c, Z.row_ptr.get(), rp.data(), nb + 1);

@@ -1,13 +1,13 @@
 // Block-sparse operations on device block-CSR matrices.  Each operation
-// allocates its outputs from the handle's pool, queues its kernels on the
-// handle's stream and reads back only the sizes it needs to allocate.
+// allocates its outputs from the handle's pool and queues its kernels on the
+// handle's stream.  Only the symbolic phase of a product reads sizes back to
+// the host (it has no host-known bound); truncation, filters and sums size
+// their outputs by a bound and leave the exact count on the device.
 #include <algorithm>
 
 #include "common.h"
 
 namespace lif {
-
-size_t symbolic_lds_bytes(int nb, bool fill);
 
 namespace {
 
@@ -18,7 +18,20 @@ T read1(Ctx& c, const T* dev) {
   return v;
 }
 
+Bsr like(const Bsr& A) {
+  Bsr C;
+  C.n = A.n;
+  C.b = A.b;
+  C.nb = A.nb;
+  return C;
+}
+
 }  // namespace
+
+int64_t exact_nnzb(Ctx& c, const Bsr& A) {
+  if (A.nnzb < 0) A.nnzb = read1(c, A.live());
+  return A.nnzb;
+}
 
 Bsr bsr_empty(Ctx& c, int64_t n, int b) {
   Bsr A;
@@ -26,6 +39,7 @@ Bsr bsr_empty(Ctx& c, int64_t n, int b) {
   A.b = b;
   A.nb = (int)((n + b - 1) / b);
   A.nnzb = 0;
+  A.cap = 0;
   A.row_ptr = DBuf<int>(c.pool, A.nb + 1);
   launch_fill_i32(c, A.row_ptr.get(), 0, A.nb + 1);
   return A;
@@ -37,6 +51,7 @@ Bsr bsr_from_blocks(Ctx& c, const lif_blocks& in) {
   A.b = in.b;
   A.nb = (int)((in.n + in.b - 1) / in.b);
   A.nnzb = in.nnzb;
+  A.cap = in.nnzb;
   const hipMemcpyKind kind = in.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   DBuf<int> brow(c.pool, (size_t)in.nnzb);
   A.col = DBuf<int>(c.pool, (size_t)in.nnzb);
@@ -52,82 +67,75 @@ Bsr bsr_from_blocks(Ctx& c, const lif_blocks& in) {
 }
 
 void bsr_to_blocks(Ctx& c, const Bsr& A, int32_t* brow, int32_t* bcol, double* vals, bool on_device) {
-  if (A.nnzb == 0) return;
-  DBuf<int> rows(c.pool, (size_t)A.nnzb);
-  launch_block_row_of(c, A.row_ptr.get(), A.nb, A.nnzb, rows.get());
+  const int64_t nnz = exact_nnzb(c, A);
+  if (nnz == 0) return;
+  DBuf<int> rows(c.pool, (size_t)nnz);
+  launch_block_row_of(c, A.row_ptr.get(), A.nb, nnz, rows.get());
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  LIF_HIP(hipMemcpyAsync(brow, rows.get(), A.nnzb * sizeof(int), kind, c.stream));
-  LIF_HIP(hipMemcpyAsync(bcol, A.col.get(), A.nnzb * sizeof(int), kind, c.stream));
-  LIF_HIP(hipMemcpyAsync(vals, A.val.get(), A.nnzb * (size_t)A.b * A.b * sizeof(double), kind, c.stream));
+  LIF_HIP(hipMemcpyAsync(brow, rows.get(), nnz * sizeof(int), kind, c.stream));
+  LIF_HIP(hipMemcpyAsync(bcol, A.col.get(), nnz * sizeof(int), kind, c.stream));
+  LIF_HIP(hipMemcpyAsync(vals, A.val.get(), nnz * (size_t)A.b * A.b * sizeof(double), kind, c.stream));
   c.sync();
 }
 
 Bsr copy(Ctx& c, const Bsr& A) {
-  Bsr B;
-  B.n = A.n;
-  B.b = A.b;
-  B.nb = A.nb;
+  Bsr B = like(A);
   B.nnzb = A.nnzb;
+  B.cap = A.bound();
   B.row_ptr = DBuf<int>(c.pool, A.nb + 1);
-  B.col = DBuf<int>(c.pool, (size_t)A.nnzb);
-  B.val = DBuf<double>(c.pool, (size_t)A.nnzb * A.b * A.b);
+  B.col = DBuf<int>(c.pool, (size_t)B.cap);
+  B.val = DBuf<double>(c.pool, (size_t)B.cap * A.b * A.b);
   LIF_HIP(hipMemcpyAsync(B.row_ptr.get(), A.row_ptr.get(), (A.nb + 1) * sizeof(int), hipMemcpyDeviceToDevice,
                          c.stream));
-  if (A.nnzb) {
-    LIF_HIP(hipMemcpyAsync(B.col.get(), A.col.get(), A.nnzb * sizeof(int), hipMemcpyDeviceToDevice, c.stream));
-    LIF_HIP(hipMemcpyAsync(B.val.get(), A.val.get(), A.nnzb * (size_t)A.b * A.b * sizeof(double),
+  if (B.cap) {
+    LIF_HIP(hipMemcpyAsync(B.col.get(), A.col.get(), B.cap * sizeof(int), hipMemcpyDeviceToDevice, c.stream));
+    LIF_HIP(hipMemcpyAsync(B.val.get(), A.val.get(), B.cap * (size_t)A.b * A.b * sizeof(double),
                            hipMemcpyDeviceToDevice, c.stream));
   }
   return B;
 }
 
 DBuf<double> block_norms(Ctx& c, const Bsr& A) {
-  DBuf<double> nrm(c.pool, (size_t)A.nnzb);
-  launch_block_sumsq(c, A.val.get(), A.nnzb, A.b, nrm.get(), true);
+  DBuf<double> nrm(c.pool, (size_t)A.bound());
+  launch_block_sumsq(c, A.val.get(), A.bound(), A.b, nrm.get(), true, A.live());
   return nrm;
 }
 
 // Sec. 5 truncation: drop blocks with Frobenius norm < tau, keep the order.
+// The kept count stays on the device; the capacity is the input's bound.
 Bsr truncate(Ctx& c, Bsr&& A, const double* norms, double tau) {
-  if (tau <= 0.0 || A.nnzb == 0) return std::move(A);
+  if (tau <= 0.0 || A.bound() == 0) return std::move(A);
+  Bsr B = like(A);
+  B.nnzb = -1;
+  B.cap = A.bound();
   DBuf<int> cnt(c.pool, A.nb);
   launch_keep_counts(c, A.row_ptr.get(), norms, tau, A.nb, cnt.get());
-  DBuf<int> nrp(c.pool, A.nb + 1);
-  scan_exclusive_i32(c, cnt.get(), nrp.get(), A.nb);
-  const int nnz = read1(c, nrp.get() + A.nb);
-  if (nnz == A.nnzb) return std::move(A);
-  Bsr B;
-  B.n = A.n;
-  B.b = A.b;
-  B.nb = A.nb;
-  B.nnzb = nnz;
-  B.row_ptr = std::move(nrp);
-  B.col = DBuf<int>(c.pool, (size_t)nnz);
-  DBuf<int> src(c.pool, (size_t)nnz);
+  B.row_ptr = DBuf<int>(c.pool, A.nb + 1);
+  scan_exclusive_i32(c, cnt.get(), B.row_ptr.get(), A.nb);
+  B.col = DBuf<int>(c.pool, (size_t)B.cap);
+  DBuf<int> src(c.pool, (size_t)B.cap);
   launch_compact_index(c, A.row_ptr.get(), A.col.get(), norms, tau, B.row_ptr.get(), A.nb, B.col.get(), src.get());
-  B.val = DBuf<double>(c.pool, (size_t)nnz * A.b * A.b);
-  launch_gather_blocks(c, A.val.get(), src.get(), nnz, A.b, B.val.get());
+  B.val = DBuf<double>(c.pool, (size_t)B.cap * A.b * A.b);
+  launch_gather_blocks(c, A.val.get(), src.get(), B.cap, A.b, B.val.get(), B.live());
   return B;
 }
 
 CsrView transpose_view(Ctx& c, const Bsr& A) {
   CsrView v;
   const int nb = A.nb;
+  const int64_t cap = A.bound();
   DBuf<int> cnt(c.pool, nb);
   launch_fill_i32(c, cnt.get(), 0, nb);
-  launch_transpose_counts(c, A.col.get(), A.nnzb, cnt.get());
+  launch_transpose_counts(c, A.col.get(), cap, cnt.get(), A.live());
   v.own_rp = DBuf<int>(c.pool, nb + 1);
   scan_exclusive_i32(c, cnt.get(), v.own_rp.get(), nb);
   launch_fill_i32(c, cnt.get(), 0, nb);
-  DBuf<int> tcol(c.pool, (size_t)A.nnzb), tsrc(c.pool, (size_t)A.nnzb);
-  if (A.nnzb) {
+  DBuf<int> tcol(c.pool, (size_t)cap), tsrc(c.pool, (size_t)cap);
+  if (cap)
     launch_transpose_fill(c, A.row_ptr.get(), A.col.get(), v.own_rp.get(), nb, cnt.get(), tcol.get(), tsrc.get());
-  }
-  v.own_col = DBuf<int>(c.pool, (size_t)A.nnzb);
-  v.own_idx = DBuf<int>(c.pool, (size_t)A.nnzb);
-  if (A.nnzb) {
-    launch_transpose_sort(c, v.own_rp.get(), nb, tcol.get(), tsrc.get(), v.own_col.get(), v.own_idx.get());
-  }
+  v.own_col = DBuf<int>(c.pool, (size_t)cap);
+  v.own_idx = DBuf<int>(c.pool, (size_t)cap);
+  if (cap) launch_transpose_sort(c, v.own_rp.get(), nb, tcol.get(), tsrc.get(), v.own_col.get(), v.own_idx.get());
   v.rp = v.own_rp.get();
   v.col = v.own_col.get();
   v.idx = v.own_idx.get();
@@ -136,25 +144,20 @@ CsrView transpose_view(Ctx& c, const Bsr& A) {
 
 Bsr transpose(Ctx& c, const Bsr& A) {
   CsrView v = transpose_view(c, A);
-  Bsr T;
-  T.n = A.n;
-  T.b = A.b;
-  T.nb = A.nb;
+  Bsr T = like(A);
   T.nnzb = A.nnzb;
+  T.cap = A.bound();
   T.row_ptr = std::move(v.own_rp);
   T.col = std::move(v.own_col);
-  T.val = DBuf<double>(c.pool, (size_t)A.nnzb * A.b * A.b);
-  launch_transpose_blocks(c, A.val.get(), v.own_idx.get(), A.nnzb, A.b, T.val.get());
+  T.val = DBuf<double>(c.pool, (size_t)T.cap * A.b * A.b);
+  launch_transpose_blocks(c, A.val.get(), v.own_idx.get(), T.cap, A.b, T.val.get(), T.live());
   return T;
 }
 
 Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec) {
   LIF_REQUIRE(A.nb == B.nb && A.b == B.b, LIF_ERR_INVALID, "spgemm: operand shapes differ");
   const int nb = A.nb;
-  Bsr C;
-  C.n = A.n;
-  C.b = A.b;
-  C.nb = nb;
+  Bsr C = like(A);
   CsrView av, bv;
   if (ta) {
     av = transpose_view(c, A);
@@ -175,19 +178,26 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
   DBuf<int64_t> prp(c.pool, nb + 1);
   scan_exclusive_i32(c, cnt_c.get(), C.row_ptr.get(), nb);
   scan_exclusive_i64(c, cnt_p.get(), prp.get(), nb);
-  int nnzc32 = 0;
+  // the one read-back of a product: output and product counts, plus the
+  // operands' block counts while only the device knows them
+  int nnzc32 = 0, na = 0, nbk = 0;
   int64_t P = 0;
-  c.d2h2(&nnzc32, C.row_ptr.get() + nb, sizeof(int), &P, prp.get() + nb, sizeof(int64_t));
+  std::vector<Ctx::Read> reads{{&nnzc32, C.row_ptr.get() + nb, sizeof(int)}, {&P, prp.get() + nb, sizeof(int64_t)}};
+  const bool need_a = A.nnzb < 0, need_b = B.nnzb < 0 && &A != &B;
+  if (need_a) reads.push_back({&na, A.live(), sizeof(int)});
+  if (need_b) reads.push_back({&nbk, B.live(), sizeof(int)});
+  c.d2h_batch(reads);
+  if (need_a) A.nnzb = na;
+  if (need_b) B.nnzb = nbk;
   const int64_t nnzc = nnzc32;
   C.nnzb = nnzc;
+  C.cap = nnzc;
   C.col = DBuf<int>(c.pool, (size_t)nnzc);
   DBuf<int64_t> seg(c.pool, (size_t)nnzc + 1);
   DBuf<int2> pairs(c.pool, (size_t)P);
-  if (nnzc) {
+  if (nnzc)
     launch_symbolic_fill(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, nb, C.row_ptr.get(), prp.get(),
                          C.col.get(), seg.get(), pairs.get());
-    LIF_HIP(hipMemcpyAsync(seg.get() + nnzc, prp.get() + nb, sizeof(int64_t), hipMemcpyDeviceToDevice, c.stream));
-  }
   C.val = DBuf<double>(c.pool, (size_t)nnzc * C.b * C.b);
   DBuf<double> nrm(c.pool, (size_t)nnzc);
   launch_numeric(c, prec, A.val.get(), B.val.get(), ta, tb, seg.get(), pairs.get(), nnzc, C.b, C.val.get(),
@@ -199,56 +209,78 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
   return truncate(c, std::move(C), nrm.get(), tau);
 }
 
-Bsr axpby(Ctx& c, double alpha, const Bsr* A, double beta, const Bsr* B, double gamma,
-          const unsigned char* diag_on) {
-  const Bsr* ref = A ? A : B;
-  const int nb = ref ? ref->nb : c.nb;
+namespace {
+
+Bsr union_sum(Ctx& c, const Bsr* const src[3], const double coef[3], double gamma, const unsigned char* diag_on) {
+  const Bsr* ref = nullptr;
+  for (int t = 0; t < 3; ++t)
+    if (src[t] && !ref) ref = src[t];
   Bsr C;
   C.n = ref ? ref->n : c.n;
   C.b = ref ? ref->b : c.b;
-  C.nb = nb;
-  const int* ra = A ? A->row_ptr.get() : nullptr;
-  const int* ca = A ? A->col.get() : nullptr;
-  const int* rb = B ? B->row_ptr.get() : nullptr;
-  const int* cb = B ? B->col.get() : nullptr;
+  C.nb = ref ? ref->nb : c.nb;
+  const int nb = C.nb;
+  const int* rp[3];
+  const int* col[3];
+  const double* val[3];
+  int64_t cap = diag_on ? nb : 0;
+  for (int t = 0; t < 3; ++t) {
+    rp[t] = src[t] ? src[t]->row_ptr.get() : nullptr;
+    col[t] = src[t] ? src[t]->col.get() : nullptr;
+    val[t] = src[t] ? src[t]->val.get() : nullptr;
+    if (src[t]) cap += src[t]->bound();
+  }
+  cap = std::min<int64_t>(cap, (int64_t)nb * nb);
+  C.nnzb = -1;
+  C.cap = cap;
   DBuf<int> cnt(c.pool, nb);
-  launch_union_counts(c, ra, ca, rb, cb, diag_on, nb, cnt.get());
+  launch_union3(c, rp, col, diag_on, nb, cnt.get());
   C.row_ptr = DBuf<int>(c.pool, nb + 1);
   scan_exclusive_i32(c, cnt.get(), C.row_ptr.get(), nb);
-  const int nnz = read1(c, C.row_ptr.get() + nb);
-  C.nnzb = nnz;
-  C.col = DBuf<int>(c.pool, (size_t)nnz);
-  DBuf<int> ia(c.pool, (size_t)nnz), ib(c.pool, (size_t)nnz), rowof(c.pool, (size_t)nnz);
-  DBuf<unsigned char> id(c.pool, (size_t)nnz);
-  C.val = DBuf<double>(c.pool, (size_t)nnz * C.b * C.b);
-  if (nnz) {
-    launch_union_fill(c, ra, ca, rb, cb, diag_on, C.row_ptr.get(), nb, C.col.get(), ia.get(), ib.get(), id.get());
-    launch_block_row_of(c, C.row_ptr.get(), nb, nnz, rowof.get());
-    launch_axpby_values(c, alpha, A ? A->val.get() : nullptr, ia.get(), beta, B ? B->val.get() : nullptr, ib.get(),
-                        gamma, id.get(), rowof.get(), nnz, C.b, C.n, C.val.get());
+  C.col = DBuf<int>(c.pool, (size_t)cap);
+  DBuf<int> ix(c.pool, (size_t)cap * 3), rowof(c.pool, (size_t)cap);
+  DBuf<unsigned char> id(c.pool, (size_t)cap);
+  C.val = DBuf<double>(c.pool, (size_t)cap * C.b * C.b);
+  if (cap) {
+    launch_union3_fill(c, rp, col, diag_on, C.row_ptr.get(), nb, C.col.get(), ix.get(), cap, id.get());
+    launch_block_row_of(c, C.row_ptr.get(), nb, cap, rowof.get());
+    launch_axpby3_values(c, val, coef, ix.get(), cap, gamma, id.get(), rowof.get(), cap, C.b, C.n, C.val.get(),
+                         C.live());
   }
   return C;
 }
 
+}  // namespace
+
+Bsr axpby(Ctx& c, double alpha, const Bsr* A, double beta, const Bsr* B, double gamma,
+          const unsigned char* diag_on) {
+  const Bsr* src[3] = {A, B, nullptr};
+  const double coef[3] = {alpha, beta, 0.0};
+  return union_sum(c, src, coef, gamma, diag_on);
+}
+
+Bsr axpby3(Ctx& c, double alpha, const Bsr* A, double beta, const Bsr* B, double kappa, const Bsr* C) {
+  const Bsr* src[3] = {A, B, C};
+  const double coef[3] = {alpha, beta, kappa};
+  return union_sum(c, src, coef, 0.0, nullptr);
+}
+
 Bsr filter(Ctx& c, const Bsr& A, const int* rlab, const int* clab, int mode) {
   const int nb = A.nb;
-  Bsr C;
-  C.n = A.n;
-  C.b = A.b;
-  C.nb = nb;
+  Bsr C = like(A);
+  C.nnzb = -1;
+  C.cap = A.bound();
   DBuf<int> cnt(c.pool, nb);
   launch_filter_counts(c, A.row_ptr.get(), A.col.get(), rlab, clab ? clab : rlab, mode, nb, cnt.get());
   C.row_ptr = DBuf<int>(c.pool, nb + 1);
   scan_exclusive_i32(c, cnt.get(), C.row_ptr.get(), nb);
-  const int nnz = read1(c, C.row_ptr.get() + nb);
-  C.nnzb = nnz;
-  C.col = DBuf<int>(c.pool, (size_t)nnz);
-  DBuf<int> src(c.pool, (size_t)nnz);
-  C.val = DBuf<double>(c.pool, (size_t)nnz * C.b * C.b);
-  if (nnz) {
+  C.col = DBuf<int>(c.pool, (size_t)C.cap);
+  DBuf<int> src(c.pool, (size_t)C.cap);
+  C.val = DBuf<double>(c.pool, (size_t)C.cap * C.b * C.b);
+  if (C.cap) {
     launch_filter_fill(c, A.row_ptr.get(), A.col.get(), rlab, clab ? clab : rlab, mode, C.row_ptr.get(), nb,
                        C.col.get(), src.get());
-    launch_gather_blocks(c, A.val.get(), src.get(), nnz, C.b, C.val.get());
+    launch_gather_blocks(c, A.val.get(), src.get(), C.cap, C.b, C.val.get(), C.live());
   }
   return C;
 }
@@ -263,10 +295,17 @@ double gershgorin(Ctx& c, const Bsr& A) {
 std::vector<double> node_sumsq(Ctx& c, const Bsr& A, const int* rlo, const int* rhi, int nseg) {
   std::vector<double> out(nseg, 0.0);
   if (nseg == 0) return out;
-  DBuf<double> ss(c.pool, (size_t)std::max<int64_t>(A.nnzb, 1)), seg(c.pool, nseg);
-  launch_block_sumsq(c, A.val.get(), A.nnzb, A.b, ss.get(), false);
+  DBuf<double> ss(c.pool, (size_t)std::max<int64_t>(A.bound(), 1)), seg(c.pool, nseg);
+  launch_block_sumsq(c, A.val.get(), A.bound(), A.b, ss.get(), false, A.live());
   launch_segment_sum(c, ss.get(), A.row_ptr.get(), rlo, rhi, nseg, seg.get());
-  c.d2h(out.data(), seg.get(), nseg * sizeof(double));
+  int na = 0;
+  std::vector<Ctx::Read> reads;
+  for (int s = 0; s < nseg; s += 8)
+    reads.push_back({out.data() + s, seg.get() + s, sizeof(double) * (size_t)std::min(8, nseg - s)});
+  const bool need = A.nnzb < 0;
+  if (need) reads.push_back({&na, A.live(), sizeof(int)});
+  c.d2h_batch(reads);
+  if (need) A.nnzb = na;
   return out;
 }
 

@@ -110,19 +110,20 @@ void Ctx::d2h(void* dst, const void* src, size_t bytes) {
   std::memcpy(dst, pinned, bytes);
 }
 
-void Ctx::d2h2(void* d0, const void* s0, size_t b0, void* d1, const void* s1, size_t b1) {
-  if (pinned_bytes < 128) {
+void Ctx::d2h_batch(const std::vector<Read>& reads) {
+  const size_t need = 64 * reads.size();
+  if (pinned_bytes < need || pinned_bytes < 4096) {
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
-    LIF_HIP(hipHostMalloc(&pinned, 4096, hipHostMallocDefault));
-    pinned_bytes = 4096;
+    const size_t want = need < 4096 ? 4096 : need;
+    LIF_HIP(hipHostMalloc(&pinned, want, hipHostMallocDefault));
+    pinned_bytes = want;
   }
   char* p = static_cast<char*>(pinned);
-  LIF_HIP(hipMemcpyAsync(p, s0, b0, hipMemcpyDeviceToHost, stream));
-  LIF_HIP(hipMemcpyAsync(p + 64, s1, b1, hipMemcpyDeviceToHost, stream));
+  for (size_t i = 0; i < reads.size(); ++i)
+    LIF_HIP(hipMemcpyAsync(p + 64 * i, reads[i].src, reads[i].bytes, hipMemcpyDeviceToHost, stream));
   LIF_HIP(hipStreamSynchronize(stream));
-  std::memcpy(d0, p, b0);
-  std::memcpy(d1, p + 64, b1);
+  for (size_t i = 0; i < reads.size(); ++i) std::memcpy(reads[i].dst, p + 64 * i, reads[i].bytes);
 }
 
 Ctx::~Ctx() {

@@ -160,6 +160,7 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
     __syncthreads();
   }
   int64_t prow = prp[i];
+  if (i == nb - 1 && threadIdx.x == 0) seg[crp[nb]] = prp[nb];  // closing segment pointer
   int acc = threadIdx.x ? scan_tmp[threadIdx.x - 1] : 0;
   for (int r = c0; r < c1; ++r) {
     const int cnt = cur[r];
