@@ -158,6 +158,25 @@ lif_status lif_multiply(lif_handle h, const lif_blocks* A, int32_t transA, const
                         int32_t transB, double tau, int64_t* nnzb, int32_t* brow, int32_t* bcol,
                         double* vals, int32_t on_device, int64_t* products);
 
+/* Reverse-mode derivative of the last factorization (differentiation form):
+ * dS = sym(dL/dS) = (A + A^T) / 2 for the linear loss L = tr(G^T Z), so that
+ * dL = <dS, E> for every symmetric perturbation E of S.  Returned on S's block
+ * pattern (the truncated S the handle holds; blocks where the derivative has
+ * no contribution are zero).  The iteration is differentiated through the
+ * regular recurrence delta_i = I - Z_i^T S Z_i of eq. refinement_nonlocal
+ * (equal to the localized iterates in exact arithmetic) with the iteration
+ * counts of the forward run frozen and untruncated FP64 products; LIF levels
+ * pass the diagonal parts of dL/dZ_0 to their children, and leaves use the
+ * inverse-Cholesky adjoint.  The IRSI start scale c is held constant.
+ * Needs the forward (lif_refine with Z0 == NULL, or lif_localized) to have
+ * run with opts.checkpoint = 1, else LIF_ERR_STATE.  G: the handle's n and
+ * b, any block pattern.  Two-phase: with brow == NULL the derivative is
+ * computed, kept in the handle and *nnzb is set; a call with arrays copies
+ * the kept derivative (G may then be NULL) or, if none is kept, computes it
+ * first; the kept derivative is released after the copy. */
+lif_status lif_backward(lif_handle h, const lif_blocks* G, int64_t* nnzb, int32_t* brow, int32_t* bcol, double* dS,
+                        int32_t on_device);
+
 /* Releases the handle and all its device memory.  NULL is ignored. */
 void lif_destroy(lif_handle h);
 

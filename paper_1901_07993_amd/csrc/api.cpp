@@ -16,6 +16,9 @@ struct lif_handle_s {
   Bsr S;
   Bsr Z;
   bool has_Z = false;
+  Checkpoints ck;
+  Bsr dS;
+  bool has_dS = false;
   std::string err;
   explicit lif_handle_s(uint64_t cap) : pool(cap) {}
 };
@@ -261,7 +264,9 @@ lif_status lif_refine(lif_handle h, const lif_blocks* Z0, lif_info* info) {
       Bsr z = bsr_from_blocks(h->ctx, *Z0);
       Z = run_refine_from(h->ctx, h->S, std::move(z), h->opts, ri);
     } else {
-      Z = run_irsi(h->ctx, h->S, h->opts, ri);
+      h->ck.clear();
+      h->has_dS = false;
+      Z = run_irsi(h->ctx, h->S, h->opts, ri, h->opts.checkpoint ? &h->ck : nullptr);
     }
     h->ctx.sync();
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -277,7 +282,9 @@ lif_status lif_localized(lif_handle h, lif_info* info) {
     reset_stats(h);
     const auto t0 = std::chrono::steady_clock::now();
     RunInfo ri;
-    Bsr Z = run_lif(h->ctx, h->S, h->opts, ri);
+    h->ck.clear();
+    h->has_dS = false;
+    Bsr Z = run_lif(h->ctx, h->S, h->opts, ri, h->opts.checkpoint ? &h->ck : nullptr);
     h->ctx.sync();
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     h->Z = std::move(Z);
@@ -327,6 +334,30 @@ lif_status lif_multiply(lif_handle h, const lif_blocks* A, int32_t transA, const
     st = copy_out(h, C, nnzb, brow, bcol, vals, on_device);
     h->ctx.sync();
     h->ctx.flush_timing();
+  });
+  return g != LIF_OK ? g : st;
+}
+
+lif_status lif_backward(lif_handle h, const lif_blocks* G, int64_t* nnzb, int32_t* brow, int32_t* bcol, double* dS,
+                        int32_t on_device) {
+  if (!h) return LIF_ERR_INVALID;
+  lif_status st = LIF_OK;
+  lif_status g = guarded(h, [&] {
+    LIF_REQUIRE(nnzb != nullptr, LIF_ERR_INVALID, "nnzb is null");
+    LIF_REQUIRE(h->ck.valid, LIF_ERR_STATE,
+                "no checkpoints: run lif_refine (IRSI) or lif_localized with opts.checkpoint = 1 first");
+    if (!h->has_dS || brow == nullptr) {
+      validate_blocks(G, false, "G");
+      LIF_REQUIRE(G->n == h->S.n && G->b == h->S.b, LIF_ERR_INVALID, "G must have the n and b of S");
+      Bsr g = bsr_from_blocks(h->ctx, *G);
+      h->dS = run_backward(h->ctx, h->S, h->ck, g, h->opts);
+      h->has_dS = true;
+    }
+    st = copy_out(h, h->dS, nnzb, brow, bcol, dS, on_device);
+    if (brow != nullptr && st == LIF_OK) {
+      h->dS = Bsr();
+      h->has_dS = false;
+    }
   });
   return g != LIF_OK ? g : st;
 }

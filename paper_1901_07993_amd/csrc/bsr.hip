@@ -241,10 +241,13 @@ __global__ void k_block_row_of(const int* __restrict__ rp, int nb, int* __restri
 //   mode 1: rlab[i] >= 0, rlab[i] even, clab[j] == rlab[i] + 1
 //           (labels 2 g + side: leading part A to trailing part C of group g)
 //   mode 2: rlab[i] >= 0                                   (rows of active groups)
+//   mode 3: rlab[i] >= 0 && clab[j] >= rlab[i]             (upper block triangle
+//           when the labels are the block indices)
 __device__ inline bool keep_pred(int mode, int li, int lj) {
   if (li < 0) return false;
   if (mode == 0) return li == lj;
   if (mode == 1) return ((li & 1) == 0) && lj == li + 1;
+  if (mode == 3) return lj >= li;
   return true;
 }
 
@@ -351,6 +354,50 @@ __global__ __launch_bounds__(kWG) void k_segment_sum(const double* __restrict__ 
   for (int e = lo + threadIdx.x; e < hi; e += kWG) v += sumsq[e];
   double r = block_sum_256(v, sh);
   if (threadIdx.x == 0) out[s] = r;
+}
+
+// Blocks of A whose coordinates also occur in the reference pattern R.
+__global__ void k_intersect_counts(const int* __restrict__ ra, const int* __restrict__ ca, const int* __restrict__ rr,
+                                   const int* __restrict__ cr, int nb, int* __restrict__ counts,
+                                   const int* __restrict__ nrp, int* __restrict__ ncol, int* __restrict__ src) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  int pa = ra[i], ea = ra[i + 1], pr = rr[i], er = rr[i + 1];
+  int o = nrp ? nrp[i] : 0, cnt = 0;
+  while (pa < ea && pr < er) {
+    const int xa = ca[pa], xr = cr[pr];
+    if (xa == xr) {
+      if (nrp) {
+        ncol[o] = xa;
+        src[o] = pa;
+        ++o;
+      }
+      ++cnt;
+      ++pa;
+      ++pr;
+    } else if (xa < xr) {
+      ++pa;
+    } else {
+      ++pr;
+    }
+  }
+  if (!nrp) counts[i] = cnt;
+}
+
+// Inverse-Cholesky adjoint mask on block row/col coordinates: diagonal
+// blocks keep their upper triangle with the diagonal halved; other blocks
+// are left as they are (the caller keeps only blocks with col >= row).
+__global__ __launch_bounds__(kWG) void k_phi_diag(const int* __restrict__ row_of, const int* __restrict__ col,
+                                                  int b, double* __restrict__ val, const int* __restrict__ live) {
+  const int64_t e = blockIdx.x;
+  if (live && e >= *live) return;
+  if (row_of[e] != col[e]) return;
+  double* v = val + e * (int64_t)b * b;
+  for (int q = threadIdx.x; q < b * b; q += kWG) {
+    const int r = q / b, cc = q % b;
+    if (cc < r) v[q] = 0.0;
+    else if (cc == r) v[q] *= 0.5;
+  }
 }
 
 __global__ void k_fill_i32(int* p, int value, int64_t count) {
@@ -478,6 +525,17 @@ void launch_segment_sum(Ctx& c, const double* sumsq, const int* row_ptr, const i
                         double* out) {
   if (nseg == 0) return;
   LIF_LAUNCH(k_segment_sum, dim3(nseg), dim3(kWG), 0, c.stream, sumsq, row_ptr, rlo, rhi, out);
+}
+
+void launch_intersect(Ctx& c, const int* ra, const int* ca, const int* rr, const int* cr, int nb, int* counts,
+                      const int* nrp, int* ncol, int* src) {
+  LIF_LAUNCH(k_intersect_counts, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, ra, ca, rr, cr, nb, counts, nrp, ncol,
+             src);
+}
+
+void launch_phi_diag(Ctx& c, const int* row_of, const int* col, int64_t nnzb, int b, double* val, const int* live) {
+  if (nnzb == 0) return;
+  LIF_LAUNCH(k_phi_diag, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, row_of, col, b, val, live);
 }
 
 void launch_fill_i32(Ctx& c, int* p, int value, int64_t count) {

@@ -199,6 +199,10 @@ void launch_transpose_blocks(Ctx& c, const double* val, const int* src, int64_t 
 void launch_segment_sum(Ctx& c, const double* sumsq, const int* row_ptr, const int* rlo, const int* rhi, int nseg,
                         double* out);
 void launch_fill_i32(Ctx& c, int* p, int value, int64_t count);
+// counts (nrp == null) or fills (nrp given) the blocks of A present in pattern R
+void launch_intersect(Ctx& c, const int* ra, const int* ca, const int* rr, const int* cr, int nb, int* counts,
+                      const int* nrp, int* ncol, int* src);
+void launch_phi_diag(Ctx& c, const int* row_of, const int* col, int64_t nnzb, int b, double* val, const int* live);
 
 // spgemm.hip
 // Symbolic phase.  opA given as CSR (row ptr, col, value index) of op(A);
@@ -267,5 +271,10 @@ std::vector<double> node_sumsq(Ctx& c, const Bsr& A, const int* rlo, const int* 
 Bsr copy(Ctx& c, const Bsr& A);
 // exact block count (reads it from the device when only the device knows it)
 int64_t exact_nnzb(Ctx& c, const Bsr& A);
+// blocks of A that also occur in R's pattern
+Bsr intersect(Ctx& c, const Bsr& A, const Bsr& R);
+// upper block triangle of W with the diagonal blocks' upper triangles and
+// halved diagonals (the mask of the inverse-Cholesky adjoint)
+Bsr phi_upper(Ctx& c, const Bsr& W);
 
 }  // namespace lif

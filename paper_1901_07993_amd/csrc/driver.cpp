@@ -60,7 +60,7 @@ struct Batch {
 };
 
 void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, const Opts& o,
-                  std::vector<NodeState>& st, int max_iter) {
+                  std::vector<NodeState>& st, int max_iter, std::vector<Bsr>* ck = nullptr) {
   const int nn = (int)bt.rlo.size();
   const int nb = bt.nb;
   const std::vector<double> bk = coefficients(o.m);
@@ -136,6 +136,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
     delta = axpby3(c, 1.0, &delta, -1.0, &X1, -1.0, &X2);
     X1 = Bsr();
     X2 = Bsr();
+    if (ck) ck->push_back(std::move(Z));  // Z_k is immutable: keep it, no copy
     Z = std::move(Znew);
 
     std::vector<double> ss = node_sumsq(c, delta, d_rlo.get(), d_rhi.get(), nn);
@@ -202,7 +203,7 @@ Plan make_plan(int64_t n, int b, int64_t base_rows) {
   return p;
 }
 
-Bsr run_irsi(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info) {
+Bsr run_irsi(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck) {
   double cs = 0.0;
   if (o.start == LIF_START_GIVEN) {
     cs = o.start_value;
@@ -222,7 +223,19 @@ Bsr run_irsi(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info) {
   bt.rlo = {0};
   bt.rhi = {S.nb};
   std::vector<NodeState> st;
-  refine_batch(c, S, Z, std::move(delta), bt, o, st, o.max_iter);
+  LevelCk* L = nullptr;
+  if (ck) {
+    ck->clear();
+    ck->levels.emplace_back();
+    L = &ck->levels.back();
+    L->rlo = bt.rlo;
+    L->rhi = bt.rhi;
+  }
+  refine_batch(c, S, Z, std::move(delta), bt, o, st, o.max_iter, L ? &L->Z : nullptr);
+  if (L) {
+    L->iters = {st[0].iterations};
+    ck->valid = true;
+  }
   info.iterations_top = st[0].iterations;
   info.iterations_total = st[0].iterations;
   info.stagnated = st[0].stagnated;
@@ -337,7 +350,7 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   return truncate(c, std::move(Z), nrm.get(), std::max(tau, std::numeric_limits<double>::denorm_min()));
 }
 
-Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info) {
+Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck) {
   const int b = S.b, nb = S.nb;
   const Plan plan = make_plan(S.n, b, o.base_rows);
   std::vector<std::pair<int64_t, int64_t>> leaves;
@@ -345,6 +358,11 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info) {
     if (nd.left < 0) leaves.emplace_back(nd.lo, nd.hi);
   std::sort(leaves.begin(), leaves.end());
   Bsr Z = leaf_inverse_cholesky(c, S, leaves, o.tau);
+  if (ck) {
+    ck->clear();
+    ck->lif = true;
+    ck->Z_leaf = copy(c, Z);
+  }
   info.levels = 0;
   info.iterations_total = 0;
   for (int d = plan.max_depth - 1; d >= 0; --d) {
@@ -384,7 +402,33 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info) {
     X = Bsr();
     Xt = Bsr();
     std::vector<NodeState> st;
-    refine_batch(c, S_lvl, Z, std::move(delta0), bt, o, st, o.max_iter);
+    LevelCk* L = nullptr;
+    if (ck) {
+      ck->levels.emplace(ck->levels.begin());  // top level first
+      L = &ck->levels.front();
+      L->rlo = bt.rlo;
+      L->rhi = bt.rhi;
+      // parts after the split: children of this depth's nodes, and every
+      // other row keeps the leaf or node it belongs to at this stage
+      L->part_lab.assign(nb, -1);
+      int next = 0;
+      for (int s = 0; s < nn; ++s)
+        for (int i = bt.rlo[s]; i < bt.rhi[s]; ++i) L->part_lab[i] = 2 * s + (side[i] & 1);
+      next = 2 * nn;
+      for (const auto& nd : plan.nodes) {
+        const bool part = (nd.depth == d + 1) || (nd.left < 0 && nd.depth <= d);
+        if (!part) continue;
+        const int r0 = (int)(nd.lo / b), r1 = (int)((nd.hi + b - 1) / b);
+        if (L->part_lab[r0] >= 0) continue;  // a child of this depth, labelled above
+        for (int i = r0; i < r1; ++i) L->part_lab[i] = next;
+        ++next;
+      }
+    }
+    refine_batch(c, S_lvl, Z, std::move(delta0), bt, o, st, o.max_iter, L ? &L->Z : nullptr);
+    if (L) {
+      for (auto& ns : st) L->iters.push_back(ns.iterations);
+      L->S_lvl = std::move(S_lvl);
+    }
     info.levels += 1;
     for (auto& ns : st) info.iterations_total += ns.iterations;
     if (d == 0) {
@@ -395,6 +439,7 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info) {
     }
     c.sync();  // label vectors go out of scope
   }
+  if (ck) ck->valid = true;
   return Z;
 }
 

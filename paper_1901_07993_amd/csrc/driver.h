@@ -46,16 +46,44 @@ struct RunInfo {
   std::vector<double> norms_top;
 };
 
+// Per-iteration checkpoints of a forward run, for the reverse sweep.
+// A level is one batch of independent problems refined together (IRSI: one
+// problem on all rows).
+struct LevelCk {
+  std::vector<int> rlo, rhi;   // block-row range of each problem
+  std::vector<int> iters;      // refinement iterations of each problem
+  std::vector<Bsr> Z;          // Z before each batch iteration: Z_0 .. Z_{K-1}
+  Bsr S_lvl;                   // the level's block-diagonal S (empty: the handle's S)
+  std::vector<int> part_lab;   // per block row: the part (child) the row belongs to after the split
+};
+
+struct Checkpoints {
+  bool valid = false;
+  bool lif = false;
+  std::vector<LevelCk> levels;  // top level first
+  Bsr Z_leaf;                   // LIF: the leaf factors (block diagonal, upper triangular)
+  void clear() {
+    valid = lif = false;
+    levels.clear();
+    Z_leaf = Bsr();
+  }
+};
+
 // Identity-like helpers on the context: a per-block-row flag array with
 // every row set.
 const unsigned char* all_rows_on(Ctx& c);
 
-// IRSI: Z_0 = c I, delta_0 = I - c^2 S.
-Bsr run_irsi(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info);
+// IRSI: Z_0 = c I, delta_0 = I - c^2 S.  ck (may be null) receives the
+// per-iteration checkpoints.
+Bsr run_irsi(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck = nullptr);
 // Refinement from a given start: delta_0 = I - Z0^T S Z0 (products truncated).
 Bsr run_refine_from(Ctx& c, const Bsr& S, Bsr&& Z0, const Opts& o, RunInfo& info);
 // Localized inverse factorization.
-Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info);
+Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck = nullptr);
+// Reverse sweep: sym(dL/dS) on S's block pattern for L = tr(G^T Z), through
+// the regular recurrence delta_i = I - Z_i^T S Z_i with the checkpointed Z_i
+// and frozen iteration counts; untruncated FP64 products.
+Bsr run_backward(Ctx& c, const Bsr& S, const Checkpoints& ck, const Bsr& G, const Opts& o);
 // Batched leaf factorization of the diagonal ranges [lo_k, hi_k) of S:
 // block-diagonal upper-triangular Z with Z_k^T S_k Z_k = I, truncated at tau.
 Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int64_t, int64_t>>& ranges,

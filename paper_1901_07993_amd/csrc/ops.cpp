@@ -285,6 +285,40 @@ Bsr filter(Ctx& c, const Bsr& A, const int* rlab, const int* clab, int mode) {
   return C;
 }
 
+Bsr intersect(Ctx& c, const Bsr& A, const Bsr& R) {
+  const int nb = A.nb;
+  Bsr C = like(A);
+  C.nnzb = -1;
+  C.cap = A.bound();
+  DBuf<int> cnt(c.pool, nb);
+  launch_intersect(c, A.row_ptr.get(), A.col.get(), R.row_ptr.get(), R.col.get(), nb, cnt.get(), nullptr, nullptr,
+                   nullptr);
+  C.row_ptr = DBuf<int>(c.pool, nb + 1);
+  scan_exclusive_i32(c, cnt.get(), C.row_ptr.get(), nb);
+  C.col = DBuf<int>(c.pool, (size_t)C.cap);
+  DBuf<int> src(c.pool, (size_t)C.cap);
+  C.val = DBuf<double>(c.pool, (size_t)C.cap * C.b * C.b);
+  if (C.cap) {
+    launch_intersect(c, A.row_ptr.get(), A.col.get(), R.row_ptr.get(), R.col.get(), nb, nullptr, C.row_ptr.get(),
+                     C.col.get(), src.get());
+    launch_gather_blocks(c, A.val.get(), src.get(), C.cap, C.b, C.val.get(), C.live());
+  }
+  return C;
+}
+
+Bsr phi_upper(Ctx& c, const Bsr& W) {
+  std::vector<int> idx(W.nb);
+  for (int i = 0; i < W.nb; ++i) idx[i] = i;
+  DBuf<int> d_idx(c.pool, W.nb);
+  h2d(c, d_idx.get(), idx.data(), W.nb);
+  Bsr U = filter(c, W, d_idx.get(), d_idx.get(), 3);
+  DBuf<int> rowof(c.pool, (size_t)std::max<int64_t>(U.cap, 1));
+  launch_block_row_of(c, U.row_ptr.get(), U.nb, U.cap, rowof.get());
+  launch_phi_diag(c, rowof.get(), U.col.get(), U.cap, U.b, U.val.get(), U.live());
+  c.sync();  // idx goes out of scope
+  return U;
+}
+
 double gershgorin(Ctx& c, const Bsr& A) {
   DBuf<double> rowmax(c.pool, A.nb), mx(c.pool, 1);
   launch_gershgorin(c, A.row_ptr.get(), A.val.get(), A.nb, A.b, rowmax.get());

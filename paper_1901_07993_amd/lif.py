@@ -27,7 +27,7 @@ _STATUS_NAMES = {1: "LIF_ERR_INVALID", 2: "LIF_ERR_NOT_PD", 3: "LIF_ERR_NO_CONVE
                  4: "LIF_ERR_OUT_OF_MEMORY", 5: "LIF_ERR_HIP", 6: "LIF_ERR_STATE"}
 
 EXPORTED = ("lif_opts_default", "lif_create", "lif_refine", "lif_localized", "lif_get_Z", "lif_residual",
-            "lif_multiply", "lif_destroy", "lif_last_error")
+            "lif_multiply", "lif_backward", "lif_destroy", "lif_last_error")
 
 
 class LifError(RuntimeError):
@@ -79,6 +79,7 @@ def load() -> ctypes.CDLL:
     lib.lif_residual.argtypes = [c_void_p, POINTER(c_double)]
     lib.lif_multiply.argtypes = [c_void_p, POINTER(Blocks), c_int32, POINTER(Blocks), c_int32, c_double,
                                  POINTER(c_int64), c_void_p, c_void_p, c_void_p, c_int32, POINTER(c_int64)]
+    lib.lif_backward.argtypes = [c_void_p, POINTER(Blocks), POINTER(c_int64), c_void_p, c_void_p, c_void_p, c_int32]
     lib.lif_destroy.argtypes = [c_void_p]
     lib.lif_destroy.restype = None
     lib.lif_last_error.argtypes = [c_void_p]
@@ -225,6 +226,21 @@ class Factorization:
                                      brow.ctypes.data, bcol.ctypes.data, vals.ctypes.data, 0, byref(prods)))
         del ka, kb
         return HostBlocks(self.n, self.b, brow, bcol, vals), prods.value
+
+    def backward(self, G) -> HostBlocks:
+        """sym(dL/dS) on S's block pattern for L = tr(G^T Z) (needs checkpoint=1)."""
+        lib = load()
+        st, keep = _marshal(G)
+        nnzb = c_int64(0)
+        self._check(lib.lif_backward(self._h, byref(st), byref(nnzb), None, None, None, 0))
+        k = nnzb.value
+        brow = np.empty(k, np.int32)
+        bcol = np.empty(k, np.int32)
+        vals = np.empty((k, self.b, self.b), np.float64)
+        self._check(lib.lif_backward(self._h, None, byref(nnzb), brow.ctypes.data, bcol.ctypes.data,
+                                     vals.ctypes.data, 0))
+        del keep
+        return HostBlocks(self.n, self.b, brow, bcol, vals)
 
     def close(self):
         if getattr(self, "_h", None):
