@@ -161,7 +161,7 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trsm(int k, const int* 
   const int j = k + 1 + blockIdx.x;
   if (j >= nbb || !nz[packed_tile(tile0[s], nbb, k, j)]) return;
   const Frag f = frag_coords<B>();
-  double2 reg[Cfg::V2];
+  v2d reg[Cfg::V2];
   tile_load<B>(Z + packed_tile(tile0[s], nbb, k, k) * B * B, reg);
   tile_store<B>(As, reg, true);  // op(A) = Z_kk^T: LDS row k is row k of Z_kk
   double* g = U + packed_tile(tile0[s], nbb, k, j) * B * B;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_update(int k, const int
   const int i = k + 1 + ip, j = k + 1 + jp;
   if (!nz[packed_tile(tile0[s], nbb, k, i)] || !nz[packed_tile(tile0[s], nbb, k, j)]) return;
   const Frag f = frag_coords<B>();
-  double2 reg[Cfg::V2];
+  v2d reg[Cfg::V2];
   tile_load<B>(U + packed_tile(tile0[s], nbb, k, i) * B * B, reg);
   tile_store<B>(As, reg, true);  // op(A) = U_ki^T
   tile_load<B>(U + packed_tile(tile0[s], nbb, k, j) * B * B, reg);
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, const int*
   const int64_t t0 = tile0[s];
   v4d acc[2][2];
   acc_zero(acc);
-  double2 ra[Cfg::V2], rb[Cfg::V2];
+  v2d ra[Cfg::V2], rb[Cfg::V2];
   // k with U_kj != 0, visited in ascending order; the next pair's tiles are
   // loaded into registers while the current one is multiplied
   auto next_k = [&](int k) {

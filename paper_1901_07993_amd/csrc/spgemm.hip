@@ -11,13 +11,11 @@
 // each output block in ascending inner index k -- so every output block is
 // summed in the same order on every run (no atomics on values).
 //
-// Numeric phase (FP64 MFMA): one workgroup per output block.  For each pair
-// of its segment the two b x b operand blocks are staged through LDS (k-major
-// layout so MFMA fragments are contiguous 16-double rows), with the next
-// pair's blocks prefetched into registers while the current one is
-// multiplied.  v_mfma_f64_16x16x4f64 accumulates the whole segment in
-// registers; the block is written once, together with its Frobenius norm
-// (fixed-order FP64 reduction) for the truncation pass.
+// Numeric phase (FP64 MFMA): one workgroup per output block.  The operand
+// blocks of its segment stream through two LDS stages (see k_numeric_f64);
+// v_mfma_f64_16x16x4f64 accumulates the whole segment in registers; the
+// block is written once, together with its Frobenius norm (fixed-order FP64
+// reduction) for the truncation pass.
 #include "common.h"
 #include "tile_mma.h"
 
@@ -199,6 +197,33 @@ __device__ inline int64_t xcd_remap(int64_t wg, int64_t total) {
   return x * q + (x < r ? x : r) + l;
 }
 
+// Operand blocks are stored into LDS as they are (row-major, 16-byte
+// stores); op() is applied when the MFMA fragments are read: a fragment is
+// either 16 consecutive doubles or 16 doubles one LDS row (66 doubles) apart,
+// both conflict-free within a quarter-wave.  Two LDS stages: while the
+// waves multiply the tiles of pair p, the tiles of pair p+1 are written to
+// the other stage and those of pair p+2 are loaded into registers, with one
+// barrier per pair.
+template <int B, bool TA, bool TB>
+__device__ inline void mma_stage(const double* __restrict__ As, const double* __restrict__ Bs, const Frag& f,
+                                 v4d (&acc)[2][2]) {
+  constexpr int LD = TileCfg<B>::LD;
+#pragma unroll 4
+  for (int kk = 0; kk < B / 4; ++kk) {
+    const int k = 4 * kk + f.kq;
+    // op(A)[i][k]: A[i][k] (row i of the stored block) or A[k][i] (row k)
+    const double a0 = TA ? As[k * LD + f.rb + f.l16] : As[(f.rb + f.l16) * LD + k];
+    const double a1 = TA ? As[k * LD + f.rb + 16 + f.l16] : As[(f.rb + 16 + f.l16) * LD + k];
+    // op(B)[k][j]: B[k][j] or B[j][k]
+    const double b0 = TB ? Bs[(f.cb + f.l16) * LD + k] : Bs[k * LD + f.cb + f.l16];
+    const double b1 = TB ? Bs[(f.cb + 16 + f.l16) * LD + k] : Bs[k * LD + f.cb + 16 + f.l16];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
+
 template <int B, bool TA, bool TB>
 __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const double* __restrict__ A,
                                                                      const double* __restrict__ Bm,
@@ -207,8 +232,8 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const doubl
                                                                      double* __restrict__ C,
                                                                      double* __restrict__ norms) {
   using Cfg = TileCfg<B>;
-  __shared__ double As[Cfg::LDS_DOUBLES];
-  __shared__ double Bs[Cfg::LDS_DOUBLES];
+  __shared__ double As[2][Cfg::LDS_DOUBLES];
+  __shared__ double Bs[2][Cfg::LDS_DOUBLES];
   __shared__ double red[Cfg::WAVES];
   const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
   if (blk >= nnzc) return;
@@ -217,25 +242,33 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const doubl
 
   v4d acc[2][2];
   acc_zero(acc);
-  double2 ra[Cfg::V2], rbv[Cfg::V2];
+  // The loop body has no branches around the prefetch registers (the
+  // prefetch index is clamped to the last pair; the surplus loads and the
+  // last surplus LDS store are never read), which keeps them in VGPRs.
+  v2d ra[Cfg::V2], rbv[Cfg::V2];
+  const int64_t plast = p1 - 1;
   {
     const int2 pr = pairs[p0];
     tile_load<B>(A + (int64_t)pr.x * B * B, ra);
     tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
   }
+  tile_store<B>(As[0], ra, true);
+  tile_store<B>(Bs[0], rbv, true);
+  {
+    const int2 pr = pairs[min(p0 + 1, plast)];
+    tile_load<B>(A + (int64_t)pr.x * B * B, ra);
+    tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
+  }
+  int stage = 0;
   for (int64_t p = p0; p < p1; ++p) {
-    __syncthreads();
-    // op(A) = A needs LDS row k = column k of the block (transposing store);
-    // op(A) = A^T has it as row k already.  For B the other way round.
-    tile_store<B>(As, ra, TA);
-    tile_store<B>(Bs, rbv, !TB);
-    __syncthreads();
-    if (p + 1 < p1) {
-      const int2 pr = pairs[p + 1];
-      tile_load<B>(A + (int64_t)pr.x * B * B, ra);
-      tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
-    }
-    tile_mma<B>(As, Bs, f, acc);
+    __syncthreads();  // stage p visible; stage p+1's previous readers done
+    tile_store<B>(As[stage ^ 1], ra, true);
+    tile_store<B>(Bs[stage ^ 1], rbv, true);
+    const int2 pr = pairs[min(p + 2, plast)];
+    tile_load<B>(A + (int64_t)pr.x * B * B, ra);
+    tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
+    mma_stage<B, TA, TB>(As[stage], Bs[stage], f, acc);
+    stage ^= 1;
   }
 
   // epilogue: write the block, FP64 sum of squares in a fixed order

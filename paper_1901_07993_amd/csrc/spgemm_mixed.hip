@@ -48,7 +48,7 @@ struct MixCfg {
 
 // FP32 staging, k-major: direct -> LDS row r holds global row r.
 template <int B>
-__device__ inline void store_f32(float* __restrict__ s, const double2* reg, bool direct) {
+__device__ inline void store_f32(float* __restrict__ s, const v2d* reg, bool direct) {
   using Cfg = MixCfg<B>;
 #pragma unroll
   for (int v = 0; v < Cfg::V2; ++v) {
@@ -66,7 +66,7 @@ __device__ inline void store_f32(float* __restrict__ s, const double2* reg, bool
 
 // BF16 staging: direct -> LDS row r holds global row r, else row c holds column c.
 template <int B>
-__device__ inline void store_bf16(unsigned short* __restrict__ s, const double2* reg, bool direct) {
+__device__ inline void store_bf16(unsigned short* __restrict__ s, const v2d* reg, bool direct) {
   using Cfg = MixCfg<B>;
 #pragma unroll
   for (int v = 0; v < Cfg::V2; ++v) {
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(const double
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-  double2 ra[Cfg::V2], rbv[Cfg::V2];
+  v2d ra[Cfg::V2], rbv[Cfg::V2];
   {
     const int2 pr = pairs[p0];
     tile_load<B>(A + (int64_t)pr.x * B * B, ra);
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(const doubl
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-  double2 ra[Cfg::V2], rbv[Cfg::V2];
+  v2d ra[Cfg::V2], rbv[Cfg::V2];
   {
     const int2 pr = pairs[p0];
     tile_load<B>(A + (int64_t)pr.x * B * B, ra);

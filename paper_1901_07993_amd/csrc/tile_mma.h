@@ -19,6 +19,9 @@
 namespace lif {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+// native 2-vector for the prefetch registers (HIP's double2 struct is copied
+// through memory when stored whole, which sends the arrays to scratch)
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 template <int B>
 struct TileCfg {
@@ -31,9 +34,10 @@ struct TileCfg {
 
 // Global (row-major b x b tile) -> registers, coalesced 16-byte loads.
 template <int B>
-__device__ inline void tile_load(const double* __restrict__ g, double2* reg) {
+__device__ __attribute__((always_inline)) inline void tile_load(const double* __restrict__ g,
+                                                                v2d (&reg)[TileCfg<B>::V2]) {
   using Cfg = TileCfg<B>;
-  const double2* p = reinterpret_cast<const double2*>(g);
+  const v2d* p = reinterpret_cast<const v2d*>(g);
 #pragma unroll
   for (int v = 0; v < Cfg::V2; ++v) reg[v] = p[threadIdx.x + v * Cfg::THREADS];
 }
@@ -42,14 +46,15 @@ __device__ inline void tile_load(const double* __restrict__ g, double2* reg) {
 // (operand used as its own k-major layout); otherwise LDS row c takes global
 // column c (a transposing store).
 template <int B>
-__device__ inline void tile_store(double* __restrict__ s, const double2* reg, bool direct) {
+__device__ __attribute__((always_inline)) inline void tile_store(double* __restrict__ s,
+                                                                 const v2d (&reg)[TileCfg<B>::V2], bool direct) {
   using Cfg = TileCfg<B>;
 #pragma unroll
   for (int v = 0; v < Cfg::V2; ++v) {
     const int q = 2 * (threadIdx.x + v * Cfg::THREADS);
     const int r = q / B, c = q % B;
     if (direct) {
-      *reinterpret_cast<double2*>(s + r * Cfg::LD + c) = reg[v];
+      *reinterpret_cast<v2d*>(s + r * Cfg::LD + c) = reg[v];
     } else {
       s[c * Cfg::LD + r] = reg[v].x;
       s[(c + 1) * Cfg::LD + r] = reg[v].y;
