@@ -1,0 +1,97 @@
+"""Parity at full size: the 100,000-row chain (the benchmark workload, in
+the configuration bench.py times) and the dense 14,000-row water cluster.
+
+The dense oracle cannot hold these sizes, so the checks are
+* exact integer results: block-product counts of a product, from the
+  patterns alone (oracle.blocks.product_count);
+* sampled outputs the oracle computes one by one: single output blocks of
+  a product, summed over k by oracle.blocks.product_block;
+* properties that hold at any size: the residual floor under truncation,
+  bitwise determinism, the stopping record.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gen import config_matrix  # noqa: E402
+from oracle.blocks import BlockDict, product_block, product_count  # noqa: E402
+from paper_1901_07993_amd import lif  # noqa: E402
+
+from test_gpu_parity import dev  # noqa: E402
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not torch.cuda.is_available(), reason="no GPU")]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def chain():
+    S, cfg = config_matrix(1)
+    return S, cfg
+
+
+def sample_blocks(C, k, seed):
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(C.nnzb, size=min(k, C.nnzb), replace=False)
+    return [(int(C.brow[e]), int(C.bcol[e]), C.vals[e]) for e in idx]
+
+
+def check_product(A, ta, B, tb, C, P, k=40, seed=0, rtol=1e-13):
+    assert P == product_count(A, ta, B, tb)
+    da, db = BlockDict(A), BlockDict(B)
+    for i, j, got in sample_blocks(C, k, seed):
+        ref, nk = product_block(da, ta, db, tb, i, j)
+        assert ref is not None
+        scale = max(1.0, float(np.max(np.abs(ref))))
+        assert np.max(np.abs(got - ref)) <= rtol * scale * nk * A.b
+
+
+def test_chain_full_lif_and_products(chain):
+    S, cfg = chain
+    say(f"case full chain-5000 n={S.n} LIF tau={cfg['tau']}")
+    Sd = dev(S)
+    with lif.Factorization(Sd, tau=cfg["tau"], base_rows=4096, stop=lif.STOP_PAPER) as f:
+        info = f.localized()
+        Z1 = f.get_Z()
+        res = f.residual()
+        info2 = f.localized()
+        Z2 = f.get_Z()
+        say(f"  levels {info['levels']} top iterations {info['iterations_top']} residual {res:.3e}")
+        # the factor: residual floor of per-block truncation at tau = 1e-10
+        assert info["levels"] == 5
+        assert res <= 1e-8 and info["delta_tracked"] <= 1e-9
+        # paper rule: the last norm exceeded the previous one to the power m + 1
+        nr = info["norms"]
+        assert len(nr) == info["iterations_top"] and nr[-1] > nr[-2] ** 5
+        # determinism
+        assert np.array_equal(Z1.brow, Z2.brow) and np.array_equal(Z1.vals, Z2.vals)
+        assert info2["products_total"] == info["products_total"]
+        # products at full size: S S, and Z^T (S Z) with the factor just computed
+        C, P = f.multiply(Sd, False, Sd, False, 0.0)
+        check_product(S, False, S, False, C, P, seed=1)
+        SZ, P2 = f.multiply(Sd, False, dev(Z1), False, 0.0)
+        check_product(S, False, Z1, False, SZ, P2, seed=2)
+        ZSZ, P3 = f.multiply(dev(Z1), True, dev(SZ), False, 0.0)
+        check_product(Z1, True, SZ, False, ZSZ, P3, seed=3)
+        # truncated product at the workload's tau: kept blocks are exact sums
+        Ct, _ = f.multiply(Sd, False, Sd, False, cfg["tau"])
+        norms = np.sqrt(np.einsum("kij,kij->k", Ct.vals, Ct.vals))
+        assert np.all(norms >= cfg["tau"])
+        check_product(S, False, S, False, Ct, P, seed=4)
+
+
+def test_water2000_dense_product_full_size():
+    S, cfg = config_matrix(3)   # n = 14000, tau = 0: all 219^2 blocks
+    say(f"case full water-2000 dense product n={S.n} nnzb={S.nnzb}")
+    assert S.nnzb == S.nb * S.nb
+    Sd = dev(S)
+    with lif.Factorization(Sd) as f:
+        C, P = f.multiply(Sd, False, Sd, True, 0.0)
+    assert P == S.nb ** 3
+    check_product(S, False, S, True, C, P, k=20, seed=5)
