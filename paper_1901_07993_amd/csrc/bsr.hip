@@ -7,6 +7,7 @@
 // These passes stream over HBM; each block is handled by one workgroup with
 // coalesced 16-byte accesses, index work by one thread per block row.
 #include "common.h"
+#include "tile_mma.h"
 
 namespace lif {
 
@@ -138,7 +139,7 @@ struct Src3 {
 };
 
 __device__ inline int union_row(const Src3& S, const unsigned char* diag_on, int i, int* cc, int* ix,
-                                int64_t stride, unsigned char* id) {
+                                int64_t stride, unsigned char* id, int* rowof) {
   int p[3], e[3];
 #pragma unroll
   for (int t = 0; t < 3; ++t) {
@@ -155,6 +156,7 @@ __device__ inline int union_row(const Src3& S, const unsigned char* diag_on, int
     if (cc) {
       cc[o] = x;
       id[o] = (dg && x == i) ? 1 : 0;
+      rowof[o] = i;
     }
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
@@ -171,16 +173,16 @@ __device__ inline int union_row(const Src3& S, const unsigned char* diag_on, int
 __global__ void k_union_counts(Src3 S, const unsigned char* diag_on, int nb, int* counts) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
-  counts[i] = union_row(S, diag_on, i, nullptr, nullptr, 0, nullptr);
+  counts[i] = union_row(S, diag_on, i, nullptr, nullptr, 0, nullptr, nullptr);
 }
 
 // ix holds three index arrays of length stride (one per source), -1 = absent
 __global__ void k_union_fill(Src3 S, const unsigned char* diag_on, const int* rc, int nb, int* cc, int* ix,
-                             int64_t stride, unsigned char* id) {
+                             int64_t stride, unsigned char* id, int* rowof) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
   int o = rc[i];
-  union_row(S, diag_on, i, cc + o, ix + o, stride, id + o);
+  union_row(S, diag_on, i, cc + o, ix + o, stride, id + o, rowof + o);
 }
 
 struct Val3 {
@@ -400,6 +402,122 @@ __global__ __launch_bounds__(kWG) void k_phi_diag(const int* __restrict__ row_of
   }
 }
 
+// ---------------------------------------------------------------------------
+// Per-row counts and their exclusive prefix sum in one workgroup: each thread
+// takes a contiguous run of rows, counts them, the run totals are scanned in
+// LDS, then each thread counts its rows again while writing the row pointers.
+// One launch instead of a count kernel and a scan kernel.
+// ---------------------------------------------------------------------------
+constexpr int kCS = 1024;
+
+template <class Count>
+__global__ __launch_bounds__(kCS) void k_count_scan(Count cnt, int nb, int* __restrict__ rp) {
+  __shared__ int part[kCS];
+  const int t = threadIdx.x;
+  const int chunk = (nb + kCS - 1) / kCS;
+  const int lo = min(nb, t * chunk), hi = min(nb, lo + chunk);
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += cnt(i);
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < kCS; off <<= 1) {
+    const int v = (t >= off) ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = t ? part[t - 1] : 0;
+  for (int i = lo; i < hi; ++i) {
+    rp[i] = run;
+    run += cnt(i);
+  }
+  if (t == kCS - 1) rp[nb] = part[kCS - 1];
+}
+
+struct KeepCount {
+  const int* rp;
+  const double* norms;
+  double tau;
+  __device__ int operator()(int i) const {
+    int c = 0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) c += (norms[e] >= tau) ? 1 : 0;
+    return c;
+  }
+};
+
+struct UnionCount {
+  Src3 S;
+  const unsigned char* diag_on;
+  __device__ int operator()(int i) const { return union_row(S, diag_on, i, nullptr, nullptr, 0, nullptr, nullptr); }
+};
+
+struct FilterCount {
+  const int* rp;
+  const int* col;
+  const int* rlab;
+  const int* clab;
+  int mode;
+  __device__ int operator()(int i) const {
+    const int li = rlab[i];
+    if (li < 0) return 0;
+    int c = 0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) c += keep_pred(mode, li, clab[col[e]]) ? 1 : 0;
+    return c;
+  }
+};
+
+struct IntersectCount {
+  const int* ra;
+  const int* ca;
+  const int* rr;
+  const int* cr;
+  __device__ int operator()(int i) const {
+    int pa = ra[i], ea = ra[i + 1], pr = rr[i], er = rr[i + 1], c = 0;
+    while (pa < ea && pr < er) {
+      const int xa = ca[pa], xr = cr[pr];
+      if (xa == xr) {
+        ++c;
+        ++pa;
+        ++pr;
+      } else if (xa < xr) {
+        ++pa;
+      } else {
+        ++pr;
+      }
+    }
+    return c;
+  }
+};
+
+// Truncation compaction, one workgroup per block of the untruncated matrix:
+// a kept block finds its row (binary search in the row pointers) and its
+// rank among the kept blocks before it in that row, then moves there.
+__global__ __launch_bounds__(kWG) void k_compact_gather(const int* __restrict__ rp, int nb,
+                                                        const int* __restrict__ col,
+                                                        const double* __restrict__ norms, double tau,
+                                                        const int* __restrict__ nrp, const double* __restrict__ val,
+                                                        int bb, int* __restrict__ ncol, double* __restrict__ nval) {
+  __shared__ int dst;
+  const int64_t e = blockIdx.x;
+  if (e >= rp[nb] || !(norms[e] >= tau)) return;
+  if (threadIdx.x == 0) {
+    int lo = 0, hi = nb;  // largest row with rp[row] <= e
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (rp[mid] <= e) lo = mid;
+      else hi = mid;
+    }
+    int rank = 0;
+    for (int f = rp[lo]; f < e; ++f) rank += (norms[f] >= tau) ? 1 : 0;
+    dst = nrp[lo] + rank;
+    ncol[dst] = col[e];
+  }
+  __syncthreads();
+  const v2d* s = reinterpret_cast<const v2d*>(val + e * (int64_t)bb);
+  v2d* d = reinterpret_cast<v2d*>(nval + (int64_t)dst * bb);
+  for (int i = threadIdx.x; i < bb / 2; i += kWG) d[i] = s[i];
+}
+
 __global__ void k_fill_i32(int* p, int value, int64_t count) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = value;
@@ -461,13 +579,50 @@ void launch_union3(Ctx& c, const int* const rp[3], const int* const col[3], cons
 }
 
 void launch_union3_fill(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on,
-                        const int* rc, int nb, int* cc, int* ix, int64_t stride, unsigned char* id) {
+                        const int* rc, int nb, int* cc, int* ix, int64_t stride, unsigned char* id, int* rowof) {
   Src3 S;
   for (int t = 0; t < 3; ++t) {
     S.rp[t] = rp[t];
     S.col[t] = col[t];
   }
-  LIF_LAUNCH(k_union_fill, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, S, diag_on, rc, nb, cc, ix, stride, id);
+  LIF_LAUNCH(k_union_fill, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, S, diag_on, rc, nb, cc, ix, stride, id,
+             rowof);
+}
+
+void launch_union3_count_scan(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on,
+                              int nb, int* out_rp) {
+  UnionCount u;
+  for (int t = 0; t < 3; ++t) {
+    u.S.rp[t] = rp[t];
+    u.S.col[t] = col[t];
+  }
+  u.diag_on = diag_on;
+  LIF_LAUNCH(k_count_scan<UnionCount>, dim3(1), dim3(kCS), 0, c.stream, u, nb, out_rp);
+}
+
+void launch_keep_count_scan(Ctx& c, const int* row_ptr, const double* norms, double tau, int nb, int* out_rp) {
+  KeepCount k{row_ptr, norms, tau};
+  LIF_LAUNCH(k_count_scan<KeepCount>, dim3(1), dim3(kCS), 0, c.stream, k, nb, out_rp);
+}
+
+void launch_filter_count_scan(Ctx& c, const int* row_ptr, const int* col, const int* rlab, const int* clab, int mode,
+                              int nb, int* out_rp) {
+  FilterCount fc{row_ptr, col, rlab, clab, mode};
+  LIF_LAUNCH(k_count_scan<FilterCount>, dim3(1), dim3(kCS), 0, c.stream, fc, nb, out_rp);
+}
+
+void launch_intersect_count_scan(Ctx& c, const int* ra, const int* ca, const int* rr, const int* cr, int nb,
+                                 int* out_rp) {
+  IntersectCount ic{ra, ca, rr, cr};
+  LIF_LAUNCH(k_count_scan<IntersectCount>, dim3(1), dim3(kCS), 0, c.stream, ic, nb, out_rp);
+}
+
+void launch_compact_gather(Ctx& c, const int* row_ptr, int nb, const int* col, const double* norms, double tau,
+                           const int* new_row_ptr, const double* val, int64_t nnzb, int b, int* new_col,
+                           double* new_val) {
+  if (nnzb == 0) return;
+  LIF_LAUNCH(k_compact_gather, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, row_ptr, nb, col, norms, tau,
+             new_row_ptr, val, b * b, new_col, new_val);
 }
 
 void launch_axpby3_values(Ctx& c, const double* const v[3], const double coef[3], const int* ix, int64_t stride,

@@ -136,6 +136,7 @@ struct Ctx {
   // pinned host staging for small device->host reads
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
+  void* readback = nullptr;  // mapped pinned area written by the read-back kernel
   // per-block-row flags, all set (identity on every row)
   DBuf<unsigned char> ones;
   // events around leaf-GEMM launches (timing mode), resolved at flush_timing()
@@ -165,6 +166,8 @@ struct Ctx {
 // out[0] = 0, out[i+1] = out[i] + in[i] for i < count (int32 or int64 input)
 void scan_exclusive_i32(Ctx& c, const int* in, int* out, int count);
 void scan_exclusive_i64(Ctx& c, const int64_t* in, int64_t* out, int count);
+// both scans of the symbolic phase in one launch
+void scan_exclusive_pair(Ctx& c, const int* in32, int* out32, const int64_t* in64, int64_t* out64, int count);
 
 // bsr.hip
 void launch_row_ptr_from_rows(Ctx& c, const int* brow, int64_t nnzb, int nb, int* row_ptr);
@@ -180,7 +183,18 @@ void launch_max_reduce(Ctx& c, const double* in, int count, double* out);
 void launch_union3(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on, int nb,
                    int* counts);
 void launch_union3_fill(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on,
-                        const int* rc, int nb, int* cc, int* ix, int64_t stride, unsigned char* id);
+                        const int* rc, int nb, int* cc, int* ix, int64_t stride, unsigned char* id, int* rowof);
+// one-workgroup per-row count + exclusive scan (writes out_rp[0..nb])
+void launch_union3_count_scan(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on,
+                              int nb, int* out_rp);
+void launch_keep_count_scan(Ctx& c, const int* row_ptr, const double* norms, double tau, int nb, int* out_rp);
+void launch_filter_count_scan(Ctx& c, const int* row_ptr, const int* col, const int* rlab, const int* clab, int mode,
+                              int nb, int* out_rp);
+void launch_intersect_count_scan(Ctx& c, const int* ra, const int* ca, const int* rr, const int* cr, int nb,
+                                 int* out_rp);
+void launch_compact_gather(Ctx& c, const int* row_ptr, int nb, const int* col, const double* norms, double tau,
+                           const int* new_row_ptr, const double* val, int64_t nnzb, int b, int* new_col,
+                           double* new_val);
 void launch_axpby3_values(Ctx& c, const double* const v[3], const double coef[3], const int* ix, int64_t stride,
                           double gamma, const unsigned char* id, const int* row_of, int64_t nnzb, int b, int64_t n,
                           double* out, const int* live);

@@ -108,15 +108,13 @@ Bsr truncate(Ctx& c, Bsr&& A, const double* norms, double tau) {
   Bsr B = like(A);
   B.nnzb = -1;
   B.cap = A.bound();
-  DBuf<int> cnt(c.pool, A.nb);
-  launch_keep_counts(c, A.row_ptr.get(), norms, tau, A.nb, cnt.get());
   B.row_ptr = DBuf<int>(c.pool, A.nb + 1);
-  scan_exclusive_i32(c, cnt.get(), B.row_ptr.get(), A.nb);
+  launch_keep_count_scan(c, A.row_ptr.get(), norms, tau, A.nb, B.row_ptr.get());
   B.col = DBuf<int>(c.pool, (size_t)B.cap);
-  DBuf<int> src(c.pool, (size_t)B.cap);
-  launch_compact_index(c, A.row_ptr.get(), A.col.get(), norms, tau, B.row_ptr.get(), A.nb, B.col.get(), src.get());
   B.val = DBuf<double>(c.pool, (size_t)B.cap * A.b * A.b);
-  launch_gather_blocks(c, A.val.get(), src.get(), B.cap, A.b, B.val.get(), B.live());
+  // A's count is exact here (a product output or a checked input)
+  launch_compact_gather(c, A.row_ptr.get(), A.nb, A.col.get(), norms, tau, B.row_ptr.get(), A.val.get(), A.bound(),
+                        A.b, B.col.get(), B.val.get());
   return B;
 }
 
@@ -176,8 +174,7 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
   launch_symbolic_count(c, av.rp, av.col, bv.rp, bv.col, nb, cnt_c.get(), cnt_p.get());
   C.row_ptr = DBuf<int>(c.pool, nb + 1);
   DBuf<int64_t> prp(c.pool, nb + 1);
-  scan_exclusive_i32(c, cnt_c.get(), C.row_ptr.get(), nb);
-  scan_exclusive_i64(c, cnt_p.get(), prp.get(), nb);
+  scan_exclusive_pair(c, cnt_c.get(), C.row_ptr.get(), cnt_p.get(), prp.get(), nb);
   // the one read-back of a product: output and product counts, plus the
   // operands' block counts while only the device knows them
   int nnzc32 = 0, na = 0, nbk = 0;
@@ -233,17 +230,18 @@ Bsr union_sum(Ctx& c, const Bsr* const src[3], const double coef[3], double gamm
   cap = std::min<int64_t>(cap, (int64_t)nb * nb);
   C.nnzb = -1;
   C.cap = cap;
-  DBuf<int> cnt(c.pool, nb);
-  launch_union3(c, rp, col, diag_on, nb, cnt.get());
   C.row_ptr = DBuf<int>(c.pool, nb + 1);
-  scan_exclusive_i32(c, cnt.get(), C.row_ptr.get(), nb);
+  {
+    DBuf<int> cnt(c.pool, nb);
+    launch_union3(c, rp, col, diag_on, nb, cnt.get());
+    scan_exclusive_i32(c, cnt.get(), C.row_ptr.get(), nb);
+  }
   C.col = DBuf<int>(c.pool, (size_t)cap);
   DBuf<int> ix(c.pool, (size_t)cap * 3), rowof(c.pool, (size_t)cap);
   DBuf<unsigned char> id(c.pool, (size_t)cap);
   C.val = DBuf<double>(c.pool, (size_t)cap * C.b * C.b);
   if (cap) {
-    launch_union3_fill(c, rp, col, diag_on, C.row_ptr.get(), nb, C.col.get(), ix.get(), cap, id.get());
-    launch_block_row_of(c, C.row_ptr.get(), nb, cap, rowof.get());
+    launch_union3_fill(c, rp, col, diag_on, C.row_ptr.get(), nb, C.col.get(), ix.get(), cap, id.get(), rowof.get());
     launch_axpby3_values(c, val, coef, ix.get(), cap, gamma, id.get(), rowof.get(), cap, C.b, C.n, C.val.get(),
                          C.live());
   }
@@ -270,10 +268,8 @@ Bsr filter(Ctx& c, const Bsr& A, const int* rlab, const int* clab, int mode) {
   Bsr C = like(A);
   C.nnzb = -1;
   C.cap = A.bound();
-  DBuf<int> cnt(c.pool, nb);
-  launch_filter_counts(c, A.row_ptr.get(), A.col.get(), rlab, clab ? clab : rlab, mode, nb, cnt.get());
   C.row_ptr = DBuf<int>(c.pool, nb + 1);
-  scan_exclusive_i32(c, cnt.get(), C.row_ptr.get(), nb);
+  launch_filter_count_scan(c, A.row_ptr.get(), A.col.get(), rlab, clab ? clab : rlab, mode, nb, C.row_ptr.get());
   C.col = DBuf<int>(c.pool, (size_t)C.cap);
   DBuf<int> src(c.pool, (size_t)C.cap);
   C.val = DBuf<double>(c.pool, (size_t)C.cap * C.b * C.b);
@@ -290,11 +286,8 @@ Bsr intersect(Ctx& c, const Bsr& A, const Bsr& R) {
   Bsr C = like(A);
   C.nnzb = -1;
   C.cap = A.bound();
-  DBuf<int> cnt(c.pool, nb);
-  launch_intersect(c, A.row_ptr.get(), A.col.get(), R.row_ptr.get(), R.col.get(), nb, cnt.get(), nullptr, nullptr,
-                   nullptr);
   C.row_ptr = DBuf<int>(c.pool, nb + 1);
-  scan_exclusive_i32(c, cnt.get(), C.row_ptr.get(), nb);
+  launch_intersect_count_scan(c, A.row_ptr.get(), A.col.get(), R.row_ptr.get(), R.col.get(), nb, C.row_ptr.get());
   C.col = DBuf<int>(c.pool, (size_t)C.cap);
   DBuf<int> src(c.pool, (size_t)C.cap);
   C.val = DBuf<double>(c.pool, (size_t)C.cap * C.b * C.b);

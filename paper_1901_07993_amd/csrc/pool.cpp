@@ -97,7 +97,13 @@ void Ctx::flush_timing() {
   ev_pending.clear();
 }
 
+void launch_gather_bytes(hipStream_t stream, const void* const* src, const unsigned* bytes, int count, void* dst);
+
 void Ctx::d2h(void* dst, const void* src, size_t bytes) {
+  if (bytes <= 64) {
+    d2h_batch({{dst, src, bytes}});
+    return;
+  }
   if (bytes > pinned_bytes) {
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
@@ -110,20 +116,31 @@ void Ctx::d2h(void* dst, const void* src, size_t bytes) {
   std::memcpy(dst, pinned, bytes);
 }
 
+// Small reads: one kernel copies every requested value into a mapped pinned
+// buffer (the GPU writes host memory directly), then one synchronization.
 void Ctx::d2h_batch(const std::vector<Read>& reads) {
-  const size_t need = 64 * reads.size();
-  if (pinned_bytes < need || pinned_bytes < 4096) {
-    if (pinned) (void)hipHostFree(pinned);
-    pinned = nullptr;
-    const size_t want = need < 4096 ? 4096 : need;
-    LIF_HIP(hipHostMalloc(&pinned, want, hipHostMallocDefault));
-    pinned_bytes = want;
+  const int n = (int)reads.size();
+  LIF_REQUIRE(n <= 32, LIF_ERR_INVALID, "too many values in one read-back");
+  if (!readback) {
+    LIF_HIP(hipHostMalloc(&readback, 64 * 32 + 32 * (sizeof(void*) + sizeof(unsigned)), hipHostMallocMapped));
   }
-  char* p = static_cast<char*>(pinned);
-  for (size_t i = 0; i < reads.size(); ++i)
-    LIF_HIP(hipMemcpyAsync(p + 64 * i, reads[i].src, reads[i].bytes, hipMemcpyDeviceToHost, stream));
+  char* base = static_cast<char*>(readback);
+  const void** srcs = reinterpret_cast<const void**>(base + 64 * 32);
+  unsigned* lens = reinterpret_cast<unsigned*>(base + 64 * 32 + 32 * sizeof(void*));
+  // the previous read-back has completed (it synchronized), so the argument
+  // area may be rewritten
+  for (int i = 0; i < n; ++i) {
+    LIF_REQUIRE(reads[i].bytes <= 64, LIF_ERR_INVALID, "read-back value larger than 64 bytes");
+    srcs[i] = reads[i].src;
+    lens[i] = (unsigned)reads[i].bytes;
+  }
+  void* dev_args = nullptr;
+  LIF_HIP(hipHostGetDevicePointer(&dev_args, readback, 0));
+  char* dbase = static_cast<char*>(dev_args);
+  launch_gather_bytes(stream, reinterpret_cast<const void* const*>(dbase + 64 * 32),
+                      reinterpret_cast<const unsigned*>(dbase + 64 * 32 + 32 * sizeof(void*)), n, dbase);
   LIF_HIP(hipStreamSynchronize(stream));
-  for (size_t i = 0; i < reads.size(); ++i) std::memcpy(reads[i].dst, p + 64 * i, reads[i].bytes);
+  for (int i = 0; i < n; ++i) std::memcpy(reads[i].dst, base + 64 * i, reads[i].bytes);
 }
 
 Ctx::~Ctx() {
@@ -133,6 +150,7 @@ Ctx::~Ctx() {
   }
   for (auto e : ev_free) (void)hipEventDestroy(e);
   if (pinned) (void)hipHostFree(pinned);
+  if (readback) (void)hipHostFree(readback);
 }
 
 }  // namespace lif

@@ -39,7 +39,79 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_exclusive(const T* __rest
   if (t == kScanThreads - 1) out[count] = part[kScanThreads - 1];
 }
 
+// both arrays in one launch: workgroup 0 scans the int32 array, workgroup 1
+// the int64 array
+__global__ __launch_bounds__(kScanThreads) void k_scan_pair(const int* __restrict__ in32, int* __restrict__ out32,
+                                                            const int64_t* __restrict__ in64,
+                                                            int64_t* __restrict__ out64, int count) {
+  if (blockIdx.x == 0) {
+    __shared__ int part[kScanThreads];
+    const int t = threadIdx.x;
+    const int chunk = (count + kScanThreads - 1) / kScanThreads;
+    const int lo = min(count, t * chunk), hi = min(count, lo + chunk);
+    int s = 0;
+    for (int i = lo; i < hi; ++i) s += in32[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+      int v = (t >= off) ? part[t - off] : 0;
+      __syncthreads();
+      part[t] += v;
+      __syncthreads();
+    }
+    int run = t ? part[t - 1] : 0;
+    for (int i = lo; i < hi; ++i) {
+      out32[i] = run;
+      run += in32[i];
+    }
+    if (t == kScanThreads - 1) out32[count] = part[kScanThreads - 1];
+  } else {
+    __shared__ int64_t part64[kScanThreads];
+    const int t = threadIdx.x;
+    const int chunk = (count + kScanThreads - 1) / kScanThreads;
+    const int lo = min(count, t * chunk), hi = min(count, lo + chunk);
+    int64_t s = 0;
+    for (int i = lo; i < hi; ++i) s += in64[i];
+    part64[t] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+      int64_t v = (t >= off) ? part64[t - off] : 0;
+      __syncthreads();
+      part64[t] += v;
+      __syncthreads();
+    }
+    int64_t run = t ? part64[t - 1] : 0;
+    for (int i = lo; i < hi; ++i) {
+      out64[i] = run;
+      run += in64[i];
+    }
+    if (t == kScanThreads - 1) out64[count] = part64[kScanThreads - 1];
+  }
+}
+
+// Copies up to 32 small device values (<= 64 bytes each) into slots of 64
+// bytes of a mapped host buffer; one lane per byte.
+__global__ void k_gather_bytes(const void* const* __restrict__ src, const unsigned* __restrict__ bytes, int count,
+                               unsigned char* __restrict__ dst) {
+  const int i = blockIdx.x;
+  if (i >= count) return;
+  const unsigned char* s = static_cast<const unsigned char*>(src[i]);
+  for (unsigned t = threadIdx.x; t < bytes[i]; t += blockDim.x) dst[64 * i + t] = s[t];
+  __threadfence_system();
+}
+
 }  // namespace
+
+void launch_gather_bytes(hipStream_t stream, const void* const* src, const unsigned* bytes, int count, void* dst) {
+  hipLaunchKernelGGL(k_gather_bytes, dim3(count), dim3(64), 0, stream, src, bytes, count,
+                     static_cast<unsigned char*>(dst));
+  LIF_HIP(hipGetLastError());
+}
+
+void scan_exclusive_pair(Ctx& c, const int* in32, int* out32, const int64_t* in64, int64_t* out64, int count) {
+  hipLaunchKernelGGL(k_scan_pair, dim3(2), dim3(kScanThreads), 0, c.stream, in32, out32, in64, out64, count);
+  LIF_HIP(hipGetLastError());
+}
 
 void scan_exclusive_i32(Ctx& c, const int* in, int* out, int count) {
   hipLaunchKernelGGL(k_scan_exclusive<int>, dim3(1), dim3(kScanThreads), 0, c.stream, in, out, count);
