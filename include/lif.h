@@ -89,6 +89,13 @@ typedef struct {
   uint64_t mem_cap_bytes; /* device memory the handle may hold (0 = no cap) */
   void* stream;           /* hipStream_t for all work (NULL = null stream) */
   int32_t timing;         /* 1: time every leaf-GEMM launch with HIP events */
+  int32_t presize;        /* 1: from the second iteration of a refinement on, size each
+                           * product from the previous iteration's counts (with a
+                           * margin) instead of reading its counts back; an iteration
+                           * whose sizes fell short is redone with exact sizes, so the
+                           * results are identical.  2: the same without the margin
+                           * (least memory, most redone iterations).  0: read back the
+                           * counts of every product */
 } lif_opts;
 
 typedef struct {
@@ -106,11 +113,12 @@ typedef struct {
   int64_t nnzb_Z;            /* blocks of the result */
   int32_t n_norms;           /* entries used in norms[] */
   double norms[64];          /* ||delta_k||_F of the top-level problem, k = 1.. */
+  int32_t iterations_redone; /* presized iterations redone with exact sizes */
 } lif_info;
 
 /* Fills *o with the defaults: m = 4, tau = 0, FP64, paper stopping rule,
  * tol = 1e-10, max_iter = 100, base_rows = 4096, start = SQRT2_OVER_GERSH,
- * checkpoint = 0, no cap, null stream, timing = 0. */
+ * checkpoint = 0, no cap, null stream, timing = 0, presize = 1. */
 lif_status lif_opts_default(lif_opts* o);
 
 /* Validates S and copies it into library-owned device memory (the caller may

@@ -35,6 +35,7 @@ void validate_opts(const lif_opts& o) {
   LIF_REQUIRE(o.stop == LIF_STOP_PAPER || o.stop == LIF_STOP_TOL, LIF_ERR_INVALID, "opts.stop is invalid");
   LIF_REQUIRE(std::isfinite(o.tol) && o.tol >= 0.0, LIF_ERR_INVALID, "opts.tol must be finite and >= 0");
   LIF_REQUIRE(o.max_iter >= 1 && o.max_iter <= 10000, LIF_ERR_INVALID, "opts.max_iter must be in 1..10000");
+  LIF_REQUIRE(o.presize >= 0 && o.presize <= 2, LIF_ERR_INVALID, "opts.presize must be 0, 1 or 2");
   LIF_REQUIRE(o.start >= 0 && o.start <= 3, LIF_ERR_INVALID, "opts.start is invalid");
   if (o.start == LIF_START_INV_SQRT_LMAX || o.start == LIF_START_GIVEN)
     LIF_REQUIRE(std::isfinite(o.start_value) && o.start_value > 0.0, LIF_ERR_INVALID,
@@ -153,6 +154,7 @@ void fill_info(lif_handle h, const RunInfo& ri, double seconds, lif_info* info) 
   info->nnzb_Z = h->has_Z ? exact_nnzb(h->ctx, h->Z) : 0;
   info->n_norms = (int32_t)std::min<size_t>(64, ri.norms_top.size());
   for (int k = 0; k < info->n_norms; ++k) info->norms[k] = ri.norms_top[k];
+  info->iterations_redone = h->ctx.stats.redone;
 }
 
 void reset_stats(lif_handle h) {
@@ -196,6 +198,7 @@ lif_status lif_opts_default(lif_opts* o) {
   o->mem_cap_bytes = 0;
   o->stream = nullptr;
   o->timing = 0;
+  o->presize = 1;
   return LIF_OK;
 }
 
@@ -223,6 +226,7 @@ lif_status lif_create(const lif_blocks* S, const lif_opts* o, lif_handle* out) {
     p.start = o->start;
     p.start_value = o->start_value;
     p.checkpoint = o->checkpoint != 0;
+    p.presize = o->presize;
     Ctx& c = h->ctx;
     c.stream = static_cast<hipStream_t>(o->stream);
     c.pool = &h->pool;

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void k_chol_scatter(const int* __restrict__ ro
                                                       const int* __restrict__ base_of_row,
                                                       const int* __restrict__ blk0, const int* __restrict__ nbbv,
                                                       const int64_t* __restrict__ tile0, double* __restrict__ U,
-                                                      unsigned char* __restrict__ nz) {
+                                                      unsigned char* __restrict__ nz, int* __restrict__ band) {
   const int64_t e = blockIdx.x;
   const int I = row_of[e], J = col[e];
   const int s = base_of_row[I];
@@ -47,7 +47,10 @@ __global__ __launch_bounds__(256) void k_chol_scatter(const int* __restrict__ ro
   const double2* src = reinterpret_cast<const double2*>(val + e * (int64_t)b * b);
   double2* dst = reinterpret_cast<double2*>(U + t * (int64_t)b * b);
   for (int q = threadIdx.x; q < b * b / 2; q += 256) dst[q] = src[q];
-  if (threadIdx.x == 0) nz[t] = 1;
+  if (threadIdx.x == 0) {
+    nz[t] = 1;
+    atomicMax(band, j - i);
+  }
 }
 
 // set (pad = 1) or clear (pad = 0) the diagonal of padded rows of the last tile
@@ -60,23 +63,39 @@ __global__ void k_chol_pad(int nbase, const int* __restrict__ nbbv, const int* _
   for (int r = real + threadIdx.x; r < b; r += blockDim.x) M[t * b * b + (int64_t)r * b + r] = value;
 }
 
-// Cholesky of the diagonal tile (k, k) and the inverse of its factor, in LDS.
-// G = 256 / B threads share a column and split its dot products by residue
-// of the summation index, reducing with lane shuffles (they sit in one wave).
-//   rows of U, top to bottom: s_c = T[j][c] - sum_{i<j} U[i][j] U[i][c],
-//     U[j][j] = sqrt(s_j), U[j][c] = s_c / U[j][j]        (2 barriers per row)
-//   columns of W = U^{-1}, independently: W[c][c] = 1 / U[c][c],
-//     W[r][c] = -sum_{q=r+1}^{c} U[r][q] W[q][c] / U[r][r], r = c-1 .. 0;
-//     the lane owning residue r % G writes W[r][c], and each lane only reads
-//     the W entries of its own residue, so no barrier is needed.
+// Lane `src`'s value of v, for every lane (two v_readlane_b32; src uniform).
+__device__ __attribute__((always_inline)) inline double bcast(double v, int src) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffull), src);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+  return __hiloint2double(hi, lo);
+}
+
+// Cholesky of the diagonal tile (k, k) and the inverse of its factor, in LDS,
+// blocked by 16 x 16 sub-blocks (NS = B / 16 of them per side).  For each
+// sub-block column p:
+//   A (wave 0, in registers; lane c owns column c of the sub-block)
+//       U_pp = chol(T_pp) by rank-1 updates, pivots and row entries
+//       broadcast with v_readlane; V_pp = U_pp^{-1} by back substitution
+//   B (one wave per task, 16x16x16 MFMA products)
+//       panel  U_pq = V_pp^T T_pq, q > p
+//       inverse W_rp = -Y_r V_pp, r < p
+//   C (one wave per task)
+//       trailing T_qq' -= U_pq^T U_pq', p < q <= q'
+//       Y_r = sum_{s=r..p} W_rs U_s,p+1 for the next column's inverse blocks
+// W = U^{-1} is built column block by column block from
+//   W_rp = -(sum_{s=r}^{p-1} W_rs U_sp) V_pp,
+// so the inverse costs no extra step.  Three barriers per sub-block column.
 template <int B>
 __global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nbbv, const int* __restrict__ blk0,
                                                const int64_t* __restrict__ tile0, double* __restrict__ U,
                                                double* __restrict__ Z, int* __restrict__ err) {
   constexpr int L = B + 1;
-  constexpr int G = 256 / B;
+  constexpr int NS = B / 16;
+  constexpr int YL = 17;
   __shared__ double T[B * L];
   __shared__ double W[B * L];
+  __shared__ double Y[NS * 16 * YL];
   const int s = blockIdx.x;
   const int nbb = nbbv[s];
   if (k >= nbb) return;
@@ -84,61 +103,113 @@ __global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nb
   double* g = U + t * B * B;
   for (int q = threadIdx.x; q < B * B; q += 256) T[(q / B) * L + (q % B)] = g[q];
   __syncthreads();
-  __shared__ double piv;
-  const int c = threadIdx.x / G, gi = threadIdx.x % G;
-  for (int j = 0; j < B; ++j) {
-    double v = 0.0;
-    if (c >= j) {
-      // four independent partial sums keep several LDS reads in flight
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int i = gi;
-      for (; i + 3 * G < j; i += 4 * G) {
-        a0 += T[i * L + j] * T[i * L + c];
-        a1 += T[(i + G) * L + j] * T[(i + G) * L + c];
-        a2 += T[(i + 2 * G) * L + j] * T[(i + 2 * G) * L + c];
-        a3 += T[(i + 3 * G) * L + j] * T[(i + 3 * G) * L + c];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  int bad = -1;  // first non-positive pivot (wave 0)
+  for (int p = 0; p < NS; ++p) {
+    const int o = 16 * p;
+    if (wave == 0) {
+      double a[16], rd[16], v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) a[i] = T[(o + i) * L + o + l16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        double piv = bcast(a[j], j);
+        if (!(piv > 0.0)) {
+          if (bad < 0) bad = o + j;
+          piv = 1.0;
+        }
+        const double pj = sqrt(piv);
+        const double rj = 1.0 / pj;
+        rd[j] = rj;
+        // row j of U: U[j][c] = a[j] / p_j (c > j), p_j at c = j, 0 below
+        const double x = (l16 == j) ? pj : (l16 > j ? a[j] * rj : 0.0);
+        a[j] = x;
+#pragma unroll
+        for (int i = j + 1; i < 16; ++i) a[i] = fma(-bcast(x, i), x, a[i]);
       }
-      for (; i < j; i += G) a0 += T[i * L + j] * T[i * L + c];
-      double acc = (a0 + a1) + (a2 + a3);
-      for (int off = 1; off < G; off <<= 1) acc += __shfl_xor(acc, off, 64);
-      v = T[j * L + c] - acc;
-      if (c == j && gi == 0) piv = v;
-    }
-    __syncthreads();  // pivot visible; every read of row j's old values done
-    double d = piv;
-    if (!(d > 0.0)) {
-      if (threadIdx.x == 0) atomicMin(&err[s], (blk0[s] + k) * B + j);
-      d = 1.0;
-    }
-    const double p = sqrt(d);
-    if (gi == 0 && c >= j) T[j * L + c] = (c == j) ? p : v / p;
-    __syncthreads();  // row j of U final before the next row reads it
-  }
-  for (int r = gi; r < B; r += G) W[r * L + c] = 0.0;
-  // reciprocal pivots once, so the column sweeps multiply instead of divide
-  __shared__ double rdiag[B];
-  for (int r = threadIdx.x; r < B; r += 256) rdiag[r] = 1.0 / T[r * L + r];
-  __syncthreads();
-  {
-    if (c % G == gi) W[c * L + c] = rdiag[c];
-    for (int r = c - 1; r >= 0; --r) {
-      // q in (r, c] with q % G == gi, four independent partial sums
-      const int q0 = r + 1 + ((gi - (r + 1) % G) + G) % G;
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int q = q0;
-      for (; q + 3 * G <= c; q += 4 * G) {
-        a0 += T[r * L + q] * W[q * L + c];
-        a1 += T[r * L + q + G] * W[(q + G) * L + c];
-        a2 += T[r * L + q + 2 * G] * W[(q + 2 * G) * L + c];
-        a3 += T[r * L + q + 3 * G] * W[(q + 3 * G) * L + c];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) a[i] = (i <= l16) ? a[i] : 0.0;
+      // column c of V: V[r][c] = (delta_rc - sum_{q>r} U[r][q] V[q][c]) / U[r][r]
+#pragma unroll
+      for (int r = 15; r >= 0; --r) {
+        double acc = (l16 == r) ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = r + 1; q < 16; ++q) acc = fma(-bcast(a[r], q), v[q], acc);
+        v[r] = acc * rd[r];
       }
-      for (; q <= c; q += G) a0 += T[r * L + q] * W[q * L + c];
-      double acc = (a0 + a1) + (a2 + a3);
-      for (int off = 1; off < G; off <<= 1) acc += __shfl_xor(acc, off, 64);
-      if (r % G == gi) W[r * L + c] = -acc * rdiag[r];
+      if (lane < 16) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          T[(o + i) * L + o + l16] = a[i];
+          W[(o + i) * L + o + l16] = v[i];
+        }
+      }
     }
+    __syncthreads();
+    // B: task w < NS - 1 - p is the panel block q = p + 1 + w, the others the
+    // inverse blocks r = w - (NS - 1 - p); each task reads only what it writes
+    // and sub-blocks no other task touches in this phase
+    if (wave < NS - 1) {
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+      const int npanel = NS - 1 - p;
+      if (wave < npanel) {
+        const int q = p + 1 + wave;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int kk = o + 4 * ks + kq;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(W[kk * L + o + l16], T[kk * L + 16 * q + l16], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) T[(o + 4 * r + kq) * L + 16 * q + l16] = acc[r];
+      } else {
+        const int rb = wave - npanel;
+        const double* Yr = Y + rb * 16 * YL;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int kk = 4 * ks + kq;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Yr[l16 * YL + kk], W[(o + kk) * L + o + l16], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) W[(16 * rb + 4 * r + kq) * L + o + l16] = -acc[r];
+      }
+    }
+    __syncthreads();
+    if (p == NS - 1) break;
+    // C: trailing blocks (q1, q2), p < q1 <= q2, then the Y blocks r = 0..p
+    const int m = NS - 1 - p;
+    const int ntrail = m * (m + 1) / 2;
+    for (int task = wave; task < ntrail + p + 1; task += 4) {
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+      if (task < ntrail) {
+        int q1 = 0, rem = task;
+        while (rem >= m - q1) {
+          rem -= m - q1;
+          ++q1;
+        }
+        const int c1 = 16 * (p + 1 + q1), c2 = c1 + 16 * rem;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int kk = o + 4 * ks + kq;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[kk * L + c1 + l16], T[kk * L + c2 + l16], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) T[(c1 + 4 * r + kq) * L + c2 + l16] -= acc[r];
+      } else {
+        const int rb = task - ntrail;
+        const int c2 = 16 * (p + 1);
+        for (int ks = 0; ks < 4 * (p + 1 - rb); ++ks) {
+          const int kk = 16 * rb + 4 * ks + kq;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(W[(16 * rb + l16) * L + kk], T[kk * L + c2 + l16], acc, 0, 0,
+                                                     0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Y[rb * 16 * YL + (4 * r + kq) * YL + l16] = acc[r];
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
+  if (threadIdx.x == 0 && bad >= 0) atomicMin(&err[s], (blk0[s] + k) * B + bad);
   double* gz = Z + t * B * B;
   for (int q = threadIdx.x; q < B * B; q += 256) {
     const int r = q / B, cc = q % B;
@@ -147,7 +218,8 @@ __global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nb
   }
 }
 
-// U_kj = Z_kk^T U_kj for j = k + 1 + blockIdx.x
+// U_kj = Z_kk^T U_kj for j = k + 1 + blockIdx.x (j - k <= band: the grid
+// covers the band only)
 template <int B>
 __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trsm(int k, const int* __restrict__ nbbv,
                                                               const int64_t* __restrict__ tile0,
@@ -188,9 +260,10 @@ __device__ inline void tri_decode(int64_t t, int& ip, int& jp) {
   ip = (int)(t - (int64_t)j * (j + 1) / 2);
 }
 
-// U_ij -= U_ki^T U_kj for k < i <= j
+// U_ij -= U_ki^T U_kj for k < i <= j <= k + band (the factor keeps the band
+// of S within a leaf)
 template <int B>
-__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_update(int k, const int* __restrict__ nbbv,
+__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_update(int k, int band, const int* __restrict__ nbbv,
                                                                 const int64_t* __restrict__ tile0,
                                                                 double* __restrict__ U, unsigned char* __restrict__ nz) {
   using Cfg = TileCfg<B>;
@@ -198,7 +271,7 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_update(int k, const int
   __shared__ double Bs[Cfg::LDS_DOUBLES];
   const int s = blockIdx.y;
   const int nbb = nbbv[s];
-  const int m = nbb - k - 1;
+  const int m = min(band, nbb - k - 1);
   const int64_t t = blockIdx.x;
   if (m <= 0 || t >= (int64_t)m * (m + 1) / 2) return;
   int ip, jp;
@@ -228,9 +301,10 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_update(int k, const int
   if (threadIdx.x == 0) nz[packed_tile(tile0[s], nbb, i, j)] = 1;
 }
 
-// Z_ij = -(sum_{k=i}^{j-1} Z_ik U_kj) Z_jj for i = blockIdx.x < j
+// Z_ij = -(sum_{k=i}^{j-1} Z_ik U_kj) Z_jj for i = blockIdx.x < j; U_kj = 0
+// for k < j - band
 template <int B>
-__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, const int* __restrict__ nbbv,
+__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, int band, const int* __restrict__ nbbv,
                                                                const int64_t* __restrict__ tile0,
                                                                const double* __restrict__ U,
                                                                double* __restrict__ Z,
@@ -253,7 +327,7 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, const int*
     while (k < j && !nz[packed_tile(t0, nbb, k, j)]) ++k;
     return k;
   };
-  int k = next_k(i);
+  int k = next_k(max(i, j - band));
   if (k >= j) return;  // Z_ij = 0 (the buffer starts zeroed)
   tile_load<B>(Z + packed_tile(t0, nbb, i, k) * B * B, ra);
   tile_load<B>(U + packed_tile(t0, nbb, k, j) * B * B, rb);
@@ -302,10 +376,10 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, const int*
 
 void launch_chol_scatter(Ctx& c, const int* row_of, const int* col, const double* val, int64_t nnzb, int b,
                          const int* base_of_row, const int* blk0, const int* nbb, const int64_t* tile0, double* U,
-                         unsigned char* nz) {
+                         unsigned char* nz, int* band) {
   if (nnzb == 0) return;
   LIF_LAUNCH(k_chol_scatter, dim3((unsigned)nnzb), dim3(256), 0, c.stream, row_of, col, val, b, base_of_row, blk0,
-             nbb, tile0, U, nz);
+             nbb, tile0, U, nz, band);
 }
 
 void launch_chol_pad(Ctx& c, int nbase, const int* nbb, const int* rows, const int64_t* tile0, int b, double* M,
@@ -321,35 +395,36 @@ void launch_potrf(Ctx& c, int k, int nbase, const int* nbb, const int* blk0, con
     LIF_LAUNCH(k_potrf<32>, dim3(nbase), dim3(256), 0, c.stream, k, nbb, blk0, tile0, U, Z, err);
 }
 
-void launch_trsm(Ctx& c, int k, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b, double* U,
-                 const double* Z, const unsigned char* nz) {
-  if (max_nbb - k - 1 <= 0) return;
-  dim3 grid(max_nbb - k - 1, nbase);
+void launch_trsm(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b,
+                 double* U, const double* Z, const unsigned char* nz) {
+  const int m = std::min(band, max_nbb - k - 1);
+  if (m <= 0) return;
+  dim3 grid(m, nbase);
   if (b == 64)
     LIF_LAUNCH(k_trsm<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, k, nbb, tile0, U, Z, nz);
   else
     LIF_LAUNCH(k_trsm<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, k, nbb, tile0, U, Z, nz);
 }
 
-void launch_update(Ctx& c, int k, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b, double* U,
-                   unsigned char* nz) {
-  const int64_t m = max_nbb - k - 1;
+void launch_update(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b,
+                   double* U, unsigned char* nz) {
+  const int64_t m = std::min(band, max_nbb - k - 1);
   if (m <= 0) return;
   dim3 grid((unsigned)(m * (m + 1) / 2), nbase);
   if (b == 64)
-    LIF_LAUNCH(k_update<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, k, nbb, tile0, U, nz);
+    LIF_LAUNCH(k_update<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, k, band, nbb, tile0, U, nz);
   else
-    LIF_LAUNCH(k_update<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, k, nbb, tile0, U, nz);
+    LIF_LAUNCH(k_update<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, k, band, nbb, tile0, U, nz);
 }
 
-void launch_trinv(Ctx& c, int j, int nbase, const int* nbb, const int64_t* tile0, int b, const double* U, double* Z,
-                  const unsigned char* nz) {
+void launch_trinv(Ctx& c, int j, int band, int nbase, const int* nbb, const int64_t* tile0, int b, const double* U,
+                  double* Z, const unsigned char* nz) {
   if (j <= 0) return;
   dim3 grid(j, nbase);
   if (b == 64)
-    LIF_LAUNCH(k_trinv<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, j, nbb, tile0, U, Z, nz);
+    LIF_LAUNCH(k_trinv<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, j, band, nbb, tile0, U, Z, nz);
   else
-    LIF_LAUNCH(k_trinv<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, j, nbb, tile0, U, Z, nz);
+    LIF_LAUNCH(k_trinv<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, j, band, nbb, tile0, U, Z, nz);
 }
 
 }  // namespace lif

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -122,6 +123,7 @@ struct Stats {
   int64_t products = 0;
   int64_t gemm_launches = 0;
   double gemm_ms = 0;
+  int redone = 0;  // presized iterations redone with exact sizes
 };
 
 // Execution context shared by all operations of a handle.
@@ -139,6 +141,21 @@ struct Ctx {
   void* readback = nullptr;  // mapped pinned area written by the read-back kernel
   // per-block-row flags, all set (identity on every row)
   DBuf<unsigned char> ones;
+  // Products sized in advance.  While `on`, spgemm takes its output and pair
+  // capacities from caps[next] instead of reading the counts back, writes
+  // the true counts to sizes[2 next .. 2 next + 1] and raises *overflow when
+  // a capacity was short (the product then reads as empty, and the caller
+  // redoes the work with exact sizes).  While `record` (and not `on`), the
+  // counts spgemm reads back are appended to `seen`.
+  struct Spec {
+    static constexpr int kSlots = 32;
+    bool on = false, record = false;
+    size_t next = 0;
+    std::vector<std::array<int64_t, 2>> caps, seen;
+    std::vector<int> prec;  // precision of each sized-in-advance product
+    DBuf<int64_t> sizes;
+    DBuf<int> overflow;
+  } spec;
   // events around leaf-GEMM launches (timing mode), resolved at flush_timing()
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
   std::vector<hipEvent_t> ev_free;
@@ -168,6 +185,11 @@ void scan_exclusive_i32(Ctx& c, const int* in, int* out, int count);
 void scan_exclusive_i64(Ctx& c, const int64_t* in, int64_t* out, int count);
 // both scans of the symbolic phase in one launch
 void scan_exclusive_pair(Ctx& c, const int* in32, int* out32, const int64_t* in64, int64_t* out64, int count);
+// the same against capacities fixed in advance: the totals go to sizes[0..1];
+// if either exceeds its capacity both outputs are zeroed (an empty product)
+// and *overflow is set to 1
+void scan_exclusive_pair_capped(Ctx& c, const int* in32, int* out32, const int64_t* in64, int64_t* out64, int count,
+                                int64_t cap32, int64_t cap64, int64_t* sizes, int* overflow);
 
 // bsr.hip
 void launch_row_ptr_from_rows(Ctx& c, const int* brow, int64_t nnzb, int nb, int* row_ptr);
@@ -222,33 +244,53 @@ void launch_phi_diag(Ctx& c, const int* row_of, const int* col, int64_t nnzb, in
 // Symbolic phase.  opA given as CSR (row ptr, col, value index) of op(A);
 // B as CSR of op(B) with value index.  Writes per-row output and product
 // counts.
+// `diag_on` (nullable): rows whose diagonal block is added to the output
+// pattern (a fused identity term); the fill pass then writes dflag (one byte
+// per output block: the real rows of such a diagonal block, else 0).
 void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* brp, const int* bcol,
-                           int nb, int* cnt_c, int64_t* cnt_p);
+                           const unsigned char* diag_on, int nb, int* cnt_c, int64_t* cnt_p);
 void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp,
-                          const int* bcol, const int* bidx, int nb, const int* crp,
-                          const int64_t* prp, int* ccol, int64_t* seg, int2* pairs);
+                          const int* bcol, const int* bidx, const unsigned char* diag_on, int b, int64_t n, int nb,
+                          const int* crp, const int64_t* prp, int* ccol, int64_t* seg, int2* pairs,
+                          unsigned char* dflag);
+// Fused identity term of a product: an output block with dflag[e] = r > 0
+// is the diagonal block of a row that takes gamma I.  Its product part is
+// dropped when its norm is below tau (tau > 0), gamma is added to its first
+// r diagonal entries, and its norm is reported as +inf so truncation keeps
+// it: the result equals truncating the product, then adding gamma I.
+struct Epilogue {
+  const unsigned char* dflag = nullptr;
+  double tau = 0.0;
+  double gamma = 0.0;
+};
 // Numeric phase: C_blk = sum over its segment of op(A_a) op(B_b), in FP64
 // (prec = LIF_FP64) or with FP32 / BF16 inputs and FP32 accumulation.
+// `nnzc` is the grid (the output capacity); `live` (device) the number of
+// output blocks actually present, <= nnzc.
 void launch_numeric(Ctx& c, int prec, const double* A, const double* B, bool ta, bool tb, const int64_t* seg,
-                    const int2* pairs, int64_t nnzc, int b, double* C, double* norms);
+                    const int2* pairs, int64_t nnzc, const int* live, int b, double* C, double* norms,
+                    const Epilogue& epi);
 // spgemm_mixed.hip
 void launch_numeric_mixed(Ctx& c, int prec, const double* A, const double* Bm, bool ta, bool tb,
-                          const int64_t* seg, const int2* pairs, int64_t nnzc, int b, double* C, double* norms);
+                          const int64_t* seg, const int2* pairs, int64_t nnzc, const int* live, int b, double* C,
+                          double* norms, const Epilogue& epi);
 
 // chol.hip -- batched leaf inverse Cholesky on packed upper tile grids
 void launch_chol_scatter(Ctx& c, const int* row_of, const int* col, const double* val, int64_t nnzb, int b,
                          const int* base_of_row, const int* blk0, const int* nbb, const int64_t* tile0, double* U,
-                         unsigned char* nz);
+                         unsigned char* nz, int* band);
 void launch_chol_pad(Ctx& c, int nbase, const int* nbb, const int* rows, const int64_t* tile0, int b, double* M,
                      double value);
 void launch_potrf(Ctx& c, int k, int nbase, const int* nbb, const int* blk0, const int64_t* tile0, int b, double* U,
                   double* Z, int* err);
-void launch_trsm(Ctx& c, int k, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b, double* U,
-                 const double* Z, const unsigned char* nz);
-void launch_update(Ctx& c, int k, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b, double* U,
-                   unsigned char* nz);
-void launch_trinv(Ctx& c, int j, int nbase, const int* nbb, const int64_t* tile0, int b, const double* U, double* Z,
-                  const unsigned char* nz);
+// `band`: largest j - i over the nonzero tiles (i, j) of S within a leaf;
+// the factor's nonzero tiles satisfy j - i <= band as well
+void launch_trsm(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b,
+                 double* U, const double* Z, const unsigned char* nz);
+void launch_update(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b,
+                   double* U, unsigned char* nz);
+void launch_trinv(Ctx& c, int j, int band, int nbase, const int* nbb, const int64_t* tile0, int b, const double* U,
+                  double* Z, const unsigned char* nz);
 
 // ---------------------------------------------------------------------------
 // Block-sparse operations (ops.cpp): allocate outputs, run the kernels,
@@ -273,7 +315,10 @@ DBuf<double> block_norms(Ctx& c, const Bsr& A);
 Bsr truncate(Ctx& c, Bsr&& A, const double* norms, double tau);
 CsrView transpose_view(Ctx& c, const Bsr& A);
 Bsr transpose(Ctx& c, const Bsr& A);
-Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec = LIF_FP64);
+// trunc_tau(op(A) op(B)) [+ gamma I on the rows with diag_on set, added after
+// the truncation of the product]
+Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec = LIF_FP64,
+           double gamma = 0.0, const unsigned char* diag_on = nullptr);
 // alpha A + beta B + gamma I on the block rows with diag_on set (A or B may be null)
 Bsr axpby(Ctx& c, double alpha, const Bsr* A, double beta, const Bsr* B, double gamma,
           const unsigned char* diag_on);
@@ -281,7 +326,8 @@ Bsr axpby(Ctx& c, double alpha, const Bsr* A, double beta, const Bsr* B, double 
 Bsr axpby3(Ctx& c, double alpha, const Bsr* A, double beta, const Bsr* B, double kappa, const Bsr* C);
 Bsr filter(Ctx& c, const Bsr& A, const int* rlab, const int* clab, int mode);
 double gershgorin(Ctx& c, const Bsr& A);
-std::vector<double> node_sumsq(Ctx& c, const Bsr& A, const int* rlo, const int* rhi, int nseg);
+std::vector<double> node_sumsq(Ctx& c, const Bsr& A, const int* rlo, const int* rhi, int nseg,
+                               const std::vector<Ctx::Read>& extra = {});
 Bsr copy(Ctx& c, const Bsr& A);
 // exact block count (reads it from the device when only the device knows it)
 int64_t exact_nnzb(Ctx& c, const Bsr& A);

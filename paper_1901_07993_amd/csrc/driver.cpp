@@ -81,6 +81,11 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
   DBuf<unsigned char> d_diag(c.pool, nb);
   bool labels_dirty = true;
   bool all_active = true;
+  std::vector<std::array<int64_t, 2>> caps;  // per product of an iteration: {blocks, pairs}
+  if (!c.spec.sizes.get()) {
+    c.spec.sizes = DBuf<int64_t>(c.pool, 2 * Ctx::Spec::kSlots);
+    c.spec.overflow = DBuf<int>(c.pool, 1);
+  }
 
   for (int k = 1;; ++k) {
     int n_active = 0;
@@ -104,42 +109,98 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       h2d(c, d_diag.get(), diag.data(), nb);
       labels_dirty = false;
     }
-    // delta restricted to the problems still iterating
-    Bsr dfilt;
-    const bool restrict_rows = !all_active;
-    if (restrict_rows) dfilt = filter(c, delta, d_rowlab.get(), nullptr, 2);
-    const Bsr& da = restrict_rows ? dfilt : delta;
+    // One iteration.  After the first, every product is sized from the
+    // previous iteration's counts (with a margin) instead of reading its
+    // counts back; the counts and an overflow flag come back with the norms.
+    // If a capacity was short the iteration is redone with exact sizes.
+    bool planned = o.presize != 0 && !caps.empty();
+    Bsr Znew, dnew;
+    std::vector<double> ss;
+    struct SpecOff {  // no sizing in advance outside this loop, also on errors
+      Ctx& c;
+      ~SpecOff() { c.spec.on = c.spec.record = false; }
+    } spec_off{c};
+    for (;;) {
+      c.spec.on = planned;
+      c.spec.record = !planned;
+      c.spec.next = 0;
+      c.spec.caps = caps;
+      c.spec.seen.clear();
+      c.spec.prec.clear();
+      if (planned) launch_fill_i32(c, c.spec.overflow.get(), 0, 1);
+      // delta restricted to the problems still iterating
+      Bsr dfilt;
+      const bool restrict_rows = !all_active;
+      if (restrict_rows) dfilt = filter(c, delta, d_rowlab.get(), nullptr, 2);
+      const Bsr& da = restrict_rows ? dfilt : delta;
 
-    // M = Z sum_{k=1}^m b_k delta^k, Horner form, every product truncated;
-    // these products run in the requested input precision (FP32 accumulation
-    // when reduced), the delta-update below always in FP64
-    Bsr q;
-    if (o.m == 1) {
-      q = axpby(c, bk[1], &da, 0.0, nullptr, 0.0, nullptr);
-    } else {
-      Bsr T = axpby(c, bk[o.m], &da, 0.0, nullptr, bk[o.m - 1], d_diag.get());
-      for (int j = o.m - 2; j >= 1; --j) {
-        Bsr P = spgemm(c, da, false, T, false, o.tau, o.prec);
-        T = axpby(c, 1.0, &P, 0.0, nullptr, bk[j], d_diag.get());
+      // M = Z sum_{k=1}^m b_k delta^k, Horner form, every product truncated;
+      // these products run in the requested input precision (FP32
+      // accumulation when reduced), the delta-update below always in FP64
+      Bsr q;
+      if (o.m == 1) {
+        q = axpby(c, bk[1], &da, 0.0, nullptr, 0.0, nullptr);
+      } else {
+        Bsr T = axpby(c, bk[o.m], &da, 0.0, nullptr, bk[o.m - 1], d_diag.get());
+        // T <- trunc(delta T) + b_j I: the identity term is added in the
+        // product's epilogue
+        for (int j = o.m - 2; j >= 1; --j) T = spgemm(c, da, false, T, false, o.tau, o.prec, bk[j], d_diag.get());
+        q = spgemm(c, da, false, T, false, o.tau, o.prec);
       }
-      q = spgemm(c, da, false, T, false, o.tau, o.prec);
+      Bsr M = spgemm(c, Z, false, q, false, o.tau, o.prec);
+      q = Bsr();
+      Znew = axpby(c, 1.0, &Z, 1.0, &M, 0.0, nullptr);
+      // delta_{k+1} = delta_k - Z_{k+1}^T (S M) - (S M)^T Z_k   (M^T S = (S M)^T)
+      Bsr SM = spgemm(c, S, false, M, false, o.tau);
+      M = Bsr();
+      Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau);
+      Bsr X2 = spgemm(c, SM, true, Z, false, o.tau);
+      SM = Bsr();
+      dnew = axpby3(c, 1.0, &delta, -1.0, &X1, -1.0, &X2);
+      X1 = Bsr();
+      X2 = Bsr();
+
+      const size_t nprod = planned ? c.spec.next : c.spec.seen.size();
+      const std::vector<int> pprec = c.spec.prec;
+      std::vector<std::array<int64_t, 2>> seen = c.spec.seen;
+      c.spec.on = false;
+      c.spec.record = false;
+      int over = 0;
+      std::vector<int64_t> sz(2 * nprod);
+      std::vector<Ctx::Read> extra;
+      if (planned) {
+        extra.push_back({&over, c.spec.overflow.get(), sizeof(int)});
+        for (size_t i = 0; i < sz.size(); i += 8)
+          extra.push_back({sz.data() + i, c.spec.sizes.get() + i, sizeof(int64_t) * std::min<size_t>(8, sz.size() - i)});
+      }
+      ss = node_sumsq(c, dnew, d_rlo.get(), d_rhi.get(), nn, extra);
+      if (planned && over) {
+        ++c.stats.redone;
+        planned = false;
+        continue;
+      }
+      if (planned) {
+        seen.clear();
+        for (size_t i = 0; i < nprod; ++i) {
+          seen.push_back({sz[2 * i], sz[2 * i + 1]});
+          const double fl = 2.0 * (double)S.b * S.b * S.b * (double)sz[2 * i + 1];
+          c.stats.products += sz[2 * i + 1];
+          c.stats.flops += fl;
+          if (pprec[i] != LIF_FP64) c.stats.flops_lowp += fl;
+        }
+      }
+      // margins: output counts move little between iterations, block-product
+      // counts can triple after the first iteration of a LIF level (delta_0
+      // holds only the coupling blocks); pair slots are 8 bytes
+      caps.clear();
+      for (const auto& v : seen)
+        caps.push_back(o.presize == 2 ? v : std::array<int64_t, 2>{v[0] + v[0] / 2 + 64, 4 * v[1] + 4096});
+      break;
     }
-    Bsr M = spgemm(c, Z, false, q, false, o.tau, o.prec);
-    q = Bsr();
-    Bsr Znew = axpby(c, 1.0, &Z, 1.0, &M, 0.0, nullptr);
-    // delta_{k+1} = delta_k - Z_{k+1}^T (S M) - (S M)^T Z_k   (M^T S = (S M)^T)
-    Bsr SM = spgemm(c, S, false, M, false, o.tau);
-    M = Bsr();
-    Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau);
-    Bsr X2 = spgemm(c, SM, true, Z, false, o.tau);
-    SM = Bsr();
-    delta = axpby3(c, 1.0, &delta, -1.0, &X1, -1.0, &X2);
-    X1 = Bsr();
-    X2 = Bsr();
     if (ck) ck->push_back(std::move(Z));  // Z_k is immutable: keep it, no copy
     Z = std::move(Znew);
+    delta = std::move(dnew);
 
-    std::vector<double> ss = node_sumsq(c, delta, d_rlo.get(), d_rhi.get(), nn);
     for (int s = 0; s < nn; ++s) {
       NodeState& ns = st[s];
       if (!ns.active) continue;
@@ -291,6 +352,8 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   h2d(c, d_bor.get(), base_of_row.data(), nb);
   h2d(c, d_tile0.get(), tile0.data(), nbase);
   launch_fill_i32(c, d_err.get(), std::numeric_limits<int>::max(), nbase);
+  DBuf<int> d_band(c.pool, 1);
+  launch_fill_i32(c, d_band.get(), 0, 1);
   DBuf<unsigned char> nz(c.pool, (size_t)tiles);
   LIF_HIP(hipMemsetAsync(nz.get(), 0, (size_t)tiles, c.stream));
 
@@ -308,16 +371,20 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
     DBuf<int> rowof(c.pool, (size_t)std::max<int64_t>(snz, 1));
     launch_block_row_of(c, S.row_ptr.get(), nb, snz, rowof.get());
     launch_chol_scatter(c, rowof.get(), S.col.get(), S.val.get(), snz, b, d_bor.get(), d_blk0.get(), d_nbb.get(),
-                        d_tile0.get(), U.get(), nz.get());
+                        d_tile0.get(), U.get(), nz.get(), d_band.get());
   }
+  // tile band of S within the leaves: bounds the grids of trsm and update
+  // and the first nonzero tile of each column of U
+  int band = 0;
+  c.d2h(&band, d_band.get(), sizeof(int));
   launch_chol_pad(c, nbase, d_nbb.get(), d_rows.get(), d_tile0.get(), b, U.get(), 1.0);
   for (int k = 0; k < max_nbb; ++k) {
     launch_potrf(c, k, nbase, d_nbb.get(), d_blk0.get(), d_tile0.get(), b, U.get(), Z.val.get(), d_err.get());
-    launch_trsm(c, k, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), Z.val.get(), nz.get());
-    launch_update(c, k, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), nz.get());
+    launch_trsm(c, k, band, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), Z.val.get(), nz.get());
+    launch_update(c, k, band, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), nz.get());
   }
   for (int j = 1; j < max_nbb; ++j)
-    launch_trinv(c, j, nbase, d_nbb.get(), d_tile0.get(), b, U.get(), Z.val.get(), nz.get());
+    launch_trinv(c, j, band, nbase, d_nbb.get(), d_tile0.get(), b, U.get(), Z.val.get(), nz.get());
   launch_chol_pad(c, nbase, d_nbb.get(), d_rows.get(), d_tile0.get(), b, Z.val.get(), 0.0);
   std::vector<int> err(nbase);
   c.d2h(err.data(), d_err.get(), nbase * sizeof(int));

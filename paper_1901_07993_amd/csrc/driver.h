@@ -18,6 +18,7 @@ struct Opts {
   int start = LIF_START_SQRT2_OVER_GERSH;
   double start_value = 0.0;
   bool checkpoint = false;
+  int presize = 1;  // 0 off, 1 with margins, 2 previous counts as they are
 };
 
 // One node of the split tree: scalar rows [lo, hi), lo a multiple of b.

@@ -1,7 +1,8 @@
 // Block-sparse operations on device block-CSR matrices.  Each operation
 // allocates its outputs from the handle's pool and queues its kernels on the
 // handle's stream.  Only the symbolic phase of a product reads sizes back to
-// the host (it has no host-known bound); truncation, filters and sums size
+// the host (it has no host-known bound), and not even that when the caller
+// planned its capacities (Ctx::Spec); truncation, filters and sums size
 // their outputs by a bound and leave the exact count on the device.
 #include <algorithm>
 
@@ -152,7 +153,8 @@ Bsr transpose(Ctx& c, const Bsr& A) {
   return T;
 }
 
-Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec) {
+Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec, double gamma,
+           const unsigned char* diag_on) {
   LIF_REQUIRE(A.nb == B.nb && A.b == B.b, LIF_ERR_INVALID, "spgemm: operand shapes differ");
   const int nb = A.nb;
   Bsr C = like(A);
@@ -171,38 +173,56 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
   }
   DBuf<int> cnt_c(c.pool, nb);
   DBuf<int64_t> cnt_p(c.pool, nb);
-  launch_symbolic_count(c, av.rp, av.col, bv.rp, bv.col, nb, cnt_c.get(), cnt_p.get());
+  launch_symbolic_count(c, av.rp, av.col, bv.rp, bv.col, diag_on, nb, cnt_c.get(), cnt_p.get());
   C.row_ptr = DBuf<int>(c.pool, nb + 1);
   DBuf<int64_t> prp(c.pool, nb + 1);
-  scan_exclusive_pair(c, cnt_c.get(), C.row_ptr.get(), cnt_p.get(), prp.get(), nb);
-  // the one read-back of a product: output and product counts, plus the
-  // operands' block counts while only the device knows them
-  int nnzc32 = 0, na = 0, nbk = 0;
-  int64_t P = 0;
-  std::vector<Ctx::Read> reads{{&nnzc32, C.row_ptr.get() + nb, sizeof(int)}, {&P, prp.get() + nb, sizeof(int64_t)}};
-  const bool need_a = A.nnzb < 0, need_b = B.nnzb < 0 && &A != &B;
-  if (need_a) reads.push_back({&na, A.live(), sizeof(int)});
-  if (need_b) reads.push_back({&nbk, B.live(), sizeof(int)});
-  c.d2h_batch(reads);
-  if (need_a) A.nnzb = na;
-  if (need_b) B.nnzb = nbk;
-  const int64_t nnzc = nnzc32;
-  C.nnzb = nnzc;
+  int64_t nnzc = 0, P = 0;  // capacities of the output and pair arrays
+  const bool planned = c.spec.on && c.spec.next < c.spec.caps.size() && c.spec.next < (size_t)Ctx::Spec::kSlots;
+  if (planned) {
+    const size_t slot = c.spec.next++;
+    nnzc = std::min<int64_t>(c.spec.caps[slot][0], (int64_t)nb * nb);
+    P = c.spec.caps[slot][1];
+    scan_exclusive_pair_capped(c, cnt_c.get(), C.row_ptr.get(), cnt_p.get(), prp.get(), nb, nnzc, P,
+                               c.spec.sizes.get() + 2 * slot, c.spec.overflow.get());
+    c.spec.prec.push_back(prec);
+    C.nnzb = -1;
+  } else {
+    scan_exclusive_pair(c, cnt_c.get(), C.row_ptr.get(), cnt_p.get(), prp.get(), nb);
+    // the one read-back of a product: output and product counts, plus the
+    // operands' block counts while only the device knows them
+    int nnzc32 = 0, na = 0, nbk = 0;
+    std::vector<Ctx::Read> reads{{&nnzc32, C.row_ptr.get() + nb, sizeof(int)},
+                                 {&P, prp.get() + nb, sizeof(int64_t)}};
+    const bool need_a = A.nnzb < 0, need_b = B.nnzb < 0 && &A != &B;
+    if (need_a) reads.push_back({&na, A.live(), sizeof(int)});
+    if (need_b) reads.push_back({&nbk, B.live(), sizeof(int)});
+    c.d2h_batch(reads);
+    if (need_a) A.nnzb = na;
+    if (need_b) B.nnzb = nbk;
+    nnzc = nnzc32;
+    C.nnzb = nnzc;
+    if (c.spec.record) c.spec.seen.push_back({nnzc, P});
+    c.stats.products += P;
+    const double fl = 2.0 * (double)C.b * C.b * C.b * (double)P;
+    c.stats.flops += fl;
+    if (prec != LIF_FP64) c.stats.flops_lowp += fl;
+  }
   C.cap = nnzc;
   C.col = DBuf<int>(c.pool, (size_t)nnzc);
   DBuf<int64_t> seg(c.pool, (size_t)nnzc + 1);
   DBuf<int2> pairs(c.pool, (size_t)P);
+  DBuf<unsigned char> dflag(c.pool, diag_on ? (size_t)nnzc : 0);
   if (nnzc)
-    launch_symbolic_fill(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, nb, C.row_ptr.get(), prp.get(),
-                         C.col.get(), seg.get(), pairs.get());
+    launch_symbolic_fill(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, diag_on, C.b, C.n, nb, C.row_ptr.get(),
+                         prp.get(), C.col.get(), seg.get(), pairs.get(), diag_on ? dflag.get() : nullptr);
   C.val = DBuf<double>(c.pool, (size_t)nnzc * C.b * C.b);
   DBuf<double> nrm(c.pool, (size_t)nnzc);
-  launch_numeric(c, prec, A.val.get(), B.val.get(), ta, tb, seg.get(), pairs.get(), nnzc, C.b, C.val.get(),
-                 nrm.get());
-  c.stats.products += P;
-  const double fl = 2.0 * (double)C.b * C.b * C.b * (double)P;
-  c.stats.flops += fl;
-  if (prec != LIF_FP64) c.stats.flops_lowp += fl;
+  Epilogue epi;
+  epi.dflag = diag_on ? dflag.get() : nullptr;
+  epi.tau = tau;
+  epi.gamma = gamma;
+  launch_numeric(c, prec, A.val.get(), B.val.get(), ta, tb, seg.get(), pairs.get(), nnzc, C.row_ptr.get() + nb, C.b,
+                 C.val.get(), nrm.get(), epi);
   return truncate(c, std::move(C), nrm.get(), tau);
 }
 
@@ -319,9 +339,13 @@ double gershgorin(Ctx& c, const Bsr& A) {
   return read1(c, mx.get());
 }
 
-std::vector<double> node_sumsq(Ctx& c, const Bsr& A, const int* rlo, const int* rhi, int nseg) {
+std::vector<double> node_sumsq(Ctx& c, const Bsr& A, const int* rlo, const int* rhi, int nseg,
+                               const std::vector<Ctx::Read>& extra) {
   std::vector<double> out(nseg, 0.0);
-  if (nseg == 0) return out;
+  if (nseg == 0) {
+    if (!extra.empty()) c.d2h_batch(extra);
+    return out;
+  }
   DBuf<double> ss(c.pool, (size_t)std::max<int64_t>(A.bound(), 1)), seg(c.pool, nseg);
   launch_block_sumsq(c, A.val.get(), A.bound(), A.b, ss.get(), false, A.live());
   launch_segment_sum(c, ss.get(), A.row_ptr.get(), rlo, rhi, nseg, seg.get());
@@ -331,6 +355,7 @@ std::vector<double> node_sumsq(Ctx& c, const Bsr& A, const int* rlo, const int* 
     reads.push_back({out.data() + s, seg.get() + s, sizeof(double) * (size_t)std::min(8, nseg - s)});
   const bool need = A.nnzb < 0;
   if (need) reads.push_back({&na, A.live(), sizeof(int)});
+  reads.insert(reads.end(), extra.begin(), extra.end());
   c.d2h_batch(reads);
   if (need) A.nnzb = na;
   return out;

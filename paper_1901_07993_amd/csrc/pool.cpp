@@ -12,9 +12,11 @@ size_t Pool::round(size_t bytes) {
 
 void* Pool::alloc(size_t bytes) {
   size_t r = round(bytes);
-  auto it = cache_.find(r);
-  if (it != cache_.end()) {
+  // smallest cached buffer that fits and wastes at most a quarter
+  auto it = cache_.lower_bound(r);
+  if (it != cache_.end() && it->first <= r + r / 4) {
     void* p = it->second;
+    r = it->first;
     cache_.erase(it);
     live_[p] = r;
     in_use_ += r;

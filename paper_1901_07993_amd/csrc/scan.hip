@@ -89,6 +89,65 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_pair(const int* __restric
   }
 }
 
+// Both scans in one workgroup against capacities fixed before the counts
+// were known.  When a total exceeds its capacity both row pointers are
+// zeroed, so every later kernel sees a valid empty product, and the flag is
+// raised for the host to redo the work with exact sizes.
+__global__ __launch_bounds__(kScanThreads) void k_scan_pair_capped(const int* __restrict__ in32,
+                                                                   int* __restrict__ out32,
+                                                                   const int64_t* __restrict__ in64,
+                                                                   int64_t* __restrict__ out64, int count,
+                                                                   int64_t cap32, int64_t cap64,
+                                                                   int64_t* __restrict__ sizes,
+                                                                   int* __restrict__ overflow) {
+  __shared__ int64_t part[kScanThreads];
+  const int t = threadIdx.x;
+  const int chunk = (count + kScanThreads - 1) / kScanThreads;
+  const int lo = min(count, t * chunk), hi = min(count, lo + chunk);
+  int64_t total[2];
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    int64_t s = 0;
+    for (int i = lo; i < hi; ++i) s += pass ? in64[i] : (int64_t)in32[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+      const int64_t v = (t >= off) ? part[t - off] : 0;
+      __syncthreads();
+      part[t] += v;
+      __syncthreads();
+    }
+    int64_t run = t ? part[t - 1] : 0;
+    for (int i = lo; i < hi; ++i) {
+      if (pass) {
+        out64[i] = run;
+        run += in64[i];
+      } else {
+        out32[i] = (int)run;
+        run += in32[i];
+      }
+    }
+    total[pass] = part[kScanThreads - 1];
+    __syncthreads();  // every thread has its total before the next pass reuses part
+  }
+  if (t == kScanThreads - 1) {
+    out32[count] = (int)total[0];
+    out64[count] = total[1];
+  }
+  if (t == 0) {
+    sizes[0] = total[0];
+    sizes[1] = total[1];
+  }
+  if (total[0] > cap32 || total[1] > cap64) {
+    __syncthreads();  // the scan's own writes land first
+    for (int i = t; i <= count; i += kScanThreads) {
+      out32[i] = 0;
+      out64[i] = 0;
+    }
+    if (t == 0) *overflow = 1;
+  }
+}
+
 // Copies up to 32 small device values (<= 64 bytes each) into slots of 64
 // bytes of a mapped host buffer; one lane per byte.
 __global__ void k_gather_bytes(const void* const* __restrict__ src, const unsigned* __restrict__ bytes, int count,
@@ -110,6 +169,13 @@ void launch_gather_bytes(hipStream_t stream, const void* const* src, const unsig
 
 void scan_exclusive_pair(Ctx& c, const int* in32, int* out32, const int64_t* in64, int64_t* out64, int count) {
   hipLaunchKernelGGL(k_scan_pair, dim3(2), dim3(kScanThreads), 0, c.stream, in32, out32, in64, out64, count);
+  LIF_HIP(hipGetLastError());
+}
+
+void scan_exclusive_pair_capped(Ctx& c, const int* in32, int* out32, const int64_t* in64, int64_t* out64, int count,
+                                int64_t cap32, int64_t cap64, int64_t* sizes, int* overflow) {
+  hipLaunchKernelGGL(k_scan_pair_capped, dim3(1), dim3(kScanThreads), 0, c.stream, in32, out32, in64, out64, count,
+                     cap32, cap64, sizes, overflow);
   LIF_HIP(hipGetLastError());
 }
 

@@ -29,11 +29,15 @@ constexpr int kSymWG = 256;
 // symbolic
 // ---------------------------------------------------------------------------
 
+// `diag_on` (nullable): rows whose diagonal block joins the pattern whether
+// or not a product reaches it (the target of a fused identity term)
 __device__ inline void build_row_bitmap(const int* __restrict__ arp, const int* __restrict__ acol,
-                                        const int* __restrict__ brp, const int* __restrict__ bcol, int i,
-                                        unsigned* bm, int nwords, int64_t* pcount) {
+                                        const int* __restrict__ brp, const int* __restrict__ bcol,
+                                        const unsigned char* __restrict__ diag_on, int i, unsigned* bm, int nwords,
+                                        int64_t* pcount) {
   for (int w = threadIdx.x; w < nwords; w += kSymWG) bm[w] = 0u;
   __syncthreads();
+  if (threadIdx.x == 0 && diag_on && diag_on[i]) atomicOr(&bm[i >> 5], 1u << (i & 31));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int64_t p = 0;
   for (int e = arp[i] + wave; e < arp[i + 1]; e += kSymWG / 64) {
@@ -51,8 +55,8 @@ __device__ inline void build_row_bitmap(const int* __restrict__ arp, const int* 
 
 __global__ __launch_bounds__(kSymWG) void k_symbolic_count(const int* __restrict__ arp, const int* __restrict__ acol,
                                                            const int* __restrict__ brp, const int* __restrict__ bcol,
-                                                           int nb, int* __restrict__ cnt_c,
-                                                           int64_t* __restrict__ cnt_p) {
+                                                           const unsigned char* __restrict__ diag_on, int nb,
+                                                           int* __restrict__ cnt_c, int64_t* __restrict__ cnt_p) {
   extern __shared__ unsigned smem[];
   __shared__ int64_t red_p[kSymWG];
   __shared__ int red_c[kSymWG];
@@ -60,7 +64,7 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_count(const int* __restrict
   const int nwords = (nb + 31) >> 5;
   unsigned* bm = smem;
   int64_t p = 0;
-  build_row_bitmap(arp, acol, brp, bcol, i, bm, nwords, &p);
+  build_row_bitmap(arp, acol, brp, bcol, diag_on, i, bm, nwords, &p);
   int c = 0;
   for (int w = threadIdx.x; w < nwords; w += kSymWG) c += __popc(bm[w]);
   red_p[threadIdx.x] = p;
@@ -80,12 +84,16 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_count(const int* __restrict
 }
 
 // LDS layout of the fill pass: bitmap[nwords] | word_prefix[nwords] | cursor[nb]
+// With `diag_on`, dflag[e] of each output block is the number of real rows
+// of a diagonal block that takes the identity term (0 for the others).
 __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict__ arp, const int* __restrict__ acol,
                                                           const int* __restrict__ aidx, const int* __restrict__ brp,
                                                           const int* __restrict__ bcol, const int* __restrict__ bidx,
-                                                          int nb, const int* __restrict__ crp,
+                                                          const unsigned char* __restrict__ diag_on, int b,
+                                                          int64_t n, int nb, const int* __restrict__ crp,
                                                           const int64_t* __restrict__ prp, int* __restrict__ ccol,
-                                                          int64_t* __restrict__ seg, int2* __restrict__ pairs) {
+                                                          int64_t* __restrict__ seg, int2* __restrict__ pairs,
+                                                          unsigned char* __restrict__ dflag) {
   extern __shared__ unsigned smem[];
   __shared__ int scan_tmp[kSymWG];
   const int i = blockIdx.x;
@@ -93,7 +101,8 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
   unsigned* bm = smem;
   int* wp = reinterpret_cast<int*>(smem + nwords);
   int* cur = wp + nwords;
-  build_row_bitmap(arp, acol, brp, bcol, i, bm, nwords, nullptr);
+  build_row_bitmap(arp, acol, brp, bcol, diag_on, i, bm, nwords, nullptr);
+  const int drows = (diag_on && diag_on[i]) ? (int)min<int64_t>(b, n - (int64_t)i * b) : 0;
 
   // exclusive prefix of word popcounts: contiguous chunks per thread
   const int chunk = (nwords + kSymWG - 1) / kSymWG;
@@ -123,7 +132,9 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
     int r = wp[w];
     while (bits) {
       const int bit = __ffs(bits) - 1;
-      ccol[cbase + r] = (w << 5) + bit;
+      const int j = (w << 5) + bit;
+      ccol[cbase + r] = j;
+      if (dflag) dflag[cbase + r] = (unsigned char)(j == i ? drows : 0);
       cur[r] = 0;
       ++r;
       bits &= bits - 1;
@@ -228,15 +239,19 @@ template <int B, bool TA, bool TB>
 __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const double* __restrict__ A,
                                                                      const double* __restrict__ Bm,
                                                                      const int64_t* __restrict__ seg,
-                                                                     const int2* __restrict__ pairs, int64_t nnzc,
+                                                                     const int2* __restrict__ pairs,
+                                                                     const int* __restrict__ live,
                                                                      double* __restrict__ C,
-                                                                     double* __restrict__ norms) {
+                                                                     double* __restrict__ norms, Epilogue epi) {
   using Cfg = TileCfg<B>;
   __shared__ double As[2][Cfg::LDS_DOUBLES];
   __shared__ double Bs[2][Cfg::LDS_DOUBLES];
   __shared__ double red[Cfg::WAVES];
-  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-  if (blk >= nnzc) return;
+  // the grid may exceed the live output count (capacity fixed before the
+  // count was known); the XCD remap runs over the live blocks only
+  const int64_t nlive = *live;
+  if ((int64_t)blockIdx.x >= nlive) return;
+  const int64_t blk = xcd_remap(blockIdx.x, nlive);
   const int64_t p0 = seg[blk], p1 = seg[blk + 1];
   const Frag f = frag_coords<B>();
 
@@ -247,67 +262,78 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const doubl
   // last surplus LDS store are never read), which keeps them in VGPRs.
   v2d ra[Cfg::V2], rbv[Cfg::V2];
   const int64_t plast = p1 - 1;
-  {
-    const int2 pr = pairs[p0];
-    tile_load<B>(A + (int64_t)pr.x * B * B, ra);
-    tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
-  }
-  tile_store<B>(As[0], ra, true);
-  tile_store<B>(Bs[0], rbv, true);
-  {
-    const int2 pr = pairs[min(p0 + 1, plast)];
-    tile_load<B>(A + (int64_t)pr.x * B * B, ra);
-    tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
-  }
-  int stage = 0;
-  for (int64_t p = p0; p < p1; ++p) {
-    __syncthreads();  // stage p visible; stage p+1's previous readers done
-    tile_store<B>(As[stage ^ 1], ra, true);
-    tile_store<B>(Bs[stage ^ 1], rbv, true);
-    const int2 pr = pairs[min(p + 2, plast)];
-    tile_load<B>(A + (int64_t)pr.x * B * B, ra);
-    tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
-    mma_stage<B, TA, TB>(As[stage], Bs[stage], f, acc);
-    stage ^= 1;
+  if (p1 > p0) {  // a diagonal block of a fused identity term may have no products
+    {
+      const int2 pr = pairs[p0];
+      tile_load<B>(A + (int64_t)pr.x * B * B, ra);
+      tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
+    }
+    tile_store<B>(As[0], ra, true);
+    tile_store<B>(Bs[0], rbv, true);
+    {
+      const int2 pr = pairs[min(p0 + 1, plast)];
+      tile_load<B>(A + (int64_t)pr.x * B * B, ra);
+      tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
+    }
+    int stage = 0;
+    for (int64_t p = p0; p < p1; ++p) {
+      __syncthreads();  // stage p visible; stage p+1's previous readers done
+      tile_store<B>(As[stage ^ 1], ra, true);
+      tile_store<B>(Bs[stage ^ 1], rbv, true);
+      const int2 pr = pairs[min(p + 2, plast)];
+      tile_load<B>(A + (int64_t)pr.x * B * B, ra);
+      tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
+      mma_stage<B, TA, TB>(As[stage], Bs[stage], f, acc);
+      stage ^= 1;
+    }
   }
 
-  // epilogue: write the block, FP64 sum of squares in a fixed order
-  double* Cb = C + blk * B * B;
+  // epilogue: FP64 sum of squares in a fixed order, then the block
   double ss = 0.0;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const double v = acc[ti][tj][r];
-        Cb[acc_row(f, ti, r) * B + acc_col(f, tj)] = v;
-        ss += v * v;
-      }
+      for (int r = 0; r < 4; ++r) ss += acc[ti][tj][r] * acc[ti][tj][r];
   for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
   if (f.lane == 0) red[f.wave] = ss;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
+  double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < Cfg::WAVES; ++w) t += red[w];
-    norms[blk] = sqrt(t);
-  }
+  for (int w = 0; w < Cfg::WAVES; ++w) t += red[w];
+  const double nrm = sqrt(t);
+  const int dr = epi.dflag ? epi.dflag[blk] : 0;
+  const bool keep = dr == 0 || !(epi.tau > 0.0) || nrm >= epi.tau;
+  double* Cb = C + blk * B * B;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = acc_row(f, ti, r), col = acc_col(f, tj);
+        double v = keep ? acc[ti][tj][r] : 0.0;
+        if (row == col && row < dr) v += epi.gamma;
+        Cb[row * B + col] = v;
+      }
+  if (threadIdx.x == 0) norms[blk] = dr ? INFINITY : nrm;
 }
 
 template <int B>
 void launch_numeric_b(Ctx& c, const double* A, const double* Bm, bool ta, bool tb, const int64_t* seg,
-                      const int2* pairs, int64_t nnzc, double* C, double* norms) {
+                      const int2* pairs, int64_t nnzc, const int* live, double* C, double* norms,
+                      const Epilogue& epi) {
   using Cfg = TileCfg<B>;
   dim3 grid((unsigned)nnzc), block(Cfg::THREADS);
   if (!ta && !tb)
-    hipLaunchKernelGGL((k_numeric_f64<B, false, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, nnzc, C, norms);
+    hipLaunchKernelGGL((k_numeric_f64<B, false, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, norms, epi);
   else if (ta && !tb)
-    hipLaunchKernelGGL((k_numeric_f64<B, true, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, nnzc, C, norms);
+    hipLaunchKernelGGL((k_numeric_f64<B, true, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, norms, epi);
   else if (!ta && tb)
-    hipLaunchKernelGGL((k_numeric_f64<B, false, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, nnzc, C, norms);
+    hipLaunchKernelGGL((k_numeric_f64<B, false, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, norms, epi);
   else
-    hipLaunchKernelGGL((k_numeric_f64<B, true, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, nnzc, C, norms);
+    hipLaunchKernelGGL((k_numeric_f64<B, true, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, norms, epi);
   LIF_HIP(hipGetLastError());
 }
 
@@ -323,25 +349,26 @@ static void allow_lds(const void* fn, size_t bytes) {
     LIF_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
 }
 
-void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* brp, const int* bcol, int nb,
-                           int* cnt_c, int64_t* cnt_p) {
+void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* brp, const int* bcol,
+                           const unsigned char* diag_on, int nb, int* cnt_c, int64_t* cnt_p) {
   allow_lds((const void*)k_symbolic_count, symbolic_lds_bytes(nb, false));
   hipLaunchKernelGGL(k_symbolic_count, dim3(nb), dim3(kSymWG), symbolic_lds_bytes(nb, false), c.stream, arp, acol,
-                     brp, bcol, nb, cnt_c, cnt_p);
+                     brp, bcol, diag_on, nb, cnt_c, cnt_p);
   LIF_HIP(hipGetLastError());
 }
 
 void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp, const int* bcol,
-                          const int* bidx, int nb, const int* crp, const int64_t* prp, int* ccol, int64_t* seg,
-                          int2* pairs) {
+                          const int* bidx, const unsigned char* diag_on, int b, int64_t n, int nb, const int* crp,
+                          const int64_t* prp, int* ccol, int64_t* seg, int2* pairs, unsigned char* dflag) {
   allow_lds((const void*)k_symbolic_fill, symbolic_lds_bytes(nb, true));
   hipLaunchKernelGGL(k_symbolic_fill, dim3(nb), dim3(kSymWG), symbolic_lds_bytes(nb, true), c.stream, arp, acol,
-                     aidx, brp, bcol, bidx, nb, crp, prp, ccol, seg, pairs);
+                     aidx, brp, bcol, bidx, diag_on, b, n, nb, crp, prp, ccol, seg, pairs, dflag);
   LIF_HIP(hipGetLastError());
 }
 
 void launch_numeric(Ctx& c, int prec, const double* A, const double* B, bool ta, bool tb, const int64_t* seg,
-                    const int2* pairs, int64_t nnzc, int b, double* C, double* norms) {
+                    const int2* pairs, int64_t nnzc, const int* live, int b, double* C, double* norms,
+                    const Epilogue& epi) {
   if (nnzc == 0) return;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c.timing) {
@@ -350,11 +377,11 @@ void launch_numeric(Ctx& c, int prec, const double* A, const double* B, bool ta,
     LIF_HIP(hipEventRecord(e0, c.stream));
   }
   if (prec != LIF_FP64)
-    launch_numeric_mixed(c, prec, A, B, ta, tb, seg, pairs, nnzc, b, C, norms);
+    launch_numeric_mixed(c, prec, A, B, ta, tb, seg, pairs, nnzc, live, b, C, norms, epi);
   else if (b == 64)
-    launch_numeric_b<64>(c, A, B, ta, tb, seg, pairs, nnzc, C, norms);
+    launch_numeric_b<64>(c, A, B, ta, tb, seg, pairs, nnzc, live, C, norms, epi);
   else
-    launch_numeric_b<32>(c, A, B, ta, tb, seg, pairs, nnzc, C, norms);
+    launch_numeric_b<32>(c, A, B, ta, tb, seg, pairs, nnzc, live, C, norms, epi);
   if (c.timing) {
     LIF_HIP(hipEventRecord(e1, c.stream));
     c.ev_pending.emplace_back(e0, e1);

@@ -82,9 +82,12 @@ __device__ inline void store_bf16(unsigned short* __restrict__ s, const v2d* reg
   }
 }
 
+// FP64 norm of the FP32 accumulators in a fixed order, then the block (with
+// the fused identity term of Epilogue)
 template <int B>
 __device__ inline void epilogue(const v4f (&acc)[2][2], int rb, int cb, int l16, int kq, int lane, int wave,
-                                double* __restrict__ Cb, double* red, double* __restrict__ norm_out) {
+                                double* __restrict__ Cb, double* red, double* __restrict__ norm_out, int dr,
+                                const Epilogue& epi) {
   using Cfg = MixCfg<B>;
   double ss = 0.0;
 #pragma unroll
@@ -94,33 +97,47 @@ __device__ inline void epilogue(const v4f (&acc)[2][2], int rb, int cb, int l16,
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const double v = (double)acc[ti][tj][r];
-        Cb[(rb + 16 * ti + 4 * kq + r) * B + cb + 16 * tj + l16] = v;
         ss += v * v;
       }
   for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
   if (lane == 0) red[wave] = ss;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
+  double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < Cfg::WAVES; ++w) t += red[w];
-    *norm_out = sqrt(t);
-  }
+  for (int w = 0; w < Cfg::WAVES; ++w) t += red[w];
+  const double nrm = sqrt(t);
+  const bool keep = dr == 0 || !(epi.tau > 0.0) || nrm >= epi.tau;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rb + 16 * ti + 4 * kq + r, col = cb + 16 * tj + l16;
+        double v = keep ? (double)acc[ti][tj][r] : 0.0;
+        if (row == col && row < dr) v += epi.gamma;
+        Cb[row * B + col] = v;
+      }
+  if (threadIdx.x == 0) *norm_out = dr ? INFINITY : nrm;
 }
 
 template <int B, bool TA, bool TB>
 __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(const double* __restrict__ A,
                                                                     const double* __restrict__ Bm,
                                                                     const int64_t* __restrict__ seg,
-                                                                    const int2* __restrict__ pairs, int64_t nnzc,
+                                                                    const int2* __restrict__ pairs,
+                                                                    const int* __restrict__ live,
                                                                     double* __restrict__ C,
-                                                                    double* __restrict__ norms) {
+                                                                    double* __restrict__ norms, Epilogue epi) {
   using Cfg = MixCfg<B>;
   __shared__ float As[B * Cfg::LDF];
   __shared__ float Bs[B * Cfg::LDF];
   __shared__ double red[Cfg::WAVES];
-  const int64_t blk = xcd_remap_m(blockIdx.x, gridDim.x);
-  if (blk >= nnzc) return;
+  // the grid may exceed the live output count (capacity fixed before the
+  // count was known); the XCD remap runs over the live blocks only
+  const int64_t nlive = *live;
+  if ((int64_t)blockIdx.x >= nlive) return;
+  const int64_t blk = xcd_remap_m(blockIdx.x, nlive);
   const int64_t p0 = seg[blk], p1 = seg[blk + 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rb = 32 * (wave / (B / 32)), cb = 32 * (wave % (B / 32));
@@ -131,7 +148,7 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(const double
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
   v2d ra[Cfg::V2], rbv[Cfg::V2];
-  {
+  if (p1 > p0) {  // a diagonal block of a fused identity term may have no products
     const int2 pr = pairs[p0];
     tile_load<B>(A + (int64_t)pr.x * B * B, ra);
     tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
@@ -159,22 +176,27 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(const double
       acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
     }
   }
-  epilogue<B>(acc, rb, cb, l16, kq, lane, wave, C + blk * B * B, red, norms + blk);
+  epilogue<B>(acc, rb, cb, l16, kq, lane, wave, C + blk * B * B, red, norms + blk, epi.dflag ? epi.dflag[blk] : 0,
+              epi);
 }
 
 template <int B, bool TA, bool TB>
 __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(const double* __restrict__ A,
                                                                      const double* __restrict__ Bm,
                                                                      const int64_t* __restrict__ seg,
-                                                                     const int2* __restrict__ pairs, int64_t nnzc,
+                                                                     const int2* __restrict__ pairs,
+                                                                     const int* __restrict__ live,
                                                                      double* __restrict__ C,
-                                                                     double* __restrict__ norms) {
+                                                                     double* __restrict__ norms, Epilogue epi) {
   using Cfg = MixCfg<B>;
   __shared__ __attribute__((aligned(16))) unsigned short As[B * Cfg::LDH];  // As[i][k]
   __shared__ __attribute__((aligned(16))) unsigned short Bs[B * Cfg::LDH];  // Bs[j][k]
   __shared__ double red[Cfg::WAVES];
-  const int64_t blk = xcd_remap_m(blockIdx.x, gridDim.x);
-  if (blk >= nnzc) return;
+  // the grid may exceed the live output count (capacity fixed before the
+  // count was known); the XCD remap runs over the live blocks only
+  const int64_t nlive = *live;
+  if ((int64_t)blockIdx.x >= nlive) return;
+  const int64_t blk = xcd_remap_m(blockIdx.x, nlive);
   const int64_t p0 = seg[blk], p1 = seg[blk + 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rb = 32 * (wave / (B / 32)), cb = 32 * (wave % (B / 32));
@@ -185,7 +207,7 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(const doubl
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
   v2d ra[Cfg::V2], rbv[Cfg::V2];
-  {
+  if (p1 > p0) {  // a diagonal block of a fused identity term may have no products
     const int2 pr = pairs[p0];
     tile_load<B>(A + (int64_t)pr.x * B * B, ra);
     tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
@@ -213,26 +235,28 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(const doubl
       acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
     }
   }
-  epilogue<B>(acc, rb, cb, l16, kq, lane, wave, C + blk * B * B, red, norms + blk);
+  epilogue<B>(acc, rb, cb, l16, kq, lane, wave, C + blk * B * B, red, norms + blk, epi.dflag ? epi.dflag[blk] : 0,
+              epi);
 }
 
 #define LIF_MIXED_DISPATCH(KERNEL, B)                                                                      \
   do {                                                                                                     \
     dim3 grid((unsigned)nnzc), block(MixCfg<B>::THREADS);                                                  \
     if (!ta && !tb)                                                                                        \
-      hipLaunchKernelGGL((KERNEL<B, false, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, nnzc, C, norms); \
+      hipLaunchKernelGGL((KERNEL<B, false, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, norms, epi); \
     else if (ta && !tb)                                                                                    \
-      hipLaunchKernelGGL((KERNEL<B, true, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, nnzc, C, norms); \
+      hipLaunchKernelGGL((KERNEL<B, true, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, norms, epi); \
     else if (!ta && tb)                                                                                    \
-      hipLaunchKernelGGL((KERNEL<B, false, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, nnzc, C, norms); \
+      hipLaunchKernelGGL((KERNEL<B, false, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, norms, epi); \
     else                                                                                                   \
-      hipLaunchKernelGGL((KERNEL<B, true, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, nnzc, C, norms); \
+      hipLaunchKernelGGL((KERNEL<B, true, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, norms, epi); \
   } while (0)
 
 }  // namespace
 
 void launch_numeric_mixed(Ctx& c, int prec, const double* A, const double* Bm, bool ta, bool tb,
-                          const int64_t* seg, const int2* pairs, int64_t nnzc, int b, double* C, double* norms) {
+                          const int64_t* seg, const int2* pairs, int64_t nnzc, const int* live, int b, double* C,
+                          double* norms, const Epilogue& epi) {
   if (prec == LIF_MIXED_FP32) {
     if (b == 64)
       LIF_MIXED_DISPATCH(k_numeric_f32, 64);

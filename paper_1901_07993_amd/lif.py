@@ -44,7 +44,8 @@ class Blocks(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("m", c_int32), ("tau", c_double), ("prec", c_int32), ("stop", c_int32), ("tol", c_double),
                 ("max_iter", c_int32), ("base_rows", c_int64), ("start", c_int32), ("start_value", c_double),
-                ("checkpoint", c_int32), ("mem_cap_bytes", c_uint64), ("stream", c_void_p), ("timing", c_int32)]
+                ("checkpoint", c_int32), ("mem_cap_bytes", c_uint64), ("stream", c_void_p), ("timing", c_int32),
+                ("presize", c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -52,7 +53,7 @@ class Info(ctypes.Structure):
                 ("stagnated", c_int32), ("start_scale", c_double), ("delta_tracked", c_double),
                 ("flops_leaf_gemm", c_double), ("seconds_total", c_double), ("seconds_leaf_gemm", c_double),
                 ("leaf_gemm_launches", c_int64), ("products_total", c_int64), ("nnzb_Z", c_int64),
-                ("n_norms", c_int32), ("norms", c_double * 64)]
+                ("n_norms", c_int32), ("norms", c_double * 64), ("iterations_redone", c_int32)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "norms"}

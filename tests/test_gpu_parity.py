@@ -313,6 +313,32 @@ def test_bitwise_deterministic():
     assert np.array_equal(out[0].brow, out[1].brow) and np.array_equal(out[0].vals, out[1].vals)
 
 
+@pytest.mark.parametrize("presize", [1, 2])
+@pytest.mark.parametrize("n_mol,base,tau", [(150, 320, 1e-7), (150, 320, 0.0)])
+def test_presize_matches_exact_sizes(n_mol, base, tau, presize):
+    """Products sized from the previous iteration's counts (iterations redone
+    with exact sizes where a size fell short) give bitwise the factor of
+    reading every product's counts back.  presize = 2 (no margin) redoes every
+    iteration whose products grew, which the LIF levels' second iterations do."""
+    c_, e_ = water_cluster(n_mol, 14)
+    S = overlap_blocks(c_, e_, 64)
+    say(f"case presize vs exact lif water-{n_mol} base={base} tau={tau}")
+    res = []
+    for ps in (0, presize):
+        with lif.Factorization(dev(S), tau=tau, base_rows=base, presize=ps) as f:
+            info = f.localized()
+            res.append((info, f.get_Z()))
+    (i0, z0), (i1, z1) = res
+    say(f"  redone {i1['iterations_redone']}")
+    assert i0["iterations_redone"] == 0
+    if presize == 2:
+        assert i1["iterations_redone"] > 0
+    assert i1["iterations_total"] == i0["iterations_total"] and i1["products_total"] == i0["products_total"]
+    assert i1["norms"] == i0["norms"]
+    assert np.array_equal(z0.brow, z1.brow) and np.array_equal(z0.bcol, z1.bcol)
+    assert np.array_equal(z0.vals, z1.vals)
+
+
 def test_host_inputs_match_device_inputs():
     S, _ = config_matrix(0, count=30)
     say("case host vs device inputs")
