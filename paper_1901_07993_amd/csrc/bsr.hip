@@ -4,8 +4,11 @@
 // filters that cut level- and coupling-parts out of a matrix, transposition,
 // the Gershgorin bound (Sec. 2.2) and segmented norm sums.
 //
-// These passes stream over HBM; each block is handled by one workgroup with
-// coalesced 16-byte accesses, index work by one thread per block row.
+// Value blocks are reached through per-matrix pointer arrays and are written
+// once: truncation, filters and copies move 8-byte pointers, and a sum whose
+// block comes from one operand unscaled points at that operand's block.
+// Passes that do touch values handle one block per workgroup with coalesced
+// 16-byte accesses; index work runs one thread per block row or block.
 #include "common.h"
 #include "tile_mma.h"
 
@@ -45,13 +48,12 @@ __global__ void k_row_ptr_from_rows(const int* __restrict__ brow, int64_t nnzb, 
   for (int r = prev + 1; r <= cur; ++r) rp[r] = (int)e;
 }
 
-__global__ __launch_bounds__(kWG) void k_block_sumsq(const double* __restrict__ val, int64_t nnzb, int bb,
-                                                     double* __restrict__ out, int take_sqrt,
-                                                     const int* __restrict__ live) {
+__global__ __launch_bounds__(kWG) void k_block_sumsq(BlkIn blk, int64_t nnzb, int bb, double* __restrict__ out,
+                                                     int take_sqrt, const int* __restrict__ live) {
   __shared__ double sh[4];
   const int64_t e = blockIdx.x;
   if (live && e >= *live) return;
-  const double2* p = reinterpret_cast<const double2*>(val + e * (int64_t)bb);
+  const double2* p = reinterpret_cast<const double2*>(blk[e]);
   double s = 0.0;
   for (int i = threadIdx.x; i < bb / 2; i += kWG) {
     double2 v = p[i];
@@ -61,44 +63,34 @@ __global__ __launch_bounds__(kWG) void k_block_sumsq(const double* __restrict__ 
   if (threadIdx.x == 0) out[e] = take_sqrt ? sqrt(r) : r;
 }
 
-__global__ void k_keep_counts(const int* __restrict__ rp, const double* __restrict__ norms, double tau, int nb,
-                              int* __restrict__ counts) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
-  int cnt = 0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) cnt += (norms[e] >= tau) ? 1 : 0;
-  counts[i] = cnt;
+__global__ void k_gather_ptrs(BlkIn blk, const int* __restrict__ src, int64_t nnzb, BlkOut out,
+                              const int* __restrict__ live) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnzb || (live && e >= *live)) return;
+  out[e] = blk[src[e]];
 }
 
-__global__ void k_compact_index(const int* __restrict__ rp, const int* __restrict__ col,
-                                const double* __restrict__ norms, double tau, const int* __restrict__ nrp,
-                                int nb, int* __restrict__ ncol, int* __restrict__ src) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
-  int o = nrp[i];
-  for (int e = rp[i]; e < rp[i + 1]; ++e) {
-    if (norms[e] >= tau) {
-      ncol[o] = col[e];
-      src[o] = e;
-      ++o;
-    }
-  }
+// out[e] = base + e bb: the pointers of a contiguous value array
+__global__ void k_fill_ptrs(BlkOut out, const double* base, int bb, int64_t count) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) out[e] = base + e * bb;
 }
 
-__global__ __launch_bounds__(kWG) void k_gather_blocks(const double* __restrict__ val, const int* __restrict__ src,
-                                                       int bb, double* __restrict__ out, const int* __restrict__ live) {
+// contiguous copy of the blocks (block e to out + e bb)
+__global__ __launch_bounds__(kWG) void k_gather_values(BlkIn blk, int bb, double* __restrict__ out,
+                                                       const int* __restrict__ live) {
   const int64_t e = blockIdx.x;
   if (live && e >= *live) return;
-  const double2* s = reinterpret_cast<const double2*>(val + (int64_t)src[e] * bb);
-  double2* d = reinterpret_cast<double2*>(out + e * (int64_t)bb);
+  const v2d* s = reinterpret_cast<const v2d*>(blk[e]);
+  v2d* d = reinterpret_cast<v2d*>(out + e * (int64_t)bb);
   for (int i = threadIdx.x; i < bb / 2; i += kWG) d[i] = s[i];
 }
 
 // Gershgorin: row_max[i] = max over the b scalar rows of block row i of
 // sum_j |S_rj|.  One workgroup per block row; each wave takes scalar rows
 // w, w+4, ... and reads them 64 doubles at a time.
-__global__ __launch_bounds__(kWG) void k_gershgorin(const int* __restrict__ rp, const double* __restrict__ val,
-                                                    int b, double* __restrict__ row_max) {
+__global__ __launch_bounds__(kWG) void k_gershgorin(const int* __restrict__ rp, BlkIn blk, int b,
+                                                    double* __restrict__ row_max) {
   __shared__ double sh[4];
   const int i = blockIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -106,7 +98,7 @@ __global__ __launch_bounds__(kWG) void k_gershgorin(const int* __restrict__ rp, 
   for (int r = w; r < b; r += 4) {
     double s = 0.0;
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
-      const double* row = val + (int64_t)e * b * b + (int64_t)r * b;
+      const double* row = blk[e] + (int64_t)r * b;
       for (int cc = lane; cc < b; cc += 64) s += fabs(row[cc]);
     }
     s = wave_sum(s);
@@ -170,8 +162,10 @@ __device__ inline int union_row(const Src3& S, const unsigned char* diag_on, int
   return o;
 }
 
-__global__ void k_union_counts(Src3 S, const unsigned char* diag_on, int nb, int* counts) {
+// also clears the slot counter of the values pass that follows
+__global__ void k_union_counts(Src3 S, const unsigned char* diag_on, int nb, int* counts, int* slot) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot && i == 0) *slot = 0;
   if (i >= nb) return;
   counts[i] = union_row(S, diag_on, i, nullptr, nullptr, 0, nullptr, nullptr);
 }
@@ -186,15 +180,22 @@ __global__ void k_union_fill(Src3 S, const unsigned char* diag_on, const int* rc
 }
 
 struct Val3 {
-  const double* v[3];
+  BlkIn v[3];
   double coef[3];
 };
 
 // out = sum_t coef_t src_t[ix_t] + gamma I (diagonal entries of real rows only)
+// One output block per workgroup.  A block taken unscaled from a single
+// operand, with no identity term, is not copied: its pointer is reused.
+// Every other block is computed into the next free slot of `store` (slots
+// are handed out by an atomic counter; where a block lands does not change
+// its value).
 __global__ __launch_bounds__(kWG) void k_axpby_values(Val3 V, const int* __restrict__ ix, int64_t stride,
                                                       double gamma, const unsigned char* __restrict__ id,
                                                       const int* __restrict__ row_of, int b, int64_t n,
-                                                      double* __restrict__ out, const int* __restrict__ live) {
+                                                      double* __restrict__ store, int* __restrict__ slot,
+                                                      BlkOut out, const int* __restrict__ live) {
+  __shared__ int my_slot;
   const int64_t e = blockIdx.x;
   if (live && e >= *live) return;
   const int bb = b * b;
@@ -205,14 +206,21 @@ __global__ __launch_bounds__(kWG) void k_axpby_values(Val3 V, const int* __restr
   for (int t = 0; t < 3; ++t) {
     const int x = V.v[t] ? ix[t * stride + e] : -1;
     if (x >= 0) {
-      src[ns] = reinterpret_cast<const double2*>(V.v[t] + (int64_t)x * bb);
+      src[ns] = reinterpret_cast<const double2*>(V.v[t][x]);
       cf[ns] = V.coef[t];
       ++ns;
     }
   }
   const bool dg = id[e] != 0;
+  if (ns == 1 && cf[0] == 1.0 && !dg) {
+    if (threadIdx.x == 0) out[e] = reinterpret_cast<const double*>(src[0]);
+    return;
+  }
+  if (threadIdx.x == 0) my_slot = atomicAdd(slot, 1);
+  __syncthreads();
+  double* dst = store + (int64_t)my_slot * bb;
   const int64_t row0 = (int64_t)row_of[e] * b;
-  double2* po = reinterpret_cast<double2*>(out + e * (int64_t)bb);
+  double2* po = reinterpret_cast<double2*>(dst);
   for (int q = threadIdx.x; q < bb / 2; q += kWG) {
     double2 r = make_double2(0.0, 0.0);
     for (int t = 0; t < ns; ++t) {
@@ -230,6 +238,7 @@ __global__ __launch_bounds__(kWG) void k_axpby_values(Val3 V, const int* __restr
     }
     po[q] = r;
   }
+  if (threadIdx.x == 0) out[e] = dst;
 }
 
 __global__ void k_block_row_of(const int* __restrict__ rp, int nb, int* __restrict__ row_of) {
@@ -251,17 +260,6 @@ __device__ inline bool keep_pred(int mode, int li, int lj) {
   if (mode == 1) return ((li & 1) == 0) && lj == li + 1;
   if (mode == 3) return lj >= li;
   return true;
-}
-
-__global__ void k_filter_counts(const int* __restrict__ rp, const int* __restrict__ col, const int* __restrict__ rlab,
-                                const int* __restrict__ clab, int mode, int nb, int* __restrict__ counts) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
-  int li = rlab[i];
-  int cnt = 0;
-  if (li >= 0)
-    for (int e = rp[i]; e < rp[i + 1]; ++e) cnt += keep_pred(mode, li, clab[col[e]]) ? 1 : 0;
-  counts[i] = cnt;
 }
 
 __global__ void k_filter_fill(const int* __restrict__ rp, const int* __restrict__ col, const int* __restrict__ rlab,
@@ -326,14 +324,14 @@ __global__ __launch_bounds__(kWG) void k_transpose_sort(const int* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(kWG) void k_transpose_blocks(const double* __restrict__ val, const int* __restrict__ src,
-                                                          int b, double* __restrict__ out,
+__global__ __launch_bounds__(kWG) void k_transpose_blocks(BlkIn blk, const int* __restrict__ src, int b,
+                                                          double* __restrict__ store, BlkOut out,
                                                           const int* __restrict__ live) {
   __shared__ double t[64 * 65];
   const int64_t e = blockIdx.x;
   if (live && e >= *live) return;
-  const double* s = val + (int64_t)src[e] * b * b;
-  double* d = out + e * (int64_t)b * b;
+  const double* s = blk[src[e]];
+  double* d = store + e * (int64_t)b * b;
   for (int q = threadIdx.x; q < b * b; q += kWG) {
     int r = q / b, cc = q % b;
     t[r * 65 + cc] = s[q];
@@ -343,6 +341,7 @@ __global__ __launch_bounds__(kWG) void k_transpose_blocks(const double* __restri
     int r = q / b, cc = q % b;
     d[q] = t[cc * 65 + r];
   }
+  if (threadIdx.x == 0) out[e] = d;
 }
 
 // out[s] = sum of sumsq[e] over the blocks of block rows [rlo[s], rhi[s])
@@ -387,19 +386,24 @@ __global__ void k_intersect_counts(const int* __restrict__ ra, const int* __rest
 }
 
 // Inverse-Cholesky adjoint mask on block row/col coordinates: diagonal
-// blocks keep their upper triangle with the diagonal halved; other blocks
-// are left as they are (the caller keeps only blocks with col >= row).
+// blocks keep their upper triangle with the diagonal halved (written to slot
+// `row` of `store`, the pointer redirected there); other blocks are left as
+// they are (the caller keeps only blocks with col >= row).
 __global__ __launch_bounds__(kWG) void k_phi_diag(const int* __restrict__ row_of, const int* __restrict__ col,
-                                                  int b, double* __restrict__ val, const int* __restrict__ live) {
+                                                  int b, double* __restrict__ store, BlkOut blk,
+                                                  const int* __restrict__ live) {
   const int64_t e = blockIdx.x;
   if (live && e >= *live) return;
-  if (row_of[e] != col[e]) return;
-  double* v = val + e * (int64_t)b * b;
+  const int i = row_of[e];
+  if (i != col[e]) return;
+  const double* s = blk[e];
+  double* v = store + (int64_t)i * b * b;
   for (int q = threadIdx.x; q < b * b; q += kWG) {
     const int r = q / b, cc = q % b;
-    if (cc < r) v[q] = 0.0;
-    else if (cc == r) v[q] *= 0.5;
+    v[q] = (cc < r) ? 0.0 : (cc == r ? 0.5 * s[q] : s[q]);
   }
+  __syncthreads();  // every read of the old block done before the pointer moves
+  if (threadIdx.x == 0) blk[e] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -445,12 +449,6 @@ struct KeepCount {
   }
 };
 
-struct UnionCount {
-  Src3 S;
-  const unsigned char* diag_on;
-  __device__ int operator()(int i) const { return union_row(S, diag_on, i, nullptr, nullptr, 0, nullptr, nullptr); }
-};
-
 struct FilterCount {
   const int* rp;
   const int* col;
@@ -489,33 +487,26 @@ struct IntersectCount {
   }
 };
 
-// Truncation compaction, one workgroup per block of the untruncated matrix:
-// a kept block finds its row (binary search in the row pointers) and its
-// rank among the kept blocks before it in that row, then moves there.
-__global__ __launch_bounds__(kWG) void k_compact_gather(const int* __restrict__ rp, int nb,
-                                                        const int* __restrict__ col,
-                                                        const double* __restrict__ norms, double tau,
-                                                        const int* __restrict__ nrp, const double* __restrict__ val,
-                                                        int bb, int* __restrict__ ncol, double* __restrict__ nval) {
-  __shared__ int dst;
-  const int64_t e = blockIdx.x;
-  if (e >= rp[nb] || !(norms[e] >= tau)) return;
-  if (threadIdx.x == 0) {
-    int lo = 0, hi = nb;  // largest row with rp[row] <= e
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (rp[mid] <= e) lo = mid;
-      else hi = mid;
-    }
-    int rank = 0;
-    for (int f = rp[lo]; f < e; ++f) rank += (norms[f] >= tau) ? 1 : 0;
-    dst = nrp[lo] + rank;
-    ncol[dst] = col[e];
+// Truncation compaction, one thread per block of the untruncated matrix: a
+// kept block finds its row (binary search in the row pointers) and its rank
+// among the kept blocks before it in that row; its column and value pointer
+// move there.
+__global__ void k_compact_gather(const int* __restrict__ rp, int nb, const int* __restrict__ col,
+                                 const double* __restrict__ norms, double tau, const int* __restrict__ nrp,
+                                 BlkIn blk, int64_t nnzb, int* __restrict__ ncol, BlkOut nblk) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnzb || e >= rp[nb] || !(norms[e] >= tau)) return;
+  int lo = 0, hi = nb;  // largest row with rp[row] <= e
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (rp[mid] <= e) lo = mid;
+    else hi = mid;
   }
-  __syncthreads();
-  const v2d* s = reinterpret_cast<const v2d*>(val + e * (int64_t)bb);
-  v2d* d = reinterpret_cast<v2d*>(nval + (int64_t)dst * bb);
-  for (int i = threadIdx.x; i < bb / 2; i += kWG) d[i] = s[i];
+  int rank = 0;
+  for (int64_t f = rp[lo]; f < e; ++f) rank += (norms[f] >= tau) ? 1 : 0;
+  const int dst = nrp[lo] + rank;
+  ncol[dst] = col[e];
+  nblk[dst] = blk[e];
 }
 
 __global__ void k_fill_i32(int* p, int value, int64_t count) {
@@ -537,31 +528,29 @@ void launch_row_ptr_from_rows(Ctx& c, const int* brow, int64_t nnzb, int nb, int
   LIF_LAUNCH(k_row_ptr_from_rows, dim3(grid1(nnzb + 1, 256)), dim3(256), 0, c.stream, brow, nnzb, nb, row_ptr);
 }
 
-void launch_block_sumsq(Ctx& c, const double* val, int64_t nnzb, int b, double* out, bool take_sqrt,
-                        const int* live) {
+void launch_block_sumsq(Ctx& c, BlkIn blk, int64_t nnzb, int b, double* out, bool take_sqrt, const int* live) {
   if (nnzb == 0) return;
-  LIF_LAUNCH(k_block_sumsq, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, val, nnzb, b * b, out, take_sqrt ? 1 : 0,
+  LIF_LAUNCH(k_block_sumsq, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, blk, nnzb, b * b, out, take_sqrt ? 1 : 0,
              live);
 }
 
-void launch_keep_counts(Ctx& c, const int* row_ptr, const double* norms, double tau, int nb, int* counts) {
-  LIF_LAUNCH(k_keep_counts, dim3(grid1(nb, 256)), dim3(256), 0, c.stream, row_ptr, norms, tau, nb, counts);
-}
-
-void launch_compact_index(Ctx& c, const int* row_ptr, const int* col, const double* norms, double tau,
-                          const int* new_row_ptr, int nb, int* new_col, int* src) {
-  LIF_LAUNCH(k_compact_index, dim3(grid1(nb, 256)), dim3(256), 0, c.stream, row_ptr, col, norms, tau, new_row_ptr,
-             nb, new_col, src);
-}
-
-void launch_gather_blocks(Ctx& c, const double* val, const int* src, int64_t nnzb, int b, double* out,
-                          const int* live) {
+void launch_gather_ptrs(Ctx& c, BlkIn blk, const int* src, int64_t nnzb, BlkOut out, const int* live) {
   if (nnzb == 0) return;
-  LIF_LAUNCH(k_gather_blocks, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, val, src, b * b, out, live);
+  LIF_LAUNCH(k_gather_ptrs, dim3(grid1(nnzb, 256)), dim3(256), 0, c.stream, blk, src, nnzb, out, live);
 }
 
-void launch_gershgorin(Ctx& c, const int* row_ptr, const double* val, int nb, int b, double* row_max) {
-  LIF_LAUNCH(k_gershgorin, dim3(nb), dim3(kWG), 0, c.stream, row_ptr, val, b, row_max);
+void launch_fill_ptrs(Ctx& c, BlkOut out, const double* base, int b, int64_t count) {
+  if (count == 0) return;
+  LIF_LAUNCH(k_fill_ptrs, dim3(grid1(count, 256)), dim3(256), 0, c.stream, out, base, b * b, count);
+}
+
+void launch_gather_values(Ctx& c, BlkIn blk, int64_t nnzb, int b, double* out, const int* live) {
+  if (nnzb == 0) return;
+  LIF_LAUNCH(k_gather_values, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, blk, b * b, out, live);
+}
+
+void launch_gershgorin(Ctx& c, const int* row_ptr, BlkIn blk, int nb, int b, double* row_max) {
+  LIF_LAUNCH(k_gershgorin, dim3(nb), dim3(kWG), 0, c.stream, row_ptr, blk, b, row_max);
 }
 
 void launch_max_reduce(Ctx& c, const double* in, int count, double* out) {
@@ -569,13 +558,13 @@ void launch_max_reduce(Ctx& c, const double* in, int count, double* out) {
 }
 
 void launch_union3(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on, int nb,
-                   int* counts) {
+                   int* counts, int* slot) {
   Src3 S;
   for (int t = 0; t < 3; ++t) {
     S.rp[t] = rp[t];
     S.col[t] = col[t];
   }
-  LIF_LAUNCH(k_union_counts, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, S, diag_on, nb, counts);
+  LIF_LAUNCH(k_union_counts, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, S, diag_on, nb, counts, slot);
 }
 
 void launch_union3_fill(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on,
@@ -587,17 +576,6 @@ void launch_union3_fill(Ctx& c, const int* const rp[3], const int* const col[3],
   }
   LIF_LAUNCH(k_union_fill, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, S, diag_on, rc, nb, cc, ix, stride, id,
              rowof);
-}
-
-void launch_union3_count_scan(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on,
-                              int nb, int* out_rp) {
-  UnionCount u;
-  for (int t = 0; t < 3; ++t) {
-    u.S.rp[t] = rp[t];
-    u.S.col[t] = col[t];
-  }
-  u.diag_on = diag_on;
-  LIF_LAUNCH(k_count_scan<UnionCount>, dim3(1), dim3(kCS), 0, c.stream, u, nb, out_rp);
 }
 
 void launch_keep_count_scan(Ctx& c, const int* row_ptr, const double* norms, double tau, int nb, int* out_rp) {
@@ -618,16 +596,15 @@ void launch_intersect_count_scan(Ctx& c, const int* ra, const int* ca, const int
 }
 
 void launch_compact_gather(Ctx& c, const int* row_ptr, int nb, const int* col, const double* norms, double tau,
-                           const int* new_row_ptr, const double* val, int64_t nnzb, int b, int* new_col,
-                           double* new_val) {
+                           const int* new_row_ptr, BlkIn blk, int64_t nnzb, int* new_col, BlkOut new_blk) {
   if (nnzb == 0) return;
-  LIF_LAUNCH(k_compact_gather, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, row_ptr, nb, col, norms, tau,
-             new_row_ptr, val, b * b, new_col, new_val);
+  LIF_LAUNCH(k_compact_gather, dim3(grid1(nnzb, 256)), dim3(256), 0, c.stream, row_ptr, nb, col, norms, tau,
+             new_row_ptr, blk, nnzb, new_col, new_blk);
 }
 
-void launch_axpby3_values(Ctx& c, const double* const v[3], const double coef[3], const int* ix, int64_t stride,
+void launch_axpby3_values(Ctx& c, const BlkIn v[3], const double coef[3], const int* ix, int64_t stride,
                           double gamma, const unsigned char* id, const int* row_of, int64_t nnzb, int b, int64_t n,
-                          double* out, const int* live) {
+                          double* store, int* slot, BlkOut out, const int* live) {
   if (nnzb == 0) return;
   Val3 V;
   for (int t = 0; t < 3; ++t) {
@@ -635,18 +612,12 @@ void launch_axpby3_values(Ctx& c, const double* const v[3], const double coef[3]
     V.coef[t] = coef[t];
   }
   LIF_LAUNCH(k_axpby_values, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, V, ix, stride, gamma, id, row_of, b, n,
-             out, live);
+             store, slot, out, live);
 }
 
 void launch_block_row_of(Ctx& c, const int* row_ptr, int nb, int64_t nnzb, int* row_of) {
   if (nnzb == 0) return;
   LIF_LAUNCH(k_block_row_of, dim3(nb), dim3(64), 0, c.stream, row_ptr, nb, row_of);
-}
-
-void launch_filter_counts(Ctx& c, const int* row_ptr, const int* col, const int* rlab, const int* clab, int mode,
-                          int nb, int* counts) {
-  LIF_LAUNCH(k_filter_counts, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, row_ptr, col, rlab, clab, mode, nb,
-             counts);
 }
 
 void launch_filter_fill(Ctx& c, const int* row_ptr, const int* col, const int* rlab, const int* clab, int mode,
@@ -670,10 +641,10 @@ void launch_transpose_sort(Ctx& c, const int* tptr, int nb, const int* icol, con
   LIF_LAUNCH(k_transpose_sort, dim3(nb), dim3(kWG), 0, c.stream, tptr, icol, isrc, ocol, osrc);
 }
 
-void launch_transpose_blocks(Ctx& c, const double* val, const int* src, int64_t nnzb, int b, double* out,
+void launch_transpose_blocks(Ctx& c, BlkIn blk, const int* src, int64_t nnzb, int b, double* store, BlkOut out,
                              const int* live) {
   if (nnzb == 0) return;
-  LIF_LAUNCH(k_transpose_blocks, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, val, src, b, out, live);
+  LIF_LAUNCH(k_transpose_blocks, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, blk, src, b, store, out, live);
 }
 
 void launch_segment_sum(Ctx& c, const double* sumsq, const int* row_ptr, const int* rlo, const int* rhi, int nseg,
@@ -688,9 +659,10 @@ void launch_intersect(Ctx& c, const int* ra, const int* ca, const int* rr, const
              src);
 }
 
-void launch_phi_diag(Ctx& c, const int* row_of, const int* col, int64_t nnzb, int b, double* val, const int* live) {
+void launch_phi_diag(Ctx& c, const int* row_of, const int* col, int64_t nnzb, int b, double* store, BlkOut blk,
+                     const int* live) {
   if (nnzb == 0) return;
-  LIF_LAUNCH(k_phi_diag, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, row_of, col, b, val, live);
+  LIF_LAUNCH(k_phi_diag, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, row_of, col, b, store, blk, live);
 }
 
 void launch_fill_i32(Ctx& c, int* p, int value, int64_t count) {

@@ -33,7 +33,7 @@ __device__ inline int64_t packed_tile(int64_t tile0, int nbb, int i, int j) {
 }
 
 __global__ __launch_bounds__(256) void k_chol_scatter(const int* __restrict__ row_of, const int* __restrict__ col,
-                                                      const double* __restrict__ val, int b,
+                                                      BlkIn val, int b,
                                                       const int* __restrict__ base_of_row,
                                                       const int* __restrict__ blk0, const int* __restrict__ nbbv,
                                                       const int64_t* __restrict__ tile0, double* __restrict__ U,
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void k_chol_scatter(const int* __restrict__ ro
   if (s < 0 || base_of_row[J] != s || J < I) return;
   const int i = I - blk0[s], j = J - blk0[s];
   const int64_t t = packed_tile(tile0[s], nbbv[s], i, j);
-  const double2* src = reinterpret_cast<const double2*>(val + e * (int64_t)b * b);
+  const double2* src = reinterpret_cast<const double2*>(val[e]);
   double2* dst = reinterpret_cast<double2*>(U + t * (int64_t)b * b);
   for (int q = threadIdx.x; q < b * b / 2; q += 256) dst[q] = src[q];
   if (threadIdx.x == 0) {
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, int band, 
     LIF_HIP(hipGetLastError());      \
   } while (0)
 
-void launch_chol_scatter(Ctx& c, const int* row_of, const int* col, const double* val, int64_t nnzb, int b,
+void launch_chol_scatter(Ctx& c, const int* row_of, const int* col, BlkIn val, int64_t nnzb, int b,
                          const int* base_of_row, const int* blk0, const int* nbb, const int64_t* tile0, double* U,
                          unsigned char* nz, int* band) {
   if (nnzb == 0) return;

@@ -5,10 +5,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <utility>
@@ -95,7 +97,7 @@ class DBuf {
 
 // ---------------------------------------------------------------------------
 // Device block-CSR matrix: nb block rows, row_ptr[nb+1], col[nnzb] sorted
-// within each row, val[nnzb][b][b] row-major FP64 blocks.
+// within each row, blk[nnzb] pointers to row-major FP64 b x b blocks.
 // ---------------------------------------------------------------------------
 //
 // The block count may be known only on the device (row_ptr[nb]): operations
@@ -103,17 +105,38 @@ class DBuf {
 // sums) allocate that bound as capacity and leave nnzb = -1, so they need no
 // device-to-host read.  Kernels that run over blocks take the device count
 // and skip the tail of the capacity.
+// Block pointer arrays (device): block e of a matrix is the b*b row-major
+// doubles at blk[e].  A value block is written once by the kernel that
+// creates it and only read afterwards, so matrices share blocks freely:
+// truncation, filters and copies move pointers, and a sum reuses the blocks
+// it takes unscaled from one operand.
+typedef const double* const* BlkIn;
+typedef const double** BlkOut;
+typedef std::shared_ptr<DBuf<double>> Store;
+
 struct Bsr {
   int64_t n = 0;
   int b = 0;
   int nb = 0;
   mutable int64_t nnzb = 0;  // exact block count, or -1 while only the device knows it
-  int64_t cap = 0;           // blocks allocated in col and val (>= the count)
+  int64_t cap = 0;           // blocks allocated in col and blk (>= the count)
   DBuf<int> row_ptr;
   DBuf<int> col;
-  DBuf<double> val;
+  DBuf<const double*> blk;   // [cap] value block pointers
+  std::vector<Store> store;  // value arrays the pointers point into (kept alive)
   int64_t bound() const { return nnzb >= 0 ? nnzb : cap; }
   const int* live() const { return row_ptr.get() + nb; }  // device-side count
+  BlkIn ptrs() const { return blk.get(); }
+  void share_store(const Bsr& o) {
+    for (const Store& s : o.store)
+      if (std::find(store.begin(), store.end(), s) == store.end()) store.push_back(s);
+  }
+  // blocks held by the value arrays this matrix points into
+  int64_t store_blocks() const {
+    size_t d = 0;
+    for (const Store& s : store) d += s->size();
+    return b ? (int64_t)(d / ((size_t)b * b)) : 0;
+  }
 };
 
 // Per-call statistics.
@@ -180,9 +203,8 @@ struct Ctx {
 // ---------------------------------------------------------------------------
 
 // scan.hip
-// out[0] = 0, out[i+1] = out[i] + in[i] for i < count (int32 or int64 input)
+// out[0] = 0, out[i+1] = out[i] + in[i] for i < count
 void scan_exclusive_i32(Ctx& c, const int* in, int* out, int count);
-void scan_exclusive_i64(Ctx& c, const int64_t* in, int64_t* out, int count);
 // both scans of the symbolic phase in one launch
 void scan_exclusive_pair(Ctx& c, const int* in32, int* out32, const int64_t* in64, int64_t* out64, int count);
 // the same against capacities fixed in advance: the totals go to sizes[0..1];
@@ -193,36 +215,34 @@ void scan_exclusive_pair_capped(Ctx& c, const int* in32, int* out32, const int64
 
 // bsr.hip
 void launch_row_ptr_from_rows(Ctx& c, const int* brow, int64_t nnzb, int nb, int* row_ptr);
-void launch_block_sumsq(Ctx& c, const double* val, int64_t nnzb, int b, double* out, bool take_sqrt,
-                        const int* live);
-void launch_keep_counts(Ctx& c, const int* row_ptr, const double* norms, double tau, int nb, int* counts);
-void launch_compact_index(Ctx& c, const int* row_ptr, const int* col, const double* norms, double tau,
-                          const int* new_row_ptr, int nb, int* new_col, int* src);
-void launch_gather_blocks(Ctx& c, const double* val, const int* src, int64_t nnzb, int b, double* out,
-                          const int* live);
-void launch_gershgorin(Ctx& c, const int* row_ptr, const double* val, int nb, int b, double* row_max);
+void launch_block_sumsq(Ctx& c, BlkIn blk, int64_t nnzb, int b, double* out, bool take_sqrt, const int* live);
+// out[e] = blk[src[e]]
+void launch_gather_ptrs(Ctx& c, BlkIn blk, const int* src, int64_t nnzb, BlkOut out, const int* live);
+// out[e] = base + e b^2, e < count
+void launch_fill_ptrs(Ctx& c, BlkOut out, const double* base, int b, int64_t count);
+// the blocks' values, contiguous: block e to out + e b^2
+void launch_gather_values(Ctx& c, BlkIn blk, int64_t nnzb, int b, double* out, const int* live);
+void launch_gershgorin(Ctx& c, const int* row_ptr, BlkIn blk, int nb, int b, double* row_max);
 void launch_max_reduce(Ctx& c, const double* in, int count, double* out);
+// per-row counts of the union; also zeroes *slot (nullable) for the values pass
 void launch_union3(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on, int nb,
-                   int* counts);
+                   int* counts, int* slot);
 void launch_union3_fill(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on,
                         const int* rc, int nb, int* cc, int* ix, int64_t stride, unsigned char* id, int* rowof);
-// one-workgroup per-row count + exclusive scan (writes out_rp[0..nb])
-void launch_union3_count_scan(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on,
-                              int nb, int* out_rp);
 void launch_keep_count_scan(Ctx& c, const int* row_ptr, const double* norms, double tau, int nb, int* out_rp);
 void launch_filter_count_scan(Ctx& c, const int* row_ptr, const int* col, const int* rlab, const int* clab, int mode,
                               int nb, int* out_rp);
 void launch_intersect_count_scan(Ctx& c, const int* ra, const int* ca, const int* rr, const int* cr, int nb,
                                  int* out_rp);
 void launch_compact_gather(Ctx& c, const int* row_ptr, int nb, const int* col, const double* norms, double tau,
-                           const int* new_row_ptr, const double* val, int64_t nnzb, int b, int* new_col,
-                           double* new_val);
-void launch_axpby3_values(Ctx& c, const double* const v[3], const double coef[3], const int* ix, int64_t stride,
+                           const int* new_row_ptr, BlkIn blk, int64_t nnzb, int* new_col, BlkOut new_blk);
+// out block e = sum_t coef[t] v[t][ix[t][e]] (+ gamma I on the real rows of
+// flagged diagonal blocks); computed blocks take slots of `store` from the
+// counter *slot, blocks taken unscaled from one operand are shared
+void launch_axpby3_values(Ctx& c, const BlkIn v[3], const double coef[3], const int* ix, int64_t stride,
                           double gamma, const unsigned char* id, const int* row_of, int64_t nnzb, int b, int64_t n,
-                          double* out, const int* live);
+                          double* store, int* slot, BlkOut out, const int* live);
 void launch_block_row_of(Ctx& c, const int* row_ptr, int nb, int64_t nnzb, int* row_of);
-void launch_filter_counts(Ctx& c, const int* row_ptr, const int* col, const int* rlab, const int* clab,
-                          int mode, int nb, int* counts);
 void launch_filter_fill(Ctx& c, const int* row_ptr, const int* col, const int* rlab, const int* clab,
                         int mode, const int* new_row_ptr, int nb, int* new_col, int* src);
 void launch_transpose_counts(Ctx& c, const int* col, int64_t nnzb, int* counts, const int* live);
@@ -230,7 +250,7 @@ void launch_transpose_fill(Ctx& c, const int* row_ptr, const int* col, const int
                            int* cursor, int* tcol, int* tsrc);
 void launch_transpose_sort(Ctx& c, const int* tptr, int nb, const int* icol, const int* isrc, int* ocol,
                            int* osrc);
-void launch_transpose_blocks(Ctx& c, const double* val, const int* src, int64_t nnzb, int b, double* out,
+void launch_transpose_blocks(Ctx& c, BlkIn blk, const int* src, int64_t nnzb, int b, double* store, BlkOut out,
                              const int* live);
 void launch_segment_sum(Ctx& c, const double* sumsq, const int* row_ptr, const int* rlo, const int* rhi, int nseg,
                         double* out);
@@ -238,7 +258,8 @@ void launch_fill_i32(Ctx& c, int* p, int value, int64_t count);
 // counts (nrp == null) or fills (nrp given) the blocks of A present in pattern R
 void launch_intersect(Ctx& c, const int* ra, const int* ca, const int* rr, const int* cr, int nb, int* counts,
                       const int* nrp, int* ncol, int* src);
-void launch_phi_diag(Ctx& c, const int* row_of, const int* col, int64_t nnzb, int b, double* val, const int* live);
+void launch_phi_diag(Ctx& c, const int* row_of, const int* col, int64_t nnzb, int b, double* store, BlkOut blk,
+                     const int* live);
 
 // spgemm.hip
 // Symbolic phase.  opA given as CSR (row ptr, col, value index) of op(A);
@@ -267,16 +288,16 @@ struct Epilogue {
 // (prec = LIF_FP64) or with FP32 / BF16 inputs and FP32 accumulation.
 // `nnzc` is the grid (the output capacity); `live` (device) the number of
 // output blocks actually present, <= nnzc.
-void launch_numeric(Ctx& c, int prec, const double* A, const double* B, bool ta, bool tb, const int64_t* seg,
-                    const int2* pairs, int64_t nnzc, const int* live, int b, double* C, double* norms,
-                    const Epilogue& epi);
+// Output block e is written to C + e b^2 and its pointer to Cp[e].
+void launch_numeric(Ctx& c, int prec, BlkIn A, BlkIn B, bool ta, bool tb, const int64_t* seg, const int2* pairs,
+                    int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms, const Epilogue& epi);
 // spgemm_mixed.hip
-void launch_numeric_mixed(Ctx& c, int prec, const double* A, const double* Bm, bool ta, bool tb,
-                          const int64_t* seg, const int2* pairs, int64_t nnzc, const int* live, int b, double* C,
-                          double* norms, const Epilogue& epi);
+void launch_numeric_mixed(Ctx& c, int prec, BlkIn A, BlkIn Bm, bool ta, bool tb, const int64_t* seg,
+                          const int2* pairs, int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms,
+                          const Epilogue& epi);
 
 // chol.hip -- batched leaf inverse Cholesky on packed upper tile grids
-void launch_chol_scatter(Ctx& c, const int* row_of, const int* col, const double* val, int64_t nnzb, int b,
+void launch_chol_scatter(Ctx& c, const int* row_of, const int* col, BlkIn val, int64_t nnzb, int b,
                          const int* base_of_row, const int* blk0, const int* nbb, const int64_t* tile0, double* U,
                          unsigned char* nz, int* band);
 void launch_chol_pad(Ctx& c, int nbase, const int* nbb, const int* rows, const int64_t* tile0, int b, double* M,
@@ -308,6 +329,11 @@ void h2d(Ctx& c, T* dst, const T* src, size_t count) {
   if (count) LIF_HIP(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, c.stream));
 }
 
+// a value array for `blocks` blocks of b*b doubles, from the pool
+Store new_store(Ctx& c, int64_t blocks, int b);
+// moves A's live blocks into one fresh contiguous store (releasing the
+// stores it pointed into); reads the block count back
+Bsr compact_values(Ctx& c, Bsr&& A);
 Bsr bsr_empty(Ctx& c, int64_t n, int b);
 Bsr bsr_from_blocks(Ctx& c, const lif_blocks& in);
 void bsr_to_blocks(Ctx& c, const Bsr& A, int32_t* brow, int32_t* bcol, double* vals, bool on_device);

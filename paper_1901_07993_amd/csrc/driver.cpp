@@ -165,15 +165,16 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       std::vector<std::array<int64_t, 2>> seen = c.spec.seen;
       c.spec.on = false;
       c.spec.record = false;
-      int over = 0;
+      int over = 0, nz_new = 0;
       std::vector<int64_t> sz(2 * nprod);
-      std::vector<Ctx::Read> extra;
+      std::vector<Ctx::Read> extra{{&nz_new, Znew.live(), sizeof(int)}};
       if (planned) {
         extra.push_back({&over, c.spec.overflow.get(), sizeof(int)});
         for (size_t i = 0; i < sz.size(); i += 8)
           extra.push_back({sz.data() + i, c.spec.sizes.get() + i, sizeof(int64_t) * std::min<size_t>(8, sz.size() - i)});
       }
       ss = node_sumsq(c, dnew, d_rlo.get(), d_rhi.get(), nn, extra);
+      Znew.nnzb = nz_new;
       if (planned && over) {
         ++c.stats.redone;
         planned = false;
@@ -197,6 +198,12 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
         caps.push_back(o.presize == 2 ? v : std::array<int64_t, 2>{v[0] + v[0] / 2 + 64, 4 * v[1] + 4096});
       break;
     }
+    // Z_{k+1} and delta_{k+1} share the blocks they did not change with
+    // Z_k, delta_k and the products; once the value arrays they keep alive
+    // hold more than three times their own blocks, their blocks are moved
+    // into one array (counts are known here: no extra read-back)
+    if (Znew.store_blocks() > 3 * Znew.nnzb + 64) Znew = compact_values(c, std::move(Znew));
+    if (dnew.store_blocks() > 3 * dnew.nnzb + 64) dnew = compact_values(c, std::move(dnew));
     if (ck) ck->push_back(std::move(Z));  // Z_k is immutable: keep it, no copy
     Z = std::move(Znew);
     delta = std::move(dnew);
@@ -363,14 +370,14 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   Z.n = S.n;
   Z.b = b;
   Z.nb = nb;
-  Z.val = DBuf<double>(c.pool, (size_t)tiles * tile_doubles);
+  Store zs = new_store(c, tiles, b);
   LIF_HIP(hipMemsetAsync(U.get(), 0, (size_t)tiles * tile_doubles * sizeof(double), c.stream));
-  LIF_HIP(hipMemsetAsync(Z.val.get(), 0, (size_t)tiles * tile_doubles * sizeof(double), c.stream));
+  LIF_HIP(hipMemsetAsync(zs->get(), 0, (size_t)tiles * tile_doubles * sizeof(double), c.stream));
   {
     const int64_t snz = exact_nnzb(c, S);
     DBuf<int> rowof(c.pool, (size_t)std::max<int64_t>(snz, 1));
     launch_block_row_of(c, S.row_ptr.get(), nb, snz, rowof.get());
-    launch_chol_scatter(c, rowof.get(), S.col.get(), S.val.get(), snz, b, d_bor.get(), d_blk0.get(), d_nbb.get(),
+    launch_chol_scatter(c, rowof.get(), S.col.get(), S.ptrs(), snz, b, d_bor.get(), d_blk0.get(), d_nbb.get(),
                         d_tile0.get(), U.get(), nz.get(), d_band.get());
   }
   // tile band of S within the leaves: bounds the grids of trsm and update
@@ -379,13 +386,13 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   c.d2h(&band, d_band.get(), sizeof(int));
   launch_chol_pad(c, nbase, d_nbb.get(), d_rows.get(), d_tile0.get(), b, U.get(), 1.0);
   for (int k = 0; k < max_nbb; ++k) {
-    launch_potrf(c, k, nbase, d_nbb.get(), d_blk0.get(), d_tile0.get(), b, U.get(), Z.val.get(), d_err.get());
-    launch_trsm(c, k, band, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), Z.val.get(), nz.get());
+    launch_potrf(c, k, nbase, d_nbb.get(), d_blk0.get(), d_tile0.get(), b, U.get(), zs->get(), d_err.get());
+    launch_trsm(c, k, band, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get());
     launch_update(c, k, band, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), nz.get());
   }
   for (int j = 1; j < max_nbb; ++j)
-    launch_trinv(c, j, band, nbase, d_nbb.get(), d_tile0.get(), b, U.get(), Z.val.get(), nz.get());
-  launch_chol_pad(c, nbase, d_nbb.get(), d_rows.get(), d_tile0.get(), b, Z.val.get(), 0.0);
+    launch_trinv(c, j, band, nbase, d_nbb.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get());
+  launch_chol_pad(c, nbase, d_nbb.get(), d_rows.get(), d_tile0.get(), b, zs->get(), 0.0);
   std::vector<int> err(nbase);
   c.d2h(err.data(), d_err.get(), nbase * sizeof(int));
   for (int s = 0; s < nbase; ++s)
@@ -411,10 +418,15 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   Z.col = DBuf<int>(c.pool, (size_t)tiles);
   h2d(c, Z.row_ptr.get(), rp.data(), nb + 1);
   h2d(c, Z.col.get(), col.data(), (size_t)tiles);
+  Z.blk = DBuf<const double*>(c.pool, (size_t)tiles);
+  Z.store.push_back(zs);
+  launch_fill_ptrs(c, Z.blk.get(), zs->get(), b, tiles);
   // leaf truncation (Sec. 5); exactly-zero tiles of the triangle are dropped
   // as well (the smallest positive double as threshold at tau = 0)
   DBuf<double> nrm = block_norms(c, Z);
-  return truncate(c, std::move(Z), nrm.get(), std::max(tau, std::numeric_limits<double>::denorm_min()));
+  Bsr Zt = truncate(c, std::move(Z), nrm.get(), std::max(tau, std::numeric_limits<double>::denorm_min()));
+  // the packed triangles hold every tile of each leaf; keep only the kept ones
+  return compact_values(c, std::move(Zt));
 }
 
 Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck) {

@@ -29,6 +29,19 @@ Bsr like(const Bsr& A) {
 
 }  // namespace
 
+Store new_store(Ctx& c, int64_t blocks, int b) {
+  return std::make_shared<DBuf<double>>(c.pool, (size_t)std::max<int64_t>(blocks, 0) * b * b);
+}
+
+Bsr compact_values(Ctx& c, Bsr&& A) {
+  const int64_t nnz = exact_nnzb(c, A);
+  Store st = new_store(c, nnz, A.b);
+  launch_gather_values(c, A.ptrs(), nnz, A.b, st->get(), nullptr);
+  launch_fill_ptrs(c, A.blk.get(), st->get(), A.b, nnz);
+  A.store.assign(1, st);
+  return std::move(A);
+}
+
 int64_t exact_nnzb(Ctx& c, const Bsr& A) {
   if (A.nnzb < 0) A.nnzb = read1(c, A.live());
   return A.nnzb;
@@ -56,11 +69,14 @@ Bsr bsr_from_blocks(Ctx& c, const lif_blocks& in) {
   const hipMemcpyKind kind = in.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   DBuf<int> brow(c.pool, (size_t)in.nnzb);
   A.col = DBuf<int>(c.pool, (size_t)in.nnzb);
-  A.val = DBuf<double>(c.pool, (size_t)in.nnzb * in.b * in.b);
+  Store st = new_store(c, in.nnzb, in.b);
+  A.blk = DBuf<const double*>(c.pool, (size_t)in.nnzb);
+  A.store.push_back(st);
   if (in.nnzb) {
     LIF_HIP(hipMemcpyAsync(brow.get(), in.brow, in.nnzb * sizeof(int), kind, c.stream));
     LIF_HIP(hipMemcpyAsync(A.col.get(), in.bcol, in.nnzb * sizeof(int), kind, c.stream));
-    LIF_HIP(hipMemcpyAsync(A.val.get(), in.vals, in.nnzb * (size_t)in.b * in.b * sizeof(double), kind, c.stream));
+    LIF_HIP(hipMemcpyAsync(st->get(), in.vals, in.nnzb * (size_t)in.b * in.b * sizeof(double), kind, c.stream));
+    launch_fill_ptrs(c, A.blk.get(), st->get(), in.b, in.nnzb);
   }
   A.row_ptr = DBuf<int>(c.pool, A.nb + 1);
   launch_row_ptr_from_rows(c, brow.get(), in.nnzb, A.nb, A.row_ptr.get());
@@ -75,7 +91,14 @@ void bsr_to_blocks(Ctx& c, const Bsr& A, int32_t* brow, int32_t* bcol, double* v
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   LIF_HIP(hipMemcpyAsync(brow, rows.get(), nnz * sizeof(int), kind, c.stream));
   LIF_HIP(hipMemcpyAsync(bcol, A.col.get(), nnz * sizeof(int), kind, c.stream));
-  LIF_HIP(hipMemcpyAsync(vals, A.val.get(), nnz * (size_t)A.b * A.b * sizeof(double), kind, c.stream));
+  if (on_device) {
+    launch_gather_values(c, A.ptrs(), nnz, A.b, vals, nullptr);
+  } else {
+    DBuf<double> tmp(c.pool, (size_t)nnz * A.b * A.b);
+    launch_gather_values(c, A.ptrs(), nnz, A.b, tmp.get(), nullptr);
+    LIF_HIP(hipMemcpyAsync(vals, tmp.get(), nnz * (size_t)A.b * A.b * sizeof(double), kind, c.stream));
+    c.sync();
+  }
   c.sync();
 }
 
@@ -85,20 +108,21 @@ Bsr copy(Ctx& c, const Bsr& A) {
   B.cap = A.bound();
   B.row_ptr = DBuf<int>(c.pool, A.nb + 1);
   B.col = DBuf<int>(c.pool, (size_t)B.cap);
-  B.val = DBuf<double>(c.pool, (size_t)B.cap * A.b * A.b);
+  B.blk = DBuf<const double*>(c.pool, (size_t)B.cap);
+  B.share_store(A);  // the value blocks are shared, never written again
   LIF_HIP(hipMemcpyAsync(B.row_ptr.get(), A.row_ptr.get(), (A.nb + 1) * sizeof(int), hipMemcpyDeviceToDevice,
                          c.stream));
   if (B.cap) {
     LIF_HIP(hipMemcpyAsync(B.col.get(), A.col.get(), B.cap * sizeof(int), hipMemcpyDeviceToDevice, c.stream));
-    LIF_HIP(hipMemcpyAsync(B.val.get(), A.val.get(), B.cap * (size_t)A.b * A.b * sizeof(double),
-                           hipMemcpyDeviceToDevice, c.stream));
+    LIF_HIP(hipMemcpyAsync(B.blk.get(), A.blk.get(), B.cap * sizeof(const double*), hipMemcpyDeviceToDevice,
+                           c.stream));
   }
   return B;
 }
 
 DBuf<double> block_norms(Ctx& c, const Bsr& A) {
   DBuf<double> nrm(c.pool, (size_t)A.bound());
-  launch_block_sumsq(c, A.val.get(), A.bound(), A.b, nrm.get(), true, A.live());
+  launch_block_sumsq(c, A.ptrs(), A.bound(), A.b, nrm.get(), true, A.live());
   return nrm;
 }
 
@@ -112,10 +136,10 @@ Bsr truncate(Ctx& c, Bsr&& A, const double* norms, double tau) {
   B.row_ptr = DBuf<int>(c.pool, A.nb + 1);
   launch_keep_count_scan(c, A.row_ptr.get(), norms, tau, A.nb, B.row_ptr.get());
   B.col = DBuf<int>(c.pool, (size_t)B.cap);
-  B.val = DBuf<double>(c.pool, (size_t)B.cap * A.b * A.b);
-  // A's count is exact here (a product output or a checked input)
-  launch_compact_gather(c, A.row_ptr.get(), A.nb, A.col.get(), norms, tau, B.row_ptr.get(), A.val.get(), A.bound(),
-                        A.b, B.col.get(), B.val.get());
+  B.blk = DBuf<const double*>(c.pool, (size_t)B.cap);
+  B.share_store(A);
+  launch_compact_gather(c, A.row_ptr.get(), A.nb, A.col.get(), norms, tau, B.row_ptr.get(), A.ptrs(), A.bound(),
+                        B.col.get(), B.blk.get());
   return B;
 }
 
@@ -148,8 +172,10 @@ Bsr transpose(Ctx& c, const Bsr& A) {
   T.cap = A.bound();
   T.row_ptr = std::move(v.own_rp);
   T.col = std::move(v.own_col);
-  T.val = DBuf<double>(c.pool, (size_t)T.cap * A.b * A.b);
-  launch_transpose_blocks(c, A.val.get(), v.own_idx.get(), T.cap, A.b, T.val.get(), T.live());
+  Store st = new_store(c, T.cap, A.b);
+  T.blk = DBuf<const double*>(c.pool, (size_t)T.cap);
+  T.store.push_back(st);
+  launch_transpose_blocks(c, A.ptrs(), v.own_idx.get(), T.cap, A.b, st->get(), T.blk.get(), T.live());
   return T;
 }
 
@@ -215,14 +241,16 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
   if (nnzc)
     launch_symbolic_fill(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, diag_on, C.b, C.n, nb, C.row_ptr.get(),
                          prp.get(), C.col.get(), seg.get(), pairs.get(), diag_on ? dflag.get() : nullptr);
-  C.val = DBuf<double>(c.pool, (size_t)nnzc * C.b * C.b);
+  Store st = new_store(c, nnzc, C.b);
+  C.blk = DBuf<const double*>(c.pool, (size_t)nnzc);
+  C.store.push_back(st);
   DBuf<double> nrm(c.pool, (size_t)nnzc);
   Epilogue epi;
   epi.dflag = diag_on ? dflag.get() : nullptr;
   epi.tau = tau;
   epi.gamma = gamma;
-  launch_numeric(c, prec, A.val.get(), B.val.get(), ta, tb, seg.get(), pairs.get(), nnzc, C.row_ptr.get() + nb, C.b,
-                 C.val.get(), nrm.get(), epi);
+  launch_numeric(c, prec, A.ptrs(), B.ptrs(), ta, tb, seg.get(), pairs.get(), nnzc, C.row_ptr.get() + nb, C.b,
+                 st->get(), C.blk.get(), nrm.get(), epi);
   return truncate(c, std::move(C), nrm.get(), tau);
 }
 
@@ -239,31 +267,47 @@ Bsr union_sum(Ctx& c, const Bsr* const src[3], const double coef[3], double gamm
   const int nb = C.nb;
   const int* rp[3];
   const int* col[3];
-  const double* val[3];
+  BlkIn val[3];
   int64_t cap = diag_on ? nb : 0;
+  // blocks that need new values: those of scaled operands, those present in
+  // two or more unscaled operands (at most their total minus the largest),
+  // and the identity's diagonal blocks; the rest are shared
+  int64_t computed = diag_on ? nb : 0, unit_sum = 0, unit_max = 0;
   for (int t = 0; t < 3; ++t) {
     rp[t] = src[t] ? src[t]->row_ptr.get() : nullptr;
     col[t] = src[t] ? src[t]->col.get() : nullptr;
-    val[t] = src[t] ? src[t]->val.get() : nullptr;
-    if (src[t]) cap += src[t]->bound();
+    val[t] = src[t] ? src[t]->ptrs() : nullptr;
+    if (!src[t]) continue;
+    cap += src[t]->bound();
+    if (coef[t] == 1.0) {
+      unit_sum += src[t]->bound();
+      unit_max = std::max(unit_max, src[t]->bound());
+    } else {
+      computed += src[t]->bound();
+    }
+    C.share_store(*src[t]);
   }
   cap = std::min<int64_t>(cap, (int64_t)nb * nb);
+  computed = std::min<int64_t>(computed + unit_sum - unit_max, cap);
   C.nnzb = -1;
   C.cap = cap;
   C.row_ptr = DBuf<int>(c.pool, nb + 1);
+  DBuf<int> slot(c.pool, 1);
   {
     DBuf<int> cnt(c.pool, nb);
-    launch_union3(c, rp, col, diag_on, nb, cnt.get());
+    launch_union3(c, rp, col, diag_on, nb, cnt.get(), slot.get());
     scan_exclusive_i32(c, cnt.get(), C.row_ptr.get(), nb);
   }
   C.col = DBuf<int>(c.pool, (size_t)cap);
   DBuf<int> ix(c.pool, (size_t)cap * 3), rowof(c.pool, (size_t)cap);
   DBuf<unsigned char> id(c.pool, (size_t)cap);
-  C.val = DBuf<double>(c.pool, (size_t)cap * C.b * C.b);
+  Store st = new_store(c, computed, C.b);
+  C.blk = DBuf<const double*>(c.pool, (size_t)cap);
+  C.store.push_back(st);
   if (cap) {
     launch_union3_fill(c, rp, col, diag_on, C.row_ptr.get(), nb, C.col.get(), ix.get(), cap, id.get(), rowof.get());
-    launch_axpby3_values(c, val, coef, ix.get(), cap, gamma, id.get(), rowof.get(), cap, C.b, C.n, C.val.get(),
-                         C.live());
+    launch_axpby3_values(c, val, coef, ix.get(), cap, gamma, id.get(), rowof.get(), cap, C.b, C.n, st->get(),
+                         slot.get(), C.blk.get(), C.live());
   }
   return C;
 }
@@ -292,11 +336,12 @@ Bsr filter(Ctx& c, const Bsr& A, const int* rlab, const int* clab, int mode) {
   launch_filter_count_scan(c, A.row_ptr.get(), A.col.get(), rlab, clab ? clab : rlab, mode, nb, C.row_ptr.get());
   C.col = DBuf<int>(c.pool, (size_t)C.cap);
   DBuf<int> src(c.pool, (size_t)C.cap);
-  C.val = DBuf<double>(c.pool, (size_t)C.cap * C.b * C.b);
+  C.blk = DBuf<const double*>(c.pool, (size_t)C.cap);
+  C.share_store(A);
   if (C.cap) {
     launch_filter_fill(c, A.row_ptr.get(), A.col.get(), rlab, clab ? clab : rlab, mode, C.row_ptr.get(), nb,
                        C.col.get(), src.get());
-    launch_gather_blocks(c, A.val.get(), src.get(), C.cap, C.b, C.val.get(), C.live());
+    launch_gather_ptrs(c, A.ptrs(), src.get(), C.cap, C.blk.get(), C.live());
   }
   return C;
 }
@@ -310,11 +355,12 @@ Bsr intersect(Ctx& c, const Bsr& A, const Bsr& R) {
   launch_intersect_count_scan(c, A.row_ptr.get(), A.col.get(), R.row_ptr.get(), R.col.get(), nb, C.row_ptr.get());
   C.col = DBuf<int>(c.pool, (size_t)C.cap);
   DBuf<int> src(c.pool, (size_t)C.cap);
-  C.val = DBuf<double>(c.pool, (size_t)C.cap * C.b * C.b);
+  C.blk = DBuf<const double*>(c.pool, (size_t)C.cap);
+  C.share_store(A);
   if (C.cap) {
     launch_intersect(c, A.row_ptr.get(), A.col.get(), R.row_ptr.get(), R.col.get(), nb, nullptr, C.row_ptr.get(),
                      C.col.get(), src.get());
-    launch_gather_blocks(c, A.val.get(), src.get(), C.cap, C.b, C.val.get(), C.live());
+    launch_gather_ptrs(c, A.ptrs(), src.get(), C.cap, C.blk.get(), C.live());
   }
   return C;
 }
@@ -327,14 +373,16 @@ Bsr phi_upper(Ctx& c, const Bsr& W) {
   Bsr U = filter(c, W, d_idx.get(), d_idx.get(), 3);
   DBuf<int> rowof(c.pool, (size_t)std::max<int64_t>(U.cap, 1));
   launch_block_row_of(c, U.row_ptr.get(), U.nb, U.cap, rowof.get());
-  launch_phi_diag(c, rowof.get(), U.col.get(), U.cap, U.b, U.val.get(), U.live());
+  Store st = new_store(c, U.nb, U.b);  // the new diagonal blocks, slot = block row
+  U.store.push_back(st);
+  launch_phi_diag(c, rowof.get(), U.col.get(), U.cap, U.b, st->get(), U.blk.get(), U.live());
   c.sync();  // idx goes out of scope
   return U;
 }
 
 double gershgorin(Ctx& c, const Bsr& A) {
   DBuf<double> rowmax(c.pool, A.nb), mx(c.pool, 1);
-  launch_gershgorin(c, A.row_ptr.get(), A.val.get(), A.nb, A.b, rowmax.get());
+  launch_gershgorin(c, A.row_ptr.get(), A.ptrs(), A.nb, A.b, rowmax.get());
   launch_max_reduce(c, rowmax.get(), A.nb, mx.get());
   return read1(c, mx.get());
 }
@@ -347,7 +395,7 @@ std::vector<double> node_sumsq(Ctx& c, const Bsr& A, const int* rlo, const int* 
     return out;
   }
   DBuf<double> ss(c.pool, (size_t)std::max<int64_t>(A.bound(), 1)), seg(c.pool, nseg);
-  launch_block_sumsq(c, A.val.get(), A.bound(), A.b, ss.get(), false, A.live());
+  launch_block_sumsq(c, A.ptrs(), A.bound(), A.b, ss.get(), false, A.live());
   launch_segment_sum(c, ss.get(), A.row_ptr.get(), rlo, rhi, nseg, seg.get());
   int na = 0;
   std::vector<Ctx::Read> reads;

@@ -184,10 +184,4 @@ void scan_exclusive_i32(Ctx& c, const int* in, int* out, int count) {
   LIF_HIP(hipGetLastError());
 }
 
-void scan_exclusive_i64(Ctx& c, const int64_t* in, int64_t* out, int count) {
-  hipLaunchKernelGGL(k_scan_exclusive<int64_t>, dim3(1), dim3(kScanThreads), 0, c.stream, in, out,
-                     count);
-  LIF_HIP(hipGetLastError());
-}
-
 }  // namespace lif

@@ -236,12 +236,11 @@ __device__ inline void mma_stage(const double* __restrict__ As, const double* __
 }
 
 template <int B, bool TA, bool TB>
-__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const double* __restrict__ A,
-                                                                     const double* __restrict__ Bm,
+__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(BlkIn A, BlkIn Bm,
                                                                      const int64_t* __restrict__ seg,
                                                                      const int2* __restrict__ pairs,
                                                                      const int* __restrict__ live,
-                                                                     double* __restrict__ C,
+                                                                     double* __restrict__ C, BlkOut Cp,
                                                                      double* __restrict__ norms, Epilogue epi) {
   using Cfg = TileCfg<B>;
   __shared__ double As[2][Cfg::LDS_DOUBLES];
@@ -265,15 +264,15 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const doubl
   if (p1 > p0) {  // a diagonal block of a fused identity term may have no products
     {
       const int2 pr = pairs[p0];
-      tile_load<B>(A + (int64_t)pr.x * B * B, ra);
-      tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
+      tile_load<B>(A[pr.x], ra);
+      tile_load<B>(Bm[pr.y], rbv);
     }
     tile_store<B>(As[0], ra, true);
     tile_store<B>(Bs[0], rbv, true);
     {
       const int2 pr = pairs[min(p0 + 1, plast)];
-      tile_load<B>(A + (int64_t)pr.x * B * B, ra);
-      tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
+      tile_load<B>(A[pr.x], ra);
+      tile_load<B>(Bm[pr.y], rbv);
     }
     int stage = 0;
     for (int64_t p = p0; p < p1; ++p) {
@@ -281,8 +280,8 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const doubl
       tile_store<B>(As[stage ^ 1], ra, true);
       tile_store<B>(Bs[stage ^ 1], rbv, true);
       const int2 pr = pairs[min(p + 2, plast)];
-      tile_load<B>(A + (int64_t)pr.x * B * B, ra);
-      tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
+      tile_load<B>(A[pr.x], ra);
+      tile_load<B>(Bm[pr.y], rbv);
       mma_stage<B, TA, TB>(As[stage], Bs[stage], f, acc);
       stage ^= 1;
     }
@@ -317,23 +316,25 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const doubl
         if (row == col && row < dr) v += epi.gamma;
         Cb[row * B + col] = v;
       }
-  if (threadIdx.x == 0) norms[blk] = dr ? INFINITY : nrm;
+  if (threadIdx.x == 0) {
+    norms[blk] = dr ? INFINITY : nrm;
+    Cp[blk] = Cb;
+  }
 }
 
 template <int B>
-void launch_numeric_b(Ctx& c, const double* A, const double* Bm, bool ta, bool tb, const int64_t* seg,
-                      const int2* pairs, int64_t nnzc, const int* live, double* C, double* norms,
-                      const Epilogue& epi) {
+void launch_numeric_b(Ctx& c, BlkIn A, BlkIn Bm, bool ta, bool tb, const int64_t* seg, const int2* pairs,
+                      int64_t nnzc, const int* live, double* C, BlkOut Cp, double* norms, const Epilogue& epi) {
   using Cfg = TileCfg<B>;
   dim3 grid((unsigned)nnzc), block(Cfg::THREADS);
   if (!ta && !tb)
-    hipLaunchKernelGGL((k_numeric_f64<B, false, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, norms, epi);
+    hipLaunchKernelGGL((k_numeric_f64<B, false, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, Cp, norms, epi);
   else if (ta && !tb)
-    hipLaunchKernelGGL((k_numeric_f64<B, true, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, norms, epi);
+    hipLaunchKernelGGL((k_numeric_f64<B, true, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, Cp, norms, epi);
   else if (!ta && tb)
-    hipLaunchKernelGGL((k_numeric_f64<B, false, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, norms, epi);
+    hipLaunchKernelGGL((k_numeric_f64<B, false, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, Cp, norms, epi);
   else
-    hipLaunchKernelGGL((k_numeric_f64<B, true, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, norms, epi);
+    hipLaunchKernelGGL((k_numeric_f64<B, true, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, Cp, norms, epi);
   LIF_HIP(hipGetLastError());
 }
 
@@ -366,9 +367,8 @@ void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* ai
   LIF_HIP(hipGetLastError());
 }
 
-void launch_numeric(Ctx& c, int prec, const double* A, const double* B, bool ta, bool tb, const int64_t* seg,
-                    const int2* pairs, int64_t nnzc, const int* live, int b, double* C, double* norms,
-                    const Epilogue& epi) {
+void launch_numeric(Ctx& c, int prec, BlkIn A, BlkIn B, bool ta, bool tb, const int64_t* seg, const int2* pairs,
+                    int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms, const Epilogue& epi) {
   if (nnzc == 0) return;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c.timing) {
@@ -377,11 +377,11 @@ void launch_numeric(Ctx& c, int prec, const double* A, const double* B, bool ta,
     LIF_HIP(hipEventRecord(e0, c.stream));
   }
   if (prec != LIF_FP64)
-    launch_numeric_mixed(c, prec, A, B, ta, tb, seg, pairs, nnzc, live, b, C, norms, epi);
+    launch_numeric_mixed(c, prec, A, B, ta, tb, seg, pairs, nnzc, live, b, C, Cp, norms, epi);
   else if (b == 64)
-    launch_numeric_b<64>(c, A, B, ta, tb, seg, pairs, nnzc, live, C, norms, epi);
+    launch_numeric_b<64>(c, A, B, ta, tb, seg, pairs, nnzc, live, C, Cp, norms, epi);
   else
-    launch_numeric_b<32>(c, A, B, ta, tb, seg, pairs, nnzc, live, C, norms, epi);
+    launch_numeric_b<32>(c, A, B, ta, tb, seg, pairs, nnzc, live, C, Cp, norms, epi);
   if (c.timing) {
     LIF_HIP(hipEventRecord(e1, c.stream));
     c.ev_pending.emplace_back(e0, e1);

@@ -122,12 +122,11 @@ __device__ inline void epilogue(const v4f (&acc)[2][2], int rb, int cb, int l16,
 }
 
 template <int B, bool TA, bool TB>
-__global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(const double* __restrict__ A,
-                                                                    const double* __restrict__ Bm,
+__global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(BlkIn A, BlkIn Bm,
                                                                     const int64_t* __restrict__ seg,
                                                                     const int2* __restrict__ pairs,
                                                                     const int* __restrict__ live,
-                                                                    double* __restrict__ C,
+                                                                    double* __restrict__ C, BlkOut Cp,
                                                                     double* __restrict__ norms, Epilogue epi) {
   using Cfg = MixCfg<B>;
   __shared__ float As[B * Cfg::LDF];
@@ -150,8 +149,8 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(const double
   v2d ra[Cfg::V2], rbv[Cfg::V2];
   if (p1 > p0) {  // a diagonal block of a fused identity term may have no products
     const int2 pr = pairs[p0];
-    tile_load<B>(A + (int64_t)pr.x * B * B, ra);
-    tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
+    tile_load<B>(A[pr.x], ra);
+    tile_load<B>(Bm[pr.y], rbv);
   }
   for (int64_t p = p0; p < p1; ++p) {
     __syncthreads();
@@ -160,8 +159,8 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(const double
     __syncthreads();
     if (p + 1 < p1) {
       const int2 pr = pairs[p + 1];
-      tile_load<B>(A + (int64_t)pr.x * B * B, ra);
-      tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
+      tile_load<B>(A[pr.x], ra);
+      tile_load<B>(Bm[pr.y], rbv);
     }
 #pragma unroll 4
     for (int kk = 0; kk < B / 4; ++kk) {
@@ -178,15 +177,15 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(const double
   }
   epilogue<B>(acc, rb, cb, l16, kq, lane, wave, C + blk * B * B, red, norms + blk, epi.dflag ? epi.dflag[blk] : 0,
               epi);
+  if (threadIdx.x == 0) Cp[blk] = C + blk * B * B;
 }
 
 template <int B, bool TA, bool TB>
-__global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(const double* __restrict__ A,
-                                                                     const double* __restrict__ Bm,
+__global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(BlkIn A, BlkIn Bm,
                                                                      const int64_t* __restrict__ seg,
                                                                      const int2* __restrict__ pairs,
                                                                      const int* __restrict__ live,
-                                                                     double* __restrict__ C,
+                                                                     double* __restrict__ C, BlkOut Cp,
                                                                      double* __restrict__ norms, Epilogue epi) {
   using Cfg = MixCfg<B>;
   __shared__ __attribute__((aligned(16))) unsigned short As[B * Cfg::LDH];  // As[i][k]
@@ -209,8 +208,8 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(const doubl
   v2d ra[Cfg::V2], rbv[Cfg::V2];
   if (p1 > p0) {  // a diagonal block of a fused identity term may have no products
     const int2 pr = pairs[p0];
-    tile_load<B>(A + (int64_t)pr.x * B * B, ra);
-    tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
+    tile_load<B>(A[pr.x], ra);
+    tile_load<B>(Bm[pr.y], rbv);
   }
   for (int64_t p = p0; p < p1; ++p) {
     __syncthreads();
@@ -219,8 +218,8 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(const doubl
     __syncthreads();
     if (p + 1 < p1) {
       const int2 pr = pairs[p + 1];
-      tile_load<B>(A + (int64_t)pr.x * B * B, ra);
-      tile_load<B>(Bm + (int64_t)pr.y * B * B, rbv);
+      tile_load<B>(A[pr.x], ra);
+      tile_load<B>(Bm[pr.y], rbv);
     }
 #pragma unroll
     for (int kk = 0; kk < B / 32; ++kk) {
@@ -237,26 +236,27 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(const doubl
   }
   epilogue<B>(acc, rb, cb, l16, kq, lane, wave, C + blk * B * B, red, norms + blk, epi.dflag ? epi.dflag[blk] : 0,
               epi);
+  if (threadIdx.x == 0) Cp[blk] = C + blk * B * B;
 }
 
 #define LIF_MIXED_DISPATCH(KERNEL, B)                                                                      \
   do {                                                                                                     \
     dim3 grid((unsigned)nnzc), block(MixCfg<B>::THREADS);                                                  \
     if (!ta && !tb)                                                                                        \
-      hipLaunchKernelGGL((KERNEL<B, false, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, norms, epi); \
+      hipLaunchKernelGGL((KERNEL<B, false, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, Cp, norms, epi); \
     else if (ta && !tb)                                                                                    \
-      hipLaunchKernelGGL((KERNEL<B, true, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, norms, epi); \
+      hipLaunchKernelGGL((KERNEL<B, true, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, Cp, norms, epi); \
     else if (!ta && tb)                                                                                    \
-      hipLaunchKernelGGL((KERNEL<B, false, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, norms, epi); \
+      hipLaunchKernelGGL((KERNEL<B, false, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, Cp, norms, epi); \
     else                                                                                                   \
-      hipLaunchKernelGGL((KERNEL<B, true, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, norms, epi); \
+      hipLaunchKernelGGL((KERNEL<B, true, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, Cp, norms, epi); \
   } while (0)
 
 }  // namespace
 
-void launch_numeric_mixed(Ctx& c, int prec, const double* A, const double* Bm, bool ta, bool tb,
-                          const int64_t* seg, const int2* pairs, int64_t nnzc, const int* live, int b, double* C,
-                          double* norms, const Epilogue& epi) {
+void launch_numeric_mixed(Ctx& c, int prec, BlkIn A, BlkIn Bm, bool ta, bool tb, const int64_t* seg,
+                          const int2* pairs, int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms,
+                          const Epilogue& epi) {
   if (prec == LIF_MIXED_FP32) {
     if (b == 64)
       LIF_MIXED_DISPATCH(k_numeric_f32, 64);
