@@ -18,6 +18,34 @@ namespace {
 
 constexpr int kWG = 256;
 
+// A b x b block handled by 256 threads: each thread holds V2 consecutive
+// double pairs.  The loads of a block are all issued before the first use
+// (unrolled over V2), so a block costs one memory latency, not V2 of them.
+template <int B>
+struct Blk {
+  static constexpr int V2 = B * B / 2 / kWG;
+};
+
+template <int B>
+__device__ __attribute__((always_inline)) inline void blk_load(const double* __restrict__ p, v2d (&r)[Blk<B>::V2]) {
+  const v2d* q = reinterpret_cast<const v2d*>(p);
+#pragma unroll
+  for (int v = 0; v < Blk<B>::V2; ++v) r[v] = q[threadIdx.x + v * kWG];
+}
+
+template <int B>
+__device__ __attribute__((always_inline)) inline void blk_store(double* __restrict__ p, const v2d (&r)[Blk<B>::V2]) {
+  v2d* q = reinterpret_cast<v2d*>(p);
+#pragma unroll
+  for (int v = 0; v < Blk<B>::V2; ++v) q[threadIdx.x + v * kWG] = r[v];
+}
+
+// element index (row-major in the block) of the first double of pair v
+template <int B>
+__device__ __attribute__((always_inline)) inline int blk_elem(int v) {
+  return 2 * (threadIdx.x + v * kWG);
+}
+
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
@@ -48,19 +76,19 @@ __global__ void k_row_ptr_from_rows(const int* __restrict__ brow, int64_t nnzb, 
   for (int r = prev + 1; r <= cur; ++r) rp[r] = (int)e;
 }
 
-__global__ __launch_bounds__(kWG) void k_block_sumsq(BlkIn blk, int64_t nnzb, int bb, double* __restrict__ out,
+template <int B>
+__global__ __launch_bounds__(kWG) void k_block_sumsq(BlkIn blk, int64_t nnzb, double* __restrict__ out,
                                                      int take_sqrt, const int* __restrict__ live) {
   __shared__ double sh[4];
   const int64_t e = blockIdx.x;
   if (live && e >= *live) return;
-  const double2* p = reinterpret_cast<const double2*>(blk[e]);
+  v2d r[Blk<B>::V2];
+  blk_load<B>(blk[e], r);
   double s = 0.0;
-  for (int i = threadIdx.x; i < bb / 2; i += kWG) {
-    double2 v = p[i];
-    s += v.x * v.x + v.y * v.y;
-  }
-  double r = block_sum_256(s, sh);
-  if (threadIdx.x == 0) out[e] = take_sqrt ? sqrt(r) : r;
+#pragma unroll
+  for (int v = 0; v < Blk<B>::V2; ++v) s += r[v].x * r[v].x + r[v].y * r[v].y;
+  double t = block_sum_256(s, sh);
+  if (threadIdx.x == 0) out[e] = take_sqrt ? sqrt(t) : t;
 }
 
 __global__ void k_gather_ptrs(BlkIn blk, const int* __restrict__ src, int64_t nnzb, BlkOut out,
@@ -77,13 +105,14 @@ __global__ void k_fill_ptrs(BlkOut out, const double* base, int bb, int64_t coun
 }
 
 // contiguous copy of the blocks (block e to out + e bb)
-__global__ __launch_bounds__(kWG) void k_gather_values(BlkIn blk, int bb, double* __restrict__ out,
+template <int B>
+__global__ __launch_bounds__(kWG) void k_gather_values(BlkIn blk, double* __restrict__ out,
                                                        const int* __restrict__ live) {
   const int64_t e = blockIdx.x;
   if (live && e >= *live) return;
-  const v2d* s = reinterpret_cast<const v2d*>(blk[e]);
-  v2d* d = reinterpret_cast<v2d*>(out + e * (int64_t)bb);
-  for (int i = threadIdx.x; i < bb / 2; i += kWG) d[i] = s[i];
+  v2d r[Blk<B>::V2];
+  blk_load<B>(blk[e], r);
+  blk_store<B>(out + e * B * B, r);
 }
 
 // Gershgorin: row_max[i] = max over the b scalar rows of block row i of
@@ -190,54 +219,65 @@ struct Val3 {
 // Every other block is computed into the next free slot of `store` (slots
 // are handed out by an atomic counter; where a block lands does not change
 // its value).
+template <int B>
 __global__ __launch_bounds__(kWG) void k_axpby_values(Val3 V, const int* __restrict__ ix, int64_t stride,
                                                       double gamma, const unsigned char* __restrict__ id,
-                                                      const int* __restrict__ row_of, int b, int64_t n,
+                                                      const int* __restrict__ row_of, int64_t n,
                                                       double* __restrict__ store, int* __restrict__ slot,
                                                       BlkOut out, const int* __restrict__ live) {
   __shared__ int my_slot;
   const int64_t e = blockIdx.x;
   if (live && e >= *live) return;
-  const int bb = b * b;
-  const double2* src[3];
+  const double* src[3];
   double cf[3];
   int ns = 0;
 #pragma unroll
   for (int t = 0; t < 3; ++t) {
     const int x = V.v[t] ? ix[t * stride + e] : -1;
     if (x >= 0) {
-      src[ns] = reinterpret_cast<const double2*>(V.v[t][x]);
+      src[ns] = V.v[t][x];
       cf[ns] = V.coef[t];
       ++ns;
     }
   }
   const bool dg = id[e] != 0;
   if (ns == 1 && cf[0] == 1.0 && !dg) {
-    if (threadIdx.x == 0) out[e] = reinterpret_cast<const double*>(src[0]);
+    if (threadIdx.x == 0) out[e] = src[0];
     return;
   }
   if (threadIdx.x == 0) my_slot = atomicAdd(slot, 1);
-  __syncthreads();
-  double* dst = store + (int64_t)my_slot * bb;
-  const int64_t row0 = (int64_t)row_of[e] * b;
-  double2* po = reinterpret_cast<double2*>(dst);
-  for (int q = threadIdx.x; q < bb / 2; q += kWG) {
-    double2 r = make_double2(0.0, 0.0);
-    for (int t = 0; t < ns; ++t) {
-      const double2 v = src[t][q];
-      r.x += cf[t] * v.x;
-      r.y += cf[t] * v.y;
-    }
-    if (dg) {
-      const int lin = 2 * q;
-      const int rr = lin / b, c0 = lin % b;
+  // all operand loads in flight before the first use; the sum keeps the
+  // operand order: ((0 + c0 v0) + c1 v1) + c2 v2
+  v2d r[3][Blk<B>::V2];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+    if (t < ns) blk_load<B>(src[t], r[t]);
+  v2d acc[Blk<B>::V2];
+#pragma unroll
+  for (int v = 0; v < Blk<B>::V2; ++v) {
+    acc[v] = v2d{0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+      if (t < ns) {
+        acc[v].x += cf[t] * r[t][v].x;
+        acc[v].y += cf[t] * r[t][v].y;
+      }
+  }
+  if (dg) {
+    const int64_t row0 = (int64_t)row_of[e] * B;
+#pragma unroll
+    for (int v = 0; v < Blk<B>::V2; ++v) {
+      const int lin = blk_elem<B>(v);
+      const int rr = lin / B, c0 = lin % B;
       if (row0 + rr < n) {
-        if (c0 == rr) r.x += gamma;
-        if (c0 + 1 == rr) r.y += gamma;
+        if (c0 == rr) acc[v].x += gamma;
+        if (c0 + 1 == rr) acc[v].y += gamma;
       }
     }
-    po[q] = r;
   }
+  __syncthreads();
+  double* dst = store + (int64_t)my_slot * B * B;
+  blk_store<B>(dst, acc);
   if (threadIdx.x == 0) out[e] = dst;
 }
 
@@ -324,23 +364,29 @@ __global__ __launch_bounds__(kWG) void k_transpose_sort(const int* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(kWG) void k_transpose_blocks(BlkIn blk, const int* __restrict__ src, int b,
+template <int B>
+__global__ __launch_bounds__(kWG) void k_transpose_blocks(BlkIn blk, const int* __restrict__ src,
                                                           double* __restrict__ store, BlkOut out,
                                                           const int* __restrict__ live) {
-  __shared__ double t[64 * 65];
+  __shared__ double t[B * (B + 1)];
   const int64_t e = blockIdx.x;
   if (live && e >= *live) return;
-  const double* s = blk[src[e]];
-  double* d = store + e * (int64_t)b * b;
-  for (int q = threadIdx.x; q < b * b; q += kWG) {
-    int r = q / b, cc = q % b;
-    t[r * 65 + cc] = s[q];
+  v2d r[Blk<B>::V2];
+  blk_load<B>(blk[src[e]], r);
+#pragma unroll
+  for (int v = 0; v < Blk<B>::V2; ++v) {
+    const int q = blk_elem<B>(v), rr = q / B, cc = q % B;
+    t[cc * (B + 1) + rr] = r[v].x;
+    t[(cc + 1) * (B + 1) + rr] = r[v].y;
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < b * b; q += kWG) {
-    int r = q / b, cc = q % b;
-    d[q] = t[cc * 65 + r];
+#pragma unroll
+  for (int v = 0; v < Blk<B>::V2; ++v) {
+    const int q = blk_elem<B>(v), rr = q / B, cc = q % B;
+    r[v] = v2d{t[rr * (B + 1) + cc], t[rr * (B + 1) + cc + 1]};
   }
+  double* d = store + e * B * B;
+  blk_store<B>(d, r);
   if (threadIdx.x == 0) out[e] = d;
 }
 
@@ -389,21 +435,26 @@ __global__ void k_intersect_counts(const int* __restrict__ ra, const int* __rest
 // blocks keep their upper triangle with the diagonal halved (written to slot
 // `row` of `store`, the pointer redirected there); other blocks are left as
 // they are (the caller keeps only blocks with col >= row).
+template <int B>
 __global__ __launch_bounds__(kWG) void k_phi_diag(const int* __restrict__ row_of, const int* __restrict__ col,
-                                                  int b, double* __restrict__ store, BlkOut blk,
+                                                  double* __restrict__ store, BlkOut blk,
                                                   const int* __restrict__ live) {
   const int64_t e = blockIdx.x;
   if (live && e >= *live) return;
   const int i = row_of[e];
   if (i != col[e]) return;
-  const double* s = blk[e];
-  double* v = store + (int64_t)i * b * b;
-  for (int q = threadIdx.x; q < b * b; q += kWG) {
-    const int r = q / b, cc = q % b;
-    v[q] = (cc < r) ? 0.0 : (cc == r ? 0.5 * s[q] : s[q]);
+  v2d r[Blk<B>::V2];
+  blk_load<B>(blk[e], r);
+#pragma unroll
+  for (int v = 0; v < Blk<B>::V2; ++v) {
+    const int q = blk_elem<B>(v), rr = q / B, cc = q % B;
+    r[v].x = (cc < rr) ? 0.0 : (cc == rr ? 0.5 * r[v].x : r[v].x);
+    r[v].y = (cc + 1 < rr) ? 0.0 : (cc + 1 == rr ? 0.5 * r[v].y : r[v].y);
   }
+  double* d = store + (int64_t)i * B * B;
+  blk_store<B>(d, r);
   __syncthreads();  // every read of the old block done before the pointer moves
-  if (threadIdx.x == 0) blk[e] = v;
+  if (threadIdx.x == 0) blk[e] = d;
 }
 
 // ---------------------------------------------------------------------------
@@ -530,8 +581,12 @@ void launch_row_ptr_from_rows(Ctx& c, const int* brow, int64_t nnzb, int nb, int
 
 void launch_block_sumsq(Ctx& c, BlkIn blk, int64_t nnzb, int b, double* out, bool take_sqrt, const int* live) {
   if (nnzb == 0) return;
-  LIF_LAUNCH(k_block_sumsq, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, blk, nnzb, b * b, out, take_sqrt ? 1 : 0,
-             live);
+  if (b == 64)
+    LIF_LAUNCH(k_block_sumsq<64>, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, blk, nnzb, out, take_sqrt ? 1 : 0,
+               live);
+  else
+    LIF_LAUNCH(k_block_sumsq<32>, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, blk, nnzb, out, take_sqrt ? 1 : 0,
+               live);
 }
 
 void launch_gather_ptrs(Ctx& c, BlkIn blk, const int* src, int64_t nnzb, BlkOut out, const int* live) {
@@ -546,7 +601,10 @@ void launch_fill_ptrs(Ctx& c, BlkOut out, const double* base, int b, int64_t cou
 
 void launch_gather_values(Ctx& c, BlkIn blk, int64_t nnzb, int b, double* out, const int* live) {
   if (nnzb == 0) return;
-  LIF_LAUNCH(k_gather_values, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, blk, b * b, out, live);
+  if (b == 64)
+    LIF_LAUNCH(k_gather_values<64>, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, blk, out, live);
+  else
+    LIF_LAUNCH(k_gather_values<32>, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, blk, out, live);
 }
 
 void launch_gershgorin(Ctx& c, const int* row_ptr, BlkIn blk, int nb, int b, double* row_max) {
@@ -611,8 +669,12 @@ void launch_axpby3_values(Ctx& c, const BlkIn v[3], const double coef[3], const 
     V.v[t] = v[t];
     V.coef[t] = coef[t];
   }
-  LIF_LAUNCH(k_axpby_values, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, V, ix, stride, gamma, id, row_of, b, n,
-             store, slot, out, live);
+  if (b == 64)
+    LIF_LAUNCH(k_axpby_values<64>, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, V, ix, stride, gamma, id, row_of,
+               n, store, slot, out, live);
+  else
+    LIF_LAUNCH(k_axpby_values<32>, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, V, ix, stride, gamma, id, row_of,
+               n, store, slot, out, live);
 }
 
 void launch_block_row_of(Ctx& c, const int* row_ptr, int nb, int64_t nnzb, int* row_of) {
@@ -644,7 +706,10 @@ void launch_transpose_sort(Ctx& c, const int* tptr, int nb, const int* icol, con
 void launch_transpose_blocks(Ctx& c, BlkIn blk, const int* src, int64_t nnzb, int b, double* store, BlkOut out,
                              const int* live) {
   if (nnzb == 0) return;
-  LIF_LAUNCH(k_transpose_blocks, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, blk, src, b, store, out, live);
+  if (b == 64)
+    LIF_LAUNCH(k_transpose_blocks<64>, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, blk, src, store, out, live);
+  else
+    LIF_LAUNCH(k_transpose_blocks<32>, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, blk, src, store, out, live);
 }
 
 void launch_segment_sum(Ctx& c, const double* sumsq, const int* row_ptr, const int* rlo, const int* rhi, int nseg,
@@ -662,7 +727,10 @@ void launch_intersect(Ctx& c, const int* ra, const int* ca, const int* rr, const
 void launch_phi_diag(Ctx& c, const int* row_of, const int* col, int64_t nnzb, int b, double* store, BlkOut blk,
                      const int* live) {
   if (nnzb == 0) return;
-  LIF_LAUNCH(k_phi_diag, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, row_of, col, b, store, blk, live);
+  if (b == 64)
+    LIF_LAUNCH(k_phi_diag<64>, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, row_of, col, store, blk, live);
+  else
+    LIF_LAUNCH(k_phi_diag<32>, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, row_of, col, store, blk, live);
 }
 
 void launch_fill_i32(Ctx& c, int* p, int value, int64_t count) {

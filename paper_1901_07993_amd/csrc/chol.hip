@@ -12,9 +12,11 @@
 // Blocked right-looking Cholesky, one host step per tile column k:
 //   potrf  U_kk = chol(S_kk) in LDS, and Z_kk = U_kk^{-1}   (one WG per leaf)
 //   trsm   U_kj = Z_kk^T S_kj, j > k                          (WG per tile)
+//          and V_ik = U_ik Z_kk, i < k, in place of U_ik (no later step
+//          reads U_ik)
 //   update S_ij -= U_ki^T U_kj, k < i <= j                    (WG per tile)
 // then the inverse by tile columns j:
-//   Z_ij = -(sum_{k=i}^{j-1} Z_ik U_kj) Z_jj, i < j
+//   Z_ij = -(sum_{k=i}^{j-1} Z_ik U_kj) Z_jj = -sum_{k=i}^{j-1} Z_ik V_kj, i < j
 // Tile products run on FP64 MFMA (tile_mma.h).  Padded rows of the last
 // leaf carry a unit diagonal during the factorization and are zeroed after.
 // A byte per packed tile records whether the tile of S / U can be nonzero:
@@ -44,9 +46,15 @@ __global__ __launch_bounds__(256) void k_chol_scatter(const int* __restrict__ ro
   if (s < 0 || base_of_row[J] != s || J < I) return;
   const int i = I - blk0[s], j = J - blk0[s];
   const int64_t t = packed_tile(tile0[s], nbbv[s], i, j);
-  const double2* src = reinterpret_cast<const double2*>(val[e]);
-  double2* dst = reinterpret_cast<double2*>(U + t * (int64_t)b * b);
-  for (int q = threadIdx.x; q < b * b / 2; q += 256) dst[q] = src[q];
+  const v2d* src = reinterpret_cast<const v2d*>(val[e]);
+  v2d* dst = reinterpret_cast<v2d*>(U + t * (int64_t)b * b);
+  v2d r[8];  // b * b / 2 / 256 <= 8 pairs per thread, all loads issued first
+#pragma unroll
+  for (int v = 0; v < 8; ++v)
+    if (threadIdx.x + v * 256 < b * b / 2) r[v] = src[threadIdx.x + v * 256];
+#pragma unroll
+  for (int v = 0; v < 8; ++v)
+    if (threadIdx.x + v * 256 < b * b / 2) dst[threadIdx.x + v * 256] = r[v];
   if (threadIdx.x == 0) {
     nz[t] = 1;
     atomicMax(band, j - i);
@@ -101,7 +109,20 @@ __global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nb
   if (k >= nbb) return;
   const int64_t t = packed_tile(tile0[s], nbb, k, k);
   double* g = U + t * B * B;
-  for (int q = threadIdx.x; q < B * B; q += 256) T[(q / B) * L + (q % B)] = g[q];
+  {
+    // all loads of the tile in flight before the first LDS store
+    constexpr int NV = B * B / 2 / 256;
+    v2d r[NV];
+    const v2d* gv = reinterpret_cast<const v2d*>(g);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) r[v] = gv[threadIdx.x + v * 256];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int q = 2 * (threadIdx.x + v * 256);
+      T[(q / B) * L + (q % B)] = r[v].x;
+      T[(q / B) * L + (q % B) + 1] = r[v].y;
+    }
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
@@ -211,17 +232,20 @@ __global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nb
   }
   if (threadIdx.x == 0 && bad >= 0) atomicMin(&err[s], (blk0[s] + k) * B + bad);
   double* gz = Z + t * B * B;
-  for (int q = threadIdx.x; q < B * B; q += 256) {
-    const int r = q / B, cc = q % B;
-    g[q] = (cc >= r) ? T[r * L + cc] : 0.0;
-    gz[q] = (cc >= r) ? W[r * L + cc] : 0.0;
+#pragma unroll
+  for (int v = 0; v < B * B / 2 / 256; ++v) {
+    const int q = 2 * (threadIdx.x + v * 256), r = q / B, cc = q % B;
+    reinterpret_cast<v2d*>(g)[q / 2] = v2d{(cc >= r) ? T[r * L + cc] : 0.0, (cc + 1 >= r) ? T[r * L + cc + 1] : 0.0};
+    reinterpret_cast<v2d*>(gz)[q / 2] =
+        v2d{(cc >= r) ? W[r * L + cc] : 0.0, (cc + 1 >= r) ? W[r * L + cc + 1] : 0.0};
   }
 }
 
-// U_kj = Z_kk^T U_kj for j = k + 1 + blockIdx.x (j - k <= band: the grid
-// covers the band only)
+// blockIdx.x < m: U_kj = Z_kk^T U_kj for j = k + 1 + blockIdx.x (j - k <=
+// band: the grid covers the band only); blockIdx.x >= m: V_ik = U_ik Z_kk for
+// i = max(0, k - band) + (blockIdx.x - m) < k, written over U_ik
 template <int B>
-__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trsm(int k, const int* __restrict__ nbbv,
+__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trsm(int k, int m, int band, const int* __restrict__ nbbv,
                                                               const int64_t* __restrict__ tile0,
                                                               double* __restrict__ U, const double* __restrict__ Z,
                                                               const unsigned char* __restrict__ nz) {
@@ -230,15 +254,28 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trsm(int k, const int* 
   __shared__ double Bs[Cfg::LDS_DOUBLES];
   const int s = blockIdx.y;
   const int nbb = nbbv[s];
-  const int j = k + 1 + blockIdx.x;
-  if (j >= nbb || !nz[packed_tile(tile0[s], nbb, k, j)]) return;
+  if (k >= nbb) return;
+  const bool vtask = (int)blockIdx.x >= m;
+  const int j = k + 1 + blockIdx.x;            // U task column
+  const int i = max(0, k - band) + ((int)blockIdx.x - m);  // V task row
+  if (vtask ? (i < 0 || !nz[packed_tile(tile0[s], nbb, i, k)])
+            : (j >= nbb || !nz[packed_tile(tile0[s], nbb, k, j)]))
+    return;
   const Frag f = frag_coords<B>();
   v2d reg[Cfg::V2];
-  tile_load<B>(Z + packed_tile(tile0[s], nbb, k, k) * B * B, reg);
-  tile_store<B>(As, reg, true);  // op(A) = Z_kk^T: LDS row k is row k of Z_kk
-  double* g = U + packed_tile(tile0[s], nbb, k, j) * B * B;
-  tile_load<B>(g, reg);
-  tile_store<B>(Bs, reg, true);
+  double* g = U + (vtask ? packed_tile(tile0[s], nbb, i, k) : packed_tile(tile0[s], nbb, k, j)) * B * B;
+  const double* zkk = Z + packed_tile(tile0[s], nbb, k, k) * B * B;
+  if (vtask) {
+    tile_load<B>(g, reg);
+    tile_store<B>(As, reg, false);  // op(A) = U_ik: LDS row c is column c of U_ik
+    tile_load<B>(zkk, reg);
+    tile_store<B>(Bs, reg, true);
+  } else {
+    tile_load<B>(zkk, reg);
+    tile_store<B>(As, reg, true);  // op(A) = Z_kk^T: LDS row k is row k of Z_kk
+    tile_load<B>(g, reg);
+    tile_store<B>(Bs, reg, true);
+  }
   __syncthreads();
   v4d acc[2][2];
   acc_zero(acc);
@@ -301,12 +338,12 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_update(int k, int band,
   if (threadIdx.x == 0) nz[packed_tile(tile0[s], nbb, i, j)] = 1;
 }
 
-// Z_ij = -(sum_{k=i}^{j-1} Z_ik U_kj) Z_jj for i = blockIdx.x < j; U_kj = 0
-// for k < j - band
+// Z_ij = -sum_{k=i}^{j-1} Z_ik V_kj for i = blockIdx.x < j, V_kj = U_kj Z_jj
+// (held in U's place); V_kj = 0 for k < j - band
 template <int B>
 __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, int band, const int* __restrict__ nbbv,
                                                                const int64_t* __restrict__ tile0,
-                                                               const double* __restrict__ U,
+                                                               const double* __restrict__ V,
                                                                double* __restrict__ Z,
                                                                const unsigned char* __restrict__ nz) {
   using Cfg = TileCfg<B>;
@@ -321,7 +358,7 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, int band, 
   v4d acc[2][2];
   acc_zero(acc);
   v2d ra[Cfg::V2], rb[Cfg::V2];
-  // k with U_kj != 0, visited in ascending order; the next pair's tiles are
+  // k with V_kj != 0, visited in ascending order; the next pair's tiles are
   // loaded into registers while the current one is multiplied
   auto next_k = [&](int k) {
     while (k < j && !nz[packed_tile(t0, nbb, k, j)]) ++k;
@@ -330,7 +367,7 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, int band, 
   int k = next_k(max(i, j - band));
   if (k >= j) return;  // Z_ij = 0 (the buffer starts zeroed)
   tile_load<B>(Z + packed_tile(t0, nbb, i, k) * B * B, ra);
-  tile_load<B>(U + packed_tile(t0, nbb, k, j) * B * B, rb);
+  tile_load<B>(V + packed_tile(t0, nbb, k, j) * B * B, rb);
   while (k < j) {
     __syncthreads();
     tile_store<B>(As, ra, false);  // op(A) = Z_ik
@@ -339,24 +376,11 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, int band, 
     const int kn = next_k(k + 1);
     if (kn < j) {
       tile_load<B>(Z + packed_tile(t0, nbb, i, kn) * B * B, ra);
-      tile_load<B>(U + packed_tile(t0, nbb, kn, j) * B * B, rb);
+      tile_load<B>(V + packed_tile(t0, nbb, kn, j) * B * B, rb);
     }
     tile_mma<B>(As, Bs, f, acc);
     k = kn;
   }
-  __syncthreads();
-  // W (accumulators) becomes the A operand: LDS row c holds column c of W
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) As[acc_col(f, tj) * Cfg::LD + acc_row(f, ti, r)] = acc[ti][tj][r];
-  tile_load<B>(Z + packed_tile(t0, nbb, j, j) * B * B, rb);
-  tile_store<B>(Bs, rb, true);
-  __syncthreads();
-  acc_zero(acc);
-  tile_mma<B>(As, Bs, f, acc);
   double* g = Z + packed_tile(t0, nbb, i, j) * B * B;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
@@ -397,13 +421,14 @@ void launch_potrf(Ctx& c, int k, int nbase, const int* nbb, const int* blk0, con
 
 void launch_trsm(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b,
                  double* U, const double* Z, const unsigned char* nz) {
-  const int m = std::min(band, max_nbb - k - 1);
-  if (m <= 0) return;
-  dim3 grid(m, nbase);
+  const int m = std::max(0, std::min(band, max_nbb - k - 1));
+  const int nv = std::min(band, k);
+  if (m + nv <= 0) return;
+  dim3 grid(m + nv, nbase);
   if (b == 64)
-    LIF_LAUNCH(k_trsm<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, k, nbb, tile0, U, Z, nz);
+    LIF_LAUNCH(k_trsm<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, k, m, band, nbb, tile0, U, Z, nz);
   else
-    LIF_LAUNCH(k_trsm<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, k, nbb, tile0, U, Z, nz);
+    LIF_LAUNCH(k_trsm<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, k, m, band, nbb, tile0, U, Z, nz);
 }
 
 void launch_update(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b,

@@ -114,6 +114,12 @@ typedef const double* const* BlkIn;
 typedef const double** BlkOut;
 typedef std::shared_ptr<DBuf<double>> Store;
 
+// The two operand blocks of one block product of a sparse product.
+struct BlockPair {
+  const double* a;
+  const double* b;
+};
+
 struct Bsr {
   int64_t n = 0;
   int b = 0;
@@ -175,6 +181,7 @@ struct Ctx {
     bool on = false, record = false;
     size_t next = 0;
     std::vector<std::array<int64_t, 2>> caps, seen;
+    std::vector<std::array<int64_t, 2>> prev;  // true counts behind caps
     std::vector<int> prec;  // precision of each sized-in-advance product
     DBuf<int64_t> sizes;
     DBuf<int> overflow;
@@ -184,6 +191,12 @@ struct Ctx {
   std::vector<hipEvent_t> ev_free;
 
   hipEvent_t take_event();
+  // a second stream (default priority) for work that may overlap the main
+  // stream's, ordered against it with events; created on first use
+  hipStream_t side = nullptr;
+  std::vector<hipEvent_t> order_events;
+  hipStream_t side_stream();
+  hipEvent_t order_event(size_t i);  // the i-th reusable ordering event
   void flush_timing();
   void sync() { LIF_HIP(hipStreamSynchronize(stream)); }
   // copy `bytes` from device `src` through the pinned buffer; synchronizes
@@ -270,9 +283,12 @@ void launch_phi_diag(Ctx& c, const int* row_of, const int* col, int64_t nnzb, in
 // per output block: the real rows of such a diagonal block, else 0).
 void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* brp, const int* bcol,
                            const unsigned char* diag_on, int nb, int* cnt_c, int64_t* cnt_p);
+// pairs[] receives the operand block pointers (ablk[value index of A],
+// bblk[value index of B]) of every block product
 void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp,
-                          const int* bcol, const int* bidx, const unsigned char* diag_on, int b, int64_t n, int nb,
-                          const int* crp, const int64_t* prp, int* ccol, int64_t* seg, int2* pairs,
+                          const int* bcol, const int* bidx, BlkIn ablk, BlkIn bblk, const unsigned char* diag_on,
+                          int b, int64_t n, int nb,
+                          const int* crp, const int64_t* prp, int* ccol, int64_t* seg, BlockPair* pairs,
                           unsigned char* dflag);
 // Fused identity term of a product: an output block with dflag[e] = r > 0
 // is the diagonal block of a row that takes gamma I.  Its product part is
@@ -289,11 +305,14 @@ struct Epilogue {
 // `nnzc` is the grid (the output capacity); `live` (device) the number of
 // output blocks actually present, <= nnzc.
 // Output block e is written to C + e b^2 and its pointer to Cp[e].
-void launch_numeric(Ctx& c, int prec, BlkIn A, BlkIn B, bool ta, bool tb, const int64_t* seg, const int2* pairs,
-                    int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms, const Epilogue& epi);
+// short_seg: most output blocks sum one or two block products (FP64 picks
+// its single-stage kernel).
+void launch_numeric(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg, const BlockPair* pairs,
+                    int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms, const Epilogue& epi,
+                    bool short_seg);
 // spgemm_mixed.hip
-void launch_numeric_mixed(Ctx& c, int prec, BlkIn A, BlkIn Bm, bool ta, bool tb, const int64_t* seg,
-                          const int2* pairs, int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms,
+void launch_numeric_mixed(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg,
+                          const BlockPair* pairs, int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms,
                           const Epilogue& epi);
 
 // chol.hip -- batched leaf inverse Cholesky on packed upper tile grids

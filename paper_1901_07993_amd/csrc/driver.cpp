@@ -82,6 +82,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
   bool labels_dirty = true;
   bool all_active = true;
   std::vector<std::array<int64_t, 2>> caps;  // per product of an iteration: {blocks, pairs}
+  std::vector<std::array<int64_t, 2>> prev_sizes;  // the counts caps were derived from
   if (!c.spec.sizes.get()) {
     c.spec.sizes = DBuf<int64_t>(c.pool, 2 * Ctx::Spec::kSlots);
     c.spec.overflow = DBuf<int>(c.pool, 1);
@@ -125,6 +126,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       c.spec.record = !planned;
       c.spec.next = 0;
       c.spec.caps = caps;
+      c.spec.prev = prev_sizes;
       c.spec.seen.clear();
       c.spec.prec.clear();
       if (planned) launch_fill_i32(c, c.spec.overflow.get(), 0, 1);
@@ -193,6 +195,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       // margins: output counts move little between iterations, block-product
       // counts can triple after the first iteration of a LIF level (delta_0
       // holds only the coupling blocks); pair slots are 8 bytes
+      prev_sizes = seen;
       caps.clear();
       for (const auto& v : seen)
         caps.push_back(o.presize == 2 ? v : std::array<int64_t, 2>{v[0] + v[0] / 2 + 64, 4 * v[1] + 4096});
@@ -385,13 +388,34 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   int band = 0;
   c.d2h(&band, d_band.get(), sizeof(int));
   launch_chol_pad(c, nbase, d_nbb.get(), d_rows.get(), d_tile0.get(), b, U.get(), 1.0);
+  // The factorization steps run on the main stream.  Tile column j of the
+  // inverse needs only columns < j and the V tiles of step j, so it runs on
+  // the side stream as soon as step j's trsm is done, overlapping the later
+  // (serial, small) factorization steps.
+  hipStream_t side = c.side_stream();
+  hipStream_t main_stream = c.stream;
   for (int k = 0; k < max_nbb; ++k) {
     launch_potrf(c, k, nbase, d_nbb.get(), d_blk0.get(), d_tile0.get(), b, U.get(), zs->get(), d_err.get());
     launch_trsm(c, k, band, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get());
+    if (k > 0) {
+      hipEvent_t ev = c.order_event((size_t)k);
+      LIF_HIP(hipEventRecord(ev, main_stream));
+      LIF_HIP(hipStreamWaitEvent(side, ev, 0));
+      struct OnSide {  // launches go to the side stream within this scope
+        Ctx& c;
+        hipStream_t keep;
+        ~OnSide() { c.stream = keep; }
+      } on_side{c, main_stream};
+      c.stream = side;
+      launch_trinv(c, k, band, nbase, d_nbb.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get());
+    }
     launch_update(c, k, band, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), nz.get());
   }
-  for (int j = 1; j < max_nbb; ++j)
-    launch_trinv(c, j, band, nbase, d_nbb.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get());
+  {
+    hipEvent_t ev = c.order_event(0);
+    LIF_HIP(hipEventRecord(ev, side));
+    LIF_HIP(hipStreamWaitEvent(main_stream, ev, 0));
+  }
   launch_chol_pad(c, nbase, d_nbb.get(), d_rows.get(), d_tile0.get(), b, zs->get(), 0.0);
   std::vector<int> err(nbase);
   c.d2h(err.data(), d_err.get(), nbase * sizeof(int));

@@ -203,11 +203,13 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
   C.row_ptr = DBuf<int>(c.pool, nb + 1);
   DBuf<int64_t> prp(c.pool, nb + 1);
   int64_t nnzc = 0, P = 0;  // capacities of the output and pair arrays
+  bool short_seg = false;   // at most two block products per output block
   const bool planned = c.spec.on && c.spec.next < c.spec.caps.size() && c.spec.next < (size_t)Ctx::Spec::kSlots;
   if (planned) {
     const size_t slot = c.spec.next++;
     nnzc = std::min<int64_t>(c.spec.caps[slot][0], (int64_t)nb * nb);
     P = c.spec.caps[slot][1];
+    if (slot < c.spec.prev.size()) short_seg = c.spec.prev[slot][1] <= 2 * c.spec.prev[slot][0];
     scan_exclusive_pair_capped(c, cnt_c.get(), C.row_ptr.get(), cnt_p.get(), prp.get(), nb, nnzc, P,
                                c.spec.sizes.get() + 2 * slot, c.spec.overflow.get());
     c.spec.prec.push_back(prec);
@@ -227,6 +229,7 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
     if (need_b) B.nnzb = nbk;
     nnzc = nnzc32;
     C.nnzb = nnzc;
+    short_seg = P <= 2 * nnzc;
     if (c.spec.record) c.spec.seen.push_back({nnzc, P});
     c.stats.products += P;
     const double fl = 2.0 * (double)C.b * C.b * C.b * (double)P;
@@ -236,10 +239,11 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
   C.cap = nnzc;
   C.col = DBuf<int>(c.pool, (size_t)nnzc);
   DBuf<int64_t> seg(c.pool, (size_t)nnzc + 1);
-  DBuf<int2> pairs(c.pool, (size_t)P);
+  DBuf<BlockPair> pairs(c.pool, (size_t)P);
   DBuf<unsigned char> dflag(c.pool, diag_on ? (size_t)nnzc : 0);
   if (nnzc)
-    launch_symbolic_fill(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, diag_on, C.b, C.n, nb, C.row_ptr.get(),
+    launch_symbolic_fill(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, A.ptrs(), B.ptrs(), diag_on, C.b, C.n, nb,
+                         C.row_ptr.get(),
                          prp.get(), C.col.get(), seg.get(), pairs.get(), diag_on ? dflag.get() : nullptr);
   Store st = new_store(c, nnzc, C.b);
   C.blk = DBuf<const double*>(c.pool, (size_t)nnzc);
@@ -249,8 +253,8 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
   epi.dflag = diag_on ? dflag.get() : nullptr;
   epi.tau = tau;
   epi.gamma = gamma;
-  launch_numeric(c, prec, A.ptrs(), B.ptrs(), ta, tb, seg.get(), pairs.get(), nnzc, C.row_ptr.get() + nb, C.b,
-                 st->get(), C.blk.get(), nrm.get(), epi);
+  launch_numeric(c, prec, ta, tb, seg.get(), pairs.get(), nnzc, C.row_ptr.get() + nb, C.b,
+                 st->get(), C.blk.get(), nrm.get(), epi, short_seg);
   return truncate(c, std::move(C), nrm.get(), tau);
 }
 

@@ -145,7 +145,26 @@ void Ctx::d2h_batch(const std::vector<Read>& reads) {
   for (int i = 0; i < n; ++i) std::memcpy(reads[i].dst, base + 64 * i, reads[i].bytes);
 }
 
+hipStream_t Ctx::side_stream() {
+  if (!side) LIF_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+  return side;
+}
+
+hipEvent_t Ctx::order_event(size_t i) {
+  while (order_events.size() <= i) {
+    hipEvent_t e = nullptr;
+    LIF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    order_events.push_back(e);
+  }
+  return order_events[i];
+}
+
 Ctx::~Ctx() {
+  if (side) {
+    (void)hipStreamSynchronize(side);
+    (void)hipStreamDestroy(side);
+  }
+  for (auto e : order_events) (void)hipEventDestroy(e);
   for (auto& pr : ev_pending) {
     (void)hipEventDestroy(pr.first);
     (void)hipEventDestroy(pr.second);

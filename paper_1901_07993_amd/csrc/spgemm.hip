@@ -89,10 +89,11 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_count(const int* __restrict
 __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict__ arp, const int* __restrict__ acol,
                                                           const int* __restrict__ aidx, const int* __restrict__ brp,
                                                           const int* __restrict__ bcol, const int* __restrict__ bidx,
+                                                          BlkIn ablk, BlkIn bblk,
                                                           const unsigned char* __restrict__ diag_on, int b,
                                                           int64_t n, int nb, const int* __restrict__ crp,
                                                           const int64_t* __restrict__ prp, int* __restrict__ ccol,
-                                                          int64_t* __restrict__ seg, int2* __restrict__ pairs,
+                                                          int64_t* __restrict__ seg, BlockPair* __restrict__ pairs,
                                                           unsigned char* __restrict__ dflag) {
   extern __shared__ unsigned smem[];
   __shared__ int scan_tmp[kSymWG];
@@ -183,12 +184,12 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
   // order; within one k every output column occurs at most once
   for (int e = arp[i]; e < arp[i + 1]; ++e) {
     const int k = acol[e];
-    const int a = aidx ? aidx[e] : e;
+    const double* a = ablk[aidx ? aidx[e] : e];
     for (int f = brp[k] + threadIdx.x; f < brp[k + 1]; f += kSymWG) {
       const int j = bcol[f];
       const int r = wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u));
       const int pos = cur[r];
-      pairs[prow + pos] = make_int2(a, bidx ? bidx[f] : f);
+      pairs[prow + pos] = BlockPair{a, bblk[bidx ? bidx[f] : f]};
       cur[r] = pos + 1;
     }
     __syncthreads();
@@ -235,16 +236,19 @@ __device__ inline void mma_stage(const double* __restrict__ As, const double* __
   }
 }
 
-template <int B, bool TA, bool TB>
-__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(BlkIn A, BlkIn Bm,
-                                                                     const int64_t* __restrict__ seg,
-                                                                     const int2* __restrict__ pairs,
+// STAGES = 2 for long segments (the pipeline above); STAGES = 1 halves the
+// LDS so that two workgroups share a CU, for products whose output blocks
+// sum only one or two block products (their latency is hidden across
+// workgroups instead): store, barrier, prefetch the next pair, multiply.
+template <int B, bool TA, bool TB, int STAGES>
+__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const int64_t* __restrict__ seg,
+                                                                     const BlockPair* __restrict__ pairs,
                                                                      const int* __restrict__ live,
                                                                      double* __restrict__ C, BlkOut Cp,
                                                                      double* __restrict__ norms, Epilogue epi) {
   using Cfg = TileCfg<B>;
-  __shared__ double As[2][Cfg::LDS_DOUBLES];
-  __shared__ double Bs[2][Cfg::LDS_DOUBLES];
+  __shared__ double As[STAGES][Cfg::LDS_DOUBLES];
+  __shared__ double Bs[STAGES][Cfg::LDS_DOUBLES];
   __shared__ double red[Cfg::WAVES];
   // the grid may exceed the live output count (capacity fixed before the
   // count was known); the XCD remap runs over the live blocks only
@@ -261,28 +265,44 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(BlkIn A, Bl
   // last surplus LDS store are never read), which keeps them in VGPRs.
   v2d ra[Cfg::V2], rbv[Cfg::V2];
   const int64_t plast = p1 - 1;
-  if (p1 > p0) {  // a diagonal block of a fused identity term may have no products
+  if (p1 > p0 && STAGES == 1) {
     {
-      const int2 pr = pairs[p0];
-      tile_load<B>(A[pr.x], ra);
-      tile_load<B>(Bm[pr.y], rbv);
+      const BlockPair pr = pairs[p0];
+      tile_load<B>(pr.a, ra);
+      tile_load<B>(pr.b, rbv);
+    }
+    for (int64_t p = p0; p < p1; ++p) {
+      if (p > p0) __syncthreads();  // the previous pair's fragment reads are done
+      tile_store<B>(As[0], ra, true);
+      tile_store<B>(Bs[0], rbv, true);
+      __syncthreads();
+      const BlockPair pr = pairs[min(p + 1, plast)];
+      tile_load<B>(pr.a, ra);
+      tile_load<B>(pr.b, rbv);
+      mma_stage<B, TA, TB>(As[0], Bs[0], f, acc);
+    }
+  } else if (p1 > p0) {  // a diagonal block of a fused identity term may have no products
+    {
+      const BlockPair pr = pairs[p0];
+      tile_load<B>(pr.a, ra);
+      tile_load<B>(pr.b, rbv);
     }
     tile_store<B>(As[0], ra, true);
     tile_store<B>(Bs[0], rbv, true);
     {
-      const int2 pr = pairs[min(p0 + 1, plast)];
-      tile_load<B>(A[pr.x], ra);
-      tile_load<B>(Bm[pr.y], rbv);
+      const BlockPair pr = pairs[min(p0 + 1, plast)];
+      tile_load<B>(pr.a, ra);
+      tile_load<B>(pr.b, rbv);
     }
     int stage = 0;
     for (int64_t p = p0; p < p1; ++p) {
       __syncthreads();  // stage p visible; stage p+1's previous readers done
-      tile_store<B>(As[stage ^ 1], ra, true);
-      tile_store<B>(Bs[stage ^ 1], rbv, true);
-      const int2 pr = pairs[min(p + 2, plast)];
-      tile_load<B>(A[pr.x], ra);
-      tile_load<B>(Bm[pr.y], rbv);
-      mma_stage<B, TA, TB>(As[stage], Bs[stage], f, acc);
+      tile_store<B>(As[(stage ^ 1) % STAGES], ra, true);
+      tile_store<B>(Bs[(stage ^ 1) % STAGES], rbv, true);
+      const BlockPair pr = pairs[min(p + 2, plast)];
+      tile_load<B>(pr.a, ra);
+      tile_load<B>(pr.b, rbv);
+      mma_stage<B, TA, TB>(As[stage % STAGES], Bs[stage % STAGES], f, acc);
       stage ^= 1;
     }
   }
@@ -322,20 +342,33 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(BlkIn A, Bl
   }
 }
 
-template <int B>
-void launch_numeric_b(Ctx& c, BlkIn A, BlkIn Bm, bool ta, bool tb, const int64_t* seg, const int2* pairs,
-                      int64_t nnzc, const int* live, double* C, BlkOut Cp, double* norms, const Epilogue& epi) {
+template <int B, int STAGES>
+void launch_numeric_s(Ctx& c, bool ta, bool tb, const int64_t* seg, const BlockPair* pairs, int64_t nnzc,
+                      const int* live, double* C, BlkOut Cp, double* norms, const Epilogue& epi) {
   using Cfg = TileCfg<B>;
   dim3 grid((unsigned)nnzc), block(Cfg::THREADS);
   if (!ta && !tb)
-    hipLaunchKernelGGL((k_numeric_f64<B, false, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, Cp, norms, epi);
+    hipLaunchKernelGGL((k_numeric_f64<B, false, false, STAGES>), grid, block, 0, c.stream, seg, pairs, live, C, Cp,
+                       norms, epi);
   else if (ta && !tb)
-    hipLaunchKernelGGL((k_numeric_f64<B, true, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, Cp, norms, epi);
+    hipLaunchKernelGGL((k_numeric_f64<B, true, false, STAGES>), grid, block, 0, c.stream, seg, pairs, live, C, Cp,
+                       norms, epi);
   else if (!ta && tb)
-    hipLaunchKernelGGL((k_numeric_f64<B, false, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, Cp, norms, epi);
+    hipLaunchKernelGGL((k_numeric_f64<B, false, true, STAGES>), grid, block, 0, c.stream, seg, pairs, live, C, Cp,
+                       norms, epi);
   else
-    hipLaunchKernelGGL((k_numeric_f64<B, true, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, Cp, norms, epi);
+    hipLaunchKernelGGL((k_numeric_f64<B, true, true, STAGES>), grid, block, 0, c.stream, seg, pairs, live, C, Cp,
+                       norms, epi);
   LIF_HIP(hipGetLastError());
+}
+
+template <int B>
+void launch_numeric_b(Ctx& c, bool ta, bool tb, const int64_t* seg, const BlockPair* pairs, int64_t nnzc,
+                      const int* live, double* C, BlkOut Cp, double* norms, const Epilogue& epi, bool short_seg) {
+  if (short_seg)
+    launch_numeric_s<B, 1>(c, ta, tb, seg, pairs, nnzc, live, C, Cp, norms, epi);
+  else
+    launch_numeric_s<B, 2>(c, ta, tb, seg, pairs, nnzc, live, C, Cp, norms, epi);
 }
 
 }  // namespace
@@ -359,16 +392,18 @@ void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* b
 }
 
 void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp, const int* bcol,
-                          const int* bidx, const unsigned char* diag_on, int b, int64_t n, int nb, const int* crp,
-                          const int64_t* prp, int* ccol, int64_t* seg, int2* pairs, unsigned char* dflag) {
+                          const int* bidx, BlkIn ablk, BlkIn bblk, const unsigned char* diag_on, int b, int64_t n,
+                          int nb, const int* crp,
+                          const int64_t* prp, int* ccol, int64_t* seg, BlockPair* pairs, unsigned char* dflag) {
   allow_lds((const void*)k_symbolic_fill, symbolic_lds_bytes(nb, true));
   hipLaunchKernelGGL(k_symbolic_fill, dim3(nb), dim3(kSymWG), symbolic_lds_bytes(nb, true), c.stream, arp, acol,
-                     aidx, brp, bcol, bidx, diag_on, b, n, nb, crp, prp, ccol, seg, pairs, dflag);
+                     aidx, brp, bcol, bidx, ablk, bblk, diag_on, b, n, nb, crp, prp, ccol, seg, pairs, dflag);
   LIF_HIP(hipGetLastError());
 }
 
-void launch_numeric(Ctx& c, int prec, BlkIn A, BlkIn B, bool ta, bool tb, const int64_t* seg, const int2* pairs,
-                    int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms, const Epilogue& epi) {
+void launch_numeric(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg, const BlockPair* pairs,
+                    int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms, const Epilogue& epi,
+                    bool short_seg) {
   if (nnzc == 0) return;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c.timing) {
@@ -377,11 +412,11 @@ void launch_numeric(Ctx& c, int prec, BlkIn A, BlkIn B, bool ta, bool tb, const 
     LIF_HIP(hipEventRecord(e0, c.stream));
   }
   if (prec != LIF_FP64)
-    launch_numeric_mixed(c, prec, A, B, ta, tb, seg, pairs, nnzc, live, b, C, Cp, norms, epi);
+    launch_numeric_mixed(c, prec, ta, tb, seg, pairs, nnzc, live, b, C, Cp, norms, epi);
   else if (b == 64)
-    launch_numeric_b<64>(c, A, B, ta, tb, seg, pairs, nnzc, live, C, Cp, norms, epi);
+    launch_numeric_b<64>(c, ta, tb, seg, pairs, nnzc, live, C, Cp, norms, epi, short_seg);
   else
-    launch_numeric_b<32>(c, A, B, ta, tb, seg, pairs, nnzc, live, C, Cp, norms, epi);
+    launch_numeric_b<32>(c, ta, tb, seg, pairs, nnzc, live, C, Cp, norms, epi, short_seg);
   if (c.timing) {
     LIF_HIP(hipEventRecord(e1, c.stream));
     c.ev_pending.emplace_back(e0, e1);

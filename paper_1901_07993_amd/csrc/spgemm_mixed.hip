@@ -122,9 +122,9 @@ __device__ inline void epilogue(const v4f (&acc)[2][2], int rb, int cb, int l16,
 }
 
 template <int B, bool TA, bool TB>
-__global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(BlkIn A, BlkIn Bm,
+__global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(
                                                                     const int64_t* __restrict__ seg,
-                                                                    const int2* __restrict__ pairs,
+                                                                    const BlockPair* __restrict__ pairs,
                                                                     const int* __restrict__ live,
                                                                     double* __restrict__ C, BlkOut Cp,
                                                                     double* __restrict__ norms, Epilogue epi) {
@@ -148,9 +148,9 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(BlkIn A, Blk
     for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
   v2d ra[Cfg::V2], rbv[Cfg::V2];
   if (p1 > p0) {  // a diagonal block of a fused identity term may have no products
-    const int2 pr = pairs[p0];
-    tile_load<B>(A[pr.x], ra);
-    tile_load<B>(Bm[pr.y], rbv);
+    const BlockPair pr = pairs[p0];
+    tile_load<B>(pr.a, ra);
+    tile_load<B>(pr.b, rbv);
   }
   for (int64_t p = p0; p < p1; ++p) {
     __syncthreads();
@@ -158,9 +158,9 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(BlkIn A, Blk
     store_f32<B>(Bs, rbv, !TB);  // Bs[k][j] = op(B)[k][j]
     __syncthreads();
     if (p + 1 < p1) {
-      const int2 pr = pairs[p + 1];
-      tile_load<B>(A[pr.x], ra);
-      tile_load<B>(Bm[pr.y], rbv);
+      const BlockPair pr = pairs[p + 1];
+      tile_load<B>(pr.a, ra);
+      tile_load<B>(pr.b, rbv);
     }
 #pragma unroll 4
     for (int kk = 0; kk < B / 4; ++kk) {
@@ -181,9 +181,9 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(BlkIn A, Blk
 }
 
 template <int B, bool TA, bool TB>
-__global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(BlkIn A, BlkIn Bm,
+__global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(
                                                                      const int64_t* __restrict__ seg,
-                                                                     const int2* __restrict__ pairs,
+                                                                     const BlockPair* __restrict__ pairs,
                                                                      const int* __restrict__ live,
                                                                      double* __restrict__ C, BlkOut Cp,
                                                                      double* __restrict__ norms, Epilogue epi) {
@@ -207,9 +207,9 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(BlkIn A, Bl
     for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
   v2d ra[Cfg::V2], rbv[Cfg::V2];
   if (p1 > p0) {  // a diagonal block of a fused identity term may have no products
-    const int2 pr = pairs[p0];
-    tile_load<B>(A[pr.x], ra);
-    tile_load<B>(Bm[pr.y], rbv);
+    const BlockPair pr = pairs[p0];
+    tile_load<B>(pr.a, ra);
+    tile_load<B>(pr.b, rbv);
   }
   for (int64_t p = p0; p < p1; ++p) {
     __syncthreads();
@@ -217,9 +217,9 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(BlkIn A, Bl
     store_bf16<B>(Bs, rbv, TB);  // Bs[j][k] = op(B)[k][j]
     __syncthreads();
     if (p + 1 < p1) {
-      const int2 pr = pairs[p + 1];
-      tile_load<B>(A[pr.x], ra);
-      tile_load<B>(Bm[pr.y], rbv);
+      const BlockPair pr = pairs[p + 1];
+      tile_load<B>(pr.a, ra);
+      tile_load<B>(pr.b, rbv);
     }
 #pragma unroll
     for (int kk = 0; kk < B / 32; ++kk) {
@@ -243,19 +243,19 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(BlkIn A, Bl
   do {                                                                                                     \
     dim3 grid((unsigned)nnzc), block(MixCfg<B>::THREADS);                                                  \
     if (!ta && !tb)                                                                                        \
-      hipLaunchKernelGGL((KERNEL<B, false, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, Cp, norms, epi); \
+      hipLaunchKernelGGL((KERNEL<B, false, false>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms, epi); \
     else if (ta && !tb)                                                                                    \
-      hipLaunchKernelGGL((KERNEL<B, true, false>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, Cp, norms, epi); \
+      hipLaunchKernelGGL((KERNEL<B, true, false>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms, epi); \
     else if (!ta && tb)                                                                                    \
-      hipLaunchKernelGGL((KERNEL<B, false, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, Cp, norms, epi); \
+      hipLaunchKernelGGL((KERNEL<B, false, true>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms, epi); \
     else                                                                                                   \
-      hipLaunchKernelGGL((KERNEL<B, true, true>), grid, block, 0, c.stream, A, Bm, seg, pairs, live, C, Cp, norms, epi); \
+      hipLaunchKernelGGL((KERNEL<B, true, true>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms, epi); \
   } while (0)
 
 }  // namespace
 
-void launch_numeric_mixed(Ctx& c, int prec, BlkIn A, BlkIn Bm, bool ta, bool tb, const int64_t* seg,
-                          const int2* pairs, int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms,
+void launch_numeric_mixed(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg,
+                          const BlockPair* pairs, int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms,
                           const Epilogue& epi) {
   if (prec == LIF_MIXED_FP32) {
     if (b == 64)
