@@ -79,12 +79,32 @@ __device__ __attribute__((always_inline)) inline double bcast(double v, int src)
   return __hiloint2double(hi, lo);
 }
 
+// 1 / sqrt(x) to full FP64 precision: the hardware estimate and two Newton
+// steps y <- y + y (1 - x y^2) / 2.
+__device__ __attribute__((always_inline)) inline double rsqrt_fp64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+// Orders the LDS accesses of one wavefront (the hardware keeps them in
+// order; this keeps the compiler from moving them across each other).
+__device__ __attribute__((always_inline)) inline void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Cholesky of the diagonal tile (k, k) and the inverse of its factor, in LDS,
 // blocked by 16 x 16 sub-blocks (NS = B / 16 of them per side).  For each
 // sub-block column p:
 //   A (wave 0, in registers; lane c owns column c of the sub-block)
-//       U_pp = chol(T_pp) by rank-1 updates, pivots and row entries
-//       broadcast with v_readlane; V_pp = U_pp^{-1} by back substitution
+//       U_pp = chol(T_pp) by rank-1 updates: the pivot comes by v_readlane,
+//       row j of U is broadcast through 16 doubles of LDS; then
+//       V_pp = U_pp^{-1} by back substitution, rows of U read from LDS
 //   B (one wave per task, 16x16x16 MFMA products)
 //       panel  U_pq = V_pp^T T_pq, q > p
 //       inverse W_rp = -Y_r V_pp, r < p
@@ -97,13 +117,15 @@ __device__ __attribute__((always_inline)) inline double bcast(double v, int src)
 template <int B>
 __global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nbbv, const int* __restrict__ blk0,
                                                const int64_t* __restrict__ tile0, double* __restrict__ U,
-                                               double* __restrict__ Z, int* __restrict__ err) {
+                                               double* __restrict__ Z, const unsigned char* __restrict__ nz,
+                                               int* __restrict__ err) {
   constexpr int L = B + 1;
   constexpr int NS = B / 16;
   constexpr int YL = 17;
   __shared__ double T[B * L];
   __shared__ double W[B * L];
   __shared__ double Y[NS * 16 * YL];
+  __shared__ __attribute__((aligned(16))) double rowbuf[16];
   const int s = blockIdx.x;
   const int nbb = nbbv[s];
   if (k >= nbb) return;
@@ -114,8 +136,11 @@ __global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nb
     constexpr int NV = B * B / 2 / 256;
     v2d r[NV];
     const v2d* gv = reinterpret_cast<const v2d*>(g);
+    // a diagonal tile S does not have reads as zero (and fails as not
+    // positive definite); the buffer is not cleared beforehand
+    const bool have = nz[t] != 0;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) r[v] = gv[threadIdx.x + v * 256];
+    for (int v = 0; v < NV; ++v) r[v] = have ? gv[threadIdx.x + v * 256] : v2d{0.0, 0.0};
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int q = 2 * (threadIdx.x + v * 256);
@@ -140,31 +165,40 @@ __global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nb
           if (bad < 0) bad = o + j;
           piv = 1.0;
         }
-        const double pj = sqrt(piv);
-        const double rj = 1.0 / pj;
+        const double rj = rsqrt_fp64(piv);
         rd[j] = rj;
         // row j of U: U[j][c] = a[j] / p_j (c > j), p_j at c = j, 0 below
-        const double x = (l16 == j) ? pj : (l16 > j ? a[j] * rj : 0.0);
+        const double x = (l16 == j) ? piv * rj : (l16 > j ? a[j] * rj : 0.0);
         a[j] = x;
+        if (j < 15) {
+          rowbuf[l16] = x;
+          wave_lds_fence();
+          double u[16];
 #pragma unroll
-        for (int i = j + 1; i < 16; ++i) a[i] = fma(-bcast(x, i), x, a[i]);
+          for (int i = j + 1; i < 16; ++i) u[i] = rowbuf[i];
+          wave_lds_fence();  // the reads are done before the next row is written
+#pragma unroll
+          for (int i = j + 1; i < 16; ++i) a[i] = fma(-u[i], x, a[i]);
+        }
       }
 #pragma unroll
       for (int i = 0; i < 16; ++i) a[i] = (i <= l16) ? a[i] : 0.0;
+      if (lane < 16) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) T[(o + i) * L + o + l16] = a[i];
+      }
+      wave_lds_fence();
       // column c of V: V[r][c] = (delta_rc - sum_{q>r} U[r][q] V[q][c]) / U[r][r]
 #pragma unroll
       for (int r = 15; r >= 0; --r) {
         double acc = (l16 == r) ? 1.0 : 0.0;
 #pragma unroll
-        for (int q = r + 1; q < 16; ++q) acc = fma(-bcast(a[r], q), v[q], acc);
+        for (int q = r + 1; q < 16; ++q) acc = fma(-T[(o + r) * L + o + q], v[q], acc);
         v[r] = acc * rd[r];
       }
       if (lane < 16) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          T[(o + i) * L + o + l16] = a[i];
-          W[(o + i) * L + o + l16] = v[i];
-        }
+        for (int i = 0; i < 16; ++i) W[(o + i) * L + o + l16] = v[i];
       }
     }
     __syncthreads();
@@ -325,7 +359,11 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_update(int k, int band,
   v4d acc[2][2];
   acc_zero(acc);
   tile_mma<B>(As, Bs, f, acc);
-  double* g = U + packed_tile(tile0[s], nbb, i, j) * B * B;
+  // a tile outside S's pattern that no earlier step reached holds no data
+  // yet (the buffer is not cleared): its first update writes -acc
+  const int64_t tij = packed_tile(tile0[s], nbb, i, j);
+  const bool first = !nz[tij];
+  double* g = U + tij * B * B;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -333,9 +371,10 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_update(int k, int band,
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int idx = acc_row(f, ti, r) * B + acc_col(f, tj);
-        g[idx] -= acc[ti][tj][r];
+        g[idx] = (first ? 0.0 : g[idx]) - acc[ti][tj][r];
       }
-  if (threadIdx.x == 0) nz[packed_tile(tile0[s], nbb, i, j)] = 1;
+  __syncthreads();  // every thread has read the flag before it is set
+  if (threadIdx.x == 0) nz[tij] = 1;
 }
 
 // Z_ij = -sum_{k=i}^{j-1} Z_ik V_kj for i = blockIdx.x < j, V_kj = U_kj Z_jj
@@ -365,7 +404,12 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, int band, 
     return k;
   };
   int k = next_k(max(i, j - band));
-  if (k >= j) return;  // Z_ij = 0 (the buffer starts zeroed)
+  if (k >= j) {  // Z_ij = 0 (the buffer is not cleared beforehand)
+    v2d* g = reinterpret_cast<v2d*>(Z + packed_tile(t0, nbb, i, j) * B * B);
+#pragma unroll
+    for (int v = 0; v < Cfg::V2; ++v) g[threadIdx.x + v * Cfg::THREADS] = v2d{0.0, 0.0};
+    return;
+  }
   tile_load<B>(Z + packed_tile(t0, nbb, i, k) * B * B, ra);
   tile_load<B>(V + packed_tile(t0, nbb, k, j) * B * B, rb);
   while (k < j) {
@@ -412,11 +456,11 @@ void launch_chol_pad(Ctx& c, int nbase, const int* nbb, const int* rows, const i
 }
 
 void launch_potrf(Ctx& c, int k, int nbase, const int* nbb, const int* blk0, const int64_t* tile0, int b, double* U,
-                  double* Z, int* err) {
+                  double* Z, const unsigned char* nz, int* err) {
   if (b == 64)
-    LIF_LAUNCH(k_potrf<64>, dim3(nbase), dim3(256), 0, c.stream, k, nbb, blk0, tile0, U, Z, err);
+    LIF_LAUNCH(k_potrf<64>, dim3(nbase), dim3(256), 0, c.stream, k, nbb, blk0, tile0, U, Z, nz, err);
   else
-    LIF_LAUNCH(k_potrf<32>, dim3(nbase), dim3(256), 0, c.stream, k, nbb, blk0, tile0, U, Z, err);
+    LIF_LAUNCH(k_potrf<32>, dim3(nbase), dim3(256), 0, c.stream, k, nbb, blk0, tile0, U, Z, nz, err);
 }
 
 void launch_trsm(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b,

@@ -322,7 +322,7 @@ void launch_chol_scatter(Ctx& c, const int* row_of, const int* col, BlkIn val, i
 void launch_chol_pad(Ctx& c, int nbase, const int* nbb, const int* rows, const int64_t* tile0, int b, double* M,
                      double value);
 void launch_potrf(Ctx& c, int k, int nbase, const int* nbb, const int* blk0, const int64_t* tile0, int b, double* U,
-                  double* Z, int* err);
+                  double* Z, const unsigned char* nz, int* err);
 // `band`: largest j - i over the nonzero tiles (i, j) of S within a leaf;
 // the factor's nonzero tiles satisfy j - i <= band as well
 void launch_trsm(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b,

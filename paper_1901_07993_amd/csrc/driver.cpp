@@ -373,9 +373,10 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   Z.n = S.n;
   Z.b = b;
   Z.nb = nb;
+  // neither buffer is cleared: every tile of U that is read was scattered
+  // from S or written in full by its first update, and every tile of Z is
+  // written by potrf or trinv
   Store zs = new_store(c, tiles, b);
-  LIF_HIP(hipMemsetAsync(U.get(), 0, (size_t)tiles * tile_doubles * sizeof(double), c.stream));
-  LIF_HIP(hipMemsetAsync(zs->get(), 0, (size_t)tiles * tile_doubles * sizeof(double), c.stream));
   {
     const int64_t snz = exact_nnzb(c, S);
     DBuf<int> rowof(c.pool, (size_t)std::max<int64_t>(snz, 1));
@@ -395,11 +396,14 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   hipStream_t side = c.side_stream();
   hipStream_t main_stream = c.stream;
   for (int k = 0; k < max_nbb; ++k) {
-    launch_potrf(c, k, nbase, d_nbb.get(), d_blk0.get(), d_tile0.get(), b, U.get(), zs->get(), d_err.get());
+    launch_potrf(c, k, nbase, d_nbb.get(), d_blk0.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get(),
+                 d_err.get());
     launch_trsm(c, k, band, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get());
+    hipEvent_t ev = c.order_event((size_t)k);
+    if (k > 0) LIF_HIP(hipEventRecord(ev, main_stream));
+    // the next step's inputs first, then the side stream's inverse column
+    launch_update(c, k, band, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), nz.get());
     if (k > 0) {
-      hipEvent_t ev = c.order_event((size_t)k);
-      LIF_HIP(hipEventRecord(ev, main_stream));
       LIF_HIP(hipStreamWaitEvent(side, ev, 0));
       struct OnSide {  // launches go to the side stream within this scope
         Ctx& c;
@@ -409,7 +413,6 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
       c.stream = side;
       launch_trinv(c, k, band, nbase, d_nbb.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get());
     }
-    launch_update(c, k, band, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), nz.get());
   }
   {
     hipEvent_t ev = c.order_event(0);
