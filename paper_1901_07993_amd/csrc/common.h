@@ -181,7 +181,6 @@ struct Ctx {
     bool on = false, record = false;
     size_t next = 0;
     std::vector<std::array<int64_t, 2>> caps, seen;
-    std::vector<std::array<int64_t, 2>> prev;  // true counts behind caps
     std::vector<int> prec;  // precision of each sized-in-advance product
     DBuf<int64_t> sizes;
     DBuf<int> overflow;
@@ -278,38 +277,30 @@ void launch_phi_diag(Ctx& c, const int* row_of, const int* col, int64_t nnzb, in
 // Symbolic phase.  opA given as CSR (row ptr, col, value index) of op(A);
 // B as CSR of op(B) with value index.  Writes per-row output and product
 // counts.
-// `diag_on` (nullable): rows whose diagonal block is added to the output
-// pattern (a fused identity term); the fill pass then writes dflag (one byte
-// per output block: the real rows of such a diagonal block, else 0).
+// D (drp, dcol, dblk; nullable) joins the output pattern; the fill pass
+// then writes dsrc[e], D's block at output position e (null where D has
+// none).
 void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* brp, const int* bcol,
-                           const unsigned char* diag_on, int nb, int* cnt_c, int64_t* cnt_p);
-// pairs[] receives the operand block pointers (ablk[value index of A],
-// bblk[value index of B]) of every block product
+                           const int* drp, const int* dcol, int nb, int* cnt_c, int64_t* cnt_p);
 void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp,
-                          const int* bcol, const int* bidx, BlkIn ablk, BlkIn bblk, const unsigned char* diag_on,
-                          int b, int64_t n, int nb,
-                          const int* crp, const int64_t* prp, int* ccol, int64_t* seg, BlockPair* pairs,
-                          unsigned char* dflag);
-// Fused identity term of a product: an output block with dflag[e] = r > 0
-// is the diagonal block of a row that takes gamma I.  Its product part is
-// dropped when its norm is below tau (tau > 0), gamma is added to its first
-// r diagonal entries, and its norm is reported as +inf so truncation keeps
-// it: the result equals truncating the product, then adding gamma I.
+                          const int* bcol, const int* bidx, BlkIn ablk, BlkIn bblk, const int* drp, const int* dcol,
+                          BlkIn dblk, int nb, const int* crp, const int64_t* prp, int* ccol, int64_t* seg,
+                          BlockPair* pairs, BlkOut dsrc);
+// Fused terms of a product: the output block is alpha sum op(A) op(B)
+// + gamma D_e, D_e = dsrc[e] (skipped where null), and its norm is the norm
+// of that sum (truncation then applies to the whole block).
 struct Epilogue {
-  const unsigned char* dflag = nullptr;
-  double tau = 0.0;
+  double alpha = 1.0;
   double gamma = 0.0;
+  BlkIn dsrc = nullptr;
 };
 // Numeric phase: C_blk = sum over its segment of op(A_a) op(B_b), in FP64
 // (prec = LIF_FP64) or with FP32 / BF16 inputs and FP32 accumulation.
 // `nnzc` is the grid (the output capacity); `live` (device) the number of
 // output blocks actually present, <= nnzc.
 // Output block e is written to C + e b^2 and its pointer to Cp[e].
-// short_seg: most output blocks sum one or two block products (FP64 picks
-// its single-stage kernel).
 void launch_numeric(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg, const BlockPair* pairs,
-                    int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms, const Epilogue& epi,
-                    bool short_seg);
+                    int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms, const Epilogue& epi);
 // spgemm_mixed.hip
 void launch_numeric_mixed(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg,
                           const BlockPair* pairs, int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms,
@@ -360,10 +351,10 @@ DBuf<double> block_norms(Ctx& c, const Bsr& A);
 Bsr truncate(Ctx& c, Bsr&& A, const double* norms, double tau);
 CsrView transpose_view(Ctx& c, const Bsr& A);
 Bsr transpose(Ctx& c, const Bsr& A);
-// trunc_tau(op(A) op(B)) [+ gamma I on the rows with diag_on set, added after
-// the truncation of the product]
+// trunc_tau(alpha op(A) op(B) [+ gamma D]): the optional term D is added
+// block by block before the truncation
 Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec = LIF_FP64,
-           double gamma = 0.0, const unsigned char* diag_on = nullptr);
+           double alpha = 1.0, const Bsr* D = nullptr, double gamma = 0.0);
 // alpha A + beta B + gamma I on the block rows with diag_on set (A or B may be null)
 Bsr axpby(Ctx& c, double alpha, const Bsr* A, double beta, const Bsr* B, double gamma,
           const unsigned char* diag_on);

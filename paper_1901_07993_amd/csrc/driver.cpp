@@ -76,13 +76,10 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
   }
 
   std::vector<int> rowlab(nb);
-  std::vector<unsigned char> diag(nb);
   DBuf<int> d_rowlab(c.pool, nb);
-  DBuf<unsigned char> d_diag(c.pool, nb);
   bool labels_dirty = true;
   bool all_active = true;
   std::vector<std::array<int64_t, 2>> caps;  // per product of an iteration: {blocks, pairs}
-  std::vector<std::array<int64_t, 2>> prev_sizes;  // the counts caps were derived from
   if (!c.spec.sizes.get()) {
     c.spec.sizes = DBuf<int64_t>(c.pool, 2 * Ctx::Spec::kSlots);
     c.spec.overflow = DBuf<int>(c.pool, 1);
@@ -105,9 +102,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
         }
         for (int i = bt.rlo[s]; i < bt.rhi[s]; ++i) rowlab[i] = s;
       }
-      for (int i = 0; i < nb; ++i) diag[i] = rowlab[i] >= 0 ? 1 : 0;
       h2d(c, d_rowlab.get(), rowlab.data(), nb);
-      h2d(c, d_diag.get(), diag.data(), nb);
       labels_dirty = false;
     }
     // One iteration.  After the first, every product is sized from the
@@ -126,7 +121,6 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       c.spec.record = !planned;
       c.spec.next = 0;
       c.spec.caps = caps;
-      c.spec.prev = prev_sizes;
       c.spec.seen.clear();
       c.spec.prec.clear();
       if (planned) launch_fill_i32(c, c.spec.overflow.get(), 0, 1);
@@ -136,18 +130,22 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       if (restrict_rows) dfilt = filter(c, delta, d_rowlab.get(), nullptr, 2);
       const Bsr& da = restrict_rows ? dfilt : delta;
 
-      // M = Z sum_{k=1}^m b_k delta^k, Horner form, every product truncated;
-      // these products run in the requested input precision (FP32
-      // accumulation when reduced), the delta-update below always in FP64
+      // M = Z sum_{k=1}^m b_k delta^k, Horner form, every product truncated:
+      //   T_{m-1} = b_m delta + b_{m-1} I,  T_j = b_j I + trunc(delta T_{j+1}),
+      //   q = trunc(delta T_1).
+      // T_j is kept as X_j + c_j I with only X_j stored, so that the identity
+      // is never formed: delta T = delta X + c delta, with the scaled delta
+      // added to each output block before its truncation.  These products
+      // run in the requested input precision (FP32 accumulation when
+      // reduced), the delta-update below always in FP64.
       Bsr q;
       if (o.m == 1) {
         q = axpby(c, bk[1], &da, 0.0, nullptr, 0.0, nullptr);
       } else {
-        Bsr T = axpby(c, bk[o.m], &da, 0.0, nullptr, bk[o.m - 1], d_diag.get());
-        // T <- trunc(delta T) + b_j I: the identity term is added in the
-        // product's epilogue
-        for (int j = o.m - 2; j >= 1; --j) T = spgemm(c, da, false, T, false, o.tau, o.prec, bk[j], d_diag.get());
-        q = spgemm(c, da, false, T, false, o.tau, o.prec);
+        // first product: delta (b_m delta + b_{m-1} I) = b_m delta^2 + b_{m-1} delta
+        Bsr X = spgemm(c, da, false, da, false, o.tau, o.prec, bk[o.m], &da, bk[o.m - 1]);
+        for (int j = o.m - 2; j >= 1; --j) X = spgemm(c, da, false, X, false, o.tau, o.prec, 1.0, &da, bk[j]);
+        q = std::move(X);
       }
       Bsr M = spgemm(c, Z, false, q, false, o.tau, o.prec);
       q = Bsr();
@@ -195,7 +193,6 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       // margins: output counts move little between iterations, block-product
       // counts can triple after the first iteration of a LIF level (delta_0
       // holds only the coupling blocks); pair slots are 8 bytes
-      prev_sizes = seen;
       caps.clear();
       for (const auto& v : seen)
         caps.push_back(o.presize == 2 ? v : std::array<int64_t, 2>{v[0] + v[0] / 2 + 64, 4 * v[1] + 4096});

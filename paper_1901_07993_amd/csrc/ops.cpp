@@ -179,8 +179,8 @@ Bsr transpose(Ctx& c, const Bsr& A) {
   return T;
 }
 
-Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec, double gamma,
-           const unsigned char* diag_on) {
+Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec, double alpha,
+           const Bsr* D, double gamma) {
   LIF_REQUIRE(A.nb == B.nb && A.b == B.b, LIF_ERR_INVALID, "spgemm: operand shapes differ");
   const int nb = A.nb;
   Bsr C = like(A);
@@ -199,17 +199,18 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
   }
   DBuf<int> cnt_c(c.pool, nb);
   DBuf<int64_t> cnt_p(c.pool, nb);
-  launch_symbolic_count(c, av.rp, av.col, bv.rp, bv.col, diag_on, nb, cnt_c.get(), cnt_p.get());
+  if (D) LIF_REQUIRE(D->nb == nb && D->b == A.b, LIF_ERR_INVALID, "spgemm: added term's shape differs");
+  const int* drp = D ? D->row_ptr.get() : nullptr;
+  const int* dcol = D ? D->col.get() : nullptr;
+  launch_symbolic_count(c, av.rp, av.col, bv.rp, bv.col, drp, dcol, nb, cnt_c.get(), cnt_p.get());
   C.row_ptr = DBuf<int>(c.pool, nb + 1);
   DBuf<int64_t> prp(c.pool, nb + 1);
   int64_t nnzc = 0, P = 0;  // capacities of the output and pair arrays
-  bool short_seg = false;   // at most two block products per output block
   const bool planned = c.spec.on && c.spec.next < c.spec.caps.size() && c.spec.next < (size_t)Ctx::Spec::kSlots;
   if (planned) {
     const size_t slot = c.spec.next++;
     nnzc = std::min<int64_t>(c.spec.caps[slot][0], (int64_t)nb * nb);
     P = c.spec.caps[slot][1];
-    if (slot < c.spec.prev.size()) short_seg = c.spec.prev[slot][1] <= 2 * c.spec.prev[slot][0];
     scan_exclusive_pair_capped(c, cnt_c.get(), C.row_ptr.get(), cnt_p.get(), prp.get(), nb, nnzc, P,
                                c.spec.sizes.get() + 2 * slot, c.spec.overflow.get());
     c.spec.prec.push_back(prec);
@@ -229,7 +230,6 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
     if (need_b) B.nnzb = nbk;
     nnzc = nnzc32;
     C.nnzb = nnzc;
-    short_seg = P <= 2 * nnzc;
     if (c.spec.record) c.spec.seen.push_back({nnzc, P});
     c.stats.products += P;
     const double fl = 2.0 * (double)C.b * C.b * C.b * (double)P;
@@ -240,21 +240,21 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
   C.col = DBuf<int>(c.pool, (size_t)nnzc);
   DBuf<int64_t> seg(c.pool, (size_t)nnzc + 1);
   DBuf<BlockPair> pairs(c.pool, (size_t)P);
-  DBuf<unsigned char> dflag(c.pool, diag_on ? (size_t)nnzc : 0);
+  DBuf<const double*> dsrc(c.pool, D ? (size_t)nnzc : 0);
   if (nnzc)
-    launch_symbolic_fill(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, A.ptrs(), B.ptrs(), diag_on, C.b, C.n, nb,
-                         C.row_ptr.get(),
-                         prp.get(), C.col.get(), seg.get(), pairs.get(), diag_on ? dflag.get() : nullptr);
+    launch_symbolic_fill(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, A.ptrs(), B.ptrs(), drp, dcol,
+                         D ? D->ptrs() : nullptr, nb, C.row_ptr.get(), prp.get(), C.col.get(), seg.get(),
+                         pairs.get(), D ? dsrc.get() : nullptr);
   Store st = new_store(c, nnzc, C.b);
   C.blk = DBuf<const double*>(c.pool, (size_t)nnzc);
   C.store.push_back(st);
   DBuf<double> nrm(c.pool, (size_t)nnzc);
   Epilogue epi;
-  epi.dflag = diag_on ? dflag.get() : nullptr;
-  epi.tau = tau;
+  epi.alpha = alpha;
   epi.gamma = gamma;
+  epi.dsrc = D ? dsrc.get() : nullptr;
   launch_numeric(c, prec, ta, tb, seg.get(), pairs.get(), nnzc, C.row_ptr.get() + nb, C.b,
-                 st->get(), C.blk.get(), nrm.get(), epi, short_seg);
+                 st->get(), C.blk.get(), nrm.get(), epi);
   return truncate(c, std::move(C), nrm.get(), tau);
 }
 

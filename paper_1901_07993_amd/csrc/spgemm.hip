@@ -12,10 +12,12 @@
 // summed in the same order on every run (no atomics on values).
 //
 // Numeric phase (FP64 MFMA): one workgroup per output block.  The operand
-// blocks of its segment stream through two LDS stages (see k_numeric_f64);
-// v_mfma_f64_16x16x4f64 accumulates the whole segment in registers; the
-// block is written once, together with its Frobenius norm (fixed-order FP64
-// reduction) for the truncation pass.
+// blocks of its segment are read through their pointers, contiguous
+// fragments straight into registers and the others through one LDS tile
+// (see k_numeric_f64); v_mfma_f64_16x16x4f64 accumulates the whole segment
+// in registers; the block is written once, with the fused terms of the
+// epilogue, together with its Frobenius norm (fixed-order FP64 reduction)
+// for the truncation pass.
 #include "common.h"
 #include "tile_mma.h"
 
@@ -29,15 +31,19 @@ constexpr int kSymWG = 256;
 // symbolic
 // ---------------------------------------------------------------------------
 
-// `diag_on` (nullable): rows whose diagonal block joins the pattern whether
-// or not a product reaches it (the target of a fused identity term)
+// `drp`/`dcol` (nullable): a matrix D whose row pattern joins the output
+// pattern (the target of a fused term gamma D)
 __device__ inline void build_row_bitmap(const int* __restrict__ arp, const int* __restrict__ acol,
                                         const int* __restrict__ brp, const int* __restrict__ bcol,
-                                        const unsigned char* __restrict__ diag_on, int i, unsigned* bm, int nwords,
-                                        int64_t* pcount) {
+                                        const int* __restrict__ drp, const int* __restrict__ dcol, int i,
+                                        unsigned* bm, int nwords, int64_t* pcount) {
   for (int w = threadIdx.x; w < nwords; w += kSymWG) bm[w] = 0u;
   __syncthreads();
-  if (threadIdx.x == 0 && diag_on && diag_on[i]) atomicOr(&bm[i >> 5], 1u << (i & 31));
+  if (drp)
+    for (int e = drp[i] + threadIdx.x; e < drp[i + 1]; e += kSymWG) {
+      const int j = dcol[e];
+      atomicOr(&bm[j >> 5], 1u << (j & 31));
+    }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int64_t p = 0;
   for (int e = arp[i] + wave; e < arp[i + 1]; e += kSymWG / 64) {
@@ -55,8 +61,9 @@ __device__ inline void build_row_bitmap(const int* __restrict__ arp, const int* 
 
 __global__ __launch_bounds__(kSymWG) void k_symbolic_count(const int* __restrict__ arp, const int* __restrict__ acol,
                                                            const int* __restrict__ brp, const int* __restrict__ bcol,
-                                                           const unsigned char* __restrict__ diag_on, int nb,
-                                                           int* __restrict__ cnt_c, int64_t* __restrict__ cnt_p) {
+                                                           const int* __restrict__ drp, const int* __restrict__ dcol,
+                                                           int nb, int* __restrict__ cnt_c,
+                                                           int64_t* __restrict__ cnt_p) {
   extern __shared__ unsigned smem[];
   __shared__ int64_t red_p[kSymWG];
   __shared__ int red_c[kSymWG];
@@ -64,7 +71,7 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_count(const int* __restrict
   const int nwords = (nb + 31) >> 5;
   unsigned* bm = smem;
   int64_t p = 0;
-  build_row_bitmap(arp, acol, brp, bcol, diag_on, i, bm, nwords, &p);
+  build_row_bitmap(arp, acol, brp, bcol, drp, dcol, i, bm, nwords, &p);
   int c = 0;
   for (int w = threadIdx.x; w < nwords; w += kSymWG) c += __popc(bm[w]);
   red_p[threadIdx.x] = p;
@@ -84,17 +91,17 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_count(const int* __restrict
 }
 
 // LDS layout of the fill pass: bitmap[nwords] | word_prefix[nwords] | cursor[nb]
-// With `diag_on`, dflag[e] of each output block is the number of real rows
-// of a diagonal block that takes the identity term (0 for the others).
+// With D, dsrc[e] of each output block is D's block at the same position
+// (null where D has none).
 __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict__ arp, const int* __restrict__ acol,
                                                           const int* __restrict__ aidx, const int* __restrict__ brp,
                                                           const int* __restrict__ bcol, const int* __restrict__ bidx,
-                                                          BlkIn ablk, BlkIn bblk,
-                                                          const unsigned char* __restrict__ diag_on, int b,
-                                                          int64_t n, int nb, const int* __restrict__ crp,
+                                                          BlkIn ablk, BlkIn bblk, const int* __restrict__ drp,
+                                                          const int* __restrict__ dcol, BlkIn dblk, int nb,
+                                                          const int* __restrict__ crp,
                                                           const int64_t* __restrict__ prp, int* __restrict__ ccol,
                                                           int64_t* __restrict__ seg, BlockPair* __restrict__ pairs,
-                                                          unsigned char* __restrict__ dflag) {
+                                                          BlkOut dsrc) {
   extern __shared__ unsigned smem[];
   __shared__ int scan_tmp[kSymWG];
   const int i = blockIdx.x;
@@ -102,8 +109,7 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
   unsigned* bm = smem;
   int* wp = reinterpret_cast<int*>(smem + nwords);
   int* cur = wp + nwords;
-  build_row_bitmap(arp, acol, brp, bcol, diag_on, i, bm, nwords, nullptr);
-  const int drows = (diag_on && diag_on[i]) ? (int)min<int64_t>(b, n - (int64_t)i * b) : 0;
+  build_row_bitmap(arp, acol, brp, bcol, drp, dcol, i, bm, nwords, nullptr);
 
   // exclusive prefix of word popcounts: contiguous chunks per thread
   const int chunk = (nwords + kSymWG - 1) / kSymWG;
@@ -135,13 +141,20 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
       const int bit = __ffs(bits) - 1;
       const int j = (w << 5) + bit;
       ccol[cbase + r] = j;
-      if (dflag) dflag[cbase + r] = (unsigned char)(j == i ? drows : 0);
+      if (dsrc) dsrc[cbase + r] = nullptr;
       cur[r] = 0;
       ++r;
       bits &= bits - 1;
     }
   }
   __syncthreads();
+
+  // D's blocks at their output positions
+  if (dsrc)
+    for (int e = drp[i] + threadIdx.x; e < drp[i + 1]; e += kSymWG) {
+      const int j = dcol[e];
+      dsrc[cbase + wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u))] = dblk[e];
+    }
 
   // products per output block
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -209,166 +222,172 @@ __device__ inline int64_t xcd_remap(int64_t wg, int64_t total) {
   return x * q + (x < r ? x : r) + l;
 }
 
-// Operand blocks are stored into LDS as they are (row-major, 16-byte
-// stores); op() is applied when the MFMA fragments are read: a fragment is
-// either 16 consecutive doubles or 16 doubles one LDS row (66 doubles) apart,
-// both conflict-free within a quarter-wave.  Two LDS stages: while the
-// waves multiply the tiles of pair p, the tiles of pair p+1 are written to
-// the other stage and those of pair p+2 are loaded into registers, with one
-// barrier per pair.
+// Output layout of a product tile.  Wave (rb, cb) holds the 32 x 32 quadrant
+// as 2 x 2 MFMA tiles (ti, tj).  Where an operand's fragments are contiguous
+// in memory (A stored k-major: op(A) = A^T; B stored k-major: op(B) = B), the
+// two tiles of that side interleave (rows rb + 2 m + ti, columns
+// cb + 2 m + tj), so one 16-byte access carries both tiles' fragments;
+// otherwise they are stacked (rb + 16 ti + m, cb + 16 tj + m).  Both numeric
+// kernels use this map, so they give bitwise the same blocks and norms.
 template <int B, bool TA, bool TB>
-__device__ inline void mma_stage(const double* __restrict__ As, const double* __restrict__ Bs, const Frag& f,
-                                 v4d (&acc)[2][2]) {
-  constexpr int LD = TileCfg<B>::LD;
-#pragma unroll 4
-  for (int kk = 0; kk < B / 4; ++kk) {
-    const int k = 4 * kk + f.kq;
-    // op(A)[i][k]: A[i][k] (row i of the stored block) or A[k][i] (row k)
-    const double a0 = TA ? As[k * LD + f.rb + f.l16] : As[(f.rb + f.l16) * LD + k];
-    const double a1 = TA ? As[k * LD + f.rb + 16 + f.l16] : As[(f.rb + 16 + f.l16) * LD + k];
-    // op(B)[k][j]: B[k][j] or B[j][k]
-    const double b0 = TB ? Bs[(f.cb + f.l16) * LD + k] : Bs[k * LD + f.cb + f.l16];
-    const double b1 = TB ? Bs[(f.cb + 16 + f.l16) * LD + k] : Bs[k * LD + f.cb + 16 + f.l16];
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-  }
-}
+struct OutMap {
+  static constexpr bool RI = TA, CI = !TB;
+  __device__ static int row(const Frag& f, int ti, int m) { return RI ? f.rb + 2 * m + ti : f.rb + 16 * ti + m; }
+  __device__ static int col(const Frag& f, int tj, int m) { return CI ? f.cb + 2 * m + tj : f.cb + 16 * tj + m; }
+};
 
-// STAGES = 2 for long segments (the pipeline above); STAGES = 1 halves the
-// LDS so that two workgroups share a CU, for products whose output blocks
-// sum only one or two block products (their latency is hidden across
-// workgroups instead): store, barrier, prefetch the next pair, multiply.
-template <int B, bool TA, bool TB, int STAGES>
-__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const int64_t* __restrict__ seg,
-                                                                     const BlockPair* __restrict__ pairs,
-                                                                     const int* __restrict__ live,
-                                                                     double* __restrict__ C, BlkOut Cp,
-                                                                     double* __restrict__ norms, Epilogue epi) {
+// The block alpha A B + gamma D (Epilogue), its FP64 sum of squares in a
+// fixed order, its norm and its pointer.
+template <int B, bool TA, bool TB>
+__device__ __attribute__((always_inline)) inline void numeric_epilogue(const v4d (&acc)[2][2], const Frag& f,
+                                                                       int64_t blk, double* __restrict__ C,
+                                                                       BlkOut Cp, double* __restrict__ norms,
+                                                                       const Epilogue& epi, double* red) {
   using Cfg = TileCfg<B>;
-  __shared__ double As[STAGES][Cfg::LDS_DOUBLES];
-  __shared__ double Bs[STAGES][Cfg::LDS_DOUBLES];
-  __shared__ double red[Cfg::WAVES];
-  // the grid may exceed the live output count (capacity fixed before the
-  // count was known); the XCD remap runs over the live blocks only
-  const int64_t nlive = *live;
-  if ((int64_t)blockIdx.x >= nlive) return;
-  const int64_t blk = xcd_remap(blockIdx.x, nlive);
-  const int64_t p0 = seg[blk], p1 = seg[blk + 1];
-  const Frag f = frag_coords<B>();
-
-  v4d acc[2][2];
-  acc_zero(acc);
-  // The loop body has no branches around the prefetch registers (the
-  // prefetch index is clamped to the last pair; the surplus loads and the
-  // last surplus LDS store are never read), which keeps them in VGPRs.
-  v2d ra[Cfg::V2], rbv[Cfg::V2];
-  const int64_t plast = p1 - 1;
-  if (p1 > p0 && STAGES == 1) {
-    {
-      const BlockPair pr = pairs[p0];
-      tile_load<B>(pr.a, ra);
-      tile_load<B>(pr.b, rbv);
+  using M = OutMap<B, TA, TB>;
+  // C = alpha A B (+ gamma D), D's elements loaded where this lane holds C's
+  const double* Db = epi.dsrc ? epi.dsrc[blk] : nullptr;
+  double v[2][2][4];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = M::row(f, ti, 4 * r + f.kq);
+      double d0 = 0.0, d1 = 0.0;
+      if (Db) {
+        if (M::CI) {
+          const v2d dv = *reinterpret_cast<const v2d*>(Db + row * B + M::col(f, 0, f.l16));
+          d0 = dv.x;
+          d1 = dv.y;
+        } else {
+          d0 = Db[row * B + M::col(f, 0, f.l16)];
+          d1 = Db[row * B + M::col(f, 1, f.l16)];
+        }
+      }
+      v[ti][0][r] = epi.alpha * acc[ti][0][r];
+      v[ti][1][r] = epi.alpha * acc[ti][1][r];
+      if (Db) {
+        v[ti][0][r] += epi.gamma * d0;
+        v[ti][1][r] += epi.gamma * d1;
+      }
     }
-    for (int64_t p = p0; p < p1; ++p) {
-      if (p > p0) __syncthreads();  // the previous pair's fragment reads are done
-      tile_store<B>(As[0], ra, true);
-      tile_store<B>(Bs[0], rbv, true);
-      __syncthreads();
-      const BlockPair pr = pairs[min(p + 1, plast)];
-      tile_load<B>(pr.a, ra);
-      tile_load<B>(pr.b, rbv);
-      mma_stage<B, TA, TB>(As[0], Bs[0], f, acc);
-    }
-  } else if (p1 > p0) {  // a diagonal block of a fused identity term may have no products
-    {
-      const BlockPair pr = pairs[p0];
-      tile_load<B>(pr.a, ra);
-      tile_load<B>(pr.b, rbv);
-    }
-    tile_store<B>(As[0], ra, true);
-    tile_store<B>(Bs[0], rbv, true);
-    {
-      const BlockPair pr = pairs[min(p0 + 1, plast)];
-      tile_load<B>(pr.a, ra);
-      tile_load<B>(pr.b, rbv);
-    }
-    int stage = 0;
-    for (int64_t p = p0; p < p1; ++p) {
-      __syncthreads();  // stage p visible; stage p+1's previous readers done
-      tile_store<B>(As[(stage ^ 1) % STAGES], ra, true);
-      tile_store<B>(Bs[(stage ^ 1) % STAGES], rbv, true);
-      const BlockPair pr = pairs[min(p + 2, plast)];
-      tile_load<B>(pr.a, ra);
-      tile_load<B>(pr.b, rbv);
-      mma_stage<B, TA, TB>(As[stage % STAGES], Bs[stage % STAGES], f, acc);
-      stage ^= 1;
-    }
-  }
-
-  // epilogue: FP64 sum of squares in a fixed order, then the block
   double ss = 0.0;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) ss += acc[ti][tj][r] * acc[ti][tj][r];
+      for (int r = 0; r < 4; ++r) ss += v[ti][tj][r] * v[ti][tj][r];
   for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
   if (f.lane == 0) red[f.wave] = ss;
-  __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int w = 0; w < Cfg::WAVES; ++w) t += red[w];
-  const double nrm = sqrt(t);
-  const int dr = epi.dflag ? epi.dflag[blk] : 0;
-  const bool keep = dr == 0 || !(epi.tau > 0.0) || nrm >= epi.tau;
   double* Cb = C + blk * B * B;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = acc_row(f, ti, r), col = acc_col(f, tj);
-        double v = keep ? acc[ti][tj][r] : 0.0;
-        if (row == col && row < dr) v += epi.gamma;
-        Cb[row * B + col] = v;
+    for (int r = 0; r < 4; ++r) {
+      const int row = M::row(f, ti, 4 * r + f.kq);
+      if (M::CI) {
+        *reinterpret_cast<v2d*>(Cb + row * B + M::col(f, 0, f.l16)) = v2d{v[ti][0][r], v[ti][1][r]};
+      } else {
+        Cb[row * B + M::col(f, 0, f.l16)] = v[ti][0][r];
+        Cb[row * B + M::col(f, 1, f.l16)] = v[ti][1][r];
       }
+    }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    norms[blk] = dr ? INFINITY : nrm;
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < Cfg::WAVES; ++w) t += red[w];
+    norms[blk] = sqrt(t);
     Cp[blk] = Cb;
   }
 }
 
-template <int B, int STAGES>
-void launch_numeric_s(Ctx& c, bool ta, bool tb, const int64_t* seg, const BlockPair* pairs, int64_t nnzc,
-                      const int* live, double* C, BlkOut Cp, double* norms, const Epilogue& epi) {
+// Numeric kernel, one workgroup per output block.  Fragments whose elements
+// are contiguous in memory are loaded straight from global memory into
+// registers (16 bytes per lane: both tiles of a side); only an operand read
+// across its rows (op(A) = A, op(B) = B^T) is staged in LDS, as stored.
+// With at most one LDS tile, two or three workgroups share a CU and hide
+// each other's load latency -- on the sparse products of the refinement
+// (one to three block products per output block) and on dense ones (219
+// per block) alike this beat a double-buffered two-tile LDS pipeline.
+template <int B, bool TA, bool TB>
+__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const int64_t* __restrict__ seg,
+                                                                        const BlockPair* __restrict__ pairs,
+                                                                        const int* __restrict__ live,
+                                                                        double* __restrict__ C, BlkOut Cp,
+                                                                        double* __restrict__ norms, Epilogue epi) {
   using Cfg = TileCfg<B>;
-  dim3 grid((unsigned)nnzc), block(Cfg::THREADS);
-  if (!ta && !tb)
-    hipLaunchKernelGGL((k_numeric_f64<B, false, false, STAGES>), grid, block, 0, c.stream, seg, pairs, live, C, Cp,
-                       norms, epi);
-  else if (ta && !tb)
-    hipLaunchKernelGGL((k_numeric_f64<B, true, false, STAGES>), grid, block, 0, c.stream, seg, pairs, live, C, Cp,
-                       norms, epi);
-  else if (!ta && tb)
-    hipLaunchKernelGGL((k_numeric_f64<B, false, true, STAGES>), grid, block, 0, c.stream, seg, pairs, live, C, Cp,
-                       norms, epi);
-  else
-    hipLaunchKernelGGL((k_numeric_f64<B, true, true, STAGES>), grid, block, 0, c.stream, seg, pairs, live, C, Cp,
-                       norms, epi);
-  LIF_HIP(hipGetLastError());
+  constexpr bool A_LDS = !TA, B_LDS = TB;
+  constexpr int KS = B / 4;
+  __shared__ __attribute__((aligned(16))) double As[A_LDS ? Cfg::LDS_DOUBLES : 2];
+  __shared__ __attribute__((aligned(16))) double Bs[B_LDS ? Cfg::LDS_DOUBLES : 2];
+  __shared__ double red[Cfg::WAVES];
+  const int64_t nlive = *live;
+  if ((int64_t)blockIdx.x >= nlive) return;
+  const int64_t blk = xcd_remap(blockIdx.x, nlive);
+  const int64_t p0 = seg[blk], p1 = seg[blk + 1];
+  const Frag f = frag_coords<B>();
+  v4d acc[2][2];
+  acc_zero(acc);
+  for (int64_t p = p0; p < p1; ++p) {
+    const BlockPair pr = pairs[p];
+    v2d ra[Cfg::V2], rbv[Cfg::V2];
+    v2d ad[KS], bd[KS];
+    if (A_LDS) {
+      tile_load<B>(pr.a, ra);
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk)
+        ad[kk] = *reinterpret_cast<const v2d*>(pr.a + (4 * kk + f.kq) * B + f.rb + 2 * f.l16);
+    }
+    if (B_LDS) {
+      tile_load<B>(pr.b, rbv);
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk)
+        bd[kk] = *reinterpret_cast<const v2d*>(pr.b + (4 * kk + f.kq) * B + f.cb + 2 * f.l16);
+    }
+    if (A_LDS || B_LDS) {
+      if (p > p0) __syncthreads();  // the previous pair's fragment reads are done
+      if (A_LDS) tile_store<B>(As, ra, true);
+      if (B_LDS) tile_store<B>(Bs, rbv, true);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const int k = 4 * kk + f.kq;
+      constexpr int LD = Cfg::LD;
+      const double a0 = A_LDS ? As[(f.rb + f.l16) * LD + k] : ad[kk].x;
+      const double a1 = A_LDS ? As[(f.rb + 16 + f.l16) * LD + k] : ad[kk].y;
+      const double b0 = B_LDS ? Bs[(f.cb + f.l16) * LD + k] : bd[kk].x;
+      const double b1 = B_LDS ? Bs[(f.cb + 16 + f.l16) * LD + k] : bd[kk].y;
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+  }
+  numeric_epilogue<B, TA, TB>(acc, f, blk, C, Cp, norms, epi, red);
 }
 
 template <int B>
 void launch_numeric_b(Ctx& c, bool ta, bool tb, const int64_t* seg, const BlockPair* pairs, int64_t nnzc,
-                      const int* live, double* C, BlkOut Cp, double* norms, const Epilogue& epi, bool short_seg) {
-  if (short_seg)
-    launch_numeric_s<B, 1>(c, ta, tb, seg, pairs, nnzc, live, C, Cp, norms, epi);
+                      const int* live, double* C, BlkOut Cp, double* norms, const Epilogue& epi) {
+  const dim3 grid((unsigned)nnzc), block(TileCfg<B>::THREADS);
+  if (!ta && !tb)
+    hipLaunchKernelGGL((k_numeric_f64<B, false, false>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms,
+                       epi);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((k_numeric_f64<B, true, false>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms,
+                       epi);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((k_numeric_f64<B, false, true>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms,
+                       epi);
   else
-    launch_numeric_s<B, 2>(c, ta, tb, seg, pairs, nnzc, live, C, Cp, norms, epi);
+    hipLaunchKernelGGL((k_numeric_f64<B, true, true>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms,
+                       epi);
+  LIF_HIP(hipGetLastError());
 }
 
 }  // namespace
@@ -384,26 +403,24 @@ static void allow_lds(const void* fn, size_t bytes) {
 }
 
 void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* brp, const int* bcol,
-                           const unsigned char* diag_on, int nb, int* cnt_c, int64_t* cnt_p) {
+                           const int* drp, const int* dcol, int nb, int* cnt_c, int64_t* cnt_p) {
   allow_lds((const void*)k_symbolic_count, symbolic_lds_bytes(nb, false));
   hipLaunchKernelGGL(k_symbolic_count, dim3(nb), dim3(kSymWG), symbolic_lds_bytes(nb, false), c.stream, arp, acol,
-                     brp, bcol, diag_on, nb, cnt_c, cnt_p);
+                     brp, bcol, drp, dcol, nb, cnt_c, cnt_p);
   LIF_HIP(hipGetLastError());
 }
 
 void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp, const int* bcol,
-                          const int* bidx, BlkIn ablk, BlkIn bblk, const unsigned char* diag_on, int b, int64_t n,
-                          int nb, const int* crp,
-                          const int64_t* prp, int* ccol, int64_t* seg, BlockPair* pairs, unsigned char* dflag) {
+                          const int* bidx, BlkIn ablk, BlkIn bblk, const int* drp, const int* dcol, BlkIn dblk, int nb,
+                          const int* crp, const int64_t* prp, int* ccol, int64_t* seg, BlockPair* pairs, BlkOut dsrc) {
   allow_lds((const void*)k_symbolic_fill, symbolic_lds_bytes(nb, true));
   hipLaunchKernelGGL(k_symbolic_fill, dim3(nb), dim3(kSymWG), symbolic_lds_bytes(nb, true), c.stream, arp, acol,
-                     aidx, brp, bcol, bidx, ablk, bblk, diag_on, b, n, nb, crp, prp, ccol, seg, pairs, dflag);
+                     aidx, brp, bcol, bidx, ablk, bblk, drp, dcol, dblk, nb, crp, prp, ccol, seg, pairs, dsrc);
   LIF_HIP(hipGetLastError());
 }
 
 void launch_numeric(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg, const BlockPair* pairs,
-                    int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms, const Epilogue& epi,
-                    bool short_seg) {
+                    int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms, const Epilogue& epi) {
   if (nnzc == 0) return;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c.timing) {
@@ -414,9 +431,9 @@ void launch_numeric(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg, cons
   if (prec != LIF_FP64)
     launch_numeric_mixed(c, prec, ta, tb, seg, pairs, nnzc, live, b, C, Cp, norms, epi);
   else if (b == 64)
-    launch_numeric_b<64>(c, ta, tb, seg, pairs, nnzc, live, C, Cp, norms, epi, short_seg);
+    launch_numeric_b<64>(c, ta, tb, seg, pairs, nnzc, live, C, Cp, norms, epi);
   else
-    launch_numeric_b<32>(c, ta, tb, seg, pairs, nnzc, live, C, Cp, norms, epi, short_seg);
+    launch_numeric_b<32>(c, ta, tb, seg, pairs, nnzc, live, C, Cp, norms, epi);
   if (c.timing) {
     LIF_HIP(hipEventRecord(e1, c.stream));
     c.ev_pending.emplace_back(e0, e1);

@@ -82,13 +82,15 @@ __device__ inline void store_bf16(unsigned short* __restrict__ s, const v2d* reg
   }
 }
 
-// FP64 norm of the FP32 accumulators in a fixed order, then the block (with
-// the fused identity term of Epilogue)
+// The block alpha A B + gamma D (Epilogue; FP64 from the FP32 accumulators),
+// its FP64 sum of squares in a fixed order, its norm and its pointer.
 template <int B>
 __device__ inline void epilogue(const v4f (&acc)[2][2], int rb, int cb, int l16, int kq, int lane, int wave,
-                                double* __restrict__ Cb, double* red, double* __restrict__ norm_out, int dr,
-                                const Epilogue& epi) {
+                                int64_t blk, double* __restrict__ C, BlkOut Cp, double* red,
+                                double* __restrict__ norms, const Epilogue& epi) {
   using Cfg = MixCfg<B>;
+  const double* Db = epi.dsrc ? epi.dsrc[blk] : nullptr;
+  double* Cb = C + blk * B * B;
   double ss = 0.0;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
@@ -96,29 +98,22 @@ __device__ inline void epilogue(const v4f (&acc)[2][2], int rb, int cb, int l16,
     for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double v = (double)acc[ti][tj][r];
+        const int idx = (rb + 16 * ti + 4 * kq + r) * B + cb + 16 * tj + l16;
+        double v = epi.alpha * (double)acc[ti][tj][r];
+        if (Db) v += epi.gamma * Db[idx];
+        Cb[idx] = v;
         ss += v * v;
       }
   for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
   if (lane == 0) red[wave] = ss;
   __syncthreads();
-  double t = 0.0;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
 #pragma unroll
-  for (int w = 0; w < Cfg::WAVES; ++w) t += red[w];
-  const double nrm = sqrt(t);
-  const bool keep = dr == 0 || !(epi.tau > 0.0) || nrm >= epi.tau;
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = rb + 16 * ti + 4 * kq + r, col = cb + 16 * tj + l16;
-        double v = keep ? (double)acc[ti][tj][r] : 0.0;
-        if (row == col && row < dr) v += epi.gamma;
-        Cb[row * B + col] = v;
-      }
-  if (threadIdx.x == 0) *norm_out = dr ? INFINITY : nrm;
+    for (int w = 0; w < Cfg::WAVES; ++w) t += red[w];
+    norms[blk] = sqrt(t);
+    Cp[blk] = Cb;
+  }
 }
 
 template <int B, bool TA, bool TB>
@@ -175,9 +170,7 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(
       acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
     }
   }
-  epilogue<B>(acc, rb, cb, l16, kq, lane, wave, C + blk * B * B, red, norms + blk, epi.dflag ? epi.dflag[blk] : 0,
-              epi);
-  if (threadIdx.x == 0) Cp[blk] = C + blk * B * B;
+  epilogue<B>(acc, rb, cb, l16, kq, lane, wave, blk, C, Cp, red, norms, epi);
 }
 
 template <int B, bool TA, bool TB>
@@ -234,9 +227,7 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(
       acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
     }
   }
-  epilogue<B>(acc, rb, cb, l16, kq, lane, wave, C + blk * B * B, red, norms + blk, epi.dflag ? epi.dflag[blk] : 0,
-              epi);
-  if (threadIdx.x == 0) Cp[blk] = C + blk * B * B;
+  epilogue<B>(acc, rb, cb, l16, kq, lane, wave, blk, C, Cp, red, norms, epi);
 }
 
 #define LIF_MIXED_DISPATCH(KERNEL, B)                                                                      \
