@@ -9,6 +9,7 @@
 // block comes from one operand unscaled points at that operand's block.
 // Passes that do touch values handle one block per workgroup with coalesced
 // 16-byte accesses; index work runs one thread per block row or block.
+#include "block_scan.h"
 #include "common.h"
 #include "tile_mma.h"
 
@@ -467,26 +468,19 @@ constexpr int kCS = 1024;
 
 template <class Count>
 __global__ __launch_bounds__(kCS) void k_count_scan(Count cnt, int nb, int* __restrict__ rp) {
-  __shared__ int part[kCS];
+  __shared__ int sh[kCS / 64];
   const int t = threadIdx.x;
   const int chunk = (nb + kCS - 1) / kCS;
   const int lo = min(nb, t * chunk), hi = min(nb, lo + chunk);
   int s = 0;
   for (int i = lo; i < hi; ++i) s += cnt(i);
-  part[t] = s;
-  __syncthreads();
-  for (int off = 1; off < kCS; off <<= 1) {
-    const int v = (t >= off) ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  int run = t ? part[t - 1] : 0;
+  int total;
+  int run = block_exclusive_scan<int, kCS>(s, sh, &total);
   for (int i = lo; i < hi; ++i) {
     rp[i] = run;
     run += cnt(i);
   }
-  if (t == kCS - 1) rp[nb] = part[kCS - 1];
+  if (t == 0) rp[nb] = total;
 }
 
 struct KeepCount {

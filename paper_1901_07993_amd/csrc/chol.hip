@@ -158,9 +158,13 @@ __global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nb
       double a[16], rd[16], v[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) a[i] = T[(o + i) * L + o + l16];
+      // the next pivot is lane j+1's own diagonal entry less x^2: it is
+      // formed before the row broadcast, keeping the broadcast off the
+      // serial pivot chain
+      double piv_next = bcast(a[0], 0);
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        double piv = bcast(a[j], j);
+        double piv = piv_next;
         if (!(piv > 0.0)) {
           if (bad < 0) bad = o + j;
           piv = 1.0;
@@ -170,6 +174,7 @@ __global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nb
         // row j of U: U[j][c] = a[j] / p_j (c > j), p_j at c = j, 0 below
         const double x = (l16 == j) ? piv * rj : (l16 > j ? a[j] * rj : 0.0);
         a[j] = x;
+        if (j < 15) piv_next = bcast(fma(-x, x, a[j + 1]), j + 1);
         if (j < 15) {
           rowbuf[l16] = x;
           wave_lds_fence();
@@ -350,29 +355,34 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_update(int k, int band,
   const int i = k + 1 + ip, j = k + 1 + jp;
   if (!nz[packed_tile(tile0[s], nbb, k, i)] || !nz[packed_tile(tile0[s], nbb, k, j)]) return;
   const Frag f = frag_coords<B>();
-  v2d reg[Cfg::V2];
-  tile_load<B>(U + packed_tile(tile0[s], nbb, k, i) * B * B, reg);
-  tile_store<B>(As, reg, true);  // op(A) = U_ki^T
-  tile_load<B>(U + packed_tile(tile0[s], nbb, k, j) * B * B, reg);
-  tile_store<B>(Bs, reg, true);
-  __syncthreads();
-  v4d acc[2][2];
-  acc_zero(acc);
-  tile_mma<B>(As, Bs, f, acc);
   // a tile outside S's pattern that no earlier step reached holds no data
   // yet (the buffer is not cleared): its first update writes -acc
   const int64_t tij = packed_tile(tile0[s], nbb, i, j);
   const bool first = !nz[tij];
   double* g = U + tij * B * B;
+  // the target's elements this lane updates, loaded with the operands
+  double old[2][2][4];
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int idx = acc_row(f, ti, r) * B + acc_col(f, tj);
-        g[idx] = (first ? 0.0 : g[idx]) - acc[ti][tj][r];
-      }
+      for (int r = 0; r < 4; ++r) old[ti][tj][r] = first ? 0.0 : g[acc_row(f, ti, r) * B + acc_col(f, tj)];
+  v2d ra[Cfg::V2], rb[Cfg::V2];
+  tile_load<B>(U + packed_tile(tile0[s], nbb, k, i) * B * B, ra);
+  tile_load<B>(U + packed_tile(tile0[s], nbb, k, j) * B * B, rb);
+  tile_store<B>(As, ra, true);  // op(A) = U_ki^T
+  tile_store<B>(Bs, rb, true);
+  __syncthreads();
+  v4d acc[2][2];
+  acc_zero(acc);
+  tile_mma<B>(As, Bs, f, acc);
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) g[acc_row(f, ti, r) * B + acc_col(f, tj)] = old[ti][tj][r] - acc[ti][tj][r];
   __syncthreads();  // every thread has read the flag before it is set
   if (threadIdx.x == 0) nz[tij] = 1;
 }

@@ -1,9 +1,10 @@
 // Exclusive prefix sums of per-row counts (block-CSR row pointers, product
 // offsets).  One workgroup of 1024 threads: each thread sums a contiguous
-// chunk, the chunk totals are scanned in LDS, then each thread writes its
-// chunk.  The arrays scanned here have one entry per block row (<= 2^15 on
+// chunk, the chunk totals are scanned (block_scan.h), then each thread
+// writes its chunk.  The arrays scanned here have one entry per block row (<= 2^15 on
 // the supported sizes), so one workgroup is enough and the result is exact
 // and deterministic.
+#include "block_scan.h"
 #include "common.h"
 
 namespace lif {
@@ -12,31 +13,29 @@ namespace {
 
 constexpr int kScanThreads = 1024;
 
+// Each thread sums a contiguous chunk of the input, the chunk totals are
+// scanned, then each thread writes its chunk's prefix sums.
+template <typename T, typename In>
+__device__ void scan_chunks(const In* __restrict__ in, T* __restrict__ out, int count, T* sh, T* total) {
+  const int t = threadIdx.x;
+  const int chunk = (count + kScanThreads - 1) / kScanThreads;
+  const int lo = min(count, t * chunk), hi = min(count, lo + chunk);
+  T s = 0;
+  for (int i = lo; i < hi; ++i) s += (T)in[i];
+  T run = block_exclusive_scan<T, kScanThreads>(s, sh, total);
+  for (int i = lo; i < hi; ++i) {
+    out[i] = run;
+    run += (T)in[i];
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_exclusive(const T* __restrict__ in,
                                                                   T* __restrict__ out, int count) {
-  __shared__ T part[kScanThreads];
-  const int t = threadIdx.x;
-  const int chunk = (count + kScanThreads - 1) / kScanThreads;
-  const int lo = min(count, t * chunk);
-  const int hi = min(count, lo + chunk);
-  T s = 0;
-  for (int i = lo; i < hi; ++i) s += in[i];
-  part[t] = s;
-  __syncthreads();
-  // Hillis-Steele inclusive scan of the chunk totals
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    T v = (t >= off) ? part[t - off] : T(0);
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  T run = (t == 0) ? T(0) : part[t - 1];
-  for (int i = lo; i < hi; ++i) {
-    out[i] = run;
-    run += in[i];
-  }
-  if (t == kScanThreads - 1) out[count] = part[kScanThreads - 1];
+  __shared__ T sh[kScanThreads / 64];
+  T total;
+  scan_chunks<T, T>(in, out, count, sh, &total);
+  if (threadIdx.x == 0) out[count] = total;
 }
 
 // both arrays in one launch: workgroup 0 scans the int32 array, workgroup 1
@@ -44,48 +43,15 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_exclusive(const T* __rest
 __global__ __launch_bounds__(kScanThreads) void k_scan_pair(const int* __restrict__ in32, int* __restrict__ out32,
                                                             const int64_t* __restrict__ in64,
                                                             int64_t* __restrict__ out64, int count) {
+  __shared__ int64_t sh[kScanThreads / 64];
   if (blockIdx.x == 0) {
-    __shared__ int part[kScanThreads];
-    const int t = threadIdx.x;
-    const int chunk = (count + kScanThreads - 1) / kScanThreads;
-    const int lo = min(count, t * chunk), hi = min(count, lo + chunk);
-    int s = 0;
-    for (int i = lo; i < hi; ++i) s += in32[i];
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-      int v = (t >= off) ? part[t - off] : 0;
-      __syncthreads();
-      part[t] += v;
-      __syncthreads();
-    }
-    int run = t ? part[t - 1] : 0;
-    for (int i = lo; i < hi; ++i) {
-      out32[i] = run;
-      run += in32[i];
-    }
-    if (t == kScanThreads - 1) out32[count] = part[kScanThreads - 1];
+    int total;
+    scan_chunks<int, int>(in32, out32, count, reinterpret_cast<int*>(sh), &total);
+    if (threadIdx.x == 0) out32[count] = total;
   } else {
-    __shared__ int64_t part64[kScanThreads];
-    const int t = threadIdx.x;
-    const int chunk = (count + kScanThreads - 1) / kScanThreads;
-    const int lo = min(count, t * chunk), hi = min(count, lo + chunk);
-    int64_t s = 0;
-    for (int i = lo; i < hi; ++i) s += in64[i];
-    part64[t] = s;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-      int64_t v = (t >= off) ? part64[t - off] : 0;
-      __syncthreads();
-      part64[t] += v;
-      __syncthreads();
-    }
-    int64_t run = t ? part64[t - 1] : 0;
-    for (int i = lo; i < hi; ++i) {
-      out64[i] = run;
-      run += in64[i];
-    }
-    if (t == kScanThreads - 1) out64[count] = part64[kScanThreads - 1];
+    int64_t total;
+    scan_chunks<int64_t, int64_t>(in64, out64, count, sh, &total);
+    if (threadIdx.x == 0) out64[count] = total;
   }
 }
 
@@ -100,51 +66,28 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_pair_capped(const int* __
                                                                    int64_t cap32, int64_t cap64,
                                                                    int64_t* __restrict__ sizes,
                                                                    int* __restrict__ overflow) {
-  __shared__ int64_t part[kScanThreads];
-  const int t = threadIdx.x;
-  const int chunk = (count + kScanThreads - 1) / kScanThreads;
-  const int lo = min(count, t * chunk), hi = min(count, lo + chunk);
-  int64_t total[2];
-#pragma unroll
-  for (int pass = 0; pass < 2; ++pass) {
-    int64_t s = 0;
-    for (int i = lo; i < hi; ++i) s += pass ? in64[i] : (int64_t)in32[i];
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-      const int64_t v = (t >= off) ? part[t - off] : 0;
-      __syncthreads();
-      part[t] += v;
-      __syncthreads();
-    }
-    int64_t run = t ? part[t - 1] : 0;
-    for (int i = lo; i < hi; ++i) {
-      if (pass) {
-        out64[i] = run;
-        run += in64[i];
-      } else {
-        out32[i] = (int)run;
-        run += in32[i];
-      }
-    }
-    total[pass] = part[kScanThreads - 1];
-    __syncthreads();  // every thread has its total before the next pass reuses part
+  __shared__ int64_t sh[kScanThreads / 64];
+  int64_t total32, total64;
+  {
+    int t32;
+    scan_chunks<int, int>(in32, out32, count, reinterpret_cast<int*>(sh), &t32);
+    total32 = t32;
   }
-  if (t == kScanThreads - 1) {
-    out32[count] = (int)total[0];
-    out64[count] = total[1];
+  __syncthreads();  // sh is reused
+  scan_chunks<int64_t, int64_t>(in64, out64, count, sh, &total64);
+  if (threadIdx.x == 0) {
+    out32[count] = (int)total32;
+    out64[count] = total64;
+    sizes[0] = total32;
+    sizes[1] = total64;
   }
-  if (t == 0) {
-    sizes[0] = total[0];
-    sizes[1] = total[1];
-  }
-  if (total[0] > cap32 || total[1] > cap64) {
+  if (total32 > cap32 || total64 > cap64) {
     __syncthreads();  // the scan's own writes land first
-    for (int i = t; i <= count; i += kScanThreads) {
+    for (int i = threadIdx.x; i <= count; i += kScanThreads) {
       out32[i] = 0;
       out64[i] = 0;
     }
-    if (t == 0) *overflow = 1;
+    if (threadIdx.x == 0) *overflow = 1;
   }
 }
 

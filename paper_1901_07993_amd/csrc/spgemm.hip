@@ -18,6 +18,7 @@
 // in registers; the block is written once, with the fused terms of the
 // epilogue, together with its Frobenius norm (fixed-order FP64 reduction)
 // for the truncation pass.
+#include "block_scan.h"
 #include "common.h"
 #include "tile_mma.h"
 
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
                                                           int64_t* __restrict__ seg, BlockPair* __restrict__ pairs,
                                                           BlkOut dsrc) {
   extern __shared__ unsigned smem[];
-  __shared__ int scan_tmp[kSymWG];
+  __shared__ int scan_tmp[kSymWG / 64];
   const int i = blockIdx.x;
   const int nwords = (nb + 31) >> 5;
   unsigned* bm = smem;
@@ -116,16 +117,8 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
   const int w0 = min(nwords, (int)threadIdx.x * chunk), w1 = min(nwords, w0 + chunk);
   int s = 0;
   for (int w = w0; w < w1; ++w) s += __popc(bm[w]);
-  scan_tmp[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 1; off < kSymWG; off <<= 1) {
-    int v = (threadIdx.x >= off) ? scan_tmp[threadIdx.x - off] : 0;
-    __syncthreads();
-    scan_tmp[threadIdx.x] += v;
-    __syncthreads();
-  }
-  const int ncols = scan_tmp[kSymWG - 1];
-  int run = threadIdx.x ? scan_tmp[threadIdx.x - 1] : 0;
+  int ncols;
+  int run = block_exclusive_scan<int, kSymWG>(s, scan_tmp, &ncols);
   for (int w = w0; w < w1; ++w) {
     wp[w] = run;
     run += __popc(bm[w]);
@@ -173,18 +166,11 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
   const int c1 = min(ncols, c0 + (ncols + kSymWG - 1) / kSymWG);
   int t = 0;
   for (int r = c0; r < c1; ++r) t += cur[r];
-  __syncthreads();
-  scan_tmp[threadIdx.x] = t;
-  __syncthreads();
-  for (int off = 1; off < kSymWG; off <<= 1) {
-    int v = (threadIdx.x >= off) ? scan_tmp[threadIdx.x - off] : 0;
-    __syncthreads();
-    scan_tmp[threadIdx.x] += v;
-    __syncthreads();
-  }
+  __syncthreads();  // scan_tmp is reused
+  int tot;
+  int acc = block_exclusive_scan<int, kSymWG>(t, scan_tmp, &tot);
   int64_t prow = prp[i];
   if (i == nb - 1 && threadIdx.x == 0) seg[crp[nb]] = prp[nb];  // closing segment pointer
-  int acc = threadIdx.x ? scan_tmp[threadIdx.x - 1] : 0;
   for (int r = c0; r < c1; ++r) {
     const int cnt = cur[r];
     seg[cbase + r] = prow + acc;
