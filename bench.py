@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "s per inverse factorization + leaf-GEMM GFLOP/s at ‖Z*SZ−I‖≤1e-10, FP64 vs mixed"
 PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_HBM_BPS = 8.0e12
 KERNEL_SOURCES = ("paper_1901_07993_amd/csrc/spgemm.hip", "paper_1901_07993_amd/csrc/tile_mma.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "numeric_f64_chain5000_traffic.json")
 
@@ -94,6 +95,8 @@ def main():
     ap.add_argument("--count", type=int, default=5000, help="chain residues (5000 = the full workload)")
     ap.add_argument("--no-residual", action="store_true", help="skip the untruncated residual after timing")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 / BF16 runs")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy this many MiB device to device (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
@@ -108,6 +111,13 @@ def main():
     lif.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"# generating chain-{args.count}", file=sys.stderr, flush=True)
     S, cfg = config_matrix(1, count=args.count)
     Sd = type("DevBlocks", (), dict(n=S.n, b=S.b, brow=torch.from_numpy(S.brow).cuda(),
@@ -187,7 +197,13 @@ def main():
                      "flops_per_launch": flops / max(launches, 1),
                      "avg_launch_us": gemm_s / max(launches, 1) * 1e6,
                      "launches_per_step": launches / args.steps,
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     # two b x b FP64 operand blocks per block product: b / 8 flop per byte
+                     "operand_bytes_per_launch": flops / max(launches, 1) / 8.0,
+                     "traffic_GBps": (traffic / (gemm_s / max(launches, 1)) / 1e9
+                                      if traffic and gemm_s > 0 else None),
+                     "traffic_frac_of_hbm_peak": (traffic / (gemm_s / max(launches, 1)) / PEAK_HBM_BPS
+                                                  if traffic and gemm_s > 0 else None)},
     }
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle sample)", file=sys.stderr, flush=True)

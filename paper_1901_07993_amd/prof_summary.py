@@ -1,0 +1,109 @@
+"""Summaries of rocprofv3 CSV output for the committed profiles.
+
+    python -m paper_1901_07993_amd.prof_summary stats TRACE.csv OUT.md --title T --cmd C
+        per-kernel totals of the last factorization in a kernel trace (a
+        factorization starts at its k_chol_scatter launch), plus the span
+    python -m paper_1901_07993_amd.prof_summary traffic FETCH.csv WRITE.csv OUT.json \
+            --kernel k_numeric_f64 --copy-mib N --cmd C [--hash H]
+        HBM bytes per dispatch of one kernel from FETCH_SIZE / WRITE_SIZE
+        counter runs, each scaled by the factor that maps the same counter
+        on a plain device copy of N MiB (issued before any library kernel)
+        to its known size
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import json
+
+
+def _short(name: str) -> str:
+    return name.replace("lif::(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+
+
+def stats(trace: str, out: str, title: str, cmd: str) -> None:
+    rows = list(csv.DictReader(open(trace)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    starts = [i for i, r in enumerate(rows) if "k_chol_scatter" in r["Kernel_Name"]]
+    seg = rows[starts[-1]:] if starts else rows
+    t0 = int(seg[0]["Start_Timestamp"])
+    t1 = max(int(r["End_Timestamp"]) for r in seg)
+    agg = collections.defaultdict(lambda: [0, 0])
+    busy = 0
+    for r in seg:
+        d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        agg[_short(r["Kernel_Name"])][0] += 1
+        agg[_short(r["Kernel_Name"])][1] += d
+        busy += d
+    with open(out, "w") as f:
+        f.write(f"# {title}\n\nCommand (repository root, one MI355X):\n\n```\n{cmd}\n```\n\n")
+        f.write(f"Last factorization of the run: {len(seg)} kernels, span {(t1 - t0) / 1e6:.2f} ms, "
+                f"summed kernel time {busy / 1e6:.2f} ms (the leaf inverse runs on a second stream, so "
+                f"kernels overlap; the profiler adds time between launches).\n\n")
+        f.write("| kernel | calls | total ms | avg us | % of summed |\n|---|---:|---:|---:|---:|\n")
+        for n, (c, d) in sorted(agg.items(), key=lambda x: -x[1][1]):
+            f.write(f"| `{n}` | {c} | {d / 1e6:.3f} | {d / c / 1e3:.1f} | {100 * d / busy:.1f} |\n")
+
+
+def _counter(path: str, name: str):
+    rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == name]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return rows
+
+
+def _calibration(rows, copy_mib: float) -> float:
+    """Known bytes / counted bytes of the probe copy: the first copy dispatch
+    before any library kernel whose count is at least a quarter of the
+    probe's size (smaller copies are the runtime's own)."""
+    want = copy_mib * 2 ** 20
+    for r in rows:
+        if "lif::" in r["Kernel_Name"]:
+            break
+        counted = float(r["Counter_Value"]) * 1024.0
+        if "copyBuffer" in r["Kernel_Name"] and counted >= 0.25 * want:
+            return want / counted
+    raise SystemExit("no probe copy dispatch before the first library kernel")
+
+
+def traffic(fetch: str, write: str, out: str, kernel: str, copy_mib: float, cmd: str, khash: str) -> None:
+    res = {"kernel": kernel, "command": cmd, "copy_probe_mib": copy_mib, "kernel_hash": khash}
+    for key, path, cname in (("fetch", fetch, "FETCH_SIZE"), ("write", write, "WRITE_SIZE")):
+        rows = _counter(path, cname)
+        scale = _calibration(rows, copy_mib)
+        vals = [float(r["Counter_Value"]) * 1024.0 for r in rows if _short(r["Kernel_Name"]).startswith(kernel)]
+        res[f"{key}_dispatches"] = len(vals)
+        res[f"{key}_bytes_per_dispatch_raw"] = sum(vals) / max(len(vals), 1)
+        res[f"{key}_calibration"] = scale
+        res[f"{key}_bytes_per_dispatch"] = scale * sum(vals) / max(len(vals), 1)
+    res["bytes_per_launch"] = res["fetch_bytes_per_dispatch"] + res["write_bytes_per_dispatch"]
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1)
+        f.write("\n")
+
+
+def main() -> None:
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("trace")
+    s.add_argument("out")
+    s.add_argument("--title", required=True)
+    s.add_argument("--cmd", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch")
+    t.add_argument("write")
+    t.add_argument("out")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--copy-mib", type=float, required=True)
+    t.add_argument("--cmd", required=True)
+    t.add_argument("--hash", default="")
+    a = ap.parse_args()
+    if a.what == "stats":
+        stats(a.trace, a.out, a.title, a.cmd)
+    else:
+        traffic(a.fetch, a.write, a.out, a.kernel, a.copy_mib, a.cmd, a.hash)
+
+
+if __name__ == "__main__":
+    main()
