@@ -114,41 +114,53 @@ __device__ __attribute__((always_inline)) inline void wave_lds_fence() {
 // W = U^{-1} is built column block by column block from
 //   W_rp = -(sum_{s=r}^{p-1} W_rs U_sp) V_pp,
 // so the inverse costs no extra step.  Three barriers per sub-block column.
+// NT threads (a multiple of 64) run it; LDS layout in PotrfLds.
 template <int B>
-__global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nbbv, const int* __restrict__ blk0,
-                                               const int64_t* __restrict__ tile0, double* __restrict__ U,
-                                               double* __restrict__ Z, const unsigned char* __restrict__ nz,
-                                               int* __restrict__ err) {
-  constexpr int L = B + 1;
-  constexpr int NS = B / 16;
-  constexpr int YL = 17;
-  __shared__ double T[B * L];
-  __shared__ double W[B * L];
-  __shared__ double Y[NS * 16 * YL];
-  __shared__ __attribute__((aligned(16))) double rowbuf[16];
-  const int s = blockIdx.x;
-  const int nbb = nbbv[s];
-  if (k >= nbb) return;
-  const int64_t t = packed_tile(tile0[s], nbb, k, k);
-  double* g = U + t * B * B;
-  {
-    // all loads of the tile in flight before the first LDS store
-    constexpr int NV = B * B / 2 / 256;
-    v2d r[NV];
-    const v2d* gv = reinterpret_cast<const v2d*>(g);
-    // a diagonal tile S does not have reads as zero (and fails as not
-    // positive definite); the buffer is not cleared beforehand
-    const bool have = nz[t] != 0;
+struct PotrfLds {
+  static constexpr int L = B + 1;
+  static constexpr int NS = B / 16;
+  static constexpr int YL = 17;
+  static constexpr int T_OFF = 0;
+  static constexpr int W_OFF = B * L;
+  static constexpr int Y_OFF = 2 * B * L;
+  static constexpr int R_OFF = (Y_OFF + NS * 16 * YL + 1) / 2 * 2;  // 16-byte aligned
+  static constexpr int DOUBLES = R_OFF + 16;
+};
+
+// T <- the tile at g (zeros when `have` is false: a diagonal tile S does not
+// have, which then fails as not positive definite)
+template <int B, int NT>
+__device__ __attribute__((always_inline)) inline void potrf_load(double* smem, const double* g, bool have) {
+  using Lay = PotrfLds<B>;
+  constexpr int NV = B * B / 2 / NT;
+  double* T = smem + Lay::T_OFF;
+  v2d r[NV];
+  const v2d* gv = reinterpret_cast<const v2d*>(g);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) r[v] = have ? gv[threadIdx.x + v * 256] : v2d{0.0, 0.0};
+  for (int v = 0; v < NV; ++v) r[v] = have ? gv[threadIdx.x + v * NT] : v2d{0.0, 0.0};
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int q = 2 * (threadIdx.x + v * 256);
-      T[(q / B) * L + (q % B)] = r[v].x;
-      T[(q / B) * L + (q % B) + 1] = r[v].y;
-    }
+  for (int v = 0; v < NV; ++v) {
+    const int q = 2 * (threadIdx.x + v * NT);
+    T[(q / B) * Lay::L + (q % B)] = r[v].x;
+    T[(q / B) * Lay::L + (q % B) + 1] = r[v].y;
   }
-  __syncthreads();
+}
+
+// Factorizes T (in LDS, complete and visible to all threads) and writes U_kk
+// to g, Z_kk to gz; the first non-positive pivot is reported as global row
+// row0 + its index.
+template <int B, int NT>
+__device__ __attribute__((always_inline)) inline void potrf_tile(double* smem, double* __restrict__ g, double* __restrict__ gz, int row0,
+                           int* __restrict__ err_slot) {
+  using Lay = PotrfLds<B>;
+  constexpr int L = Lay::L;
+  constexpr int NS = Lay::NS;
+  constexpr int YL = Lay::YL;
+  constexpr int NW = NT / 64;
+  double* T = smem + Lay::T_OFF;
+  double* W = smem + Lay::W_OFF;
+  double* Y = smem + Lay::Y_OFF;
+  double* rowbuf = smem + Lay::R_OFF;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
   int bad = -1;  // first non-positive pivot (wave 0)
@@ -239,7 +251,7 @@ __global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nb
     // C: trailing blocks (q1, q2), p < q1 <= q2, then the Y blocks r = 0..p
     const int m = NS - 1 - p;
     const int ntrail = m * (m + 1) / 2;
-    for (int task = wave; task < ntrail + p + 1; task += 4) {
+    for (int task = wave; task < ntrail + p + 1; task += NW) {
       v4d acc = {0.0, 0.0, 0.0, 0.0};
       if (task < ntrail) {
         int q1 = 0, rem = task;
@@ -269,15 +281,35 @@ __global__ __launch_bounds__(256) void k_potrf(int k, const int* __restrict__ nb
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0 && bad >= 0) atomicMin(&err[s], (blk0[s] + k) * B + bad);
-  double* gz = Z + t * B * B;
+  if (threadIdx.x == 0 && bad >= 0) atomicMin(err_slot, row0 + bad);
 #pragma unroll
-  for (int v = 0; v < B * B / 2 / 256; ++v) {
-    const int q = 2 * (threadIdx.x + v * 256), r = q / B, cc = q % B;
+  for (int v = 0; v < B * B / 2 / NT; ++v) {
+    const int q = 2 * (threadIdx.x + v * NT), r = q / B, cc = q % B;
     reinterpret_cast<v2d*>(g)[q / 2] = v2d{(cc >= r) ? T[r * L + cc] : 0.0, (cc + 1 >= r) ? T[r * L + cc + 1] : 0.0};
     reinterpret_cast<v2d*>(gz)[q / 2] =
         v2d{(cc >= r) ? W[r * L + cc] : 0.0, (cc + 1 >= r) ? W[r * L + cc + 1] : 0.0};
   }
+}
+
+
+// Step k's diagonal tile, one workgroup per leaf (the first step; later
+// steps run inside the update kernel of the step before).
+template <int B>
+__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_potrf(int k, const int* __restrict__ nbbv,
+                                                               const int* __restrict__ blk0,
+                                                               const int64_t* __restrict__ tile0,
+                                                               double* __restrict__ U, double* __restrict__ Z,
+                                                               const unsigned char* __restrict__ nz,
+                                                               int* __restrict__ err) {
+  constexpr int NT = TileCfg<B>::THREADS;
+  __shared__ __attribute__((aligned(16))) double smem[PotrfLds<B>::DOUBLES];
+  const int s = blockIdx.x;
+  const int nbb = nbbv[s];
+  if (k >= nbb) return;
+  const int64_t t = packed_tile(tile0[s], nbb, k, k);
+  potrf_load<B, NT>(smem, U + t * B * B, nz[t] != 0);
+  __syncthreads();
+  potrf_tile<B, NT>(smem, U + t * B * B, Z + t * B * B, (blk0[s] + k) * B, &err[s]);
 }
 
 // blockIdx.x < m: U_kj = Z_kk^T U_kj for j = k + 1 + blockIdx.x (j - k <=
@@ -337,54 +369,83 @@ __device__ inline void tri_decode(int64_t t, int& ip, int& jp) {
 }
 
 // U_ij -= U_ki^T U_kj for k < i <= j <= k + band (the factor keeps the band
-// of S within a leaf)
+// of S within a leaf), and the next step's diagonal factorization: the
+// workgroup of tile (k+1, k+1) -- the last update that tile receives --
+// hands its result to potrf_tile in LDS instead of a separate launch.
 template <int B>
 __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_update(int k, int band, const int* __restrict__ nbbv,
+                                                                const int* __restrict__ blk0,
                                                                 const int64_t* __restrict__ tile0,
-                                                                double* __restrict__ U, unsigned char* __restrict__ nz) {
+                                                                double* __restrict__ U, double* __restrict__ Z,
+                                                                unsigned char* __restrict__ nz,
+                                                                int* __restrict__ err) {
   using Cfg = TileCfg<B>;
-  __shared__ double As[Cfg::LDS_DOUBLES];
-  __shared__ double Bs[Cfg::LDS_DOUBLES];
+  constexpr int NT = Cfg::THREADS;
+  constexpr int SMEM = (2 * Cfg::LDS_DOUBLES > PotrfLds<B>::DOUBLES) ? 2 * Cfg::LDS_DOUBLES : PotrfLds<B>::DOUBLES;
+  __shared__ __attribute__((aligned(16))) double smem[SMEM];
+  double* As = smem;
+  double* Bs = smem + Cfg::LDS_DOUBLES;
   const int s = blockIdx.y;
   const int nbb = nbbv[s];
   const int m = min(band, nbb - k - 1);
   const int64_t t = blockIdx.x;
-  if (m <= 0 || t >= (int64_t)m * (m + 1) / 2) return;
-  int ip, jp;
-  tri_decode(t, ip, jp);
+  const bool next_diag = t == 0 && k + 1 < nbb;  // this workgroup also factorizes tile (k+1, k+1)
+  const bool in_band = m > 0 && t < (int64_t)m * (m + 1) / 2;
+  if (!next_diag && !in_band) return;
+  int ip = 0, jp = 0;
+  if (in_band) tri_decode(t, ip, jp);
   const int i = k + 1 + ip, j = k + 1 + jp;
-  if (!nz[packed_tile(tile0[s], nbb, k, i)] || !nz[packed_tile(tile0[s], nbb, k, j)]) return;
-  const Frag f = frag_coords<B>();
-  // a tile outside S's pattern that no earlier step reached holds no data
-  // yet (the buffer is not cleared): its first update writes -acc
   const int64_t tij = packed_tile(tile0[s], nbb, i, j);
-  const bool first = !nz[tij];
   double* g = U + tij * B * B;
-  // the target's elements this lane updates, loaded with the operands
-  double old[2][2][4];
+  const bool upd = in_band && nz[packed_tile(tile0[s], nbb, k, i)] && nz[packed_tile(tile0[s], nbb, k, j)];
+  if (upd) {
+    const Frag f = frag_coords<B>();
+    // a tile outside S's pattern that no earlier step reached holds no data
+    // yet (the buffer is not cleared): its first update writes -acc
+    const bool first = !nz[tij];
+    // the target's elements this lane updates, loaded with the operands
+    double old[2][2][4];
 #pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
+    for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
+      for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) old[ti][tj][r] = first ? 0.0 : g[acc_row(f, ti, r) * B + acc_col(f, tj)];
-  v2d ra[Cfg::V2], rb[Cfg::V2];
-  tile_load<B>(U + packed_tile(tile0[s], nbb, k, i) * B * B, ra);
-  tile_load<B>(U + packed_tile(tile0[s], nbb, k, j) * B * B, rb);
-  tile_store<B>(As, ra, true);  // op(A) = U_ki^T
-  tile_store<B>(Bs, rb, true);
-  __syncthreads();
-  v4d acc[2][2];
-  acc_zero(acc);
-  tile_mma<B>(As, Bs, f, acc);
+        for (int r = 0; r < 4; ++r) old[ti][tj][r] = first ? 0.0 : g[acc_row(f, ti, r) * B + acc_col(f, tj)];
+    v2d ra[Cfg::V2], rb[Cfg::V2];
+    tile_load<B>(U + packed_tile(tile0[s], nbb, k, i) * B * B, ra);
+    tile_load<B>(U + packed_tile(tile0[s], nbb, k, j) * B * B, rb);
+    tile_store<B>(As, ra, true);  // op(A) = U_ki^T
+    tile_store<B>(Bs, rb, true);
+    __syncthreads();
+    v4d acc[2][2];
+    acc_zero(acc);
+    tile_mma<B>(As, Bs, f, acc);
+    __syncthreads();  // every fragment read and flag read done: LDS and nz may change
+    if (next_diag) {
+      double* T = smem + PotrfLds<B>::T_OFF;
 #pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
+      for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
+        for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) g[acc_row(f, ti, r) * B + acc_col(f, tj)] = old[ti][tj][r] - acc[ti][tj][r];
-  __syncthreads();  // every thread has read the flag before it is set
-  if (threadIdx.x == 0) nz[tij] = 1;
+          for (int r = 0; r < 4; ++r)
+            T[acc_row(f, ti, r) * PotrfLds<B>::L + acc_col(f, tj)] = old[ti][tj][r] - acc[ti][tj][r];
+    } else {
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) g[acc_row(f, ti, r) * B + acc_col(f, tj)] = old[ti][tj][r] - acc[ti][tj][r];
+    }
+    if (threadIdx.x == 0) nz[tij] = 1;
+  } else if (next_diag) {
+    potrf_load<B, NT>(smem, g, nz[tij] != 0);
+  }
+  if (next_diag) {
+    __syncthreads();
+    potrf_tile<B, NT>(smem, g, Z + tij * B * B, (blk0[s] + k + 1) * B, &err[s]);
+  }
 }
 
 // Z_ij = -sum_{k=i}^{j-1} Z_ik V_kj for i = blockIdx.x < j, V_kj = U_kj Z_jj
@@ -468,9 +529,11 @@ void launch_chol_pad(Ctx& c, int nbase, const int* nbb, const int* rows, const i
 void launch_potrf(Ctx& c, int k, int nbase, const int* nbb, const int* blk0, const int64_t* tile0, int b, double* U,
                   double* Z, const unsigned char* nz, int* err) {
   if (b == 64)
-    LIF_LAUNCH(k_potrf<64>, dim3(nbase), dim3(256), 0, c.stream, k, nbb, blk0, tile0, U, Z, nz, err);
+    LIF_LAUNCH(k_potrf<64>, dim3(nbase), dim3(TileCfg<64>::THREADS), 0, c.stream, k, nbb, blk0, tile0, U, Z, nz,
+               err);
   else
-    LIF_LAUNCH(k_potrf<32>, dim3(nbase), dim3(256), 0, c.stream, k, nbb, blk0, tile0, U, Z, nz, err);
+    LIF_LAUNCH(k_potrf<32>, dim3(nbase), dim3(TileCfg<32>::THREADS), 0, c.stream, k, nbb, blk0, tile0, U, Z, nz,
+               err);
 }
 
 void launch_trsm(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b,
@@ -485,15 +548,16 @@ void launch_trsm(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb
     LIF_LAUNCH(k_trsm<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, k, m, band, nbb, tile0, U, Z, nz);
 }
 
-void launch_update(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b,
-                   double* U, unsigned char* nz) {
-  const int64_t m = std::min(band, max_nbb - k - 1);
-  if (m <= 0) return;
-  dim3 grid((unsigned)(m * (m + 1) / 2), nbase);
+void launch_update(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int* blk0,
+                   const int64_t* tile0, int b, double* U, double* Z, unsigned char* nz, int* err) {
+  const int64_t m = std::max(0, std::min(band, max_nbb - k - 1));
+  const int64_t tasks = std::max<int64_t>(m * (m + 1) / 2, k + 1 < max_nbb ? 1 : 0);
+  if (tasks <= 0) return;
+  dim3 grid((unsigned)tasks, nbase);
   if (b == 64)
-    LIF_LAUNCH(k_update<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, k, band, nbb, tile0, U, nz);
+    LIF_LAUNCH(k_update<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, k, band, nbb, blk0, tile0, U, Z, nz, err);
   else
-    LIF_LAUNCH(k_update<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, k, band, nbb, tile0, U, nz);
+    LIF_LAUNCH(k_update<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, k, band, nbb, blk0, tile0, U, Z, nz, err);
 }
 
 void launch_trinv(Ctx& c, int j, int band, int nbase, const int* nbb, const int64_t* tile0, int b, const double* U,

@@ -318,8 +318,9 @@ void launch_potrf(Ctx& c, int k, int nbase, const int* nbb, const int* blk0, con
 // the factor's nonzero tiles satisfy j - i <= band as well
 void launch_trsm(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b,
                  double* U, const double* Z, const unsigned char* nz);
-void launch_update(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b,
-                   double* U, unsigned char* nz);
+// update of step k and the diagonal factorization of step k + 1
+void launch_update(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int* blk0,
+                   const int64_t* tile0, int b, double* U, double* Z, unsigned char* nz, int* err);
 void launch_trinv(Ctx& c, int j, int band, int nbase, const int* nbb, const int64_t* tile0, int b, const double* U,
                   double* Z, const unsigned char* nz);
 

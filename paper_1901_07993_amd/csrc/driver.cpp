@@ -392,14 +392,16 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   // (serial, small) factorization steps.
   hipStream_t side = c.side_stream();
   hipStream_t main_stream = c.stream;
+  // step 0's diagonal tile; every later one is factorized by the update
+  // kernel of the step before (the workgroup of the last update it receives)
+  launch_potrf(c, 0, nbase, d_nbb.get(), d_blk0.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get(), d_err.get());
   for (int k = 0; k < max_nbb; ++k) {
-    launch_potrf(c, k, nbase, d_nbb.get(), d_blk0.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get(),
-                 d_err.get());
     launch_trsm(c, k, band, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get());
     hipEvent_t ev = c.order_event((size_t)k);
     if (k > 0) LIF_HIP(hipEventRecord(ev, main_stream));
     // the next step's inputs first, then the side stream's inverse column
-    launch_update(c, k, band, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), nz.get());
+    launch_update(c, k, band, nbase, max_nbb, d_nbb.get(), d_blk0.get(), d_tile0.get(), b, U.get(), zs->get(),
+                  nz.get(), d_err.get());
     if (k > 0) {
       LIF_HIP(hipStreamWaitEvent(side, ev, 0));
       struct OnSide {  // launches go to the side stream within this scope
