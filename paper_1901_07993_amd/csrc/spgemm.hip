@@ -222,41 +222,57 @@ struct OutMap {
   __device__ static int col(const Frag& f, int tj, int m) { return CI ? f.cb + 2 * m + tj : f.cb + 16 * tj + m; }
 };
 
-// The block alpha A B + gamma D (Epilogue), its FP64 sum of squares in a
-// fixed order, its norm and its pointer.
+// D's elements at the positions this lane holds of C (zeros without D),
+// loaded before the products so that they arrive during them.
 template <int B, bool TA, bool TB>
+__device__ __attribute__((always_inline)) inline void load_d(const Frag& f, const double* __restrict__ Db,
+                                                             double (&d)[2][2][4]) {
+  using M = OutMap<B, TA, TB>;
+  if (Db) {  // uniform across the workgroup
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double* q = Db + M::row(f, ti, 4 * r + f.kq) * B;
+        if (M::CI) {
+          const v2d dv = *reinterpret_cast<const v2d*>(q + M::col(f, 0, f.l16));
+          d[ti][0][r] = dv.x;
+          d[ti][1][r] = dv.y;
+        } else {
+          d[ti][0][r] = q[M::col(f, 0, f.l16)];
+          d[ti][1][r] = q[M::col(f, 1, f.l16)];
+        }
+      }
+  } else {
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) d[ti][tj][r] = 0.0;
+  }
+}
+
+// The block alpha A B (+ gamma D when HAS_D, D's elements in d), its FP64
+// sum of squares in a fixed order, its norm and its pointer.
+template <int B, bool TA, bool TB, bool HAS_D>
 __device__ __attribute__((always_inline)) inline void numeric_epilogue(const v4d (&acc)[2][2], const Frag& f,
                                                                        int64_t blk, double* __restrict__ C,
                                                                        BlkOut Cp, double* __restrict__ norms,
-                                                                       const Epilogue& epi, double* red) {
+                                                                       const Epilogue& epi,
+                                                                       const double (&d)[2][2][4], double* red) {
   using Cfg = TileCfg<B>;
   using M = OutMap<B, TA, TB>;
-  // C = alpha A B (+ gamma D), D's elements loaded where this lane holds C's
-  const double* Db = epi.dsrc ? epi.dsrc[blk] : nullptr;
   double v[2][2][4];
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = M::row(f, ti, 4 * r + f.kq);
-      double d0 = 0.0, d1 = 0.0;
-      if (Db) {
-        if (M::CI) {
-          const v2d dv = *reinterpret_cast<const v2d*>(Db + row * B + M::col(f, 0, f.l16));
-          d0 = dv.x;
-          d1 = dv.y;
-        } else {
-          d0 = Db[row * B + M::col(f, 0, f.l16)];
-          d1 = Db[row * B + M::col(f, 1, f.l16)];
-        }
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        v[ti][tj][r] = epi.alpha * acc[ti][tj][r];
+        if (HAS_D) v[ti][tj][r] += epi.gamma * d[ti][tj][r];
       }
-      v[ti][0][r] = epi.alpha * acc[ti][0][r];
-      v[ti][1][r] = epi.alpha * acc[ti][1][r];
-      if (Db) {
-        v[ti][0][r] += epi.gamma * d0;
-        v[ti][1][r] += epi.gamma * d1;
-      }
-    }
   double ss = 0.0;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
@@ -297,7 +313,7 @@ __device__ __attribute__((always_inline)) inline void numeric_epilogue(const v4d
 // each other's load latency -- on the sparse products of the refinement
 // (one to three block products per output block) and on dense ones (219
 // per block) alike this beat a double-buffered two-tile LDS pipeline.
-template <int B, bool TA, bool TB>
+template <int B, bool TA, bool TB, bool HAS_D>
 __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const int64_t* __restrict__ seg,
                                                                         const BlockPair* __restrict__ pairs,
                                                                         const int* __restrict__ live,
@@ -314,6 +330,8 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const int64
   const int64_t blk = xcd_remap(blockIdx.x, nlive);
   const int64_t p0 = seg[blk], p1 = seg[blk + 1];
   const Frag f = frag_coords<B>();
+  double d[2][2][4];
+  if (HAS_D) load_d<B, TA, TB>(f, epi.dsrc[blk], d);
   v4d acc[2][2];
   acc_zero(acc);
   for (int64_t p = p0; p < p1; ++p) {
@@ -354,25 +372,33 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const int64
       acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
   }
-  numeric_epilogue<B, TA, TB>(acc, f, blk, C, Cp, norms, epi, red);
+  numeric_epilogue<B, TA, TB, HAS_D>(acc, f, blk, C, Cp, norms, epi, d, red);
+}
+
+template <int B, bool TA, bool TB>
+void launch_numeric_t(Ctx& c, dim3 grid, const int64_t* seg, const BlockPair* pairs, const int* live, double* C,
+                      BlkOut Cp, double* norms, const Epilogue& epi) {
+  const dim3 block(TileCfg<B>::THREADS);
+  if (epi.dsrc)
+    hipLaunchKernelGGL((k_numeric_f64<B, TA, TB, true>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms,
+                       epi);
+  else
+    hipLaunchKernelGGL((k_numeric_f64<B, TA, TB, false>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms,
+                       epi);
 }
 
 template <int B>
 void launch_numeric_b(Ctx& c, bool ta, bool tb, const int64_t* seg, const BlockPair* pairs, int64_t nnzc,
                       const int* live, double* C, BlkOut Cp, double* norms, const Epilogue& epi) {
-  const dim3 grid((unsigned)nnzc), block(TileCfg<B>::THREADS);
+  const dim3 grid((unsigned)nnzc);
   if (!ta && !tb)
-    hipLaunchKernelGGL((k_numeric_f64<B, false, false>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms,
-                       epi);
+    launch_numeric_t<B, false, false>(c, grid, seg, pairs, live, C, Cp, norms, epi);
   else if (ta && !tb)
-    hipLaunchKernelGGL((k_numeric_f64<B, true, false>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms,
-                       epi);
+    launch_numeric_t<B, true, false>(c, grid, seg, pairs, live, C, Cp, norms, epi);
   else if (!ta && tb)
-    hipLaunchKernelGGL((k_numeric_f64<B, false, true>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms,
-                       epi);
+    launch_numeric_t<B, false, true>(c, grid, seg, pairs, live, C, Cp, norms, epi);
   else
-    hipLaunchKernelGGL((k_numeric_f64<B, true, true>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms,
-                       epi);
+    launch_numeric_t<B, true, true>(c, grid, seg, pairs, live, C, Cp, norms, epi);
   LIF_HIP(hipGetLastError());
 }
 
