@@ -49,6 +49,11 @@ class Pool {
   void* alloc(size_t bytes);
   void free(void* p);
   void trim();            // return cached (unused) memory to HIP
+  // While deferring, freed buffers are held back from reuse until
+  // release_deferred(): work on two streams may still read a buffer the host
+  // has released, and reuse is only safe after both streams have synchronized.
+  void set_defer(bool on) { defer_ = on; }
+  void release_deferred();
   uint64_t in_use() const { return in_use_; }
   uint64_t reserved() const { return reserved_; }
   uint64_t peak() const { return peak_; }
@@ -60,6 +65,8 @@ class Pool {
   uint64_t in_use_ = 0, reserved_ = 0, peak_ = 0;
   std::multimap<size_t, void*> cache_;
   std::map<void*, size_t> live_;
+  bool defer_ = false;
+  std::vector<void*> deferred_;
 };
 
 template <typename T>
@@ -196,6 +203,10 @@ struct Ctx {
   std::vector<hipEvent_t> order_events;
   hipStream_t side_stream();
   hipEvent_t order_event(size_t i);  // the i-th reusable ordering event
+  // `waiter` waits for the work queued so far on `signaler`
+  void stream_after(hipStream_t waiter, hipStream_t signaler);
+  std::vector<hipEvent_t> ring_events;
+  size_t next_order = 0;
   void flush_timing();
   void sync() { LIF_HIP(hipStreamSynchronize(stream)); }
   // copy `bytes` from device `src` through the pinned buffer; synchronizes
@@ -208,6 +219,38 @@ struct Ctx {
   };
   void d2h_batch(const std::vector<Read>& reads);
   ~Ctx();
+};
+
+// Launches within the scope go to stream s.
+struct StreamScope {
+  Ctx& c;
+  hipStream_t keep;
+  StreamScope(Ctx& ctx, hipStream_t s) : c(ctx), keep(ctx.stream) { c.stream = s; }
+  ~StreamScope() { c.stream = keep; }
+  StreamScope(const StreamScope&) = delete;
+  StreamScope& operator=(const StreamScope&) = delete;
+};
+
+// Buffers freed within the scope are reused only after release(), which the
+// caller invokes once the host has synchronized with every stream; on an
+// early exit the destructor synchronizes the device first.
+struct DeferFrees {
+  Ctx& c;
+  bool active = true;
+  explicit DeferFrees(Ctx& ctx) : c(ctx) { c.pool->set_defer(true); }
+  void release() {
+    if (!active) return;
+    c.pool->set_defer(false);
+    c.pool->release_deferred();
+    active = false;
+  }
+  ~DeferFrees() {
+    if (!active) return;
+    (void)hipDeviceSynchronize();
+    release();
+  }
+  DeferFrees(const DeferFrees&) = delete;
+  DeferFrees& operator=(const DeferFrees&) = delete;
 };
 
 // ---------------------------------------------------------------------------

@@ -149,12 +149,27 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       }
       Bsr M = spgemm(c, Z, false, q, false, o.tau, o.prec);
       q = Bsr();
-      Znew = axpby(c, 1.0, &Z, 1.0, &M, 0.0, nullptr);
       // delta_{k+1} = delta_k - Z_{k+1}^T (S M) - (S M)^T Z_k   (M^T S = (S M)^T)
-      Bsr SM = spgemm(c, S, false, M, false, o.tau);
-      M = Bsr();
+      // S M and then (S M)^T Z_k run on the side stream while Z + M and then
+      // Z_{k+1}^T (S M) run on the main one; buffers freed meanwhile are
+      // reused only after the synchronization at the end of the iteration.
+      DeferFrees defer(c);
+      const hipStream_t main_s = c.stream, side_s = c.side_stream();
+      c.stream_after(side_s, main_s);
+      Bsr SM, X2;
+      {
+        StreamScope on_side(c, side_s);
+        SM = spgemm(c, S, false, M, false, o.tau);
+      }
+      Znew = axpby(c, 1.0, &Z, 1.0, &M, 0.0, nullptr);
+      c.stream_after(main_s, side_s);  // S M is complete
+      {
+        StreamScope on_side(c, side_s);
+        X2 = spgemm(c, SM, true, Z, false, o.tau);
+      }
       Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau);
-      Bsr X2 = spgemm(c, SM, true, Z, false, o.tau);
+      c.stream_after(main_s, side_s);  // (S M)^T Z_k is complete
+      M = Bsr();
       SM = Bsr();
       dnew = axpby3(c, 1.0, &delta, -1.0, &X1, -1.0, &X2);
       X1 = Bsr();
@@ -174,6 +189,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
           extra.push_back({sz.data() + i, c.spec.sizes.get() + i, sizeof(int64_t) * std::min<size_t>(8, sz.size() - i)});
       }
       ss = node_sumsq(c, dnew, d_rlo.get(), d_rhi.get(), nn, extra);
+      defer.release();  // both streams are idle: the main one waited for the side one
       Znew.nnzb = nz_new;
       if (planned && over) {
         ++c.stats.redone;
@@ -404,12 +420,7 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
                   nz.get(), d_err.get());
     if (k > 0) {
       LIF_HIP(hipStreamWaitEvent(side, ev, 0));
-      struct OnSide {  // launches go to the side stream within this scope
-        Ctx& c;
-        hipStream_t keep;
-        ~OnSide() { c.stream = keep; }
-      } on_side{c, main_stream};
-      c.stream = side;
+      StreamScope on_side(c, side);
       launch_trinv(c, k, band, nbase, d_nbb.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get());
     }
   }

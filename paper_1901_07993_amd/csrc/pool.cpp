@@ -49,9 +49,21 @@ void* Pool::alloc(size_t bytes) {
 void Pool::free(void* p) {
   auto it = live_.find(p);
   if (it == live_.end()) return;
+  if (defer_) {
+    deferred_.push_back(p);
+    return;
+  }
   in_use_ -= it->second;
   cache_.emplace(it->second, p);
   live_.erase(it);
+}
+
+void Pool::release_deferred() {
+  const bool keep = defer_;
+  defer_ = false;
+  for (void* p : deferred_) free(p);
+  deferred_.clear();
+  defer_ = keep;
 }
 
 void Pool::trim() {
@@ -159,12 +171,27 @@ hipEvent_t Ctx::order_event(size_t i) {
   return order_events[i];
 }
 
+void Ctx::stream_after(hipStream_t waiter, hipStream_t signaler) {
+  // a ring of events, far larger than the number of waits in flight between
+  // two synchronizations of the host with the device
+  if (ring_events.size() < 64) {
+    hipEvent_t e = nullptr;
+    LIF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ring_events.push_back(e);
+  }
+  hipEvent_t e = ring_events[next_order % ring_events.size()];
+  ++next_order;
+  LIF_HIP(hipEventRecord(e, signaler));
+  LIF_HIP(hipStreamWaitEvent(waiter, e, 0));
+}
+
 Ctx::~Ctx() {
   if (side) {
     (void)hipStreamSynchronize(side);
     (void)hipStreamDestroy(side);
   }
   for (auto e : order_events) (void)hipEventDestroy(e);
+  for (auto e : ring_events) (void)hipEventDestroy(e);
   for (auto& pr : ev_pending) {
     (void)hipEventDestroy(pr.first);
     (void)hipEventDestroy(pr.second);
