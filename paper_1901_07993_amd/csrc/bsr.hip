@@ -154,11 +154,19 @@ __global__ __launch_bounds__(1024) void k_max_reduce(const double* __restrict__ 
 }
 
 // Union of the sorted column lists of up to three operands' row i, plus
-// column i when diag_on[i] is set.  Absent operands have null pointers.
+// column i when diag_on[i] is set.  Absent operands have null pointers; an
+// operand with holes gives its block pointers in `hole`, and its null
+// blocks are skipped.
 struct Src3 {
   const int* rp[3];
   const int* col[3];
+  BlkIn hole[3];
 };
+
+__device__ inline void skip_holes(const Src3& S, int t, int& p, int e) {
+  if (S.hole[t])
+    while (p < e && !S.hole[t][p]) ++p;
+}
 
 __device__ inline int union_row(const Src3& S, const unsigned char* diag_on, int i, int* cc, int* ix,
                                 int64_t stride, unsigned char* id, int* rowof) {
@@ -167,6 +175,7 @@ __device__ inline int union_row(const Src3& S, const unsigned char* diag_on, int
   for (int t = 0; t < 3; ++t) {
     p[t] = S.rp[t] ? S.rp[t][i] : 0;
     e[t] = S.rp[t] ? S.rp[t][i + 1] : 0;
+    skip_holes(S, t, p[t], e[t]);
   }
   bool dg = diag_on && diag_on[i];
   int o = 0;
@@ -184,7 +193,10 @@ __device__ inline int union_row(const Src3& S, const unsigned char* diag_on, int
     for (int t = 0; t < 3; ++t) {
       const bool hit = p[t] < e[t] && S.col[t][p[t]] == x;
       if (cc) ix[t * stride + o] = hit ? p[t] : -1;
-      if (hit) ++p[t];
+      if (hit) {
+        ++p[t];
+        skip_holes(S, t, p[t], e[t]);
+      }
     }
     if (dg && x == i) dg = false;
     ++o;
@@ -207,6 +219,80 @@ __global__ void k_union_fill(Src3 S, const unsigned char* diag_on, const int* rc
   if (i >= nb) return;
   int o = rc[i];
   union_row(S, diag_on, i, cc + o, ix + o, stride, id + o, rowof + o);
+}
+
+// The same union with one wave per block row: the operands' columns are
+// marked in LDS bitmaps (one per operand; the index of each marked column in
+// its operand kept in an nb-long LDS map), the union is their OR, and the
+// output positions come from popcounts of the OR's words -- the row's
+// entries are handled in parallel instead of merged one by one.
+constexpr int kUR = 64;
+
+inline size_t union_rows_lds(int nb, bool fill) {
+  const size_t nwords = (size_t)(nb + 31) / 32;
+  return fill ? (4 * nwords + 3 * (size_t)nb) * 4 : 3 * nwords * 4;
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(kUR) void k_union_rows(Src3 S, const unsigned char* __restrict__ diag_on, int nb,
+                                                    int* __restrict__ counts, int* __restrict__ slot,
+                                                    const int* __restrict__ rc, int* __restrict__ cc,
+                                                    int* __restrict__ ix, int64_t stride,
+                                                    unsigned char* __restrict__ id, int* __restrict__ rowof) {
+  extern __shared__ unsigned smem[];
+  __shared__ int scan_tmp[1];
+  const int i = blockIdx.x;
+  const int nwords = (nb + 31) >> 5;
+  unsigned* bm = smem;                              // [3][nwords]
+  int* c2i = reinterpret_cast<int*>(smem + 4 * nwords);  // [3][nb] (fill)
+  if (!FILL && slot && i == 0 && threadIdx.x == 0) *slot = 0;
+  for (int w = threadIdx.x; w < 3 * nwords; w += kUR) bm[w] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (!S.rp[t]) continue;
+    const int hi = S.rp[t][i + 1];
+    for (int p = S.rp[t][i] + threadIdx.x; p < hi; p += kUR) {
+      if (S.hole[t] && !S.hole[t][p]) continue;
+      const int j = S.col[t][p];
+      atomicOr(&bm[t * nwords + (j >> 5)], 1u << (j & 31));
+      if (FILL) c2i[t * nb + j] = p;
+    }
+  }
+  const bool dg = diag_on && diag_on[i];
+  __syncthreads();
+  const unsigned dbit = 1u << (i & 31);
+  auto word = [&](int w) {
+    unsigned u = bm[w] | bm[nwords + w] | bm[2 * nwords + w];
+    if (dg && (i >> 5) == w) u |= dbit;
+    return u;
+  };
+  const int chunk = (nwords + kUR - 1) / kUR;  // contiguous words per lane
+  const int w0 = min(nwords, (int)threadIdx.x * chunk), w1 = min(nwords, w0 + chunk);
+  int s = 0;
+  for (int w = w0; w < w1; ++w) s += __popc(word(w));
+  if (!FILL) {
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (threadIdx.x == 0) counts[i] = s;
+    return;
+  }
+  int total;
+  int r = rc[i] + block_exclusive_scan<int, kUR>(s, scan_tmp, &total);
+  for (int w = w0; w < w1; ++w) {
+    unsigned bits = word(w);
+    while (bits) {
+      const int bit = __ffs(bits) - 1;
+      const int j = (w << 5) + bit;
+      cc[r] = j;
+      id[r] = (dg && j == i) ? 1 : 0;
+      rowof[r] = i;
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        ix[t * stride + r] = (S.rp[t] && ((bm[t * nwords + w] >> bit) & 1u)) ? c2i[t * nb + j] : -1;
+      ++r;
+      bits &= bits - 1;
+    }
+  }
 }
 
 struct Val3 {
@@ -609,22 +695,39 @@ void launch_max_reduce(Ctx& c, const double* in, int count, double* out) {
   LIF_LAUNCH(k_max_reduce, dim3(1), dim3(1024), 0, c.stream, in, count, out);
 }
 
-void launch_union3(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on, int nb,
-                   int* counts, int* slot) {
+// the row-parallel union while its LDS stays within the default limit
+// (block rows nb up to about 4000); the per-thread merge above that
+constexpr size_t kUnionRowsLds = 48 * 1024;
+
+void launch_union3(Ctx& c, const int* const rp[3], const int* const col[3], const BlkIn hole[3],
+                   const unsigned char* diag_on, int nb, int* counts, int* slot) {
   Src3 S;
   for (int t = 0; t < 3; ++t) {
     S.rp[t] = rp[t];
     S.col[t] = col[t];
+    S.hole[t] = hole[t];
+  }
+  if (union_rows_lds(nb, true) <= kUnionRowsLds) {
+    LIF_LAUNCH(k_union_rows<false>, dim3(nb), dim3(kUR), union_rows_lds(nb, false), c.stream, S, diag_on, nb, counts,
+               slot, nullptr, nullptr, nullptr, 0, nullptr, nullptr);
+    return;
   }
   LIF_LAUNCH(k_union_counts, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, S, diag_on, nb, counts, slot);
 }
 
-void launch_union3_fill(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on,
-                        const int* rc, int nb, int* cc, int* ix, int64_t stride, unsigned char* id, int* rowof) {
+void launch_union3_fill(Ctx& c, const int* const rp[3], const int* const col[3], const BlkIn hole[3],
+                        const unsigned char* diag_on, const int* rc, int nb, int* cc, int* ix, int64_t stride,
+                        unsigned char* id, int* rowof) {
   Src3 S;
   for (int t = 0; t < 3; ++t) {
     S.rp[t] = rp[t];
     S.col[t] = col[t];
+    S.hole[t] = hole[t];
+  }
+  if (union_rows_lds(nb, true) <= kUnionRowsLds) {
+    LIF_LAUNCH(k_union_rows<true>, dim3(nb), dim3(kUR), union_rows_lds(nb, true), c.stream, S, diag_on, nb, nullptr,
+               nullptr, rc, cc, ix, stride, id, rowof);
+    return;
   }
   LIF_LAUNCH(k_union_fill, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, S, diag_on, rc, nb, cc, ix, stride, id,
              rowof);

@@ -137,6 +137,10 @@ struct Bsr {
   DBuf<int> col;
   DBuf<const double*> blk;   // [cap] value block pointers
   std::vector<Store> store;  // value arrays the pointers point into (kept alive)
+  // A product whose dropped blocks (norm below the threshold) were not
+  // compacted away: their pointers are null and they count as absent.  Only
+  // products, sums and transposed views read such a matrix.
+  bool holes = false;
   int64_t bound() const { return nnzb >= 0 ? nnzb : cap; }
   const int* live() const { return row_ptr.get() + nb; }  // device-side count
   BlkIn ptrs() const { return blk.get(); }
@@ -280,10 +284,13 @@ void launch_gather_values(Ctx& c, BlkIn blk, int64_t nnzb, int b, double* out, c
 void launch_gershgorin(Ctx& c, const int* row_ptr, BlkIn blk, int nb, int b, double* row_max);
 void launch_max_reduce(Ctx& c, const double* in, int count, double* out);
 // per-row counts of the union; also zeroes *slot (nullable) for the values pass
-void launch_union3(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on, int nb,
-                   int* counts, int* slot);
-void launch_union3_fill(Ctx& c, const int* const rp[3], const int* const col[3], const unsigned char* diag_on,
-                        const int* rc, int nb, int* cc, int* ix, int64_t stride, unsigned char* id, int* rowof);
+// hole[t]: the block pointers of an operand with holes (null otherwise);
+// its null blocks are skipped
+void launch_union3(Ctx& c, const int* const rp[3], const int* const col[3], const BlkIn hole[3],
+                   const unsigned char* diag_on, int nb, int* counts, int* slot);
+void launch_union3_fill(Ctx& c, const int* const rp[3], const int* const col[3], const BlkIn hole[3],
+                        const unsigned char* diag_on, const int* rc, int nb, int* cc, int* ix, int64_t stride,
+                        unsigned char* id, int* rowof);
 void launch_keep_count_scan(Ctx& c, const int* row_ptr, const double* norms, double tau, int nb, int* out_rp);
 void launch_filter_count_scan(Ctx& c, const int* row_ptr, const int* col, const int* rlab, const int* clab, int mode,
                               int nb, int* out_rp);
@@ -323,25 +330,34 @@ void launch_phi_diag(Ctx& c, const int* row_of, const int* col, int64_t nnzb, in
 // D (drp, dcol, dblk; nullable) joins the output pattern; the fill pass
 // then writes dsrc[e], D's block at output position e (null where D has
 // none).
-void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* brp, const int* bcol,
-                           const int* drp, const int* dcol, int nb, int* cnt_c, int64_t* cnt_p);
+// Operands with holes: `ahole`/`bhole` are their block pointers (null for an
+// operand without holes), indexed through aidx/bidx like ablk/bblk; a null
+// block takes no part in the product.
+void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp,
+                           const int* bcol, const int* bidx, BlkIn ahole, BlkIn bhole, const int* drp,
+                           const int* dcol, int nb, int* cnt_c, int64_t* cnt_p);
 void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp,
-                          const int* bcol, const int* bidx, BlkIn ablk, BlkIn bblk, const int* drp, const int* dcol,
-                          BlkIn dblk, int nb, const int* crp, const int64_t* prp, int* ccol, int64_t* seg,
-                          BlockPair* pairs, BlkOut dsrc);
+                          const int* bcol, const int* bidx, BlkIn ablk, BlkIn bblk, bool a_holes, bool b_holes,
+                          const int* drp, const int* dcol, BlkIn dblk, int nb, const int* crp, const int64_t* prp,
+                          int* ccol, int64_t* seg, BlockPair* pairs, BlkOut dsrc);
 // Fused terms of a product: the output block is alpha sum op(A) op(B)
 // + gamma D_e, D_e = dsrc[e] (skipped where null), and its norm is the norm
 // of that sum (truncation then applies to the whole block).
+// With `drop`, a block whose norm is below `tau` gets a null pointer (the
+// product keeps holes instead of being compacted).
 struct Epilogue {
   double alpha = 1.0;
   double gamma = 0.0;
   BlkIn dsrc = nullptr;
+  bool drop = false;
+  double tau = 0.0;
 };
 // Numeric phase: C_blk = sum over its segment of op(A_a) op(B_b), in FP64
 // (prec = LIF_FP64) or with FP32 / BF16 inputs and FP32 accumulation.
 // `nnzc` is the grid (the output capacity); `live` (device) the number of
 // output blocks actually present, <= nnzc.
-// Output block e is written to C + e b^2 and its pointer to Cp[e].
+// Output block e is written to C + e b^2, its pointer to Cp[e] and its
+// Frobenius norm to norms[e] (nullable).
 void launch_numeric(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg, const BlockPair* pairs,
                     int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms, const Epilogue& epi);
 // spgemm_mixed.hip
@@ -396,9 +412,11 @@ Bsr truncate(Ctx& c, Bsr&& A, const double* norms, double tau);
 CsrView transpose_view(Ctx& c, const Bsr& A);
 Bsr transpose(Ctx& c, const Bsr& A);
 // trunc_tau(alpha op(A) op(B) [+ gamma D]): the optional term D is added
-// block by block before the truncation
+// block by block before the truncation.  With `keep_holes` the dropped
+// blocks stay in the pattern with null pointers (Bsr::holes) instead of
+// being compacted away, for a result that only products and sums read.
 Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec = LIF_FP64,
-           double alpha = 1.0, const Bsr* D = nullptr, double gamma = 0.0);
+           double alpha = 1.0, const Bsr* D = nullptr, double gamma = 0.0, bool keep_holes = false);
 // alpha A + beta B + gamma I on the block rows with diag_on set (A or B may be null)
 Bsr axpby(Ctx& c, double alpha, const Bsr* A, double beta, const Bsr* B, double gamma,
           const unsigned char* diag_on);

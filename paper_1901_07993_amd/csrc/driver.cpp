@@ -130,6 +130,10 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       if (restrict_rows) dfilt = filter(c, delta, d_rowlab.get(), nullptr, 2);
       const Bsr& da = restrict_rows ? dfilt : delta;
 
+      // The products of one iteration are read only by the next product and
+      // by the two sums, so their dropped blocks are left as null pointers
+      // (holes) rather than compacted away.
+      constexpr bool kHoles = true;
       // M = Z sum_{k=1}^m b_k delta^k, Horner form, every product truncated:
       //   T_{m-1} = b_m delta + b_{m-1} I,  T_j = b_j I + trunc(delta T_{j+1}),
       //   q = trunc(delta T_1).
@@ -143,11 +147,12 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
         q = axpby(c, bk[1], &da, 0.0, nullptr, 0.0, nullptr);
       } else {
         // first product: delta (b_m delta + b_{m-1} I) = b_m delta^2 + b_{m-1} delta
-        Bsr X = spgemm(c, da, false, da, false, o.tau, o.prec, bk[o.m], &da, bk[o.m - 1]);
-        for (int j = o.m - 2; j >= 1; --j) X = spgemm(c, da, false, X, false, o.tau, o.prec, 1.0, &da, bk[j]);
+        Bsr X = spgemm(c, da, false, da, false, o.tau, o.prec, bk[o.m], &da, bk[o.m - 1], kHoles);
+        for (int j = o.m - 2; j >= 1; --j)
+          X = spgemm(c, da, false, X, false, o.tau, o.prec, 1.0, &da, bk[j], kHoles);
         q = std::move(X);
       }
-      Bsr M = spgemm(c, Z, false, q, false, o.tau, o.prec);
+      Bsr M = spgemm(c, Z, false, q, false, o.tau, o.prec, 1.0, nullptr, 0.0, kHoles);
       q = Bsr();
       // delta_{k+1} = delta_k - Z_{k+1}^T (S M) - (S M)^T Z_k   (M^T S = (S M)^T)
       // S M and then (S M)^T Z_k run on the side stream while Z + M and then
@@ -159,15 +164,15 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       Bsr SM, X2;
       {
         StreamScope on_side(c, side_s);
-        SM = spgemm(c, S, false, M, false, o.tau);
+        SM = spgemm(c, S, false, M, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles);
       }
       Znew = axpby(c, 1.0, &Z, 1.0, &M, 0.0, nullptr);
       c.stream_after(main_s, side_s);  // S M is complete
       {
         StreamScope on_side(c, side_s);
-        X2 = spgemm(c, SM, true, Z, false, o.tau);
+        X2 = spgemm(c, SM, true, Z, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles);
       }
-      Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau);
+      Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles);
       c.stream_after(main_s, side_s);  // (S M)^T Z_k is complete
       M = Bsr();
       SM = Bsr();

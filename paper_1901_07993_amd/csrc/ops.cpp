@@ -19,6 +19,11 @@ T read1(Ctx& c, const T* dev) {
   return v;
 }
 
+// operations that read every stored block take no matrix with holes
+void no_holes(const Bsr& A, const char* op) {
+  LIF_REQUIRE(!A.holes, LIF_ERR_INVALID, std::string(op) + ": operand with dropped blocks not compacted");
+}
+
 Bsr like(const Bsr& A) {
   Bsr C;
   C.n = A.n;
@@ -34,6 +39,7 @@ Store new_store(Ctx& c, int64_t blocks, int b) {
 }
 
 Bsr compact_values(Ctx& c, Bsr&& A) {
+  no_holes(A, "compact_values");
   const int64_t nnz = exact_nnzb(c, A);
   Store st = new_store(c, nnz, A.b);
   launch_gather_values(c, A.ptrs(), nnz, A.b, st->get(), nullptr);
@@ -84,6 +90,7 @@ Bsr bsr_from_blocks(Ctx& c, const lif_blocks& in) {
 }
 
 void bsr_to_blocks(Ctx& c, const Bsr& A, int32_t* brow, int32_t* bcol, double* vals, bool on_device) {
+  no_holes(A, "bsr_to_blocks");
   const int64_t nnz = exact_nnzb(c, A);
   if (nnz == 0) return;
   DBuf<int> rows(c.pool, (size_t)nnz);
@@ -109,6 +116,7 @@ Bsr copy(Ctx& c, const Bsr& A) {
   B.row_ptr = DBuf<int>(c.pool, A.nb + 1);
   B.col = DBuf<int>(c.pool, (size_t)B.cap);
   B.blk = DBuf<const double*>(c.pool, (size_t)B.cap);
+  B.holes = A.holes;
   B.share_store(A);  // the value blocks are shared, never written again
   LIF_HIP(hipMemcpyAsync(B.row_ptr.get(), A.row_ptr.get(), (A.nb + 1) * sizeof(int), hipMemcpyDeviceToDevice,
                          c.stream));
@@ -121,6 +129,7 @@ Bsr copy(Ctx& c, const Bsr& A) {
 }
 
 DBuf<double> block_norms(Ctx& c, const Bsr& A) {
+  no_holes(A, "block_norms");
   DBuf<double> nrm(c.pool, (size_t)A.bound());
   launch_block_sumsq(c, A.ptrs(), A.bound(), A.b, nrm.get(), true, A.live());
   return nrm;
@@ -129,6 +138,7 @@ DBuf<double> block_norms(Ctx& c, const Bsr& A) {
 // Sec. 5 truncation: drop blocks with Frobenius norm < tau, keep the order.
 // The kept count stays on the device; the capacity is the input's bound.
 Bsr truncate(Ctx& c, Bsr&& A, const double* norms, double tau) {
+  no_holes(A, "truncate");
   if (tau <= 0.0 || A.bound() == 0) return std::move(A);
   Bsr B = like(A);
   B.nnzb = -1;
@@ -166,6 +176,7 @@ CsrView transpose_view(Ctx& c, const Bsr& A) {
 }
 
 Bsr transpose(Ctx& c, const Bsr& A) {
+  no_holes(A, "transpose");
   CsrView v = transpose_view(c, A);
   Bsr T = like(A);
   T.nnzb = A.nnzb;
@@ -180,8 +191,9 @@ Bsr transpose(Ctx& c, const Bsr& A) {
 }
 
 Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec, double alpha,
-           const Bsr* D, double gamma) {
+           const Bsr* D, double gamma, bool keep_holes) {
   LIF_REQUIRE(A.nb == B.nb && A.b == B.b, LIF_ERR_INVALID, "spgemm: operand shapes differ");
+  LIF_REQUIRE(!D || !D->holes, LIF_ERR_INVALID, "spgemm: the added term has holes");
   const int nb = A.nb;
   Bsr C = like(A);
   CsrView av, bv;
@@ -202,7 +214,8 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
   if (D) LIF_REQUIRE(D->nb == nb && D->b == A.b, LIF_ERR_INVALID, "spgemm: added term's shape differs");
   const int* drp = D ? D->row_ptr.get() : nullptr;
   const int* dcol = D ? D->col.get() : nullptr;
-  launch_symbolic_count(c, av.rp, av.col, bv.rp, bv.col, drp, dcol, nb, cnt_c.get(), cnt_p.get());
+  launch_symbolic_count(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, A.holes ? A.ptrs() : nullptr,
+                        B.holes ? B.ptrs() : nullptr, drp, dcol, nb, cnt_c.get(), cnt_p.get());
   C.row_ptr = DBuf<int>(c.pool, nb + 1);
   DBuf<int64_t> prp(c.pool, nb + 1);
   int64_t nnzc = 0, P = 0;  // capacities of the output and pair arrays
@@ -242,17 +255,26 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
   DBuf<BlockPair> pairs(c.pool, (size_t)P);
   DBuf<const double*> dsrc(c.pool, D ? (size_t)nnzc : 0);
   if (nnzc)
-    launch_symbolic_fill(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, A.ptrs(), B.ptrs(), drp, dcol,
+    launch_symbolic_fill(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, A.ptrs(), B.ptrs(), A.holes, B.holes,
+                         drp, dcol,
                          D ? D->ptrs() : nullptr, nb, C.row_ptr.get(), prp.get(), C.col.get(), seg.get(),
                          pairs.get(), D ? dsrc.get() : nullptr);
   Store st = new_store(c, nnzc, C.b);
   C.blk = DBuf<const double*>(c.pool, (size_t)nnzc);
   C.store.push_back(st);
-  DBuf<double> nrm(c.pool, (size_t)nnzc);
   Epilogue epi;
   epi.alpha = alpha;
   epi.gamma = gamma;
   epi.dsrc = D ? dsrc.get() : nullptr;
+  if (keep_holes && tau > 0.0) {  // truncation by null pointers, no compaction
+    epi.drop = true;
+    epi.tau = tau;
+    C.holes = true;
+    launch_numeric(c, prec, ta, tb, seg.get(), pairs.get(), nnzc, C.row_ptr.get() + nb, C.b, st->get(),
+                   C.blk.get(), nullptr, epi);
+    return C;
+  }
+  DBuf<double> nrm(c.pool, (size_t)nnzc);
   launch_numeric(c, prec, ta, tb, seg.get(), pairs.get(), nnzc, C.row_ptr.get() + nb, C.b,
                  st->get(), C.blk.get(), nrm.get(), epi);
   return truncate(c, std::move(C), nrm.get(), tau);
@@ -271,7 +293,7 @@ Bsr union_sum(Ctx& c, const Bsr* const src[3], const double coef[3], double gamm
   const int nb = C.nb;
   const int* rp[3];
   const int* col[3];
-  BlkIn val[3];
+  BlkIn val[3], hole[3];
   int64_t cap = diag_on ? nb : 0;
   // blocks that need new values: those of scaled operands, those present in
   // two or more unscaled operands (at most their total minus the largest),
@@ -281,6 +303,7 @@ Bsr union_sum(Ctx& c, const Bsr* const src[3], const double coef[3], double gamm
     rp[t] = src[t] ? src[t]->row_ptr.get() : nullptr;
     col[t] = src[t] ? src[t]->col.get() : nullptr;
     val[t] = src[t] ? src[t]->ptrs() : nullptr;
+    hole[t] = src[t] && src[t]->holes ? src[t]->ptrs() : nullptr;
     if (!src[t]) continue;
     cap += src[t]->bound();
     if (coef[t] == 1.0) {
@@ -299,7 +322,7 @@ Bsr union_sum(Ctx& c, const Bsr* const src[3], const double coef[3], double gamm
   DBuf<int> slot(c.pool, 1);
   {
     DBuf<int> cnt(c.pool, nb);
-    launch_union3(c, rp, col, diag_on, nb, cnt.get(), slot.get());
+    launch_union3(c, rp, col, hole, diag_on, nb, cnt.get(), slot.get());
     scan_exclusive_i32(c, cnt.get(), C.row_ptr.get(), nb);
   }
   C.col = DBuf<int>(c.pool, (size_t)cap);
@@ -309,7 +332,8 @@ Bsr union_sum(Ctx& c, const Bsr* const src[3], const double coef[3], double gamm
   C.blk = DBuf<const double*>(c.pool, (size_t)cap);
   C.store.push_back(st);
   if (cap) {
-    launch_union3_fill(c, rp, col, diag_on, C.row_ptr.get(), nb, C.col.get(), ix.get(), cap, id.get(), rowof.get());
+    launch_union3_fill(c, rp, col, hole, diag_on, C.row_ptr.get(), nb, C.col.get(), ix.get(), cap, id.get(),
+                       rowof.get());
     launch_axpby3_values(c, val, coef, ix.get(), cap, gamma, id.get(), rowof.get(), cap, C.b, C.n, st->get(),
                          slot.get(), C.blk.get(), C.live());
   }
@@ -332,6 +356,7 @@ Bsr axpby3(Ctx& c, double alpha, const Bsr* A, double beta, const Bsr* B, double
 }
 
 Bsr filter(Ctx& c, const Bsr& A, const int* rlab, const int* clab, int mode) {
+  no_holes(A, "filter");
   const int nb = A.nb;
   Bsr C = like(A);
   C.nnzb = -1;
@@ -351,6 +376,7 @@ Bsr filter(Ctx& c, const Bsr& A, const int* rlab, const int* clab, int mode) {
 }
 
 Bsr intersect(Ctx& c, const Bsr& A, const Bsr& R) {
+  no_holes(A, "intersect");
   const int nb = A.nb;
   Bsr C = like(A);
   C.nnzb = -1;
@@ -370,6 +396,7 @@ Bsr intersect(Ctx& c, const Bsr& A, const Bsr& R) {
 }
 
 Bsr phi_upper(Ctx& c, const Bsr& W) {
+  no_holes(W, "phi_upper");
   std::vector<int> idx(W.nb);
   for (int i = 0; i < W.nb; ++i) idx[i] = i;
   DBuf<int> d_idx(c.pool, W.nb);
@@ -385,6 +412,7 @@ Bsr phi_upper(Ctx& c, const Bsr& W) {
 }
 
 double gershgorin(Ctx& c, const Bsr& A) {
+  no_holes(A, "gershgorin");
   DBuf<double> rowmax(c.pool, A.nb), mx(c.pool, 1);
   launch_gershgorin(c, A.row_ptr.get(), A.ptrs(), A.nb, A.b, rowmax.get());
   launch_max_reduce(c, rowmax.get(), A.nb, mx.get());
@@ -393,6 +421,7 @@ double gershgorin(Ctx& c, const Bsr& A) {
 
 std::vector<double> node_sumsq(Ctx& c, const Bsr& A, const int* rlo, const int* rhi, int nseg,
                                const std::vector<Ctx::Read>& extra) {
+  no_holes(A, "node_sumsq");
   std::vector<double> out(nseg, 0.0);
   if (nseg == 0) {
     if (!extra.empty()) c.d2h_batch(extra);

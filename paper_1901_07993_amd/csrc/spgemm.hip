@@ -4,6 +4,8 @@
 // children.
 //
 // Symbolic phase (integer, HBM-bound): one workgroup per block row i of C.
+// An operand may carry holes (blocks dropped by its own truncation, left in
+// its pattern with null pointers); they take no part in the product.
 // The output columns of row i are collected in an LDS bitmap over the nb
 // block columns; their number and the number of block products are counted.
 // After a host-side prefix sum the fill pass writes C's sorted column list,
@@ -32,10 +34,22 @@ constexpr int kSymWG = 256;
 // symbolic
 // ---------------------------------------------------------------------------
 
+// Operands with holes: a block whose pointer is null is absent.  `a`/`b`
+// are the block pointers of such an operand (null for one without holes),
+// reached through the view's index arrays.
+struct Holes {
+  BlkIn a = nullptr;
+  const int* aidx = nullptr;
+  BlkIn b = nullptr;
+  const int* bidx = nullptr;
+  __device__ bool a_absent(int e) const { return a && !a[aidx ? aidx[e] : e]; }
+  __device__ bool b_absent(int f) const { return b && !b[bidx ? bidx[f] : f]; }
+};
+
 // `drp`/`dcol` (nullable): a matrix D whose row pattern joins the output
 // pattern (the target of a fused term gamma D)
 __device__ inline void build_row_bitmap(const int* __restrict__ arp, const int* __restrict__ acol,
-                                        const int* __restrict__ brp, const int* __restrict__ bcol,
+                                        const int* __restrict__ brp, const int* __restrict__ bcol, const Holes& h,
                                         const int* __restrict__ drp, const int* __restrict__ dcol, int i,
                                         unsigned* bm, int nwords, int64_t* pcount) {
   for (int w = threadIdx.x; w < nwords; w += kSymWG) bm[w] = 0u;
@@ -48,10 +62,13 @@ __device__ inline void build_row_bitmap(const int* __restrict__ arp, const int* 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int64_t p = 0;
   for (int e = arp[i] + wave; e < arp[i + 1]; e += kSymWG / 64) {
+    if (h.a_absent(e)) continue;  // uniform over the wave
     const int k = acol[e];
     const int lo = brp[k], hi = brp[k + 1];
-    if (lane == 0) p += hi - lo;
+    if (!h.b && lane == 0) p += hi - lo;
     for (int f = lo + lane; f < hi; f += 64) {
+      if (h.b_absent(f)) continue;
+      if (h.b) ++p;
       const int j = bcol[f];
       atomicOr(&bm[j >> 5], 1u << (j & 31));
     }
@@ -62,9 +79,9 @@ __device__ inline void build_row_bitmap(const int* __restrict__ arp, const int* 
 
 __global__ __launch_bounds__(kSymWG) void k_symbolic_count(const int* __restrict__ arp, const int* __restrict__ acol,
                                                            const int* __restrict__ brp, const int* __restrict__ bcol,
-                                                           const int* __restrict__ drp, const int* __restrict__ dcol,
-                                                           int nb, int* __restrict__ cnt_c,
-                                                           int64_t* __restrict__ cnt_p) {
+                                                           Holes h, const int* __restrict__ drp,
+                                                           const int* __restrict__ dcol, int nb,
+                                                           int* __restrict__ cnt_c, int64_t* __restrict__ cnt_p) {
   extern __shared__ unsigned smem[];
   __shared__ int64_t red_p[kSymWG];
   __shared__ int red_c[kSymWG];
@@ -72,7 +89,7 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_count(const int* __restrict
   const int nwords = (nb + 31) >> 5;
   unsigned* bm = smem;
   int64_t p = 0;
-  build_row_bitmap(arp, acol, brp, bcol, drp, dcol, i, bm, nwords, &p);
+  build_row_bitmap(arp, acol, brp, bcol, h, drp, dcol, i, bm, nwords, &p);
   int c = 0;
   for (int w = threadIdx.x; w < nwords; w += kSymWG) c += __popc(bm[w]);
   red_p[threadIdx.x] = p;
@@ -97,7 +114,8 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_count(const int* __restrict
 __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict__ arp, const int* __restrict__ acol,
                                                           const int* __restrict__ aidx, const int* __restrict__ brp,
                                                           const int* __restrict__ bcol, const int* __restrict__ bidx,
-                                                          BlkIn ablk, BlkIn bblk, const int* __restrict__ drp,
+                                                          BlkIn ablk, BlkIn bblk, bool a_holes, bool b_holes,
+                                                          const int* __restrict__ drp,
                                                           const int* __restrict__ dcol, BlkIn dblk, int nb,
                                                           const int* __restrict__ crp,
                                                           const int64_t* __restrict__ prp, int* __restrict__ ccol,
@@ -110,7 +128,8 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
   unsigned* bm = smem;
   int* wp = reinterpret_cast<int*>(smem + nwords);
   int* cur = wp + nwords;
-  build_row_bitmap(arp, acol, brp, bcol, drp, dcol, i, bm, nwords, nullptr);
+  const Holes h{a_holes ? ablk : nullptr, aidx, b_holes ? bblk : nullptr, bidx};
+  build_row_bitmap(arp, acol, brp, bcol, h, drp, dcol, i, bm, nwords, nullptr);
 
   // exclusive prefix of word popcounts: contiguous chunks per thread
   const int chunk = (nwords + kSymWG - 1) / kSymWG;
@@ -152,8 +171,10 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
   // products per output block
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int e = arp[i] + wave; e < arp[i + 1]; e += kSymWG / 64) {
+    if (h.a_absent(e)) continue;
     const int k = acol[e];
     for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
+      if (h.b_absent(f)) continue;
       const int j = bcol[f];
       const int r = wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u));
       atomicAdd(&cur[r], 1);
@@ -181,16 +202,20 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
 
   // pairs in ascending k within each output block: the A row is walked in
   // order; within one k every output column occurs at most once
+  // (the same absent blocks as in the counts above)
   for (int e = arp[i]; e < arp[i + 1]; ++e) {
     const int k = acol[e];
     const double* a = ablk[aidx ? aidx[e] : e];
-    for (int f = brp[k] + threadIdx.x; f < brp[k + 1]; f += kSymWG) {
-      const int j = bcol[f];
-      const int r = wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u));
-      const int pos = cur[r];
-      pairs[prow + pos] = BlockPair{a, bblk[bidx ? bidx[f] : f]};
-      cur[r] = pos + 1;
-    }
+    if (!a_holes || a)  // uniform over the workgroup
+      for (int f = brp[k] + threadIdx.x; f < brp[k + 1]; f += kSymWG) {
+        const double* bp = bblk[bidx ? bidx[f] : f];
+        if (b_holes && !bp) continue;
+        const int j = bcol[f];
+        const int r = wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u));
+        const int pos = cur[r];
+        pairs[prow + pos] = BlockPair{a, bp};
+        cur[r] = pos + 1;
+      }
     __syncthreads();
   }
 }
@@ -300,8 +325,9 @@ __device__ __attribute__((always_inline)) inline void numeric_epilogue(const v4d
     double t = 0.0;
 #pragma unroll
     for (int w = 0; w < Cfg::WAVES; ++w) t += red[w];
-    norms[blk] = sqrt(t);
-    Cp[blk] = Cb;
+    const double nrm = sqrt(t);
+    if (norms) norms[blk] = nrm;
+    Cp[blk] = (epi.drop && !(nrm >= epi.tau)) ? nullptr : Cb;
   }
 }
 
@@ -414,20 +440,24 @@ static void allow_lds(const void* fn, size_t bytes) {
     LIF_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
 }
 
-void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* brp, const int* bcol,
-                           const int* drp, const int* dcol, int nb, int* cnt_c, int64_t* cnt_p) {
+void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp,
+                           const int* bcol, const int* bidx, BlkIn ahole, BlkIn bhole, const int* drp,
+                           const int* dcol, int nb, int* cnt_c, int64_t* cnt_p) {
   allow_lds((const void*)k_symbolic_count, symbolic_lds_bytes(nb, false));
+  const Holes h{ahole, aidx, bhole, bidx};
   hipLaunchKernelGGL(k_symbolic_count, dim3(nb), dim3(kSymWG), symbolic_lds_bytes(nb, false), c.stream, arp, acol,
-                     brp, bcol, drp, dcol, nb, cnt_c, cnt_p);
+                     brp, bcol, h, drp, dcol, nb, cnt_c, cnt_p);
   LIF_HIP(hipGetLastError());
 }
 
 void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp, const int* bcol,
-                          const int* bidx, BlkIn ablk, BlkIn bblk, const int* drp, const int* dcol, BlkIn dblk, int nb,
-                          const int* crp, const int64_t* prp, int* ccol, int64_t* seg, BlockPair* pairs, BlkOut dsrc) {
+                          const int* bidx, BlkIn ablk, BlkIn bblk, bool a_holes, bool b_holes, const int* drp,
+                          const int* dcol, BlkIn dblk, int nb, const int* crp, const int64_t* prp, int* ccol,
+                          int64_t* seg, BlockPair* pairs, BlkOut dsrc) {
   allow_lds((const void*)k_symbolic_fill, symbolic_lds_bytes(nb, true));
   hipLaunchKernelGGL(k_symbolic_fill, dim3(nb), dim3(kSymWG), symbolic_lds_bytes(nb, true), c.stream, arp, acol,
-                     aidx, brp, bcol, bidx, ablk, bblk, drp, dcol, dblk, nb, crp, prp, ccol, seg, pairs, dsrc);
+                     aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb, crp, prp, ccol, seg,
+                     pairs, dsrc);
   LIF_HIP(hipGetLastError());
 }
 

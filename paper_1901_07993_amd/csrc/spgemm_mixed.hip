@@ -111,8 +111,9 @@ __device__ inline void epilogue(const v4f (&acc)[2][2], int rb, int cb, int l16,
     double t = 0.0;
 #pragma unroll
     for (int w = 0; w < Cfg::WAVES; ++w) t += red[w];
-    norms[blk] = sqrt(t);
-    Cp[blk] = Cb;
+    const double nrm = sqrt(t);
+    if (norms) norms[blk] = nrm;
+    Cp[blk] = (epi.drop && !(nrm >= epi.tau)) ? nullptr : Cb;
   }
 }
 
