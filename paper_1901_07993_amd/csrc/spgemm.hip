@@ -220,6 +220,152 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
   }
 }
 
+// The fill pass without a serial walk of the A row.  A pair (e, f) of
+// output block r must land after the pairs of r from earlier A entries e'
+// (ascending k).  For a run of up to 64 consecutive A entries, every output
+// block keeps a 64-bit LDS mask with bit e - e0 set when entry e contributes
+// to it; the pair's rank in the block is the popcount of the mask below its
+// bit, plus the pairs of earlier runs.  All pairs of a run are placed in
+// parallel.  LDS: mask[nb] (64-bit) | bitmap[nwords] | word_prefix[nwords] |
+// cursor[nb].
+__global__ __launch_bounds__(kSymWG) void k_symbolic_fill_masked(
+    const int* __restrict__ arp, const int* __restrict__ acol, const int* __restrict__ aidx,
+    const int* __restrict__ brp, const int* __restrict__ bcol, const int* __restrict__ bidx, BlkIn ablk,
+    BlkIn bblk, bool a_holes, bool b_holes, const int* __restrict__ drp, const int* __restrict__ dcol, BlkIn dblk,
+    int nb, const int* __restrict__ crp, const int64_t* __restrict__ prp, int* __restrict__ ccol,
+    int64_t* __restrict__ seg, BlockPair* __restrict__ pairs, BlkOut dsrc) {
+  extern __shared__ unsigned long long smem64[];
+  __shared__ int scan_tmp[kSymWG / 64];
+  const int i = blockIdx.x;
+  const int nwords = (nb + 31) >> 5;
+  unsigned long long* mask = smem64;
+  unsigned* bm = reinterpret_cast<unsigned*>(smem64 + nb);
+  int* wp = reinterpret_cast<int*>(bm + nwords);
+  int* cur = wp + nwords;
+  const Holes h{a_holes ? ablk : nullptr, aidx, b_holes ? bblk : nullptr, bidx};
+  build_row_bitmap(arp, acol, brp, bcol, h, drp, dcol, i, bm, nwords, nullptr);
+
+  // exclusive prefix of word popcounts: contiguous chunks per thread
+  const int chunk = (nwords + kSymWG - 1) / kSymWG;
+  const int w0 = min(nwords, (int)threadIdx.x * chunk), w1 = min(nwords, w0 + chunk);
+  int s = 0;
+  for (int w = w0; w < w1; ++w) s += __popc(bm[w]);
+  int ncols;
+  int run = block_exclusive_scan<int, kSymWG>(s, scan_tmp, &ncols);
+  for (int w = w0; w < w1; ++w) {
+    wp[w] = run;
+    run += __popc(bm[w]);
+  }
+  __syncthreads();
+
+  // output columns in ascending order; clear the per-output counters and masks
+  const int cbase = crp[i];
+  for (int w = threadIdx.x; w < nwords; w += kSymWG) {
+    unsigned bits = bm[w];
+    int r = wp[w];
+    while (bits) {
+      const int j = (w << 5) + __ffs(bits) - 1;
+      ccol[cbase + r] = j;
+      if (dsrc) dsrc[cbase + r] = nullptr;
+      cur[r] = 0;
+      mask[r] = 0ull;
+      ++r;
+      bits &= bits - 1;
+    }
+  }
+  __syncthreads();
+  if (dsrc)
+    for (int e = drp[i] + threadIdx.x; e < drp[i + 1]; e += kSymWG) {
+      const int j = dcol[e];
+      dsrc[cbase + wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u))] = dblk[e];
+    }
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int alo = arp[i], ahi = arp[i + 1];
+  auto rank = [&](int j) { return wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u)); };
+  // marks the contributions of A entries [e0, e0 + 64) in the masks
+  auto mark = [&](int e0) {
+    const int e1 = min(ahi, e0 + 64);
+    for (int e = e0 + wave; e < e1; e += kSymWG / 64) {
+      if (h.a_absent(e)) continue;  // uniform over the wave
+      const int k = acol[e];
+      const unsigned long long bit = 1ull << (e - e0);
+      for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
+        if (h.b_absent(f)) continue;
+        atomicOr(&mask[rank(bcol[f])], bit);
+      }
+    }
+  };
+  // writes the pairs of A entries [e0, e0 + 64) after cur[r] in each block
+  auto place = [&](int e0, int64_t prow) {
+    const int e1 = min(ahi, e0 + 64);
+    for (int e = e0 + wave; e < e1; e += kSymWG / 64) {
+      const double* a = ablk[aidx ? aidx[e] : e];
+      if (a_holes && !a) continue;
+      const int k = acol[e];
+      const unsigned long long below = (1ull << (e - e0)) - 1ull;
+      for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
+        const double* bp = bblk[bidx ? bidx[f] : f];
+        if (b_holes && !bp) continue;
+        const int r = rank(bcol[f]);
+        pairs[prow + cur[r] + __popcll(mask[r] & below)] = BlockPair{a, bp};
+      }
+    }
+  };
+  const bool one_run = ahi - alo <= 64;
+
+  // products per output block
+  for (int e0 = alo; e0 < ahi; e0 += 64) {
+    mark(e0);
+    __syncthreads();
+    if (!one_run) {
+      for (int r = threadIdx.x; r < ncols; r += kSymWG) {
+        cur[r] += __popcll(mask[r]);
+        mask[r] = 0ull;
+      }
+      __syncthreads();
+    }
+  }
+  if (one_run)
+    for (int r = threadIdx.x; r < ncols; r += kSymWG) cur[r] = __popcll(mask[r]);
+  __syncthreads();
+
+  // exclusive scan of the per-output counts -> segment starts
+  const int c0 = min(ncols, (int)threadIdx.x * ((ncols + kSymWG - 1) / kSymWG));
+  const int c1 = min(ncols, c0 + (ncols + kSymWG - 1) / kSymWG);
+  int t = 0;
+  for (int r = c0; r < c1; ++r) t += cur[r];
+  __syncthreads();  // scan_tmp is reused
+  int tot;
+  int acc = block_exclusive_scan<int, kSymWG>(t, scan_tmp, &tot);
+  const int64_t prow = prp[i];
+  if (i == nb - 1 && threadIdx.x == 0) seg[crp[nb]] = prp[nb];  // closing segment pointer
+  for (int r = c0; r < c1; ++r) {
+    const int cnt = cur[r];
+    seg[cbase + r] = prow + acc;
+    cur[r] = acc;
+    acc += cnt;
+  }
+  __syncthreads();
+
+  // pairs: one run reuses its masks; longer rows mark each run again
+  if (one_run) {
+    place(alo, prow);
+    return;
+  }
+  for (int e0 = alo; e0 < ahi; e0 += 64) {
+    mark(e0);
+    __syncthreads();
+    place(e0, prow);
+    __syncthreads();
+    for (int r = threadIdx.x; r < ncols; r += kSymWG) {
+      cur[r] += __popcll(mask[r]);
+      mask[r] = 0ull;
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // numeric
 // ---------------------------------------------------------------------------
@@ -435,6 +581,11 @@ size_t symbolic_lds_bytes(int nb, bool fill) {
   return fill ? nwords * 8 + (size_t)nb * 4 : nwords * 4;
 }
 
+// the masked fill while its LDS (masks added) stays within 64 KiB, i.e. up
+// to about 5000 block rows; the serial-walk fill above that
+static size_t masked_fill_lds_bytes(int nb) { return symbolic_lds_bytes(nb, true) + (size_t)nb * 8; }
+constexpr size_t kMaskedFillLds = 64 * 1024;
+
 static void allow_lds(const void* fn, size_t bytes) {
   if (bytes > 48 * 1024)
     LIF_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
@@ -454,6 +605,14 @@ void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* ai
                           const int* bidx, BlkIn ablk, BlkIn bblk, bool a_holes, bool b_holes, const int* drp,
                           const int* dcol, BlkIn dblk, int nb, const int* crp, const int64_t* prp, int* ccol,
                           int64_t* seg, BlockPair* pairs, BlkOut dsrc) {
+  if (masked_fill_lds_bytes(nb) <= kMaskedFillLds) {
+    allow_lds((const void*)k_symbolic_fill_masked, masked_fill_lds_bytes(nb));
+    hipLaunchKernelGGL(k_symbolic_fill_masked, dim3(nb), dim3(kSymWG), masked_fill_lds_bytes(nb), c.stream, arp,
+                       acol, aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb, crp, prp, ccol,
+                       seg, pairs, dsrc);
+    LIF_HIP(hipGetLastError());
+    return;
+  }
   allow_lds((const void*)k_symbolic_fill, symbolic_lds_bytes(nb, true));
   hipLaunchKernelGGL(k_symbolic_fill, dim3(nb), dim3(kSymWG), symbolic_lds_bytes(nb, true), c.stream, arp, acol,
                      aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb, crp, prp, ccol, seg,

@@ -90,6 +90,23 @@ def test_multiply_tau0_matches_oracle(b, n, ta, tb):
     assert np.max(np.abs(got - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref))) * math.sqrt(n)
 
 
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True)])
+def test_multiply_long_rows_matches_oracle(ta, tb):
+    # rows of more than 64 blocks: the symbolic fill places the pairs of
+    # each output block in runs of 64 inner indices (three runs here)
+    b, n = 32, 150 * 32 - 9
+    say(f"case multiply long rows b={b} n={n} ta={ta} tb={tb}")
+    A = random_block_sparse(n, b, 0.9, 11)
+    B = random_block_sparse(n, b, 0.9, 12)
+    with lif.Factorization(identity_blocks(n, b)) as f:
+        C, prods = f.multiply(dev(A), ta, dev(B), tb, 0.0)
+    Da, Db = blocks_to_dense(A), blocks_to_dense(B)
+    ref = (Da.T if ta else Da) @ (Db.T if tb else Db)
+    assert prods == product_count(A, ta, B, tb)
+    got = blocks_to_dense(C)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref))) * math.sqrt(n)
+
+
 @pytest.mark.parametrize("b", [32, 64])
 def test_multiply_truncation_matches_oracle(b):
     n = 6 * b + 17
