@@ -29,7 +29,7 @@ struct Blk {
 
 template <int B>
 __device__ __attribute__((always_inline)) inline void blk_load(const double* __restrict__ p, v2d (&r)[Blk<B>::V2]) {
-  const v2d* q = reinterpret_cast<const v2d*>(p);
+  const auto* q = gptr(reinterpret_cast<const v2d*>(p));
 #pragma unroll
   for (int v = 0; v < Blk<B>::V2; ++v) r[v] = q[threadIdx.x + v * kWG];
 }
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kWG) void k_gershgorin(const int* __restrict__ rp, 
   for (int r = w; r < b; r += 4) {
     double s = 0.0;
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
-      const double* row = blk[e] + (int64_t)r * b;
+      const auto* row = gptr(blk[e] + (int64_t)r * b);
       for (int cc = lane; cc < b; cc += 64) s += fabs(row[cc]);
     }
     s = wave_sum(s);

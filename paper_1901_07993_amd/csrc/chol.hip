@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void k_chol_scatter(const int* __restrict__ ro
   if (s < 0 || base_of_row[J] != s || J < I) return;
   const int i = I - blk0[s], j = J - blk0[s];
   const int64_t t = packed_tile(tile0[s], nbbv[s], i, j);
-  const v2d* src = reinterpret_cast<const v2d*>(val[e]);
+  const auto* src = gptr(reinterpret_cast<const v2d*>(val[e]));
   v2d* dst = reinterpret_cast<v2d*>(U + t * (int64_t)b * b);
   v2d r[8];  // b * b / 2 / 256 <= 8 pairs per thread, all loads issued first
 #pragma unroll

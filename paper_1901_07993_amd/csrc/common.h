@@ -117,6 +117,16 @@ class DBuf {
 // creates it and only read afterwards, so matrices share blocks freely:
 // truncation, filters and copies move pointers, and a sum reuses the blocks
 // it takes unscaled from one operand.
+// Loads through a pointer that was itself read from memory compile to flat
+// loads, which count on both the vector-memory and the LDS counters, so the
+// compiler waits for all outstanding ones before the first use; through a
+// pointer cast to the global address space they are global loads, waited
+// for one by one as their data is needed.
+template <typename T>
+__device__ __attribute__((always_inline)) inline const __attribute__((address_space(1))) T* gptr(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
 typedef const double* const* BlkIn;
 typedef const double** BlkOut;
 typedef std::shared_ptr<DBuf<double>> Store;

@@ -404,9 +404,9 @@ __device__ __attribute__((always_inline)) inline void load_d(const Frag& f, cons
     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double* q = Db + M::row(f, ti, 4 * r + f.kq) * B;
+        const auto* q = gptr(Db + M::row(f, ti, 4 * r + f.kq) * B);
         if (M::CI) {
-          const v2d dv = *reinterpret_cast<const v2d*>(q + M::col(f, 0, f.l16));
+          const v2d dv = *gptr(reinterpret_cast<const v2d*>(Db + M::row(f, ti, 4 * r + f.kq) * B + M::col(f, 0, f.l16)));
           d[ti][0][r] = dv.x;
           d[ti][1][r] = dv.y;
         } else {
@@ -515,14 +515,14 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const int64
     } else {
 #pragma unroll
       for (int kk = 0; kk < KS; ++kk)
-        ad[kk] = *reinterpret_cast<const v2d*>(pr.a + (4 * kk + f.kq) * B + f.rb + 2 * f.l16);
+        ad[kk] = *gptr(reinterpret_cast<const v2d*>(pr.a + (4 * kk + f.kq) * B + f.rb + 2 * f.l16));
     }
     if (B_LDS) {
       tile_load<B>(pr.b, rbv);
     } else {
 #pragma unroll
       for (int kk = 0; kk < KS; ++kk)
-        bd[kk] = *reinterpret_cast<const v2d*>(pr.b + (4 * kk + f.kq) * B + f.cb + 2 * f.l16);
+        bd[kk] = *gptr(reinterpret_cast<const v2d*>(pr.b + (4 * kk + f.kq) * B + f.cb + 2 * f.l16));
     }
     if (A_LDS || B_LDS) {
       if (p > p0) __syncthreads();  // the previous pair's fragment reads are done

@@ -100,7 +100,7 @@ __device__ inline void epilogue(const v4f (&acc)[2][2], int rb, int cb, int l16,
       for (int r = 0; r < 4; ++r) {
         const int idx = (rb + 16 * ti + 4 * kq + r) * B + cb + 16 * tj + l16;
         double v = epi.alpha * (double)acc[ti][tj][r];
-        if (Db) v += epi.gamma * Db[idx];
+        if (Db) v += epi.gamma * gptr(Db)[idx];
         Cb[idx] = v;
         ss += v * v;
       }

@@ -37,7 +37,7 @@ template <int B>
 __device__ __attribute__((always_inline)) inline void tile_load(const double* __restrict__ g,
                                                                 v2d (&reg)[TileCfg<B>::V2]) {
   using Cfg = TileCfg<B>;
-  const v2d* p = reinterpret_cast<const v2d*>(g);
+  const auto* p = gptr(reinterpret_cast<const v2d*>(g));
 #pragma unroll
   for (int v = 0; v < Cfg::V2; ++v) reg[v] = p[threadIdx.x + v * Cfg::THREADS];
 }
