@@ -190,6 +190,7 @@ def main():
         "iterations_total": last["iterations_total"],
         "nnzb_Z": last["nnzb_Z"],
         "products_per_step": last["products_total"],
+        "iterations_redone": last.get("iterations_redone"),
         "mixed": mixed,
         "roofline": {"bound": "mfma", "kernel": "k_numeric_f64 (leaf GEMM, v_mfma_f64_16x16x4f64)",
                      "achieved": achieved, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",

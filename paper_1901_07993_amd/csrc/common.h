@@ -206,6 +206,23 @@ struct Ctx {
     DBuf<int64_t> sizes;
     DBuf<int> overflow;
   } spec;
+  // State of the single-pass scans (look-back over groups of rows), one per
+  // stream: published words (two arrays of `rows` per-row words, then two of
+  // groups(rows) per-group words) and the epoch that tells this launch's
+  // words from those of earlier ones.
+  struct Lookback {
+    static int groups(int rows) { return (rows + 63) / 64; }
+    DBuf<unsigned long long> words;
+    int rows = 0;
+    unsigned epoch = 0;
+    unsigned next_epoch() {
+      epoch = (epoch + 1) & 0x3fffu;
+      if (epoch == 0) epoch = 1;
+      return epoch;
+    }
+  };
+  std::map<hipStream_t, Lookback> lookback;
+  Lookback& lookback_for(int rows);  // the current stream's, for `rows` rows
   // events around leaf-GEMM launches (timing mode), resolved at flush_timing()
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
   std::vector<hipEvent_t> ev_free;
@@ -350,18 +367,45 @@ void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* ai
                           const int* bcol, const int* bidx, BlkIn ablk, BlkIn bblk, bool a_holes, bool b_holes,
                           const int* drp, const int* dcol, BlkIn dblk, int nb, const int* crp, const int64_t* prp,
                           int* ccol, int64_t* seg, BlockPair* pairs, BlkOut dsrc);
+// Symbolic phase in one launch when the capacities are known in advance:
+// counts, the prefix sums of the row counts (decoupled look-back) and the
+// fill.  Writes crp[0..nb]; totals to sizes[0..1]; when a total exceeds its
+// capacity the row pointers are all zero and *overflow is raised.  Only for
+// nb with symbolic_onepass_fits(nb).
+bool symbolic_onepass_fits(int nb);
+void launch_symbolic_onepass(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp,
+                             const int* bcol, const int* bidx, BlkIn ablk, BlkIn bblk, bool a_holes, bool b_holes,
+                             const int* drp, const int* dcol, BlkIn dblk, int nb, int64_t cap_c, int64_t cap_p,
+                             int* crp, int* ccol, int64_t* seg, BlockPair* pairs, BlkOut dsrc, int64_t* sizes,
+                             int* overflow);
 // Fused terms of a product: the output block is alpha sum op(A) op(B)
 // + gamma D_e, D_e = dsrc[e] (skipped where null), and its norm is the norm
 // of that sum (truncation then applies to the whole block).
 // With `drop`, a block whose norm is below `tau` gets a null pointer (the
-// product keeps holes instead of being compacted).
+// product keeps holes instead of being compacted).  When *poison (nullable)
+// is set the product is void: no block is computed and workgroup 0 clears
+// the row pointers rows[0..nrows].
 struct Epilogue {
   double alpha = 1.0;
   double gamma = 0.0;
   BlkIn dsrc = nullptr;
   bool drop = false;
   double tau = 0.0;
+  const int* poison = nullptr;
+  int* rows = nullptr;
+  int nrows = 0;
 };
+
+// The numeric kernels' count of output blocks to compute: *live, or none
+// for a voided product (whose row pointers workgroup 0 then clears).
+__device__ inline int64_t live_blocks(const int* live, const Epilogue& epi) {
+  if (epi.poison && *epi.poison) {
+    if (blockIdx.x == 0)
+      for (int r = threadIdx.x; r <= epi.nrows; r += blockDim.x) epi.rows[r] = 0;
+    return 0;
+  }
+  return *live;
+}
 // Numeric phase: C_blk = sum over its segment of op(A_a) op(B_b), in FP64
 // (prec = LIF_FP64) or with FP32 / BF16 inputs and FP32 accumulation.
 // `nnzc` is the grid (the output capacity); `live` (device) the number of

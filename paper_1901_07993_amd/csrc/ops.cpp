@@ -190,6 +190,40 @@ Bsr transpose(Ctx& c, const Bsr& A) {
   return T;
 }
 
+namespace {
+
+// The numeric phase of a product whose pattern, segments and pairs are
+// built: values, norms, truncation (or holes).
+// `poison` (nullable): the flag that voids the product (Epilogue).
+Bsr numeric_phase(Ctx& c, Bsr&& C, bool ta, bool tb, double tau, int prec, double alpha, BlkIn dsrc, double gamma,
+                  bool keep_holes, const int64_t* seg, const BlockPair* pairs, int64_t nnzc, const int* poison) {
+  const int nb = C.nb;
+  Store st = new_store(c, nnzc, C.b);
+  C.blk = DBuf<const double*>(c.pool, (size_t)nnzc);
+  C.store.push_back(st);
+  Epilogue epi;
+  epi.alpha = alpha;
+  epi.gamma = gamma;
+  epi.dsrc = dsrc;
+  epi.poison = poison;
+  epi.rows = C.row_ptr.get();
+  epi.nrows = nb;
+  if (keep_holes && tau > 0.0) {  // truncation by null pointers, no compaction
+    epi.drop = true;
+    epi.tau = tau;
+    C.holes = true;
+    launch_numeric(c, prec, ta, tb, seg, pairs, nnzc, C.row_ptr.get() + nb, C.b, st->get(), C.blk.get(), nullptr,
+                   epi);
+    return std::move(C);
+  }
+  DBuf<double> nrm(c.pool, (size_t)nnzc);
+  launch_numeric(c, prec, ta, tb, seg, pairs, nnzc, C.row_ptr.get() + nb, C.b, st->get(), C.blk.get(), nrm.get(),
+                 epi);
+  return truncate(c, std::move(C), nrm.get(), tau);
+}
+
+}  // namespace
+
 Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec, double alpha,
            const Bsr* D, double gamma, bool keep_holes) {
   LIF_REQUIRE(A.nb == B.nb && A.b == B.b, LIF_ERR_INVALID, "spgemm: operand shapes differ");
@@ -209,17 +243,42 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
     bv.rp = B.row_ptr.get();
     bv.col = B.col.get();
   }
-  DBuf<int> cnt_c(c.pool, nb);
-  DBuf<int64_t> cnt_p(c.pool, nb);
   if (D) LIF_REQUIRE(D->nb == nb && D->b == A.b, LIF_ERR_INVALID, "spgemm: added term's shape differs");
   const int* drp = D ? D->row_ptr.get() : nullptr;
   const int* dcol = D ? D->col.get() : nullptr;
-  launch_symbolic_count(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, A.holes ? A.ptrs() : nullptr,
-                        B.holes ? B.ptrs() : nullptr, drp, dcol, nb, cnt_c.get(), cnt_p.get());
   C.row_ptr = DBuf<int>(c.pool, nb + 1);
-  DBuf<int64_t> prp(c.pool, nb + 1);
   int64_t nnzc = 0, P = 0;  // capacities of the output and pair arrays
   const bool planned = c.spec.on && c.spec.next < c.spec.caps.size() && c.spec.next < (size_t)Ctx::Spec::kSlots;
+  DBuf<int64_t> seg, prp;
+  DBuf<BlockPair> pairs;
+  DBuf<const double*> dsrc;
+  auto alloc_outputs = [&]() {
+    C.cap = nnzc;
+    C.col = DBuf<int>(c.pool, (size_t)nnzc);
+    seg = DBuf<int64_t>(c.pool, (size_t)nnzc + 1);
+    pairs = DBuf<BlockPair>(c.pool, (size_t)P);
+    dsrc = DBuf<const double*>(c.pool, D ? (size_t)nnzc : 0);
+  };
+  if (planned && symbolic_onepass_fits(nb)) {
+    // sizes known in advance: count, scan and fill in one launch
+    const size_t slot = c.spec.next++;
+    nnzc = std::min<int64_t>(c.spec.caps[slot][0], (int64_t)nb * nb);
+    P = c.spec.caps[slot][1];
+    c.spec.prec.push_back(prec);
+    C.nnzb = -1;
+    alloc_outputs();
+    launch_symbolic_onepass(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, A.ptrs(), B.ptrs(), A.holes, B.holes,
+                            drp, dcol, D ? D->ptrs() : nullptr, nb, nnzc, P, C.row_ptr.get(), C.col.get(),
+                            seg.get(), pairs.get(), D ? dsrc.get() : nullptr, c.spec.sizes.get() + 2 * slot,
+                            c.spec.overflow.get());
+    return numeric_phase(c, std::move(C), ta, tb, tau, prec, alpha, D ? dsrc.get() : nullptr, gamma, keep_holes,
+                         seg.get(), pairs.get(), nnzc, c.spec.overflow.get());
+  }
+  DBuf<int> cnt_c(c.pool, nb);
+  DBuf<int64_t> cnt_p(c.pool, nb);
+  launch_symbolic_count(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, A.holes ? A.ptrs() : nullptr,
+                        B.holes ? B.ptrs() : nullptr, drp, dcol, nb, cnt_c.get(), cnt_p.get());
+  prp = DBuf<int64_t>(c.pool, nb + 1);
   if (planned) {
     const size_t slot = c.spec.next++;
     nnzc = std::min<int64_t>(c.spec.caps[slot][0], (int64_t)nb * nb);
@@ -249,35 +308,13 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
     c.stats.flops += fl;
     if (prec != LIF_FP64) c.stats.flops_lowp += fl;
   }
-  C.cap = nnzc;
-  C.col = DBuf<int>(c.pool, (size_t)nnzc);
-  DBuf<int64_t> seg(c.pool, (size_t)nnzc + 1);
-  DBuf<BlockPair> pairs(c.pool, (size_t)P);
-  DBuf<const double*> dsrc(c.pool, D ? (size_t)nnzc : 0);
+  alloc_outputs();
   if (nnzc)
     launch_symbolic_fill(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, A.ptrs(), B.ptrs(), A.holes, B.holes,
-                         drp, dcol,
-                         D ? D->ptrs() : nullptr, nb, C.row_ptr.get(), prp.get(), C.col.get(), seg.get(),
+                         drp, dcol, D ? D->ptrs() : nullptr, nb, C.row_ptr.get(), prp.get(), C.col.get(), seg.get(),
                          pairs.get(), D ? dsrc.get() : nullptr);
-  Store st = new_store(c, nnzc, C.b);
-  C.blk = DBuf<const double*>(c.pool, (size_t)nnzc);
-  C.store.push_back(st);
-  Epilogue epi;
-  epi.alpha = alpha;
-  epi.gamma = gamma;
-  epi.dsrc = D ? dsrc.get() : nullptr;
-  if (keep_holes && tau > 0.0) {  // truncation by null pointers, no compaction
-    epi.drop = true;
-    epi.tau = tau;
-    C.holes = true;
-    launch_numeric(c, prec, ta, tb, seg.get(), pairs.get(), nnzc, C.row_ptr.get() + nb, C.b, st->get(),
-                   C.blk.get(), nullptr, epi);
-    return C;
-  }
-  DBuf<double> nrm(c.pool, (size_t)nnzc);
-  launch_numeric(c, prec, ta, tb, seg.get(), pairs.get(), nnzc, C.row_ptr.get() + nb, C.b,
-                 st->get(), C.blk.get(), nrm.get(), epi);
-  return truncate(c, std::move(C), nrm.get(), tau);
+  return numeric_phase(c, std::move(C), ta, tb, tau, prec, alpha, D ? dsrc.get() : nullptr, gamma, keep_holes,
+                       seg.get(), pairs.get(), nnzc, nullptr);
 }
 
 namespace {

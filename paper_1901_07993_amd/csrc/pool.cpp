@@ -162,6 +162,18 @@ hipStream_t Ctx::side_stream() {
   return side;
 }
 
+Ctx::Lookback& Ctx::lookback_for(int rows) {
+  Lookback& lb = lookback[stream];
+  if (lb.rows < rows) {
+    // zeroed once: no word reads as published
+    const size_t words = 2 * ((size_t)rows + Lookback::groups(rows));
+    lb.words = DBuf<unsigned long long>(pool, words);
+    LIF_HIP(hipMemsetAsync(lb.words.get(), 0, words * sizeof(unsigned long long), stream));
+    lb.rows = rows;
+  }
+  return lb;
+}
+
 hipEvent_t Ctx::order_event(size_t i) {
   while (order_events.size() <= i) {
     hipEvent_t e = nullptr;

@@ -22,6 +22,7 @@
 // for the truncation pass.
 #include "block_scan.h"
 #include "common.h"
+#include "lookback.h"
 #include "tile_mma.h"
 
 namespace lif {
@@ -228,14 +229,44 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
 // bit, plus the pairs of earlier runs.  All pairs of a run are placed in
 // parallel.  LDS: mask[nb] (64-bit) | bitmap[nwords] | word_prefix[nwords] |
 // cursor[nb].
+//
+// ONEPASS: the counting pass and the scan of the row counts happen in the
+// same launch.  The workgroup of row i counts the row's output blocks and
+// block products and gets their prefix over the lower rows by a look-back
+// over groups of rows (lookback.h); it writes its row pointer itself.  The
+// output and pair arrays have the capacities cap_c, cap_p (sized in
+// advance): a row that does not fit writes nothing.  The last row writes the
+// totals to sizes[0..1] and, when a total exceeds its capacity, raises
+// *overflow and leaves the block count crp[nb] at zero; a row whose
+// look-back gave up raises *overflow too.  A raised *overflow voids the
+// product: the numeric phase then computes nothing and clears the row
+// pointers (Epilogue::poison), so that every later reader sees it empty.
+// Progress of the look-back relies on workgroups starting in the order of
+// their index; were it otherwise, the bounded wait gives up and the
+// product is voided, never hung.
+struct OnePass {
+  unsigned long long* wc = nullptr;  // published words: output blocks per row
+  unsigned long long* wp = nullptr;  // published words: block products per row
+  unsigned long long* gc = nullptr;  // published words: their sums per group of 64 rows
+  unsigned long long* gp = nullptr;
+  unsigned epoch = 0;
+  int64_t cap_c = 0, cap_p = 0;
+  int64_t* sizes = nullptr;
+  int* overflow = nullptr;
+};
+
+template <bool ONEPASS>
 __global__ __launch_bounds__(kSymWG) void k_symbolic_fill_masked(
     const int* __restrict__ arp, const int* __restrict__ acol, const int* __restrict__ aidx,
     const int* __restrict__ brp, const int* __restrict__ bcol, const int* __restrict__ bidx, BlkIn ablk,
     BlkIn bblk, bool a_holes, bool b_holes, const int* __restrict__ drp, const int* __restrict__ dcol, BlkIn dblk,
-    int nb, const int* __restrict__ crp, const int64_t* __restrict__ prp, int* __restrict__ ccol,
-    int64_t* __restrict__ seg, BlockPair* __restrict__ pairs, BlkOut dsrc) {
+    int nb, int* __restrict__ crp, const int64_t* __restrict__ prp, int* __restrict__ ccol,
+    int64_t* __restrict__ seg, BlockPair* __restrict__ pairs, BlkOut dsrc, OnePass op) {
   extern __shared__ unsigned long long smem64[];
   __shared__ int scan_tmp[kSymWG / 64];
+  __shared__ int64_t scan_tmp64[kSymWG / 64];
+  __shared__ int64_t off_sh[2];
+  __shared__ int flag_sh;
   const int i = blockIdx.x;
   const int nwords = (nb + 31) >> 5;
   unsigned long long* mask = smem64;
@@ -243,7 +274,8 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill_masked(
   int* wp = reinterpret_cast<int*>(bm + nwords);
   int* cur = wp + nwords;
   const Holes h{a_holes ? ablk : nullptr, aidx, b_holes ? bblk : nullptr, bidx};
-  build_row_bitmap(arp, acol, brp, bcol, h, drp, dcol, i, bm, nwords, nullptr);
+  int64_t pcount = 0;
+  build_row_bitmap(arp, acol, brp, bcol, h, drp, dcol, i, bm, nwords, ONEPASS ? &pcount : nullptr);
 
   // exclusive prefix of word popcounts: contiguous chunks per thread
   const int chunk = (nwords + kSymWG - 1) / kSymWG;
@@ -256,113 +288,149 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill_masked(
     wp[w] = run;
     run += __popc(bm[w]);
   }
-  __syncthreads();
 
-  // output columns in ascending order; clear the per-output counters and masks
-  const int cbase = crp[i];
-  for (int w = threadIdx.x; w < nwords; w += kSymWG) {
-    unsigned bits = bm[w];
-    int r = wp[w];
-    while (bits) {
-      const int j = (w << 5) + __ffs(bits) - 1;
-      ccol[cbase + r] = j;
-      if (dsrc) dsrc[cbase + r] = nullptr;
-      cur[r] = 0;
-      mask[r] = 0ull;
-      ++r;
-      bits &= bits - 1;
+  int cbase;
+  int64_t prow;
+  bool fits = true;
+  if (ONEPASS) {
+    int64_t prow_count;
+    block_exclusive_scan<int64_t, kSymWG>(pcount, scan_tmp64, &prow_count);
+    if (threadIdx.x < 64) {
+      unsigned long long ec = 0, ep = 0;
+      const bool ok = lb_exclusive2(op.wc, op.wp, op.gc, op.gp, i, nb, op.epoch, (unsigned long long)ncols,
+                                    (unsigned long long)prow_count, &ec, &ep);
+      if (threadIdx.x == 0) {
+        off_sh[0] = (int64_t)ec;
+        off_sh[1] = (int64_t)ep;
+        flag_sh = ok ? 1 : 0;
+        if (!ok) atomicExch(op.overflow, 1);
+      }
     }
+    __syncthreads();
+    cbase = (int)off_sh[0];
+    prow = off_sh[1];
+    fits = flag_sh && off_sh[0] + ncols <= op.cap_c && prow + prow_count <= op.cap_p;
+    if (threadIdx.x == 0) {
+      if (fits) crp[i] = cbase;
+      if (i == nb - 1) {
+        op.sizes[0] = off_sh[0] + ncols;
+        op.sizes[1] = prow + prow_count;
+        crp[nb] = fits ? cbase + ncols : 0;
+        if (fits) seg[cbase + ncols] = prow + prow_count;  // closing segment pointer
+        else atomicExch(op.overflow, 1);
+      }
+    }
+  } else {
+    cbase = crp[i];
+    prow = prp[i];
+    if (i == nb - 1 && threadIdx.x == 0) seg[crp[nb]] = prp[nb];  // closing segment pointer
   }
   __syncthreads();
-  if (dsrc)
-    for (int e = drp[i] + threadIdx.x; e < drp[i + 1]; e += kSymWG) {
-      const int j = dcol[e];
-      dsrc[cbase + wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u))] = dblk[e];
-    }
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int alo = arp[i], ahi = arp[i + 1];
-  auto rank = [&](int j) { return wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u)); };
-  // marks the contributions of A entries [e0, e0 + 64) in the masks
-  auto mark = [&](int e0) {
-    const int e1 = min(ahi, e0 + 64);
-    for (int e = e0 + wave; e < e1; e += kSymWG / 64) {
-      if (h.a_absent(e)) continue;  // uniform over the wave
-      const int k = acol[e];
-      const unsigned long long bit = 1ull << (e - e0);
-      for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
-        if (h.b_absent(f)) continue;
-        atomicOr(&mask[rank(bcol[f])], bit);
-      }
-    }
-  };
-  // writes the pairs of A entries [e0, e0 + 64) after cur[r] in each block
-  auto place = [&](int e0, int64_t prow) {
-    const int e1 = min(ahi, e0 + 64);
-    for (int e = e0 + wave; e < e1; e += kSymWG / 64) {
-      const double* a = ablk[aidx ? aidx[e] : e];
-      if (a_holes && !a) continue;
-      const int k = acol[e];
-      const unsigned long long below = (1ull << (e - e0)) - 1ull;
-      for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
-        const double* bp = bblk[bidx ? bidx[f] : f];
-        if (b_holes && !bp) continue;
-        const int r = rank(bcol[f]);
-        pairs[prow + cur[r] + __popcll(mask[r] & below)] = BlockPair{a, bp};
-      }
-    }
-  };
-  const bool one_run = ahi - alo <= 64;
-
-  // products per output block
-  for (int e0 = alo; e0 < ahi; e0 += 64) {
-    mark(e0);
-    __syncthreads();
-    if (!one_run) {
-      for (int r = threadIdx.x; r < ncols; r += kSymWG) {
-        cur[r] += __popcll(mask[r]);
+  if (fits) {
+    // output columns in ascending order; clear the per-output counters and masks
+    for (int w = threadIdx.x; w < nwords; w += kSymWG) {
+      unsigned bits = bm[w];
+      int r = wp[w];
+      while (bits) {
+        const int j = (w << 5) + __ffs(bits) - 1;
+        ccol[cbase + r] = j;
+        if (dsrc) dsrc[cbase + r] = nullptr;
+        cur[r] = 0;
         mask[r] = 0ull;
+        ++r;
+        bits &= bits - 1;
       }
+    }
+    __syncthreads();
+    if (dsrc)
+      for (int e = drp[i] + threadIdx.x; e < drp[i + 1]; e += kSymWG) {
+        const int j = dcol[e];
+        dsrc[cbase + wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u))] = dblk[e];
+      }
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int alo = arp[i], ahi = arp[i + 1];
+    auto rank = [&](int j) { return wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u)); };
+    // marks the contributions of A entries [e0, e0 + 64) in the masks
+    auto mark = [&](int e0) {
+      const int e1 = min(ahi, e0 + 64);
+      for (int e = e0 + wave; e < e1; e += kSymWG / 64) {
+        if (h.a_absent(e)) continue;  // uniform over the wave
+        const int k = acol[e];
+        const unsigned long long bit = 1ull << (e - e0);
+        for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
+          if (h.b_absent(f)) continue;
+          atomicOr(&mask[rank(bcol[f])], bit);
+        }
+      }
+    };
+    // writes the pairs of A entries [e0, e0 + 64) after cur[r] in each block
+    auto place = [&](int e0) {
+      const int e1 = min(ahi, e0 + 64);
+      for (int e = e0 + wave; e < e1; e += kSymWG / 64) {
+        const double* a = ablk[aidx ? aidx[e] : e];
+        if (a_holes && !a) continue;
+        const int k = acol[e];
+        const unsigned long long below = (1ull << (e - e0)) - 1ull;
+        for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
+          const double* bp = bblk[bidx ? bidx[f] : f];
+          if (b_holes && !bp) continue;
+          const int r = rank(bcol[f]);
+          pairs[prow + cur[r] + __popcll(mask[r] & below)] = BlockPair{a, bp};
+        }
+      }
+    };
+    const bool one_run = ahi - alo <= 64;
+
+    // products per output block
+    for (int e0 = alo; e0 < ahi; e0 += 64) {
+      mark(e0);
       __syncthreads();
+      if (!one_run) {
+        for (int r = threadIdx.x; r < ncols; r += kSymWG) {
+          cur[r] += __popcll(mask[r]);
+          mask[r] = 0ull;
+        }
+        __syncthreads();
+      }
     }
-  }
-  if (one_run)
-    for (int r = threadIdx.x; r < ncols; r += kSymWG) cur[r] = __popcll(mask[r]);
-  __syncthreads();
-
-  // exclusive scan of the per-output counts -> segment starts
-  const int c0 = min(ncols, (int)threadIdx.x * ((ncols + kSymWG - 1) / kSymWG));
-  const int c1 = min(ncols, c0 + (ncols + kSymWG - 1) / kSymWG);
-  int t = 0;
-  for (int r = c0; r < c1; ++r) t += cur[r];
-  __syncthreads();  // scan_tmp is reused
-  int tot;
-  int acc = block_exclusive_scan<int, kSymWG>(t, scan_tmp, &tot);
-  const int64_t prow = prp[i];
-  if (i == nb - 1 && threadIdx.x == 0) seg[crp[nb]] = prp[nb];  // closing segment pointer
-  for (int r = c0; r < c1; ++r) {
-    const int cnt = cur[r];
-    seg[cbase + r] = prow + acc;
-    cur[r] = acc;
-    acc += cnt;
-  }
-  __syncthreads();
-
-  // pairs: one run reuses its masks; longer rows mark each run again
-  if (one_run) {
-    place(alo, prow);
-    return;
-  }
-  for (int e0 = alo; e0 < ahi; e0 += 64) {
-    mark(e0);
+    if (one_run)
+      for (int r = threadIdx.x; r < ncols; r += kSymWG) cur[r] = __popcll(mask[r]);
     __syncthreads();
-    place(e0, prow);
-    __syncthreads();
-    for (int r = threadIdx.x; r < ncols; r += kSymWG) {
-      cur[r] += __popcll(mask[r]);
-      mask[r] = 0ull;
+
+    // exclusive scan of the per-output counts -> segment starts
+    const int c0 = min(ncols, (int)threadIdx.x * ((ncols + kSymWG - 1) / kSymWG));
+    const int c1 = min(ncols, c0 + (ncols + kSymWG - 1) / kSymWG);
+    int t = 0;
+    for (int r = c0; r < c1; ++r) t += cur[r];
+    __syncthreads();  // scan_tmp is reused
+    int tot;
+    int acc = block_exclusive_scan<int, kSymWG>(t, scan_tmp, &tot);
+    for (int r = c0; r < c1; ++r) {
+      const int cnt = cur[r];
+      seg[cbase + r] = prow + acc;
+      cur[r] = acc;
+      acc += cnt;
     }
     __syncthreads();
+
+    // pairs: one run reuses its masks; longer rows mark each run again
+    if (one_run) {
+      place(alo);
+    } else {
+      for (int e0 = alo; e0 < ahi; e0 += 64) {
+        mark(e0);
+        __syncthreads();
+        place(e0);
+        __syncthreads();
+        for (int r = threadIdx.x; r < ncols; r += kSymWG) {
+          cur[r] += __popcll(mask[r]);
+          mask[r] = 0ull;
+        }
+        __syncthreads();
+      }
+    }
   }
 }
 
@@ -497,7 +565,7 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const int64
   __shared__ __attribute__((aligned(16))) double As[A_LDS ? Cfg::LDS_DOUBLES : 2];
   __shared__ __attribute__((aligned(16))) double Bs[B_LDS ? Cfg::LDS_DOUBLES : 2];
   __shared__ double red[Cfg::WAVES];
-  const int64_t nlive = *live;
+  const int64_t nlive = live_blocks(live, epi);
   if ((int64_t)blockIdx.x >= nlive) return;
   const int64_t blk = xcd_remap(blockIdx.x, nlive);
   const int64_t p0 = seg[blk], p1 = seg[blk + 1];
@@ -606,10 +674,10 @@ void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* ai
                           const int* dcol, BlkIn dblk, int nb, const int* crp, const int64_t* prp, int* ccol,
                           int64_t* seg, BlockPair* pairs, BlkOut dsrc) {
   if (masked_fill_lds_bytes(nb) <= kMaskedFillLds) {
-    allow_lds((const void*)k_symbolic_fill_masked, masked_fill_lds_bytes(nb));
-    hipLaunchKernelGGL(k_symbolic_fill_masked, dim3(nb), dim3(kSymWG), masked_fill_lds_bytes(nb), c.stream, arp,
-                       acol, aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb, crp, prp, ccol,
-                       seg, pairs, dsrc);
+    allow_lds((const void*)k_symbolic_fill_masked<false>, masked_fill_lds_bytes(nb));
+    hipLaunchKernelGGL(k_symbolic_fill_masked<false>, dim3(nb), dim3(kSymWG), masked_fill_lds_bytes(nb), c.stream,
+                       arp, acol, aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb,
+                       const_cast<int*>(crp), prp, ccol, seg, pairs, dsrc, OnePass{});
     LIF_HIP(hipGetLastError());
     return;
   }
@@ -620,8 +688,34 @@ void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* ai
   LIF_HIP(hipGetLastError());
 }
 
+bool symbolic_onepass_fits(int nb) { return masked_fill_lds_bytes(nb) <= kMaskedFillLds; }
+
+void launch_symbolic_onepass(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp,
+                             const int* bcol, const int* bidx, BlkIn ablk, BlkIn bblk, bool a_holes, bool b_holes,
+                             const int* drp, const int* dcol, BlkIn dblk, int nb, int64_t cap_c, int64_t cap_p,
+                             int* crp, int* ccol, int64_t* seg, BlockPair* pairs, BlkOut dsrc, int64_t* sizes,
+                             int* overflow) {
+  Ctx::Lookback& lb = c.lookback_for(nb);
+  OnePass op;
+  op.wc = lb.words.get();
+  op.wp = op.wc + lb.rows;
+  op.gc = op.wp + lb.rows;
+  op.gp = op.gc + Ctx::Lookback::groups(lb.rows);
+  op.epoch = lb.next_epoch();
+  op.cap_c = cap_c;
+  op.cap_p = cap_p;
+  op.sizes = sizes;
+  op.overflow = overflow;
+  allow_lds((const void*)k_symbolic_fill_masked<true>, masked_fill_lds_bytes(nb));
+  hipLaunchKernelGGL(k_symbolic_fill_masked<true>, dim3(nb), dim3(kSymWG), masked_fill_lds_bytes(nb), c.stream, arp,
+                     acol, aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb, crp, nullptr,
+                     ccol, seg, pairs, dsrc, op);
+  LIF_HIP(hipGetLastError());
+}
+
 void launch_numeric(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg, const BlockPair* pairs,
                     int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms, const Epilogue& epi) {
+  nnzc = std::max<int64_t>(nnzc, epi.poison ? 1 : 0);  // a voided product still clears its row pointers
   if (nnzc == 0) return;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c.timing) {

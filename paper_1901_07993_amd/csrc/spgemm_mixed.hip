@@ -130,7 +130,7 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(
   __shared__ double red[Cfg::WAVES];
   // the grid may exceed the live output count (capacity fixed before the
   // count was known); the XCD remap runs over the live blocks only
-  const int64_t nlive = *live;
+  const int64_t nlive = live_blocks(live, epi);
   if ((int64_t)blockIdx.x >= nlive) return;
   const int64_t blk = xcd_remap_m(blockIdx.x, nlive);
   const int64_t p0 = seg[blk], p1 = seg[blk + 1];
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(
   __shared__ double red[Cfg::WAVES];
   // the grid may exceed the live output count (capacity fixed before the
   // count was known); the XCD remap runs over the live blocks only
-  const int64_t nlive = *live;
+  const int64_t nlive = live_blocks(live, epi);
   if ((int64_t)blockIdx.x >= nlive) return;
   const int64_t blk = xcd_remap_m(blockIdx.x, nlive);
   const int64_t p0 = seg[blk], p1 = seg[blk + 1];
