@@ -10,6 +10,7 @@
 // Passes that do touch values handle one block per workgroup with coalesced
 // 16-byte accesses; index work runs one thread per block row or block.
 #include "block_scan.h"
+#include "lookback.h"
 #include "common.h"
 #include "tile_mma.h"
 
@@ -233,19 +234,25 @@ inline size_t union_rows_lds(int nb, bool fill) {
   return fill ? (4 * nwords + 3 * (size_t)nb) * 4 : 3 * nwords * 4;
 }
 
-template <bool FILL>
+// MODE 0: counts[i]; 1: fill at the row pointers rc; 2: one pass -- the
+// row pointers are the prefix sums of the counts over the lower rows,
+// obtained by look-back (lookback.h) and written to rc by each row.  Modes 0
+// and 2 also zero *slot.
+template <int MODE>
 __global__ __launch_bounds__(kUR) void k_union_rows(Src3 S, const unsigned char* __restrict__ diag_on, int nb,
                                                     int* __restrict__ counts, int* __restrict__ slot,
-                                                    const int* __restrict__ rc, int* __restrict__ cc,
+                                                    int* __restrict__ rc, int* __restrict__ cc,
                                                     int* __restrict__ ix, int64_t stride,
-                                                    unsigned char* __restrict__ id, int* __restrict__ rowof) {
+                                                    unsigned char* __restrict__ id, int* __restrict__ rowof,
+                                                    Ctx::LbWords lbw) {
+  constexpr bool FILL = MODE != 0;
   extern __shared__ unsigned smem[];
   __shared__ int scan_tmp[1];
   const int i = blockIdx.x;
   const int nwords = (nb + 31) >> 5;
   unsigned* bm = smem;                              // [3][nwords]
   int* c2i = reinterpret_cast<int*>(smem + 4 * nwords);  // [3][nb] (fill)
-  if (!FILL && slot && i == 0 && threadIdx.x == 0) *slot = 0;
+  if (MODE != 1 && slot && i == 0 && threadIdx.x == 0) *slot = 0;
   for (int w = threadIdx.x; w < 3 * nwords; w += kUR) bm[w] = 0u;
   __syncthreads();
 #pragma unroll
@@ -277,7 +284,24 @@ __global__ __launch_bounds__(kUR) void k_union_rows(Src3 S, const unsigned char*
     return;
   }
   int total;
-  int r = rc[i] + block_exclusive_scan<int, kUR>(s, scan_tmp, &total);
+  int r = block_exclusive_scan<int, kUR>(s, scan_tmp, &total);
+  if (MODE == 2) {  // one wave: the whole workgroup takes part in the look-back
+    unsigned long long ea = 0, eb = 0;
+    const bool ok =
+        lb_exclusive2(lbw.ra, lbw.rb, lbw.ga, lbw.gb, i, nb, lbw.epoch, (unsigned long long)total, 0ull, &ea, &eb);
+    // a union's size is bounded by its operands', so no capacity can be
+    // short; a look-back that gave up leaves the prefix at 0 (in bounds,
+    // wrong) and raises the flag the host checks
+    if (!ok && threadIdx.x == 0) atomicExch(lbw.fail, 1);
+    const int base = ok ? (int)ea : 0;
+    if (threadIdx.x == 0) {
+      rc[i] = base;
+      if (i == nb - 1) rc[nb] = base + total;
+    }
+    r += base;
+  } else {
+    r += rc[i];
+  }
   for (int w = w0; w < w1; ++w) {
     unsigned bits = word(w);
     while (bits) {
@@ -708,8 +732,8 @@ void launch_union3(Ctx& c, const int* const rp[3], const int* const col[3], cons
     S.hole[t] = hole[t];
   }
   if (union_rows_lds(nb, true) <= kUnionRowsLds) {
-    LIF_LAUNCH(k_union_rows<false>, dim3(nb), dim3(kUR), union_rows_lds(nb, false), c.stream, S, diag_on, nb, counts,
-               slot, nullptr, nullptr, nullptr, 0, nullptr, nullptr);
+    LIF_LAUNCH(k_union_rows<0>, dim3(nb), dim3(kUR), union_rows_lds(nb, false), c.stream, S, diag_on, nb, counts,
+               slot, nullptr, nullptr, nullptr, 0, nullptr, nullptr, Ctx::LbWords{});
     return;
   }
   LIF_LAUNCH(k_union_counts, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, S, diag_on, nb, counts, slot);
@@ -725,12 +749,28 @@ void launch_union3_fill(Ctx& c, const int* const rp[3], const int* const col[3],
     S.hole[t] = hole[t];
   }
   if (union_rows_lds(nb, true) <= kUnionRowsLds) {
-    LIF_LAUNCH(k_union_rows<true>, dim3(nb), dim3(kUR), union_rows_lds(nb, true), c.stream, S, diag_on, nb, nullptr,
-               nullptr, rc, cc, ix, stride, id, rowof);
+    LIF_LAUNCH(k_union_rows<1>, dim3(nb), dim3(kUR), union_rows_lds(nb, true), c.stream, S, diag_on, nb, nullptr,
+               nullptr, const_cast<int*>(rc), cc, ix, stride, id, rowof, Ctx::LbWords{});
     return;
   }
   LIF_LAUNCH(k_union_fill, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, S, diag_on, rc, nb, cc, ix, stride, id,
              rowof);
+}
+
+bool union_onepass_fits(int nb) { return union_rows_lds(nb, true) <= kUnionRowsLds; }
+
+void launch_union3_onepass(Ctx& c, const int* const rp[3], const int* const col[3], const BlkIn hole[3],
+                           const unsigned char* diag_on, int* rc, int nb, int* cc, int* ix, int64_t stride,
+                           unsigned char* id, int* rowof, int* slot) {
+  Src3 S;
+  for (int t = 0; t < 3; ++t) {
+    S.rp[t] = rp[t];
+    S.col[t] = col[t];
+    S.hole[t] = hole[t];
+  }
+  const Ctx::LbWords w = c.lookback_words(nb);
+  LIF_LAUNCH(k_union_rows<2>, dim3(nb), dim3(kUR), union_rows_lds(nb, true), c.stream, S, diag_on, nb, nullptr, slot,
+             rc, cc, ix, stride, id, rowof, w);
 }
 
 void launch_keep_count_scan(Ctx& c, const int* row_ptr, const double* norms, double tau, int nb, int* out_rp) {

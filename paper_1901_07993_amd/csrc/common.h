@@ -223,6 +223,20 @@ struct Ctx {
   };
   std::map<hipStream_t, Lookback> lookback;
   Lookback& lookback_for(int rows);  // the current stream's, for `rows` rows
+  // the word arrays of the current stream's look-back and a fresh epoch,
+  // for one launch over `rows` rows
+  struct LbWords {
+    unsigned long long* ra = nullptr;  // per-row words, first value
+    unsigned long long* rb = nullptr;  // per-row words, second value
+    unsigned long long* ga = nullptr;  // per-group sums, first value
+    unsigned long long* gb = nullptr;  // per-group sums, second value
+    unsigned epoch = 0;
+    int* fail = nullptr;  // raised by a row whose wait gave up
+  };
+  LbWords lookback_words(int rows);
+  // raised on the device when a single-pass scan gave up waiting (its
+  // result is wrong); checked with the refinement's norms
+  DBuf<int> lb_fail;
   // events around leaf-GEMM launches (timing mode), resolved at flush_timing()
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
   std::vector<hipEvent_t> ev_free;
@@ -318,6 +332,13 @@ void launch_union3(Ctx& c, const int* const rp[3], const int* const col[3], cons
 void launch_union3_fill(Ctx& c, const int* const rp[3], const int* const col[3], const BlkIn hole[3],
                         const unsigned char* diag_on, const int* rc, int nb, int* cc, int* ix, int64_t stride,
                         unsigned char* id, int* rowof);
+// counts, row pointers (written to rc[0..nb]) and fill in one launch, with
+// the row counts' prefix sums by look-back; also zeroes *slot.  Only for nb
+// with union_onepass_fits(nb).
+bool union_onepass_fits(int nb);
+void launch_union3_onepass(Ctx& c, const int* const rp[3], const int* const col[3], const BlkIn hole[3],
+                           const unsigned char* diag_on, int* rc, int nb, int* cc, int* ix, int64_t stride,
+                           unsigned char* id, int* rowof, int* slot);
 void launch_keep_count_scan(Ctx& c, const int* row_ptr, const double* norms, double tau, int nb, int* out_rp);
 void launch_filter_count_scan(Ctx& c, const int* row_ptr, const int* col, const int* rlab, const int* clab, int mode,
                               int nb, int* out_rp);

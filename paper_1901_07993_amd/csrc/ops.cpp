@@ -357,23 +357,28 @@ Bsr union_sum(Ctx& c, const Bsr* const src[3], const double coef[3], double gamm
   C.cap = cap;
   C.row_ptr = DBuf<int>(c.pool, nb + 1);
   DBuf<int> slot(c.pool, 1);
-  {
-    DBuf<int> cnt(c.pool, nb);
-    launch_union3(c, rp, col, hole, diag_on, nb, cnt.get(), slot.get());
-    scan_exclusive_i32(c, cnt.get(), C.row_ptr.get(), nb);
-  }
   C.col = DBuf<int>(c.pool, (size_t)cap);
   DBuf<int> ix(c.pool, (size_t)cap * 3), rowof(c.pool, (size_t)cap);
   DBuf<unsigned char> id(c.pool, (size_t)cap);
   Store st = new_store(c, computed, C.b);
   C.blk = DBuf<const double*>(c.pool, (size_t)cap);
   C.store.push_back(st);
-  if (cap) {
-    launch_union3_fill(c, rp, col, hole, diag_on, C.row_ptr.get(), nb, C.col.get(), ix.get(), cap, id.get(),
-                       rowof.get());
+  if (union_onepass_fits(nb)) {  // pattern in one launch
+    launch_union3_onepass(c, rp, col, hole, diag_on, C.row_ptr.get(), nb, C.col.get(), ix.get(), cap, id.get(),
+                          rowof.get(), slot.get());
+  } else {
+    {
+      DBuf<int> cnt(c.pool, nb);
+      launch_union3(c, rp, col, hole, diag_on, nb, cnt.get(), slot.get());
+      scan_exclusive_i32(c, cnt.get(), C.row_ptr.get(), nb);
+    }
+    if (cap)
+      launch_union3_fill(c, rp, col, hole, diag_on, C.row_ptr.get(), nb, C.col.get(), ix.get(), cap, id.get(),
+                         rowof.get());
+  }
+  if (cap)
     launch_axpby3_values(c, val, coef, ix.get(), cap, gamma, id.get(), rowof.get(), cap, C.b, C.n, st->get(),
                          slot.get(), C.blk.get(), C.live());
-  }
   return C;
 }
 
@@ -473,8 +478,12 @@ std::vector<double> node_sumsq(Ctx& c, const Bsr& A, const int* rlo, const int* 
     reads.push_back({out.data() + s, seg.get() + s, sizeof(double) * (size_t)std::min(8, nseg - s)});
   const bool need = A.nnzb < 0;
   if (need) reads.push_back({&na, A.live(), sizeof(int)});
+  int lb_fail = 0;
+  if (c.lb_fail.get()) reads.push_back({&lb_fail, c.lb_fail.get(), sizeof(int)});
   reads.insert(reads.end(), extra.begin(), extra.end());
   c.d2h_batch(reads);
+  LIF_REQUIRE(!lb_fail, LIF_ERR_HIP, "a single-pass scan gave up waiting for a lower row (workgroups started out "
+                                     "of order); results of this call are invalid");
   if (need) A.nnzb = na;
   return out;
 }

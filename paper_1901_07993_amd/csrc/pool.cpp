@@ -164,6 +164,10 @@ hipStream_t Ctx::side_stream() {
 
 Ctx::Lookback& Ctx::lookback_for(int rows) {
   Lookback& lb = lookback[stream];
+  if (!lb_fail.get()) {
+    lb_fail = DBuf<int>(pool, 1);
+    LIF_HIP(hipMemsetAsync(lb_fail.get(), 0, sizeof(int), stream));
+  }
   if (lb.rows < rows) {
     // zeroed once: no word reads as published
     const size_t words = 2 * ((size_t)rows + Lookback::groups(rows));
@@ -172,6 +176,18 @@ Ctx::Lookback& Ctx::lookback_for(int rows) {
     lb.rows = rows;
   }
   return lb;
+}
+
+Ctx::LbWords Ctx::lookback_words(int rows) {
+  Lookback& lb = lookback_for(rows);
+  LbWords w;
+  w.ra = lb.words.get();
+  w.rb = w.ra + lb.rows;
+  w.ga = w.rb + lb.rows;
+  w.gb = w.ga + Lookback::groups(lb.rows);
+  w.epoch = lb.next_epoch();
+  w.fail = lb_fail.get();
+  return w;
 }
 
 hipEvent_t Ctx::order_event(size_t i) {

@@ -245,11 +245,7 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
 // their index; were it otherwise, the bounded wait gives up and the
 // product is voided, never hung.
 struct OnePass {
-  unsigned long long* wc = nullptr;  // published words: output blocks per row
-  unsigned long long* wp = nullptr;  // published words: block products per row
-  unsigned long long* gc = nullptr;  // published words: their sums per group of 64 rows
-  unsigned long long* gp = nullptr;
-  unsigned epoch = 0;
+  Ctx::LbWords lb;  // look-back words: output blocks (a) and block products (b) per row
   int64_t cap_c = 0, cap_p = 0;
   int64_t* sizes = nullptr;
   int* overflow = nullptr;
@@ -297,13 +293,16 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill_masked(
     block_exclusive_scan<int64_t, kSymWG>(pcount, scan_tmp64, &prow_count);
     if (threadIdx.x < 64) {
       unsigned long long ec = 0, ep = 0;
-      const bool ok = lb_exclusive2(op.wc, op.wp, op.gc, op.gp, i, nb, op.epoch, (unsigned long long)ncols,
-                                    (unsigned long long)prow_count, &ec, &ep);
+      const bool ok = lb_exclusive2(op.lb.ra, op.lb.rb, op.lb.ga, op.lb.gb, i, nb, op.lb.epoch,
+                                    (unsigned long long)ncols, (unsigned long long)prow_count, &ec, &ep);
       if (threadIdx.x == 0) {
         off_sh[0] = (int64_t)ec;
         off_sh[1] = (int64_t)ep;
         flag_sh = ok ? 1 : 0;
-        if (!ok) atomicExch(op.overflow, 1);
+        if (!ok) {
+          atomicExch(op.overflow, 1);
+          atomicExch(op.lb.fail, 1);
+        }
       }
     }
     __syncthreads();
@@ -695,13 +694,8 @@ void launch_symbolic_onepass(Ctx& c, const int* arp, const int* acol, const int*
                              const int* drp, const int* dcol, BlkIn dblk, int nb, int64_t cap_c, int64_t cap_p,
                              int* crp, int* ccol, int64_t* seg, BlockPair* pairs, BlkOut dsrc, int64_t* sizes,
                              int* overflow) {
-  Ctx::Lookback& lb = c.lookback_for(nb);
   OnePass op;
-  op.wc = lb.words.get();
-  op.wp = op.wc + lb.rows;
-  op.gc = op.wp + lb.rows;
-  op.gp = op.gc + Ctx::Lookback::groups(lb.rows);
-  op.epoch = lb.next_epoch();
+  op.lb = c.lookback_words(nb);
   op.cap_c = cap_c;
   op.cap_p = cap_p;
   op.sizes = sizes;
