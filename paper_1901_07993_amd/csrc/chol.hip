@@ -312,53 +312,6 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_potrf(int k, const int*
   potrf_tile<B, NT>(smem, U + t * B * B, Z + t * B * B, (blk0[s] + k) * B, &err[s]);
 }
 
-// blockIdx.x < m: U_kj = Z_kk^T U_kj for j = k + 1 + blockIdx.x (j - k <=
-// band: the grid covers the band only); blockIdx.x >= m: V_ik = U_ik Z_kk for
-// i = max(0, k - band) + (blockIdx.x - m) < k, written over U_ik
-template <int B>
-__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trsm(int k, int m, int band, const int* __restrict__ nbbv,
-                                                              const int64_t* __restrict__ tile0,
-                                                              double* __restrict__ U, const double* __restrict__ Z,
-                                                              const unsigned char* __restrict__ nz) {
-  using Cfg = TileCfg<B>;
-  __shared__ double As[Cfg::LDS_DOUBLES];
-  __shared__ double Bs[Cfg::LDS_DOUBLES];
-  const int s = blockIdx.y;
-  const int nbb = nbbv[s];
-  if (k >= nbb) return;
-  const bool vtask = (int)blockIdx.x >= m;
-  const int j = k + 1 + blockIdx.x;            // U task column
-  const int i = max(0, k - band) + ((int)blockIdx.x - m);  // V task row
-  if (vtask ? (i < 0 || !nz[packed_tile(tile0[s], nbb, i, k)])
-            : (j >= nbb || !nz[packed_tile(tile0[s], nbb, k, j)]))
-    return;
-  const Frag f = frag_coords<B>();
-  v2d reg[Cfg::V2];
-  double* g = U + (vtask ? packed_tile(tile0[s], nbb, i, k) : packed_tile(tile0[s], nbb, k, j)) * B * B;
-  const double* zkk = Z + packed_tile(tile0[s], nbb, k, k) * B * B;
-  if (vtask) {
-    tile_load<B>(g, reg);
-    tile_store<B>(As, reg, false);  // op(A) = U_ik: LDS row c is column c of U_ik
-    tile_load<B>(zkk, reg);
-    tile_store<B>(Bs, reg, true);
-  } else {
-    tile_load<B>(zkk, reg);
-    tile_store<B>(As, reg, true);  // op(A) = Z_kk^T: LDS row k is row k of Z_kk
-    tile_load<B>(g, reg);
-    tile_store<B>(Bs, reg, true);
-  }
-  __syncthreads();
-  v4d acc[2][2];
-  acc_zero(acc);
-  tile_mma<B>(As, Bs, f, acc);
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) g[acc_row(f, ti, r) * B + acc_col(f, tj)] = acc[ti][tj][r];
-}
-
 __device__ inline void tri_decode(int64_t t, int& ip, int& jp) {
   // t = jp (jp + 1) / 2 + ip with 0 <= ip <= jp
   int j = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -368,17 +321,43 @@ __device__ inline void tri_decode(int64_t t, int& ip, int& jp) {
   ip = (int)(t - (int64_t)j * (j + 1) / 2);
 }
 
-// U_ij -= U_ki^T U_kj for k < i <= j <= k + band (the factor keeps the band
-// of S within a leaf), and the next step's diagonal factorization: the
-// workgroup of tile (k+1, k+1) -- the last update that tile receives --
-// hands its result to potrf_tile in LDS instead of a separate launch.
+// Registers of an MFMA accumulator -> LDS tile (row-major, stride LD), as
+// an operand for tile_mma: row r of the stored tile is LDS row r.
 template <int B>
-__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_update(int k, int band, const int* __restrict__ nbbv,
-                                                                const int* __restrict__ blk0,
-                                                                const int64_t* __restrict__ tile0,
-                                                                double* __restrict__ U, double* __restrict__ Z,
-                                                                unsigned char* __restrict__ nz,
-                                                                int* __restrict__ err) {
+__device__ __attribute__((always_inline)) inline void acc_to_lds(double* s, const v4d (&acc)[2][2], const Frag& f) {
+  constexpr int LD = TileCfg<B>::LD;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s[acc_row(f, ti, r) * LD + acc_col(f, tj)] = acc[ti][tj][r];
+}
+
+// Step k of the batched leaf factorization, one launch (grid.y = leaf).
+// Task t < nupd is the trailing tile (i, j) = (k+1+ip, k+1+jp), ip <= jp,
+// of the tile band:
+//     U_ki = Z_kk^T T_ki and U_kj = Z_kk^T T_kj (the row-k panel of the
+//     factor, recomputed by each task that needs it, so that no task waits
+//     for another), then T_ij -= U_ki^T U_kj.
+//   A diagonal task (i = j) also stores U_kj, in Z's (k, j) slot: Z_kj is
+//   written only by the inverse's column j, after the V task of step j has
+//   read U_kj there.  Task 0 -- tile (k+1, k+1), whose last update this is
+//   -- then factorizes that tile in LDS (U_{k+1,k+1}, Z_{k+1,k+1}).
+// The other tasks are the V tiles of column k:
+//     V_ik = U_ik Z_kk for max(0, k - band) <= i < k,
+//   U_ik read from Z's (i, k) slot and V_ik written to U's (i, k) slot,
+//   whose T_ik no step reads any more.
+// Within a step no task reads what another writes; the serial chain per
+// tile column is this one launch.
+template <int B>
+__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_step(int k, int band, int nupd,
+                                                              const int* __restrict__ nbbv,
+                                                              const int* __restrict__ blk0,
+                                                              const int64_t* __restrict__ tile0,
+                                                              double* __restrict__ U, double* __restrict__ Z,
+                                                              unsigned char* __restrict__ nz,
+                                                              int* __restrict__ err) {
   using Cfg = TileCfg<B>;
   constexpr int NT = Cfg::THREADS;
   constexpr int SMEM = (2 * Cfg::LDS_DOUBLES > PotrfLds<B>::DOUBLES) ? 2 * Cfg::LDS_DOUBLES : PotrfLds<B>::DOUBLES;
@@ -387,23 +366,49 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_update(int k, int band,
   double* Bs = smem + Cfg::LDS_DOUBLES;
   const int s = blockIdx.y;
   const int nbb = nbbv[s];
+  if (k >= nbb) return;
+  const int64_t t0 = tile0[s];
+  const int t = blockIdx.x;
+  const Frag f = frag_coords<B>();
+  const double* zkk = Z + packed_tile(t0, nbb, k, k) * B * B;
+
+  if (t >= nupd) {  // V task
+    const int i = max(0, k - band) + (t - nupd);
+    if (i >= k || !nz[packed_tile(t0, nbb, i, k)]) return;
+    const int64_t tik = packed_tile(t0, nbb, i, k);
+    v2d reg[Cfg::V2];
+    tile_load<B>(Z + tik * B * B, reg);
+    tile_store<B>(As, reg, false);  // op(A) = U_ik: LDS row c is column c of U_ik
+    tile_load<B>(zkk, reg);
+    tile_store<B>(Bs, reg, true);
+    __syncthreads();
+    v4d acc[2][2];
+    acc_zero(acc);
+    tile_mma<B>(As, Bs, f, acc);
+    double* g = U + tik * B * B;
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) g[acc_row(f, ti, r) * B + acc_col(f, tj)] = acc[ti][tj][r];
+    return;
+  }
+
   const int m = min(band, nbb - k - 1);
-  const int64_t t = blockIdx.x;
-  const bool next_diag = t == 0 && k + 1 < nbb;  // this workgroup also factorizes tile (k+1, k+1)
-  const bool in_band = m > 0 && t < (int64_t)m * (m + 1) / 2;
-  if (!next_diag && !in_band) return;
+  if (t >= m * (m + 1) / 2) return;  // this leaf's band is narrower here
   int ip = 0, jp = 0;
-  if (in_band) tri_decode(t, ip, jp);
+  tri_decode(t, ip, jp);
   const int i = k + 1 + ip, j = k + 1 + jp;
-  const int64_t tij = packed_tile(tile0[s], nbb, i, j);
+  const bool diag = i == j;
+  const bool next_diag = t == 0;  // tile (k+1, k+1)
+  const int64_t tki = packed_tile(t0, nbb, k, i), tkj = packed_tile(t0, nbb, k, j);
+  const int64_t tij = packed_tile(t0, nbb, i, j);
   double* g = U + tij * B * B;
-  const bool upd = in_band && nz[packed_tile(tile0[s], nbb, k, i)] && nz[packed_tile(tile0[s], nbb, k, j)];
-  if (upd) {
-    const Frag f = frag_coords<B>();
+  if (nz[tki] && nz[tkj]) {
     // a tile outside S's pattern that no earlier step reached holds no data
     // yet (the buffer is not cleared): its first update writes -acc
     const bool first = !nz[tij];
-    // the target's elements this lane updates, loaded with the operands
     double old[2][2][4];
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
@@ -411,11 +416,38 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_update(int k, int band,
       for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
         for (int r = 0; r < 4; ++r) old[ti][tj][r] = first ? 0.0 : g[acc_row(f, ti, r) * B + acc_col(f, tj)];
-    v2d ra[Cfg::V2], rb[Cfg::V2];
-    tile_load<B>(U + packed_tile(tile0[s], nbb, k, i) * B * B, ra);
-    tile_load<B>(U + packed_tile(tile0[s], nbb, k, j) * B * B, rb);
-    tile_store<B>(As, ra, true);  // op(A) = U_ki^T
-    tile_store<B>(Bs, rb, true);
+    v2d rz[Cfg::V2], ri[Cfg::V2], rj[Cfg::V2];
+    tile_load<B>(zkk, rz);
+    tile_load<B>(U + tki * B * B, ri);
+    if (!diag) tile_load<B>(U + tkj * B * B, rj);
+    tile_store<B>(As, rz, true);  // op(A) = Z_kk^T
+    tile_store<B>(Bs, ri, true);  // op(B) = T_ki
+    __syncthreads();
+    v4d ui[2][2], uj[2][2];
+    acc_zero(ui);
+    tile_mma<B>(As, Bs, f, ui);  // U_ki
+    if (!diag) {
+      __syncthreads();
+      tile_store<B>(Bs, rj, true);  // op(B) = T_kj
+      __syncthreads();
+      acc_zero(uj);
+      tile_mma<B>(As, Bs, f, uj);  // U_kj
+    }
+    __syncthreads();
+    acc_to_lds<B>(As, ui, f);  // op(A) = U_ki^T: LDS row r is row r of U_ki
+    if (diag)
+      acc_to_lds<B>(Bs, ui, f);
+    else
+      acc_to_lds<B>(Bs, uj, f);
+    if (diag) {  // the panel tile for the V task of step j
+      double* zs = Z + tkj * B * B;
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) zs[acc_row(f, ti, r) * B + acc_col(f, tj)] = ui[ti][tj][r];
+    }
     __syncthreads();
     v4d acc[2][2];
     acc_zero(acc);
@@ -536,28 +568,19 @@ void launch_potrf(Ctx& c, int k, int nbase, const int* nbb, const int* blk0, con
                err);
 }
 
-void launch_trsm(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b,
-                 double* U, const double* Z, const unsigned char* nz) {
+void launch_step(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int* blk0,
+                 const int64_t* tile0, int b, double* U, double* Z, unsigned char* nz, int* err) {
   const int m = std::max(0, std::min(band, max_nbb - k - 1));
+  const int nupd = m * (m + 1) / 2;
   const int nv = std::min(band, k);
-  if (m + nv <= 0) return;
-  dim3 grid(m + nv, nbase);
+  if (nupd + nv <= 0) return;
+  dim3 grid(nupd + nv, nbase);
   if (b == 64)
-    LIF_LAUNCH(k_trsm<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, k, m, band, nbb, tile0, U, Z, nz);
+    LIF_LAUNCH(k_step<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, k, band, nupd, nbb, blk0, tile0, U, Z, nz,
+               err);
   else
-    LIF_LAUNCH(k_trsm<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, k, m, band, nbb, tile0, U, Z, nz);
-}
-
-void launch_update(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int* blk0,
-                   const int64_t* tile0, int b, double* U, double* Z, unsigned char* nz, int* err) {
-  const int64_t m = std::max(0, std::min(band, max_nbb - k - 1));
-  const int64_t tasks = std::max<int64_t>(m * (m + 1) / 2, k + 1 < max_nbb ? 1 : 0);
-  if (tasks <= 0) return;
-  dim3 grid((unsigned)tasks, nbase);
-  if (b == 64)
-    LIF_LAUNCH(k_update<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, k, band, nbb, blk0, tile0, U, Z, nz, err);
-  else
-    LIF_LAUNCH(k_update<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, k, band, nbb, blk0, tile0, U, Z, nz, err);
+    LIF_LAUNCH(k_step<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, k, band, nupd, nbb, blk0, tile0, U, Z, nz,
+               err);
 }
 
 void launch_trinv(Ctx& c, int j, int band, int nbase, const int* nbb, const int64_t* tile0, int b, const double* U,

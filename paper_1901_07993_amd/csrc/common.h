@@ -449,12 +449,11 @@ void launch_chol_pad(Ctx& c, int nbase, const int* nbb, const int* rows, const i
 void launch_potrf(Ctx& c, int k, int nbase, const int* nbb, const int* blk0, const int64_t* tile0, int b, double* U,
                   double* Z, const unsigned char* nz, int* err);
 // `band`: largest j - i over the nonzero tiles (i, j) of S within a leaf;
-// the factor's nonzero tiles satisfy j - i <= band as well
-void launch_trsm(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int64_t* tile0, int b,
-                 double* U, const double* Z, const unsigned char* nz);
-// update of step k and the diagonal factorization of step k + 1
-void launch_update(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int* blk0,
-                   const int64_t* tile0, int b, double* U, double* Z, unsigned char* nz, int* err);
+// the factor's nonzero tiles satisfy j - i <= band as well.
+// Step k: the trailing update with the row-k panel of the factor, the
+// diagonal factorization of step k + 1 and the V tiles of column k.
+void launch_step(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int* blk0,
+                 const int64_t* tile0, int b, double* U, double* Z, unsigned char* nz, int* err);
 void launch_trinv(Ctx& c, int j, int band, int nbase, const int* nbb, const int64_t* tile0, int b, const double* U,
                   double* Z, const unsigned char* nz);
 

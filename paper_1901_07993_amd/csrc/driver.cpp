@@ -407,23 +407,21 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   int band = 0;
   c.d2h(&band, d_band.get(), sizeof(int));
   launch_chol_pad(c, nbase, d_nbb.get(), d_rows.get(), d_tile0.get(), b, U.get(), 1.0);
-  // The factorization steps run on the main stream.  Tile column j of the
-  // inverse needs only columns < j and the V tiles of step j, so it runs on
-  // the side stream as soon as step j's trsm is done, overlapping the later
-  // (serial, small) factorization steps.
+  // The factorization steps run on the main stream, one launch each.  Tile
+  // column j of the inverse needs only columns < j and the V tiles of step
+  // j, so it runs on the side stream as soon as step j is done, overlapping
+  // the later (serial, small) factorization steps.
   hipStream_t side = c.side_stream();
   hipStream_t main_stream = c.stream;
-  // step 0's diagonal tile; every later one is factorized by the update
-  // kernel of the step before (the workgroup of the last update it receives)
+  // step 0's diagonal tile; every later one is factorized by the step before
+  // (the workgroup of the last update it receives)
   launch_potrf(c, 0, nbase, d_nbb.get(), d_blk0.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get(), d_err.get());
   for (int k = 0; k < max_nbb; ++k) {
-    launch_trsm(c, k, band, nbase, max_nbb, d_nbb.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get());
-    hipEvent_t ev = c.order_event((size_t)k);
-    if (k > 0) LIF_HIP(hipEventRecord(ev, main_stream));
-    // the next step's inputs first, then the side stream's inverse column
-    launch_update(c, k, band, nbase, max_nbb, d_nbb.get(), d_blk0.get(), d_tile0.get(), b, U.get(), zs->get(),
-                  nz.get(), d_err.get());
+    launch_step(c, k, band, nbase, max_nbb, d_nbb.get(), d_blk0.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get(),
+                d_err.get());
     if (k > 0) {
+      hipEvent_t ev = c.order_event((size_t)k);
+      LIF_HIP(hipEventRecord(ev, main_stream));
       LIF_HIP(hipStreamWaitEvent(side, ev, 0));
       StreamScope on_side(c, side);
       launch_trinv(c, k, band, nbase, d_nbb.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get());
