@@ -59,8 +59,12 @@ struct Batch {
   int nb = 0;
 };
 
+// `carry` (nullable): product capacities handed from one batch to the next
+// of the same factorization; the first iteration is then sized in advance
+// too (and redone with exact sizes if a capacity was short).
 void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, const Opts& o,
-                  std::vector<NodeState>& st, int max_iter, std::vector<Bsr>* ck = nullptr) {
+                  std::vector<NodeState>& st, int max_iter, std::vector<Bsr>* ck = nullptr,
+                  std::vector<std::array<int64_t, 2>>* carry = nullptr) {
   const int nn = (int)bt.rlo.size();
   const int nb = bt.nb;
   const std::vector<double> bk = coefficients(o.m);
@@ -80,6 +84,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
   bool labels_dirty = true;
   bool all_active = true;
   std::vector<std::array<int64_t, 2>> caps;  // per product of an iteration: {blocks, pairs}
+  if (carry) caps = *carry;
   if (!c.spec.sizes.get()) {
     c.spec.sizes = DBuf<int64_t>(c.pool, 2 * Ctx::Spec::kSlots);
     c.spec.overflow = DBuf<int>(c.pool, 1);
@@ -225,6 +230,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
     // into one array (counts are known here: no extra read-back)
     if (Znew.store_blocks() > 3 * Znew.nnzb + 64) Znew = compact_values(c, std::move(Znew));
     if (dnew.store_blocks() > 3 * dnew.nnzb + 64) dnew = compact_values(c, std::move(dnew));
+    if (carry) *carry = caps;
     if (ck) ck->push_back(std::move(Z));  // Z_k is immutable: keep it, no copy
     Z = std::move(Znew);
     delta = std::move(dnew);
@@ -484,6 +490,9 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck)
   }
   info.levels = 0;
   info.iterations_total = 0;
+  // every level's refinement runs the same sequence of products; each
+  // level starts from the capacities the level below ended with
+  std::vector<std::array<int64_t, 2>> carry;
   for (int d = plan.max_depth - 1; d >= 0; --d) {
     std::vector<int> ids;
     for (int i = 0; i < (int)plan.nodes.size(); ++i)
@@ -543,7 +552,8 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck)
         ++next;
       }
     }
-    refine_batch(c, S_lvl, Z, std::move(delta0), bt, o, st, o.max_iter, L ? &L->Z : nullptr);
+    refine_batch(c, S_lvl, Z, std::move(delta0), bt, o, st, o.max_iter, L ? &L->Z : nullptr,
+                 o.presize != 0 ? &carry : nullptr);
     if (L) {
       for (auto& ns : st) L->iters.push_back(ns.iterations);
       L->S_lvl = std::move(S_lvl);
