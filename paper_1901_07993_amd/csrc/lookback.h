@@ -75,22 +75,26 @@ __device__ inline bool lb_sum_window(unsigned long long* wa, unsigned long long*
   }
 }
 
-// Called by all lanes of one wave for row i of nb.  Publishes the row's
-// values (a, b) in rows_a/rows_b, the group sums in grp_a/grp_b when row i
-// closes its group, and returns the exclusive prefixes of a and b over rows
-// < i.  False if a lower row did not publish within the spin budget (the
-// group sum is then published anyway, as zero, so that no other row waits
-// on this one).
-__device__ inline bool lb_exclusive2(unsigned long long* rows_a, unsigned long long* rows_b,
-                                     unsigned long long* grp_a, unsigned long long* grp_b, int i, int nb,
-                                     unsigned epoch, unsigned long long a, unsigned long long b,
-                                     unsigned long long* ea, unsigned long long* eb) {
+// Row i's own values (a, b), published by one lane.
+__device__ inline void lb_publish(unsigned long long* rows_a, unsigned long long* rows_b, int i, unsigned epoch,
+                                  unsigned long long a, unsigned long long b) {
+  lb_store(rows_a + i, lb_word(epoch, a));
+  lb_store(rows_b + i, lb_word(epoch, b));
+}
+
+// Called by all lanes of one wave for row i of nb, after row i published
+// its values (a, b) with lb_publish -- as early as possible, so that the
+// rows above find them when they get here.  Publishes the group sums when
+// row i closes its group and returns the exclusive prefixes of a and b over
+// rows < i.  False if a lower row did not publish within the spin budget
+// (the group sum is then published anyway, as zero, so that no other row
+// waits on this one).
+__device__ inline bool lb_resolve2(unsigned long long* rows_a, unsigned long long* rows_b,
+                                   unsigned long long* grp_a, unsigned long long* grp_b, int i, int nb,
+                                   unsigned epoch, unsigned long long a, unsigned long long b,
+                                   unsigned long long* ea, unsigned long long* eb) {
   const int lane = threadIdx.x & 63;
   const int g = i >> 6, g0 = g << 6;
-  if (lane == 0) {
-    lb_store(rows_a + i, lb_word(epoch, a));
-    lb_store(rows_b + i, lb_word(epoch, b));
-  }
   int spins = 0;
   bool ok = true;
   if (i == min(nb, g0 + 64) - 1) {  // the group's last row publishes its sum
@@ -108,6 +112,15 @@ __device__ inline bool lb_exclusive2(unsigned long long* rows_a, unsigned long l
   *ea = sa;
   *eb = sb;
   return ok;
+}
+
+// Both steps at once (when there is nothing to do between them).
+__device__ inline bool lb_exclusive2(unsigned long long* rows_a, unsigned long long* rows_b,
+                                     unsigned long long* grp_a, unsigned long long* grp_b, int i, int nb,
+                                     unsigned epoch, unsigned long long a, unsigned long long b,
+                                     unsigned long long* ea, unsigned long long* eb) {
+  if ((threadIdx.x & 63) == 0) lb_publish(rows_a, rows_b, i, epoch, a, b);
+  return lb_resolve2(rows_a, rows_b, grp_a, grp_b, i, nb, epoch, a, b, ea, eb);
 }
 
 }  // namespace lif

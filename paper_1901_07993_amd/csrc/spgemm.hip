@@ -285,16 +285,99 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill_masked(
     run += __popc(bm[w]);
   }
 
+  int64_t prow_count = 0;
+  if (ONEPASS) {
+    block_exclusive_scan<int64_t, kSymWG>(pcount, scan_tmp64, &prow_count);
+    // published now, so that the rows above find it while this row works
+    if (threadIdx.x == 0)
+      lb_publish(op.lb.ra, op.lb.rb, i, op.lb.epoch, (unsigned long long)ncols, (unsigned long long)prow_count);
+  }
+  __syncthreads();
+
+  // local work first (needs no offset): clear the per-output counters and
+  // masks, count the products of each output block, scan them
+  for (int w = threadIdx.x; w < nwords; w += kSymWG) {
+    unsigned bits = bm[w];
+    int r = wp[w];
+    while (bits) {
+      cur[r] = 0;
+      mask[r] = 0ull;
+      ++r;
+      bits &= bits - 1;
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int alo = arp[i], ahi = arp[i + 1];
+  auto rank = [&](int j) { return wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u)); };
+  // marks the contributions of A entries [e0, e0 + 64) in the masks
+  auto mark = [&](int e0) {
+    const int e1 = min(ahi, e0 + 64);
+    for (int e = e0 + wave; e < e1; e += kSymWG / 64) {
+      if (h.a_absent(e)) continue;  // uniform over the wave
+      const int k = acol[e];
+      const unsigned long long bit = 1ull << (e - e0);
+      for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
+        if (h.b_absent(f)) continue;
+        atomicOr(&mask[rank(bcol[f])], bit);
+      }
+    }
+  };
+  // writes the pairs of A entries [e0, e0 + 64) after cur[r] in each block
+  auto place = [&](int e0, int64_t prow) {
+    const int e1 = min(ahi, e0 + 64);
+    for (int e = e0 + wave; e < e1; e += kSymWG / 64) {
+      const double* a = ablk[aidx ? aidx[e] : e];
+      if (a_holes && !a) continue;
+      const int k = acol[e];
+      const unsigned long long below = (1ull << (e - e0)) - 1ull;
+      for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
+        const double* bp = bblk[bidx ? bidx[f] : f];
+        if (b_holes && !bp) continue;
+        const int r = rank(bcol[f]);
+        pairs[prow + cur[r] + __popcll(mask[r] & below)] = BlockPair{a, bp};
+      }
+    }
+  };
+  const bool one_run = ahi - alo <= 64;
+  for (int e0 = alo; e0 < ahi; e0 += 64) {
+    mark(e0);
+    __syncthreads();
+    if (!one_run) {
+      for (int r = threadIdx.x; r < ncols; r += kSymWG) {
+        cur[r] += __popcll(mask[r]);
+        mask[r] = 0ull;
+      }
+      __syncthreads();
+    }
+  }
+  if (one_run)
+    for (int r = threadIdx.x; r < ncols; r += kSymWG) cur[r] = __popcll(mask[r]);
+  __syncthreads();
+  // exclusive scan of the per-output counts: segment starts within the row
+  const int c0 = min(ncols, (int)threadIdx.x * ((ncols + kSymWG - 1) / kSymWG));
+  const int c1 = min(ncols, c0 + (ncols + kSymWG - 1) / kSymWG);
+  {
+    int t = 0;
+    for (int r = c0; r < c1; ++r) t += cur[r];
+    int tot;
+    int acc = block_exclusive_scan<int, kSymWG>(t, scan_tmp, &tot);
+    for (int r = c0; r < c1; ++r) {
+      const int cnt = cur[r];
+      cur[r] = acc;
+      acc += cnt;
+    }
+  }
+
+  // the row's offsets in the output and pair arrays
   int cbase;
   int64_t prow;
   bool fits = true;
   if (ONEPASS) {
-    int64_t prow_count;
-    block_exclusive_scan<int64_t, kSymWG>(pcount, scan_tmp64, &prow_count);
     if (threadIdx.x < 64) {
       unsigned long long ec = 0, ep = 0;
-      const bool ok = lb_exclusive2(op.lb.ra, op.lb.rb, op.lb.ga, op.lb.gb, i, nb, op.lb.epoch,
-                                    (unsigned long long)ncols, (unsigned long long)prow_count, &ec, &ep);
+      const bool ok = lb_resolve2(op.lb.ra, op.lb.rb, op.lb.ga, op.lb.gb, i, nb, op.lb.epoch,
+                                  (unsigned long long)ncols, (unsigned long long)prow_count, &ec, &ep);
       if (threadIdx.x == 0) {
         off_sh[0] = (int64_t)ec;
         off_sh[1] = (int64_t)ep;
@@ -324,112 +407,43 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill_masked(
     prow = prp[i];
     if (i == nb - 1 && threadIdx.x == 0) seg[crp[nb]] = prp[nb];  // closing segment pointer
   }
+  if (!fits) return;  // uniform over the workgroup
+
+  // output columns in ascending order, segment starts
+  for (int w = threadIdx.x; w < nwords; w += kSymWG) {
+    unsigned bits = bm[w];
+    int r = wp[w];
+    while (bits) {
+      const int j = (w << 5) + __ffs(bits) - 1;
+      ccol[cbase + r] = j;
+      if (dsrc) dsrc[cbase + r] = nullptr;
+      ++r;
+      bits &= bits - 1;
+    }
+  }
+  for (int r = c0; r < c1; ++r) seg[cbase + r] = prow + cur[r];
   __syncthreads();
+  if (dsrc)  // D's blocks at their output positions
+    for (int e = drp[i] + threadIdx.x; e < drp[i + 1]; e += kSymWG) {
+      const int j = dcol[e];
+      dsrc[cbase + rank(j)] = dblk[e];
+    }
 
-  if (fits) {
-    // output columns in ascending order; clear the per-output counters and masks
-    for (int w = threadIdx.x; w < nwords; w += kSymWG) {
-      unsigned bits = bm[w];
-      int r = wp[w];
-      while (bits) {
-        const int j = (w << 5) + __ffs(bits) - 1;
-        ccol[cbase + r] = j;
-        if (dsrc) dsrc[cbase + r] = nullptr;
-        cur[r] = 0;
-        mask[r] = 0ull;
-        ++r;
-        bits &= bits - 1;
-      }
+  // pairs: one run reuses its masks; longer rows mark each run again
+  if (one_run) {
+    place(alo, prow);
+    return;
+  }
+  for (int e0 = alo; e0 < ahi; e0 += 64) {
+    mark(e0);
+    __syncthreads();
+    place(e0, prow);
+    __syncthreads();
+    for (int r = threadIdx.x; r < ncols; r += kSymWG) {
+      cur[r] += __popcll(mask[r]);
+      mask[r] = 0ull;
     }
     __syncthreads();
-    if (dsrc)
-      for (int e = drp[i] + threadIdx.x; e < drp[i + 1]; e += kSymWG) {
-        const int j = dcol[e];
-        dsrc[cbase + wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u))] = dblk[e];
-      }
-
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int alo = arp[i], ahi = arp[i + 1];
-    auto rank = [&](int j) { return wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u)); };
-    // marks the contributions of A entries [e0, e0 + 64) in the masks
-    auto mark = [&](int e0) {
-      const int e1 = min(ahi, e0 + 64);
-      for (int e = e0 + wave; e < e1; e += kSymWG / 64) {
-        if (h.a_absent(e)) continue;  // uniform over the wave
-        const int k = acol[e];
-        const unsigned long long bit = 1ull << (e - e0);
-        for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
-          if (h.b_absent(f)) continue;
-          atomicOr(&mask[rank(bcol[f])], bit);
-        }
-      }
-    };
-    // writes the pairs of A entries [e0, e0 + 64) after cur[r] in each block
-    auto place = [&](int e0) {
-      const int e1 = min(ahi, e0 + 64);
-      for (int e = e0 + wave; e < e1; e += kSymWG / 64) {
-        const double* a = ablk[aidx ? aidx[e] : e];
-        if (a_holes && !a) continue;
-        const int k = acol[e];
-        const unsigned long long below = (1ull << (e - e0)) - 1ull;
-        for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
-          const double* bp = bblk[bidx ? bidx[f] : f];
-          if (b_holes && !bp) continue;
-          const int r = rank(bcol[f]);
-          pairs[prow + cur[r] + __popcll(mask[r] & below)] = BlockPair{a, bp};
-        }
-      }
-    };
-    const bool one_run = ahi - alo <= 64;
-
-    // products per output block
-    for (int e0 = alo; e0 < ahi; e0 += 64) {
-      mark(e0);
-      __syncthreads();
-      if (!one_run) {
-        for (int r = threadIdx.x; r < ncols; r += kSymWG) {
-          cur[r] += __popcll(mask[r]);
-          mask[r] = 0ull;
-        }
-        __syncthreads();
-      }
-    }
-    if (one_run)
-      for (int r = threadIdx.x; r < ncols; r += kSymWG) cur[r] = __popcll(mask[r]);
-    __syncthreads();
-
-    // exclusive scan of the per-output counts -> segment starts
-    const int c0 = min(ncols, (int)threadIdx.x * ((ncols + kSymWG - 1) / kSymWG));
-    const int c1 = min(ncols, c0 + (ncols + kSymWG - 1) / kSymWG);
-    int t = 0;
-    for (int r = c0; r < c1; ++r) t += cur[r];
-    __syncthreads();  // scan_tmp is reused
-    int tot;
-    int acc = block_exclusive_scan<int, kSymWG>(t, scan_tmp, &tot);
-    for (int r = c0; r < c1; ++r) {
-      const int cnt = cur[r];
-      seg[cbase + r] = prow + acc;
-      cur[r] = acc;
-      acc += cnt;
-    }
-    __syncthreads();
-
-    // pairs: one run reuses its masks; longer rows mark each run again
-    if (one_run) {
-      place(alo);
-    } else {
-      for (int e0 = alo; e0 < ahi; e0 += 64) {
-        mark(e0);
-        __syncthreads();
-        place(e0);
-        __syncthreads();
-        for (int r = threadIdx.x; r < ncols; r += kSymWG) {
-          cur[r] += __popcll(mask[r]);
-          mask[r] = 0ull;
-        }
-        __syncthreads();
-      }
-    }
   }
 }
 
