@@ -234,6 +234,34 @@ inline size_t union_rows_lds(int nb, bool fill) {
   return fill ? (4 * nwords + 3 * (size_t)nb) * 4 : 3 * nwords * 4;
 }
 
+// One-pass unions also sort the output blocks into those taken unchanged
+// from one operand (a unit coefficient, no identity term: the union writes
+// the operand's block pointer to out) and those that need new values,
+// listed in list[0..*ncomp) for the values pass; the list is in row order
+// (each row's part placed by the same look-back as its output positions).
+struct UnionList {
+  BlkIn val[3];
+  bool unit[3];
+  BlkOut out;
+  int* list;
+  int* ncomp;
+};
+
+// Whether output column j (bit `bit` of word w) of the row needs new
+// values; *tsrc is the operand holding it when it has a single one.
+__device__ inline bool union_needs_value(const Src3& S, const UnionList& L, const unsigned* bm, int nwords, int w,
+                                         int bit, bool dgj, int* tsrc) {
+  int present = 0, t1 = 0;
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+    if (S.rp[t] && ((bm[t * nwords + w] >> bit) & 1u)) {
+      ++present;
+      t1 = t;
+    }
+  *tsrc = t1;
+  return dgj || present != 1 || !L.unit[t1];
+}
+
 // MODE 0: counts[i]; 1: fill at the row pointers rc; 2: one pass -- the
 // row pointers are the prefix sums of the counts over the lower rows,
 // obtained by look-back (lookback.h) and written to rc by each row.  Modes 0
@@ -244,10 +272,10 @@ __global__ __launch_bounds__(kUR) void k_union_rows(Src3 S, const unsigned char*
                                                     int* __restrict__ rc, int* __restrict__ cc,
                                                     int* __restrict__ ix, int64_t stride,
                                                     unsigned char* __restrict__ id, int* __restrict__ rowof,
-                                                    Ctx::LbWords lbw) {
+                                                    Ctx::LbWords lbw, UnionList L) {
   constexpr bool FILL = MODE != 0;
   extern __shared__ unsigned smem[];
-  __shared__ int scan_tmp[1];
+  __shared__ int scan_tmp[1], scan_tmp2[1];
   const int i = blockIdx.x;
   const int nwords = (nb + 31) >> 5;
   unsigned* bm = smem;                              // [3][nwords]
@@ -285,20 +313,37 @@ __global__ __launch_bounds__(kUR) void k_union_rows(Src3 S, const unsigned char*
   }
   int total;
   int r = block_exclusive_scan<int, kUR>(s, scan_tmp, &total);
+  int q = 0;  // position in the list of blocks that need values (MODE 2)
   if (MODE == 2) {  // one wave: the whole workgroup takes part in the look-back
+    int nc = 0;
+    for (int w = w0; w < w1; ++w) {
+      unsigned bits = word(w);
+      while (bits) {
+        const int bit = __ffs(bits) - 1;
+        int tsrc;
+        nc += union_needs_value(S, L, bm, nwords, w, bit, dg && (w << 5) + bit == i, &tsrc) ? 1 : 0;
+        bits &= bits - 1;
+      }
+    }
+    int nctot;
+    q = block_exclusive_scan<int, kUR>(nc, scan_tmp2, &nctot);
     unsigned long long ea = 0, eb = 0;
-    const bool ok =
-        lb_exclusive2(lbw.ra, lbw.rb, lbw.ga, lbw.gb, i, nb, lbw.epoch, (unsigned long long)total, 0ull, &ea, &eb);
+    const bool ok = lb_exclusive2(lbw.ra, lbw.rb, lbw.ga, lbw.gb, i, nb, lbw.epoch, (unsigned long long)total,
+                                  (unsigned long long)nctot, &ea, &eb);
     // a union's size is bounded by its operands', so no capacity can be
     // short; a look-back that gave up leaves the prefix at 0 (in bounds,
     // wrong) and raises the flag the host checks
     if (!ok && threadIdx.x == 0) atomicExch(lbw.fail, 1);
-    const int base = ok ? (int)ea : 0;
+    const int base = ok ? (int)ea : 0, qbase = ok ? (int)eb : 0;
     if (threadIdx.x == 0) {
       rc[i] = base;
-      if (i == nb - 1) rc[nb] = base + total;
+      if (i == nb - 1) {
+        rc[nb] = base + total;
+        *L.ncomp = qbase + nctot;
+      }
     }
     r += base;
+    q += qbase;
   } else {
     r += rc[i];
   }
@@ -313,6 +358,13 @@ __global__ __launch_bounds__(kUR) void k_union_rows(Src3 S, const unsigned char*
 #pragma unroll
       for (int t = 0; t < 3; ++t)
         ix[t * stride + r] = (S.rp[t] && ((bm[t * nwords + w] >> bit) & 1u)) ? c2i[t * nb + j] : -1;
+      if (MODE == 2) {
+        int tsrc;
+        if (union_needs_value(S, L, bm, nwords, w, bit, dg && j == i, &tsrc))
+          L.list[q++] = r;
+        else
+          L.out[r] = L.val[tsrc][c2i[tsrc * nb + j]];
+      }
       ++r;
       bits &= bits - 1;
     }
@@ -330,15 +382,18 @@ struct Val3 {
 // Every other block is computed into the next free slot of `store` (slots
 // are handed out by an atomic counter; where a block lands does not change
 // its value).
-template <int B>
+// LIST: one workgroup per entry w of list (the blocks that need values),
+// *live entries, output block e = list[w], store slot w.
+template <int B, bool LIST>
 __global__ __launch_bounds__(kWG) void k_axpby_values(Val3 V, const int* __restrict__ ix, int64_t stride,
                                                       double gamma, const unsigned char* __restrict__ id,
                                                       const int* __restrict__ row_of, int64_t n,
                                                       double* __restrict__ store, int* __restrict__ slot,
-                                                      BlkOut out, const int* __restrict__ live) {
+                                                      BlkOut out, const int* __restrict__ live,
+                                                      const int* __restrict__ list) {
   __shared__ int my_slot;
-  const int64_t e = blockIdx.x;
-  if (live && e >= *live) return;
+  if (live && (int64_t)blockIdx.x >= *live) return;
+  const int64_t e = LIST ? list[blockIdx.x] : blockIdx.x;
   const double* src[3];
   double cf[3];
   int ns = 0;
@@ -352,11 +407,15 @@ __global__ __launch_bounds__(kWG) void k_axpby_values(Val3 V, const int* __restr
     }
   }
   const bool dg = id[e] != 0;
-  if (ns == 1 && cf[0] == 1.0 && !dg) {
+  if (!LIST && ns == 1 && cf[0] == 1.0 && !dg) {
     if (threadIdx.x == 0) out[e] = src[0];
     return;
   }
-  if (threadIdx.x == 0) my_slot = atomicAdd(slot, 1);
+  if (LIST) {
+    if (threadIdx.x == 0) my_slot = (int)blockIdx.x;
+  } else if (threadIdx.x == 0) {
+    my_slot = atomicAdd(slot, 1);
+  }
   // all operand loads in flight before the first use; the sum keeps the
   // operand order: ((0 + c0 v0) + c1 v1) + c2 v2
   v2d r[3][Blk<B>::V2];
@@ -435,6 +494,35 @@ __global__ void k_transpose_counts(const int* __restrict__ col, int64_t nnzb, in
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t lim = live ? min(nnzb, (int64_t)*live) : nnzb;
   if (e < lim) atomicAdd(&counts[col[e]], 1);
+}
+
+// The column counts of a pattern, their exclusive prefix sums (the row
+// pointers of the transposed pattern) and a cleared cursor per column for
+// the fill, in one workgroup: the counts are LDS atomics, the scan runs over
+// contiguous runs of columns per thread.  LDS: nb counters.
+constexpr int kTC = 1024;
+__global__ __launch_bounds__(kTC) void k_transpose_count_scan(const int* __restrict__ col, int64_t nnzb,
+                                                              const int* __restrict__ live, int nb,
+                                                              int* __restrict__ tptr, int* __restrict__ cursor) {
+  extern __shared__ int cnt[];
+  __shared__ int sh[kTC / 64];
+  for (int j = threadIdx.x; j < nb; j += kTC) cnt[j] = 0;
+  __syncthreads();
+  const int64_t lim = live ? min(nnzb, (int64_t)*live) : nnzb;
+  for (int64_t e = threadIdx.x; e < lim; e += kTC) atomicAdd(&cnt[col[e]], 1);
+  __syncthreads();
+  const int chunk = (nb + kTC - 1) / kTC;
+  const int lo = min(nb, (int)threadIdx.x * chunk), hi = min(nb, lo + chunk);
+  int s = 0;
+  for (int j = lo; j < hi; ++j) s += cnt[j];
+  int total;
+  int run = block_exclusive_scan<int, kTC>(s, sh, &total);
+  for (int j = lo; j < hi; ++j) {
+    tptr[j] = run;
+    run += cnt[j];
+    cursor[j] = 0;
+  }
+  if (threadIdx.x == 0) tptr[nb] = total;
 }
 
 __global__ void k_transpose_fill(const int* __restrict__ rp, const int* __restrict__ col, const int* __restrict__ tptr,
@@ -733,7 +821,7 @@ void launch_union3(Ctx& c, const int* const rp[3], const int* const col[3], cons
   }
   if (union_rows_lds(nb, true) <= kUnionRowsLds) {
     LIF_LAUNCH(k_union_rows<0>, dim3(nb), dim3(kUR), union_rows_lds(nb, false), c.stream, S, diag_on, nb, counts,
-               slot, nullptr, nullptr, nullptr, 0, nullptr, nullptr, Ctx::LbWords{});
+               slot, nullptr, nullptr, nullptr, 0, nullptr, nullptr, Ctx::LbWords{}, UnionList{});
     return;
   }
   LIF_LAUNCH(k_union_counts, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, S, diag_on, nb, counts, slot);
@@ -750,7 +838,7 @@ void launch_union3_fill(Ctx& c, const int* const rp[3], const int* const col[3],
   }
   if (union_rows_lds(nb, true) <= kUnionRowsLds) {
     LIF_LAUNCH(k_union_rows<1>, dim3(nb), dim3(kUR), union_rows_lds(nb, true), c.stream, S, diag_on, nb, nullptr,
-               nullptr, const_cast<int*>(rc), cc, ix, stride, id, rowof, Ctx::LbWords{});
+               nullptr, const_cast<int*>(rc), cc, ix, stride, id, rowof, Ctx::LbWords{}, UnionList{});
     return;
   }
   LIF_LAUNCH(k_union_fill, dim3(grid1(nb, 128)), dim3(128), 0, c.stream, S, diag_on, rc, nb, cc, ix, stride, id,
@@ -760,17 +848,24 @@ void launch_union3_fill(Ctx& c, const int* const rp[3], const int* const col[3],
 bool union_onepass_fits(int nb) { return union_rows_lds(nb, true) <= kUnionRowsLds; }
 
 void launch_union3_onepass(Ctx& c, const int* const rp[3], const int* const col[3], const BlkIn hole[3],
-                           const unsigned char* diag_on, int* rc, int nb, int* cc, int* ix, int64_t stride,
-                           unsigned char* id, int* rowof, int* slot) {
+                           const BlkIn val[3], const double coef[3], const unsigned char* diag_on, int* rc, int nb,
+                           int* cc, int* ix, int64_t stride, unsigned char* id, int* rowof, BlkOut out, int* list,
+                           int* ncomp) {
   Src3 S;
+  UnionList L;
   for (int t = 0; t < 3; ++t) {
     S.rp[t] = rp[t];
     S.col[t] = col[t];
     S.hole[t] = hole[t];
+    L.val[t] = val[t];
+    L.unit[t] = coef[t] == 1.0;
   }
+  L.out = out;
+  L.list = list;
+  L.ncomp = ncomp;
   const Ctx::LbWords w = c.lookback_words(nb);
-  LIF_LAUNCH(k_union_rows<2>, dim3(nb), dim3(kUR), union_rows_lds(nb, true), c.stream, S, diag_on, nb, nullptr, slot,
-             rc, cc, ix, stride, id, rowof, w);
+  LIF_LAUNCH(k_union_rows<2>, dim3(nb), dim3(kUR), union_rows_lds(nb, true), c.stream, S, diag_on, nb, nullptr,
+             nullptr, rc, cc, ix, stride, id, rowof, w, L);
 }
 
 void launch_keep_count_scan(Ctx& c, const int* row_ptr, const double* norms, double tau, int nb, int* out_rp) {
@@ -799,19 +894,28 @@ void launch_compact_gather(Ctx& c, const int* row_ptr, int nb, const int* col, c
 
 void launch_axpby3_values(Ctx& c, const BlkIn v[3], const double coef[3], const int* ix, int64_t stride,
                           double gamma, const unsigned char* id, const int* row_of, int64_t nnzb, int b, int64_t n,
-                          double* store, int* slot, BlkOut out, const int* live) {
+                          double* store, int* slot, BlkOut out, const int* live, const int* list) {
   if (nnzb == 0) return;
   Val3 V;
   for (int t = 0; t < 3; ++t) {
     V.v[t] = v[t];
     V.coef[t] = coef[t];
   }
+  if (list) {
+    if (b == 64)
+      LIF_LAUNCH((k_axpby_values<64, true>), dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, V, ix, stride, gamma, id,
+                 row_of, n, store, slot, out, live, list);
+    else
+      LIF_LAUNCH((k_axpby_values<32, true>), dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, V, ix, stride, gamma, id,
+                 row_of, n, store, slot, out, live, list);
+    return;
+  }
   if (b == 64)
-    LIF_LAUNCH(k_axpby_values<64>, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, V, ix, stride, gamma, id, row_of,
-               n, store, slot, out, live);
+    LIF_LAUNCH((k_axpby_values<64, false>), dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, V, ix, stride, gamma, id,
+               row_of, n, store, slot, out, live, nullptr);
   else
-    LIF_LAUNCH(k_axpby_values<32>, dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, V, ix, stride, gamma, id, row_of,
-               n, store, slot, out, live);
+    LIF_LAUNCH((k_axpby_values<32, false>), dim3((unsigned)nnzb), dim3(kWG), 0, c.stream, V, ix, stride, gamma, id,
+               row_of, n, store, slot, out, live, nullptr);
 }
 
 void launch_block_row_of(Ctx& c, const int* row_ptr, int nb, int64_t nnzb, int* row_of) {
@@ -828,6 +932,14 @@ void launch_filter_fill(Ctx& c, const int* row_ptr, const int* col, const int* r
 void launch_transpose_counts(Ctx& c, const int* col, int64_t nnzb, int* counts, const int* live) {
   if (nnzb == 0) return;
   LIF_LAUNCH(k_transpose_counts, dim3(grid1(nnzb, 256)), dim3(256), 0, c.stream, col, nnzb, counts, live);
+}
+
+bool transpose_count_scan_fits(int nb) { return (size_t)nb * sizeof(int) <= 48 * 1024; }
+
+void launch_transpose_count_scan(Ctx& c, const int* col, int64_t nnzb, const int* live, int nb, int* tptr,
+                                 int* cursor) {
+  LIF_LAUNCH(k_transpose_count_scan, dim3(1), dim3(kTC), (size_t)nb * sizeof(int), c.stream, col, nnzb, live, nb, tptr,
+             cursor);
 }
 
 void launch_transpose_fill(Ctx& c, const int* row_ptr, const int* col, const int* tptr, int nb, int* cursor,

@@ -333,12 +333,15 @@ void launch_union3_fill(Ctx& c, const int* const rp[3], const int* const col[3],
                         const unsigned char* diag_on, const int* rc, int nb, int* cc, int* ix, int64_t stride,
                         unsigned char* id, int* rowof);
 // counts, row pointers (written to rc[0..nb]) and fill in one launch, with
-// the row counts' prefix sums by look-back; also zeroes *slot.  Only for nb
-// with union_onepass_fits(nb).
+// the row counts' prefix sums by look-back.  Output blocks taken unchanged
+// from one operand (coefficient 1, no identity term) get that operand's
+// pointer in out; the others are listed, in row order, in list[0..*ncomp)
+// for the values pass.  Only for nb with union_onepass_fits(nb).
 bool union_onepass_fits(int nb);
 void launch_union3_onepass(Ctx& c, const int* const rp[3], const int* const col[3], const BlkIn hole[3],
-                           const unsigned char* diag_on, int* rc, int nb, int* cc, int* ix, int64_t stride,
-                           unsigned char* id, int* rowof, int* slot);
+                           const BlkIn val[3], const double coef[3], const unsigned char* diag_on, int* rc, int nb,
+                           int* cc, int* ix, int64_t stride, unsigned char* id, int* rowof, BlkOut out, int* list,
+                           int* ncomp);
 void launch_keep_count_scan(Ctx& c, const int* row_ptr, const double* norms, double tau, int nb, int* out_rp);
 void launch_filter_count_scan(Ctx& c, const int* row_ptr, const int* col, const int* rlab, const int* clab, int mode,
                               int nb, int* out_rp);
@@ -348,14 +351,22 @@ void launch_compact_gather(Ctx& c, const int* row_ptr, int nb, const int* col, c
                            const int* new_row_ptr, BlkIn blk, int64_t nnzb, int* new_col, BlkOut new_blk);
 // out block e = sum_t coef[t] v[t][ix[t][e]] (+ gamma I on the real rows of
 // flagged diagonal blocks); computed blocks take slots of `store` from the
-// counter *slot, blocks taken unscaled from one operand are shared
+// counter *slot, blocks taken unscaled from one operand are shared.  With
+// `list` (nullable): only the blocks e = list[w], w < *live, each computed
+// into slot w (nnzb is then the list's capacity).
 void launch_axpby3_values(Ctx& c, const BlkIn v[3], const double coef[3], const int* ix, int64_t stride,
                           double gamma, const unsigned char* id, const int* row_of, int64_t nnzb, int b, int64_t n,
-                          double* store, int* slot, BlkOut out, const int* live);
+                          double* store, int* slot, BlkOut out, const int* live, const int* list);
 void launch_block_row_of(Ctx& c, const int* row_ptr, int nb, int64_t nnzb, int* row_of);
 void launch_filter_fill(Ctx& c, const int* row_ptr, const int* col, const int* rlab, const int* clab,
                         int mode, const int* new_row_ptr, int nb, int* new_col, int* src);
 void launch_transpose_counts(Ctx& c, const int* col, int64_t nnzb, int* counts, const int* live);
+// tptr[0..nb]: exclusive prefix sums of the column counts of the first
+// *live (else nnzb) entries of col; cursor[0..nb) cleared.  One workgroup,
+// for nb with transpose_count_scan_fits(nb).
+bool transpose_count_scan_fits(int nb);
+void launch_transpose_count_scan(Ctx& c, const int* col, int64_t nnzb, const int* live, int nb, int* tptr,
+                                 int* cursor);
 void launch_transpose_fill(Ctx& c, const int* row_ptr, const int* col, const int* tptr, int nb,
                            int* cursor, int* tcol, int* tsrc);
 void launch_transpose_sort(Ctx& c, const int* tptr, int nb, const int* icol, const int* isrc, int* ocol,

@@ -158,11 +158,15 @@ CsrView transpose_view(Ctx& c, const Bsr& A) {
   const int nb = A.nb;
   const int64_t cap = A.bound();
   DBuf<int> cnt(c.pool, nb);
-  launch_fill_i32(c, cnt.get(), 0, nb);
-  launch_transpose_counts(c, A.col.get(), cap, cnt.get(), A.live());
   v.own_rp = DBuf<int>(c.pool, nb + 1);
-  scan_exclusive_i32(c, cnt.get(), v.own_rp.get(), nb);
-  launch_fill_i32(c, cnt.get(), 0, nb);
+  if (transpose_count_scan_fits(nb)) {  // counts, scan and cleared cursors in one launch
+    launch_transpose_count_scan(c, A.col.get(), cap, A.live(), nb, v.own_rp.get(), cnt.get());
+  } else {
+    launch_fill_i32(c, cnt.get(), 0, nb);
+    launch_transpose_counts(c, A.col.get(), cap, cnt.get(), A.live());
+    scan_exclusive_i32(c, cnt.get(), v.own_rp.get(), nb);
+    launch_fill_i32(c, cnt.get(), 0, nb);
+  }
   DBuf<int> tcol(c.pool, (size_t)cap), tsrc(c.pool, (size_t)cap);
   if (cap)
     launch_transpose_fill(c, A.row_ptr.get(), A.col.get(), v.own_rp.get(), nb, cnt.get(), tcol.get(), tsrc.get());
@@ -363,9 +367,16 @@ Bsr union_sum(Ctx& c, const Bsr* const src[3], const double coef[3], double gamm
   Store st = new_store(c, computed, C.b);
   C.blk = DBuf<const double*>(c.pool, (size_t)cap);
   C.store.push_back(st);
-  if (union_onepass_fits(nb)) {  // pattern in one launch
-    launch_union3_onepass(c, rp, col, hole, diag_on, C.row_ptr.get(), nb, C.col.get(), ix.get(), cap, id.get(),
-                          rowof.get(), slot.get());
+  if (union_onepass_fits(nb)) {
+    // pattern and the blocks taken unchanged in one launch, then values only
+    // for the blocks that need them
+    DBuf<int> list(c.pool, (size_t)std::max<int64_t>(computed, 1)), ncomp(c.pool, 1);
+    launch_union3_onepass(c, rp, col, hole, val, coef, diag_on, C.row_ptr.get(), nb, C.col.get(), ix.get(), cap,
+                          id.get(), rowof.get(), C.blk.get(), list.get(), ncomp.get());
+    if (computed)
+      launch_axpby3_values(c, val, coef, ix.get(), cap, gamma, id.get(), rowof.get(), computed, C.b, C.n, st->get(),
+                           nullptr, C.blk.get(), ncomp.get(), list.get());
+    return C;
   } else {
     {
       DBuf<int> cnt(c.pool, nb);
@@ -378,7 +389,7 @@ Bsr union_sum(Ctx& c, const Bsr* const src[3], const double coef[3], double gamm
   }
   if (cap)
     launch_axpby3_values(c, val, coef, ix.get(), cap, gamma, id.get(), rowof.get(), cap, C.b, C.n, st->get(),
-                         slot.get(), C.blk.get(), C.live());
+                         slot.get(), C.blk.get(), C.live(), nullptr);
   return C;
 }
 
