@@ -351,7 +351,7 @@ __device__ __attribute__((always_inline)) inline void acc_to_lds(double* s, cons
 // Within a step no task reads what another writes; the serial chain per
 // tile column is this one launch.
 template <int B>
-__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_step(int k, int band, int nupd,
+__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_step(int k, int band, int nupd, int ntask, int nbase,
                                                               const int* __restrict__ nbbv,
                                                               const int* __restrict__ blk0,
                                                               const int64_t* __restrict__ tile0,
@@ -364,11 +364,20 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_step(int k, int band, i
   __shared__ __attribute__((aligned(16))) double smem[SMEM];
   double* As = smem;
   double* Bs = smem + Cfg::LDS_DOUBLES;
-  const int s = blockIdx.y;
+  // 1-D grid: the first nbase workgroups are task 0 of every leaf -- the
+  // serial chain -- so that they are dispatched before anything else
+  int s, t;
+  if ((int)blockIdx.x < nbase) {
+    s = blockIdx.x;
+    t = 0;
+  } else {
+    const int w = (int)blockIdx.x - nbase;
+    s = w / (ntask - 1);
+    t = 1 + w % (ntask - 1);
+  }
   const int nbb = nbbv[s];
   if (k >= nbb) return;
   const int64_t t0 = tile0[s];
-  const int t = blockIdx.x;
   const Frag f = frag_coords<B>();
   const double* zkk = Z + packed_tile(t0, nbb, k, k) * B * B;
 
@@ -574,13 +583,14 @@ void launch_step(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb
   const int nupd = m * (m + 1) / 2;
   const int nv = std::min(band, k);
   if (nupd + nv <= 0) return;
-  dim3 grid(nupd + nv, nbase);
+  const int ntask = nupd + nv;
+  dim3 grid((unsigned)(ntask * nbase));
   if (b == 64)
-    LIF_LAUNCH(k_step<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, k, band, nupd, nbb, blk0, tile0, U, Z, nz,
-               err);
+    LIF_LAUNCH(k_step<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, k, band, nupd, ntask, nbase, nbb, blk0,
+               tile0, U, Z, nz, err);
   else
-    LIF_LAUNCH(k_step<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, k, band, nupd, nbb, blk0, tile0, U, Z, nz,
-               err);
+    LIF_LAUNCH(k_step<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, k, band, nupd, ntask, nbase, nbb, blk0,
+               tile0, U, Z, nz, err);
 }
 
 void launch_trinv(Ctx& c, int j, int band, int nbase, const int* nbb, const int64_t* tile0, int b, const double* U,
