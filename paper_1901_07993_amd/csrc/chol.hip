@@ -489,10 +489,15 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_step(int k, int band, i
   }
 }
 
-// Z_ij = -sum_{k=i}^{j-1} Z_ik V_kj for i = blockIdx.x < j, V_kj = U_kj Z_jj
-// (held in U's place); V_kj = 0 for k < j - band
+// Tile columns j0 .. j0 + ncol - 1 of the inverse, one workgroup per
+// (row i, leaf): Z_ij = -sum_{k=i}^{j-1} Z_ik V_kj for every column j > i of
+// the range, V_kj = U_kj Z_jj (held in U's place), V_kj = 0 for k < j -
+// band.  A row's columns are done in order by the same workgroup (column j+1
+// reads the Z_ij it just wrote), so the tiles Z_ik two neighbouring columns
+// share are read from HBM once and then found in L2.
 template <int B>
-__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, int band, const int* __restrict__ nbbv,
+__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j0, int ncol, int band,
+                                                               const int* __restrict__ nbbv,
                                                                const int64_t* __restrict__ tile0,
                                                                const double* __restrict__ V,
                                                                double* __restrict__ Z,
@@ -503,47 +508,51 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_trinv(int j, int band, 
   const int s = blockIdx.y;
   const int nbb = nbbv[s];
   const int i = blockIdx.x;
-  if (j >= nbb || i >= j) return;
   const Frag f = frag_coords<B>();
   const int64_t t0 = tile0[s];
-  v4d acc[2][2];
-  acc_zero(acc);
-  v2d ra[Cfg::V2], rb[Cfg::V2];
-  // k with V_kj != 0, visited in ascending order; the next pair's tiles are
-  // loaded into registers while the current one is multiplied
-  auto next_k = [&](int k) {
-    while (k < j && !nz[packed_tile(t0, nbb, k, j)]) ++k;
-    return k;
-  };
-  int k = next_k(max(i, j - band));
-  if (k >= j) {  // Z_ij = 0 (the buffer is not cleared beforehand)
-    v2d* g = reinterpret_cast<v2d*>(Z + packed_tile(t0, nbb, i, j) * B * B);
+  for (int j = max(j0, i + 1); j < j0 + ncol && j < nbb; ++j) {
+    __syncthreads();  // the previous column's LDS reads and Z writes are done
+    v4d acc[2][2];
+    acc_zero(acc);
+    v2d ra[Cfg::V2], rb[Cfg::V2];
+    // k with V_kj != 0, visited in ascending order; the next pair's tiles are
+    // loaded into registers while the current one is multiplied
+    auto next_k = [&](int k) {
+      while (k < j && !nz[packed_tile(t0, nbb, k, j)]) ++k;
+      return k;
+    };
+    int k = next_k(max(i, j - band));
+    if (k >= j) {  // Z_ij = 0 (the buffer is not cleared beforehand)
+      v2d* g = reinterpret_cast<v2d*>(Z + packed_tile(t0, nbb, i, j) * B * B);
 #pragma unroll
-    for (int v = 0; v < Cfg::V2; ++v) g[threadIdx.x + v * Cfg::THREADS] = v2d{0.0, 0.0};
-    return;
-  }
-  tile_load<B>(Z + packed_tile(t0, nbb, i, k) * B * B, ra);
-  tile_load<B>(V + packed_tile(t0, nbb, k, j) * B * B, rb);
-  while (k < j) {
-    __syncthreads();
-    tile_store<B>(As, ra, false);  // op(A) = Z_ik
-    tile_store<B>(Bs, rb, true);
-    __syncthreads();
-    const int kn = next_k(k + 1);
-    if (kn < j) {
-      tile_load<B>(Z + packed_tile(t0, nbb, i, kn) * B * B, ra);
-      tile_load<B>(V + packed_tile(t0, nbb, kn, j) * B * B, rb);
+      for (int v = 0; v < Cfg::V2; ++v) g[threadIdx.x + v * Cfg::THREADS] = v2d{0.0, 0.0};
+      continue;
     }
-    tile_mma<B>(As, Bs, f, acc);
-    k = kn;
+    tile_load<B>(Z + packed_tile(t0, nbb, i, k) * B * B, ra);
+    tile_load<B>(V + packed_tile(t0, nbb, k, j) * B * B, rb);
+    bool first = true;
+    while (k < j) {
+      if (!first) __syncthreads();
+      first = false;
+      tile_store<B>(As, ra, false);  // op(A) = Z_ik
+      tile_store<B>(Bs, rb, true);
+      __syncthreads();
+      const int kn = next_k(k + 1);
+      if (kn < j) {
+        tile_load<B>(Z + packed_tile(t0, nbb, i, kn) * B * B, ra);
+        tile_load<B>(V + packed_tile(t0, nbb, kn, j) * B * B, rb);
+      }
+      tile_mma<B>(As, Bs, f, acc);
+      k = kn;
+    }
+    double* g = Z + packed_tile(t0, nbb, i, j) * B * B;
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) g[acc_row(f, ti, r) * B + acc_col(f, tj)] = -acc[ti][tj][r];
   }
-  double* g = Z + packed_tile(t0, nbb, i, j) * B * B;
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) g[acc_row(f, ti, r) * B + acc_col(f, tj)] = -acc[ti][tj][r];
 }
 
 }  // namespace
@@ -593,14 +602,15 @@ void launch_step(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb
                tile0, U, Z, nz, err);
 }
 
-void launch_trinv(Ctx& c, int j, int band, int nbase, const int* nbb, const int64_t* tile0, int b, const double* U,
-                  double* Z, const unsigned char* nz) {
-  if (j <= 0) return;
-  dim3 grid(j, nbase);
+void launch_trinv(Ctx& c, int j0, int ncol, int band, int nbase, const int* nbb, const int64_t* tile0, int b,
+                  const double* U, double* Z, const unsigned char* nz) {
+  const int rows = j0 + ncol - 1;  // rows 0 .. j0 + ncol - 2 have a column of the range right of them
+  if (ncol <= 0 || rows <= 0) return;
+  dim3 grid(rows, nbase);
   if (b == 64)
-    LIF_LAUNCH(k_trinv<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, j, band, nbb, tile0, U, Z, nz);
+    LIF_LAUNCH(k_trinv<64>, grid, dim3(TileCfg<64>::THREADS), 0, c.stream, j0, ncol, band, nbb, tile0, U, Z, nz);
   else
-    LIF_LAUNCH(k_trinv<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, j, band, nbb, tile0, U, Z, nz);
+    LIF_LAUNCH(k_trinv<32>, grid, dim3(TileCfg<32>::THREADS), 0, c.stream, j0, ncol, band, nbb, tile0, U, Z, nz);
 }
 
 }  // namespace lif

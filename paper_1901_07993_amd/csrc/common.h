@@ -465,8 +465,10 @@ void launch_potrf(Ctx& c, int k, int nbase, const int* nbb, const int* blk0, con
 // diagonal factorization of step k + 1 and the V tiles of column k.
 void launch_step(Ctx& c, int k, int band, int nbase, int max_nbb, const int* nbb, const int* blk0,
                  const int64_t* tile0, int b, double* U, double* Z, unsigned char* nz, int* err);
-void launch_trinv(Ctx& c, int j, int band, int nbase, const int* nbb, const int64_t* tile0, int b, const double* U,
-                  double* Z, const unsigned char* nz);
+// tile columns j0 .. j0 + ncol - 1 of the inverse (those of step j0 + ncol -
+// 1 and the steps before it must be done)
+void launch_trinv(Ctx& c, int j0, int ncol, int band, int nbase, const int* nbb, const int64_t* tile0, int b,
+                  const double* U, double* Z, const unsigned char* nz);
 
 // ---------------------------------------------------------------------------
 // Block-sparse operations (ops.cpp): allocate outputs, run the kernels,

@@ -422,15 +422,21 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   // step 0's diagonal tile; every later one is factorized by the step before
   // (the workgroup of the last update it receives)
   launch_potrf(c, 0, nbase, d_nbb.get(), d_blk0.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get(), d_err.get());
+  // the inverse's columns go in pairs: a row's two tiles share most of
+  // their operands (read once from HBM, then from L2)
+  constexpr int kInvCols = 2;
+  int next_col = 1;  // the first column of the inverse not yet launched
   for (int k = 0; k < max_nbb; ++k) {
     launch_step(c, k, band, nbase, max_nbb, d_nbb.get(), d_blk0.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get(),
                 d_err.get());
-    if (k > 0) {
+    if (k >= next_col && (k - next_col + 1 == kInvCols || k == max_nbb - 1)) {
       hipEvent_t ev = c.order_event((size_t)k);
       LIF_HIP(hipEventRecord(ev, main_stream));
       LIF_HIP(hipStreamWaitEvent(side, ev, 0));
       StreamScope on_side(c, side);
-      launch_trinv(c, k, band, nbase, d_nbb.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get());
+      launch_trinv(c, next_col, k - next_col + 1, band, nbase, d_nbb.get(), d_tile0.get(), b, U.get(), zs->get(),
+                   nz.get());
+      next_col = k + 1;
     }
   }
   {
