@@ -62,9 +62,11 @@ struct Batch {
 // `carry` (nullable): product capacities handed from one batch to the next
 // of the same factorization; the first iteration is then sized in advance
 // too (and redone with exact sizes if a capacity was short).
+// `ss0` (nullable): the problems' ||delta_0||_F^2, when the caller already
+// read them back.
 void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, const Opts& o,
                   std::vector<NodeState>& st, int max_iter, std::vector<Bsr>* ck = nullptr,
-                  std::vector<std::array<int64_t, 2>>* carry = nullptr) {
+                  std::vector<std::array<int64_t, 2>>* carry = nullptr, const std::vector<double>* ss0 = nullptr) {
   const int nn = (int)bt.rlo.size();
   const int nb = bt.nb;
   const std::vector<double> bk = coefficients(o.m);
@@ -74,7 +76,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
   h2d(c, d_rhi.get(), bt.rhi.data(), nn);
 
   {  // problems whose delta_0 is exactly zero need no iteration
-    std::vector<double> ss = node_sumsq(c, delta, d_rlo.get(), d_rhi.get(), nn);
+    const std::vector<double> ss = ss0 ? *ss0 : node_sumsq(c, delta, d_rlo.get(), d_rhi.get(), nn);
     for (int s = 0; s < nn; ++s)
       if (ss[s] == 0.0) st[s].active = false;
   }
@@ -498,7 +500,7 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck)
   info.iterations_total = 0;
   // every level's refinement runs the same sequence of products; each
   // level starts from the capacities the level below ended with
-  std::vector<std::array<int64_t, 2>> carry;
+  std::vector<std::array<int64_t, 2>> carry, setup_caps;
   for (int d = plan.max_depth - 1; d >= 0; --d) {
     std::vector<int> ids;
     for (int i = 0; i < (int)plan.nodes.size(); ++i)
@@ -526,15 +528,65 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck)
     // the level's diagonal problems, and the couplings B of each split
     Bsr S_lvl = filter(c, S, d_lab.get(), d_lab.get(), 0);
     Bsr S_up = filter(c, S, d_side.get(), d_side.get(), 1);
-    // delta_0 = -[[0, X], [X^T, 0]], X = (Z_A^T B) Z_C
-    Bsr W = spgemm(c, Z, true, S_up, false, o.tau);
+    // delta_0 = -[[0, X], [X^T, 0]], X = (Z_A^T B) Z_C.  The two products
+    // are sized in advance from the level below (their counts and an
+    // overflow flag come back with delta_0's norms; a short capacity redoes
+    // them with exact sizes).
+    Bsr delta0;
+    std::vector<double> ss0;
+    {
+      DBuf<int> d_rlo(c.pool, nn), d_rhi(c.pool, nn);
+      h2d(c, d_rlo.get(), bt.rlo.data(), nn);
+      h2d(c, d_rhi.get(), bt.rhi.data(), nn);
+      if (!c.spec.sizes.get()) {
+        c.spec.sizes = DBuf<int64_t>(c.pool, 2 * Ctx::Spec::kSlots);
+        c.spec.overflow = DBuf<int>(c.pool, 1);
+      }
+      for (bool planned = o.presize != 0 && !setup_caps.empty();; planned = false) {
+        struct SpecOff {
+          Ctx& c;
+          ~SpecOff() { c.spec.on = c.spec.record = false; }
+        } spec_off{c};
+        c.spec.on = planned;
+        c.spec.record = !planned;
+        c.spec.next = 0;
+        c.spec.caps = setup_caps;
+        c.spec.seen.clear();
+        c.spec.prec.clear();
+        if (planned) launch_fill_i32(c, c.spec.overflow.get(), 0, 1);
+        Bsr W = spgemm(c, Z, true, S_up, false, o.tau);
+        Bsr X = spgemm(c, W, false, Z, false, o.tau);
+        W = Bsr();
+        Bsr Xt = transpose(c, X);
+        delta0 = axpby(c, -1.0, &X, -1.0, &Xt, 0.0, nullptr);
+        c.spec.on = c.spec.record = false;
+        int over = 0;
+        int64_t sz[4] = {0, 0, 0, 0};
+        std::vector<Ctx::Read> extra;
+        if (planned) {
+          extra.push_back({&over, c.spec.overflow.get(), sizeof(int)});
+          extra.push_back({sz, c.spec.sizes.get(), sizeof(sz)});
+        }
+        ss0 = node_sumsq(c, delta0, d_rlo.get(), d_rhi.get(), nn, extra);
+        if (planned && over) {
+          ++c.stats.redone;
+          continue;
+        }
+        std::vector<std::array<int64_t, 2>> seen = c.spec.seen;
+        if (planned) {
+          seen = {{sz[0], sz[1]}, {sz[2], sz[3]}};
+          for (const auto& v : seen) {  // statistics that exact sizing counts in spgemm
+            const double fl = 2.0 * (double)S.b * S.b * S.b * (double)v[1];
+            c.stats.products += v[1];
+            c.stats.flops += fl;
+          }
+        }
+        setup_caps.clear();
+        for (const auto& v : seen) setup_caps.push_back({v[0] + v[0] / 2 + 64, 4 * v[1] + 4096});
+        break;
+      }
+    }
     S_up = Bsr();
-    Bsr X = spgemm(c, W, false, Z, false, o.tau);
-    W = Bsr();
-    Bsr Xt = transpose(c, X);
-    Bsr delta0 = axpby(c, -1.0, &X, -1.0, &Xt, 0.0, nullptr);
-    X = Bsr();
-    Xt = Bsr();
     std::vector<NodeState> st;
     LevelCk* L = nullptr;
     if (ck) {
@@ -559,7 +611,7 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck)
       }
     }
     refine_batch(c, S_lvl, Z, std::move(delta0), bt, o, st, o.max_iter, L ? &L->Z : nullptr,
-                 o.presize != 0 ? &carry : nullptr);
+                 o.presize != 0 ? &carry : nullptr, &ss0);
     if (L) {
       for (auto& ns : st) L->iters.push_back(ns.iterations);
       L->S_lvl = std::move(S_lvl);
