@@ -142,6 +142,18 @@ lif_status lif_refine(lif_handle h, const lif_blocks* Z0, lif_info* info);
  * processed together.  A non-positive leaf pivot gives LIF_ERR_NOT_PD. */
 lif_status lif_localized(lif_handle h, lif_info* info);
 
+/* Recursive inverse Cholesky (Alg. 1) of the handle's S, as a standalone
+ * method: ranges of more than base_rows rows split at ceil(nb/2) blocks
+ * (as in lif_localized); with S = [[S00, S01], [S01^T, S11]],
+ *   Z00 = rinch(S00), R = Z00^T S01, Q = S11 - R^T R, Z11 = rinch(Q),
+ *   Z01 = -(Z00 R) Z11,
+ * every product truncated at tau, Q itself not; leaves of at most base_rows
+ * rows are inverse Cholesky factors, truncated.  The result replaces the
+ * handle's Z (upper triangular, Z^T S Z = I up to truncation); info->levels
+ * is the recursion depth, no refinement runs.  A non-positive leaf pivot
+ * gives LIF_ERR_NOT_PD.  Checkpoints for lif_backward are not kept. */
+lif_status lif_rinch(lif_handle h, lif_info* info);
+
 /* Copies the handle's Z out as a block list.  Two-phase: with brow == NULL
  * only *nnzb is written; otherwise the arrays (capacity *nnzb blocks, host or
  * device per on_device) receive the blocks in (row, col) order.

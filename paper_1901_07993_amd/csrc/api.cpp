@@ -297,6 +297,23 @@ lif_status lif_localized(lif_handle h, lif_info* info) {
   });
 }
 
+lif_status lif_rinch(lif_handle h, lif_info* info) {
+  if (!h) return LIF_ERR_INVALID;
+  return guarded(h, [&] {
+    reset_stats(h);
+    const auto t0 = std::chrono::steady_clock::now();
+    RunInfo ri;
+    h->ck.clear();
+    h->has_dS = false;
+    Bsr Z = run_rinch(h->ctx, h->S, h->opts, ri);
+    h->ctx.sync();
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    h->Z = std::move(Z);
+    h->has_Z = true;
+    fill_info(h, ri, secs, info);
+  });
+}
+
 lif_status lif_get_Z(lif_handle h, int64_t* nnzb, int32_t* brow, int32_t* bcol, double* vals, int32_t on_device) {
   if (!h) return LIF_ERR_INVALID;
   lif_status st = LIF_OK;

@@ -483,6 +483,65 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   return compact_values(c, std::move(Zt));
 }
 
+namespace {
+
+// One node of the recursive inverse Cholesky (Alg. 1) on rows [lo, hi) of
+// Sn (global coordinates; Sn holds no block outside the range):
+//   Z00 = rinch(S00), R = trunc(Z00^T S01), Q = S11 - trunc(R^T R),
+//   Z11 = rinch(Q), Z01 = -trunc(trunc(Z00 R) Z11), Z10 = 0;
+// ranges of at most base_rows rows are leaves (truncated inverse Cholesky).
+// The split is LIF's (the leading ceil(nb/2) blocks).  Q's rows depend on
+// Z00, so the two halves run one after the other.
+Bsr rinch_node(Ctx& c, const Bsr& Sn, int64_t lo, int64_t hi, const Opts& o, int depth, RunInfo& info) {
+  info.levels = std::max(info.levels, depth + 1);
+  const int b = Sn.b, nb = Sn.nb;
+  if (hi - lo <= o.base_rows) return leaf_inverse_cholesky(c, Sn, {{lo, hi}}, o.tau);
+  const int64_t nbr = (hi - lo + b - 1) / b;
+  const int64_t mid = lo + ((nbr + 1) / 2) * b;
+  // block-row labels: 0 = leading part, 1 = trailing part, -1 = elsewhere
+  std::vector<int> lab(nb, -1), lab0(nb, -1), lab1(nb, -1);
+  const int r0 = (int)(lo / b), rm = (int)(mid / b), r1 = (int)((hi + b - 1) / b);
+  for (int i = r0; i < r1; ++i) {
+    lab[i] = i < rm ? 0 : 1;
+    (i < rm ? lab0 : lab1)[i] = 0;
+  }
+  DBuf<int> d_lab(c.pool, nb), d_lab0(c.pool, nb), d_lab1(c.pool, nb);
+  h2d(c, d_lab.get(), lab.data(), nb);
+  h2d(c, d_lab0.get(), lab0.data(), nb);
+  h2d(c, d_lab1.get(), lab1.data(), nb);
+  Bsr S00 = filter(c, Sn, d_lab0.get(), d_lab0.get(), 0);
+  Bsr S01 = filter(c, Sn, d_lab.get(), d_lab.get(), 1);
+  Bsr S11 = filter(c, Sn, d_lab1.get(), d_lab1.get(), 0);
+  c.sync();  // the label vectors go out of scope
+  Bsr Z00 = rinch_node(c, S00, lo, mid, o, depth + 1, info);
+  S00 = Bsr();
+  Bsr R = spgemm(c, Z00, true, S01, false, o.tau);
+  S01 = Bsr();
+  Bsr Q;
+  {
+    Bsr RtR = spgemm(c, R, true, R, false, o.tau);
+    Q = axpby(c, 1.0, &S11, -1.0, &RtR, 0.0, nullptr);  // the difference is not truncated
+  }
+  S11 = Bsr();
+  Bsr Z11 = rinch_node(c, Q, mid, hi, o, depth + 1, info);
+  Q = Bsr();
+  Bsr Z01;
+  {
+    Bsr T = spgemm(c, Z00, false, R, false, o.tau);
+    Z01 = spgemm(c, T, false, Z11, false, o.tau, LIF_FP64, -1.0);
+  }
+  return axpby3(c, 1.0, &Z00, 1.0, &Z01, 1.0, &Z11);  // disjoint parts: every block shared
+}
+
+}  // namespace
+
+Bsr run_rinch(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info) {
+  info.levels = 0;
+  info.iterations_total = 0;
+  info.iterations_top = 0;
+  return rinch_node(c, S, 0, S.n, o, 0, info);
+}
+
 Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck) {
   const int b = S.b, nb = S.nb;
   const Plan plan = make_plan(S.n, b, o.base_rows);

@@ -81,6 +81,9 @@ Bsr run_irsi(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck
 Bsr run_refine_from(Ctx& c, const Bsr& S, Bsr&& Z0, const Opts& o, RunInfo& info);
 // Localized inverse factorization.
 Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck = nullptr);
+// Recursive inverse Cholesky (Alg. 1), split like LIF; info.levels = the
+// recursion depth (leaves included).
+Bsr run_rinch(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info);
 // Reverse sweep: sym(dL/dS) on S's block pattern for L = tr(G^T Z), through
 // the regular recurrence delta_i = I - Z_i^T S Z_i with the checkpointed Z_i
 // and frozen iteration counts; untruncated FP64 products.

@@ -26,7 +26,7 @@ START_SQRT2_OVER_GERSH, START_INV_SQRT_GERSH, START_INV_SQRT_LMAX, START_GIVEN =
 _STATUS_NAMES = {1: "LIF_ERR_INVALID", 2: "LIF_ERR_NOT_PD", 3: "LIF_ERR_NO_CONVERGENCE",
                  4: "LIF_ERR_OUT_OF_MEMORY", 5: "LIF_ERR_HIP", 6: "LIF_ERR_STATE"}
 
-EXPORTED = ("lif_opts_default", "lif_create", "lif_refine", "lif_localized", "lif_get_Z", "lif_residual",
+EXPORTED = ("lif_opts_default", "lif_create", "lif_refine", "lif_localized", "lif_rinch", "lif_get_Z", "lif_residual",
             "lif_multiply", "lif_backward", "lif_destroy", "lif_last_error")
 
 
@@ -76,6 +76,7 @@ def load() -> ctypes.CDLL:
     lib.lif_create.argtypes = [POINTER(Blocks), POINTER(Opts), POINTER(c_void_p)]
     lib.lif_refine.argtypes = [c_void_p, POINTER(Blocks), POINTER(Info)]
     lib.lif_localized.argtypes = [c_void_p, POINTER(Info)]
+    lib.lif_rinch.argtypes = [c_void_p, POINTER(Info)]
     lib.lif_get_Z.argtypes = [c_void_p, POINTER(c_int64), c_void_p, c_void_p, c_void_p, c_int32]
     lib.lif_residual.argtypes = [c_void_p, POINTER(c_double)]
     lib.lif_multiply.argtypes = [c_void_p, POINTER(Blocks), c_int32, POINTER(Blocks), c_int32, c_double,
@@ -192,6 +193,12 @@ class Factorization:
     def localized(self) -> dict:
         info = Info()
         self._check(load().lif_localized(self._h, byref(info)))
+        return info.as_dict()
+
+    def rinch(self) -> dict:
+        """Recursive inverse Cholesky (lif_rinch)."""
+        info = Info()
+        self._check(load().lif_rinch(self._h, byref(info)))
         return info.as_dict()
 
     def get_Z(self) -> HostBlocks:

@@ -226,6 +226,49 @@ def test_lif_water_matches_oracle(b, n_mol, base, tau):
         assert abs(res - R.true_residual(Dt, Zo)) <= 1e-3 * R.true_residual(Dt, Zo)
 
 
+# ----------------------------------------------------------------------------
+# recursive inverse Cholesky (next row f1: Alg. 1 on the device)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("b,n_mol,base,tau", [(32, 200, 256, 0.0), (32, 200, 256, 1e-6), (64, 150, 320, 0.0),
+                                              (64, 150, 320, 1e-7), (32, 60, 64, 1e-5)])
+def test_rinch_water_matches_oracle(b, n_mol, base, tau):
+    c_, e_ = water_cluster(n_mol, 7)
+    S = overlap_blocks(c_, e_, b)
+    D = blocks_to_dense(S)
+    say(f"case rinch water-{n_mol} n={S.n} b={b} base={base} tau={tau}")
+    with lif.Factorization(dev(S), tau=tau, base_rows=base) as f:
+        info = f.rinch()
+        Z = blocks_to_dense(f.get_Z())
+        res = f.residual()
+    Zo = R.rinch(D, b, tau, base_rows=base)
+    say(f"  gpu depth {info['levels']}")
+    assert info["levels"] >= 2
+    assert np.allclose(Z, np.triu(Z))
+    if tau == 0.0:
+        # untruncated, the recursion reaches the inverse Cholesky factor
+        assert np.max(np.abs(Z - Zo)) <= 1e-11 * np.max(np.abs(Zo))
+        U = np.linalg.cholesky(D).T
+        assert np.max(np.abs(Z - np.linalg.inv(U))) <= 1e-10 * np.max(np.abs(Zo))
+        assert res <= 1e-12
+    else:
+        assert np.linalg.norm(Z - Zo) <= 1e-8 * np.linalg.norm(Zo)
+        Dt = R.truncate(D, b, tau)
+        assert abs(res - R.true_residual(Dt, Zo)) <= 1e-3 * R.true_residual(Dt, Zo)
+
+
+def test_rinch_chain_matches_oracle():
+    S, cfg = config_matrix(1, count=150)   # n = 3000 chain, b = 64
+    D = blocks_to_dense(S)
+    tau = 1e-8
+    say(f"case rinch chain n={S.n} b=64 base=512 tau={tau}")
+    with lif.Factorization(dev(S), tau=tau, base_rows=512) as f:
+        f.rinch()
+        Z = blocks_to_dense(f.get_Z())
+    Zo = R.rinch(D, 64, tau, base_rows=512)
+    assert np.linalg.norm(Z - Zo) <= 1e-8 * np.linalg.norm(Zo)
+
+
 def test_leaf_only_is_inverse_cholesky():
     c_, e_ = water_cluster(30, 8)     # n = 210 <= base_rows: one leaf
     S = overlap_blocks(c_, e_, 64)
