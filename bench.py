@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--count", type=int, default=5000, help="chain residues (5000 = the full workload)")
     ap.add_argument("--no-residual", action="store_true", help="skip the untruncated residual after timing")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 / BF16 runs")
+    ap.add_argument("--no-rinch", action="store_true", help="skip the recursive inverse Cholesky run")
+    ap.add_argument("--rinch-steps", type=int, default=2)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device to device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -163,6 +165,24 @@ def main():
                            "stagnated": inf_m[-1]["stagnated"], "delta_tracked": inf_m[-1]["delta_tracked"],
                            "residual": res_m,
                            "rel_diff_vs_fp64_Z": None if Zm is None else rel_diff(Zm, Z64)}
+    rinch = None
+    if not args.no_rinch:
+        # the paper's recursive inverse Cholesky on the same matrix (the
+        # sequential recursion LIF shortens): one warm-up, then timed runs
+        f = lif.Factorization(Sd, tau=cfg["tau"], base_rows=4096, prec=lif.FP64, timing=1)
+        f.rinch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.rinch_steps):
+            inf_r = f.rinch()
+        torch.cuda.synchronize()
+        s_r = (time.perf_counter() - t0) / args.rinch_steps
+        rinch = {"s_per_factorization": s_r, "depth": inf_r["levels"], "nnzb_Z": inf_r["nnzb_Z"],
+                 "residual": None if args.no_residual else f.residual(),
+                 "leaf_gemm_gflops": (inf_r["flops_leaf_gemm"] / inf_r["seconds_leaf_gemm"] / 1e9
+                                      if inf_r["seconds_leaf_gemm"] > 0 else None),
+                 "lif_speedup": s_r / step_s}
+        f.close()
     out = {
         "metric": METRIC,
         "value": ms / 1e3,
@@ -192,6 +212,7 @@ def main():
         "products_per_step": last["products_total"],
         "iterations_redone": last.get("iterations_redone"),
         "mixed": mixed,
+        "rinch": rinch,
         "roofline": {"bound": "mfma", "kernel": "k_numeric_f64 (leaf GEMM, v_mfma_f64_16x16x4f64)",
                      "achieved": achieved, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
