@@ -265,14 +265,22 @@ def nonlocal_refinement(S, Z0, b, tau, m=4, iterations=None, stop="paper", tol=0
 # ----------------------------------------------------------------------------
 
 def irsi(S, b, tau, m=4, start="sqrt2_over_gersh", start_value=None, stop="paper", tol=0.0,
-         max_iter=100, truncate_input=True, prec="fp64"):
+         max_iter=100, truncate_input=True, prec="fp64", refinement="local"):
     """Iterative refinement from a scaled identity (IRSI, Sec. 2.2):
     Z_0 = c I, delta_0 = I - c^2 S (a scaling, no product), then localized
-    refinement.  Returns (Z, RefineInfo, c)."""
+    refinement.  With ``refinement="nonlocal"`` the regular form of
+    eq. refinement_nonlocal runs from the same Z_0 instead (its delta_0 is
+    then I - (Z_0^T S) Z_0 with both products truncated).
+    Returns (Z, RefineInfo, c)."""
     St = truncate(S, b, tau) if truncate_input else S
     c = start_scale(St, start, start_value)
     n = S.shape[0]
     Z0 = c * np.eye(n)
+    if refinement == "nonlocal":
+        assert prec == "fp64", "the regular form is FP64 only"
+        Z, info = nonlocal_refinement(St, Z0, b, tau, m, stop=stop, tol=tol, max_iter=max_iter)
+        return Z, info, c
+    assert refinement == "local", refinement
     delta0 = np.eye(n) - (c * c) * St
     Z, info = localized_refinement(St, Z0, delta0, b, tau, m, stop, tol, max_iter, prec=prec)
     return Z, info, c
@@ -301,7 +309,7 @@ def lif_plan(n: int, b: int, base_rows: int) -> LifNode:
 
 
 def lif(S, b, tau, m=4, base_rows=4096, stop="paper", tol=0.0, max_iter=100, truncate_input=True,
-        plan=None, prec="fp64"):
+        plan=None, prec="fp64", refinement="local"):
     """Localized inverse factorization (Alg. 2) with an inverse Cholesky leaf.
 
     For a node with children A (leading rows) and C:
@@ -309,8 +317,14 @@ def lif(S, b, tau, m=4, base_rows=4096, stop="paper", tol=0.0, max_iter=100, tru
         X = (Z_A^T B) Z_C (each product truncated),
         delta_0 = -[[0, X], [X^T, 0]],
         then localized refinement of Z_0 on the node's S.
+    With ``refinement="nonlocal"`` (recursive inverse factorization with the
+    regular correction, Sec. 2.3): each node is corrected by the regular form
+    of eq. refinement_nonlocal from the same Z_0, whose delta_0 is
+    I - (Z_0^T S) Z_0 (products truncated); X is not formed.
     Returns (Z, plan) with per-node RefineInfo stored in the plan.
     """
+    assert refinement in ("local", "nonlocal"), refinement
+    assert refinement == "local" or prec == "fp64", "the regular form is FP64 only"
     St = truncate(S, b, tau) if truncate_input else S
     plan = plan if plan is not None else lif_plan(S.shape[0], b, base_rows)
 
@@ -322,12 +336,16 @@ def lif(S, b, tau, m=4, base_rows=4096, stop="paper", tol=0.0, max_iter=100, tru
         ZA = rec(a)
         ZC = rec(c)
         h = a.hi - a.lo
-        B = Sn[:h, h:]
-        X = mult(mult(ZA.T, B, b, tau), ZC, b, tau)
         rows = node.hi - node.lo
         Z0 = np.zeros((rows, rows))
         Z0[:h, :h] = ZA
         Z0[h:, h:] = ZC
+        if refinement == "nonlocal":
+            node.info = RefineInfo()
+            Z, node.info = nonlocal_refinement(Sn, Z0, b, tau, m, stop=stop, tol=tol, max_iter=max_iter)
+            return Z
+        B = Sn[:h, h:]
+        X = mult(mult(ZA.T, B, b, tau), ZC, b, tau)
         delta0 = np.zeros((rows, rows))
         delta0[:h, h:] = -X
         delta0[h:, :h] = -X.T

@@ -264,6 +264,55 @@ def test_lif_contraction_bound_and_norms(water100):
     assert plan.children and plan.info.iterations >= 2
 
 
+def test_nonlocal_irsi_reaches_loewdin_and_spectral_map(water100):
+    # the regular form from Z_0 = c I: same limit (S^{-1/2}) and, in exact
+    # arithmetic, the same norms as the localized form (spectral map of delta_0)
+    D, lam = water100
+    Z, info, c = R.irsi(D, 32, 0.0, start="inv_sqrt_lmax", start_value=lam[-1], refinement="nonlocal")
+    Zref = inv_sqrt(D)
+    assert np.linalg.norm(Z - Zref) <= 1e-10 * np.linalg.norm(Zref) * 100
+    assert R.true_residual(D, Z) <= 1e-12
+    pred = predicted_norms(1.0 - c * c * lam, 4, info.iterations)
+    for got, want in zip(info.norms, pred):
+        if want > 1e-9:
+            assert abs(got - want) <= 1e-9 * want + 1e-12
+    Zl, infol, _ = R.irsi(D, 32, 0.0, start="inv_sqrt_lmax", start_value=lam[-1])
+    assert info.iterations == infol.iterations
+
+
+def test_nonlocal_lif_reaches_recursive_limit(water100):
+    # recursive inverse factorization with the regular correction (Sec. 2.3)
+    # has the limit of LIF: each node's refinement converges to
+    # Z_0 (Z_0^T S_n Z_0)^{-1/2} from the same Z_0, with delta_0 = I - Z_0^T S Z_0
+    D, _ = water100
+    Z, plan = R.lif(D, 32, 0.0, base_rows=128, refinement="nonlocal")
+    Zref = lif_limit(D, 32, 128)
+    assert np.linalg.norm(Z - Zref) <= 1e-13 * np.linalg.norm(Zref) * 10
+    assert R.true_residual(D, Z) < 1e-12
+
+    def walk(node):
+        if not node.children:
+            return
+        Sn = D[node.lo:node.hi, node.lo:node.hi]
+        a, c = node.children
+        Z0 = np.zeros_like(Sn)
+        h = a.hi - a.lo
+        Z0[:h, :h] = lif_limit(Sn[:h, :h], 32, 128)
+        Z0[h:, h:] = lif_limit(Sn[h:, h:], 32, 128)
+        mu = np.linalg.eigvalsh(np.eye(Sn.shape[0]) - Z0.T @ Sn @ Z0)
+        pred = predicted_norms(mu, 4, node.info.iterations)
+        for got, want in zip(node.info.norms, pred):
+            if want > 1e-8:
+                assert abs(got - want) <= 1e-8 * want
+        walk(a)
+        walk(c)
+
+    walk(plan)
+    assert plan.children and plan.info.iterations >= 2
+    _, plan_l = R.lif(D, 32, 0.0, base_rows=128)
+    assert plan.info.iterations == plan_l.info.iterations
+
+
 def test_lif_block_diagonal_needs_no_iteration():
     D = small_water(12)
     n = D.shape[0]
