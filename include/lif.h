@@ -59,6 +59,11 @@ typedef int32_t lif_status;
 #define LIF_STOP_PAPER  0  /* stop when ||delta_k||_F > ||delta_{k-1}||_F^{m+1} (Sec. 2.2), first tested at k = 2 */
 #define LIF_STOP_TOL    1  /* stop when ||delta_k||_F <= tol, or when it stops decreasing */
 
+/* lif_opts.refinement: form of the refinement (Sec. 2.2, Sec. 2.3) */
+#define LIF_REFINE_LOCAL    0  /* eq. refinement_local: delta updated from the correction, never recomputed */
+#define LIF_REFINE_NONLOCAL 1  /* eq. refinement_nonlocal: delta_i = I - (Z_i^T S) Z_i recomputed every
+                                * iteration, Z_{i+1} = Z_i P(delta_i), every product truncated; FP64 only */
+
 /* lif_opts.start: scale c of the IRSI start Z_0 = c I (Sec. 2.2) */
 #define LIF_START_SQRT2_OVER_GERSH 0  /* c = sqrt(2 / beta), beta the Gershgorin bound of S */
 #define LIF_START_INV_SQRT_GERSH   1  /* c = 1 / sqrt(beta) */
@@ -96,6 +101,7 @@ typedef struct {
                            * results are identical.  2: the same without the margin
                            * (least memory, most redone iterations).  0: read back the
                            * counts of every product */
+  int32_t refinement;     /* LIF_REFINE_LOCAL / LIF_REFINE_NONLOCAL (the latter needs prec = LIF_FP64) */
 } lif_opts;
 
 typedef struct {
@@ -118,7 +124,8 @@ typedef struct {
 
 /* Fills *o with the defaults: m = 4, tau = 0, FP64, paper stopping rule,
  * tol = 1e-10, max_iter = 100, base_rows = 4096, start = SQRT2_OVER_GERSH,
- * checkpoint = 0, no cap, null stream, timing = 0, presize = 1. */
+ * checkpoint = 0, no cap, null stream, timing = 0, presize = 1,
+ * refinement = LIF_REFINE_LOCAL. */
 lif_status lif_opts_default(lif_opts* o);
 
 /* Validates S and copies it into library-owned device memory (the caller may
@@ -130,8 +137,11 @@ lif_status lif_create(const lif_blocks* S, const lif_opts* o, lif_handle* out);
 
 /* Iterative refinement (eq. refinement_local).  Z0 == NULL: IRSI, start
  * Z_0 = c I, delta_0 = I - c^2 S (Sec. 2.2).  Otherwise Z0 (same n and b)
- * is the start and delta_0 = I - Z0^T S Z0 (products truncated).  The result
- * replaces the handle's Z.  info may be NULL. */
+ * is the start and delta_0 = I - Z0^T S Z0 (products truncated).  With
+ * opts.refinement = LIF_REFINE_NONLOCAL the regular form runs instead
+ * (eq. refinement_nonlocal): delta_0 = I - (Z_0^T S) Z_0 for either start,
+ * and every iteration recomputes delta from the new Z.  The result replaces
+ * the handle's Z.  info may be NULL. */
 lif_status lif_refine(lif_handle h, const lif_blocks* Z0, lif_info* info);
 
 /* Localized inverse factorization (Alg. 2): ranges of more than base_rows
@@ -139,7 +149,11 @@ lif_status lif_refine(lif_handle h, const lif_blocks* Z0, lif_info* info);
  * (S_leaf = U^T U, Z_leaf = U^{-1}); each level of the recursion is corrected
  * by localized refinement from diag(Z_A, Z_C) with
  * delta_0 = -[[0, X], [X^T, 0]], X = (Z_A^T B) Z_C.  All nodes of one depth are
- * processed together.  A non-positive leaf pivot gives LIF_ERR_NOT_PD. */
+ * processed together.  A non-positive leaf pivot gives LIF_ERR_NOT_PD.
+ * With opts.refinement = LIF_REFINE_NONLOCAL this is the recursive inverse
+ * factorization of Sec. 2.3 instead: the same recursion and start
+ * diag(Z_A, Z_C), corrected by the regular form (eq. refinement_nonlocal)
+ * with delta_0 = I - (Z_0^T S) Z_0 on each node. */
 lif_status lif_localized(lif_handle h, lif_info* info);
 
 /* Recursive inverse Cholesky (Alg. 1) of the handle's S, as a standalone

@@ -37,6 +37,10 @@ void validate_opts(const lif_opts& o) {
   LIF_REQUIRE(o.max_iter >= 1 && o.max_iter <= 10000, LIF_ERR_INVALID, "opts.max_iter must be in 1..10000");
   LIF_REQUIRE(o.presize >= 0 && o.presize <= 2, LIF_ERR_INVALID, "opts.presize must be 0, 1 or 2");
   LIF_REQUIRE(o.start >= 0 && o.start <= 3, LIF_ERR_INVALID, "opts.start is invalid");
+  LIF_REQUIRE(o.refinement == LIF_REFINE_LOCAL || o.refinement == LIF_REFINE_NONLOCAL, LIF_ERR_INVALID,
+              "opts.refinement is invalid");
+  LIF_REQUIRE(o.refinement == LIF_REFINE_LOCAL || o.prec == LIF_FP64, LIF_ERR_INVALID,
+              "opts.refinement = LIF_REFINE_NONLOCAL needs prec = LIF_FP64");
   if (o.start == LIF_START_INV_SQRT_LMAX || o.start == LIF_START_GIVEN)
     LIF_REQUIRE(std::isfinite(o.start_value) && o.start_value > 0.0, LIF_ERR_INVALID,
                 "opts.start_value must be > 0 for this start");
@@ -199,6 +203,7 @@ lif_status lif_opts_default(lif_opts* o) {
   o->stream = nullptr;
   o->timing = 0;
   o->presize = 1;
+  o->refinement = LIF_REFINE_LOCAL;
   return LIF_OK;
 }
 
@@ -227,6 +232,7 @@ lif_status lif_create(const lif_blocks* S, const lif_opts* o, lif_handle* out) {
     p.start_value = o->start_value;
     p.checkpoint = o->checkpoint != 0;
     p.presize = o->presize;
+    p.refinement = o->refinement;
     Ctx& c = h->ctx;
     c.stream = static_cast<hipStream_t>(o->stream);
     c.pool = &h->pool;

@@ -59,6 +59,16 @@ struct Batch {
   int nb = 0;
 };
 
+// delta = I - trunc(trunc(Z^T S) Z) on the block rows flagged in `on`, the
+// residual of the regular form (eq. refinement_nonlocal).  Both products
+// keep their dropped blocks as holes: only the sum reads them.
+Bsr regular_delta(Ctx& c, const Bsr& S, const Bsr& Z, double tau, const unsigned char* on) {
+  Bsr W = spgemm(c, Z, true, S, false, tau, LIF_FP64, 1.0, nullptr, 0.0, true);
+  Bsr V = spgemm(c, W, false, Z, false, tau, LIF_FP64, 1.0, nullptr, 0.0, true);
+  W = Bsr();
+  return axpby(c, -1.0, &V, 0.0, nullptr, 1.0, on);
+}
+
 // `carry` (nullable): product capacities handed from one batch to the next
 // of the same factorization; the first iteration is then sized in advance
 // too (and redone with exact sizes if a capacity was short).
@@ -83,6 +93,20 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
 
   std::vector<int> rowlab(nb);
   DBuf<int> d_rowlab(c.pool, nb);
+  // regular form: the identity of delta = I - Z^T S Z lives on the rows of
+  // the batch's problems only
+  const bool regular = o.refinement == LIF_REFINE_NONLOCAL;
+  DBuf<unsigned char> d_inb;
+  std::vector<unsigned char> inb;  // host source of an async copy: lives to the end
+  Bsr none;
+  if (regular) {
+    inb.assign(nb, 0);
+    for (int s = 0; s < nn; ++s)
+      for (int i = bt.rlo[s]; i < bt.rhi[s]; ++i) inb[i] = 1;
+    d_inb = DBuf<unsigned char>(c.pool, nb);
+    h2d(c, d_inb.get(), inb.data(), nb);
+    none = bsr_empty(c, S.n, S.b);
+  }
   bool labels_dirty = true;
   bool all_active = true;
   std::vector<std::array<int64_t, 2>> caps;  // per product of an iteration: {blocks, pairs}
@@ -141,6 +165,30 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       // by the two sums, so their dropped blocks are left as null pointers
       // (holes) rather than compacted away.
       constexpr bool kHoles = true;
+      DeferFrees defer(c);
+      if (regular) {
+        // Regular form (eq. refinement_nonlocal): P = b_m I, then
+        // P <- b_j I + trunc(delta P) for j = m-1 .. 0, Z_{k+1} = trunc(Z P),
+        // delta_{k+1} = I - trunc(trunc(Z_{k+1}^T S) Z_{k+1}).  P is kept as
+        // X_j + b_j I with only X_j stored: delta P = delta X + b delta, the
+        // scaled delta added to each output block before its truncation.
+        // The first step has no product (X_m = 0): X_{m-1} = trunc(b_m delta).
+        // Everything runs on the one stream: freed buffers are reusable at once.
+        defer.release();
+        Bsr X = spgemm(c, da, false, none, false, o.tau, LIF_FP64, 1.0, &da, bk[o.m], kHoles);
+        for (int j = o.m - 2; j >= 0; --j)
+          X = spgemm(c, da, false, X, false, o.tau, LIF_FP64, 1.0, &da, bk[j + 1], kHoles);
+        // Z P = Z X_0 + b_0 Z; rows of finished problems (X_0 is empty there)
+        // keep their blocks, which all passed the same truncation before
+        Znew = spgemm(c, Z, false, X, false, o.tau, LIF_FP64, 1.0, &Z, bk[0]);
+        X = Bsr();
+        if (restrict_rows) {
+          Bsr Zf = filter(c, Znew, d_rowlab.get(), nullptr, 2);
+          dnew = regular_delta(c, S, Zf, o.tau, d_inb.get());
+        } else {
+          dnew = regular_delta(c, S, Znew, o.tau, d_inb.get());
+        }
+      } else {
       // M = Z sum_{k=1}^m b_k delta^k, Horner form, every product truncated:
       //   T_{m-1} = b_m delta + b_{m-1} I,  T_j = b_j I + trunc(delta T_{j+1}),
       //   q = trunc(delta T_1).
@@ -165,7 +213,6 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       // S M and then (S M)^T Z_k run on the side stream while Z + M and then
       // Z_{k+1}^T (S M) run on the main one; buffers freed meanwhile are
       // reused only after the synchronization at the end of the iteration.
-      DeferFrees defer(c);
       const hipStream_t main_s = c.stream, side_s = c.side_stream();
       c.stream_after(side_s, main_s);
       Bsr SM, X2;
@@ -186,6 +233,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       dnew = axpby3(c, 1.0, &delta, -1.0, &X1, -1.0, &X2);
       X1 = Bsr();
       X2 = Bsr();
+      }
 
       const size_t nprod = planned ? c.spec.next : c.spec.seen.size();
       const std::vector<int> pprec = c.spec.prec;
@@ -314,7 +362,10 @@ Bsr run_irsi(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck
   info.start_scale = cs;
   const unsigned char* on = all_rows_on(c);
   Bsr Z = axpby(c, 0.0, nullptr, 0.0, nullptr, cs, on);
-  Bsr delta = axpby(c, -cs * cs, &S, 0.0, nullptr, 1.0, on);
+  // localized form: delta_0 = I - c^2 S by scaling; regular form: from the
+  // truncated products like every later delta
+  Bsr delta = o.refinement == LIF_REFINE_NONLOCAL ? regular_delta(c, S, Z, o.tau, on)
+                                                   : axpby(c, -cs * cs, &S, 0.0, nullptr, 1.0, on);
   Batch bt;
   bt.nb = S.nb;
   bt.rlo = {0};
@@ -343,10 +394,15 @@ Bsr run_irsi(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck
 
 Bsr run_refine_from(Ctx& c, const Bsr& S, Bsr&& Z0, const Opts& o, RunInfo& info) {
   const unsigned char* on = all_rows_on(c);
-  Bsr SZ = spgemm(c, S, false, Z0, false, o.tau);
-  Bsr ZSZ = spgemm(c, Z0, true, SZ, false, o.tau);
-  SZ = Bsr();
-  Bsr delta = axpby(c, -1.0, &ZSZ, 0.0, nullptr, 1.0, on);
+  Bsr delta;
+  if (o.refinement == LIF_REFINE_NONLOCAL) {
+    delta = regular_delta(c, S, Z0, o.tau, on);
+  } else {
+    Bsr SZ = spgemm(c, S, false, Z0, false, o.tau);
+    Bsr ZSZ = spgemm(c, Z0, true, SZ, false, o.tau);
+    SZ = Bsr();
+    delta = axpby(c, -1.0, &ZSZ, 0.0, nullptr, 1.0, on);
+  }
   Batch bt;
   bt.nb = S.nb;
   bt.rlo = {0};
@@ -586,14 +642,25 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck)
     h2d(c, d_side.get(), side.data(), nb);
     // the level's diagonal problems, and the couplings B of each split
     Bsr S_lvl = filter(c, S, d_lab.get(), d_lab.get(), 0);
-    Bsr S_up = filter(c, S, d_side.get(), d_side.get(), 1);
-    // delta_0 = -[[0, X], [X^T, 0]], X = (Z_A^T B) Z_C.  The two products
-    // are sized in advance from the level below (their counts and an
+    const bool regular = o.refinement == LIF_REFINE_NONLOCAL;
+    Bsr S_up = regular ? Bsr() : filter(c, S, d_side.get(), d_side.get(), 1);
+    // Localized form: delta_0 = -[[0, X], [X^T, 0]], X = (Z_A^T B) Z_C.  The
+    // two products are sized in advance from the level below (their counts and an
     // overflow flag come back with delta_0's norms; a short capacity redoes
     // them with exact sizes).
     Bsr delta0;
     std::vector<double> ss0;
-    {
+    std::vector<unsigned char> inb;
+    DBuf<unsigned char> d_inb;
+    if (regular) {
+      // recursive inverse factorization with the regular correction
+      // (Sec. 2.3): delta_0 = I - (Z_0^T S) Z_0 on the level's rows
+      inb.resize(nb);
+      for (int i = 0; i < nb; ++i) inb[i] = lab[i] >= 0 ? 1 : 0;
+      d_inb = DBuf<unsigned char>(c.pool, nb);
+      h2d(c, d_inb.get(), inb.data(), nb);
+      delta0 = regular_delta(c, S_lvl, Z, o.tau, d_inb.get());
+    } else {
       DBuf<int> d_rlo(c.pool, nn), d_rhi(c.pool, nn);
       h2d(c, d_rlo.get(), bt.rlo.data(), nn);
       h2d(c, d_rhi.get(), bt.rhi.data(), nn);
@@ -670,7 +737,7 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck)
       }
     }
     refine_batch(c, S_lvl, Z, std::move(delta0), bt, o, st, o.max_iter, L ? &L->Z : nullptr,
-                 o.presize != 0 ? &carry : nullptr, &ss0);
+                 o.presize != 0 ? &carry : nullptr, regular ? nullptr : &ss0);
     if (L) {
       for (auto& ns : st) L->iters.push_back(ns.iterations);
       L->S_lvl = std::move(S_lvl);

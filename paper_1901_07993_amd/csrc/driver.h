@@ -19,6 +19,7 @@ struct Opts {
   double start_value = 0.0;
   bool checkpoint = false;
   int presize = 1;  // 0 off, 1 with margins, 2 previous counts as they are
+  int refinement = LIF_REFINE_LOCAL;
 };
 
 // One node of the split tree: scalar rows [lo, hi), lo a multiple of b.

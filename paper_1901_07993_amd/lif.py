@@ -22,6 +22,7 @@ OK, ERR_INVALID, ERR_NOT_PD, ERR_NO_CONVERGENCE, ERR_OUT_OF_MEMORY, ERR_HIP, ERR
 FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
 STOP_PAPER, STOP_TOL = 0, 1
 START_SQRT2_OVER_GERSH, START_INV_SQRT_GERSH, START_INV_SQRT_LMAX, START_GIVEN = 0, 1, 2, 3
+REFINE_LOCAL, REFINE_NONLOCAL = 0, 1
 
 _STATUS_NAMES = {1: "LIF_ERR_INVALID", 2: "LIF_ERR_NOT_PD", 3: "LIF_ERR_NO_CONVERGENCE",
                  4: "LIF_ERR_OUT_OF_MEMORY", 5: "LIF_ERR_HIP", 6: "LIF_ERR_STATE"}
@@ -45,7 +46,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("m", c_int32), ("tau", c_double), ("prec", c_int32), ("stop", c_int32), ("tol", c_double),
                 ("max_iter", c_int32), ("base_rows", c_int64), ("start", c_int32), ("start_value", c_double),
                 ("checkpoint", c_int32), ("mem_cap_bytes", c_uint64), ("stream", c_void_p), ("timing", c_int32),
-                ("presize", c_int32)]
+                ("presize", c_int32), ("refinement", c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -159,7 +160,8 @@ class Factorization:
     """One inverse-factorization problem: S (block list) and options.
 
     Keyword options mirror ``lif_opts``: m, tau, prec, stop, tol, max_iter,
-    base_rows, start, start_value, checkpoint, mem_cap_bytes, timing.
+    base_rows, start, start_value, checkpoint, mem_cap_bytes, timing, presize,
+    refinement.
     """
 
     def __init__(self, S, **opts):
