@@ -86,6 +86,45 @@ def rel_diff(A, B) -> float:
     return (num / float(np.sum(B.vals ** 2))) ** 0.5
 
 
+def time_method(lif, Sd, tau, meth, steps, **kw):
+    """(seconds per call, info of the last call) of one untimed and `steps`
+    timed calls of a Factorization method on the device matrix Sd."""
+    import torch
+    f = lif.Factorization(Sd, tau=tau, base_rows=4096, **kw)
+    getattr(f, meth)()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = getattr(f, meth)()
+    torch.cuda.synchronize()
+    s = (time.perf_counter() - t0) / steps
+    f.close()
+    return s, info
+
+
+def cpl_sweep(counts, steps):
+    """Critical-path task counts (the one-GPU shadow of Sec. 3) and times of
+    the four methods on chains of the given lengths."""
+    import torch
+    from gen import config_matrix
+    from paper_1901_07993_amd import lif
+    rows = []
+    for count in counts:
+        S, cfg = config_matrix(1, count=count)
+        Sd = type("DevBlocks", (), dict(n=S.n, b=S.b, brow=torch.from_numpy(S.brow).cuda(),
+                                        bcol=torch.from_numpy(S.bcol).cuda(), vals=torch.from_numpy(S.vals).cuda()))
+        row = {"count": count, "n": S.n}
+        for name, meth, kw in (("lif", "localized", {}), ("rinch", "rinch", {}), ("irsi", "refine", {}),
+                               ("recursive_regular", "localized", {"refinement": lif.REFINE_NONLOCAL})):
+            s_v, inf = time_method(lif, Sd, cfg["tau"], meth, steps, **kw)
+            row[name] = {"s": s_v, "cpl_tasks": inf["cpl_tasks"], "cpl_products": inf["cpl_products"],
+                         "iterations_total": inf["iterations_total"]}
+            print(f"# chain-{count} {name}: {s_v * 1e3:.1f} ms, {inf['cpl_tasks']} tasks on the critical path",
+                  file=sys.stderr, flush=True)
+        rows.append(row)
+    return {"cpl_sweep": rows, "unit": "tasks", "data": "synthetic"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +136,11 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 / BF16 runs")
     ap.add_argument("--no-rinch", action="store_true", help="skip the recursive inverse Cholesky run")
     ap.add_argument("--rinch-steps", type=int, default=2)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip IRSI and the regular-form recursive factorization on the same matrix")
+    ap.add_argument("--cpl-sweep", type=str, default="",
+                    help="comma-separated chain lengths: print critical-path task counts and times of "
+                         "LIF, RINCH, IRSI and the regular-form recursion per size (one JSON line) and exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device to device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -120,6 +164,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.cpl_sweep:
+        print(json.dumps(cpl_sweep([int(x) for x in args.cpl_sweep.split(",")], args.rinch_steps)), flush=True)
+        return
     print(f"# generating chain-{args.count}", file=sys.stderr, flush=True)
     S, cfg = config_matrix(1, count=args.count)
     Sd = type("DevBlocks", (), dict(n=S.n, b=S.b, brow=torch.from_numpy(S.brow).cuda(),
@@ -178,11 +225,29 @@ def main():
         torch.cuda.synchronize()
         s_r = (time.perf_counter() - t0) / args.rinch_steps
         rinch = {"s_per_factorization": s_r, "depth": inf_r["levels"], "nnzb_Z": inf_r["nnzb_Z"],
+                 "cpl_tasks": inf_r["cpl_tasks"], "cpl_products": inf_r["cpl_products"],
                  "residual": None if args.no_residual else f.residual(),
                  "leaf_gemm_gflops": (inf_r["flops_leaf_gemm"] / inf_r["seconds_leaf_gemm"] / 1e9
                                       if inf_r["seconds_leaf_gemm"] > 0 else None),
                  "lif_speedup": s_r / step_s}
         f.close()
+    variants = None
+    if not args.no_variants:
+        # the other methods of the paper on the same matrix: IRSI (Sec. 2.2)
+        # and the recursive factorization with the regular correction
+        # (Sec. 2.3), with their critical-path shadows beside LIF's
+        variants = {"lif": {"s_per_factorization": step_s, "cpl_tasks": last["cpl_tasks"],
+                            "cpl_products": last["cpl_products"]}}
+        if rinch:
+            variants["rinch"] = {"s_per_factorization": rinch["s_per_factorization"],
+                                 "cpl_tasks": rinch["cpl_tasks"], "cpl_products": rinch["cpl_products"]}
+        for name, meth, kw in (("irsi", "refine", {}),
+                               ("recursive_regular", "localized", {"refinement": lif.REFINE_NONLOCAL})):
+            s_v, inf_v = time_method(lif, Sd, cfg["tau"], meth, args.rinch_steps, **kw)
+            variants[name] = {"s_per_factorization": s_v, "lif_speedup": s_v / step_s,
+                              "cpl_tasks": inf_v["cpl_tasks"], "cpl_products": inf_v["cpl_products"],
+                              "iterations_top": inf_v["iterations_top"],
+                              "iterations_total": inf_v["iterations_total"], "nnzb_Z": inf_v["nnzb_Z"]}
     out = {
         "metric": METRIC,
         "value": ms / 1e3,
@@ -213,6 +278,7 @@ def main():
         "iterations_redone": last.get("iterations_redone"),
         "mixed": mixed,
         "rinch": rinch,
+        "variants": variants,
         "roofline": {"bound": "mfma", "kernel": "k_numeric_f64 (leaf GEMM, v_mfma_f64_16x16x4f64)",
                      "achieved": achieved, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_MFMA_TFLOPS,

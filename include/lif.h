@@ -120,6 +120,11 @@ typedef struct {
   int32_t n_norms;           /* entries used in norms[] */
   double norms[64];          /* ||delta_k||_F of the top-level problem, k = 1.. */
   int32_t iterations_redone; /* presized iterations redone with exact sizes */
+  int32_t cpl_tasks;         /* one-GPU shadow of the critical path (Sec. 3): the longest chain of
+                              * dependent tasks the call ran, where a product, a sum or scaling, a
+                              * separate transpose and a batched leaf factorization each count one
+                              * (independent problems of a level run as one batch) */
+  int32_t cpl_products;      /* products on that chain */
 } lif_info;
 
 /* Fills *o with the defaults: m = 4, tau = 0, FP64, paper stopping rule,

@@ -155,6 +155,8 @@ void fill_info(lif_handle h, const RunInfo& ri, double seconds, lif_info* info) 
   info->seconds_leaf_gemm = h->ctx.stats.gemm_ms * 1e-3;
   info->leaf_gemm_launches = h->ctx.stats.gemm_launches;
   info->products_total = h->ctx.stats.products;
+  info->cpl_tasks = h->ctx.stats.cpl;
+  info->cpl_products = h->ctx.stats.cpl_products;
   info->nnzb_Z = h->has_Z ? exact_nnzb(h->ctx, h->Z) : 0;
   info->n_norms = (int32_t)std::min<size_t>(64, ri.norms_top.size());
   for (int k = 0; k < info->n_norms; ++k) info->norms[k] = ri.norms_top[k];

@@ -9,6 +9,7 @@
 #include <array>
 #include <cstdint>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <memory>
 #include <stdexcept>
@@ -151,6 +152,13 @@ struct Bsr {
   // compacted away: their pointers are null and they count as absent.  Only
   // products, sums and transposed views read such a matrix.
   bool holes = false;
+  // Task-graph shadow (the critical-path model of Sec. 3, where products,
+  // sums, scalings, separate transposes and factorizations are tasks): the
+  // longest chain of dependent tasks that ends in this matrix, and the
+  // products on that chain.  Inputs start at 0; operations that are not
+  // tasks (filters, truncation, compaction) pass the counts on.
+  int cpl = 0;
+  int cpl_products = 0;
   int64_t bound() const { return nnzb >= 0 ? nnzb : cap; }
   const int* live() const { return row_ptr.get() + nb; }  // device-side count
   BlkIn ptrs() const { return blk.get(); }
@@ -174,6 +182,8 @@ struct Stats {
   int64_t gemm_launches = 0;
   double gemm_ms = 0;
   int redone = 0;  // presized iterations redone with exact sizes
+  int cpl = 0;           // longest chain of dependent tasks so far (Bsr::cpl)
+  int cpl_products = 0;  // products on it
 };
 
 // Execution context shared by all operations of a handle.
@@ -502,6 +512,10 @@ Bsr transpose(Ctx& c, const Bsr& A);
 // block by block before the truncation.  With `keep_holes` the dropped
 // blocks stay in the pattern with null pointers (Bsr::holes) instead of
 // being compacted away, for a result that only products and sums read.
+// Records `out` as the result of one task that depends on the matrices in
+// `in` (null entries ignored): its chain is one longer than the longest of
+// theirs (among equally long ones, the one with most products).
+void task_after(Ctx& c, Bsr& out, bool product, std::initializer_list<const Bsr*> in);
 Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec = LIF_FP64,
            double alpha = 1.0, const Bsr* D = nullptr, double gamma = 0.0, bool keep_holes = false);
 // alpha A + beta B + gamma I on the block rows with diag_on set (A or B may be null)

@@ -536,7 +536,9 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   DBuf<double> nrm = block_norms(c, Z);
   Bsr Zt = truncate(c, std::move(Z), nrm.get(), std::max(tau, std::numeric_limits<double>::denorm_min()));
   // the packed triangles hold every tile of each leaf; keep only the kept ones
-  return compact_values(c, std::move(Zt));
+  Bsr out = compact_values(c, std::move(Zt));
+  task_after(c, out, false, {&S});  // one factorization task for all leaves of the batch
+  return out;
 }
 
 namespace {

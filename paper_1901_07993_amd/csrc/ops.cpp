@@ -29,10 +29,27 @@ Bsr like(const Bsr& A) {
   C.n = A.n;
   C.b = A.b;
   C.nb = A.nb;
+  C.cpl = A.cpl;
+  C.cpl_products = A.cpl_products;
   return C;
 }
 
 }  // namespace
+
+void task_after(Ctx& c, Bsr& out, bool product, std::initializer_list<const Bsr*> in) {
+  int d = 0, p = 0;
+  for (const Bsr* x : in)
+    if (x && (x->cpl > d || (x->cpl == d && x->cpl_products > p))) {
+      d = x->cpl;
+      p = x->cpl_products;
+    }
+  out.cpl = d + 1;
+  out.cpl_products = p + (product ? 1 : 0);
+  if (out.cpl > c.stats.cpl || (out.cpl == c.stats.cpl && out.cpl_products > c.stats.cpl_products)) {
+    c.stats.cpl = out.cpl;
+    c.stats.cpl_products = out.cpl_products;
+  }
+}
 
 Store new_store(Ctx& c, int64_t blocks, int b) {
   return std::make_shared<DBuf<double>>(c.pool, (size_t)std::max<int64_t>(blocks, 0) * b * b);
@@ -191,6 +208,7 @@ Bsr transpose(Ctx& c, const Bsr& A) {
   T.blk = DBuf<const double*>(c.pool, (size_t)T.cap);
   T.store.push_back(st);
   launch_transpose_blocks(c, A.ptrs(), v.own_idx.get(), T.cap, A.b, st->get(), T.blk.get(), T.live());
+  task_after(c, T, false, {&A});  // a separate transpose is a task
   return T;
 }
 
@@ -228,8 +246,10 @@ Bsr numeric_phase(Ctx& c, Bsr&& C, bool ta, bool tb, double tau, int prec, doubl
 
 }  // namespace
 
-Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec, double alpha,
-           const Bsr* D, double gamma, bool keep_holes) {
+namespace {
+
+Bsr spgemm_body(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec, double alpha,
+                const Bsr* D, double gamma, bool keep_holes) {
   LIF_REQUIRE(A.nb == B.nb && A.b == B.b, LIF_ERR_INVALID, "spgemm: operand shapes differ");
   LIF_REQUIRE(!D || !D->holes, LIF_ERR_INVALID, "spgemm: the added term has holes");
   const int nb = A.nb;
@@ -321,6 +341,17 @@ Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int
                        seg.get(), pairs.get(), nnzc, nullptr);
 }
 
+}  // namespace
+
+Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec, double alpha,
+           const Bsr* D, double gamma, bool keep_holes) {
+  Bsr C = spgemm_body(c, A, ta, B, tb, tau, prec, alpha, D, gamma, keep_holes);
+  // with an operand known to be empty only the scaled added term remains
+  const bool scaling = A.nnzb == 0 || B.nnzb == 0;
+  task_after(c, C, !scaling, {&A, &B, D});
+  return C;
+}
+
 namespace {
 
 Bsr union_sum(Ctx& c, const Bsr* const src[3], const double coef[3], double gamma, const unsigned char* diag_on) {
@@ -399,13 +430,17 @@ Bsr axpby(Ctx& c, double alpha, const Bsr* A, double beta, const Bsr* B, double 
           const unsigned char* diag_on) {
   const Bsr* src[3] = {A, B, nullptr};
   const double coef[3] = {alpha, beta, 0.0};
-  return union_sum(c, src, coef, gamma, diag_on);
+  Bsr R = union_sum(c, src, coef, gamma, diag_on);
+  task_after(c, R, false, {A, B});
+  return R;
 }
 
 Bsr axpby3(Ctx& c, double alpha, const Bsr* A, double beta, const Bsr* B, double kappa, const Bsr* C) {
   const Bsr* src[3] = {A, B, C};
   const double coef[3] = {alpha, beta, kappa};
-  return union_sum(c, src, coef, 0.0, nullptr);
+  Bsr R = union_sum(c, src, coef, 0.0, nullptr);
+  task_after(c, R, false, {A, B, C});
+  return R;
 }
 
 Bsr filter(Ctx& c, const Bsr& A, const int* rlab, const int* clab, int mode) {

@@ -54,7 +54,8 @@ class Info(ctypes.Structure):
                 ("stagnated", c_int32), ("start_scale", c_double), ("delta_tracked", c_double),
                 ("flops_leaf_gemm", c_double), ("seconds_total", c_double), ("seconds_leaf_gemm", c_double),
                 ("leaf_gemm_launches", c_int64), ("products_total", c_int64), ("nnzb_Z", c_int64),
-                ("n_norms", c_int32), ("norms", c_double * 64), ("iterations_redone", c_int32)]
+                ("n_norms", c_int32), ("norms", c_double * 64), ("iterations_redone", c_int32),
+                ("cpl_tasks", c_int32), ("cpl_products", c_int32)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "norms"}

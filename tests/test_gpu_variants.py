@@ -218,3 +218,71 @@ def test_regular_forms_backward_matches_oracle():
     ref = on_pattern(ADJ.lif_grad(D, Gd, 32, 160, 4, iters), S)
     scale = np.max(np.abs(ref))
     assert np.max(np.abs(dS - ref)) <= 1e-9 * scale
+
+
+# ----------------------------------------------------------------------------
+# one-GPU shadow of the critical path (Sec. 3): chains of dependent tasks
+# ----------------------------------------------------------------------------
+
+def _plan_levels(plan):
+    """Per depth with refinement: the most iterations over its nodes."""
+    by_depth = {}
+
+    def walk(nd):
+        if nd.children:
+            by_depth[nd.depth] = max(by_depth.get(nd.depth, 0), nd.info.iterations)
+            walk(nd.children[0])
+            walk(nd.children[1])
+
+    walk(plan)
+    return [by_depth[d] for d in sorted(by_depth, reverse=True)]   # deepest level first
+
+
+def _rinch_counts(nd):
+    """(tasks, products) a recursive inverse Cholesky node adds to the chain:
+    leaf factorization 1; inner node: the leading child, R = Z00^T S01,
+    R^T R, Q, the trailing child, Z01 = (Z00 R) Z11 and the final sum
+    (Z00 R runs beside the trailing child)."""
+    if not nd.children:
+        return 1, 0
+    ta, pa = _rinch_counts(nd.children[0])
+    tc, pc = _rinch_counts(nd.children[1])
+    return ta + tc + 5, pa + pc + 3
+
+
+def test_critical_path_shadow_counts():
+    m = 4
+    S, _ = config_matrix(0)
+    D = blocks_to_dense(S)
+    say("case critical-path shadow: irsi water-100, localized and regular")
+    with lif.Factorization(dev(S)) as f:
+        info = f.refine()
+    K = info["iterations_top"]
+    # Z_0 = c I and delta_0 = I - c^2 S (independent); per iteration m - 1
+    # products for q (the Horner sums ride in their epilogues), M = Z q,
+    # S M, X_1 = Z_{k+1}^T (S M) and the delta sum
+    assert (info["cpl_tasks"], info["cpl_products"]) == (1 + K * (m + 3), K * (m + 2))
+    with lif.Factorization(dev(S), **NONLOCAL) as f:
+        info = f.refine()
+    K = info["iterations_top"]
+    # Z_0, then delta_0 = I - (Z_0^T S) Z_0 (two products and a sum); per
+    # iteration the scaling b_m delta, m - 1 products, Z P, the two products
+    # of the new delta and its sum
+    assert (info["cpl_tasks"], info["cpl_products"]) == (4 + K * (m + 4), 2 + K * (m + 2))
+
+    S, cfg = config_matrix(1, count=150)   # n = 3000 chain, b = 64
+    D = blocks_to_dense(S)
+    tau = 1e-10
+    say("case critical-path shadow: lif and rinch, chain n=3000 base=512")
+    with lif.Factorization(dev(S), tau=tau, base_rows=512) as f:
+        info = f.localized()
+        info_r = f.rinch()
+    Zo, plan = R.lif(D, 64, tau, base_rows=512)
+    Ks = _plan_levels(plan)
+    say(f"  levels (deepest first) iterations {Ks}: lif {info['cpl_tasks']} tasks, rinch {info_r['cpl_tasks']}")
+    assert info["iterations_top"] == Ks[-1]
+    # leaves: one batched task; each level: W = Z^T B, X = W Z, X^T and
+    # delta_0, then K_l iterations; the top level ends with its last delta
+    assert info["cpl_tasks"] == 1 + sum(k * (m + 3) + 2 for k in Ks) + 2
+    assert info["cpl_products"] == sum(k * (m + 2) for k in Ks) + 2
+    assert (info_r["cpl_tasks"], info_r["cpl_products"]) == _rinch_counts(plan)
