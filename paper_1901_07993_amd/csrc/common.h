@@ -12,6 +12,7 @@
 #include <initializer_list>
 #include <map>
 #include <memory>
+#include <set>
 #include <stdexcept>
 #include <string>
 #include <utility>
@@ -43,13 +44,17 @@ struct Error : std::runtime_error {
 // refinement loop does not call hipMalloc/hipFree once warm.  All memory of a
 // handle goes through one pool, which enforces the handle's byte cap.
 // ---------------------------------------------------------------------------
+// Device memory: a few large segments from hipMalloc, carved into buffers
+// best-fit and merged again when freed, so that the changing sizes of
+// products from one iteration to the next cost no hipMalloc / hipFree
+// (each of those can take milliseconds for a large buffer).
 class Pool {
  public:
   explicit Pool(uint64_t cap) : cap_(cap) {}
   ~Pool() { release_all(); }
   void* alloc(size_t bytes);
   void free(void* p);
-  void trim();            // return cached (unused) memory to HIP
+  void trim();            // return wholly unused segments to HIP
   // While deferring, freed buffers are held back from reuse until
   // release_deferred(): work on two streams may still read a buffer the host
   // has released, and reuse is only safe after both streams have synchronized.
@@ -58,14 +63,24 @@ class Pool {
   uint64_t in_use() const { return in_use_; }
   uint64_t reserved() const { return reserved_; }
   uint64_t peak() const { return peak_; }
+  int64_t segments_allocated() const { return seg_allocs_; }
 
  private:
+  struct Piece {
+    size_t size;
+    bool free;
+    char* seg;  // base of the segment it lies in
+  };
   static size_t round(size_t bytes);
+  bool grow(size_t need);
+  void take(std::map<char*, Piece>::iterator it, size_t r);
   void release_all();
   uint64_t cap_;
   uint64_t in_use_ = 0, reserved_ = 0, peak_ = 0;
-  std::multimap<size_t, void*> cache_;
-  std::map<void*, size_t> live_;
+  int64_t seg_allocs_ = 0;
+  std::map<char*, size_t> segs_;                  // segment base -> size
+  std::map<char*, Piece> pieces_;                 // every piece of every segment, by address
+  std::set<std::pair<size_t, char*>> free_;       // free pieces by (size, address)
   bool defer_ = false;
   std::vector<void*> deferred_;
 };

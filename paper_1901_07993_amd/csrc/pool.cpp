@@ -4,58 +4,97 @@
 namespace lif {
 
 size_t Pool::round(size_t bytes) {
-  // 256-byte granularity below 1 MiB, 1 MiB above: keeps reuse high for the
-  // repeated, similarly sized buffers of the refinement loop.
-  if (bytes < (1u << 20)) return (bytes + 255) & ~size_t(255);
-  return (bytes + (1u << 20) - 1) & ~size_t((1u << 20) - 1);
+  return (bytes + 255) & ~size_t(255);  // every buffer 256-byte aligned
+}
+
+// A new segment for at least `need` bytes: at least 64 MiB, and half of what
+// is already held (up to 16 GiB), so a growing problem needs few segments.
+bool Pool::grow(size_t need) {
+  constexpr size_t kMin = size_t(64) << 20, kMax = size_t(16) << 30, kGrain = size_t(2) << 20;
+  size_t want = std::max(need, std::min(kMax, std::max(kMin, (size_t)(reserved_ / 2))));
+  want = (want + kGrain - 1) & ~(kGrain - 1);
+  if (cap_ && reserved_ + want > cap_) want = std::max(need, (size_t)(cap_ > reserved_ ? cap_ - reserved_ : 0));
+  if (cap_ && reserved_ + want > cap_) return false;
+  void* p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    if (want == need) return false;
+    want = need;
+    if (hipMalloc(&p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+  }
+  char* base = static_cast<char*>(p);
+  segs_[base] = want;
+  pieces_[base] = Piece{want, true, base};
+  free_.insert({want, base});
+  reserved_ += want;
+  ++seg_allocs_;
+  return true;
+}
+
+// Marks the free piece `it` used for r bytes, splitting off the rest.
+void Pool::take(std::map<char*, Piece>::iterator it, size_t r) {
+  char* p = it->first;
+  Piece& pc = it->second;
+  free_.erase({pc.size, p});
+  if (pc.size > r) {
+    pieces_[p + r] = Piece{pc.size - r, true, pc.seg};
+    free_.insert({pc.size - r, p + r});
+    pc.size = r;
+  }
+  pc.free = false;
+  in_use_ += r;
+  if (in_use_ > peak_) peak_ = in_use_;
 }
 
 void* Pool::alloc(size_t bytes) {
-  size_t r = round(bytes);
-  // smallest cached buffer that fits and wastes at most a quarter
-  auto it = cache_.lower_bound(r);
-  if (it != cache_.end() && it->first <= r + r / 4) {
-    void* p = it->second;
-    r = it->first;
-    cache_.erase(it);
-    live_[p] = r;
-    in_use_ += r;
-    if (in_use_ > peak_) peak_ = in_use_;
-    return p;
-  }
-  if (cap_ && reserved_ + r > cap_) trim();
-  if (cap_ && reserved_ + r > cap_)
-    throw Error(LIF_ERR_OUT_OF_MEMORY, "device memory cap exceeded: need " + std::to_string(r) +
-                                           " more bytes with " + std::to_string(reserved_) +
-                                           " held, cap " + std::to_string(cap_));
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, r);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    trim();
-    e = hipMalloc(&p, r);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      throw Error(LIF_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(r) + " bytes failed");
+  const size_t r = round(bytes);
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    auto f = free_.lower_bound({r, nullptr});  // best fit: the smallest free piece that fits
+    if (f != free_.end()) {
+      auto it = pieces_.find(f->second);
+      take(it, r);
+      return it->first;
+    }
+    if (attempt == 0 && grow(r)) continue;
+    if (attempt == 1) {
+      trim();  // give back whole unused segments, then try once more
+      if (grow(r)) continue;
     }
   }
-  reserved_ += r;
-  live_[p] = r;
-  in_use_ += r;
-  if (in_use_ > peak_) peak_ = in_use_;
-  return p;
+  throw Error(LIF_ERR_OUT_OF_MEMORY, "device memory: cannot allocate " + std::to_string(r) + " bytes with " +
+                                         std::to_string(reserved_) + " held" +
+                                         (cap_ ? ", cap " + std::to_string(cap_) : std::string()));
 }
 
-void Pool::free(void* p) {
-  auto it = live_.find(p);
-  if (it == live_.end()) return;
+void Pool::free(void* ptr) {
+  auto it = pieces_.find(static_cast<char*>(ptr));
+  if (it == pieces_.end() || it->second.free) return;
   if (defer_) {
-    deferred_.push_back(p);
+    deferred_.push_back(ptr);
     return;
   }
-  in_use_ -= it->second;
-  cache_.emplace(it->second, p);
-  live_.erase(it);
+  in_use_ -= it->second.size;
+  it->second.free = true;
+  // merge with the free neighbours inside the same segment
+  auto next = std::next(it);
+  if (next != pieces_.end() && next->second.free && next->second.seg == it->second.seg) {
+    free_.erase({next->second.size, next->first});
+    it->second.size += next->second.size;
+    pieces_.erase(next);
+  }
+  if (it != pieces_.begin()) {
+    auto prev = std::prev(it);
+    if (prev->second.free && prev->second.seg == it->second.seg) {
+      free_.erase({prev->second.size, prev->first});
+      prev->second.size += it->second.size;
+      pieces_.erase(it);
+      it = prev;
+    }
+  }
+  free_.insert({it->second.size, it->first});
 }
 
 void Pool::release_deferred() {
@@ -67,23 +106,34 @@ void Pool::release_deferred() {
 }
 
 void Pool::trim() {
-  if (cache_.empty()) return;
-  // memory in the cache may still be read by queued kernels of the stream
-  // that freed it; wait for the device before giving it back
-  (void)hipDeviceSynchronize();
-  for (auto& kv : cache_) {
-    (void)hipFree(kv.second);
-    reserved_ -= kv.first;
+  // a free segment may still be read by queued kernels of the stream that
+  // freed its last buffer; wait for the device before giving it back
+  bool synced = false;
+  for (auto s = segs_.begin(); s != segs_.end();) {
+    auto it = pieces_.find(s->first);
+    if (it != pieces_.end() && it->second.free && it->second.size == s->second) {
+      if (!synced) {
+        (void)hipDeviceSynchronize();
+        synced = true;
+      }
+      free_.erase({it->second.size, it->first});
+      pieces_.erase(it);
+      (void)hipFree(s->first);
+      reserved_ -= s->second;
+      s = segs_.erase(s);
+    } else {
+      ++s;
+    }
   }
-  cache_.clear();
 }
 
 void Pool::release_all() {
   (void)hipDeviceSynchronize();
-  for (auto& kv : cache_) (void)hipFree(kv.second);
-  for (auto& kv : live_) (void)hipFree(kv.first);
-  cache_.clear();
-  live_.clear();
+  for (auto& kv : segs_) (void)hipFree(kv.first);
+  segs_.clear();
+  pieces_.clear();
+  free_.clear();
+  deferred_.clear();
   reserved_ = in_use_ = 0;
 }
 
