@@ -151,6 +151,15 @@ class RefineInfo:
     iterations: int = 0
     norms: list = field(default_factory=list)     # ||delta_k||_F, k = 1..iterations
     stagnated: bool = False
+    reduced: list = field(default_factory=list)   # per iteration: correction in reduced precision
+
+
+def check_divergence(k: int, e: float, e_prev: float | None) -> None:
+    """A non-finite norm, or one that grows while >= 1, means divergence."""
+    if not math.isfinite(e):
+        raise NoConvergence(f"non-finite ||delta|| at iteration {k}")
+    if e_prev is not None and e > e_prev and e >= 1.0:
+        raise NoConvergence(f"||delta|| grew from {e_prev:g} to {e:g} at iteration {k}")
 
 
 def stop_now(k: int, e: float, e_prev: float | None, m: int, stop: str, tol: float) -> bool:
@@ -162,10 +171,7 @@ def stop_now(k: int, e: float, e_prev: float | None, m: int, stop: str, tol: flo
     ||delta_k||_F <= tol, or when the norm stops decreasing.  A norm that grows
     while >= 1 means divergence.
     """
-    if not math.isfinite(e):
-        raise NoConvergence(f"non-finite ||delta|| at iteration {k}")
-    if e_prev is not None and e > e_prev and e >= 1.0:
-        raise NoConvergence(f"||delta|| grew from {e_prev:g} to {e:g} at iteration {k}")
+    check_divergence(k, e, e_prev)
     if stop == "paper":
         if e == 0.0:
             return True
@@ -178,7 +184,7 @@ def stop_now(k: int, e: float, e_prev: float | None, m: int, stop: str, tol: flo
 
 
 def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_iter=100, info=None,
-                         prec="fp64"):
+                         prec="fp64", prec_switch=0.0):
     """Localized iterative refinement (eq. refinement_local; Alg. 2 repeat loop).
 
     Each iteration, with T_k the Horner terms of sum_{k=1}^m b_k delta^k:
@@ -191,7 +197,12 @@ def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_
         delta' = delta - Z'^T SM - SM^T Z      (each product truncated;
                                                 M^T S is formed as (SM)^T)
     ``prec`` applies to the products that form M (delta T and Z q); the
-    delta-update products stay FP64.
+    delta-update products stay FP64, so delta keeps tracking I - Z^T S Z.
+    ``prec_switch`` > 0 is the precision schedule: an iteration uses ``prec``
+    only while ||delta||_F before it exceeds ``prec_switch`` and FP64 after;
+    an inexact correction converges linearly, so the stopping rule is applied
+    to the FP64 iterations only (reduced ones are checked for divergence).
+    With ``prec_switch`` = 0 every iteration uses ``prec`` and is tested.
     Returns (Z, RefineInfo).
     """
     info = info if info is not None else RefineInfo()
@@ -202,15 +213,18 @@ def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_
     if not np.any(delta):
         return Z, info
     e_prev = None
+    e_cur = float(np.sqrt(np.sum(delta * delta)))
     for k in range(1, max_iter + 1):
+        reduced = prec != "fp64" and (prec_switch == 0.0 or e_cur > prec_switch)
+        p = prec if reduced else "fp64"
         if m == 1:
             q = bk[1] * delta
         else:
             T = bk[m - 1] * I + bk[m] * delta
             for j in range(m - 2, 0, -1):
-                T = bk[j] * I + mult(delta, T, b, tau, prec)
-            q = mult(delta, T, b, tau, prec)
-        M = mult(Z, q, b, tau, prec)
+                T = bk[j] * I + mult(delta, T, b, tau, p)
+            q = mult(delta, T, b, tau, p)
+        M = mult(Z, q, b, tau, p)
         Z_new = Z + M
         SM = mult(S, M, b, tau)
         X1 = mult(Z_new.T, SM, b, tau)
@@ -219,12 +233,16 @@ def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_
         Z = Z_new
         e = float(np.sqrt(np.sum(delta * delta)))
         info.norms.append(e)
+        info.reduced.append(reduced)
         info.iterations = k
-        if stop_now(k, e, e_prev, m, stop, tol):
+        if prec_switch > 0.0 and reduced:
+            check_divergence(k, e, e_prev)
+        elif stop_now(k, e, e_prev, m, stop, tol):
             if stop == "tol" and e > tol:
                 info.stagnated = True
             return Z, info
         e_prev = e
+        e_cur = e
     raise NoConvergence(f"no convergence in {max_iter} iterations")
 
 
@@ -265,7 +283,7 @@ def nonlocal_refinement(S, Z0, b, tau, m=4, iterations=None, stop="paper", tol=0
 # ----------------------------------------------------------------------------
 
 def irsi(S, b, tau, m=4, start="sqrt2_over_gersh", start_value=None, stop="paper", tol=0.0,
-         max_iter=100, truncate_input=True, prec="fp64", refinement="local"):
+         max_iter=100, truncate_input=True, prec="fp64", refinement="local", prec_switch=0.0):
     """Iterative refinement from a scaled identity (IRSI, Sec. 2.2):
     Z_0 = c I, delta_0 = I - c^2 S (a scaling, no product), then localized
     refinement.  With ``refinement="nonlocal"`` the regular form of
@@ -282,7 +300,8 @@ def irsi(S, b, tau, m=4, start="sqrt2_over_gersh", start_value=None, stop="paper
         return Z, info, c
     assert refinement == "local", refinement
     delta0 = np.eye(n) - (c * c) * St
-    Z, info = localized_refinement(St, Z0, delta0, b, tau, m, stop, tol, max_iter, prec=prec)
+    Z, info = localized_refinement(St, Z0, delta0, b, tau, m, stop, tol, max_iter, prec=prec,
+                                   prec_switch=prec_switch)
     return Z, info, c
 
 
@@ -309,7 +328,7 @@ def lif_plan(n: int, b: int, base_rows: int) -> LifNode:
 
 
 def lif(S, b, tau, m=4, base_rows=4096, stop="paper", tol=0.0, max_iter=100, truncate_input=True,
-        plan=None, prec="fp64", refinement="local"):
+        plan=None, prec="fp64", refinement="local", prec_switch=0.0):
     """Localized inverse factorization (Alg. 2) with an inverse Cholesky leaf.
 
     For a node with children A (leading rows) and C:
@@ -351,7 +370,8 @@ def lif(S, b, tau, m=4, base_rows=4096, stop="paper", tol=0.0, max_iter=100, tru
         delta0[h:, :h] = -X.T
         node.delta0_norm2 = float(np.linalg.norm(delta0, 2)) if rows <= 4000 else float("nan")
         node.info = RefineInfo()
-        Z, _ = localized_refinement(Sn, Z0, delta0, b, tau, m, stop, tol, max_iter, node.info, prec=prec)
+        Z, _ = localized_refinement(Sn, Z0, delta0, b, tau, m, stop, tol, max_iter, node.info, prec=prec,
+                                    prec_switch=prec_switch)
         return Z
 
     return rec(plan), plan

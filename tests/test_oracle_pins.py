@@ -510,6 +510,34 @@ def test_bf16_and_fp32_rounding_by_hand():
     assert R.round_to(np.array([one]), "fp64")[0] == one
 
 
+def test_precision_schedule_reaches_fp64_floor(water100):
+    # precision schedule: reduced-precision corrections while ||delta||_F
+    # exceeds the switch, FP64 after, the paper's rule on the FP64 iterations.
+    # The result is an inverse factor at the FP64 floor, the reduced
+    # iterations are exactly those that start above the switch, and the
+    # count stays within one of the FP64 run's.
+    D, lam = water100
+    n = D.shape[0]
+    Z64, i64, c = R.irsi(D, 32, 0.0, start="inv_sqrt_lmax", start_value=lam[-1])
+    e0 = float(np.linalg.norm(np.eye(n) - c * c * D))
+    for prec, u_in in (("fp32", 2.0 ** -24), ("bf16", 2.0 ** -8)):
+        Z, info, _ = R.irsi(D, 32, 0.0, start="inv_sqrt_lmax", start_value=lam[-1], prec=prec, prec_switch=1e-2)
+        res = R.true_residual(D, Z)
+        assert res <= 1e-12 and abs(res - info.norms[-1]) <= 1e-12
+        before = [e0] + info.norms[:-1]
+        assert info.reduced == [e > 1e-2 for e in before]
+        assert any(info.reduced) and not all(info.reduced)
+        assert info.iterations <= i64.iterations + 1
+        dev = np.linalg.norm(Z - Z64) / np.linalg.norm(Z64)
+        assert dev <= 10 * u_in
+    # per LIF node as well
+    _, plan64 = R.lif(D, 32, 0.0, base_rows=128)
+    Z, plan = R.lif(D, 32, 0.0, base_rows=128, prec="bf16", prec_switch=1e-2)
+    assert R.true_residual(D, Z) <= 1e-12
+    assert any(plan.info.reduced) and not plan.info.reduced[-1]
+    assert plan.info.iterations <= plan64.info.iterations + 1
+
+
 def test_mixed_refinement_reaches_fp64_accuracy(water100):
     # the refinement wins back the accuracy lost in the correction products:
     # with FP64 delta updates the tracked delta is the true residual, and TOL
