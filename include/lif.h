@@ -102,6 +102,12 @@ typedef struct {
                            * (least memory, most redone iterations).  0: read back the
                            * counts of every product */
   int32_t refinement;     /* LIF_REFINE_LOCAL / LIF_REFINE_NONLOCAL (the latter needs prec = LIF_FP64) */
+  double prec_switch;     /* precision schedule, >= 0.  0: with a reduced prec every iteration runs its
+                           * correction in that precision and is tested by the stopping rule.  > 0: a
+                           * problem's correction runs in reduced precision only while its ||delta||_F
+                           * exceeds prec_switch, in FP64 after; such reduced iterations converge
+                           * linearly and are checked for divergence only, the stopping rule judges the
+                           * FP64 ones (so LIF_STOP_PAPER stops at the FP64 floor) */
 } lif_opts;
 
 typedef struct {
@@ -125,12 +131,13 @@ typedef struct {
                               * separate transpose and a batched leaf factorization each count one
                               * (independent problems of a level run as one batch) */
   int32_t cpl_products;      /* products on that chain */
+  int32_t iterations_reduced;/* node iterations whose correction ran in reduced precision */
 } lif_info;
 
 /* Fills *o with the defaults: m = 4, tau = 0, FP64, paper stopping rule,
  * tol = 1e-10, max_iter = 100, base_rows = 4096, start = SQRT2_OVER_GERSH,
  * checkpoint = 0, no cap, null stream, timing = 0, presize = 1,
- * refinement = LIF_REFINE_LOCAL. */
+ * refinement = LIF_REFINE_LOCAL, prec_switch = 0. */
 lif_status lif_opts_default(lif_opts* o);
 
 /* Validates S and copies it into library-owned device memory (the caller may

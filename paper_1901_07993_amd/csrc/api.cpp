@@ -41,6 +41,8 @@ void validate_opts(const lif_opts& o) {
               "opts.refinement is invalid");
   LIF_REQUIRE(o.refinement == LIF_REFINE_LOCAL || o.prec == LIF_FP64, LIF_ERR_INVALID,
               "opts.refinement = LIF_REFINE_NONLOCAL needs prec = LIF_FP64");
+  LIF_REQUIRE(std::isfinite(o.prec_switch) && o.prec_switch >= 0.0, LIF_ERR_INVALID,
+              "opts.prec_switch must be finite and >= 0");
   if (o.start == LIF_START_INV_SQRT_LMAX || o.start == LIF_START_GIVEN)
     LIF_REQUIRE(std::isfinite(o.start_value) && o.start_value > 0.0, LIF_ERR_INVALID,
                 "opts.start_value must be > 0 for this start");
@@ -157,6 +159,7 @@ void fill_info(lif_handle h, const RunInfo& ri, double seconds, lif_info* info) 
   info->products_total = h->ctx.stats.products;
   info->cpl_tasks = h->ctx.stats.cpl;
   info->cpl_products = h->ctx.stats.cpl_products;
+  info->iterations_reduced = ri.iterations_reduced;
   info->nnzb_Z = h->has_Z ? exact_nnzb(h->ctx, h->Z) : 0;
   info->n_norms = (int32_t)std::min<size_t>(64, ri.norms_top.size());
   for (int k = 0; k < info->n_norms; ++k) info->norms[k] = ri.norms_top[k];
@@ -206,6 +209,7 @@ lif_status lif_opts_default(lif_opts* o) {
   o->timing = 0;
   o->presize = 1;
   o->refinement = LIF_REFINE_LOCAL;
+  o->prec_switch = 0.0;
   return LIF_OK;
 }
 
@@ -235,6 +239,7 @@ lif_status lif_create(const lif_blocks* S, const lif_opts* o, lif_handle* out) {
     p.checkpoint = o->checkpoint != 0;
     p.presize = o->presize;
     p.refinement = o->refinement;
+    p.prec_switch = o->prec_switch;
     Ctx& c = h->ctx;
     c.stream = static_cast<hipStream_t>(o->stream);
     c.pool = &h->pool;

@@ -174,6 +174,17 @@ struct Bsr {
   // tasks (filters, truncation, compaction) pass the counts on.
   int cpl = 0;
   int cpl_products = 0;
+  // Copies of the blocks in a product input precision (FP32 or BF16), one
+  // per layout: [0] blocks as stored, [1] each block transposed.  ptr[e]
+  // is block e's copy (null where blk[e] is null).  Made on first use by a
+  // reduced-precision product, or written by the product that created the
+  // matrix; anything that moves blk drops them.
+  struct Shadow {
+    int prec = LIF_FP64;  // LIF_FP64: no copy
+    DBuf<const void*> ptr;
+    Store store;
+  };
+  mutable Shadow lp[2];
   int64_t bound() const { return nnzb >= 0 ? nnzb : cap; }
   const int* live() const { return row_ptr.get() + nb; }  // device-side count
   BlkIn ptrs() const { return blk.get(); }
@@ -451,6 +462,11 @@ struct Epilogue {
   const int* poison = nullptr;
   int* rows = nullptr;
   int nrows = 0;
+  // reduced-precision products only (nullable): the output block e is also
+  // written transposed in the input precision at lp_store + e b^2 elements,
+  // with its pointer (null for a dropped block) in lp_ptr[e]
+  void* lp_store = nullptr;
+  const void** lp_ptr = nullptr;
 };
 
 // The numeric kernels' count of output blocks to compute: *live, or none
@@ -472,9 +488,17 @@ __device__ inline int64_t live_blocks(const int* live, const Epilogue& epi) {
 void launch_numeric(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg, const BlockPair* pairs,
                     int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms, const Epilogue& epi);
 // spgemm_mixed.hip
-void launch_numeric_mixed(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg,
-                          const BlockPair* pairs, int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms,
-                          const Epilogue& epi);
+// Reduced-precision numeric phase: pairs[p].a is op(A)'s block row-major and
+// pairs[p].b op(B)'s block transposed, both in the input precision (the
+// matrices' copies, Bsr::lp).
+void launch_numeric_mixed(Ctx& c, int prec, const int64_t* seg, const BlockPair* pairs, int64_t nnzc,
+                          const int* live, int b, double* C, BlkOut Cp, double* norms, const Epilogue& epi);
+// Input-precision copies of the first *live of the n blocks blk[e]: block e
+// (FP32, or BF16 through FP32, rounded to nearest even; transposed when
+// `transposed`) at store + e b^2 elements, ptr[e] its address (null where
+// blk[e] is null).
+void launch_make_shadow(Ctx& c, int prec, bool transposed, BlkIn blk, int64_t n, const int* live, int b,
+                        void* store, const void** ptr);
 
 // chol.hip -- batched leaf inverse Cholesky on packed upper tile grids
 void launch_chol_scatter(Ctx& c, const int* row_of, const int* col, BlkIn val, int64_t nnzb, int b,
@@ -531,8 +555,15 @@ Bsr transpose(Ctx& c, const Bsr& A);
 // `in` (null entries ignored): its chain is one longer than the longest of
 // theirs (among equally long ones, the one with most products).
 void task_after(Ctx& c, Bsr& out, bool product, std::initializer_list<const Bsr*> in);
+// With prec FP32 / BF16 the operands are read from their input-precision
+// copies (made here when missing); `out_lp`: with keep_holes, the result
+// also gets its transposed copy ([1]) in that precision, for a later
+// reduced-precision product that takes it as right operand.
 Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec = LIF_FP64,
-           double alpha = 1.0, const Bsr* D = nullptr, double gamma = 0.0, bool keep_holes = false);
+           double alpha = 1.0, const Bsr* D = nullptr, double gamma = 0.0, bool keep_holes = false,
+           bool out_lp = false);
+// makes A.lp[layout] hold A's blocks in precision prec (no-op when it does)
+void ensure_shadow(Ctx& c, const Bsr& A, int prec, int layout);
 // alpha A + beta B + gamma I on the block rows with diag_on set (A or B may be null)
 Bsr axpby(Ctx& c, double alpha, const Bsr* A, double beta, const Bsr* B, double gamma,
           const unsigned char* diag_on);

@@ -26,9 +26,13 @@ std::vector<double> coefficients(int m) {
 // contraction); a non-finite norm likewise.
 enum class Step { Continue, Stop, Diverged };
 
-Step stop_decision(int k, double e, double e_prev, bool has_prev, int m, int stop, double tol, bool* stagnated) {
+// `test` false (an iteration with a reduced-precision correction under the
+// precision schedule, which converges linearly): divergence checks only.
+Step stop_decision(int k, double e, double e_prev, bool has_prev, int m, int stop, double tol, bool* stagnated,
+                   bool test) {
   if (!std::isfinite(e)) return Step::Diverged;
   if (has_prev && e > e_prev && e >= 1.0) return Step::Diverged;
+  if (!test) return Step::Continue;
   if (stop == LIF_STOP_PAPER) {
     if (e == 0.0) return Step::Stop;
     if (has_prev && e > std::pow(e_prev, m + 1)) return Step::Stop;
@@ -47,7 +51,9 @@ struct NodeState {
   bool has_prev = false;
   double e_prev = 0.0;
   double e = 0.0;
+  double e_cur = 0.0;   // ||delta||_F before the next iteration
   int iterations = 0;
+  int reduced = 0;      // iterations whose correction ran in reduced precision
   bool stagnated = false;
   std::vector<double> norms;
 };
@@ -87,8 +93,10 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
 
   {  // problems whose delta_0 is exactly zero need no iteration
     const std::vector<double> ss = ss0 ? *ss0 : node_sumsq(c, delta, d_rlo.get(), d_rhi.get(), nn);
-    for (int s = 0; s < nn; ++s)
+    for (int s = 0; s < nn; ++s) {
+      st[s].e_cur = std::sqrt(ss[s]);
       if (ss[s] == 0.0) st[s].active = false;
+    }
   }
 
   std::vector<int> rowlab(nb);
@@ -111,6 +119,14 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
   bool all_active = true;
   std::vector<std::array<int64_t, 2>> caps;  // per product of an iteration: {blocks, pairs}
   if (carry) caps = *carry;
+  // Under the precision schedule the problems of a batch may need different
+  // precisions in one iteration; the correction products then run twice, on
+  // each group's rows (the sequence of products, and so the capacities of an
+  // iteration, differs: caps_split records which sequence caps describes).
+  bool caps_split = false;
+  std::vector<char> red(nn, 0);
+  std::vector<int> lab_red(nb), lab_full(nb);
+  DBuf<int> d_lab_red, d_lab_full;
   if (!c.spec.sizes.get()) {
     c.spec.sizes = DBuf<int64_t>(c.pool, 2 * Ctx::Spec::kSlots);
     c.spec.overflow = DBuf<int>(c.pool, 1);
@@ -136,11 +152,34 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       h2d(c, d_rowlab.get(), rowlab.data(), nb);
       labels_dirty = false;
     }
+    // precision of each problem's correction in this iteration
+    int n_red = 0, n_full = 0;
+    for (int s = 0; s < nn; ++s) {
+      red[s] = 0;
+      if (!st[s].active) continue;
+      red[s] = (o.prec != LIF_FP64 && (o.prec_switch <= 0.0 || st[s].e_cur > o.prec_switch)) ? 1 : 0;
+      ++(red[s] ? n_red : n_full);
+    }
+    const bool split = n_red > 0 && n_full > 0;
+    const int prec_it = n_red > 0 ? o.prec : LIF_FP64;
+    if (split) {
+      for (int i = 0; i < nb; ++i) {
+        const int s = rowlab[i];
+        lab_red[i] = (s >= 0 && red[s]) ? s : -1;
+        lab_full[i] = (s >= 0 && !red[s]) ? s : -1;
+      }
+      if (!d_lab_red.get()) {
+        d_lab_red = DBuf<int>(c.pool, nb);
+        d_lab_full = DBuf<int>(c.pool, nb);
+      }
+      h2d(c, d_lab_red.get(), lab_red.data(), nb);
+      h2d(c, d_lab_full.get(), lab_full.data(), nb);
+    }
     // One iteration.  After the first, every product is sized from the
     // previous iteration's counts (with a margin) instead of reading its
     // counts back; the counts and an overflow flag come back with the norms.
     // If a capacity was short the iteration is redone with exact sizes.
-    bool planned = o.presize != 0 && !caps.empty();
+    bool planned = o.presize != 0 && !caps.empty() && caps_split == split;
     Bsr Znew, dnew;
     std::vector<double> ss;
     struct SpecOff {  // no sizing in advance outside this loop, also on errors
@@ -197,18 +236,40 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       // added to each output block before its truncation.  These products
       // run in the requested input precision (FP32 accumulation when
       // reduced), the delta-update below always in FP64.
-      Bsr q;
-      if (o.m == 1) {
-        q = axpby(c, bk[1], &da, 0.0, nullptr, 0.0, nullptr);
+      // the correction M on the rows of dd, with products in precision p
+      auto correction = [&](const Bsr& dd, int p) {
+        Bsr q;
+        if (o.m == 1) {
+          q = axpby(c, bk[1], &dd, 0.0, nullptr, 0.0, nullptr);
+        } else {
+          // first product: delta (b_m delta + b_{m-1} I) = b_m delta^2 + b_{m-1} delta
+          // reduced precision: each Horner term is also written as the
+          // transposed input-precision copy the next product reads
+          const bool lp_out = p != LIF_FP64;
+          Bsr X = spgemm(c, dd, false, dd, false, o.tau, p, bk[o.m], &dd, bk[o.m - 1], kHoles, lp_out);
+          for (int j = o.m - 2; j >= 1; --j)
+            X = spgemm(c, dd, false, X, false, o.tau, p, 1.0, &dd, bk[j], kHoles, lp_out);
+          q = std::move(X);
+        }
+        return spgemm(c, Z, false, q, false, o.tau, p, 1.0, nullptr, 0.0, kHoles);
+      };
+      Bsr M;
+      if (!split) {
+        M = correction(da, prec_it);
       } else {
-        // first product: delta (b_m delta + b_{m-1} I) = b_m delta^2 + b_{m-1} delta
-        Bsr X = spgemm(c, da, false, da, false, o.tau, o.prec, bk[o.m], &da, bk[o.m - 1], kHoles);
-        for (int j = o.m - 2; j >= 1; --j)
-          X = spgemm(c, da, false, X, false, o.tau, o.prec, 1.0, &da, bk[j], kHoles);
-        q = std::move(X);
+        // problems above the switch in reduced precision, the others in
+        // FP64; Z is block diagonal, so the two parts of M share no row
+        Bsr MR, MF;
+        {
+          Bsr dR = filter(c, delta, d_lab_red.get(), nullptr, 2);
+          MR = correction(dR, o.prec);
+        }
+        {
+          Bsr dF = filter(c, delta, d_lab_full.get(), nullptr, 2);
+          MF = correction(dF, LIF_FP64);
+        }
+        M = axpby(c, 1.0, &MR, 1.0, &MF, 0.0, nullptr);
       }
-      Bsr M = spgemm(c, Z, false, q, false, o.tau, o.prec, 1.0, nullptr, 0.0, kHoles);
-      q = Bsr();
       // delta_{k+1} = delta_k - Z_{k+1}^T (S M) - (S M)^T Z_k   (M^T S = (S M)^T)
       // S M and then (S M)^T Z_k run on the side stream while Z + M and then
       // Z_{k+1}^T (S M) run on the main one; buffers freed meanwhile are
@@ -280,7 +341,8 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
     // into one array (counts are known here: no extra read-back)
     if (Znew.store_blocks() > 3 * Znew.nnzb + 64) Znew = compact_values(c, std::move(Znew));
     if (dnew.store_blocks() > 3 * dnew.nnzb + 64) dnew = compact_values(c, std::move(dnew));
-    if (carry) *carry = caps;
+    caps_split = split;
+    if (carry && !split) *carry = caps;
     if (ck) ck->push_back(std::move(Z));  // Z_k is immutable: keep it, no copy
     Z = std::move(Znew);
     delta = std::move(dnew);
@@ -291,7 +353,10 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       const double e = std::sqrt(ss[s]);
       ns.iterations = k;
       ns.norms.push_back(e);
-      const Step d = stop_decision(k, e, ns.e_prev, ns.has_prev, o.m, o.stop, o.tol, &ns.stagnated);
+      if (red[s]) ++ns.reduced;
+      const bool tested = !(o.prec_switch > 0.0 && red[s]);
+      const Step d = stop_decision(k, e, ns.e_prev, ns.has_prev, o.m, o.stop, o.tol, &ns.stagnated, tested);
+      ns.e_cur = e;
       if (d == Step::Diverged)
         throw Error(LIF_ERR_NO_CONVERGENCE, "refinement diverged: ||delta||_F = " + std::to_string(e) +
                                                 " at iteration " + std::to_string(k) + " of problem " +
@@ -386,6 +451,7 @@ Bsr run_irsi(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck
   }
   info.iterations_top = st[0].iterations;
   info.iterations_total = st[0].iterations;
+  info.iterations_reduced = st[0].reduced;
   info.stagnated = st[0].stagnated;
   info.delta_top = st[0].e;
   info.norms_top = st[0].norms;
@@ -412,6 +478,7 @@ Bsr run_refine_from(Ctx& c, const Bsr& S, Bsr&& Z0, const Opts& o, RunInfo& info
   refine_batch(c, S, Z, std::move(delta), bt, o, st, o.max_iter);
   info.iterations_top = st[0].iterations;
   info.iterations_total = st[0].iterations;
+  info.iterations_reduced = st[0].reduced;
   info.stagnated = st[0].stagnated;
   info.delta_top = st[0].e;
   info.norms_top = st[0].norms;
@@ -745,7 +812,10 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck)
       L->S_lvl = std::move(S_lvl);
     }
     info.levels += 1;
-    for (auto& ns : st) info.iterations_total += ns.iterations;
+    for (auto& ns : st) {
+      info.iterations_total += ns.iterations;
+      info.iterations_reduced += ns.reduced;
+    }
     if (d == 0) {
       info.iterations_top = st[0].iterations;
       info.stagnated = st[0].stagnated;

@@ -20,6 +20,7 @@ struct Opts {
   bool checkpoint = false;
   int presize = 1;  // 0 off, 1 with margins, 2 previous counts as they are
   int refinement = LIF_REFINE_LOCAL;
+  double prec_switch = 0.0;  // > 0: reduced precision only while ||delta||_F exceeds it
 };
 
 // One node of the split tree: scalar rows [lo, hi), lo a multiple of b.
@@ -46,6 +47,7 @@ struct RunInfo {
   double start_scale = 0.0;
   double delta_top = 0.0;
   std::vector<double> norms_top;
+  int iterations_reduced = 0;  // node iterations with a reduced-precision correction
 };
 
 // Per-iteration checkpoints of a forward run, for the reverse sweep.

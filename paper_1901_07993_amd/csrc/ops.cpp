@@ -62,7 +62,21 @@ Bsr compact_values(Ctx& c, Bsr&& A) {
   launch_gather_values(c, A.ptrs(), nnz, A.b, st->get(), nullptr);
   launch_fill_ptrs(c, A.blk.get(), st->get(), A.b, nnz);
   A.store.assign(1, st);
+  A.lp[0] = Bsr::Shadow();  // the copies point at the old blocks' places
+  A.lp[1] = Bsr::Shadow();
   return std::move(A);
+}
+
+void ensure_shadow(Ctx& c, const Bsr& A, int prec, int layout) {
+  Bsr::Shadow& s = A.lp[layout];
+  if (s.prec == prec) return;
+  s = Bsr::Shadow();
+  const int64_t n = A.bound();
+  const size_t bytes = (size_t)n * A.b * A.b * (prec == LIF_MIXED_BF16 ? 2 : 4);
+  s.store = std::make_shared<DBuf<double>>(c.pool, (bytes + 7) / 8);
+  s.ptr = DBuf<const void*>(c.pool, (size_t)n);
+  launch_make_shadow(c, prec, layout == 1, A.ptrs(), n, A.live(), A.b, s.store->get(), s.ptr.get());
+  s.prec = prec;
 }
 
 int64_t exact_nnzb(Ctx& c, const Bsr& A) {
@@ -218,7 +232,8 @@ namespace {
 // built: values, norms, truncation (or holes).
 // `poison` (nullable): the flag that voids the product (Epilogue).
 Bsr numeric_phase(Ctx& c, Bsr&& C, bool ta, bool tb, double tau, int prec, double alpha, BlkIn dsrc, double gamma,
-                  bool keep_holes, const int64_t* seg, const BlockPair* pairs, int64_t nnzc, const int* poison) {
+                  bool keep_holes, const int64_t* seg, const BlockPair* pairs, int64_t nnzc, const int* poison,
+                  bool out_lp) {
   const int nb = C.nb;
   Store st = new_store(c, nnzc, C.b);
   C.blk = DBuf<const double*>(c.pool, (size_t)nnzc);
@@ -230,6 +245,16 @@ Bsr numeric_phase(Ctx& c, Bsr&& C, bool ta, bool tb, double tau, int prec, doubl
   epi.poison = poison;
   epi.rows = C.row_ptr.get();
   epi.nrows = nb;
+  if (out_lp && keep_holes && prec != LIF_FP64 && nnzc > 0) {
+    // the result's transposed input-precision copy, written with its blocks
+    Bsr::Shadow& sh = C.lp[1];
+    const size_t bytes = (size_t)nnzc * C.b * C.b * (prec == LIF_MIXED_BF16 ? 2 : 4);
+    sh.store = std::make_shared<DBuf<double>>(c.pool, (bytes + 7) / 8);
+    sh.ptr = DBuf<const void*>(c.pool, (size_t)nnzc);
+    sh.prec = prec;
+    epi.lp_store = sh.store->get();
+    epi.lp_ptr = sh.ptr.get();
+  }
   if (keep_holes && tau > 0.0) {  // truncation by null pointers, no compaction
     epi.drop = true;
     epi.tau = tau;
@@ -249,8 +274,19 @@ Bsr numeric_phase(Ctx& c, Bsr&& C, bool ta, bool tb, double tau, int prec, doubl
 namespace {
 
 Bsr spgemm_body(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec, double alpha,
-                const Bsr* D, double gamma, bool keep_holes) {
+                const Bsr* D, double gamma, bool keep_holes, bool out_lp) {
   LIF_REQUIRE(A.nb == B.nb && A.b == B.b, LIF_ERR_INVALID, "spgemm: operand shapes differ");
+  // block pointers the pairs are built from: the FP64 blocks, or for a
+  // reduced-precision product op(A)'s blocks row-major and op(B)'s blocks
+  // transposed in the input precision
+  BlkIn pa = A.ptrs(), pb = B.ptrs();
+  if (prec != LIF_FP64) {
+    const int la = ta ? 1 : 0, lb = tb ? 0 : 1;
+    ensure_shadow(c, A, prec, la);
+    ensure_shadow(c, B, prec, lb);
+    pa = reinterpret_cast<BlkIn>(A.lp[la].ptr.get());
+    pb = reinterpret_cast<BlkIn>(B.lp[lb].ptr.get());
+  }
   LIF_REQUIRE(!D || !D->holes, LIF_ERR_INVALID, "spgemm: the added term has holes");
   const int nb = A.nb;
   Bsr C = like(A);
@@ -291,17 +327,17 @@ Bsr spgemm_body(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau
     c.spec.prec.push_back(prec);
     C.nnzb = -1;
     alloc_outputs();
-    launch_symbolic_onepass(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, A.ptrs(), B.ptrs(), A.holes, B.holes,
+    launch_symbolic_onepass(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, pa, pb, A.holes, B.holes,
                             drp, dcol, D ? D->ptrs() : nullptr, nb, nnzc, P, C.row_ptr.get(), C.col.get(),
                             seg.get(), pairs.get(), D ? dsrc.get() : nullptr, c.spec.sizes.get() + 2 * slot,
                             c.spec.overflow.get());
     return numeric_phase(c, std::move(C), ta, tb, tau, prec, alpha, D ? dsrc.get() : nullptr, gamma, keep_holes,
-                         seg.get(), pairs.get(), nnzc, c.spec.overflow.get());
+                         seg.get(), pairs.get(), nnzc, c.spec.overflow.get(), out_lp);
   }
   DBuf<int> cnt_c(c.pool, nb);
   DBuf<int64_t> cnt_p(c.pool, nb);
-  launch_symbolic_count(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, A.holes ? A.ptrs() : nullptr,
-                        B.holes ? B.ptrs() : nullptr, drp, dcol, nb, cnt_c.get(), cnt_p.get());
+  launch_symbolic_count(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, A.holes ? pa : nullptr,
+                        B.holes ? pb : nullptr, drp, dcol, nb, cnt_c.get(), cnt_p.get());
   prp = DBuf<int64_t>(c.pool, nb + 1);
   if (planned) {
     const size_t slot = c.spec.next++;
@@ -334,18 +370,18 @@ Bsr spgemm_body(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau
   }
   alloc_outputs();
   if (nnzc)
-    launch_symbolic_fill(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, A.ptrs(), B.ptrs(), A.holes, B.holes,
+    launch_symbolic_fill(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, pa, pb, A.holes, B.holes,
                          drp, dcol, D ? D->ptrs() : nullptr, nb, C.row_ptr.get(), prp.get(), C.col.get(), seg.get(),
                          pairs.get(), D ? dsrc.get() : nullptr);
   return numeric_phase(c, std::move(C), ta, tb, tau, prec, alpha, D ? dsrc.get() : nullptr, gamma, keep_holes,
-                       seg.get(), pairs.get(), nnzc, nullptr);
+                       seg.get(), pairs.get(), nnzc, nullptr, out_lp);
 }
 
 }  // namespace
 
 Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec, double alpha,
-           const Bsr* D, double gamma, bool keep_holes) {
-  Bsr C = spgemm_body(c, A, ta, B, tb, tau, prec, alpha, D, gamma, keep_holes);
+           const Bsr* D, double gamma, bool keep_holes, bool out_lp) {
+  Bsr C = spgemm_body(c, A, ta, B, tb, tau, prec, alpha, D, gamma, keep_holes, out_lp);
   // with an operand known to be empty only the scaled added term remains
   const bool scaling = A.nnzb == 0 || B.nnzb == 0;
   task_after(c, C, !scaling, {&A, &B, D});

@@ -732,7 +732,7 @@ void launch_numeric(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg, cons
     LIF_HIP(hipEventRecord(e0, c.stream));
   }
   if (prec != LIF_FP64)
-    launch_numeric_mixed(c, prec, ta, tb, seg, pairs, nnzc, live, b, C, Cp, norms, epi);
+    launch_numeric_mixed(c, prec, seg, pairs, nnzc, live, b, C, Cp, norms, epi);
   else if (b == 64)
     launch_numeric_b<64>(c, ta, tb, seg, pairs, nnzc, live, C, Cp, norms, epi);
   else

@@ -1,18 +1,26 @@
 // Numeric phase of the block-sparse product in reduced input precision with
-// FP32 accumulation (the precision form of the correction products): the
-// FP64 operand blocks are rounded while they are staged into LDS, the
-// products of one output block accumulate in FP32 MFMA registers, and the
-// block is written back as FP64 together with its FP64 Frobenius norm.
+// FP32 accumulation (the precision form of the correction products), and the
+// reduced-precision copies of the operand blocks it reads.
 //
-//   FP32:  inputs rounded to FP32 (round to nearest even), v_mfma_f32_16x16x4f32,
-//          operands k-major in LDS as in the FP64 kernel.
-//   BF16:  inputs rounded FP64 -> FP32 -> BF16 (both round to nearest even),
-//          v_mfma_f32_16x16x32_bf16; A staged row-major (row i holds A[i][k],
-//          k contiguous) and B column-major (row j holds B[k][j] over k), so
-//          each lane's 8 consecutive k values are one 16-byte LDS read.
-// Fragment layouts (checked on the GPU): FP32 A lane l holds A[l%16][l/16],
-// B lane l holds B[l/16][l%16]; BF16 A lane l holds A[l%16][8(l/16)+v],
-// B lane l holds B[8(l/16)+v][l%16], v = 0..7; both accumulate
+// Operands are never rounded inside the product: every matrix that enters
+// one carries a copy of its blocks in the input precision (FP32, or BF16
+// through FP32, both rounded to nearest even), made once per matrix by
+// k_make_shadow or written by the product that created the matrix.  The
+// copies hold op(A)'s blocks row-major and op(B)'s blocks transposed, so
+// that every MFMA fragment below is one 16-byte global load of consecutive
+// k (no LDS staging): a quarter of the FP64 operand bytes for BF16, half for
+// FP32.  The products of one output block accumulate in FP32 MFMA
+// registers; the block is written back as FP64 with its FP64 Frobenius norm
+// (and, when asked, as the transposed reduced-precision copy the next
+// product reads).
+//
+//   FP32: v_mfma_f32_16x16x4f32; in k-block kb (16 values of k) lane group
+//         g = l/16 supplies k = 16 kb + 4 g + t in step t = 0..3.
+//   BF16: v_mfma_f32_16x16x32_bf16; lane group g supplies k = 32 ks + 8 g + v,
+//         v = 0..7, in k-step ks.
+// Fragment layouts (checked on the GPU): FP32 A lane l holds A[l%16][k of
+// its group], B lane l holds B[k of its group][l%16]; BF16 A lane l holds
+// A[l%16][8(l/16)+v], B lane l holds B[8(l/16)+v][l%16]; both accumulate
 // D[4(l/16)+r][l%16], r = 0..3.
 #include "common.h"
 #include "tile_mma.h"
@@ -41,69 +49,60 @@ template <int B>
 struct MixCfg {
   static constexpr int WAVES = (B / 32) * (B / 32);
   static constexpr int THREADS = 64 * WAVES;
-  static constexpr int V2 = B * B / 2 / THREADS;
-  static constexpr int LDF = B + 4;   // FP32 LDS row stride (floats)
-  static constexpr int LDH = B + 8;   // BF16 LDS row stride (halves), rows 16-byte aligned
 };
 
-// FP32 staging, k-major: direct -> LDS row r holds global row r.
-template <int B>
-__device__ inline void store_f32(float* __restrict__ s, const v2d* reg, bool direct) {
-  using Cfg = MixCfg<B>;
-#pragma unroll
-  for (int v = 0; v < Cfg::V2; ++v) {
-    const int q = 2 * (threadIdx.x + v * Cfg::THREADS);
-    const int r = q / B, c = q % B;
-    const float x = (float)reg[v].x, y = (float)reg[v].y;
-    if (direct) {
-      *reinterpret_cast<float2*>(s + r * Cfg::LDF + c) = make_float2(x, y);
-    } else {
-      s[c * Cfg::LDF + r] = x;
-      s[(c + 1) * Cfg::LDF + r] = y;
-    }
-  }
-}
-
-// BF16 staging: direct -> LDS row r holds global row r, else row c holds column c.
-template <int B>
-__device__ inline void store_bf16(unsigned short* __restrict__ s, const v2d* reg, bool direct) {
-  using Cfg = MixCfg<B>;
-#pragma unroll
-  for (int v = 0; v < Cfg::V2; ++v) {
-    const int q = 2 * (threadIdx.x + v * Cfg::THREADS);
-    const int r = q / B, c = q % B;
-    const unsigned short x = bf16_bits_rne((float)reg[v].x), y = bf16_bits_rne((float)reg[v].y);
-    if (direct) {
-      *reinterpret_cast<unsigned*>(s + r * Cfg::LDH + c) = (unsigned)x | ((unsigned)y << 16);
-    } else {
-      s[c * Cfg::LDH + r] = x;
-      s[(c + 1) * Cfg::LDH + r] = y;
-    }
-  }
-}
+template <int PREC>
+struct Lp;
+template <>
+struct Lp<LIF_MIXED_FP32> {
+  typedef float T;
+  __device__ static T round(double v) { return (float)v; }
+};
+template <>
+struct Lp<LIF_MIXED_BF16> {
+  typedef unsigned short T;
+  __device__ static T round(double v) { return bf16_bits_rne((float)v); }
+};
 
 // The block alpha A B + gamma D (Epilogue; FP64 from the FP32 accumulators),
-// its FP64 sum of squares in a fixed order, its norm and its pointer.
-template <int B>
+// its FP64 sum of squares in a fixed order, its norm and its pointer; with
+// OUT_LP also its transposed reduced-precision copy and that copy's pointer.
+template <int B, int PREC, bool OUT_LP>
 __device__ inline void epilogue(const v4f (&acc)[2][2], int rb, int cb, int l16, int kq, int lane, int wave,
                                 int64_t blk, double* __restrict__ C, BlkOut Cp, double* red,
                                 double* __restrict__ norms, const Epilogue& epi) {
   using Cfg = MixCfg<B>;
+  typedef typename Lp<PREC>::T T;
   const double* Db = epi.dsrc ? epi.dsrc[blk] : nullptr;
   double* Cb = C + blk * B * B;
+  T* Lb = OUT_LP ? static_cast<T*>(epi.lp_store) + blk * B * B : nullptr;
   double ss = 0.0;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
+    for (int tj = 0; tj < 2; ++tj) {
+      const int col = cb + 16 * tj + l16, row0 = rb + 16 * ti + 4 * kq;
+      T lv[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int idx = (rb + 16 * ti + 4 * kq + r) * B + cb + 16 * tj + l16;
+        const int idx = (row0 + r) * B + col;
         double v = epi.alpha * (double)acc[ti][tj][r];
         if (Db) v += epi.gamma * gptr(Db)[idx];
         Cb[idx] = v;
         ss += v * v;
+        lv[r] = Lp<PREC>::round(v);
       }
+      if (OUT_LP) {  // transposed: the four rows of this lane are consecutive
+        T* q = Lb + col * B + row0;
+        if (PREC == LIF_MIXED_BF16) {
+          const unsigned lo = (unsigned)lv[0] | ((unsigned)lv[1] << 16);
+          const unsigned hi = (unsigned)lv[2] | ((unsigned)lv[3] << 16);
+          *reinterpret_cast<uint2*>(q) = make_uint2(lo, hi);
+        } else {
+          *reinterpret_cast<float4*>(q) = make_float4(lv[0], lv[1], lv[2], lv[3]);
+        }
+      }
+    }
   for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
   if (lane == 0) red[wave] = ss;
   __syncthreads();
@@ -113,78 +112,23 @@ __device__ inline void epilogue(const v4f (&acc)[2][2], int rb, int cb, int l16,
     for (int w = 0; w < Cfg::WAVES; ++w) t += red[w];
     const double nrm = sqrt(t);
     if (norms) norms[blk] = nrm;
-    Cp[blk] = (epi.drop && !(nrm >= epi.tau)) ? nullptr : Cb;
+    const bool keep = !(epi.drop && !(nrm >= epi.tau));
+    Cp[blk] = keep ? Cb : nullptr;
+    if (OUT_LP) epi.lp_ptr[blk] = keep ? static_cast<const void*>(Lb) : nullptr;
   }
 }
 
-template <int B, bool TA, bool TB>
-__global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(
-                                                                    const int64_t* __restrict__ seg,
-                                                                    const BlockPair* __restrict__ pairs,
-                                                                    const int* __restrict__ live,
-                                                                    double* __restrict__ C, BlkOut Cp,
-                                                                    double* __restrict__ norms, Epilogue epi) {
-  using Cfg = MixCfg<B>;
-  __shared__ float As[B * Cfg::LDF];
-  __shared__ float Bs[B * Cfg::LDF];
-  __shared__ double red[Cfg::WAVES];
-  // the grid may exceed the live output count (capacity fixed before the
-  // count was known); the XCD remap runs over the live blocks only
-  const int64_t nlive = live_blocks(live, epi);
-  if ((int64_t)blockIdx.x >= nlive) return;
-  const int64_t blk = xcd_remap_m(blockIdx.x, nlive);
-  const int64_t p0 = seg[blk], p1 = seg[blk + 1];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int rb = 32 * (wave / (B / 32)), cb = 32 * (wave % (B / 32));
-  const int l16 = lane & 15, kq = lane >> 4;
-  v4f acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-  v2d ra[Cfg::V2], rbv[Cfg::V2];
-  if (p1 > p0) {  // a diagonal block of a fused identity term may have no products
-    const BlockPair pr = pairs[p0];
-    tile_load<B>(pr.a, ra);
-    tile_load<B>(pr.b, rbv);
-  }
-  for (int64_t p = p0; p < p1; ++p) {
-    __syncthreads();
-    store_f32<B>(As, ra, TA);    // As[k][i] = op(A)[i][k]
-    store_f32<B>(Bs, rbv, !TB);  // Bs[k][j] = op(B)[k][j]
-    __syncthreads();
-    if (p + 1 < p1) {
-      const BlockPair pr = pairs[p + 1];
-      tile_load<B>(pr.a, ra);
-      tile_load<B>(pr.b, rbv);
-    }
-#pragma unroll 4
-    for (int kk = 0; kk < B / 4; ++kk) {
-      const int k = 4 * kk + kq;
-      const float a0 = As[k * Cfg::LDF + rb + l16];
-      const float a1 = As[k * Cfg::LDF + rb + 16 + l16];
-      const float b0 = Bs[k * Cfg::LDF + cb + l16];
-      const float b1 = Bs[k * Cfg::LDF + cb + 16 + l16];
-      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
-    }
-  }
-  epilogue<B>(acc, rb, cb, l16, kq, lane, wave, blk, C, Cp, red, norms, epi);
-}
-
-template <int B, bool TA, bool TB>
-__global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(
-                                                                     const int64_t* __restrict__ seg,
+// One workgroup per output block; pair p gives op(A)'s block row-major
+// (pairs[p].a) and op(B)'s block transposed (pairs[p].b), both in the input
+// precision.  Each wave computes a 32 x 32 quadrant as 2 x 2 MFMA tiles.
+template <int B, bool OUT_LP>
+__global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(const int64_t* __restrict__ seg,
                                                                      const BlockPair* __restrict__ pairs,
                                                                      const int* __restrict__ live,
                                                                      double* __restrict__ C, BlkOut Cp,
                                                                      double* __restrict__ norms, Epilogue epi) {
-  using Cfg = MixCfg<B>;
-  __shared__ __attribute__((aligned(16))) unsigned short As[B * Cfg::LDH];  // As[i][k]
-  __shared__ __attribute__((aligned(16))) unsigned short Bs[B * Cfg::LDH];  // Bs[j][k]
-  __shared__ double red[Cfg::WAVES];
+  constexpr int KS = B / 32;
+  __shared__ double red[MixCfg<B>::WAVES];
   // the grid may exceed the live output count (capacity fixed before the
   // count was known); the XCD remap runs over the live blocks only
   const int64_t nlive = live_blocks(live, epi);
@@ -199,66 +143,169 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-  v2d ra[Cfg::V2], rbv[Cfg::V2];
-  if (p1 > p0) {  // a diagonal block of a fused identity term may have no products
-    const BlockPair pr = pairs[p0];
-    tile_load<B>(pr.a, ra);
-    tile_load<B>(pr.b, rbv);
-  }
   for (int64_t p = p0; p < p1; ++p) {
-    __syncthreads();
-    store_bf16<B>(As, ra, !TA);  // As[i][k] = op(A)[i][k]
-    store_bf16<B>(Bs, rbv, TB);  // Bs[j][k] = op(B)[k][j]
-    __syncthreads();
-    if (p + 1 < p1) {
-      const BlockPair pr = pairs[p + 1];
-      tile_load<B>(pr.a, ra);
-      tile_load<B>(pr.b, rbv);
-    }
+    const BlockPair pr = pairs[p];
+    const unsigned short* a = reinterpret_cast<const unsigned short*>(pr.a);
+    const unsigned short* bt = reinterpret_cast<const unsigned short*>(pr.b);
+    v8bf af[KS][2], bf[KS][2];
 #pragma unroll
-    for (int kk = 0; kk < B / 32; ++kk) {
-      const int k0 = 32 * kk + 8 * kq;
-      const v8bf a0 = *reinterpret_cast<const v8bf*>(As + (rb + l16) * Cfg::LDH + k0);
-      const v8bf a1 = *reinterpret_cast<const v8bf*>(As + (rb + 16 + l16) * Cfg::LDH + k0);
-      const v8bf b0 = *reinterpret_cast<const v8bf*>(Bs + (cb + l16) * Cfg::LDH + k0);
-      const v8bf b1 = *reinterpret_cast<const v8bf*>(Bs + (cb + 16 + l16) * Cfg::LDH + k0);
-      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int k0 = 32 * ks + 8 * kq;
+        af[ks][t] = *gptr(reinterpret_cast<const v8bf*>(a + (rb + 16 * t + l16) * B + k0));
+        bf[ks][t] = *gptr(reinterpret_cast<const v8bf*>(bt + (cb + 16 * t + l16) * B + k0));
+      }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][0], bf[ks][0], acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][0], bf[ks][1], acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][1], bf[ks][0], acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][1], bf[ks][1], acc[1][1], 0, 0, 0);
     }
   }
-  epilogue<B>(acc, rb, cb, l16, kq, lane, wave, blk, C, Cp, red, norms, epi);
+  epilogue<B, LIF_MIXED_BF16, OUT_LP>(acc, rb, cb, l16, kq, lane, wave, blk, C, Cp, red, norms, epi);
 }
 
-#define LIF_MIXED_DISPATCH(KERNEL, B)                                                                      \
-  do {                                                                                                     \
-    dim3 grid((unsigned)nnzc), block(MixCfg<B>::THREADS);                                                  \
-    if (!ta && !tb)                                                                                        \
-      hipLaunchKernelGGL((KERNEL<B, false, false>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms, epi); \
-    else if (ta && !tb)                                                                                    \
-      hipLaunchKernelGGL((KERNEL<B, true, false>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms, epi); \
-    else if (!ta && tb)                                                                                    \
-      hipLaunchKernelGGL((KERNEL<B, false, true>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms, epi); \
-    else                                                                                                   \
-      hipLaunchKernelGGL((KERNEL<B, true, true>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms, epi); \
-  } while (0)
+template <int B, bool OUT_LP>
+__global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(const int64_t* __restrict__ seg,
+                                                                    const BlockPair* __restrict__ pairs,
+                                                                    const int* __restrict__ live,
+                                                                    double* __restrict__ C, BlkOut Cp,
+                                                                    double* __restrict__ norms, Epilogue epi) {
+  constexpr int KB = B / 16;
+  __shared__ double red[MixCfg<B>::WAVES];
+  const int64_t nlive = live_blocks(live, epi);
+  if ((int64_t)blockIdx.x >= nlive) return;
+  const int64_t blk = xcd_remap_m(blockIdx.x, nlive);
+  const int64_t p0 = seg[blk], p1 = seg[blk + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rb = 32 * (wave / (B / 32)), cb = 32 * (wave % (B / 32));
+  const int l16 = lane & 15, kq = lane >> 4;
+  v4f acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int64_t p = p0; p < p1; ++p) {
+    const BlockPair pr = pairs[p];
+    const float* a = reinterpret_cast<const float*>(pr.a);
+    const float* bt = reinterpret_cast<const float*>(pr.b);
+    v4f af[KB][2], bf[KB][2];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int k0 = 16 * kb + 4 * kq;
+        af[kb][t] = *gptr(reinterpret_cast<const v4f*>(a + (rb + 16 * t + l16) * B + k0));
+        bf[kb][t] = *gptr(reinterpret_cast<const v4f*>(bt + (cb + 16 * t + l16) * B + k0));
+      }
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[kb][0][s], bf[kb][0][s], acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[kb][0][s], bf[kb][1][s], acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[kb][1][s], bf[kb][0][s], acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[kb][1][s], bf[kb][1][s], acc[1][1], 0, 0, 0);
+      }
+  }
+  epilogue<B, LIF_MIXED_FP32, OUT_LP>(acc, rb, cb, l16, kq, lane, wave, blk, C, Cp, red, norms, epi);
+}
+
+// Reduced-precision copy of block e of blk (one workgroup per block, the
+// first *live entries): row-major, or transposed through LDS.
+template <int B, int PREC, bool TRANS>
+__global__ __launch_bounds__(256) void k_make_shadow(BlkIn blk, const int* __restrict__ live,
+                                                     typename Lp<PREC>::T* __restrict__ store,
+                                                     const void** __restrict__ ptr) {
+  typedef typename Lp<PREC>::T T;
+  __shared__ T tile[TRANS ? B * (B + 1) : 1];
+  const int64_t e = blockIdx.x;
+  if (e >= (int64_t)*live) return;
+  const double* src = blk[e];
+  if (!src) {
+    if (threadIdx.x == 0) ptr[e] = nullptr;
+    return;
+  }
+  T* dst = store + e * B * B;
+  const auto* s2 = gptr(reinterpret_cast<const v2d*>(src));
+  for (int q = threadIdx.x; q < B * B / 2; q += 256) {
+    const v2d v = s2[q];
+    const int i = (2 * q) / B, j = (2 * q) % B;
+    if (TRANS) {
+      tile[i * (B + 1) + j] = Lp<PREC>::round(v.x);
+      tile[i * (B + 1) + j + 1] = Lp<PREC>::round(v.y);
+    } else {
+      dst[2 * q] = Lp<PREC>::round(v.x);
+      dst[2 * q + 1] = Lp<PREC>::round(v.y);
+    }
+  }
+  if (TRANS) {
+    __syncthreads();
+    for (int q = threadIdx.x; q < B * B; q += 256) {
+      const int j = q / B, i = q % B;  // dst row j holds column j of the block
+      dst[q] = tile[i * (B + 1) + j];
+    }
+  }
+  if (threadIdx.x == 0) ptr[e] = dst;
+}
+
+template <int B, int PREC>
+void make_shadow_b(Ctx& c, bool transposed, BlkIn blk, int64_t n, const int* live, void* store,
+                   const void** ptr) {
+  typedef typename Lp<PREC>::T T;
+  if (transposed)
+    hipLaunchKernelGGL((k_make_shadow<B, PREC, true>), dim3((unsigned)n), dim3(256), 0, c.stream, blk, live,
+                       static_cast<T*>(store), ptr);
+  else
+    hipLaunchKernelGGL((k_make_shadow<B, PREC, false>), dim3((unsigned)n), dim3(256), 0, c.stream, blk, live,
+                       static_cast<T*>(store), ptr);
+}
+
+template <int B>
+void launch_mixed_b(Ctx& c, int prec, const int64_t* seg, const BlockPair* pairs, int64_t nnzc, const int* live,
+                    double* C, BlkOut Cp, double* norms, const Epilogue& epi) {
+  const dim3 grid((unsigned)nnzc), block(MixCfg<B>::THREADS);
+  const bool out_lp = epi.lp_store != nullptr;
+  if (prec == LIF_MIXED_FP32) {
+    if (out_lp)
+      hipLaunchKernelGGL((k_numeric_f32<B, true>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms, epi);
+    else
+      hipLaunchKernelGGL((k_numeric_f32<B, false>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms, epi);
+  } else {
+    if (out_lp)
+      hipLaunchKernelGGL((k_numeric_bf16<B, true>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms, epi);
+    else
+      hipLaunchKernelGGL((k_numeric_bf16<B, false>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms, epi);
+  }
+}
 
 }  // namespace
 
-void launch_numeric_mixed(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg,
-                          const BlockPair* pairs, int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms,
-                          const Epilogue& epi) {
+void launch_numeric_mixed(Ctx& c, int prec, const int64_t* seg, const BlockPair* pairs, int64_t nnzc,
+                          const int* live, int b, double* C, BlkOut Cp, double* norms, const Epilogue& epi) {
+  LIF_REQUIRE(prec == LIF_MIXED_FP32 || prec == LIF_MIXED_BF16, LIF_ERR_INVALID, "mixed product: precision");
+  if (b == 64)
+    launch_mixed_b<64>(c, prec, seg, pairs, nnzc, live, C, Cp, norms, epi);
+  else
+    launch_mixed_b<32>(c, prec, seg, pairs, nnzc, live, C, Cp, norms, epi);
+  LIF_HIP(hipGetLastError());
+}
+
+void launch_make_shadow(Ctx& c, int prec, bool transposed, BlkIn blk, int64_t n, const int* live, int b,
+                        void* store, const void** ptr) {
+  if (n == 0) return;
   if (prec == LIF_MIXED_FP32) {
     if (b == 64)
-      LIF_MIXED_DISPATCH(k_numeric_f32, 64);
+      make_shadow_b<64, LIF_MIXED_FP32>(c, transposed, blk, n, live, store, ptr);
     else
-      LIF_MIXED_DISPATCH(k_numeric_f32, 32);
+      make_shadow_b<32, LIF_MIXED_FP32>(c, transposed, blk, n, live, store, ptr);
   } else {
     if (b == 64)
-      LIF_MIXED_DISPATCH(k_numeric_bf16, 64);
+      make_shadow_b<64, LIF_MIXED_BF16>(c, transposed, blk, n, live, store, ptr);
     else
-      LIF_MIXED_DISPATCH(k_numeric_bf16, 32);
+      make_shadow_b<32, LIF_MIXED_BF16>(c, transposed, blk, n, live, store, ptr);
   }
   LIF_HIP(hipGetLastError());
 }

@@ -46,7 +46,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("m", c_int32), ("tau", c_double), ("prec", c_int32), ("stop", c_int32), ("tol", c_double),
                 ("max_iter", c_int32), ("base_rows", c_int64), ("start", c_int32), ("start_value", c_double),
                 ("checkpoint", c_int32), ("mem_cap_bytes", c_uint64), ("stream", c_void_p), ("timing", c_int32),
-                ("presize", c_int32), ("refinement", c_int32)]
+                ("presize", c_int32), ("refinement", c_int32), ("prec_switch", c_double)]
 
 
 class Info(ctypes.Structure):
@@ -55,7 +55,7 @@ class Info(ctypes.Structure):
                 ("flops_leaf_gemm", c_double), ("seconds_total", c_double), ("seconds_leaf_gemm", c_double),
                 ("leaf_gemm_launches", c_int64), ("products_total", c_int64), ("nnzb_Z", c_int64),
                 ("n_norms", c_int32), ("norms", c_double * 64), ("iterations_redone", c_int32),
-                ("cpl_tasks", c_int32), ("cpl_products", c_int32)]
+                ("cpl_tasks", c_int32), ("cpl_products", c_int32), ("iterations_reduced", c_int32)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "norms"}
@@ -162,7 +162,7 @@ class Factorization:
 
     Keyword options mirror ``lif_opts``: m, tau, prec, stop, tol, max_iter,
     base_rows, start, start_value, checkpoint, mem_cap_bytes, timing, presize,
-    refinement.
+    refinement, prec_switch.
     """
 
     def __init__(self, S, **opts):

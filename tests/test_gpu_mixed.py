@@ -89,3 +89,64 @@ def test_mixed_lif_water(prec):
     Z64, _ = R.lif(D, 64, 0.0, base_rows=320, stop="tol", tol=1e-10)
     assert res <= 1e-10
     assert np.linalg.norm(Z - Z64) <= 10 * U_IN[prec] * np.linalg.norm(Z64)
+
+
+# ----------------------------------------------------------------------------
+# precision schedule: reduced precision while ||delta||_F > the switch, FP64
+# after, the paper's stopping rule on the FP64 iterations
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_schedule_irsi_water100(prec):
+    S, _ = config_matrix(0)
+    D = blocks_to_dense(S)
+    lam = float(np.linalg.eigvalsh(D)[-1])
+    say(f"case schedule irsi water-100 {prec}")
+    with lif.Factorization(dev(S), prec=PREC[prec], prec_switch=1e-2, start=lif.START_INV_SQRT_LMAX,
+                           start_value=lam) as f:
+        info = f.refine()
+        Z = blocks_to_dense(f.get_Z())
+        res = f.residual()
+    Zm, im, _ = R.irsi(D, 32, 0.0, start="inv_sqrt_lmax", start_value=lam, prec=prec, prec_switch=1e-2)
+    say(f"  gpu iterations {info['iterations_top']} reduced {info['iterations_reduced']}, oracle "
+        f"{im.iterations} reduced {sum(im.reduced)}; norms {info['norms']}")
+    # the switch decisions match; the last FP64 step may be a near-tie at the floor
+    assert info["iterations_reduced"] == sum(im.reduced)
+    assert abs(info["iterations_top"] - im.iterations) <= 1
+    assert res <= 1e-12   # the FP64 floor, as the paper's rule reaches in FP64
+    assert np.linalg.norm(Z - Zm) <= 10 * U_IN[prec] * np.linalg.norm(Zm)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_schedule_lif_chain_split_batches(prec):
+    # several problems per level: in some iterations part of a level is
+    # above the switch and part below, so the correction runs split
+    S, cfg = config_matrix(1, count=150)   # n = 3000 chain, b = 64
+    D = blocks_to_dense(S)
+    tau = 1e-10
+    say(f"case schedule lif chain n={S.n} {prec}")
+    with lif.Factorization(dev(S), tau=tau, base_rows=512) as f:
+        i64 = f.localized()
+        res64 = f.residual()
+    with lif.Factorization(dev(S), tau=tau, base_rows=512, prec=PREC[prec], prec_switch=1e-2) as f:
+        info = f.localized()
+        Z = blocks_to_dense(f.get_Z())
+        res = f.residual()
+    Zm, plan = R.lif(D, 64, tau, base_rows=512, prec=prec, prec_switch=1e-2)
+    nodes = []
+
+    def walk(nd):
+        if nd.children:
+            nodes.append(nd.info)
+            walk(nd.children[0])
+            walk(nd.children[1])
+
+    walk(plan)
+    red = sum(sum(i.reduced) for i in nodes)
+    say(f"  gpu total {info['iterations_total']} reduced {info['iterations_reduced']} (fp64 run "
+        f"{i64['iterations_total']}), oracle total {sum(i.iterations for i in nodes)} reduced {red}; "
+        f"residual {res:.3e} (fp64 {res64:.3e})")
+    assert info["iterations_reduced"] == red
+    assert abs(info["iterations_total"] - sum(i.iterations for i in nodes)) <= len(nodes)
+    assert res <= 2 * res64 + 1e-12
+    assert np.linalg.norm(Z - Zm) <= 10 * U_IN[prec] * np.linalg.norm(Zm)
