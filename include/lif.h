@@ -132,6 +132,8 @@ typedef struct {
                               * (independent problems of a level run as one batch) */
   int32_t cpl_products;      /* products on that chain */
   int32_t iterations_reduced;/* node iterations whose correction ran in reduced precision */
+  uint64_t mem_peak_bytes;   /* most device memory the handle's buffers held at once during the call */
+  uint64_t mem_reserved_bytes;/* device memory the handle holds from HIP at the end of the call */
 } lif_info;
 
 /* Fills *o with the defaults: m = 4, tau = 0, FP64, paper stopping rule,

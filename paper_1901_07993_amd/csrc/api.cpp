@@ -160,6 +160,8 @@ void fill_info(lif_handle h, const RunInfo& ri, double seconds, lif_info* info) 
   info->cpl_tasks = h->ctx.stats.cpl;
   info->cpl_products = h->ctx.stats.cpl_products;
   info->iterations_reduced = ri.iterations_reduced;
+  info->mem_peak_bytes = h->pool.peak();
+  info->mem_reserved_bytes = h->pool.reserved();
   info->nnzb_Z = h->has_Z ? exact_nnzb(h->ctx, h->Z) : 0;
   info->n_norms = (int32_t)std::min<size_t>(64, ri.norms_top.size());
   for (int k = 0; k < info->n_norms; ++k) info->norms[k] = ri.norms_top[k];
@@ -169,6 +171,7 @@ void fill_info(lif_handle h, const RunInfo& ri, double seconds, lif_info* info) 
 void reset_stats(lif_handle h) {
   h->ctx.flush_timing();
   h->ctx.stats = Stats();
+  h->pool.reset_peak();
 }
 
 lif_status copy_out(lif_handle h, const Bsr& A, int64_t* nnzb, int32_t* brow, int32_t* bcol, double* vals,

@@ -63,6 +63,7 @@ class Pool {
   uint64_t in_use() const { return in_use_; }
   uint64_t reserved() const { return reserved_; }
   uint64_t peak() const { return peak_; }
+  void reset_peak() { peak_ = in_use_; }
   int64_t segments_allocated() const { return seg_allocs_; }
 
  private:
@@ -71,16 +72,21 @@ class Pool {
     bool free;
     char* seg;  // base of the segment it lies in
   };
+  // Buffers of at least kLarge bytes and smaller ones live in separate
+  // segments, so that small long-lived buffers never pin a large segment.
+  static constexpr size_t kLarge = size_t(64) << 20;
+  static int size_class(size_t r) { return r >= kLarge ? 1 : 0; }
   static size_t round(size_t bytes);
-  bool grow(size_t need);
+  bool grow(size_t need, int cls);
   void take(std::map<char*, Piece>::iterator it, size_t r);
   void release_all();
   uint64_t cap_;
   uint64_t in_use_ = 0, reserved_ = 0, peak_ = 0;
+  uint64_t reserved_cls_[2] = {0, 0};
   int64_t seg_allocs_ = 0;
-  std::map<char*, size_t> segs_;                  // segment base -> size
+  std::map<char*, std::pair<size_t, int>> segs_;  // segment base -> (size, class)
   std::map<char*, Piece> pieces_;                 // every piece of every segment, by address
-  std::set<std::pair<size_t, char*>> free_;       // free pieces by (size, address)
+  std::set<std::pair<size_t, char*>> free_[2];    // free pieces of each class by (size, address)
   bool defer_ = false;
   std::vector<void*> deferred_;
 };
@@ -239,6 +245,13 @@ struct Ctx {
     size_t next = 0;
     std::vector<std::array<int64_t, 2>> caps, seen;
     std::vector<int> prec;  // precision of each sized-in-advance product
+    // While exact_large, a product whose capacity would take more than
+    // kMaxBytes is sized exactly even in a planned sequence (a read-back
+    // costs little next to it, a margin costs gigabytes): exact[slot] holds
+    // its counts, {-1, -1} for the planned slots.
+    static constexpr double kMaxBytes = double(1u << 30);
+    bool exact_large = false;  // set while memory is tight
+    std::vector<std::array<int64_t, 2>> exact;
     DBuf<int64_t> sizes;
     DBuf<int> overflow;
   } spec;
@@ -283,6 +296,10 @@ struct Ctx {
   hipStream_t side = nullptr;
   std::vector<hipEvent_t> order_events;
   hipStream_t side_stream();
+  // device memory of the GPU (queried once); the limit below which the
+  // refinement may hold an iteration's buffers until its end (two streams)
+  uint64_t device_bytes();
+  uint64_t device_total = 0;
   hipEvent_t order_event(size_t i);  // the i-th reusable ordering event
   // `waiter` waits for the work queued so far on `signaler`
   void stream_after(hipStream_t waiter, hipStream_t signaler);

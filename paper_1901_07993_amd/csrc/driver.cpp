@@ -184,7 +184,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
     std::vector<double> ss;
     struct SpecOff {  // no sizing in advance outside this loop, also on errors
       Ctx& c;
-      ~SpecOff() { c.spec.on = c.spec.record = false; }
+      ~SpecOff() { c.spec.on = c.spec.record = c.spec.exact_large = false; }
     } spec_off{c};
     for (;;) {
       c.spec.on = planned;
@@ -193,6 +193,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       c.spec.caps = caps;
       c.spec.seen.clear();
       c.spec.prec.clear();
+      c.spec.exact.clear();
       if (planned) launch_fill_i32(c, c.spec.overflow.get(), 0, 1);
       // delta restricted to the problems still iterating
       Bsr dfilt;
@@ -204,7 +205,21 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       // by the two sums, so their dropped blocks are left as null pointers
       // (holes) rather than compacted away.
       constexpr bool kHoles = true;
+      // Two streams hold the iteration's buffers until its end; when the
+      // products of the last iteration, or six matrices the size of Z, or
+      // eight the size of delta would take more than a quarter of the GPU's
+      // memory, the iteration runs on one stream, frees each buffer at once
+      // and sizes its large products exactly.
+      const double blk_bytes = (double)S.b * S.b * sizeof(double);
+      double caps_bytes = 0.0;
+      for (const auto& cp : caps) caps_bytes += (double)cp[0] * blk_bytes + (double)cp[1] * sizeof(BlockPair);
+      const double iter_bytes =
+          std::max({caps_bytes, 6.0 * (double)Z.bound() * blk_bytes, 8.0 * (double)delta.bound() * blk_bytes});
+      const double dev = (double)c.device_bytes();
+      const bool big = iter_bytes > 0.25 * dev || (double)c.pool->reserved() + iter_bytes > 0.5 * dev;
+      c.spec.exact_large = big;
       DeferFrees defer(c);
+      if (big) defer.release();
       if (regular) {
         // Regular form (eq. refinement_nonlocal): P = b_m I, then
         // P <- b_j I + trunc(delta P) for j = m-1 .. 0, Z_{k+1} = trunc(Z P),
@@ -271,6 +286,17 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
         M = axpby(c, 1.0, &MR, 1.0, &MF, 0.0, nullptr);
       }
       // delta_{k+1} = delta_k - Z_{k+1}^T (S M) - (S M)^T Z_k   (M^T S = (S M)^T)
+      if (big) {
+        // large products fill the GPU by themselves: one stream, and every
+        // operand is released as soon as its last reader is queued
+        Bsr SM = spgemm(c, S, false, M, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles);
+        Znew = axpby(c, 1.0, &Z, 1.0, &M, 0.0, nullptr);
+        M = Bsr();
+        Bsr X2 = spgemm(c, SM, true, Z, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles);
+        Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles);
+        SM = Bsr();
+        dnew = axpby3(c, 1.0, &delta, -1.0, &X1, -1.0, &X2);
+      } else {
       // S M and then (S M)^T Z_k run on the side stream while Z + M and then
       // Z_{k+1}^T (S M) run on the main one; buffers freed meanwhile are
       // reused only after the synchronization at the end of the iteration.
@@ -294,6 +320,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       dnew = axpby3(c, 1.0, &delta, -1.0, &X1, -1.0, &X2);
       X1 = Bsr();
       X2 = Bsr();
+      }
       }
 
       const size_t nprod = planned ? c.spec.next : c.spec.seen.size();
@@ -320,16 +347,18 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       if (planned) {
         seen.clear();
         for (size_t i = 0; i < nprod; ++i) {
-          seen.push_back({sz[2 * i], sz[2 * i + 1]});
-          const double fl = 2.0 * (double)S.b * S.b * S.b * (double)sz[2 * i + 1];
-          c.stats.products += sz[2 * i + 1];
+          const bool ex = i < c.spec.exact.size() && c.spec.exact[i][0] >= 0;  // sized exactly
+          seen.push_back(ex ? c.spec.exact[i] : std::array<int64_t, 2>{sz[2 * i], sz[2 * i + 1]});
+          const double fl = 2.0 * (double)S.b * S.b * S.b * (double)seen.back()[1];
+          c.stats.products += seen.back()[1];
           c.stats.flops += fl;
           if (pprec[i] != LIF_FP64) c.stats.flops_lowp += fl;
         }
       }
       // margins: output counts move little between iterations, block-product
       // counts can triple after the first iteration of a LIF level (delta_0
-      // holds only the coupling blocks); pair slots are 8 bytes
+      // holds only the coupling blocks); pair slots are 16 bytes, and a
+      // product over the planning limit is sized exactly anyway
       caps.clear();
       for (const auto& v : seen)
         caps.push_back(o.presize == 2 ? v : std::array<int64_t, 2>{v[0] + v[0] / 2 + 64, 4 * v[1] + 4096});
@@ -740,7 +769,7 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck)
       for (bool planned = o.presize != 0 && !setup_caps.empty();; planned = false) {
         struct SpecOff {
           Ctx& c;
-          ~SpecOff() { c.spec.on = c.spec.record = false; }
+          ~SpecOff() { c.spec.on = c.spec.record = c.spec.exact_large = false; }
         } spec_off{c};
         c.spec.on = planned;
         c.spec.record = !planned;
@@ -748,6 +777,10 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck)
         c.spec.caps = setup_caps;
         c.spec.seen.clear();
         c.spec.prec.clear();
+        c.spec.exact.clear();
+        // large levels: the two products are sized exactly once they are large
+        const double zb = 4.0 * (double)Z.bound() * b * b * sizeof(double), dev = (double)c.device_bytes();
+        c.spec.exact_large = zb > 0.25 * dev || (double)c.pool->reserved() + zb > 0.5 * dev;
         if (planned) launch_fill_i32(c, c.spec.overflow.get(), 0, 1);
         Bsr W = spgemm(c, Z, true, S_up, false, o.tau);
         Bsr X = spgemm(c, W, false, Z, false, o.tau);
@@ -770,9 +803,10 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck)
         std::vector<std::array<int64_t, 2>> seen = c.spec.seen;
         if (planned) {
           seen = {{sz[0], sz[1]}, {sz[2], sz[3]}};
-          for (const auto& v : seen) {  // statistics that exact sizing counts in spgemm
-            const double fl = 2.0 * (double)S.b * S.b * S.b * (double)v[1];
-            c.stats.products += v[1];
+          for (size_t i = 0; i < seen.size(); ++i) {
+            if (i < c.spec.exact.size() && c.spec.exact[i][0] >= 0) seen[i] = c.spec.exact[i];  // sized exactly
+            const double fl = 2.0 * (double)S.b * S.b * S.b * (double)seen[i][1];
+            c.stats.products += seen[i][1];
             c.stats.flops += fl;
           }
         }

@@ -308,7 +308,18 @@ Bsr spgemm_body(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau
   const int* dcol = D ? D->col.get() : nullptr;
   C.row_ptr = DBuf<int>(c.pool, nb + 1);
   int64_t nnzc = 0, P = 0;  // capacities of the output and pair arrays
-  const bool planned = c.spec.on && c.spec.next < c.spec.caps.size() && c.spec.next < (size_t)Ctx::Spec::kSlots;
+  bool planned = c.spec.on && c.spec.next < c.spec.caps.size() && c.spec.next < (size_t)Ctx::Spec::kSlots;
+  int64_t exact_slot = -1;  // a slot of the planned sequence that this large product sizes exactly
+  if (planned && c.spec.exact_large) {
+    const auto& cp = c.spec.caps[c.spec.next];
+    const double bytes = (double)std::min<int64_t>(cp[0], (int64_t)nb * nb) * A.b * A.b * sizeof(double) +
+                         (double)cp[1] * sizeof(BlockPair);
+    if (bytes > Ctx::Spec::kMaxBytes) {
+      planned = false;
+      exact_slot = (int64_t)c.spec.next++;
+      c.spec.prec.push_back(prec);
+    }
+  }
   DBuf<int64_t> seg, prp;
   DBuf<BlockPair> pairs;
   DBuf<const double*> dsrc;
@@ -363,10 +374,16 @@ Bsr spgemm_body(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau
     nnzc = nnzc32;
     C.nnzb = nnzc;
     if (c.spec.record) c.spec.seen.push_back({nnzc, P});
-    c.stats.products += P;
-    const double fl = 2.0 * (double)C.b * C.b * C.b * (double)P;
-    c.stats.flops += fl;
-    if (prec != LIF_FP64) c.stats.flops_lowp += fl;
+    if (exact_slot >= 0) {
+      if (c.spec.exact.size() <= (size_t)exact_slot) c.spec.exact.resize(exact_slot + 1, {-1, -1});
+      c.spec.exact[exact_slot] = {nnzc, P};
+    }
+    if (exact_slot < 0) {  // a slot's statistics are counted once its sequence is kept
+      c.stats.products += P;
+      const double fl = 2.0 * (double)C.b * C.b * C.b * (double)P;
+      c.stats.flops += fl;
+      if (prec != LIF_FP64) c.stats.flops_lowp += fl;
+    }
   }
   alloc_outputs();
   if (nnzc)

@@ -7,11 +7,14 @@ size_t Pool::round(size_t bytes) {
   return (bytes + 255) & ~size_t(255);  // every buffer 256-byte aligned
 }
 
-// A new segment for at least `need` bytes: at least 64 MiB, and half of what
-// is already held (up to 16 GiB), so a growing problem needs few segments.
-bool Pool::grow(size_t need) {
-  constexpr size_t kMin = size_t(64) << 20, kMax = size_t(16) << 30, kGrain = size_t(2) << 20;
-  size_t want = std::max(need, std::min(kMax, std::max(kMin, (size_t)(reserved_ / 2))));
+// A new segment for at least `need` bytes of class cls.  Small class: at
+// least 64 MiB and half of what that class holds (up to 1 GiB).  Large class:
+// at least 1 GiB, so that neighbouring large buffers can share one.
+bool Pool::grow(size_t need, int cls) {
+  constexpr size_t kGrain = size_t(2) << 20;
+  size_t want = cls == 0 ? std::max(need, std::min(size_t(1) << 30,
+                                                   std::max(size_t(64) << 20, (size_t)(reserved_cls_[0] / 2))))
+                         : std::max(need, size_t(1) << 30);
   want = (want + kGrain - 1) & ~(kGrain - 1);
   if (cap_ && reserved_ + want > cap_) want = std::max(need, (size_t)(cap_ > reserved_ ? cap_ - reserved_ : 0));
   if (cap_ && reserved_ + want > cap_) return false;
@@ -26,10 +29,11 @@ bool Pool::grow(size_t need) {
     }
   }
   char* base = static_cast<char*>(p);
-  segs_[base] = want;
+  segs_[base] = {want, cls};
   pieces_[base] = Piece{want, true, base};
-  free_.insert({want, base});
+  free_[cls].insert({want, base});
   reserved_ += want;
+  reserved_cls_[cls] += want;
   ++seg_allocs_;
   return true;
 }
@@ -38,10 +42,11 @@ bool Pool::grow(size_t need) {
 void Pool::take(std::map<char*, Piece>::iterator it, size_t r) {
   char* p = it->first;
   Piece& pc = it->second;
-  free_.erase({pc.size, p});
+  const int cls = segs_[pc.seg].second;
+  free_[cls].erase({pc.size, p});
   if (pc.size > r) {
     pieces_[p + r] = Piece{pc.size - r, true, pc.seg};
-    free_.insert({pc.size - r, p + r});
+    free_[cls].insert({pc.size - r, p + r});
     pc.size = r;
   }
   pc.free = false;
@@ -51,22 +56,23 @@ void Pool::take(std::map<char*, Piece>::iterator it, size_t r) {
 
 void* Pool::alloc(size_t bytes) {
   const size_t r = round(bytes);
+  const int cls = size_class(r);
   for (int attempt = 0; attempt < 3; ++attempt) {
-    auto f = free_.lower_bound({r, nullptr});  // best fit: the smallest free piece that fits
-    if (f != free_.end()) {
+    auto f = free_[cls].lower_bound({r, nullptr});  // best fit: the smallest free piece that fits
+    if (f != free_[cls].end()) {
       auto it = pieces_.find(f->second);
       take(it, r);
       return it->first;
     }
-    if (attempt == 0 && grow(r)) continue;
+    if (attempt == 0 && grow(r, cls)) continue;
     if (attempt == 1) {
       trim();  // give back whole unused segments, then try once more
-      if (grow(r)) continue;
+      if (grow(r, cls)) continue;
     }
   }
   throw Error(LIF_ERR_OUT_OF_MEMORY, "device memory: cannot allocate " + std::to_string(r) + " bytes with " +
-                                         std::to_string(reserved_) + " held" +
-                                         (cap_ ? ", cap " + std::to_string(cap_) : std::string()));
+                                         std::to_string(reserved_) + " held (" + std::to_string(in_use_) +
+                                         " in use)" + (cap_ ? ", cap " + std::to_string(cap_) : std::string()));
 }
 
 void Pool::free(void* ptr) {
@@ -76,25 +82,26 @@ void Pool::free(void* ptr) {
     deferred_.push_back(ptr);
     return;
   }
+  const int cls = segs_[it->second.seg].second;
   in_use_ -= it->second.size;
   it->second.free = true;
   // merge with the free neighbours inside the same segment
   auto next = std::next(it);
   if (next != pieces_.end() && next->second.free && next->second.seg == it->second.seg) {
-    free_.erase({next->second.size, next->first});
+    free_[cls].erase({next->second.size, next->first});
     it->second.size += next->second.size;
     pieces_.erase(next);
   }
   if (it != pieces_.begin()) {
     auto prev = std::prev(it);
     if (prev->second.free && prev->second.seg == it->second.seg) {
-      free_.erase({prev->second.size, prev->first});
+      free_[cls].erase({prev->second.size, prev->first});
       prev->second.size += it->second.size;
       pieces_.erase(it);
       it = prev;
     }
   }
-  free_.insert({it->second.size, it->first});
+  free_[cls].insert({it->second.size, it->first});
 }
 
 void Pool::release_deferred() {
@@ -111,15 +118,16 @@ void Pool::trim() {
   bool synced = false;
   for (auto s = segs_.begin(); s != segs_.end();) {
     auto it = pieces_.find(s->first);
-    if (it != pieces_.end() && it->second.free && it->second.size == s->second) {
+    if (it != pieces_.end() && it->second.free && it->second.size == s->second.first) {
       if (!synced) {
         (void)hipDeviceSynchronize();
         synced = true;
       }
-      free_.erase({it->second.size, it->first});
+      free_[s->second.second].erase({it->second.size, it->first});
       pieces_.erase(it);
       (void)hipFree(s->first);
-      reserved_ -= s->second;
+      reserved_ -= s->second.first;
+      reserved_cls_[s->second.second] -= s->second.first;
       s = segs_.erase(s);
     } else {
       ++s;
@@ -132,9 +140,11 @@ void Pool::release_all() {
   for (auto& kv : segs_) (void)hipFree(kv.first);
   segs_.clear();
   pieces_.clear();
-  free_.clear();
+  free_[0].clear();
+  free_[1].clear();
   deferred_.clear();
   reserved_ = in_use_ = 0;
+  reserved_cls_[0] = reserved_cls_[1] = 0;
 }
 
 hipEvent_t Ctx::take_event() {
@@ -205,6 +215,15 @@ void Ctx::d2h_batch(const std::vector<Read>& reads) {
                       reinterpret_cast<const unsigned*>(dbase + 64 * 32 + 32 * sizeof(void*)), n, dbase);
   LIF_HIP(hipStreamSynchronize(stream));
   for (int i = 0; i < n; ++i) std::memcpy(reads[i].dst, base + 64 * i, reads[i].bytes);
+}
+
+uint64_t Ctx::device_bytes() {
+  if (!device_total) {
+    size_t free_b = 0, total_b = 0;
+    LIF_HIP(hipMemGetInfo(&free_b, &total_b));
+    device_total = total_b;
+  }
+  return device_total;
 }
 
 hipStream_t Ctx::side_stream() {

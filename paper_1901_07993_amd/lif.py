@@ -55,7 +55,8 @@ class Info(ctypes.Structure):
                 ("flops_leaf_gemm", c_double), ("seconds_total", c_double), ("seconds_leaf_gemm", c_double),
                 ("leaf_gemm_launches", c_int64), ("products_total", c_int64), ("nnzb_Z", c_int64),
                 ("n_norms", c_int32), ("norms", c_double * 64), ("iterations_redone", c_int32),
-                ("cpl_tasks", c_int32), ("cpl_products", c_int32), ("iterations_reduced", c_int32)]
+                ("cpl_tasks", c_int32), ("cpl_products", c_int32), ("iterations_reduced", c_int32),
+                ("mem_peak_bytes", c_uint64), ("mem_reserved_bytes", c_uint64)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "norms"}

@@ -37,19 +37,20 @@ def test_exports_every_declared_symbol():
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lif.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lif_blocks),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lif_blocks),'
                    ' sizeof(lif_opts), sizeof(lif_info), offsetof(lif_opts, stream), offsetof(lif_info, norms),'
                    ' offsetof(lif_blocks, on_device), offsetof(lif_opts, presize),'
                    ' offsetof(lif_info, iterations_redone), offsetof(lif_opts, refinement),'
                    ' offsetof(lif_info, cpl_products), offsetof(lif_opts, prec_switch),'
-                   ' offsetof(lif_info, iterations_reduced)); return 0;}\n')
+                   ' offsetof(lif_info, iterations_reduced), offsetof(lif_info, mem_reserved_bytes));'
+                   ' return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     want = [ctypes.sizeof(lif.Blocks), ctypes.sizeof(lif.Opts), ctypes.sizeof(lif.Info), lif.Opts.stream.offset,
             lif.Info.norms.offset, lif.Blocks.on_device.offset, lif.Opts.presize.offset,
             lif.Info.iterations_redone.offset, lif.Opts.refinement.offset, lif.Info.cpl_products.offset,
-            lif.Opts.prec_switch.offset, lif.Info.iterations_reduced.offset]
+            lif.Opts.prec_switch.offset, lif.Info.iterations_reduced.offset, lif.Info.mem_reserved_bytes.offset]
     assert got == want
 
 
