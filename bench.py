@@ -102,6 +102,47 @@ def time_method(lif, Sd, tau, meth, steps, **kw):
     return s, info
 
 
+def water_comparison(lif, count, which=("fp64", "fp32_schedule", "bf16_schedule")):
+    """FP64 against the scheduled FP32 / BF16 corrections on a water cluster
+    (tau = 1e-8, b = 64, LIF to 4096-row leaves): compute-bound products, the
+    regime where reduced precision pays.  One untimed and one timed
+    factorization each; every run stops at its FP64 floor."""
+    import torch
+    from gen import config_matrix
+    print(f"# generating water-{count}", file=sys.stderr, flush=True)
+    S, cfg = config_matrix(2, count=count)
+    Sd = type("DevBlocks", (), dict(n=S.n, b=S.b, brow=torch.from_numpy(S.brow).cuda(),
+                                    bcol=torch.from_numpy(S.bcol).cuda(), vals=torch.from_numpy(S.vals).cuda()))
+    out = {"workload": f"water-{count}: {count} molecules x 7 s-Gaussians, n={S.n}, b=64, tau={cfg['tau']}, "
+                       f"LIF to 4096-row leaves, m=4, paper stop", "n": S.n}
+    t64 = None
+    for name, prec, sw in (("fp64", lif.FP64, 0.0), ("fp32_schedule", lif.MIXED_FP32, 1e-2),
+                           ("bf16_schedule", lif.MIXED_BF16, 1e-2)):
+        if name not in which:
+            continue
+        f = lif.Factorization(Sd, tau=cfg["tau"], base_rows=4096, prec=prec, prec_switch=sw, timing=1)
+        f.localized()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = f.localized()
+        torch.cuda.synchronize()
+        s = time.perf_counter() - t0
+        res = f.residual()
+        f.close()
+        torch.cuda.empty_cache()
+        gemm_tf = info["flops_leaf_gemm"] / info["seconds_leaf_gemm"] / 1e12 if info["seconds_leaf_gemm"] else None
+        out[name] = {"s_per_factorization": s, "residual": res, "iterations_total": info["iterations_total"],
+                     "iterations_reduced": info["iterations_reduced"], "leaf_gemm_tflops": gemm_tf,
+                     "mem_peak_gib": info["mem_peak_bytes"] / 2 ** 30}
+        if prec == lif.FP64:
+            t64 = s
+            out[name]["leaf_gemm_frac_of_fp64_peak"] = gemm_tf / PEAK_FP64_MFMA_TFLOPS if gemm_tf else None
+        elif t64:
+            out[name]["speedup_vs_fp64"] = t64 / s
+        print(f"# water-{count} {name}: {s:.2f} s, residual {res:.3e}", file=sys.stderr, flush=True)
+    return out
+
+
 def cpl_sweep(counts, steps):
     """Critical-path task counts (the one-GPU shadow of Sec. 3) and times of
     the four methods on chains of the given lengths."""
@@ -138,6 +179,12 @@ def main():
     ap.add_argument("--rinch-steps", type=int, default=2)
     ap.add_argument("--no-variants", action="store_true",
                     help="skip IRSI and the regular-form recursive factorization on the same matrix")
+    ap.add_argument("--no-water", action="store_true",
+                    help="skip the FP64 vs scheduled mixed-precision comparison on the water-5000 cluster")
+    ap.add_argument("--water-count", type=int, default=5000, help="molecules of that water cluster")
+    ap.add_argument("--water-only", type=str, default="",
+                    help="comma-separated subset of fp64,fp32_schedule,bf16_schedule: run only the water "
+                         "comparison with these (one JSON line) and exit")
     ap.add_argument("--cpl-sweep", type=str, default="",
                     help="comma-separated chain lengths: print critical-path task counts and times of "
                          "LIF, RINCH, IRSI and the regular-form recursion per size (one JSON line) and exit")
@@ -164,6 +211,14 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.water_only:
+        import torch
+        from paper_1901_07993_amd import lif as lifmod
+        lifmod.load()
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        print(json.dumps({"water": water_comparison(lifmod, args.water_count, args.water_only.split(","))}),
+              flush=True)
+        return
     if args.cpl_sweep:
         print(json.dumps(cpl_sweep([int(x) for x in args.cpl_sweep.split(",")], args.rinch_steps)), flush=True)
         return
@@ -171,8 +226,9 @@ def main():
     S, cfg = config_matrix(1, count=args.count)
     Sd = type("DevBlocks", (), dict(n=S.n, b=S.b, brow=torch.from_numpy(S.brow).cuda(),
                                     bcol=torch.from_numpy(S.bcol).cuda(), vals=torch.from_numpy(S.vals).cuda()))
-    def run(prec, stop, tol):
-        f = lif.Factorization(Sd, tau=cfg["tau"], base_rows=4096, stop=stop, tol=tol, prec=prec, timing=1)
+    def run(prec, stop, tol, prec_switch=0.0):
+        f = lif.Factorization(Sd, tau=cfg["tau"], base_rows=4096, stop=stop, tol=tol, prec=prec, timing=1,
+                              prec_switch=prec_switch)
         torch.cuda.synchronize()
         for w in range(args.warmup):
             info = f.localized()
@@ -201,14 +257,18 @@ def main():
     traffic = measured_traffic()
     mixed = {}
     if not args.no_mixed:
+        # the precision schedule: reduced-precision corrections while
+        # ||delta||_F > 1e-2, FP64 iterations and the paper's rule after, so
+        # the run stops at the same floor as the FP64 one
         for name, prec in (("fp32", lif.MIXED_FP32), ("bf16", lif.MIXED_BF16)):
-            s_m, inf_m, res_m, Zm = run(prec, lif.STOP_TOL, 1e-10)
+            s_m, inf_m, res_m, Zm = run(prec, lif.STOP_PAPER, 1e-10, prec_switch=1e-2)
             fl = sum(i["flops_leaf_gemm"] for i in inf_m)
             gs = sum(i["seconds_leaf_gemm"] for i in inf_m)
             mixed[name] = {"s_per_factorization": s_m, "speedup_vs_fp64": step_s / s_m,
                            "leaf_gemm_gflops": fl / gs / 1e9 if gs > 0 else None,
                            "iterations_top": inf_m[-1]["iterations_top"],
                            "iterations_total": inf_m[-1]["iterations_total"],
+                           "iterations_reduced": inf_m[-1]["iterations_reduced"], "prec_switch": 1e-2,
                            "stagnated": inf_m[-1]["stagnated"], "delta_tracked": inf_m[-1]["delta_tracked"],
                            "residual": res_m,
                            "rel_diff_vs_fp64_Z": None if Zm is None else rel_diff(Zm, Z64)}
@@ -248,6 +308,9 @@ def main():
                               "cpl_tasks": inf_v["cpl_tasks"], "cpl_products": inf_v["cpl_products"],
                               "iterations_top": inf_v["iterations_top"],
                               "iterations_total": inf_v["iterations_total"], "nnzb_Z": inf_v["nnzb_Z"]}
+    water = None
+    if not args.no_water:
+        water = water_comparison(lif, args.water_count)
     out = {
         "metric": METRIC,
         "value": ms / 1e3,
@@ -279,6 +342,7 @@ def main():
         "mixed": mixed,
         "rinch": rinch,
         "variants": variants,
+        "water": water,
         "roofline": {"bound": "mfma", "kernel": "k_numeric_f64 (leaf GEMM, v_mfma_f64_16x16x4f64)",
                      "achieved": achieved, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_MFMA_TFLOPS,

@@ -46,6 +46,10 @@ Step stop_decision(int k, double e, double e_prev, bool has_prev, int m, int sto
   return Step::Continue;
 }
 
+// An iteration whose products (with margins) would take more than this is
+// not sized in advance.
+constexpr double kPlanIterBytes = 4.0 * double(1u << 30);
+
 struct NodeState {
   bool active = true;
   bool has_prev = false;
@@ -179,7 +183,13 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
     // previous iteration's counts (with a margin) instead of reading its
     // counts back; the counts and an overflow flag come back with the norms.
     // If a capacity was short the iteration is redone with exact sizes.
-    bool planned = o.presize != 0 && !caps.empty() && caps_split == split;
+    // Sizing in advance saves a read-back per product, which only matters
+    // for small products; an iteration whose products take more than a few
+    // gigabytes reads its counts back (no margins, no redone work).
+    const double blk_bytes = (double)S.b * S.b * sizeof(double);
+    double caps_bytes = 0.0;
+    for (const auto& cp : caps) caps_bytes += (double)cp[0] * blk_bytes + (double)cp[1] * sizeof(BlockPair);
+    bool planned = o.presize != 0 && !caps.empty() && caps_split == split && caps_bytes <= kPlanIterBytes;
     Bsr Znew, dnew;
     std::vector<double> ss;
     struct SpecOff {  // no sizing in advance outside this loop, also on errors
@@ -210,9 +220,6 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       // eight the size of delta would take more than a quarter of the GPU's
       // memory, the iteration runs on one stream, frees each buffer at once
       // and sizes its large products exactly.
-      const double blk_bytes = (double)S.b * S.b * sizeof(double);
-      double caps_bytes = 0.0;
-      for (const auto& cp : caps) caps_bytes += (double)cp[0] * blk_bytes + (double)cp[1] * sizeof(BlockPair);
       const double iter_bytes =
           std::max({caps_bytes, 6.0 * (double)Z.bound() * blk_bytes, 8.0 * (double)delta.bound() * blk_bytes});
       const double dev = (double)c.device_bytes();
@@ -766,7 +773,11 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck)
         c.spec.sizes = DBuf<int64_t>(c.pool, 2 * Ctx::Spec::kSlots);
         c.spec.overflow = DBuf<int>(c.pool, 1);
       }
-      for (bool planned = o.presize != 0 && !setup_caps.empty();; planned = false) {
+      double setup_bytes = 0.0;
+      for (const auto& cp : setup_caps)
+        setup_bytes += (double)cp[0] * b * b * sizeof(double) + (double)cp[1] * sizeof(BlockPair);
+      for (bool planned = o.presize != 0 && !setup_caps.empty() && setup_bytes <= kPlanIterBytes;;
+           planned = false) {
         struct SpecOff {
           Ctx& c;
           ~SpecOff() { c.spec.on = c.spec.record = c.spec.exact_large = false; }

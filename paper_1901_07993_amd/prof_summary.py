@@ -9,6 +9,10 @@
         counter runs, each scaled by the factor that maps the same counter
         on a plain device copy of N MiB (issued before any library kernel)
         to its known size
+    python -m paper_1901_07993_amd.prof_summary mfma COUNTERS.csv TRACE.csv OUT.json \
+            --kernel k_numeric_f64 --peak-tflops P --cmd C
+        MFMA busy fraction and MFMA flop rate of one kernel (MfmaUtil and
+        MfmaFlopsF64 counters, dispatch times from the same run's trace)
 """
 from __future__ import annotations
 
@@ -82,6 +86,37 @@ def traffic(fetch: str, write: str, out: str, kernel: str, copy_mib: float, cmd:
         f.write("\n")
 
 
+def mfma(counters: str, trace: str, out: str, kernel: str, peak_tflops: float, cmd: str) -> None:
+    """MFMA busy fraction and MFMA flop rate of one kernel from a counter run
+    that also traced the kernels (durations by dispatch id): the derived
+    counters MfmaUtil (MFMA busy cycles over active cycles and SIMDs, in %)
+    and MfmaFlopsF64 (512 flops per MFMA op), weighted by dispatch time."""
+    dur = {}
+    for r in csv.DictReader(open(trace)):
+        if _short(r["Kernel_Name"]).startswith(kernel):
+            dur[int(r["Dispatch_Id"])] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    util, flops = {}, {}
+    for r in csv.DictReader(open(counters)):
+        if not _short(r["Kernel_Name"]).startswith(kernel):
+            continue
+        d = int(r["Dispatch_Id"])
+        if r["Counter_Name"] == "MfmaUtil":
+            util[d] = util.get(d, 0.0) + float(r["Counter_Value"])
+        elif r["Counter_Name"] == "MfmaFlopsF64":
+            flops[d] = flops.get(d, 0.0) + float(r["Counter_Value"])
+    ids = sorted(set(util) & set(flops) & set(dur))
+    t = sum(dur[i] for i in ids)
+    res = {"kernel": kernel, "command": cmd, "dispatches": len(ids), "kernel_seconds": t / 1e9,
+           "mfma_util_pct_time_weighted": sum(util[i] * dur[i] for i in ids) / t if t else None,
+           "mfma_f64_flops": sum(flops[i] for i in ids),
+           "mfma_f64_tflops": sum(flops[i] for i in ids) / (t / 1e9) / 1e12 if t else None,
+           "peak_tflops": peak_tflops}
+    res["frac_of_peak"] = res["mfma_f64_tflops"] / peak_tflops if res["mfma_f64_tflops"] else None
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1)
+        f.write("\n")
+
+
 def main() -> None:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -98,11 +133,20 @@ def main() -> None:
     t.add_argument("--copy-mib", type=float, required=True)
     t.add_argument("--cmd", required=True)
     t.add_argument("--hash", default="")
+    m = sub.add_parser("mfma")
+    m.add_argument("counters")
+    m.add_argument("trace")
+    m.add_argument("out")
+    m.add_argument("--kernel", required=True)
+    m.add_argument("--peak-tflops", type=float, required=True)
+    m.add_argument("--cmd", required=True)
     a = ap.parse_args()
     if a.what == "stats":
         stats(a.trace, a.out, a.title, a.cmd)
-    else:
+    elif a.what == "traffic":
         traffic(a.fetch, a.write, a.out, a.kernel, a.copy_mib, a.cmd, a.hash)
+    else:
+        mfma(a.counters, a.trace, a.out, a.kernel, a.peak_tflops, a.cmd)
 
 
 if __name__ == "__main__":
