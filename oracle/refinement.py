@@ -183,8 +183,17 @@ def stop_now(k: int, e: float, e_prev: float | None, m: int, stop: str, tol: flo
     raise ValueError(stop)
 
 
+def upper_blocks(A: np.ndarray, b: int, strict: bool = False) -> np.ndarray:
+    """A with every b x b block below the block diagonal zeroed (and the
+    diagonal blocks too when ``strict``)."""
+    n = A.shape[0]
+    I, J = np.meshgrid(np.arange(n) // b, np.arange(n) // b, indexing="ij")
+    keep = J > I if strict else J >= I
+    return np.where(keep, A, 0.0)
+
+
 def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_iter=100, info=None,
-                         prec="fp64", prec_switch=0.0):
+                         prec="fp64", prec_switch=0.0, sym_delta=False):
     """Localized iterative refinement (eq. refinement_local; Alg. 2 repeat loop).
 
     Each iteration, with T_k the Horner terms of sum_{k=1}^m b_k delta^k:
@@ -203,6 +212,9 @@ def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_
     an inexact correction converges linearly, so the stopping rule is applied
     to the FP64 iterations only (reduced ones are checked for divergence).
     With ``prec_switch`` = 0 every iteration uses ``prec`` and is tested.
+    ``sym_delta``: delta is symmetric in exact arithmetic, so only its upper
+    block triangle is updated (the blocks (I, J), J >= I, of the two
+    truncated products) and the strictly upper part is mirrored below.
     Returns (Z, RefineInfo).
     """
     info = info if info is not None else RefineInfo()
@@ -230,6 +242,9 @@ def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_
         X1 = mult(Z_new.T, SM, b, tau)
         X2 = mult(SM.T, Z, b, tau)
         delta = delta - X1 - X2
+        if sym_delta:
+            U = upper_blocks(delta, b)
+            delta = U + upper_blocks(U, b, strict=True).T
         Z = Z_new
         e = float(np.sqrt(np.sum(delta * delta)))
         info.norms.append(e)
@@ -283,7 +298,8 @@ def nonlocal_refinement(S, Z0, b, tau, m=4, iterations=None, stop="paper", tol=0
 # ----------------------------------------------------------------------------
 
 def irsi(S, b, tau, m=4, start="sqrt2_over_gersh", start_value=None, stop="paper", tol=0.0,
-         max_iter=100, truncate_input=True, prec="fp64", refinement="local", prec_switch=0.0):
+         max_iter=100, truncate_input=True, prec="fp64", refinement="local", prec_switch=0.0,
+         sym_delta=False):
     """Iterative refinement from a scaled identity (IRSI, Sec. 2.2):
     Z_0 = c I, delta_0 = I - c^2 S (a scaling, no product), then localized
     refinement.  With ``refinement="nonlocal"`` the regular form of
@@ -301,7 +317,7 @@ def irsi(S, b, tau, m=4, start="sqrt2_over_gersh", start_value=None, stop="paper
     assert refinement == "local", refinement
     delta0 = np.eye(n) - (c * c) * St
     Z, info = localized_refinement(St, Z0, delta0, b, tau, m, stop, tol, max_iter, prec=prec,
-                                   prec_switch=prec_switch)
+                                   prec_switch=prec_switch, sym_delta=sym_delta)
     return Z, info, c
 
 
@@ -328,7 +344,7 @@ def lif_plan(n: int, b: int, base_rows: int) -> LifNode:
 
 
 def lif(S, b, tau, m=4, base_rows=4096, stop="paper", tol=0.0, max_iter=100, truncate_input=True,
-        plan=None, prec="fp64", refinement="local", prec_switch=0.0):
+        plan=None, prec="fp64", refinement="local", prec_switch=0.0, sym_delta=False):
     """Localized inverse factorization (Alg. 2) with an inverse Cholesky leaf.
 
     For a node with children A (leading rows) and C:
@@ -371,7 +387,7 @@ def lif(S, b, tau, m=4, base_rows=4096, stop="paper", tol=0.0, max_iter=100, tru
         node.delta0_norm2 = float(np.linalg.norm(delta0, 2)) if rows <= 4000 else float("nan")
         node.info = RefineInfo()
         Z, _ = localized_refinement(Sn, Z0, delta0, b, tau, m, stop, tol, max_iter, node.info, prec=prec,
-                                    prec_switch=prec_switch)
+                                    prec_switch=prec_switch, sym_delta=sym_delta)
         return Z
 
     return rec(plan), plan

@@ -538,6 +538,27 @@ def test_precision_schedule_reaches_fp64_floor(water100):
     assert plan.info.iterations <= plan64.info.iterations + 1
 
 
+def test_symmetric_delta_reaches_closed_forms(water100):
+    # delta is symmetric in exact arithmetic: updating its upper block
+    # triangle and mirroring it keeps the limits and the spectral-map norms
+    D, lam = water100
+    Z, info, c = R.irsi(D, 32, 0.0, start="inv_sqrt_lmax", start_value=lam[-1], sym_delta=True)
+    Zref = inv_sqrt(D)
+    assert np.linalg.norm(Z - Zref) <= 1e-10 * np.linalg.norm(Zref) * 100
+    assert R.true_residual(D, Z) <= 1e-12
+    pred = predicted_norms(1.0 - c * c * lam, 4, info.iterations)
+    for got, want in zip(info.norms, pred):
+        if want > 1e-9:
+            assert abs(got - want) <= 1e-9 * want + 1e-12
+    Zl, plan = R.lif(D, 32, 0.0, base_rows=128, sym_delta=True)
+    assert np.linalg.norm(Zl - lif_limit(D, 32, 128)) <= 1e-12 * np.linalg.norm(Zl)
+    # the mirror: a matrix with a ragged last block, upper part kept, lower rebuilt
+    A = np.arange(49.0).reshape(7, 7)
+    U = R.upper_blocks(A, 3)
+    assert U[4, 1] == 0.0 and U[1, 4] == A[1, 4] and U[4, 4] == A[4, 4] and U[5, 6] == A[5, 6] and U[6, 5] == 0.0
+    assert R.upper_blocks(A, 3, strict=True)[4, 4] == 0.0
+
+
 def test_mixed_refinement_reaches_fp64_accuracy(water100):
     # the refinement wins back the accuracy lost in the correction products:
     # with FP64 delta updates the tracked delta is the true residual, and TOL
