@@ -102,7 +102,7 @@ def time_method(lif, Sd, tau, meth, steps, **kw):
     return s, info
 
 
-def water_comparison(lif, count, which=("fp64", "fp32_schedule", "bf16_schedule")):
+def water_comparison(lif, count, which=("fp64", "fp64_sym", "fp32_schedule_sym", "bf16_schedule_sym")):
     """FP64 against the scheduled FP32 / BF16 corrections on a water cluster
     (tau = 1e-8, b = 64, LIF to 4096-row leaves): compute-bound products, the
     regime where reduced precision pays.  One untimed and one timed
@@ -115,12 +115,16 @@ def water_comparison(lif, count, which=("fp64", "fp32_schedule", "bf16_schedule"
                                     bcol=torch.from_numpy(S.bcol).cuda(), vals=torch.from_numpy(S.vals).cuda()))
     out = {"workload": f"water-{count}: {count} molecules x 7 s-Gaussians, n={S.n}, b=64, tau={cfg['tau']}, "
                        f"LIF to 4096-row leaves, m=4, paper stop", "n": S.n}
-    t64 = None
-    for name, prec, sw in (("fp64", lif.FP64, 0.0), ("fp32_schedule", lif.MIXED_FP32, 1e-2),
-                           ("bf16_schedule", lif.MIXED_BF16, 1e-2)):
+    t64 = {}
+    for name, prec, sw, sym in (("fp64", lif.FP64, 0.0, 0), ("fp64_sym", lif.FP64, 0.0, 1),
+                                ("fp32_schedule", lif.MIXED_FP32, 1e-2, 0),
+                                ("bf16_schedule", lif.MIXED_BF16, 1e-2, 0),
+                                ("fp32_schedule_sym", lif.MIXED_FP32, 1e-2, 1),
+                                ("bf16_schedule_sym", lif.MIXED_BF16, 1e-2, 1)):
         if name not in which:
             continue
-        f = lif.Factorization(Sd, tau=cfg["tau"], base_rows=4096, prec=prec, prec_switch=sw, timing=1)
+        f = lif.Factorization(Sd, tau=cfg["tau"], base_rows=4096, prec=prec, prec_switch=sw, timing=1,
+                              sym_delta=sym)
         f.localized()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -134,11 +138,16 @@ def water_comparison(lif, count, which=("fp64", "fp32_schedule", "bf16_schedule"
         out[name] = {"s_per_factorization": s, "residual": res, "iterations_total": info["iterations_total"],
                      "iterations_reduced": info["iterations_reduced"], "leaf_gemm_tflops": gemm_tf,
                      "mem_peak_gib": info["mem_peak_bytes"] / 2 ** 30}
+        out[name]["sym_delta"] = sym
         if prec == lif.FP64:
-            t64 = s
+            t64[sym] = s
             out[name]["leaf_gemm_frac_of_fp64_peak"] = gemm_tf / PEAK_FP64_MFMA_TFLOPS if gemm_tf else None
-        elif t64:
-            out[name]["speedup_vs_fp64"] = t64 / s
+        else:
+            # against FP64 with the same delta update, and against the plain FP64 run
+            if sym in t64:
+                out[name]["speedup_vs_fp64_same_update"] = t64[sym] / s
+            if 0 in t64:
+                out[name]["speedup_vs_fp64"] = t64[0] / s
         print(f"# water-{count} {name}: {s:.2f} s, residual {res:.3e}", file=sys.stderr, flush=True)
     return out
 
@@ -179,11 +188,14 @@ def main():
     ap.add_argument("--rinch-steps", type=int, default=2)
     ap.add_argument("--no-variants", action="store_true",
                     help="skip IRSI and the regular-form recursive factorization on the same matrix")
+    ap.add_argument("--sym-delta", action="store_true",
+                    help="chain runs with opts.sym_delta = 1 (upper-triangle delta update)")
     ap.add_argument("--no-water", action="store_true",
                     help="skip the FP64 vs scheduled mixed-precision comparison on the water-5000 cluster")
     ap.add_argument("--water-count", type=int, default=5000, help="molecules of that water cluster")
     ap.add_argument("--water-only", type=str, default="",
-                    help="comma-separated subset of fp64,fp32_schedule,bf16_schedule: run only the water "
+                    help="comma-separated subset of fp64,fp64_sym,fp32_schedule,bf16_schedule,"
+                         "fp32_schedule_sym,bf16_schedule_sym: run only the water "
                          "comparison with these (one JSON line) and exit")
     ap.add_argument("--cpl-sweep", type=str, default="",
                     help="comma-separated chain lengths: print critical-path task counts and times of "
@@ -228,7 +240,7 @@ def main():
                                     bcol=torch.from_numpy(S.bcol).cuda(), vals=torch.from_numpy(S.vals).cuda()))
     def run(prec, stop, tol, prec_switch=0.0):
         f = lif.Factorization(Sd, tau=cfg["tau"], base_rows=4096, stop=stop, tol=tol, prec=prec, timing=1,
-                              prec_switch=prec_switch)
+                              prec_switch=prec_switch, sym_delta=1 if args.sym_delta else 0)
         torch.cuda.synchronize()
         for w in range(args.warmup):
             info = f.localized()

@@ -64,6 +64,9 @@ typedef int32_t lif_status;
 #define LIF_REFINE_NONLOCAL 1  /* eq. refinement_nonlocal: delta_i = I - (Z_i^T S) Z_i recomputed every
                                 * iteration, Z_{i+1} = Z_i P(delta_i), every product truncated; FP64 only */
 
+/* lif_multiply: flag in transA */
+#define LIF_PRODUCT_UPPER 2
+
 /* lif_opts.start: scale c of the IRSI start Z_0 = c I (Sec. 2.2) */
 #define LIF_START_SQRT2_OVER_GERSH 0  /* c = sqrt(2 / beta), beta the Gershgorin bound of S */
 #define LIF_START_INV_SQRT_GERSH   1  /* c = 1 / sqrt(beta) */
@@ -108,6 +111,9 @@ typedef struct {
                            * exceeds prec_switch, in FP64 after; such reduced iterations converge
                            * linearly and are checked for divergence only, the stopping rule judges the
                            * FP64 ones (so LIF_STOP_PAPER stops at the FP64 floor) */
+  int32_t sym_delta;      /* 1: delta (symmetric in exact arithmetic) is updated on its upper block triangle
+                           * only, the update's two products forming just those blocks, and the strictly
+                           * upper part is mirrored below (localized refinement); 0: the full update */
 } lif_opts;
 
 typedef struct {
@@ -139,7 +145,7 @@ typedef struct {
 /* Fills *o with the defaults: m = 4, tau = 0, FP64, paper stopping rule,
  * tol = 1e-10, max_iter = 100, base_rows = 4096, start = SQRT2_OVER_GERSH,
  * checkpoint = 0, no cap, null stream, timing = 0, presize = 1,
- * refinement = LIF_REFINE_LOCAL, prec_switch = 0. */
+ * refinement = LIF_REFINE_LOCAL, prec_switch = 0, sym_delta = 0. */
 lif_status lif_opts_default(lif_opts* o);
 
 /* Validates S and copies it into library-owned device memory (the caller may
@@ -196,7 +202,9 @@ lif_status lif_residual(lif_handle h, double* out);
 
 /* C = op(A) op(B) truncated at tau: the block-sparse product of Sec. 4 with
  * the leaf truncation of Sec. 5, on the handle's stream and memory.  op is
- * the identity (trans = 0) or the transpose (trans = 1).  A and B must have
+ * the identity (bit 0 of trans clear) or the transpose (bit 0 set); with
+ * LIF_PRODUCT_UPPER set in transA only the output blocks (i, j) with j >= i
+ * are formed (the upper block triangle).  A and B must have
  * the handle's n and b.  The product uses the handle's opts.prec: FP64, or
  * inputs rounded to FP32 / BF16 (round to nearest even; BF16 via FP32) with
  * FP32 accumulation and an FP64 result.  Two-phase output like lif_get_Z (the product is

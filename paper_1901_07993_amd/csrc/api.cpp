@@ -43,6 +43,7 @@ void validate_opts(const lif_opts& o) {
               "opts.refinement = LIF_REFINE_NONLOCAL needs prec = LIF_FP64");
   LIF_REQUIRE(std::isfinite(o.prec_switch) && o.prec_switch >= 0.0, LIF_ERR_INVALID,
               "opts.prec_switch must be finite and >= 0");
+  LIF_REQUIRE(o.sym_delta == 0 || o.sym_delta == 1, LIF_ERR_INVALID, "opts.sym_delta must be 0 or 1");
   if (o.start == LIF_START_INV_SQRT_LMAX || o.start == LIF_START_GIVEN)
     LIF_REQUIRE(std::isfinite(o.start_value) && o.start_value > 0.0, LIF_ERR_INVALID,
                 "opts.start_value must be > 0 for this start");
@@ -213,6 +214,7 @@ lif_status lif_opts_default(lif_opts* o) {
   o->presize = 1;
   o->refinement = LIF_REFINE_LOCAL;
   o->prec_switch = 0.0;
+  o->sym_delta = 0;
   return LIF_OK;
 }
 
@@ -243,6 +245,7 @@ lif_status lif_create(const lif_blocks* S, const lif_opts* o, lif_handle* out) {
     p.presize = o->presize;
     p.refinement = o->refinement;
     p.prec_switch = o->prec_switch;
+    p.sym_delta = o->sym_delta != 0;
     Ctx& c = h->ctx;
     c.stream = static_cast<hipStream_t>(o->stream);
     c.pool = &h->pool;
@@ -366,7 +369,10 @@ lif_status lif_multiply(lif_handle h, const lif_blocks* A, int32_t transA, const
     reset_stats(h);
     Bsr a = bsr_from_blocks(h->ctx, *A);
     Bsr b = bsr_from_blocks(h->ctx, *B);
-    Bsr C = spgemm(h->ctx, a, transA != 0, b, transB != 0, tau, h->opts.prec);
+    LIF_REQUIRE((transA & ~(1 | LIF_PRODUCT_UPPER)) == 0 && (transB & ~1) == 0, LIF_ERR_INVALID,
+                "transA / transB: unknown flags");
+    Bsr C = spgemm(h->ctx, a, (transA & 1) != 0, b, (transB & 1) != 0, tau, h->opts.prec, 1.0, nullptr, 0.0,
+                   false, false, (transA & LIF_PRODUCT_UPPER) != 0);
     if (products) *products = h->ctx.stats.products;
     st = copy_out(h, C, nnzb, brow, bcol, vals, on_device);
     h->ctx.sync();

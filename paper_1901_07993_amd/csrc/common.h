@@ -445,13 +445,15 @@ void launch_phi_diag(Ctx& c, const int* row_of, const int* col, int64_t nnzb, in
 // Operands with holes: `ahole`/`bhole` are their block pointers (null for an
 // operand without holes), indexed through aidx/bidx like ablk/bblk; a null
 // block takes no part in the product.
+// `upper`: only the output blocks (i, j) with j >= i are formed (the upper
+// block triangle of a product known to be symmetric).
 void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp,
                            const int* bcol, const int* bidx, BlkIn ahole, BlkIn bhole, const int* drp,
-                           const int* dcol, int nb, int* cnt_c, int64_t* cnt_p);
+                           const int* dcol, int nb, int* cnt_c, int64_t* cnt_p, bool upper = false);
 void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp,
                           const int* bcol, const int* bidx, BlkIn ablk, BlkIn bblk, bool a_holes, bool b_holes,
                           const int* drp, const int* dcol, BlkIn dblk, int nb, const int* crp, const int64_t* prp,
-                          int* ccol, int64_t* seg, BlockPair* pairs, BlkOut dsrc);
+                          int* ccol, int64_t* seg, BlockPair* pairs, BlkOut dsrc, bool upper = false);
 // Symbolic phase in one launch when the capacities are known in advance:
 // counts, the prefix sums of the row counts (decoupled look-back) and the
 // fill.  Writes crp[0..nb]; totals to sizes[0..1]; when a total exceeds its
@@ -462,7 +464,7 @@ void launch_symbolic_onepass(Ctx& c, const int* arp, const int* acol, const int*
                              const int* bcol, const int* bidx, BlkIn ablk, BlkIn bblk, bool a_holes, bool b_holes,
                              const int* drp, const int* dcol, BlkIn dblk, int nb, int64_t cap_c, int64_t cap_p,
                              int* crp, int* ccol, int64_t* seg, BlockPair* pairs, BlkOut dsrc, int64_t* sizes,
-                             int* overflow);
+                             int* overflow, bool upper = false);
 // Fused terms of a product: the output block is alpha sum op(A) op(B)
 // + gamma D_e, D_e = dsrc[e] (skipped where null), and its norm is the norm
 // of that sum (truncation then applies to the whole block).
@@ -576,9 +578,11 @@ void task_after(Ctx& c, Bsr& out, bool product, std::initializer_list<const Bsr*
 // copies (made here when missing); `out_lp`: with keep_holes, the result
 // also gets its transposed copy ([1]) in that precision, for a later
 // reduced-precision product that takes it as right operand.
+// `upper`: only the output blocks (i, j) with j >= i (the upper block
+// triangle, for a product whose caller uses only that part).
 Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec = LIF_FP64,
            double alpha = 1.0, const Bsr* D = nullptr, double gamma = 0.0, bool keep_holes = false,
-           bool out_lp = false);
+           bool out_lp = false, bool upper = false);
 // makes A.lp[layout] hold A's blocks in precision prec (no-op when it does)
 void ensure_shadow(Ctx& c, const Bsr& A, int prec, int layout);
 // alpha A + beta B + gamma I on the block rows with diag_on set (A or B may be null)

@@ -131,6 +131,40 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
   std::vector<char> red(nn, 0);
   std::vector<int> lab_red(nb), lab_full(nb);
   DBuf<int> d_lab_red, d_lab_full;
+  // symmetric delta: block-index labels (i and i + 1) select the upper and
+  // the strictly upper block triangles
+  std::vector<int> iota, iota1;
+  DBuf<int> d_iota, d_iota1;
+  if (o.sym_delta) {
+    iota.resize(nb);
+    iota1.resize(nb);
+    for (int i = 0; i < nb; ++i) {
+      iota[i] = i;
+      iota1[i] = i + 1;
+    }
+    d_iota = DBuf<int>(c.pool, nb);
+    d_iota1 = DBuf<int>(c.pool, nb);
+    h2d(c, d_iota.get(), iota.data(), nb);
+    h2d(c, d_iota1.get(), iota1.data(), nb);
+  }
+  // delta_{k+1} from delta_k and the two products: the full difference, or
+  // with a symmetric delta the difference on the upper block triangle (the
+  // products hold only those blocks) with its strictly upper part mirrored
+  auto delta_update = [&](const Bsr& X1, const Bsr& X2) {
+    if (!o.sym_delta) return axpby3(c, 1.0, &delta, -1.0, &X1, -1.0, &X2);
+    Bsr U;
+    {
+      Bsr dU = filter(c, delta, d_iota.get(), d_iota.get(), 3);
+      U = axpby3(c, 1.0, &dU, -1.0, &X1, -1.0, &X2);
+    }
+    Bsr L;
+    {
+      Bsr SU = filter(c, U, d_iota1.get(), d_iota.get(), 3);
+      L = transpose(c, SU);
+    }
+    return axpby(c, 1.0, &U, 1.0, &L, 0.0, nullptr);
+  };
+  const bool up = o.sym_delta;
   if (!c.spec.sizes.get()) {
     c.spec.sizes = DBuf<int64_t>(c.pool, 2 * Ctx::Spec::kSlots);
     c.spec.overflow = DBuf<int>(c.pool, 1);
@@ -299,10 +333,10 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
         Bsr SM = spgemm(c, S, false, M, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles);
         Znew = axpby(c, 1.0, &Z, 1.0, &M, 0.0, nullptr);
         M = Bsr();
-        Bsr X2 = spgemm(c, SM, true, Z, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles);
-        Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles);
+        Bsr X2 = spgemm(c, SM, true, Z, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles, false, up);
+        Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles, false, up);
         SM = Bsr();
-        dnew = axpby3(c, 1.0, &delta, -1.0, &X1, -1.0, &X2);
+        dnew = delta_update(X1, X2);
       } else {
       // S M and then (S M)^T Z_k run on the side stream while Z + M and then
       // Z_{k+1}^T (S M) run on the main one; buffers freed meanwhile are
@@ -318,13 +352,13 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       c.stream_after(main_s, side_s);  // S M is complete
       {
         StreamScope on_side(c, side_s);
-        X2 = spgemm(c, SM, true, Z, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles);
+        X2 = spgemm(c, SM, true, Z, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles, false, up);
       }
-      Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles);
+      Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles, false, up);
       c.stream_after(main_s, side_s);  // (S M)^T Z_k is complete
       M = Bsr();
       SM = Bsr();
-      dnew = axpby3(c, 1.0, &delta, -1.0, &X1, -1.0, &X2);
+      dnew = delta_update(X1, X2);
       X1 = Bsr();
       X2 = Bsr();
       }

@@ -21,6 +21,7 @@ struct Opts {
   int presize = 1;  // 0 off, 1 with margins, 2 previous counts as they are
   int refinement = LIF_REFINE_LOCAL;
   double prec_switch = 0.0;  // > 0: reduced precision only while ||delta||_F exceeds it
+  bool sym_delta = false;    // update delta's upper block triangle and mirror it
 };
 
 // One node of the split tree: scalar rows [lo, hi), lo a multiple of b.

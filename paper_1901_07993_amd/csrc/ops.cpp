@@ -274,7 +274,7 @@ Bsr numeric_phase(Ctx& c, Bsr&& C, bool ta, bool tb, double tau, int prec, doubl
 namespace {
 
 Bsr spgemm_body(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec, double alpha,
-                const Bsr* D, double gamma, bool keep_holes, bool out_lp) {
+                const Bsr* D, double gamma, bool keep_holes, bool out_lp, bool upper) {
   LIF_REQUIRE(A.nb == B.nb && A.b == B.b, LIF_ERR_INVALID, "spgemm: operand shapes differ");
   // block pointers the pairs are built from: the FP64 blocks, or for a
   // reduced-precision product op(A)'s blocks row-major and op(B)'s blocks
@@ -341,14 +341,14 @@ Bsr spgemm_body(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau
     launch_symbolic_onepass(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, pa, pb, A.holes, B.holes,
                             drp, dcol, D ? D->ptrs() : nullptr, nb, nnzc, P, C.row_ptr.get(), C.col.get(),
                             seg.get(), pairs.get(), D ? dsrc.get() : nullptr, c.spec.sizes.get() + 2 * slot,
-                            c.spec.overflow.get());
+                            c.spec.overflow.get(), upper);
     return numeric_phase(c, std::move(C), ta, tb, tau, prec, alpha, D ? dsrc.get() : nullptr, gamma, keep_holes,
                          seg.get(), pairs.get(), nnzc, c.spec.overflow.get(), out_lp);
   }
   DBuf<int> cnt_c(c.pool, nb);
   DBuf<int64_t> cnt_p(c.pool, nb);
   launch_symbolic_count(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, A.holes ? pa : nullptr,
-                        B.holes ? pb : nullptr, drp, dcol, nb, cnt_c.get(), cnt_p.get());
+                        B.holes ? pb : nullptr, drp, dcol, nb, cnt_c.get(), cnt_p.get(), upper);
   prp = DBuf<int64_t>(c.pool, nb + 1);
   if (planned) {
     const size_t slot = c.spec.next++;
@@ -389,7 +389,7 @@ Bsr spgemm_body(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau
   if (nnzc)
     launch_symbolic_fill(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, pa, pb, A.holes, B.holes,
                          drp, dcol, D ? D->ptrs() : nullptr, nb, C.row_ptr.get(), prp.get(), C.col.get(), seg.get(),
-                         pairs.get(), D ? dsrc.get() : nullptr);
+                         pairs.get(), D ? dsrc.get() : nullptr, upper);
   return numeric_phase(c, std::move(C), ta, tb, tau, prec, alpha, D ? dsrc.get() : nullptr, gamma, keep_holes,
                        seg.get(), pairs.get(), nnzc, nullptr, out_lp);
 }
@@ -397,8 +397,8 @@ Bsr spgemm_body(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau
 }  // namespace
 
 Bsr spgemm(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau, int prec, double alpha,
-           const Bsr* D, double gamma, bool keep_holes, bool out_lp) {
-  Bsr C = spgemm_body(c, A, ta, B, tb, tau, prec, alpha, D, gamma, keep_holes, out_lp);
+           const Bsr* D, double gamma, bool keep_holes, bool out_lp, bool upper) {
+  Bsr C = spgemm_body(c, A, ta, B, tb, tau, prec, alpha, D, gamma, keep_holes, out_lp, upper);
   // with an operand known to be empty only the scaled added term remains
   const bool scaling = A.nnzb == 0 || B.nnzb == 0;
   task_after(c, C, !scaling, {&A, &B, D});

@@ -38,11 +38,14 @@ constexpr int kSymWG = 256;
 // Operands with holes: a block whose pointer is null is absent.  `a`/`b`
 // are the block pointers of such an operand (null for one without holes),
 // reached through the view's index arrays.
+// `jmin`: output columns below it are not formed (the upper block triangle
+// of a product: jmin = the row).
 struct Holes {
   BlkIn a = nullptr;
   const int* aidx = nullptr;
   BlkIn b = nullptr;
   const int* bidx = nullptr;
+  int jmin = 0;
   __device__ bool a_absent(int e) const { return a && !a[aidx ? aidx[e] : e]; }
   __device__ bool b_absent(int f) const { return b && !b[bidx ? bidx[f] : f]; }
 };
@@ -58,19 +61,22 @@ __device__ inline void build_row_bitmap(const int* __restrict__ arp, const int* 
   if (drp)
     for (int e = drp[i] + threadIdx.x; e < drp[i + 1]; e += kSymWG) {
       const int j = dcol[e];
+      if (j < h.jmin) continue;
       atomicOr(&bm[j >> 5], 1u << (j & 31));
     }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool each = h.b || h.jmin > 0;  // products counted one by one
   int64_t p = 0;
   for (int e = arp[i] + wave; e < arp[i + 1]; e += kSymWG / 64) {
     if (h.a_absent(e)) continue;  // uniform over the wave
     const int k = acol[e];
     const int lo = brp[k], hi = brp[k + 1];
-    if (!h.b && lane == 0) p += hi - lo;
+    if (!each && lane == 0) p += hi - lo;
     for (int f = lo + lane; f < hi; f += 64) {
       if (h.b_absent(f)) continue;
-      if (h.b) ++p;
       const int j = bcol[f];
+      if (j < h.jmin) continue;
+      if (each) ++p;
       atomicOr(&bm[j >> 5], 1u << (j & 31));
     }
   }
@@ -81,12 +87,13 @@ __device__ inline void build_row_bitmap(const int* __restrict__ arp, const int* 
 __global__ __launch_bounds__(kSymWG) void k_symbolic_count(const int* __restrict__ arp, const int* __restrict__ acol,
                                                            const int* __restrict__ brp, const int* __restrict__ bcol,
                                                            Holes h, const int* __restrict__ drp,
-                                                           const int* __restrict__ dcol, int nb,
+                                                           const int* __restrict__ dcol, int nb, bool upper,
                                                            int* __restrict__ cnt_c, int64_t* __restrict__ cnt_p) {
   extern __shared__ unsigned smem[];
   __shared__ int64_t red_p[kSymWG];
   __shared__ int red_c[kSymWG];
   const int i = blockIdx.x;
+  h.jmin = upper ? i : 0;
   const int nwords = (nb + 31) >> 5;
   unsigned* bm = smem;
   int64_t p = 0;
@@ -118,7 +125,7 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
                                                           BlkIn ablk, BlkIn bblk, bool a_holes, bool b_holes,
                                                           const int* __restrict__ drp,
                                                           const int* __restrict__ dcol, BlkIn dblk, int nb,
-                                                          const int* __restrict__ crp,
+                                                          bool upper, const int* __restrict__ crp,
                                                           const int64_t* __restrict__ prp, int* __restrict__ ccol,
                                                           int64_t* __restrict__ seg, BlockPair* __restrict__ pairs,
                                                           BlkOut dsrc) {
@@ -129,7 +136,7 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
   unsigned* bm = smem;
   int* wp = reinterpret_cast<int*>(smem + nwords);
   int* cur = wp + nwords;
-  const Holes h{a_holes ? ablk : nullptr, aidx, b_holes ? bblk : nullptr, bidx};
+  const Holes h{a_holes ? ablk : nullptr, aidx, b_holes ? bblk : nullptr, bidx, upper ? i : 0};
   build_row_bitmap(arp, acol, brp, bcol, h, drp, dcol, i, bm, nwords, nullptr);
 
   // exclusive prefix of word popcounts: contiguous chunks per thread
@@ -166,6 +173,7 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
   if (dsrc)
     for (int e = drp[i] + threadIdx.x; e < drp[i + 1]; e += kSymWG) {
       const int j = dcol[e];
+      if (j < h.jmin) continue;
       dsrc[cbase + wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u))] = dblk[e];
     }
 
@@ -177,6 +185,7 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
     for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
       if (h.b_absent(f)) continue;
       const int j = bcol[f];
+      if (j < h.jmin) continue;
       const int r = wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u));
       atomicAdd(&cur[r], 1);
     }
@@ -212,6 +221,7 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
         const double* bp = bblk[bidx ? bidx[f] : f];
         if (b_holes && !bp) continue;
         const int j = bcol[f];
+        if (j < h.jmin) continue;
         const int r = wp[j >> 5] + __popc(bm[j >> 5] & ((1u << (j & 31)) - 1u));
         const int pos = cur[r];
         pairs[prow + pos] = BlockPair{a, bp};
@@ -256,7 +266,7 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill_masked(
     const int* __restrict__ arp, const int* __restrict__ acol, const int* __restrict__ aidx,
     const int* __restrict__ brp, const int* __restrict__ bcol, const int* __restrict__ bidx, BlkIn ablk,
     BlkIn bblk, bool a_holes, bool b_holes, const int* __restrict__ drp, const int* __restrict__ dcol, BlkIn dblk,
-    int nb, int* __restrict__ crp, const int64_t* __restrict__ prp, int* __restrict__ ccol,
+    int nb, bool upper, int* __restrict__ crp, const int64_t* __restrict__ prp, int* __restrict__ ccol,
     int64_t* __restrict__ seg, BlockPair* __restrict__ pairs, BlkOut dsrc, OnePass op) {
   extern __shared__ unsigned long long smem64[];
   __shared__ int scan_tmp[kSymWG / 64];
@@ -269,7 +279,7 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill_masked(
   unsigned* bm = reinterpret_cast<unsigned*>(smem64 + nb);
   int* wp = reinterpret_cast<int*>(bm + nwords);
   int* cur = wp + nwords;
-  const Holes h{a_holes ? ablk : nullptr, aidx, b_holes ? bblk : nullptr, bidx};
+  const Holes h{a_holes ? ablk : nullptr, aidx, b_holes ? bblk : nullptr, bidx, upper ? i : 0};
   int64_t pcount = 0;
   build_row_bitmap(arp, acol, brp, bcol, h, drp, dcol, i, bm, nwords, ONEPASS ? &pcount : nullptr);
 
@@ -319,7 +329,9 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill_masked(
       const unsigned long long bit = 1ull << (e - e0);
       for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
         if (h.b_absent(f)) continue;
-        atomicOr(&mask[rank(bcol[f])], bit);
+        const int j = bcol[f];
+        if (j < h.jmin) continue;
+        atomicOr(&mask[rank(j)], bit);
       }
     }
   };
@@ -334,7 +346,9 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill_masked(
       for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
         const double* bp = bblk[bidx ? bidx[f] : f];
         if (b_holes && !bp) continue;
-        const int r = rank(bcol[f]);
+        const int j = bcol[f];
+        if (j < h.jmin) continue;
+        const int r = rank(j);
         pairs[prow + cur[r] + __popcll(mask[r] & below)] = BlockPair{a, bp};
       }
     }
@@ -426,6 +440,7 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill_masked(
   if (dsrc)  // D's blocks at their output positions
     for (int e = drp[i] + threadIdx.x; e < drp[i + 1]; e += kSymWG) {
       const int j = dcol[e];
+      if (j < h.jmin) continue;
       dsrc[cbase + rank(j)] = dblk[e];
     }
 
@@ -674,30 +689,30 @@ static void allow_lds(const void* fn, size_t bytes) {
 
 void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp,
                            const int* bcol, const int* bidx, BlkIn ahole, BlkIn bhole, const int* drp,
-                           const int* dcol, int nb, int* cnt_c, int64_t* cnt_p) {
+                           const int* dcol, int nb, int* cnt_c, int64_t* cnt_p, bool upper) {
   allow_lds((const void*)k_symbolic_count, symbolic_lds_bytes(nb, false));
   const Holes h{ahole, aidx, bhole, bidx};
   hipLaunchKernelGGL(k_symbolic_count, dim3(nb), dim3(kSymWG), symbolic_lds_bytes(nb, false), c.stream, arp, acol,
-                     brp, bcol, h, drp, dcol, nb, cnt_c, cnt_p);
+                     brp, bcol, h, drp, dcol, nb, upper, cnt_c, cnt_p);
   LIF_HIP(hipGetLastError());
 }
 
 void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp, const int* bcol,
                           const int* bidx, BlkIn ablk, BlkIn bblk, bool a_holes, bool b_holes, const int* drp,
                           const int* dcol, BlkIn dblk, int nb, const int* crp, const int64_t* prp, int* ccol,
-                          int64_t* seg, BlockPair* pairs, BlkOut dsrc) {
+                          int64_t* seg, BlockPair* pairs, BlkOut dsrc, bool upper) {
   if (masked_fill_lds_bytes(nb) <= kMaskedFillLds) {
     allow_lds((const void*)k_symbolic_fill_masked<false>, masked_fill_lds_bytes(nb));
     hipLaunchKernelGGL(k_symbolic_fill_masked<false>, dim3(nb), dim3(kSymWG), masked_fill_lds_bytes(nb), c.stream,
-                       arp, acol, aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb,
+                       arp, acol, aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb, upper,
                        const_cast<int*>(crp), prp, ccol, seg, pairs, dsrc, OnePass{});
     LIF_HIP(hipGetLastError());
     return;
   }
   allow_lds((const void*)k_symbolic_fill, symbolic_lds_bytes(nb, true));
   hipLaunchKernelGGL(k_symbolic_fill, dim3(nb), dim3(kSymWG), symbolic_lds_bytes(nb, true), c.stream, arp, acol,
-                     aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb, crp, prp, ccol, seg,
-                     pairs, dsrc);
+                     aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb, upper, crp, prp, ccol,
+                     seg, pairs, dsrc);
   LIF_HIP(hipGetLastError());
 }
 
@@ -707,7 +722,7 @@ void launch_symbolic_onepass(Ctx& c, const int* arp, const int* acol, const int*
                              const int* bcol, const int* bidx, BlkIn ablk, BlkIn bblk, bool a_holes, bool b_holes,
                              const int* drp, const int* dcol, BlkIn dblk, int nb, int64_t cap_c, int64_t cap_p,
                              int* crp, int* ccol, int64_t* seg, BlockPair* pairs, BlkOut dsrc, int64_t* sizes,
-                             int* overflow) {
+                             int* overflow, bool upper) {
   OnePass op;
   op.lb = c.lookback_words(nb);
   op.cap_c = cap_c;
@@ -716,8 +731,8 @@ void launch_symbolic_onepass(Ctx& c, const int* arp, const int* acol, const int*
   op.overflow = overflow;
   allow_lds((const void*)k_symbolic_fill_masked<true>, masked_fill_lds_bytes(nb));
   hipLaunchKernelGGL(k_symbolic_fill_masked<true>, dim3(nb), dim3(kSymWG), masked_fill_lds_bytes(nb), c.stream, arp,
-                     acol, aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb, crp, nullptr,
-                     ccol, seg, pairs, dsrc, op);
+                     acol, aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb, upper, crp,
+                     nullptr, ccol, seg, pairs, dsrc, op);
   LIF_HIP(hipGetLastError());
 }
 

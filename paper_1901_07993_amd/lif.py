@@ -23,6 +23,7 @@ FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
 STOP_PAPER, STOP_TOL = 0, 1
 START_SQRT2_OVER_GERSH, START_INV_SQRT_GERSH, START_INV_SQRT_LMAX, START_GIVEN = 0, 1, 2, 3
 REFINE_LOCAL, REFINE_NONLOCAL = 0, 1
+PRODUCT_UPPER = 2
 
 _STATUS_NAMES = {1: "LIF_ERR_INVALID", 2: "LIF_ERR_NOT_PD", 3: "LIF_ERR_NO_CONVERGENCE",
                  4: "LIF_ERR_OUT_OF_MEMORY", 5: "LIF_ERR_HIP", 6: "LIF_ERR_STATE"}
@@ -46,7 +47,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("m", c_int32), ("tau", c_double), ("prec", c_int32), ("stop", c_int32), ("tol", c_double),
                 ("max_iter", c_int32), ("base_rows", c_int64), ("start", c_int32), ("start_value", c_double),
                 ("checkpoint", c_int32), ("mem_cap_bytes", c_uint64), ("stream", c_void_p), ("timing", c_int32),
-                ("presize", c_int32), ("refinement", c_int32), ("prec_switch", c_double)]
+                ("presize", c_int32), ("refinement", c_int32), ("prec_switch", c_double),
+                ("sym_delta", c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -163,7 +165,7 @@ class Factorization:
 
     Keyword options mirror ``lif_opts``: m, tau, prec, stop, tol, max_iter,
     base_rows, start, start_value, checkpoint, mem_cap_bytes, timing, presize,
-    refinement, prec_switch.
+    refinement, prec_switch, sym_delta.
     """
 
     def __init__(self, S, **opts):
@@ -221,8 +223,10 @@ class Factorization:
         self._check(load().lif_residual(self._h, byref(out)))
         return out.value
 
-    def multiply(self, A, transA: bool, B, transB: bool, tau: float = 0.0):
-        """C = op(A) op(B) truncated at tau; returns (HostBlocks, products)."""
+    def multiply(self, A, transA: bool, B, transB: bool, tau: float = 0.0, upper: bool = False):
+        """C = op(A) op(B) truncated at tau (only its upper block triangle when
+        ``upper``); returns (HostBlocks, products)."""
+        transA = int(transA) | (PRODUCT_UPPER if upper else 0)
         lib = load()
         sa, ka = _marshal(A)
         sb, kb = _marshal(B)

@@ -1,0 +1,120 @@
+"""GPU parity of the symmetric delta update: products formed on their upper
+block triangle only (lif_multiply with LIF_PRODUCT_UPPER), and refinement
+with opts.sym_delta = 1 against the oracle's sym_delta form.
+
+Tolerances as for the full forms: an upper product's blocks are those of the
+full product (the same pairs in the same order), so values agree with the
+dense reference to 1e-13 relative and the pattern and block-product count
+exactly; refinement at tau = 0 agrees to 1e-11 of the largest entry of Z,
+at tau > 0 within a tau-scaled bound, with equal iteration counts.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gen import blocks_to_dense, config_matrix, overlap_blocks, water_cluster  # noqa: E402
+from oracle import refinement as R  # noqa: E402
+from paper_1901_07993_amd import lif  # noqa: E402
+
+from test_gpu_parity import dev, identity_blocks, random_block_sparse  # noqa: E402
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not torch.cuda.is_available(), reason="no GPU")]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _patterns(A, ta, B, tb, nb):
+    pa = np.zeros((nb, nb), bool)
+    pa[A.brow, A.bcol] = True
+    pb = np.zeros((nb, nb), bool)
+    pb[B.brow, B.bcol] = True
+    pa = pa.T if ta else pa
+    pb = pb.T if tb else pb
+    return pa.astype(np.int64) @ pb.astype(np.int64)
+
+
+@pytest.mark.parametrize("b,n,density", [(32, 200, 0.3), (64, 300, 0.3), (32, 150 * 32 - 9, 0.9)])
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
+def test_upper_product_matches_oracle(b, n, density, ta, tb):
+    # the last case has rows of more than 64 blocks (several runs of masks)
+    say(f"case upper multiply b={b} n={n} density={density} ta={ta} tb={tb}")
+    A = random_block_sparse(n, b, density, 21)
+    B = random_block_sparse(n, b, density, 22)
+    with lif.Factorization(identity_blocks(n, b)) as f:
+        C, prods = f.multiply(dev(A), ta, dev(B), tb, 0.0, upper=True)
+    Da, Db = blocks_to_dense(A), blocks_to_dense(B)
+    ref = R.upper_blocks((Da.T if ta else Da) @ (Db.T if tb else Db), b)
+    nb = (n + b - 1) // b
+    cnt = _patterns(A, ta, B, tb, nb)
+    up = np.triu(np.ones((nb, nb), bool))
+    assert prods == int(cnt[up].sum())
+    gc = np.zeros((nb, nb), bool)
+    gc[C.brow, C.bcol] = True
+    assert np.array_equal(gc, (cnt > 0) & up)
+    got = blocks_to_dense(C)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref))) * math.sqrt(n)
+
+
+def test_sym_delta_irsi_water100():
+    S, _ = config_matrix(0)
+    D = blocks_to_dense(S)
+    lam = float(np.linalg.eigvalsh(D)[-1])
+    say("case sym-delta irsi water-100")
+    with lif.Factorization(dev(S), start=lif.START_INV_SQRT_LMAX, start_value=lam, sym_delta=1) as f:
+        info = f.refine()
+        Z = blocks_to_dense(f.get_Z())
+        res = f.residual()
+    Zo, oi, _ = R.irsi(D, 32, 0.0, start="inv_sqrt_lmax", start_value=lam, sym_delta=True)
+    say(f"  gpu iterations {info['iterations_top']} oracle {oi.iterations}")
+    assert info["iterations_top"] == oi.iterations
+    for g, o in zip(info["norms"], oi.norms):
+        assert abs(g - o) <= 1e-9 * o + 1e-13
+    assert np.max(np.abs(Z - Zo)) <= 1e-11 * np.max(np.abs(Zo))
+    assert res <= 1e-12
+
+
+@pytest.mark.parametrize("b,n_mol,base,tau", [(32, 200, 256, 0.0), (32, 200, 256, 1e-6), (64, 150, 320, 1e-7)])
+def test_sym_delta_lif_water_matches_oracle(b, n_mol, base, tau):
+    c_, e_ = water_cluster(n_mol, 7)
+    S = overlap_blocks(c_, e_, b)
+    D = blocks_to_dense(S)
+    say(f"case sym-delta lif water-{n_mol} n={S.n} b={b} base={base} tau={tau}")
+    with lif.Factorization(dev(S), tau=tau, base_rows=base, sym_delta=1) as f:
+        info = f.localized()
+        Z = blocks_to_dense(f.get_Z())
+        res = f.residual()
+    Zo, plan = R.lif(D, b, tau, base_rows=base, sym_delta=True)
+    assert info["iterations_top"] == plan.info.iterations
+    if tau == 0.0:
+        assert np.max(np.abs(Z - Zo)) <= 1e-11 * np.max(np.abs(Zo))
+        assert res <= 1e-12
+    else:
+        assert np.linalg.norm(Z - Zo) <= 1e-8 * np.linalg.norm(Zo)
+
+
+def test_sym_delta_lif_chain_matches_oracle_and_presize():
+    # several problems per level (some stop early), products sized in
+    # advance after the first iteration; the sizes read back give the same bits
+    S, cfg = config_matrix(1, count=150)   # n = 3000 chain, b = 64
+    D = blocks_to_dense(S)
+    tau = 1e-10
+    say(f"case sym-delta lif chain n={S.n} b=64 base=512 tau={tau}")
+    out = {}
+    for presize in (0, 1):
+        with lif.Factorization(dev(S), tau=tau, base_rows=512, sym_delta=1, presize=presize) as f:
+            info = f.localized()
+            out[presize] = (info, f.get_Z())
+    Zo, plan = R.lif(D, 64, tau, base_rows=512, sym_delta=True)
+    info, Zb = out[1]
+    assert info["iterations_top"] == plan.info.iterations
+    assert np.linalg.norm(blocks_to_dense(Zb) - Zo) <= 1e-9 * np.linalg.norm(Zo)
+    Z0 = out[0][1]
+    assert np.array_equal(Z0.brow, Zb.brow) and np.array_equal(Z0.bcol, Zb.bcol)
+    assert np.array_equal(Z0.vals, Zb.vals)
