@@ -118,3 +118,63 @@ def test_sym_delta_lif_chain_matches_oracle_and_presize():
     Z0 = out[0][1]
     assert np.array_equal(Z0.brow, Zb.brow) and np.array_equal(Z0.bcol, Zb.bcol)
     assert np.array_equal(Z0.vals, Zb.vals)
+
+
+@pytest.mark.parametrize("prec", ["bf16"])
+def test_sym_delta_with_schedule_on_split_batches(prec):
+    # the precision schedule splits a level's correction products between
+    # problems above and below the switch; the symmetric update mirrors delta
+    S, cfg = config_matrix(1, count=150)   # n = 3000 chain, b = 64
+    D = blocks_to_dense(S)
+    tau = 1e-10
+    code = {"fp32": lif.MIXED_FP32, "bf16": lif.MIXED_BF16}[prec]
+    say(f"case sym-delta schedule lif chain {prec}")
+    with lif.Factorization(dev(S), tau=tau, base_rows=512, prec=code, prec_switch=1e-2, sym_delta=1) as f:
+        info = f.localized()
+        Z = blocks_to_dense(f.get_Z())
+        res = f.residual()
+    Zo, plan = R.lif(D, 64, tau, base_rows=512, prec=prec, prec_switch=1e-2, sym_delta=True)
+    nodes = []
+
+    def walk(nd):
+        if nd.children:
+            nodes.append(nd.info)
+            walk(nd.children[0])
+            walk(nd.children[1])
+
+    walk(plan)
+    assert info["iterations_reduced"] == sum(sum(i.reduced) for i in nodes)
+    assert abs(info["iterations_total"] - sum(i.iterations for i in nodes)) <= len(nodes)
+    u_in = {"fp32": 2.0 ** -24, "bf16": 2.0 ** -8}[prec]
+    assert np.linalg.norm(Z - Zo) <= 10 * u_in * np.linalg.norm(Zo)
+    assert res <= 1e-8
+
+
+def test_sym_delta_backward_matches_oracle():
+    # the reverse sweep differentiates the regular recurrence from the
+    # checkpointed Z_i, which the symmetric update leaves unchanged in exact
+    # arithmetic
+    from oracle import adjoint as ADJ
+    from gen import random_on_pattern
+    from test_gpu_adjoint import on_pattern
+    c_, e_ = water_cluster(40, 13)
+    S = overlap_blocks(c_, e_, 32)                 # n = 280
+    D = blocks_to_dense(S)
+    G = random_on_pattern(S, 1003)
+    say("case sym-delta lif backward water-40 base=160")
+    with lif.Factorization(dev(S), base_rows=160, checkpoint=1, sym_delta=1) as f:
+        info = f.localized()
+        dS = blocks_to_dense(f.backward(dev(G)))
+    Zo, plan = R.lif(D, 32, 0.0, base_rows=160, sym_delta=True)
+    iters = {}
+
+    def walk(nd):
+        if nd.children:
+            iters[(nd.lo, nd.hi)] = nd.info.iterations
+            walk(nd.children[0])
+            walk(nd.children[1])
+
+    walk(plan)
+    assert info["iterations_top"] == plan.info.iterations
+    ref = on_pattern(ADJ.lif_grad(D, blocks_to_dense(G), 32, 160, 4, iters), S)
+    assert np.max(np.abs(dS - ref)) <= 1e-9 * np.max(np.abs(ref))
