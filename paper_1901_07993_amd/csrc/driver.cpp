@@ -49,6 +49,11 @@ Step stop_decision(int k, double e, double e_prev, bool has_prev, int m, int sto
 // An iteration whose products (with margins) would take more than this is
 // not sized in advance.
 constexpr double kPlanIterBytes = 4.0 * double(1u << 30);
+// Capacities carried over from the level below predict the next level's
+// first iteration only roughly (its problems are twice as large); they are
+// used while they describe small products, where a read-back would cost more
+// than the rare redone iteration.
+constexpr double kPlanCarryBytes = 256.0 * double(1u << 20);
 
 struct NodeState {
   bool active = true;
@@ -223,7 +228,9 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
     const double blk_bytes = (double)S.b * S.b * sizeof(double);
     double caps_bytes = 0.0;
     for (const auto& cp : caps) caps_bytes += (double)cp[0] * blk_bytes + (double)cp[1] * sizeof(BlockPair);
-    bool planned = o.presize != 0 && !caps.empty() && caps_split == split && caps_bytes <= kPlanIterBytes;
+    const bool carried = k == 1 && carry != nullptr;
+    bool planned = o.presize != 0 && !caps.empty() && caps_split == split &&
+                   caps_bytes <= (carried ? kPlanCarryBytes : kPlanIterBytes);
     Bsr Znew, dnew;
     std::vector<double> ss;
     struct SpecOff {  // no sizing in advance outside this loop, also on errors
@@ -810,7 +817,7 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck)
       double setup_bytes = 0.0;
       for (const auto& cp : setup_caps)
         setup_bytes += (double)cp[0] * b * b * sizeof(double) + (double)cp[1] * sizeof(BlockPair);
-      for (bool planned = o.presize != 0 && !setup_caps.empty() && setup_bytes <= kPlanIterBytes;;
+      for (bool planned = o.presize != 0 && !setup_caps.empty() && setup_bytes <= kPlanCarryBytes;;
            planned = false) {
         struct SpecOff {
           Ctx& c;
