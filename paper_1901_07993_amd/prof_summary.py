@@ -117,6 +117,51 @@ def mfma(counters: str, trace: str, out: str, kernel: str, peak_tflops: float, c
         f.write("\n")
 
 
+def _last_factorization(rows, id_key):
+    """Rows of the last factorization (from its k_chol_scatter dispatch on)."""
+    rows = sorted(rows, key=lambda r: int(r[id_key]))
+    starts = [i for i, r in enumerate(rows) if "k_chol_scatter" in r["Kernel_Name"]]
+    return rows[starts[-1]:] if starts else rows
+
+
+def hbm(trace: str, fetch: str, write: str, out: str, copy_mib: float, peak_gbps: float, title: str,
+        cmd: str) -> None:
+    """Per kernel of the last factorization: HBM bytes per dispatch (FETCH_SIZE
+    + WRITE_SIZE, each calibrated on the probe copy) from the two counter runs,
+    mean duration per dispatch from the trace run of the same command, and
+    their ratio against the HBM peak."""
+    dur = collections.defaultdict(list)
+    for r in _last_factorization(list(csv.DictReader(open(trace))), "Dispatch_Id"):
+        dur[_short(r["Kernel_Name"])].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    byts = collections.defaultdict(lambda: [0.0, 0])
+    for path, cname in ((fetch, "FETCH_SIZE"), (write, "WRITE_SIZE")):
+        rows = _counter(path, cname)
+        scale = _calibration(rows, copy_mib)
+        per = collections.defaultdict(list)
+        for r in _last_factorization(rows, "Dispatch_Id"):
+            per[_short(r["Kernel_Name"])].append(scale * float(r["Counter_Value"]) * 1024.0)
+        for k, v in per.items():
+            byts[k][0] += sum(v) / len(v)
+            byts[k][1] = len(v)
+    total_t = sum(sum(v) for v in dur.values())
+    with open(out, "w") as f:
+        f.write(f"# {title}\n\nCommands (repository root, one MI355X):\n\n```\n{cmd}\n```\n\n")
+        f.write("Bytes per dispatch: FETCH_SIZE + WRITE_SIZE of the counter runs, each scaled by the factor "
+                f"that maps the same counter on a {copy_mib:g} MiB device copy to its size; duration per "
+                "dispatch: the kernel trace of the same command. Both over the last factorization of the "
+                f"run. HBM peak {peak_gbps:g} GB/s.\n\n")
+        f.write("| kernel | dispatches | % of kernel time | MB per dispatch | us per dispatch | GB/s | "
+                "% of HBM peak |\n|---|---:|---:|---:|---:|---:|---:|\n")
+        for k, d in sorted(dur.items(), key=lambda x: -sum(x[1])):
+            if k not in byts:
+                continue
+            b = byts[k][0]
+            t = sum(d) / len(d)
+            gbps = b / t if t else 0.0
+            f.write(f"| `{k}` | {len(d)} | {100 * sum(d) / total_t:.1f} | {b / 1e6:.2f} | {t / 1e3:.1f} | "
+                    f"{gbps:.0f} | {100 * gbps / peak_gbps:.1f} |\n")
+
+
 def main() -> None:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -133,6 +178,15 @@ def main() -> None:
     t.add_argument("--copy-mib", type=float, required=True)
     t.add_argument("--cmd", required=True)
     t.add_argument("--hash", default="")
+    h = sub.add_parser("hbm")
+    h.add_argument("trace")
+    h.add_argument("fetch")
+    h.add_argument("write")
+    h.add_argument("out")
+    h.add_argument("--copy-mib", type=float, required=True)
+    h.add_argument("--peak-gbps", type=float, default=8000.0)
+    h.add_argument("--title", required=True)
+    h.add_argument("--cmd", required=True)
     m = sub.add_parser("mfma")
     m.add_argument("counters")
     m.add_argument("trace")
@@ -145,6 +199,8 @@ def main() -> None:
         stats(a.trace, a.out, a.title, a.cmd)
     elif a.what == "traffic":
         traffic(a.fetch, a.write, a.out, a.kernel, a.copy_mib, a.cmd, a.hash)
+    elif a.what == "hbm":
+        hbm(a.trace, a.fetch, a.write, a.out, a.copy_mib, a.peak_gbps, a.title, a.cmd)
     else:
         mfma(a.counters, a.trace, a.out, a.kernel, a.peak_tflops, a.cmd)
 
