@@ -95,3 +95,48 @@ def test_water2000_dense_product_full_size():
         C, P = f.multiply(Sd, False, Sd, True, 0.0)
     assert P == S.nb ** 3
     check_product(S, False, S, True, C, P, k=20, seed=5)
+
+
+@pytest.mark.parametrize("method", ["irsi", "lif"])
+def test_water2000_backward_full_size_central_differences(method):
+    # the differentiation workload at full size (n = 14,000, tau = 0, dense):
+    # the adjoint against central differences of the GPU forward along a
+    # symmetric unit direction on S's pattern -- a property at any size.
+    # h = 1e-4 keeps the rounding of L = sum(G * Z) (2e8 terms, bounded by
+    # 30 u sum|G * Z|) below the tolerance after division by 2h; the
+    # truncation error of the difference is O(h^2) relative.
+    from gen import blocks_to_dense, random_on_pattern, random_symmetric_on_pattern
+    from gen import BlockMatrix
+    S, cfg = config_matrix(3)
+    G = random_on_pattern(S, 1003)            # S is dense at tau = 0: Z's pattern as well
+    E = random_symmetric_on_pattern(S, 2000)
+    Gd = blocks_to_dense(G)
+    opts = dict(checkpoint=1) if method == "irsi" else dict(checkpoint=1, base_rows=4096)
+    say(f"case full water-2000 backward {method} n={S.n}")
+
+    def loss(Sp, **kw):
+        with lif.Factorization(dev(Sp), **kw) as f:
+            info = f.refine() if method == "irsi" else f.localized()
+            Z = blocks_to_dense(f.get_Z())
+        t = Gd * Z
+        return float(np.sum(t)), float(np.sum(np.abs(t))), info
+
+    with lif.Factorization(dev(S), **opts) as f:
+        info = f.refine() if method == "irsi" else f.localized()
+        dS = f.backward(dev(G))
+    assert np.array_equal(dS.brow, S.brow) and np.array_equal(dS.bcol, S.bcol)
+    an = float(np.sum(dS.vals * E.vals))
+    h = 1e-4
+    kw = {k: v for k, v in opts.items() if k != "checkpoint"}
+    lp, ap, ip = loss(BlockMatrix(S.n, S.b, S.brow, S.bcol, S.vals + h * E.vals), **kw)
+    lm, am, im = loss(BlockMatrix(S.n, S.b, S.brow, S.bcol, S.vals - h * E.vals), **kw)
+    fd = (lp - lm) / (2 * h)
+    noise = 30 * 2.0 ** -53 * (ap + am) / (2 * h)
+    say(f"  iterations {info['iterations_top']} ({ip['iterations_top']}, {im['iterations_top']}); "
+        f"adjoint {an:.10e} central difference {fd:.10e} rounding bound {noise:.2e}")
+    assert abs(fd - an) <= 1e-6 * abs(an) + noise
+    # dS is symmetric on S's symmetric pattern
+    pos = {(int(r), int(c)): k for k, (r, c) in enumerate(zip(dS.brow, dS.bcol))}
+    for k in range(0, dS.nnzb, 997):
+        t = pos[(int(dS.bcol[k]), int(dS.brow[k]))]
+        assert np.max(np.abs(dS.vals[k] - dS.vals[t].T)) <= 1e-12 * np.max(np.abs(dS.vals))
