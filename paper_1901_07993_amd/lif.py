@@ -115,6 +115,20 @@ class HostBlocks:
         return (self.n + self.b - 1) // self.b
 
 
+@dataclass
+class DeviceBlocks:
+    """A block list whose arrays are torch tensors on the GPU."""
+    n: int
+    b: int
+    brow: object
+    bcol: object
+    vals: object
+
+    @property
+    def nnzb(self) -> int:
+        return int(self.brow.shape[0])
+
+
 def _is_torch(x) -> bool:
     return type(x).__module__.startswith("torch")
 
@@ -207,16 +221,30 @@ class Factorization:
         self._check(load().lif_rinch(self._h, byref(info)))
         return info.as_dict()
 
-    def get_Z(self) -> HostBlocks:
-        lib = load()
-        nnzb = c_int64(0)
-        self._check(lib.lif_get_Z(self._h, byref(nnzb), None, None, None, 0))
-        k = nnzb.value
+    def _out_arrays(self, k: int, on_device: bool):
+        if on_device:
+            import torch
+            brow = torch.empty(k, dtype=torch.int32, device="cuda")
+            bcol = torch.empty(k, dtype=torch.int32, device="cuda")
+            vals = torch.empty((k, self.b, self.b), dtype=torch.float64, device="cuda")
+            return (brow, bcol, vals), (brow.data_ptr(), bcol.data_ptr(), vals.data_ptr())
         brow = np.empty(k, np.int32)
         bcol = np.empty(k, np.int32)
         vals = np.empty((k, self.b, self.b), np.float64)
-        self._check(lib.lif_get_Z(self._h, byref(nnzb), brow.ctypes.data, bcol.ctypes.data, vals.ctypes.data, 0))
-        return HostBlocks(self.n, self.b, brow, bcol, vals)
+        return (brow, bcol, vals), (brow.ctypes.data, bcol.ctypes.data, vals.ctypes.data)
+
+    def _blocks(self, arrs, on_device: bool):
+        return (DeviceBlocks if on_device else HostBlocks)(self.n, self.b, *arrs)
+
+    def get_Z(self, on_device: bool = False):
+        """The factor as a block list (HostBlocks, or DeviceBlocks of torch
+        tensors on the GPU with ``on_device``)."""
+        lib = load()
+        nnzb = c_int64(0)
+        self._check(lib.lif_get_Z(self._h, byref(nnzb), None, None, None, int(on_device)))
+        arrs, ptrs = self._out_arrays(nnzb.value, on_device)
+        self._check(lib.lif_get_Z(self._h, byref(nnzb), *ptrs, int(on_device)))
+        return self._blocks(arrs, on_device)
 
     def residual(self) -> float:
         out = c_double(0.0)
@@ -243,20 +271,17 @@ class Factorization:
         del ka, kb
         return HostBlocks(self.n, self.b, brow, bcol, vals), prods.value
 
-    def backward(self, G) -> HostBlocks:
-        """sym(dL/dS) on S's block pattern for L = tr(G^T Z) (needs checkpoint=1)."""
+    def backward(self, G, on_device: bool = False):
+        """sym(dL/dS) on S's block pattern for L = tr(G^T Z) (needs checkpoint=1);
+        HostBlocks, or DeviceBlocks with ``on_device``."""
         lib = load()
         st, keep = _marshal(G)
         nnzb = c_int64(0)
-        self._check(lib.lif_backward(self._h, byref(st), byref(nnzb), None, None, None, 0))
-        k = nnzb.value
-        brow = np.empty(k, np.int32)
-        bcol = np.empty(k, np.int32)
-        vals = np.empty((k, self.b, self.b), np.float64)
-        self._check(lib.lif_backward(self._h, None, byref(nnzb), brow.ctypes.data, bcol.ctypes.data,
-                                     vals.ctypes.data, 0))
+        self._check(lib.lif_backward(self._h, byref(st), byref(nnzb), None, None, None, int(on_device)))
+        arrs, ptrs = self._out_arrays(nnzb.value, on_device)
+        self._check(lib.lif_backward(self._h, None, byref(nnzb), *ptrs, int(on_device)))
         del keep
-        return HostBlocks(self.n, self.b, brow, bcol, vals)
+        return self._blocks(arrs, on_device)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -274,3 +299,80 @@ class Factorization:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def factorize(S, method: str = "lif", **opts):
+    """Z with S^{-1} = Z Z^T for a block list S: ``method`` "lif" (lif_localized),
+    "irsi" (lif_refine from a scaled identity) or "rinch" (lif_rinch); opts as
+    for Factorization.  Returns (Z, info): Z as DeviceBlocks when S's arrays
+    are torch GPU tensors, else HostBlocks."""
+    on_device = _is_torch(S.vals)
+    with Factorization(S, **opts) as f:
+        info = {"lif": f.localized, "irsi": f.refine, "rinch": f.rinch}[method]()
+        return f.get_Z(on_device=on_device), info
+
+
+def _scatter_to_pattern(brow_from, bcol_from, vals_from, brow_to, bcol_to, nb):
+    """Blocks of one sorted block list placed at the positions of another
+    (zeros where the second has a block the first lacks), on the GPU."""
+    import torch
+    key_to = brow_to.to(torch.int64) * nb + bcol_to.to(torch.int64)
+    key_from = brow_from.to(torch.int64) * nb + bcol_from.to(torch.int64)
+    out = torch.zeros((key_to.shape[0],) + tuple(vals_from.shape[1:]), dtype=vals_from.dtype,
+                      device=vals_from.device)
+    if key_from.numel():
+        pos = torch.searchsorted(key_to, key_from)
+        out[pos] = vals_from
+    return out
+
+
+try:
+    import torch as _torch
+
+    class LIFFunction(_torch.autograd.Function):
+        """Z = the inverse factor of S as a differentiable torch operation.
+
+        apply(S_vals, pattern, method="lif", opts=None) -> (Z_vals, Z_brow, Z_bcol)
+          S_vals  [nnzb, b, b] float64 CUDA tensor, the blocks of S listed in
+                  ``pattern`` (an object with n, b, brow, bcol; int32 CUDA
+                  tensors sorted by (row, col), both (i, j) and (j, i) of the
+                  symmetric pattern);
+          method  "lif" or "irsi"; opts: keyword options of Factorization.
+        The backward pass calls lif_backward with G = dL/dZ on Z's pattern
+        and returns sym(dL/dS) on S's pattern: for a symmetric perturbation E
+        of S, dL = <grad, E>.  Blocks of S dropped by the truncation at tau
+        get a zero gradient.  The handle (and its per-iteration checkpoints)
+        lives until the backward pass has run.
+        """
+
+        @staticmethod
+        def forward(ctx, S_vals, pattern, method="lif", opts=None):
+            S = DeviceBlocks(int(pattern.n), int(pattern.b), pattern.brow, pattern.bcol, S_vals.detach())
+            f = Factorization(S, checkpoint=1, **(opts or {}))
+            {"lif": f.localized, "irsi": f.refine}[method]()
+            Z = f.get_Z(on_device=True)
+            ctx.f = f
+            ctx.pattern = pattern
+            ctx.zpat = (Z.brow, Z.bcol)
+            ctx.mark_non_differentiable(Z.brow, Z.bcol)
+            return Z.vals, Z.brow, Z.bcol
+
+        @staticmethod
+        def backward(ctx, g_vals, g_brow=None, g_bcol=None):
+            p = ctx.pattern
+            n, b = int(p.n), int(p.b)
+            nb = (n + b - 1) // b
+            g = g_vals.contiguous()
+            tail = n - (nb - 1) * b
+            if tail < b:
+                # Z's entries beyond n are constant zeros: their gradient is dropped
+                g = g.clone()
+                g[ctx.zpat[0] == nb - 1, tail:, :] = 0.0
+                g[ctx.zpat[1] == nb - 1, :, tail:] = 0.0
+            G = DeviceBlocks(n, b, ctx.zpat[0], ctx.zpat[1], g)
+            dS = ctx.f.backward(G, on_device=True)
+            ctx.f.close()
+            grad = _scatter_to_pattern(dS.brow, dS.bcol, dS.vals, p.brow, p.bcol, nb)
+            return grad, None, None, None
+except ImportError:  # torch absent: the ctypes binding still works with host arrays
+    pass
