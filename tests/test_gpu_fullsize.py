@@ -97,6 +97,43 @@ def test_water2000_dense_product_full_size():
     check_product(S, False, S, True, C, P, k=20, seed=5)
 
 
+def test_chain_full_lif_matches_blocked_oracle(chain):
+    # the benchmark workload in the configuration bench.py times, against the
+    # block-sparse oracle on the whole matrix: per-node iteration counts and
+    # every block of Z (differences: summation order, and blocks whose norm
+    # lies within rounding of tau)
+    import oracle.blocked as OB
+    S, cfg = chain
+    say(f"case full chain-5000 n={S.n} LIF against the block-sparse oracle")
+    with lif.Factorization(dev(S), tau=cfg["tau"], base_rows=4096, stop=lif.STOP_PAPER) as f:
+        info = f.localized()
+        Z = f.get_Z()
+    Zo, plan = OB.lif(S, cfg["tau"], base_rows=4096)
+    iters = []
+
+    def walk(nd):
+        if nd.children:
+            iters.append(nd.info.iterations)
+            walk(nd.children[0])
+            walk(nd.children[1])
+
+    walk(plan)
+    say(f"  gpu top {info['iterations_top']} total {info['iterations_total']}; oracle top "
+        f"{plan.info.iterations} total {sum(iters)}; blocks {Z.nnzb} vs {len(Zo.blocks)}")
+    assert info["iterations_top"] == plan.info.iterations
+    assert info["iterations_total"] == sum(iters)
+    got = {(int(r), int(c)): v for r, c, v in zip(Z.brow, Z.bcol, Z.vals)}
+    keys = set(got) | set(Zo.blocks)
+    diff2 = sum(float(np.sum((got.get(k, 0.0) - Zo.blocks.get(k, 0.0)) ** 2)) for k in keys)
+    ref2 = sum(float(np.sum(v * v)) for v in Zo.blocks.values())
+    say(f"  ||Z - Z_oracle||_F / ||Z_oracle||_F = {np.sqrt(diff2 / ref2):.3e}")
+    assert np.sqrt(diff2 / ref2) <= 1e-9
+    # blocks present on one side only lie near the truncation threshold
+    for k in set(got) ^ set(Zo.blocks):
+        v = got[k] if k in got else Zo.blocks[k]
+        assert np.sqrt(np.sum(v * v)) <= 10 * cfg["tau"]
+
+
 @pytest.mark.parametrize("method", ["irsi", "lif"])
 def test_water2000_backward_full_size_central_differences(method):
     # the differentiation workload at full size (n = 14,000, tau = 0, dense):
