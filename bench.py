@@ -206,8 +206,8 @@ def main():
                     help="first copy this many MiB device to device (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
-              "DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding the recursion over several "
+              "GPUs is a design that is not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

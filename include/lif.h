@@ -94,7 +94,10 @@ typedef struct {
   int32_t start;          /* LIF_START_* (IRSI only) */
   double start_value;     /* lambda_max or c, see LIF_START_* */
   int32_t checkpoint;     /* 1: keep per-iteration Z for lif_backward */
-  uint64_t mem_cap_bytes; /* device memory the handle may hold (0 = no cap) */
+  uint64_t mem_cap_bytes; /* device memory the handle may hold (0 = no cap).  The large-problem
+                           * policies are sized against it when it is below the GPU's memory:
+                           * iterations on one stream with buffers freed early, products
+                           * written as kept blocks only, the residual's panels */
   void* stream;           /* hipStream_t for all work (NULL = null stream) */
   int32_t timing;         /* 1: time every leaf-GEMM launch with HIP events */
   int32_t presize;        /* 1: from the second iteration of a refinement on, size each
@@ -114,6 +117,10 @@ typedef struct {
   int32_t sym_delta;      /* 1: delta (symmetric in exact arithmetic) is updated on its upper block triangle
                            * only, the update's two products forming just those blocks, and the strictly
                            * upper part is mirrored below (localized refinement); 0: the full update */
+  int32_t residual_panel_rows; /* lif_residual forms I - Z^T S Z this many block rows at a time (>= 0;
+                           * 0: panels of at most min(8 GiB, 1/16 of the device memory the
+                           * handle may use) of dense block rows, the whole matrix when it
+                           * fits), bounding its memory by Z, S Z and one panel */
 } lif_opts;
 
 typedef struct {
@@ -145,7 +152,7 @@ typedef struct {
 /* Fills *o with the defaults: m = 4, tau = 0, FP64, paper stopping rule,
  * tol = 1e-10, max_iter = 100, base_rows = 4096, start = SQRT2_OVER_GERSH,
  * checkpoint = 0, no cap, null stream, timing = 0, presize = 1,
- * refinement = LIF_REFINE_LOCAL, prec_switch = 0, sym_delta = 0. */
+ * refinement = LIF_REFINE_LOCAL, prec_switch = 0, sym_delta = 0, residual_panel_rows = 0. */
 lif_status lif_opts_default(lif_opts* o);
 
 /* Validates S and copies it into library-owned device memory (the caller may
@@ -197,7 +204,8 @@ lif_status lif_get_Z(lif_handle h, int64_t* nnzb, int32_t* brow, int32_t* bcol, 
                      int32_t on_device);
 
 /* ||I - Z^T S Z||_F of the handle's Z in FP64 with no truncation (Table 1's
- * error measure), against the truncated S the handle factorized. */
+ * error measure), against the truncated S the handle factorized; formed by
+ * panels of block rows (opts.residual_panel_rows), never stored whole. */
 lif_status lif_residual(lif_handle h, double* out);
 
 /* C = op(A) op(B) truncated at tau: the block-sparse product of Sec. 4 with

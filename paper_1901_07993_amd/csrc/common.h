@@ -54,12 +54,18 @@ class Pool {
   ~Pool() { release_all(); }
   void* alloc(size_t bytes);
   void free(void* p);
+  // Gives back the tail of a buffer beyond its first `bytes` (which the
+  // device must no longer touch); false when the buffer keeps its size
+  // (freed buffers are being held back, or nothing to give).
+  bool shrink(void* p, size_t bytes);
   void trim();            // return wholly unused segments to HIP
   // While deferring, freed buffers are held back from reuse until
   // release_deferred(): work on two streams may still read a buffer the host
   // has released, and reuse is only safe after both streams have synchronized.
   void set_defer(bool on) { defer_ = on; }
+  bool deferring() const { return defer_; }
   void release_deferred();
+  uint64_t cap() const { return cap_; }  // 0: no cap
   uint64_t in_use() const { return in_use_; }
   uint64_t reserved() const { return reserved_; }
   uint64_t peak() const { return peak_; }
@@ -117,6 +123,14 @@ class DBuf {
   }
   T* get() const { return p_; }
   size_t size() const { return n_; }
+  // keeps the first n elements and returns the rest to the pool
+  void shrink(size_t n) {
+    if (n == 0) {
+      reset();
+    } else if (n < n_ && p_ && pool_ && pool_->shrink(p_, n * sizeof(T))) {
+      n_ = n;
+    }
+  }
 
  private:
   Pool* pool_ = nullptr;
@@ -296,8 +310,10 @@ struct Ctx {
   hipStream_t side = nullptr;
   std::vector<hipEvent_t> order_events;
   hipStream_t side_stream();
-  // device memory of the GPU (queried once); the limit below which the
-  // refinement may hold an iteration's buffers until its end (two streams)
+  // device memory the handle may use: the GPU's (queried once), or the
+  // pool's cap when smaller.  Sizes the large-problem policies: when an
+  // iteration's buffers go to one stream and are freed early, which
+  // products are written compacted, and the panels of the residual.
   uint64_t device_bytes();
   uint64_t device_total = 0;
   hipEvent_t order_event(size_t i);  // the i-th reusable ordering event
@@ -486,24 +502,39 @@ struct Epilogue {
   // with its pointer (null for a dropped block) in lp_ptr[e]
   void* lp_store = nullptr;
   const void** lp_ptr = nullptr;
+  // nullable (with drop): kept blocks take consecutive slots of C (and of
+  // lp_store) in the order they finish, counted by this device counter
+  // (zero before the launch), so that C holds kept blocks only
+  unsigned long long* slots = nullptr;
 };
 
-// The numeric kernels' count of output blocks to compute: *live, or none
-// for a voided product (whose row pointers workgroup 0 then clears).
+// Thread 0 of an output block's workgroup, once the block's norm is known:
+// the slot the block is written to (its own index, or the next free slot of
+// a compacted output), or -1 for a dropped block, which is not written.
+__device__ inline int64_t output_slot(const Epilogue& epi, int64_t blk, double nrm) {
+  if (epi.drop && !(nrm >= epi.tau)) return -1;
+  if (epi.slots) return (int64_t)atomicAdd(epi.slots, 1ull);
+  return blk;
+}
+
+// The numeric kernels' count of output blocks to compute: *live (the grid
+// when live is null), or none for a voided product (whose row pointers
+// workgroup 0 then clears).
 __device__ inline int64_t live_blocks(const int* live, const Epilogue& epi) {
   if (epi.poison && *epi.poison) {
     if (blockIdx.x == 0)
       for (int r = threadIdx.x; r <= epi.nrows; r += blockDim.x) epi.rows[r] = 0;
     return 0;
   }
-  return *live;
+  return live ? *live : (int64_t)gridDim.x;
 }
 // Numeric phase: C_blk = sum over its segment of op(A_a) op(B_b), in FP64
 // (prec = LIF_FP64) or with FP32 / BF16 inputs and FP32 accumulation.
-// `nnzc` is the grid (the output capacity); `live` (device) the number of
-// output blocks actually present, <= nnzc.
-// Output block e is written to C + e b^2, its pointer to Cp[e] and its
-// Frobenius norm to norms[e] (nullable).
+// `nnzc` is the grid (the output capacity); `live` (device, nullable: all
+// nnzc) the number of output blocks actually present, <= nnzc.
+// Output block e is written to C + e b^2 (or to the next slot of C, see
+// Epilogue::slots), its pointer to Cp[e] and its Frobenius norm to norms[e]
+// (nullable).
 void launch_numeric(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg, const BlockPair* pairs,
                     int64_t nnzc, const int* live, int b, double* C, BlkOut Cp, double* norms, const Epilogue& epi);
 // spgemm_mixed.hip

@@ -233,6 +233,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
                    caps_bytes <= (carried ? kPlanCarryBytes : kPlanIterBytes);
     Bsr Znew, dnew;
     std::vector<double> ss;
+    bool big_iter = false;
     struct SpecOff {  // no sizing in advance outside this loop, also on errors
       Ctx& c;
       ~SpecOff() { c.spec.on = c.spec.record = c.spec.exact_large = false; }
@@ -266,6 +267,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       const double dev = (double)c.device_bytes();
       const bool big = iter_bytes > 0.25 * dev || (double)c.pool->reserved() + iter_bytes > 0.5 * dev;
       c.spec.exact_large = big;
+      big_iter = big;
       DeferFrees defer(c);
       if (big) defer.release();
       if (regular) {
@@ -414,10 +416,12 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
     }
     // Z_{k+1} and delta_{k+1} share the blocks they did not change with
     // Z_k, delta_k and the products; once the value arrays they keep alive
-    // hold more than three times their own blocks, their blocks are moved
-    // into one array (counts are known here: no extra read-back)
-    if (Znew.store_blocks() > 3 * Znew.nnzb + 64) Znew = compact_values(c, std::move(Znew));
-    if (dnew.store_blocks() > 3 * dnew.nnzb + 64) dnew = compact_values(c, std::move(dnew));
+    // hold more than three times their own blocks (a quarter more on large
+    // problems, where that memory is what limits the size), their blocks
+    // are moved into one array (counts are known here: no extra read-back)
+    const int64_t slack_num = big_iter ? 5 : 12, slack_den = 4;
+    if (slack_den * Znew.store_blocks() > slack_num * Znew.nnzb + 256) Znew = compact_values(c, std::move(Znew));
+    if (slack_den * dnew.store_blocks() > slack_num * dnew.nnzb + 256) dnew = compact_values(c, std::move(dnew));
     caps_split = split;
     if (carry && !split) *carry = caps;
     if (ck) ck->push_back(std::move(Z));  // Z_k is immutable: keep it, no copy
@@ -914,17 +918,50 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck)
   return Z;
 }
 
-double residual(Ctx& c, const Bsr& S, const Bsr& Z) {
+double residual(Ctx& c, const Bsr& S, const Bsr& Z, int panel_rows) {
+  // R = I - Z^T (S Z), untruncated, with ||R||_F^2 summed over panels of
+  // R's block rows: rows [p0, p1) of R take only Z's block columns in
+  // [p0, p1).  Automatic panels: one, unless R could take more than
+  // min(8 GiB, 1/16 of the device memory the handle may use).
+  const double kPanelBytes = std::min(8.0 * double(1u << 30), (double)c.device_bytes() / 16.0);
+  const int nb = S.nb;
+  const double row_bytes = (double)nb * S.b * S.b * sizeof(double);  // a dense block row of R
+  const int rows = panel_rows > 0 ? std::min(panel_rows, nb)
+                                  : (int)std::max(1.0, std::min((double)nb, std::floor(kPanelBytes / row_bytes)));
   Bsr SZ = spgemm(c, S, false, Z, false, 0.0);
-  Bsr ZSZ = spgemm(c, Z, true, SZ, false, 0.0);
-  SZ = Bsr();
-  Bsr R = axpby(c, -1.0, &ZSZ, 0.0, nullptr, 1.0, all_rows_on(c));
-  std::vector<int> lo{0}, hi{S.nb};
-  DBuf<int> d_lo(c.pool, 1), d_hi(c.pool, 1);
-  h2d(c, d_lo.get(), lo.data(), 1);
-  h2d(c, d_hi.get(), hi.data(), 1);
-  std::vector<double> ss = node_sumsq(c, R, d_lo.get(), d_hi.get(), 1);
-  return std::sqrt(ss[0]);
+  // host sources of asynchronous copies, rewritten only after the
+  // read-back that ends each panel
+  std::vector<int> zeros(nb, 0), clab(nb), lo(1), hi(1);
+  std::vector<unsigned char> on(nb);
+  DBuf<int> d_zeros(c.pool, nb), d_clab(c.pool, nb), d_lo(c.pool, 1), d_hi(c.pool, 1);
+  DBuf<unsigned char> d_on(c.pool, nb);
+  h2d(c, d_zeros.get(), zeros.data(), nb);
+  double ss = 0.0;
+  for (int p0 = 0; p0 < nb; p0 += rows) {
+    const int p1 = std::min(nb, p0 + rows);
+    lo[0] = p0;
+    hi[0] = p1;
+    h2d(c, d_lo.get(), lo.data(), 1);
+    h2d(c, d_hi.get(), hi.data(), 1);
+    Bsr R;
+    if (rows >= nb) {
+      Bsr ZSZ = spgemm(c, Z, true, SZ, false, 0.0);
+      R = axpby(c, -1.0, &ZSZ, 0.0, nullptr, 1.0, all_rows_on(c));
+    } else {
+      for (int j = 0; j < nb; ++j) {
+        clab[j] = (j >= p0 && j < p1) ? 0 : -1;
+        on[j] = (j >= p0 && j < p1) ? 1 : 0;
+      }
+      h2d(c, d_clab.get(), clab.data(), nb);
+      h2d(c, d_on.get(), on.data(), nb);
+      Bsr Zp = filter(c, Z, d_zeros.get(), d_clab.get(), 0);
+      Bsr P = spgemm(c, Zp, true, SZ, false, 0.0);
+      Zp = Bsr();
+      R = axpby(c, -1.0, &P, 0.0, nullptr, 1.0, d_on.get());
+    }
+    ss += node_sumsq(c, R, d_lo.get(), d_hi.get(), 1)[0];
+  }
+  return std::sqrt(ss);
 }
 
 }  // namespace lif

@@ -22,6 +22,7 @@ struct Opts {
   int refinement = LIF_REFINE_LOCAL;
   double prec_switch = 0.0;  // > 0: reduced precision only while ||delta||_F exceeds it
   bool sym_delta = false;    // update delta's upper block triangle and mirror it
+  int residual_panel_rows = 0;  // block rows of I - Z^T S Z formed at once (0: automatic)
 };
 
 // One node of the split tree: scalar rows [lo, hi), lo a multiple of b.
@@ -96,7 +97,8 @@ Bsr run_backward(Ctx& c, const Bsr& S, const Checkpoints& ck, const Bsr& G, cons
 // block-diagonal upper-triangular Z with Z_k^T S_k Z_k = I, truncated at tau.
 Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int64_t, int64_t>>& ranges,
                           double tau);
-// ||I - Z^T S Z||_F with untruncated products.
-double residual(Ctx& c, const Bsr& S, const Bsr& Z);
+// ||I - Z^T S Z||_F with untruncated products, formed `panel_rows` block rows
+// at a time (0: panels of at most 8 GiB of dense block rows).
+double residual(Ctx& c, const Bsr& S, const Bsr& Z, int panel_rows = 0);
 
 }  // namespace lif

@@ -228,6 +228,12 @@ Bsr transpose(Ctx& c, const Bsr& A) {
 
 namespace {
 
+// Output stores above min(512 MiB, 1/64 of the device memory the handle may
+// use) are written compacted (kept blocks only), in chunks of at most
+// min(4 GiB, 1/16 of it) of untruncated output.
+constexpr double kCompactMinBytes = 512.0 * double(1u << 20);
+constexpr double kCompactChunkBytes = 4.0 * double(1u << 30);
+
 // The numeric phase of a product whose pattern, segments and pairs are
 // built: values, norms, truncation (or holes).
 // `poison` (nullable): the flag that voids the product (Epilogue).
@@ -235,9 +241,7 @@ Bsr numeric_phase(Ctx& c, Bsr&& C, bool ta, bool tb, double tau, int prec, doubl
                   bool keep_holes, const int64_t* seg, const BlockPair* pairs, int64_t nnzc, const int* poison,
                   bool out_lp) {
   const int nb = C.nb;
-  Store st = new_store(c, nnzc, C.b);
   C.blk = DBuf<const double*>(c.pool, (size_t)nnzc);
-  C.store.push_back(st);
   Epilogue epi;
   epi.alpha = alpha;
   epi.gamma = gamma;
@@ -245,6 +249,38 @@ Bsr numeric_phase(Ctx& c, Bsr&& C, bool ta, bool tb, double tau, int prec, doubl
   epi.poison = poison;
   epi.rows = C.row_ptr.get();
   epi.nrows = nb;
+  const double blk_bytes = (double)C.b * C.b * sizeof(double);
+  const double dev = (double)c.device_bytes();
+  if (keep_holes && tau > 0.0 && !poison && !c.pool->deferring() &&
+      (double)nnzc * blk_bytes > std::min(kCompactMinBytes, dev / 64.0)) {
+    // A large product with a known block count: kept blocks only, written
+    // to consecutive slots of one store per chunk of output blocks, each
+    // store cut to its kept blocks once the chunk is done (a read-back per
+    // chunk), so that the untruncated product is never held.  A
+    // reduced-precision copy for the next product is made by that product.
+    // Only where freed memory is reusable at once (one stream).
+    epi.drop = true;
+    epi.tau = tau;
+    C.holes = true;
+    const int64_t chunk = std::max<int64_t>(1, (int64_t)(std::min(kCompactChunkBytes, dev / 16.0) / blk_bytes));
+    DBuf<unsigned long long> kept(c.pool, 1);
+    for (int64_t e0 = 0; e0 < nnzc; e0 += chunk) {
+      const int64_t n = std::min(chunk, nnzc - e0);
+      Store st = new_store(c, n, C.b);
+      launch_fill_i32(c, reinterpret_cast<int*>(kept.get()), 0, 2);
+      Epilogue e = epi;
+      e.slots = kept.get();
+      e.dsrc = dsrc ? dsrc + e0 : nullptr;
+      launch_numeric(c, prec, ta, tb, seg + e0, pairs, n, nullptr, C.b, st->get(), C.blk.get() + e0, nullptr, e);
+      unsigned long long k = 0;
+      c.d2h_batch({{&k, kept.get(), sizeof(k)}});
+      st->shrink((size_t)k * C.b * C.b);
+      if (k) C.store.push_back(st);
+    }
+    return std::move(C);
+  }
+  Store st = new_store(c, nnzc, C.b);
+  C.store.push_back(st);
   if (out_lp && keep_holes && prec != LIF_FP64 && nnzc > 0) {
     // the result's transposed input-precision copy, written with its blocks
     Bsr::Shadow& sh = C.lp[1];

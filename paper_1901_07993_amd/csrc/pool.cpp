@@ -104,6 +104,28 @@ void Pool::free(void* ptr) {
   free_[cls].insert({it->second.size, it->first});
 }
 
+bool Pool::shrink(void* ptr, size_t bytes) {
+  auto it = pieces_.find(static_cast<char*>(ptr));
+  if (it == pieces_.end() || it->second.free || defer_) return false;
+  const size_t r = round(bytes);
+  Piece& pc = it->second;
+  if (r == 0 || r >= pc.size) return false;
+  const int cls = segs_[pc.seg].second;
+  char* tail = it->first + r;
+  size_t tsize = pc.size - r;
+  in_use_ -= tsize;
+  pc.size = r;
+  auto next = std::next(it);
+  if (next != pieces_.end() && next->second.free && next->second.seg == pc.seg) {
+    free_[cls].erase({next->second.size, next->first});
+    tsize += next->second.size;
+    pieces_.erase(next);
+  }
+  pieces_[tail] = Piece{tsize, true, pc.seg};
+  free_[cls].insert({tsize, tail});
+  return true;
+}
+
 void Pool::release_deferred() {
   const bool keep = defer_;
   defer_ = false;
@@ -223,7 +245,7 @@ uint64_t Ctx::device_bytes() {
     LIF_HIP(hipMemGetInfo(&free_b, &total_b));
     device_total = total_b;
   }
-  return device_total;
+  return pool->cap() ? std::min<uint64_t>(pool->cap(), device_total) : device_total;
 }
 
 hipStream_t Ctx::side_stream() {

@@ -521,7 +521,8 @@ __device__ __attribute__((always_inline)) inline void load_d(const Frag& f, cons
 }
 
 // The block alpha A B (+ gamma D when HAS_D, D's elements in d), its FP64
-// sum of squares in a fixed order, its norm and its pointer.
+// sum of squares in a fixed order, its norm and its pointer; the values are
+// written once the norm has decided whether (and where) the block is kept.
 template <int B, bool TA, bool TB, bool HAS_D>
 __device__ __attribute__((always_inline)) inline void numeric_epilogue(const v4d (&acc)[2][2], const Frag& f,
                                                                        int64_t blk, double* __restrict__ C,
@@ -549,7 +550,21 @@ __device__ __attribute__((always_inline)) inline void numeric_epilogue(const v4d
       for (int r = 0; r < 4; ++r) ss += v[ti][tj][r] * v[ti][tj][r];
   for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
   if (f.lane == 0) red[f.wave] = ss;
-  double* Cb = C + blk * B * B;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < Cfg::WAVES; ++w) t += red[w];
+    const double nrm = sqrt(t);
+    if (norms) norms[blk] = nrm;
+    const int64_t s = output_slot(epi, blk, nrm);
+    Cp[blk] = s >= 0 ? C + s * B * B : nullptr;
+    red[Cfg::WAVES] = __longlong_as_double(s);
+  }
+  __syncthreads();
+  const int64_t slot = __double_as_longlong(red[Cfg::WAVES]);
+  if (slot < 0) return;  // dropped: never written
+  double* Cb = C + slot * B * B;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -562,15 +577,6 @@ __device__ __attribute__((always_inline)) inline void numeric_epilogue(const v4d
         Cb[row * B + M::col(f, 1, f.l16)] = v[ti][1][r];
       }
     }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-#pragma unroll
-    for (int w = 0; w < Cfg::WAVES; ++w) t += red[w];
-    const double nrm = sqrt(t);
-    if (norms) norms[blk] = nrm;
-    Cp[blk] = (epi.drop && !(nrm >= epi.tau)) ? nullptr : Cb;
-  }
 }
 
 // Numeric kernel, one workgroup per output block.  Fragments whose elements
@@ -592,7 +598,7 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const int64
   constexpr int KS = B / 4;
   __shared__ __attribute__((aligned(16))) double As[A_LDS ? Cfg::LDS_DOUBLES : 2];
   __shared__ __attribute__((aligned(16))) double Bs[B_LDS ? Cfg::LDS_DOUBLES : 2];
-  __shared__ double red[Cfg::WAVES];
+  __shared__ double red[Cfg::WAVES + 1];  // partial sums, then the output slot
   const int64_t nlive = live_blocks(live, epi);
   if ((int64_t)blockIdx.x >= nlive) return;
   const int64_t blk = xcd_remap(blockIdx.x, nlive);

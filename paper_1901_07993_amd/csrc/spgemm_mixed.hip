@@ -67,6 +67,8 @@ struct Lp<LIF_MIXED_BF16> {
 // The block alpha A B + gamma D (Epilogue; FP64 from the FP32 accumulators),
 // its FP64 sum of squares in a fixed order, its norm and its pointer; with
 // OUT_LP also its transposed reduced-precision copy and that copy's pointer.
+// The values are written once the norm has decided whether (and where) the
+// block is kept.
 template <int B, int PREC, bool OUT_LP>
 __device__ inline void epilogue(const v4f (&acc)[2][2], int rb, int cb, int l16, int kq, int lane, int wave,
                                 int64_t blk, double* __restrict__ C, BlkOut Cp, double* red,
@@ -74,9 +76,41 @@ __device__ inline void epilogue(const v4f (&acc)[2][2], int rb, int cb, int l16,
   using Cfg = MixCfg<B>;
   typedef typename Lp<PREC>::T T;
   const double* Db = epi.dsrc ? epi.dsrc[blk] : nullptr;
-  double* Cb = C + blk * B * B;
-  T* Lb = OUT_LP ? static_cast<T*>(epi.lp_store) + blk * B * B : nullptr;
+  double v[2][2][4];
   double ss = 0.0;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) {
+      const int col = cb + 16 * tj + l16, row0 = rb + 16 * ti + 4 * kq;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double x = epi.alpha * (double)acc[ti][tj][r];
+        if (Db) x += epi.gamma * gptr(Db)[(row0 + r) * B + col];
+        v[ti][tj][r] = x;
+        ss += x * x;
+      }
+    }
+  for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+  if (lane == 0) red[wave] = ss;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < Cfg::WAVES; ++w) t += red[w];
+    const double nrm = sqrt(t);
+    if (norms) norms[blk] = nrm;
+    const int64_t s = output_slot(epi, blk, nrm);
+    Cp[blk] = s >= 0 ? C + s * B * B : nullptr;
+    if (OUT_LP) epi.lp_ptr[blk] = s >= 0 ? static_cast<const void*>(static_cast<T*>(epi.lp_store) + s * B * B)
+                                         : nullptr;
+    red[Cfg::WAVES] = __longlong_as_double(s);
+  }
+  __syncthreads();
+  const int64_t slot = __double_as_longlong(red[Cfg::WAVES]);
+  if (slot < 0) return;  // dropped: never written
+  double* Cb = C + slot * B * B;
+  T* Lb = OUT_LP ? static_cast<T*>(epi.lp_store) + slot * B * B : nullptr;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -85,12 +119,8 @@ __device__ inline void epilogue(const v4f (&acc)[2][2], int rb, int cb, int l16,
       T lv[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int idx = (row0 + r) * B + col;
-        double v = epi.alpha * (double)acc[ti][tj][r];
-        if (Db) v += epi.gamma * gptr(Db)[idx];
-        Cb[idx] = v;
-        ss += v * v;
-        lv[r] = Lp<PREC>::round(v);
+        Cb[(row0 + r) * B + col] = v[ti][tj][r];
+        lv[r] = Lp<PREC>::round(v[ti][tj][r]);
       }
       if (OUT_LP) {  // transposed: the four rows of this lane are consecutive
         T* q = Lb + col * B + row0;
@@ -103,19 +133,6 @@ __device__ inline void epilogue(const v4f (&acc)[2][2], int rb, int cb, int l16,
         }
       }
     }
-  for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
-  if (lane == 0) red[wave] = ss;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-#pragma unroll
-    for (int w = 0; w < Cfg::WAVES; ++w) t += red[w];
-    const double nrm = sqrt(t);
-    if (norms) norms[blk] = nrm;
-    const bool keep = !(epi.drop && !(nrm >= epi.tau));
-    Cp[blk] = keep ? Cb : nullptr;
-    if (OUT_LP) epi.lp_ptr[blk] = keep ? static_cast<const void*>(Lb) : nullptr;
-  }
 }
 
 // One workgroup per output block; pair p gives op(A)'s block row-major
@@ -128,7 +145,7 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(const int64
                                                                      double* __restrict__ C, BlkOut Cp,
                                                                      double* __restrict__ norms, Epilogue epi) {
   constexpr int KS = B / 32;
-  __shared__ double red[MixCfg<B>::WAVES];
+  __shared__ double red[MixCfg<B>::WAVES + 1];  // partial sums, then the output slot
   // the grid may exceed the live output count (capacity fixed before the
   // count was known); the XCD remap runs over the live blocks only
   const int64_t nlive = live_blocks(live, epi);
@@ -174,7 +191,7 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(const int64_
                                                                     double* __restrict__ C, BlkOut Cp,
                                                                     double* __restrict__ norms, Epilogue epi) {
   constexpr int KB = B / 16;
-  __shared__ double red[MixCfg<B>::WAVES];
+  __shared__ double red[MixCfg<B>::WAVES + 1];  // partial sums, then the output slot
   const int64_t nlive = live_blocks(live, epi);
   if ((int64_t)blockIdx.x >= nlive) return;
   const int64_t blk = xcd_remap_m(blockIdx.x, nlive);
