@@ -147,6 +147,8 @@ typedef struct {
   int32_t iterations_reduced;/* node iterations whose correction ran in reduced precision */
   uint64_t mem_peak_bytes;   /* most device memory the handle's buffers held at once during the call */
   uint64_t mem_reserved_bytes;/* device memory the handle holds from HIP at the end of the call */
+  int32_t products_compacted;/* products written as kept blocks only (large products on one stream) */
+  int32_t pair_panels;       /* panels of block rows whose pair lists were built one at a time */
 } lif_info;
 
 /* Fills *o with the defaults: m = 4, tau = 0, FP64, paper stopping rule,

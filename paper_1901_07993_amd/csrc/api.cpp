@@ -164,6 +164,8 @@ void fill_info(lif_handle h, const RunInfo& ri, double seconds, lif_info* info) 
   info->iterations_reduced = ri.iterations_reduced;
   info->mem_peak_bytes = h->pool.peak();
   info->mem_reserved_bytes = h->pool.reserved();
+  info->products_compacted = (int32_t)h->ctx.stats.compacted;
+  info->pair_panels = (int32_t)h->ctx.stats.panels;
   info->nnzb_Z = h->has_Z ? exact_nnzb(h->ctx, h->Z) : 0;
   info->n_norms = (int32_t)std::min<size_t>(64, ri.norms_top.size());
   for (int k = 0; k < info->n_norms; ++k) info->norms[k] = ri.norms_top[k];

@@ -230,6 +230,8 @@ struct Stats {
   int redone = 0;  // presized iterations redone with exact sizes
   int cpl = 0;           // longest chain of dependent tasks so far (Bsr::cpl)
   int cpl_products = 0;  // products on it
+  int64_t compacted = 0;  // products written as kept blocks only
+  int64_t panels = 0;     // row panels of products built one pair list at a time
 };
 
 // Execution context shared by all operations of a handle.
@@ -469,7 +471,8 @@ void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* a
 void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp,
                           const int* bcol, const int* bidx, BlkIn ablk, BlkIn bblk, bool a_holes, bool b_holes,
                           const int* drp, const int* dcol, BlkIn dblk, int nb, const int* crp, const int64_t* prp,
-                          int* ccol, int64_t* seg, BlockPair* pairs, BlkOut dsrc, bool upper = false);
+                          int* ccol, int64_t* seg, BlockPair* pairs, BlkOut dsrc, bool upper = false, int row0 = 0,
+                          int rows = -1);
 // Symbolic phase in one launch when the capacities are known in advance:
 // counts, the prefix sums of the row counts (decoupled look-back) and the
 // fill.  Writes crp[0..nb]; totals to sizes[0..1]; when a total exceeds its

@@ -230,9 +230,46 @@ namespace {
 
 // Output stores above min(512 MiB, 1/64 of the device memory the handle may
 // use) are written compacted (kept blocks only), in chunks of at most
-// min(4 GiB, 1/16 of it) of untruncated output.
+// min(4 GiB, 1/16 of it) of untruncated output; pair lists above
+// min(2 GiB, 1/512 of it) are built one panel of block rows at a time.
 constexpr double kCompactMinBytes = 512.0 * double(1u << 20);
 constexpr double kCompactChunkBytes = 4.0 * double(1u << 30);
+constexpr double kPairPanelBytes = 2.0 * double(1u << 30);
+
+// Whether a product of `blocks` output blocks is written compacted: only
+// where freed memory is reusable at once (one stream).
+bool compact_output(Ctx& c, int64_t blocks, int b) {
+  const double dev = (double)c.device_bytes();
+  return !c.pool->deferring() && (double)blocks * b * b * sizeof(double) > std::min(kCompactMinBytes, dev / 64.0);
+}
+
+// Numeric phase of output blocks [e0, e1) of C (pattern and blk array
+// allocated), compacted: kept blocks only, written to consecutive slots of
+// one store per chunk of output blocks, each store cut to its kept blocks
+// once the chunk is done (a read-back per chunk), so that the untruncated
+// product is never held.  Dropped blocks get null pointers.  A
+// reduced-precision copy for the next product is made by that product.
+void numeric_compacted(Ctx& c, Bsr& C, int prec, bool ta, bool tb, const int64_t* seg, const BlockPair* pairs,
+                       int64_t e0, int64_t e1, const Epilogue& epi) {
+  const double blk_bytes = (double)C.b * C.b * sizeof(double);
+  const double dev = (double)c.device_bytes();
+  const int64_t chunk = std::max<int64_t>(1, (int64_t)(std::min(kCompactChunkBytes, dev / 16.0) / blk_bytes));
+  DBuf<unsigned long long> kept(c.pool, 1);
+  if (e0 == 0) ++c.stats.compacted;  // counted once per product
+  for (int64_t a = e0; a < e1; a += chunk) {
+    const int64_t n = std::min(chunk, e1 - a);
+    Store st = new_store(c, n, C.b);
+    launch_fill_i32(c, reinterpret_cast<int*>(kept.get()), 0, 2);
+    Epilogue e = epi;
+    e.slots = kept.get();
+    e.dsrc = epi.dsrc ? epi.dsrc + a : nullptr;
+    launch_numeric(c, prec, ta, tb, seg + a, pairs, n, nullptr, C.b, st->get(), C.blk.get() + a, nullptr, e);
+    unsigned long long k = 0;
+    c.d2h_batch({{&k, kept.get(), sizeof(k)}});
+    st->shrink((size_t)k * C.b * C.b);
+    if (k) C.store.push_back(st);
+  }
+}
 
 // The numeric phase of a product whose pattern, segments and pairs are
 // built: values, norms, truncation (or holes).
@@ -251,32 +288,11 @@ Bsr numeric_phase(Ctx& c, Bsr&& C, bool ta, bool tb, double tau, int prec, doubl
   epi.nrows = nb;
   const double blk_bytes = (double)C.b * C.b * sizeof(double);
   const double dev = (double)c.device_bytes();
-  if (keep_holes && tau > 0.0 && !poison && !c.pool->deferring() &&
-      (double)nnzc * blk_bytes > std::min(kCompactMinBytes, dev / 64.0)) {
-    // A large product with a known block count: kept blocks only, written
-    // to consecutive slots of one store per chunk of output blocks, each
-    // store cut to its kept blocks once the chunk is done (a read-back per
-    // chunk), so that the untruncated product is never held.  A
-    // reduced-precision copy for the next product is made by that product.
-    // Only where freed memory is reusable at once (one stream).
+  if (keep_holes && tau > 0.0 && !poison && compact_output(c, nnzc, C.b)) {
     epi.drop = true;
     epi.tau = tau;
     C.holes = true;
-    const int64_t chunk = std::max<int64_t>(1, (int64_t)(std::min(kCompactChunkBytes, dev / 16.0) / blk_bytes));
-    DBuf<unsigned long long> kept(c.pool, 1);
-    for (int64_t e0 = 0; e0 < nnzc; e0 += chunk) {
-      const int64_t n = std::min(chunk, nnzc - e0);
-      Store st = new_store(c, n, C.b);
-      launch_fill_i32(c, reinterpret_cast<int*>(kept.get()), 0, 2);
-      Epilogue e = epi;
-      e.slots = kept.get();
-      e.dsrc = dsrc ? dsrc + e0 : nullptr;
-      launch_numeric(c, prec, ta, tb, seg + e0, pairs, n, nullptr, C.b, st->get(), C.blk.get() + e0, nullptr, e);
-      unsigned long long k = 0;
-      c.d2h_batch({{&k, kept.get(), sizeof(k)}});
-      st->shrink((size_t)k * C.b * C.b);
-      if (k) C.store.push_back(st);
-    }
+    numeric_compacted(c, C, prec, ta, tb, seg, pairs, 0, nnzc, epi);
     return std::move(C);
   }
   Store st = new_store(c, nnzc, C.b);
@@ -420,6 +436,49 @@ Bsr spgemm_body(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau
       c.stats.flops += fl;
       if (prec != LIF_FP64) c.stats.flops_lowp += fl;
     }
+  }
+  const double dev = (double)c.device_bytes();
+  if (!planned && keep_holes && tau > 0.0 && nnzc > 0 && compact_output(c, nnzc, A.b) &&
+      (double)P * sizeof(BlockPair) > std::min(kPairPanelBytes, dev / 512.0)) {
+    // A large pair list: built and consumed one panel of block rows at a
+    // time (a pair list of at most the panel budget, except a single row
+    // above it), each panel's output compacted as it is computed.
+    const int64_t budget = std::max<int64_t>(1, (int64_t)(std::min(kPairPanelBytes, dev / 512.0) / sizeof(BlockPair)));
+    P = 0;  // no whole pair list
+    alloc_outputs();
+    C.blk = DBuf<const double*>(c.pool, (size_t)nnzc);
+    C.holes = true;
+    std::vector<int> hrp(nb + 1);
+    std::vector<int64_t> hpp(nb + 1);
+    c.d2h(hrp.data(), C.row_ptr.get(), sizeof(int) * (nb + 1));
+    c.d2h(hpp.data(), prp.get(), sizeof(int64_t) * (nb + 1));
+    Epilogue epi;
+    epi.alpha = alpha;
+    epi.gamma = gamma;
+    epi.dsrc = D ? dsrc.get() : nullptr;
+    epi.rows = C.row_ptr.get();
+    epi.nrows = nb;
+    epi.drop = true;
+    epi.tau = tau;
+    for (int r0 = 0; r0 < nb;) {
+      int r1 = r0 + 1;
+      while (r1 < nb && hpp[r1 + 1] - hpp[r0] <= budget) ++r1;
+      const int64_t base = hpp[r0], np = hpp[r1] - base;
+      if (hrp[r1] > hrp[r0]) {
+        DBuf<BlockPair> pp(c.pool, (size_t)std::max<int64_t>(np, 1));
+        // segment values stay global pair indices: the panel's pairs are
+        // addressed through a pointer shifted back by the panel's first one
+        BlockPair* shifted = reinterpret_cast<BlockPair*>(reinterpret_cast<uintptr_t>(pp.get()) -
+                                                          (uintptr_t)base * sizeof(BlockPair));
+        launch_symbolic_fill(c, av.rp, av.col, av.idx, bv.rp, bv.col, bv.idx, pa, pb, A.holes, B.holes, drp, dcol,
+                             D ? D->ptrs() : nullptr, nb, C.row_ptr.get(), prp.get(), C.col.get(), seg.get(), shifted,
+                             D ? dsrc.get() : nullptr, upper, r0, r1 - r0);
+        numeric_compacted(c, C, prec, ta, tb, seg.get(), shifted, hrp[r0], hrp[r1], epi);
+        ++c.stats.panels;
+      }
+      r0 = r1;
+    }
+    return C;
   }
   alloc_outputs();
   if (nnzc)

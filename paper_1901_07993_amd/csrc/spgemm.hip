@@ -128,10 +128,11 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
                                                           bool upper, const int* __restrict__ crp,
                                                           const int64_t* __restrict__ prp, int* __restrict__ ccol,
                                                           int64_t* __restrict__ seg, BlockPair* __restrict__ pairs,
-                                                          BlkOut dsrc) {
+                                                          BlkOut dsrc, int row0) {
   extern __shared__ unsigned smem[];
   __shared__ int scan_tmp[kSymWG / 64];
-  const int i = blockIdx.x;
+  const int i = row0 + (int)blockIdx.x;
+  const int row_end = row0 + (int)gridDim.x;  // rows [row0, row_end) in this launch
   const int nwords = (nb + 31) >> 5;
   unsigned* bm = smem;
   int* wp = reinterpret_cast<int*>(smem + nwords);
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill(const int* __restrict_
   int tot;
   int acc = block_exclusive_scan<int, kSymWG>(t, scan_tmp, &tot);
   int64_t prow = prp[i];
-  if (i == nb - 1 && threadIdx.x == 0) seg[crp[nb]] = prp[nb];  // closing segment pointer
+  if (i == row_end - 1 && threadIdx.x == 0) seg[crp[row_end]] = prp[row_end];  // closing segment pointer
   for (int r = c0; r < c1; ++r) {
     const int cnt = cur[r];
     seg[cbase + r] = prow + acc;
@@ -267,13 +268,13 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill_masked(
     const int* __restrict__ brp, const int* __restrict__ bcol, const int* __restrict__ bidx, BlkIn ablk,
     BlkIn bblk, bool a_holes, bool b_holes, const int* __restrict__ drp, const int* __restrict__ dcol, BlkIn dblk,
     int nb, bool upper, int* __restrict__ crp, const int64_t* __restrict__ prp, int* __restrict__ ccol,
-    int64_t* __restrict__ seg, BlockPair* __restrict__ pairs, BlkOut dsrc, OnePass op) {
+    int64_t* __restrict__ seg, BlockPair* __restrict__ pairs, BlkOut dsrc, OnePass op, int row0) {
   extern __shared__ unsigned long long smem64[];
   __shared__ int scan_tmp[kSymWG / 64];
   __shared__ int64_t scan_tmp64[kSymWG / 64];
   __shared__ int64_t off_sh[2];
   __shared__ int flag_sh;
-  const int i = blockIdx.x;
+  const int i = row0 + (int)blockIdx.x;  // row0 = 0 in the one-pass form
   const int nwords = (nb + 31) >> 5;
   unsigned long long* mask = smem64;
   unsigned* bm = reinterpret_cast<unsigned*>(smem64 + nb);
@@ -419,7 +420,8 @@ __global__ __launch_bounds__(kSymWG) void k_symbolic_fill_masked(
   } else {
     cbase = crp[i];
     prow = prp[i];
-    if (i == nb - 1 && threadIdx.x == 0) seg[crp[nb]] = prp[nb];  // closing segment pointer
+    const int row_end = row0 + (int)gridDim.x;  // rows [row0, row_end) in this launch
+    if (i == row_end - 1 && threadIdx.x == 0) seg[crp[row_end]] = prp[row_end];  // closing segment pointer
   }
   if (!fits) return;  // uniform over the workgroup
 
@@ -706,19 +708,21 @@ void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* a
 void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp, const int* bcol,
                           const int* bidx, BlkIn ablk, BlkIn bblk, bool a_holes, bool b_holes, const int* drp,
                           const int* dcol, BlkIn dblk, int nb, const int* crp, const int64_t* prp, int* ccol,
-                          int64_t* seg, BlockPair* pairs, BlkOut dsrc, bool upper) {
+                          int64_t* seg, BlockPair* pairs, BlkOut dsrc, bool upper, int row0, int rows) {
+  if (rows < 0) rows = nb - row0;
+  LIF_REQUIRE(row0 >= 0 && rows >= 1 && row0 + rows <= nb, LIF_ERR_INVALID, "symbolic fill: row range");
   if (masked_fill_lds_bytes(nb) <= kMaskedFillLds) {
     allow_lds((const void*)k_symbolic_fill_masked<false>, masked_fill_lds_bytes(nb));
-    hipLaunchKernelGGL(k_symbolic_fill_masked<false>, dim3(nb), dim3(kSymWG), masked_fill_lds_bytes(nb), c.stream,
+    hipLaunchKernelGGL(k_symbolic_fill_masked<false>, dim3(rows), dim3(kSymWG), masked_fill_lds_bytes(nb), c.stream,
                        arp, acol, aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb, upper,
-                       const_cast<int*>(crp), prp, ccol, seg, pairs, dsrc, OnePass{});
+                       const_cast<int*>(crp), prp, ccol, seg, pairs, dsrc, OnePass{}, row0);
     LIF_HIP(hipGetLastError());
     return;
   }
   allow_lds((const void*)k_symbolic_fill, symbolic_lds_bytes(nb, true));
-  hipLaunchKernelGGL(k_symbolic_fill, dim3(nb), dim3(kSymWG), symbolic_lds_bytes(nb, true), c.stream, arp, acol,
+  hipLaunchKernelGGL(k_symbolic_fill, dim3(rows), dim3(kSymWG), symbolic_lds_bytes(nb, true), c.stream, arp, acol,
                      aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb, upper, crp, prp, ccol,
-                     seg, pairs, dsrc);
+                     seg, pairs, dsrc, row0);
   LIF_HIP(hipGetLastError());
 }
 
@@ -738,7 +742,7 @@ void launch_symbolic_onepass(Ctx& c, const int* arp, const int* acol, const int*
   allow_lds((const void*)k_symbolic_fill_masked<true>, masked_fill_lds_bytes(nb));
   hipLaunchKernelGGL(k_symbolic_fill_masked<true>, dim3(nb), dim3(kSymWG), masked_fill_lds_bytes(nb), c.stream, arp,
                      acol, aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb, upper, crp,
-                     nullptr, ccol, seg, pairs, dsrc, op);
+                     nullptr, ccol, seg, pairs, dsrc, op, 0);
   LIF_HIP(hipGetLastError());
 }
 

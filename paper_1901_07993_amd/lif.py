@@ -58,7 +58,8 @@ class Info(ctypes.Structure):
                 ("leaf_gemm_launches", c_int64), ("products_total", c_int64), ("nnzb_Z", c_int64),
                 ("n_norms", c_int32), ("norms", c_double * 64), ("iterations_redone", c_int32),
                 ("cpl_tasks", c_int32), ("cpl_products", c_int32), ("iterations_reduced", c_int32),
-                ("mem_peak_bytes", c_uint64), ("mem_reserved_bytes", c_uint64)]
+                ("mem_peak_bytes", c_uint64), ("mem_reserved_bytes", c_uint64), ("products_compacted", c_int32),
+                ("pair_panels", c_int32)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "norms"}

@@ -4,7 +4,8 @@ GPU's memory):
 
 * iterations on one stream with every buffer freed after its last reader;
 * products written as kept blocks only, in chunks, each chunk's store cut to
-  its kept blocks (the untruncated product is never held);
+  its kept blocks (the untruncated product is never held), their pair lists
+  built one panel of block rows at a time;
 * the true residual formed by panels of block rows.
 
 None of them changes a value: a capped factorization gives Z bit for bit
@@ -54,13 +55,21 @@ def test_capped_run_matches_uncapped(variant):
     say(f"case memory cap water-300 n={S.n} {variant}")
     i0, Z0, r0 = _run(S, 0, **opts)
     peak = int(i0["mem_peak_bytes"])
-    # twice the uncapped peak: every policy switches on (one stream from an
-    # iteration's 6 Z-sized buffers over a quarter of the cap, compaction
-    # above 1/64 of it, chunks of 1/16, residual panels of 1/16)
-    cap = 2 * peak
+    # a quarter above the uncapped peak (the capped runs need about 0.7 of
+    # it): every policy switches on (one stream once an iteration's buffers
+    # exceed a quarter of the cap or take the pool past half of it,
+    # compaction above 1/64 of it, chunks of 1/16, pair lists in row panels
+    # above 1/512, residual panels of 1/16)
+    cap = peak + peak // 4
     i1, Z1, r1 = _run(S, cap, **opts)
     say(f"  uncapped peak {peak / 2**20:.1f} MiB, capped peak {i1['mem_peak_bytes'] / 2**20:.1f} MiB; "
-        f"iterations {i0['iterations_total']} / {i1['iterations_total']}; residual {r0:.6e} / {r1:.6e}")
+        f"iterations {i0['iterations_total']} / {i1['iterations_total']}; residual {r0:.6e} / {r1:.6e}; "
+        f"compacted {i0['products_compacted']} / {i1['products_compacted']}, "
+        f"pair panels {i0['pair_panels']} / {i1['pair_panels']}")
+    assert i0["products_compacted"] == 0 and i0["pair_panels"] == 0
+    assert i1["products_compacted"] > 0
+    if variant == "fp64":  # the full products' pair lists exceed the panel budget
+        assert i1["pair_panels"] > 0
     zblk = Z0.vals.shape[1] * Z0.vals.shape[2] * 8
     assert Z0.nnzb * zblk > cap / 64, "the factor is too small for the cap to compact its products"
     assert i1["mem_peak_bytes"] <= cap
