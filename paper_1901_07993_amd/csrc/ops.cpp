@@ -231,7 +231,9 @@ namespace {
 // Output stores above min(512 MiB, 1/64 of the device memory the handle may
 // use) are written compacted (kept blocks only), in chunks of at most
 // min(4 GiB, 1/16 of it) of untruncated output; pair lists above
-// min(2 GiB, 1/512 of it) are built one panel of block rows at a time.
+// min(2 GiB, 1/512 of it) are built one panel of block rows at a time when
+// memory is short (the list above 1/64 of it, or taking the pool past half
+// of it): each panel ends in a drain of the GPU, a cost paid only there.
 constexpr double kCompactMinBytes = 512.0 * double(1u << 20);
 constexpr double kCompactChunkBytes = 4.0 * double(1u << 30);
 constexpr double kPairPanelBytes = 2.0 * double(1u << 30);
@@ -437,9 +439,10 @@ Bsr spgemm_body(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau
       if (prec != LIF_FP64) c.stats.flops_lowp += fl;
     }
   }
-  const double dev = (double)c.device_bytes();
+  const double dev = (double)c.device_bytes(), pair_bytes = (double)P * sizeof(BlockPair);
   if (!planned && keep_holes && tau > 0.0 && nnzc > 0 && compact_output(c, nnzc, A.b) &&
-      (double)P * sizeof(BlockPair) > std::min(kPairPanelBytes, dev / 512.0)) {
+      pair_bytes > std::min(kPairPanelBytes, dev / 512.0) &&
+      (pair_bytes > dev / 64.0 || (double)c.pool->reserved() + pair_bytes > 0.5 * dev)) {
     // A large pair list: built and consumed one panel of block rows at a
     // time (a pair list of at most the panel budget, except a single row
     // above it), each panel's output compacted as it is computed.
