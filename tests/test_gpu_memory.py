@@ -43,12 +43,18 @@ def _run(S, cap, **opts):
     return info, Z, res
 
 
-@pytest.mark.parametrize("variant", ["fp64", "fp64_sym", "bf16_schedule_sym"])
+@pytest.mark.parametrize("variant", ["fp64", "fp64_sym", "bf16_schedule_sym", "chain_fp64"])
 def test_capped_run_matches_uncapped(variant):
-    c_, e_ = water_cluster(300, 17)
-    S = overlap_blocks(c_, e_, 32)                 # n = 2100, b = 32, 66 block rows
-    opts = dict(tau=1e-6, base_rows=512)
-    if variant != "fp64":
+    if variant.startswith("chain"):
+        # several problems per level, sparse products (a few block products
+        # per output block), some problems stopping before others
+        S, cfg = config_matrix(1, count=150)       # n = 3000, b = 64, 47 block rows
+        opts = dict(tau=cfg["tau"], base_rows=512)
+    else:
+        c_, e_ = water_cluster(300, 17)
+        S = overlap_blocks(c_, e_, 32)             # n = 2100, b = 32, 66 block rows
+        opts = dict(tau=1e-6, base_rows=512)
+    if variant in ("fp64_sym", "bf16_schedule_sym"):
         opts["sym_delta"] = 1
     if variant.startswith("bf16"):
         opts.update(prec=lif.MIXED_BF16, prec_switch=1e-2)
