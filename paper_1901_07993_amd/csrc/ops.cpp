@@ -232,17 +232,23 @@ namespace {
 // use) are written compacted (kept blocks only), in chunks of at most
 // min(4 GiB, 1/16 of it) of untruncated output; pair lists above
 // min(2 GiB, 1/512 of it) are built one panel of block rows at a time when
-// memory is short (the list above 1/64 of it, or taking the pool past half
-// of it): each panel ends in a drain of the GPU, a cost paid only there.
+// the product is compacted and memory is short (the list above 1/64 of it,
+// or taking the pool past half of it): each panel ends in a drain of the
+// GPU, a cost paid only there.
 constexpr double kCompactMinBytes = 512.0 * double(1u << 20);
 constexpr double kCompactChunkBytes = 4.0 * double(1u << 30);
 constexpr double kPairPanelBytes = 2.0 * double(1u << 30);
 
 // Whether a product of `blocks` output blocks is written compacted: only
-// where freed memory is reusable at once (one stream).
+// where freed memory is reusable at once (one stream); with a memory cap
+// whenever the store is large, without one only when memory is short (the
+// untruncated store would take the buffers in use past half of the GPU's
+// memory): the chunks' read-backs and slot atomics cost about 6 % of the
+// products' time on a water cluster that fits without them.
 bool compact_output(Ctx& c, int64_t blocks, int b) {
-  const double dev = (double)c.device_bytes();
-  return !c.pool->deferring() && (double)blocks * b * b * sizeof(double) > std::min(kCompactMinBytes, dev / 64.0);
+  const double dev = (double)c.device_bytes(), bytes = (double)blocks * b * b * sizeof(double);
+  return !c.pool->deferring() && bytes > std::min(kCompactMinBytes, dev / 64.0) &&
+         (c.pool->cap() != 0 || (double)c.pool->in_use() + bytes > 0.5 * dev);
 }
 
 // Numeric phase of output blocks [e0, e1) of C (pattern and blk array
