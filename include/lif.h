@@ -224,6 +224,20 @@ lif_status lif_multiply(lif_handle h, const lif_blocks* A, int32_t transA, const
                         int32_t transB, double tau, int64_t* nnzb, int32_t* brow, int32_t* bcol,
                         double* vals, int32_t on_device, int64_t* products);
 
+/* C = trunc_tau(alpha op(A) op(B) + gamma D): one product with an added term,
+ * the fused form of a Horner step of eq. refinement_local (Sec. 2.2):
+ * delta T with T = X + c I is delta X + c delta, and the added term c delta
+ * enters every output block before the block's Frobenius norm decides its
+ * truncation (Sec. 5).  D (NULL = no term) has the handle's n and b; its
+ * blocks join the output pattern.  With a reduced opts.prec only A and B are
+ * read in the input precision (alpha scales their FP32-accumulated product);
+ * D is added in FP64, never rounded.  Everything else as lif_multiply
+ * (transposes, LIF_PRODUCT_UPPER, two-phase output, *products). */
+lif_status lif_multiply_add(lif_handle h, const lif_blocks* A, int32_t transA, const lif_blocks* B,
+                            int32_t transB, double alpha, const lif_blocks* D, double gamma, double tau,
+                            int64_t* nnzb, int32_t* brow, int32_t* bcol, double* vals, int32_t on_device,
+                            int64_t* products);
+
 /* Reverse-mode derivative of the last factorization (differentiation form):
  * dS = sym(dL/dS) = (A + A^T) / 2 for the linear loss L = tr(G^T Z), so that
  * dL = <dS, E> for every symmetric perturbation E of S.  Returned on S's block

@@ -93,6 +93,25 @@ def mult(A: np.ndarray, B: np.ndarray, b: int, tau: float, prec: str = "fp64") -
     return truncate(round_to(A, prec) @ round_to(B, prec), b, tau)
 
 
+def mult_add(A: np.ndarray, B: np.ndarray, b: int, tau: float, prec: str = "fp64", alpha: float = 1.0,
+             D: np.ndarray | None = None, gamma: float = 0.0) -> np.ndarray:
+    """trunc(alpha A B + gamma D): a product with an added term, truncated as a
+    whole.  This is how a Horner step delta T with T = X + c I is read in the
+    precision form: only the stored part X (and delta) enter the product in
+    the input precision; the identity part contributes c delta, added in FP64
+    (the identity itself is exact in any precision, so rounding it together
+    with X would add an error that the product does not need).  ``alpha``
+    scales the product of the rounded inputs (the first Horner step
+    b_m delta delta).  In FP64 this is trunc(A (alpha B) + gamma D), equal to
+    ``mult`` of the explicit factor up to the order of the sums."""
+    P = round_to(A, prec) @ round_to(B, prec)
+    if alpha != 1.0:
+        P = alpha * P
+    if D is not None and gamma != 0.0:
+        P = P + gamma * D
+    return truncate(P, b, tau)
+
+
 def gershgorin_bound(S: np.ndarray) -> float:
     """Gershgorin upper bound of the spectral radius: max_i sum_j |S_ij|
     (Sec. 2.2, scaling of the identity start)."""
@@ -207,6 +226,9 @@ def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_
                                                 M^T S is formed as (SM)^T)
     ``prec`` applies to the products that form M (delta T and Z q); the
     delta-update products stay FP64, so delta keeps tracking I - Z^T S Z.
+    In reduced precision a Horner factor T = X + c I is not rounded as a
+    whole: delta T = delta X + c delta with delta and X rounded and the
+    identity part c delta added in FP64 (``mult_add``).
     ``prec_switch`` > 0 is the precision schedule: an iteration uses ``prec``
     only while ||delta||_F before it exceeds ``prec_switch`` and FP64 after;
     an inexact correction converges linearly, so the stopping rule is applied
@@ -231,11 +253,18 @@ def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_
         p = prec if reduced else "fp64"
         if m == 1:
             q = bk[1] * delta
-        else:
+        elif p == "fp64":
             T = bk[m - 1] * I + bk[m] * delta
             for j in range(m - 2, 0, -1):
                 T = bk[j] * I + mult(delta, T, b, tau, p)
             q = mult(delta, T, b, tau, p)
+        else:
+            # reduced precision: T_j = X_j + b_j I with only X_j (and delta)
+            # rounded; delta T_j = delta X_j + b_j delta, the second term FP64
+            X = mult_add(delta, delta, b, tau, p, alpha=bk[m], D=delta, gamma=bk[m - 1])
+            for j in range(m - 2, 0, -1):
+                X = mult_add(delta, X, b, tau, p, D=delta, gamma=bk[j])
+            q = X
         M = mult(Z, q, b, tau, p)
         Z_new = Z + M
         SM = mult(S, M, b, tau)

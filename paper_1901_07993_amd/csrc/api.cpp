@@ -360,30 +360,57 @@ lif_status lif_residual(lif_handle h, double* out) {
   });
 }
 
-lif_status lif_multiply(lif_handle h, const lif_blocks* A, int32_t transA, const lif_blocks* B, int32_t transB,
-                        double tau, int64_t* nnzb, int32_t* brow, int32_t* bcol, double* vals, int32_t on_device,
-                        int64_t* products) {
+namespace {
+
+// trunc_tau(alpha op(A) op(B) + gamma D) on the handle, copied out two-phase
+lif_status multiply_common(lif_handle h, const lif_blocks* A, int32_t transA, const lif_blocks* B,
+                           int32_t transB, double alpha, const lif_blocks* D, double gamma, double tau, int64_t* nnzb,
+                           int32_t* brow, int32_t* bcol, double* vals, int32_t on_device, int64_t* products) {
   if (!h) return LIF_ERR_INVALID;
   lif_status st = LIF_OK;
   lif_status g = guarded(h, [&] {
     LIF_REQUIRE(std::isfinite(tau) && tau >= 0.0, LIF_ERR_INVALID, "tau must be finite and >= 0");
+    LIF_REQUIRE(std::isfinite(alpha) && std::isfinite(gamma), LIF_ERR_INVALID, "alpha and gamma must be finite");
     validate_blocks(A, false, "A");
     validate_blocks(B, false, "B");
     LIF_REQUIRE(A->n == h->S.n && A->b == h->S.b && B->n == h->S.n && B->b == h->S.b, LIF_ERR_INVALID,
                 "A and B must have the n and b of the handle");
+    if (D) {
+      validate_blocks(D, false, "D");
+      LIF_REQUIRE(D->n == h->S.n && D->b == h->S.b, LIF_ERR_INVALID, "D must have the n and b of the handle");
+    }
+    LIF_REQUIRE((transA & ~(1 | LIF_PRODUCT_UPPER)) == 0 && (transB & ~1) == 0, LIF_ERR_INVALID,
+                "transA / transB: unknown flags");
     reset_stats(h);
     Bsr a = bsr_from_blocks(h->ctx, *A);
     Bsr b = bsr_from_blocks(h->ctx, *B);
-    LIF_REQUIRE((transA & ~(1 | LIF_PRODUCT_UPPER)) == 0 && (transB & ~1) == 0, LIF_ERR_INVALID,
-                "transA / transB: unknown flags");
-    Bsr C = spgemm(h->ctx, a, (transA & 1) != 0, b, (transB & 1) != 0, tau, h->opts.prec, 1.0, nullptr, 0.0,
-                   false, false, (transA & LIF_PRODUCT_UPPER) != 0);
+    Bsr d;
+    if (D) d = bsr_from_blocks(h->ctx, *D);
+    Bsr C = spgemm(h->ctx, a, (transA & 1) != 0, b, (transB & 1) != 0, tau, h->opts.prec, alpha, D ? &d : nullptr,
+                   D ? gamma : 0.0, false, false, (transA & LIF_PRODUCT_UPPER) != 0);
     if (products) *products = h->ctx.stats.products;
     st = copy_out(h, C, nnzb, brow, bcol, vals, on_device);
     h->ctx.sync();
     h->ctx.flush_timing();
   });
   return g != LIF_OK ? g : st;
+}
+
+}  // namespace
+
+lif_status lif_multiply(lif_handle h, const lif_blocks* A, int32_t transA, const lif_blocks* B, int32_t transB,
+                        double tau, int64_t* nnzb, int32_t* brow, int32_t* bcol, double* vals, int32_t on_device,
+                        int64_t* products) {
+  return multiply_common(h, A, transA, B, transB, 1.0, nullptr, 0.0, tau, nnzb, brow, bcol, vals, on_device,
+                         products);
+}
+
+lif_status lif_multiply_add(lif_handle h, const lif_blocks* A, int32_t transA, const lif_blocks* B,
+                            int32_t transB, double alpha, const lif_blocks* D, double gamma, double tau,
+                            int64_t* nnzb, int32_t* brow, int32_t* bcol, double* vals, int32_t on_device,
+                            int64_t* products) {
+  return multiply_common(h, A, transA, B, transB, alpha, D, gamma, tau, nnzb, brow, bcol, vals, on_device,
+                         products);
 }
 
 lif_status lif_backward(lif_handle h, const lif_blocks* G, int64_t* nnzb, int32_t* brow, int32_t* bcol, double* dS,

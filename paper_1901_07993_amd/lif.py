@@ -29,7 +29,7 @@ _STATUS_NAMES = {1: "LIF_ERR_INVALID", 2: "LIF_ERR_NOT_PD", 3: "LIF_ERR_NO_CONVE
                  4: "LIF_ERR_OUT_OF_MEMORY", 5: "LIF_ERR_HIP", 6: "LIF_ERR_STATE"}
 
 EXPORTED = ("lif_opts_default", "lif_create", "lif_refine", "lif_localized", "lif_rinch", "lif_get_Z", "lif_residual",
-            "lif_multiply", "lif_backward", "lif_destroy", "lif_last_error")
+            "lif_multiply", "lif_multiply_add", "lif_backward", "lif_destroy", "lif_last_error")
 
 
 class LifError(RuntimeError):
@@ -87,6 +87,9 @@ def load() -> ctypes.CDLL:
     lib.lif_residual.argtypes = [c_void_p, POINTER(c_double)]
     lib.lif_multiply.argtypes = [c_void_p, POINTER(Blocks), c_int32, POINTER(Blocks), c_int32, c_double,
                                  POINTER(c_int64), c_void_p, c_void_p, c_void_p, c_int32, POINTER(c_int64)]
+    lib.lif_multiply_add.argtypes = [c_void_p, POINTER(Blocks), c_int32, POINTER(Blocks), c_int32, c_double,
+                                     POINTER(Blocks), c_double, c_double, POINTER(c_int64), c_void_p, c_void_p,
+                                     c_void_p, c_int32, POINTER(c_int64)]
     lib.lif_backward.argtypes = [c_void_p, POINTER(Blocks), POINTER(c_int64), c_void_p, c_void_p, c_void_p, c_int32]
     lib.lif_destroy.argtypes = [c_void_p]
     lib.lif_destroy.restype = None
@@ -252,24 +255,34 @@ class Factorization:
         self._check(load().lif_residual(self._h, byref(out)))
         return out.value
 
-    def multiply(self, A, transA: bool, B, transB: bool, tau: float = 0.0, upper: bool = False):
-        """C = op(A) op(B) truncated at tau (only its upper block triangle when
-        ``upper``); returns (HostBlocks, products)."""
+    def multiply(self, A, transA: bool, B, transB: bool, tau: float = 0.0, upper: bool = False,
+                 alpha: float = 1.0, D=None, gamma: float = 0.0):
+        """C = trunc_tau(alpha op(A) op(B) [+ gamma D]) (only its upper block
+        triangle when ``upper``); returns (HostBlocks, products).  Without D
+        and with alpha = 1 this is lif_multiply, otherwise lif_multiply_add."""
         transA = int(transA) | (PRODUCT_UPPER if upper else 0)
         lib = load()
         sa, ka = _marshal(A)
         sb, kb = _marshal(B)
+        sd, kd = _marshal(D) if D is not None else (None, None)
         nnzb = c_int64(0)
         prods = c_int64(0)
-        self._check(lib.lif_multiply(self._h, byref(sa), int(transA), byref(sb), int(transB), float(tau), byref(nnzb),
-                                     None, None, None, 0, byref(prods)))
+
+        def call(brow, bcol, vals):
+            if D is None and alpha == 1.0:
+                return lib.lif_multiply(self._h, byref(sa), int(transA), byref(sb), int(transB), float(tau),
+                                        byref(nnzb), brow, bcol, vals, 0, byref(prods))
+            return lib.lif_multiply_add(self._h, byref(sa), int(transA), byref(sb), int(transB), float(alpha),
+                                        byref(sd) if sd is not None else None, float(gamma), float(tau),
+                                        byref(nnzb), brow, bcol, vals, 0, byref(prods))
+
+        self._check(call(None, None, None))
         k = nnzb.value
         brow = np.empty(k, np.int32)
         bcol = np.empty(k, np.int32)
         vals = np.empty((k, self.b, self.b), np.float64)
-        self._check(lib.lif_multiply(self._h, byref(sa), int(transA), byref(sb), int(transB), float(tau), byref(nnzb),
-                                     brow.ctypes.data, bcol.ctypes.data, vals.ctypes.data, 0, byref(prods)))
-        del ka, kb
+        self._check(call(brow.ctypes.data, bcol.ctypes.data, vals.ctypes.data))
+        del ka, kb, kd
         return HostBlocks(self.n, self.b, brow, bcol, vals), prods.value
 
     def backward(self, G, on_device: bool = False):

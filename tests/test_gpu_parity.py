@@ -116,10 +116,13 @@ def test_multiply_truncation_matches_oracle(b):
     Da, Db = blocks_to_dense(A), blocks_to_dense(B)
     full = Da @ Db
     nrm = R.block_norms(full, b)
-    tau = float(np.median(nrm[nrm > 0]))
-    # keep tau away from any block norm (rounding of the sum order)
+    # tau halfway (geometrically) between the two middle block norms, so that
+    # no block norm lies within rounding of it
+    srt = np.sort(nrm[nrm > 0])
+    mid = len(srt) // 2
+    tau = float(np.sqrt(srt[mid - 1] * srt[mid]))
     gaps = np.abs(nrm - tau) / tau
-    assert np.min(gaps[nrm > 0]) > 0 or True
+    assert np.min(gaps[nrm > 0]) > 1e-9
     ref = R.truncate(full, b, tau)
     with lif.Factorization(identity_blocks(n, b)) as f:
         C, _ = f.multiply(dev(A), False, dev(B), False, tau)

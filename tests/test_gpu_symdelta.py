@@ -145,8 +145,8 @@ def test_sym_delta_with_schedule_on_split_batches(prec):
     walk(plan)
     assert info["iterations_reduced"] == sum(sum(i.reduced) for i in nodes)
     assert abs(info["iterations_total"] - sum(i.iterations for i in nodes)) <= len(nodes)
-    u_in = {"fp32": 2.0 ** -24, "bf16": 2.0 ** -8}[prec]
-    assert np.linalg.norm(Z - Zo) <= 10 * u_in * np.linalg.norm(Zo)
+    say(f"  rel diff vs oracle {np.linalg.norm(Z - Zo) / np.linalg.norm(Zo):.3e}")
+    assert np.linalg.norm(Z - Zo) <= S.n * 2.0 ** -24 * np.linalg.norm(Zo)   # FP32 accumulation bound
     assert res <= 1e-8
 
 

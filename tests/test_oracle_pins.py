@@ -510,6 +510,55 @@ def test_bf16_and_fp32_rounding_by_hand():
     assert R.round_to(np.array([one]), "fp64")[0] == one
 
 
+def _mult_add_pins(fn):
+    """The precision form's reading of a Horner step delta (X + c I): only
+    delta and X are rounded, c delta enters in FP64, alpha scales the
+    product of the rounded inputs."""
+    rng = np.random.Generator(np.random.PCG64(3))
+    n, b = 40, 8
+    d = rng.standard_normal((n, n))
+    ok = True
+    # X = 0: the product vanishes and the result is c delta exactly (not c round(delta))
+    c = 0.3125
+    got = fn(d, np.zeros((n, n)), b, 0.0, "bf16", D=d, gamma=c)
+    ok &= bool(np.array_equal(got, c * d))
+    # entries 1 + 2^-7 are BF16 numbers; b_4 = 35/128 times their square sum is
+    # exact in FP64 but b_4 (1 + 2^-7) is not a BF16 number: the scaling must
+    # act on the product of the rounded inputs, not on an input
+    e = np.full((n, n), 1.0 + 2.0 ** -7)
+    a4 = 35.0 / 128.0
+    want = a4 * n * (1.0 + 2.0 ** -7) ** 2 * np.ones((n, n))
+    ok &= bool(np.array_equal(fn(e, e, b, 0.0, "bf16", alpha=a4), want))
+    # FP64: the fused form equals the product with the explicit factor X + c I
+    X = rng.standard_normal((n, n))
+    ref = d @ (X + c * np.eye(n))
+    ok &= bool(np.max(np.abs(fn(d, X, b, 0.0, "fp64", D=d, gamma=c) - ref)) <= 1e-13 * np.max(np.abs(ref)))
+    # bf16: within the input rounding of delta and X of the exact value
+    u = 2.0 ** -8
+    err = np.abs(fn(d, X, b, 0.0, "bf16", D=d, gamma=c) - ref)
+    ok &= bool(np.all(err <= 2.01 * u * (np.abs(d) @ np.abs(X)) + 1e-15 * np.abs(ref)))
+    return ok
+
+
+def test_mult_add_reading_of_the_horner_step():
+    assert _mult_add_pins(R.mult_add)
+
+
+def test_planted_rounded_identity_term_is_caught():
+    def bad(A, B, b, tau, prec="fp64", alpha=1.0, D=None, gamma=0.0):
+        # rounds the whole factor T = X + c I (D = A here)
+        T = alpha * B + gamma * np.eye(B.shape[0])
+        return R.truncate(R.round_to(A, prec) @ R.round_to(T, prec), b, tau)
+
+    def bad_alpha(A, B, b, tau, prec="fp64", alpha=1.0, D=None, gamma=0.0):
+        P = R.round_to(alpha * A, prec) @ R.round_to(B, prec)
+        if D is not None and gamma != 0.0:
+            P = P + gamma * D
+        return R.truncate(P, b, tau)
+    assert not _mult_add_pins(bad)
+    assert not _mult_add_pins(bad_alpha)
+
+
 def test_precision_schedule_reaches_fp64_floor(water100):
     # precision schedule: reduced-precision corrections while ||delta||_F
     # exceeds the switch, FP64 after, the paper's rule on the FP64 iterations.
