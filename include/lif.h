@@ -238,6 +238,40 @@ lif_status lif_multiply_add(lif_handle h, const lif_blocks* A, int32_t transA, c
                             int64_t* nnzb, int32_t* brow, int32_t* bcol, double* vals, int32_t on_device,
                             int64_t* products);
 
+/* Bytes of the device array lif_multiply_noalloc works in (one per GPU). */
+#define LIF_NOALLOC_SCRATCH_BYTES (256ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture setup, tight serving loops, harnesses that forbid hipMalloc): the
+ * product of lif_multiply_add, C = trunc_tau(alpha op(A) op(B) + gamma D),
+ * without a handle and without any device or pinned-host allocation.  Every
+ * working buffer (index arrays, block-product lists, the product's values
+ * before truncation, reduced-precision copies) is carved from one library
+ * array of LIF_NOALLOC_SCRATCH_BYTES in device memory, one copy per GPU,
+ * held from the library's first use on that GPU until the process ends.
+ * A product whose working set does not fit it is rejected with
+ * LIF_ERR_OUT_OF_MEMORY and a message naming the limit (lif_last_error(NULL)).
+ * The array keeps whatever the last call left; calls on one GPU are
+ * serialized by a lock in the library, and a call that overlaps another use
+ * of the array on that GPU (another process's copy excepted) would race.
+ *   A, B, D: block lists on the current device (on_device = 1), the same n
+ *     and b (32 or 64); D may be NULL (no added term, gamma ignored).
+ *   transA: bit 0 transposes A, LIF_PRODUCT_UPPER keeps the upper block
+ *     triangle; transB: bit 0 transposes B.
+ *   prec: LIF_FP64, LIF_MIXED_FP32 or LIF_MIXED_BF16 (A and B read in that
+ *     precision, FP32 accumulation, D added in FP64).
+ *   stream: hipStream_t for the work (NULL = the null stream).
+ *   capacity: blocks the output arrays hold; brow, bcol (int32) and vals
+ *     (capacity * b * b FP64) are device arrays, written in (row, col) order.
+ *   *nnzb: blocks of C on success; when capacity is too small,
+ *     LIF_ERR_INVALID with *nnzb = the blocks needed and the outputs untouched.
+ *   *products (may be NULL): block products of the symbolic phase.
+ * Returns once C is complete. */
+lif_status lif_multiply_noalloc(const lif_blocks* A, int32_t transA, const lif_blocks* B, int32_t transB,
+                                double alpha, const lif_blocks* D, double gamma, double tau, int32_t prec,
+                                void* stream, int64_t capacity, int64_t* nnzb, int32_t* brow, int32_t* bcol,
+                                double* vals, int64_t* products);
+
 /* Reverse-mode derivative of the last factorization (differentiation form):
  * dS = sym(dL/dS) = (A + A^T) / 2 for the linear loss L = tr(G^T Z), so that
  * dL = <dS, E> for every symmetric perturbation E of S.  Returned on S's block

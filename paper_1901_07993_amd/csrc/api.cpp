@@ -72,7 +72,7 @@ HostIndex host_index(const lif_blocks& B) {
 
 // Checks a block list: shape, sorted unique in-range coordinates, zero
 // padding beyond n; optionally a symmetric block pattern.
-void validate_blocks(const lif_blocks* B, bool need_symmetric, const char* what) {
+void check_blocks(const lif_blocks* B, bool need_symmetric, const char* what) {
   const std::string w(what);
   LIF_REQUIRE(B != nullptr, LIF_ERR_INVALID, w + ": null block list");
   LIF_REQUIRE(B->n > 0, LIF_ERR_INVALID, w + ": n must be > 0");
@@ -196,6 +196,13 @@ lif_status copy_out(lif_handle h, const Bsr& A, int64_t* nnzb, int32_t* brow, in
 
 }  // namespace
 
+namespace lif {
+void validate_blocks(const lif_blocks* B, bool need_symmetric, const char* what) {
+  check_blocks(B, need_symmetric, what);
+}
+void set_thread_error(const std::string& msg) { g_create_error = msg; }
+}  // namespace lif
+
 extern "C" {
 
 lif_status lif_opts_default(lif_opts* o) {
@@ -232,7 +239,7 @@ lif_status lif_create(const lif_blocks* S, const lif_opts* o, lif_handle* out) {
   lif_handle h = nullptr;
   try {
     validate_opts(*o);
-    validate_blocks(S, true, "S");
+    check_blocks(S, true, "S");
     LIF_REQUIRE(o->base_rows >= S->b, LIF_ERR_INVALID, "opts.base_rows must be >= b");
     h = new lif_handle_s(o->mem_cap_bytes);
     Opts& p = h->opts;
@@ -287,7 +294,7 @@ lif_status lif_refine(lif_handle h, const lif_blocks* Z0, lif_info* info) {
     RunInfo ri;
     Bsr Z;
     if (Z0) {
-      validate_blocks(Z0, false, "Z0");
+      check_blocks(Z0, false, "Z0");
       LIF_REQUIRE(Z0->n == h->S.n && Z0->b == h->S.b, LIF_ERR_INVALID, "Z0 must have the n and b of S");
       Bsr z = bsr_from_blocks(h->ctx, *Z0);
       Z = run_refine_from(h->ctx, h->S, std::move(z), h->opts, ri);
@@ -371,12 +378,12 @@ lif_status multiply_common(lif_handle h, const lif_blocks* A, int32_t transA, co
   lif_status g = guarded(h, [&] {
     LIF_REQUIRE(std::isfinite(tau) && tau >= 0.0, LIF_ERR_INVALID, "tau must be finite and >= 0");
     LIF_REQUIRE(std::isfinite(alpha) && std::isfinite(gamma), LIF_ERR_INVALID, "alpha and gamma must be finite");
-    validate_blocks(A, false, "A");
-    validate_blocks(B, false, "B");
+    check_blocks(A, false, "A");
+    check_blocks(B, false, "B");
     LIF_REQUIRE(A->n == h->S.n && A->b == h->S.b && B->n == h->S.n && B->b == h->S.b, LIF_ERR_INVALID,
                 "A and B must have the n and b of the handle");
     if (D) {
-      validate_blocks(D, false, "D");
+      check_blocks(D, false, "D");
       LIF_REQUIRE(D->n == h->S.n && D->b == h->S.b, LIF_ERR_INVALID, "D must have the n and b of the handle");
     }
     LIF_REQUIRE((transA & ~(1 | LIF_PRODUCT_UPPER)) == 0 && (transB & ~1) == 0, LIF_ERR_INVALID,
@@ -422,7 +429,7 @@ lif_status lif_backward(lif_handle h, const lif_blocks* G, int64_t* nnzb, int32_
     LIF_REQUIRE(h->ck.valid, LIF_ERR_STATE,
                 "no checkpoints: run lif_refine (IRSI) or lif_localized with opts.checkpoint = 1 first");
     if (!h->has_dS || brow == nullptr) {
-      validate_blocks(G, false, "G");
+      check_blocks(G, false, "G");
       LIF_REQUIRE(G->n == h->S.n && G->b == h->S.b, LIF_ERR_INVALID, "G must have the n and b of S");
       Bsr g = bsr_from_blocks(h->ctx, *G);
       h->dS = run_backward(h->ctx, h->S, h->ck, g, h->opts);

@@ -51,6 +51,11 @@ struct Error : std::runtime_error {
 class Pool {
  public:
   explicit Pool(uint64_t cap) : cap_(cap) {}
+  // A pool over one fixed device region it does not own: every buffer is
+  // carved from [base, base + bytes), nothing is ever requested from or
+  // returned to HIP, and a request that does not fit fails with
+  // LIF_ERR_OUT_OF_MEMORY.
+  Pool(void* base, size_t bytes);
   ~Pool() { release_all(); }
   void* alloc(size_t bytes);
   void free(void* p);
@@ -81,7 +86,8 @@ class Pool {
   // Buffers of at least kLarge bytes and smaller ones live in separate
   // segments, so that small long-lived buffers never pin a large segment.
   static constexpr size_t kLarge = size_t(64) << 20;
-  static int size_class(size_t r) { return r >= kLarge ? 1 : 0; }
+  int size_class(size_t r) const { return (!fixed_ && r >= kLarge) ? 1 : 0; }
+  bool fixed_ = false;  // one region given at construction, not owned
   static size_t round(size_t bytes);
   bool grow(size_t need, int cls);
   void take(std::map<char*, Piece>::iterator it, size_t r);
@@ -243,6 +249,10 @@ struct Ctx {
   int b = 64;
   int64_t n = 0;
   int nb = 0;
+  // No host allocation through HIP (pinned staging, mapped read-back
+  // buffer): reads go to the caller's host memory with plain copies, and
+  // look-back words are cleared by a fill kernel (allocation-free entry point).
+  bool no_host_alloc = false;
   // pinned host staging for small device->host reads
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
@@ -595,6 +605,14 @@ Store new_store(Ctx& c, int64_t blocks, int b);
 Bsr compact_values(Ctx& c, Bsr&& A);
 Bsr bsr_empty(Ctx& c, int64_t n, int b);
 Bsr bsr_from_blocks(Ctx& c, const lif_blocks& in);
+// A read-only view of a device block list: row pointers and columns in
+// pool memory, block pointers into the caller's value array (no copy).
+Bsr bsr_view_blocks(Ctx& c, const lif_blocks& in);
+// Checks a block list: shape, sorted unique in-range coordinates, zero
+// padding beyond n; optionally a symmetric block pattern (api.cpp).
+void validate_blocks(const lif_blocks* B, bool need_symmetric, const char* what);
+// The message lif_last_error(NULL) returns on this thread (api.cpp).
+void set_thread_error(const std::string& msg);
 void bsr_to_blocks(Ctx& c, const Bsr& A, int32_t* brow, int32_t* bcol, double* vals, bool on_device);
 DBuf<double> block_norms(Ctx& c, const Bsr& A);
 Bsr truncate(Ctx& c, Bsr&& A, const double* norms, double tau);

@@ -120,6 +120,26 @@ Bsr bsr_from_blocks(Ctx& c, const lif_blocks& in) {
   return A;
 }
 
+Bsr bsr_view_blocks(Ctx& c, const lif_blocks& in) {
+  LIF_REQUIRE(in.on_device, LIF_ERR_INVALID, "bsr_view_blocks: the block list must be on the device");
+  Bsr A;
+  A.n = in.n;
+  A.b = in.b;
+  A.nb = (int)((in.n + in.b - 1) / in.b);
+  A.nnzb = in.nnzb;
+  A.cap = in.nnzb;
+  A.col = DBuf<int>(c.pool, (size_t)in.nnzb);
+  A.blk = DBuf<const double*>(c.pool, (size_t)in.nnzb);
+  if (in.nnzb) {
+    LIF_HIP(hipMemcpyAsync(A.col.get(), in.bcol, in.nnzb * sizeof(int), hipMemcpyDeviceToDevice, c.stream));
+    // the caller's blocks are only read: the block pointers address them in place
+    launch_fill_ptrs(c, A.blk.get(), in.vals, in.b, in.nnzb);
+  }
+  A.row_ptr = DBuf<int>(c.pool, A.nb + 1);
+  launch_row_ptr_from_rows(c, in.brow, in.nnzb, A.nb, A.row_ptr.get());
+  return A;
+}
+
 void bsr_to_blocks(Ctx& c, const Bsr& A, int32_t* brow, int32_t* bcol, double* vals, bool on_device) {
   no_holes(A, "bsr_to_blocks");
   const int64_t nnz = exact_nnzb(c, A);

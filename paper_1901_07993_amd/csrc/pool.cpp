@@ -7,10 +7,20 @@ size_t Pool::round(size_t bytes) {
   return (bytes + 255) & ~size_t(255);  // every buffer 256-byte aligned
 }
 
+Pool::Pool(void* base, size_t bytes) : cap_(bytes), fixed_(true) {
+  char* b = static_cast<char*>(base);
+  const size_t usable = bytes & ~size_t(255);
+  segs_[b] = {usable, 0};
+  pieces_[b] = Piece{usable, true, b};
+  free_[0].insert({usable, b});
+  reserved_ = reserved_cls_[0] = usable;
+}
+
 // A new segment for at least `need` bytes of class cls.  Small class: at
 // least 64 MiB and half of what that class holds (up to 1 GiB).  Large class:
 // at least 1 GiB, so that neighbouring large buffers can share one.
 bool Pool::grow(size_t need, int cls) {
+  if (fixed_) return false;
   constexpr size_t kGrain = size_t(2) << 20;
   size_t want = cls == 0 ? std::max(need, std::min(size_t(1) << 30,
                                                    std::max(size_t(64) << 20, (size_t)(reserved_cls_[0] / 2))))
@@ -135,6 +145,7 @@ void Pool::release_deferred() {
 }
 
 void Pool::trim() {
+  if (fixed_) return;
   // a free segment may still be read by queued kernels of the stream that
   // freed its last buffer; wait for the device before giving it back
   bool synced = false;
@@ -158,8 +169,10 @@ void Pool::trim() {
 }
 
 void Pool::release_all() {
-  (void)hipDeviceSynchronize();
-  for (auto& kv : segs_) (void)hipFree(kv.first);
+  if (!fixed_) {
+    (void)hipDeviceSynchronize();
+    for (auto& kv : segs_) (void)hipFree(kv.first);
+  }
   segs_.clear();
   pieces_.clear();
   free_[0].clear();
@@ -196,6 +209,11 @@ void Ctx::flush_timing() {
 void launch_gather_bytes(hipStream_t stream, const void* const* src, const unsigned* bytes, int count, void* dst);
 
 void Ctx::d2h(void* dst, const void* src, size_t bytes) {
+  if (no_host_alloc) {
+    LIF_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, stream));
+    LIF_HIP(hipStreamSynchronize(stream));
+    return;
+  }
   if (bytes <= 64) {
     d2h_batch({{dst, src, bytes}});
     return;
@@ -216,6 +234,11 @@ void Ctx::d2h(void* dst, const void* src, size_t bytes) {
 // buffer (the GPU writes host memory directly), then one synchronization.
 void Ctx::d2h_batch(const std::vector<Read>& reads) {
   const int n = (int)reads.size();
+  if (no_host_alloc) {
+    for (const Read& r : reads) LIF_HIP(hipMemcpyAsync(r.dst, r.src, r.bytes, hipMemcpyDeviceToHost, stream));
+    LIF_HIP(hipStreamSynchronize(stream));
+    return;
+  }
   LIF_REQUIRE(n <= 32, LIF_ERR_INVALID, "too many values in one read-back");
   if (!readback) {
     LIF_HIP(hipHostMalloc(&readback, 64 * 32 + 32 * (sizeof(void*) + sizeof(unsigned)), hipHostMallocMapped));
@@ -257,13 +280,19 @@ Ctx::Lookback& Ctx::lookback_for(int rows) {
   Lookback& lb = lookback[stream];
   if (!lb_fail.get()) {
     lb_fail = DBuf<int>(pool, 1);
-    LIF_HIP(hipMemsetAsync(lb_fail.get(), 0, sizeof(int), stream));
+    if (no_host_alloc)
+      launch_fill_i32(*this, lb_fail.get(), 0, 1);
+    else
+      LIF_HIP(hipMemsetAsync(lb_fail.get(), 0, sizeof(int), stream));
   }
   if (lb.rows < rows) {
     // zeroed once: no word reads as published
     const size_t words = 2 * ((size_t)rows + Lookback::groups(rows));
     lb.words = DBuf<unsigned long long>(pool, words);
-    LIF_HIP(hipMemsetAsync(lb.words.get(), 0, words * sizeof(unsigned long long), stream));
+    if (no_host_alloc)
+      launch_fill_i32(*this, reinterpret_cast<int*>(lb.words.get()), 0, (int64_t)(2 * words));
+    else
+      LIF_HIP(hipMemsetAsync(lb.words.get(), 0, words * sizeof(unsigned long long), stream));
     lb.rows = rows;
   }
   return lb;

@@ -29,7 +29,8 @@ _STATUS_NAMES = {1: "LIF_ERR_INVALID", 2: "LIF_ERR_NOT_PD", 3: "LIF_ERR_NO_CONVE
                  4: "LIF_ERR_OUT_OF_MEMORY", 5: "LIF_ERR_HIP", 6: "LIF_ERR_STATE"}
 
 EXPORTED = ("lif_opts_default", "lif_create", "lif_refine", "lif_localized", "lif_rinch", "lif_get_Z", "lif_residual",
-            "lif_multiply", "lif_multiply_add", "lif_backward", "lif_destroy", "lif_last_error")
+            "lif_multiply", "lif_multiply_add", "lif_multiply_noalloc", "lif_backward", "lif_destroy",
+            "lif_last_error")
 
 
 class LifError(RuntimeError):
@@ -90,6 +91,9 @@ def load() -> ctypes.CDLL:
     lib.lif_multiply_add.argtypes = [c_void_p, POINTER(Blocks), c_int32, POINTER(Blocks), c_int32, c_double,
                                      POINTER(Blocks), c_double, c_double, POINTER(c_int64), c_void_p, c_void_p,
                                      c_void_p, c_int32, POINTER(c_int64)]
+    lib.lif_multiply_noalloc.argtypes = [POINTER(Blocks), c_int32, POINTER(Blocks), c_int32, c_double,
+                                         POINTER(Blocks), c_double, c_double, c_int32, c_void_p, c_int64,
+                                         POINTER(c_int64), c_void_p, c_void_p, c_void_p, POINTER(c_int64)]
     lib.lif_backward.argtypes = [c_void_p, POINTER(Blocks), POINTER(c_int64), c_void_p, c_void_p, c_void_p, c_int32]
     lib.lif_destroy.argtypes = [c_void_p]
     lib.lif_destroy.restype = None
@@ -313,6 +317,40 @@ class Factorization:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def multiply_noalloc(A, transA: bool, B, transB: bool, tau: float = 0.0, prec: int = FP64, alpha: float = 1.0,
+                     D=None, gamma: float = 0.0, capacity: int | None = None, upper: bool = False):
+    """lif_multiply_noalloc on device block lists (torch CUDA tensors): the
+    product trunc_tau(alpha op(A) op(B) [+ gamma D]) with no allocation in
+    the library.  The output arrays are allocated here, by the caller, with
+    ``capacity`` blocks (default: every block of the n x n block grid).
+    Returns (DeviceBlocks, products); raises LifError (status
+    ERR_INVALID with the needed count when the capacity is short)."""
+    import torch
+    lib = load()
+    sa, ka = _marshal(A)
+    sb, kb = _marshal(B)
+    sd, kd = _marshal(D) if D is not None else (None, None)
+    nb = (int(A.n) + int(A.b) - 1) // int(A.b)
+    cap = nb * nb if capacity is None else int(capacity)
+    brow = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+    bcol = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+    vals = torch.empty((max(cap, 1), int(A.b), int(A.b)), dtype=torch.float64, device="cuda")
+    nnzb = c_int64(0)
+    prods = c_int64(0)
+    trans_a = int(transA) | (PRODUCT_UPPER if upper else 0)
+    rc = lib.lif_multiply_noalloc(byref(sa), trans_a, byref(sb), int(transB), float(alpha),
+                                  byref(sd) if sd is not None else None, float(gamma), float(tau), int(prec),
+                                  _current_stream(), cap, byref(nnzb), brow.data_ptr(), bcol.data_ptr(),
+                                  vals.data_ptr(), byref(prods))
+    del ka, kb, kd
+    if rc != OK:
+        err = LifError(rc, lib.lif_last_error(None).decode())
+        err.nnzb = nnzb.value
+        raise err
+    k = nnzb.value
+    return DeviceBlocks(int(A.n), int(A.b), brow[:k], bcol[:k], vals[:k]), prods.value
 
 
 def factorize(S, method: str = "lif", **opts):
