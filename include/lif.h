@@ -121,6 +121,12 @@ typedef struct {
                            * 0: panels of at most min(8 GiB, 1/16 of the device memory the
                            * handle may use) of dense block rows, the whole matrix when it
                            * fits), bounding its memory by Z, S Z and one panel */
+  int32_t update_panel_rows; /* localized refinement on large problems: the two products of the delta
+                           * update and their difference are formed this many block rows at a time
+                           * (>= 0; 0: automatic -- panels only on iterations whose buffers fill a
+                           * large part of the device memory, sized so that the two products of a
+                           * panel take at most 1/32 of it), so that neither product is ever
+                           * held whole; the result is the same bit for bit */
 } lif_opts;
 
 typedef struct {
@@ -154,7 +160,8 @@ typedef struct {
 /* Fills *o with the defaults: m = 4, tau = 0, FP64, paper stopping rule,
  * tol = 1e-10, max_iter = 100, base_rows = 4096, start = SQRT2_OVER_GERSH,
  * checkpoint = 0, no cap, null stream, timing = 0, presize = 1,
- * refinement = LIF_REFINE_LOCAL, prec_switch = 0, sym_delta = 0, residual_panel_rows = 0. */
+ * refinement = LIF_REFINE_LOCAL, prec_switch = 0, sym_delta = 0, residual_panel_rows = 0,
+ * update_panel_rows = 0. */
 lif_status lif_opts_default(lif_opts* o);
 
 /* Validates S and copies it into library-owned device memory (the caller may

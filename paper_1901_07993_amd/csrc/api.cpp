@@ -45,6 +45,7 @@ void validate_opts(const lif_opts& o) {
               "opts.prec_switch must be finite and >= 0");
   LIF_REQUIRE(o.sym_delta == 0 || o.sym_delta == 1, LIF_ERR_INVALID, "opts.sym_delta must be 0 or 1");
   LIF_REQUIRE(o.residual_panel_rows >= 0, LIF_ERR_INVALID, "opts.residual_panel_rows must be >= 0");
+  LIF_REQUIRE(o.update_panel_rows >= 0, LIF_ERR_INVALID, "opts.update_panel_rows must be >= 0");
   if (o.start == LIF_START_INV_SQRT_LMAX || o.start == LIF_START_GIVEN)
     LIF_REQUIRE(std::isfinite(o.start_value) && o.start_value > 0.0, LIF_ERR_INVALID,
                 "opts.start_value must be > 0 for this start");
@@ -226,6 +227,7 @@ lif_status lif_opts_default(lif_opts* o) {
   o->prec_switch = 0.0;
   o->sym_delta = 0;
   o->residual_panel_rows = 0;
+  o->update_panel_rows = 0;
   return LIF_OK;
 }
 
@@ -258,6 +260,7 @@ lif_status lif_create(const lif_blocks* S, const lif_opts* o, lif_handle* out) {
     p.prec_switch = o->prec_switch;
     p.sym_delta = o->sym_delta != 0;
     p.residual_panel_rows = o->residual_panel_rows;
+    p.update_panel_rows = o->update_panel_rows;
     Ctx& c = h->ctx;
     c.stream = static_cast<hipStream_t>(o->stream);
     c.pool = &h->pool;

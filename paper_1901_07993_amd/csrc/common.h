@@ -347,6 +347,10 @@ struct Ctx {
   ~Ctx();
 };
 
+// LIF_VERBOSE set in the environment: one line per refinement iteration and
+// per large product on stderr (sizes, memory), for following long runs.
+bool verbose();
+
 // Launches within the scope go to stream s.
 struct StreamScope {
   Ctx& c;

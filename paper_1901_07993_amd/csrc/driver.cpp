@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <limits>
 
 namespace lif {
@@ -169,6 +171,73 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
     }
     return axpby(c, 1.0, &U, 1.0, &L, 0.0, nullptr);
   };
+  // The update on large problems, formed by panels of block rows so that
+  // neither product is ever held whole: rows [p0, p1) of Z_{k+1}^T (S M) take
+  // Z_{k+1}'s block columns in [p0, p1), rows of (S M)^T Z_k the same columns
+  // of S M; each output block is the whole product's block (same block
+  // products in the same order), so the result is bit for bit that of the
+  // whole update.  The panels' row sets are disjoint: joining them moves
+  // pointers only, and like the assembly of submatrices it is not a task.
+  DBuf<int> d_pzero, d_plab, d_piota;
+  auto delta_update_panels = [&](const Bsr& SM, const Bsr& Zk, const Bsr& Zn, int rows) {
+    if (!d_pzero.get()) {
+      d_pzero = DBuf<int>(c.pool, nb);
+      d_plab = DBuf<int>(c.pool, nb);
+      launch_fill_i32(c, d_pzero.get(), 0, nb);
+      if (o.sym_delta) d_piota = DBuf<int>(c.pool, nb);
+    }
+    Bsr acc;
+    bool have = false;
+    int part_cpl = 0, part_prod = 0;
+    for (int p0 = 0; p0 < nb; p0 += rows) {
+      const int p1 = std::min(nb, p0 + rows);
+      // label 0 on the panel's block indices, -1 elsewhere
+      launch_fill_i32(c, d_plab.get(), -1, nb);
+      launch_fill_i32(c, d_plab.get() + p0, 0, p1 - p0);
+      Bsr X1, X2;
+      {
+        Bsr Zc = filter(c, Zn, d_pzero.get(), d_plab.get(), 0);
+        X1 = spgemm(c, Zc, true, SM, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, true, false, o.sym_delta);
+      }
+      {
+        Bsr Sc = filter(c, SM, d_pzero.get(), d_plab.get(), 0);
+        X2 = spgemm(c, Sc, true, Zk, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, true, false, o.sym_delta);
+      }
+      Bsr dP;
+      if (o.sym_delta) {
+        // the panel's rows of delta's upper block triangle
+        launch_fill_i32(c, d_piota.get(), -1, nb);
+        LIF_HIP(hipMemcpyAsync(d_piota.get() + p0, d_iota.get() + p0, (size_t)(p1 - p0) * sizeof(int),
+                               hipMemcpyDeviceToDevice, c.stream));
+        dP = filter(c, delta, d_piota.get(), d_iota.get(), 3);
+      } else {
+        dP = filter(c, delta, d_plab.get(), nullptr, 2);
+      }
+      Bsr part = axpby3(c, 1.0, &dP, -1.0, &X1, -1.0, &X2);
+      if (part.cpl > part_cpl || (part.cpl == part_cpl && part.cpl_products > part_prod)) {
+        part_cpl = part.cpl;
+        part_prod = part.cpl_products;
+      }
+      if (!have) {
+        acc = std::move(part);
+        have = true;
+      } else {
+        const int sc = c.stats.cpl, sp = c.stats.cpl_products;
+        acc = axpby(c, 1.0, &acc, 1.0, &part, 0.0, nullptr);
+        c.stats.cpl = sc;
+        c.stats.cpl_products = sp;
+      }
+    }
+    acc.cpl = part_cpl;
+    acc.cpl_products = part_prod;
+    if (!o.sym_delta) return acc;
+    Bsr L;
+    {
+      Bsr SU = filter(c, acc, d_iota1.get(), d_iota.get(), 3);
+      L = transpose(c, SU);
+    }
+    return axpby(c, 1.0, &acc, 1.0, &L, 0.0, nullptr);
+  };
   const bool up = o.sym_delta;
   if (!c.spec.sizes.get()) {
     c.spec.sizes = DBuf<int64_t>(c.pool, 2 * Ctx::Spec::kSlots);
@@ -265,7 +334,9 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       const double iter_bytes =
           std::max({caps_bytes, 6.0 * (double)Z.bound() * blk_bytes, 8.0 * (double)delta.bound() * blk_bytes});
       const double dev = (double)c.device_bytes();
-      const bool big = iter_bytes > 0.25 * dev || (double)c.pool->reserved() + iter_bytes > 0.5 * dev;
+      // (a panel size given in the options asks for this path too)
+      const bool big = o.update_panel_rows > 0 || iter_bytes > 0.25 * dev ||
+                       (double)c.pool->reserved() + iter_bytes > 0.5 * dev;
       c.spec.exact_large = big;
       big_iter = big;
       DeferFrees defer(c);
@@ -342,10 +413,26 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
         Bsr SM = spgemm(c, S, false, M, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles);
         Znew = axpby(c, 1.0, &Z, 1.0, &M, 0.0, nullptr);
         M = Bsr();
-        Bsr X2 = spgemm(c, SM, true, Z, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles, false, up);
-        Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles, false, up);
-        SM = Bsr();
-        dnew = delta_update(X1, X2);
+        // panels of the update: as asked, or when its two products (about
+        // delta's size each, half with a symmetric delta) would take more
+        // than 1/16 of the memory, panels whose products take about 1/32
+        int prow = o.update_panel_rows;
+        if (prow == 0 && !planned) {
+          const double upd = (o.sym_delta ? 1.0 : 2.0) * (double)delta.bound() * blk_bytes;
+          if (upd > dev / 16.0) {
+            const int np = (int)std::ceil(upd / (dev / 32.0));
+            prow = (nb + np - 1) / np;
+          }
+        }
+        if (prow > 0 && prow < nb) {
+          dnew = delta_update_panels(SM, Z, Znew, prow);
+          SM = Bsr();
+        } else {
+          Bsr X2 = spgemm(c, SM, true, Z, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles, false, up);
+          Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles, false, up);
+          SM = Bsr();
+          dnew = delta_update(X1, X2);
+        }
       } else {
       // S M and then (S M)^T Z_k run on the side stream while Z + M and then
       // Z_{k+1}^T (S M) run on the main one; buffers freed meanwhile are
@@ -427,6 +514,16 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
     if (ck) ck->push_back(std::move(Z));  // Z_k is immutable: keep it, no copy
     Z = std::move(Znew);
     delta = std::move(dnew);
+    if (verbose()) {
+      double mx = 0.0;
+      for (int s = 0; s < nn; ++s)
+        if (st[s].active) mx = std::max(mx, std::sqrt(ss[s]));
+      std::fprintf(stderr, "[lif] batch of %d problems, iteration %d: max ||delta||_F %.3e, Z %lld blocks, "
+                   "delta %lld blocks (bound), %s stream(s), memory in use %.2f GiB, peak %.2f GiB, held %.2f GiB\n",
+                   nn, k, mx, (long long)Z.nnzb, (long long)delta.bound(), big_iter ? "one" : "two",
+                   c.pool->in_use() / 1073741824.0, c.pool->peak() / 1073741824.0,
+                   c.pool->reserved() / 1073741824.0);
+    }
 
     for (int s = 0; s < nn; ++s) {
       NodeState& ns = st[s];

@@ -23,6 +23,7 @@ struct Opts {
   double prec_switch = 0.0;  // > 0: reduced precision only while ||delta||_F exceeds it
   bool sym_delta = false;    // update delta's upper block triangle and mirror it
   int residual_panel_rows = 0;  // block rows of I - Z^T S Z formed at once (0: automatic)
+  int update_panel_rows = 0;    // block rows of the delta update formed at once (0: automatic)
 };
 
 // One node of the split tree: scalar rows [lo, hi), lo a multiple of b.

@@ -6,6 +6,8 @@
 // their outputs by a bound and leave the exact count on the device.
 #include <algorithm>
 
+#include <cstdio>
+
 #include "common.h"
 
 namespace lif {
@@ -49,6 +51,11 @@ void task_after(Ctx& c, Bsr& out, bool product, std::initializer_list<const Bsr*
     c.stats.cpl = out.cpl;
     c.stats.cpl_products = out.cpl_products;
   }
+}
+
+bool exact_store_pays(Ctx& c, int64_t blocks, int b) {
+  const double bytes = (double)blocks * b * b * sizeof(double);
+  return bytes > std::min(double(1u << 30), (double)c.device_bytes() / 64.0);
 }
 
 Store new_store(Ctx& c, int64_t blocks, int b) {
@@ -232,6 +239,9 @@ CsrView transpose_view(Ctx& c, const Bsr& A) {
 
 Bsr transpose(Ctx& c, const Bsr& A) {
   no_holes(A, "transpose");
+  // a large matrix known only by a bound (a filter of a sum) gets its exact
+  // count first: the transposed values are stored for that many blocks
+  if (A.nnzb < 0 && exact_store_pays(c, A.bound(), A.b)) exact_nnzb(c, A);
   CsrView v = transpose_view(c, A);
   Bsr T = like(A);
   T.nnzb = A.nnzb;
@@ -466,6 +476,10 @@ Bsr spgemm_body(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau
     }
   }
   const double dev = (double)c.device_bytes(), pair_bytes = (double)P * sizeof(BlockPair);
+  if (verbose() && (double)nnzc * A.b * A.b * sizeof(double) + pair_bytes > double(1u << 30))
+    std::fprintf(stderr, "[lif]   product%s%s: %lld output blocks, %lld block products, in use %.2f GiB\n",
+                 ta ? " A^T" : " A", tb ? " B^T" : " B", (long long)nnzc, (long long)P,
+                 c.pool->in_use() / 1073741824.0);
   if (!planned && keep_holes && tau > 0.0 && nnzc > 0 && compact_output(c, nnzc, A.b) &&
       pair_bytes > std::min(kPairPanelBytes, dev / 512.0) &&
       (pair_bytes > dev / 64.0 || (double)c.pool->reserved() + pair_bytes > 0.5 * dev)) {
@@ -565,6 +579,9 @@ Bsr union_sum(Ctx& c, const Bsr* const src[3], const double coef[3], double gamm
   }
   cap = std::min<int64_t>(cap, (int64_t)nb * nb);
   computed = std::min<int64_t>(computed + unit_sum - unit_max, cap);
+  if (verbose() && (double)computed * C.b * C.b * sizeof(double) > double(1u << 30))
+    std::fprintf(stderr, "[lif]   sum: %lld blocks at most, %lld computed at most, in use %.2f GiB\n", (long long)cap,
+                 (long long)computed, c.pool->in_use() / 1073741824.0);
   C.nnzb = -1;
   C.cap = cap;
   C.row_ptr = DBuf<int>(c.pool, nb + 1);
@@ -572,20 +589,39 @@ Bsr union_sum(Ctx& c, const Bsr* const src[3], const double coef[3], double gamm
   C.col = DBuf<int>(c.pool, (size_t)cap);
   DBuf<int> ix(c.pool, (size_t)cap * 3), rowof(c.pool, (size_t)cap);
   DBuf<unsigned char> id(c.pool, (size_t)cap);
-  Store st = new_store(c, computed, C.b);
   C.blk = DBuf<const double*>(c.pool, (size_t)cap);
-  C.store.push_back(st);
   if (union_onepass_fits(nb)) {
     // pattern and the blocks taken unchanged in one launch, then values only
-    // for the blocks that need them
+    // for the blocks that need them.  The bound on those can be far above
+    // their number (operands with holes count their dropped blocks, and
+    // operands with disjoint patterns share every block): above a gigabyte
+    // the store waits for the count, one read-back.
+    const bool exact = exact_store_pays(c, computed, C.b);
+    Store st;
+    if (!exact) {
+      st = new_store(c, computed, C.b);
+      C.store.push_back(st);
+    }
     DBuf<int> list(c.pool, (size_t)std::max<int64_t>(computed, 1)), ncomp(c.pool, 1);
     launch_union3_onepass(c, rp, col, hole, val, coef, diag_on, C.row_ptr.get(), nb, C.col.get(), ix.get(), cap,
                           id.get(), rowof.get(), C.blk.get(), list.get(), ncomp.get());
+    if (exact) {
+      int nc = 0;
+      c.d2h_batch({{&nc, ncomp.get(), sizeof(int)}});
+      computed = nc;
+      if (computed) {
+        st = new_store(c, computed, C.b);
+        C.store.push_back(st);
+      }
+    }
     if (computed)
       launch_axpby3_values(c, val, coef, ix.get(), cap, gamma, id.get(), rowof.get(), computed, C.b, C.n, st->get(),
                            nullptr, C.blk.get(), ncomp.get(), list.get());
     return C;
-  } else {
+  }
+  Store st = new_store(c, computed, C.b);
+  C.store.push_back(st);
+  {
     {
       DBuf<int> cnt(c.pool, nb);
       launch_union3(c, rp, col, hole, diag_on, nb, cnt.get(), slot.get());
@@ -621,11 +657,11 @@ Bsr axpby3(Ctx& c, double alpha, const Bsr* A, double beta, const Bsr* B, double
 }
 
 Bsr filter(Ctx& c, const Bsr& A, const int* rlab, const int* clab, int mode) {
-  no_holes(A, "filter");
   const int nb = A.nb;
   Bsr C = like(A);
   C.nnzb = -1;
   C.cap = A.bound();
+  C.holes = A.holes;  // dropped blocks pass as null pointers, for products and sums
   C.row_ptr = DBuf<int>(c.pool, nb + 1);
   launch_filter_count_scan(c, A.row_ptr.get(), A.col.get(), rlab, clab ? clab : rlab, mode, nb, C.row_ptr.get());
   C.col = DBuf<int>(c.pool, (size_t)C.cap);

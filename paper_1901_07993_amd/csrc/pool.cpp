@@ -1,4 +1,6 @@
 // Device memory pool and execution context.
+#include <cstdlib>
+
 #include "common.h"
 
 namespace lif {
@@ -180,6 +182,11 @@ void Pool::release_all() {
   deferred_.clear();
   reserved_ = in_use_ = 0;
   reserved_cls_[0] = reserved_cls_[1] = 0;
+}
+
+bool verbose() {
+  static const bool on = std::getenv("LIF_VERBOSE") != nullptr;
+  return on;
 }
 
 hipEvent_t Ctx::take_event() {

@@ -49,7 +49,7 @@ class Opts(ctypes.Structure):
                 ("max_iter", c_int32), ("base_rows", c_int64), ("start", c_int32), ("start_value", c_double),
                 ("checkpoint", c_int32), ("mem_cap_bytes", c_uint64), ("stream", c_void_p), ("timing", c_int32),
                 ("presize", c_int32), ("refinement", c_int32), ("prec_switch", c_double),
-                ("sym_delta", c_int32), ("residual_panel_rows", c_int32)]
+                ("sym_delta", c_int32), ("residual_panel_rows", c_int32), ("update_panel_rows", c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -187,7 +187,7 @@ class Factorization:
 
     Keyword options mirror ``lif_opts``: m, tau, prec, stop, tol, max_iter,
     base_rows, start, start_value, checkpoint, mem_cap_bytes, timing, presize,
-    refinement, prec_switch, sym_delta, residual_panel_rows.
+    refinement, prec_switch, sym_delta, residual_panel_rows, update_panel_rows.
     """
 
     def __init__(self, S, **opts):

@@ -37,14 +37,14 @@ def test_exports_every_declared_symbol():
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lif.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lif_blocks),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lif_blocks),'
                    ' sizeof(lif_opts), sizeof(lif_info), offsetof(lif_opts, stream), offsetof(lif_info, norms),'
                    ' offsetof(lif_blocks, on_device), offsetof(lif_opts, presize),'
                    ' offsetof(lif_info, iterations_redone), offsetof(lif_opts, refinement),'
                    ' offsetof(lif_info, cpl_products), offsetof(lif_opts, prec_switch),'
                    ' offsetof(lif_info, iterations_reduced), offsetof(lif_info, mem_reserved_bytes),'
                    ' offsetof(lif_opts, sym_delta), offsetof(lif_opts, residual_panel_rows),'
-                   ' offsetof(lif_info, pair_panels)); return 0;}\n')
+                   ' offsetof(lif_info, pair_panels), offsetof(lif_opts, update_panel_rows)); return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
@@ -52,7 +52,8 @@ def test_struct_layout_matches_header(tmp_path):
             lif.Info.norms.offset, lif.Blocks.on_device.offset, lif.Opts.presize.offset,
             lif.Info.iterations_redone.offset, lif.Opts.refinement.offset, lif.Info.cpl_products.offset,
             lif.Opts.prec_switch.offset, lif.Info.iterations_reduced.offset, lif.Info.mem_reserved_bytes.offset,
-            lif.Opts.sym_delta.offset, lif.Opts.residual_panel_rows.offset, lif.Info.pair_panels.offset]
+            lif.Opts.sym_delta.offset, lif.Opts.residual_panel_rows.offset, lif.Info.pair_panels.offset,
+            lif.Opts.update_panel_rows.offset]
     assert got == want
 
 
@@ -60,7 +61,7 @@ def test_default_options():
     o = lif.default_opts()
     assert (o.m, o.tau, o.prec, o.stop, o.max_iter, o.base_rows) == (4, 0.0, 0, 0, 100, 4096)
     assert o.tol == 1e-10 and o.timing == 0 and o.presize == 1 and o.refinement == 0 and o.prec_switch == 0.0
-    assert o.sym_delta == 0 and o.residual_panel_rows == 0
+    assert o.sym_delta == 0 and o.residual_panel_rows == 0 and o.update_panel_rows == 0
 
 
 def _blocks(n, b, rows, cols, vals=None):
@@ -98,7 +99,7 @@ def test_nonzero_padding_rejected():
                                      ("max_iter", 0), ("base_rows", 16), ("start", 9),
                                      ("presize", 3), ("presize", -1), ("refinement", 2),
                                      ("refinement", -1), ("prec_switch", -1.0), ("prec_switch", float("nan")),
-                                     ("sym_delta", 2), ("residual_panel_rows", -1)])
+                                     ("sym_delta", 2), ("residual_panel_rows", -1), ("update_panel_rows", -1)])
 def test_invalid_options_rejected(opt, val):
     S = _blocks(64, 64, [0], [0], np.eye(64)[None])
     with pytest.raises(lif.LifError) as ei:
