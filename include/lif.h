@@ -155,6 +155,9 @@ typedef struct {
   uint64_t mem_reserved_bytes;/* device memory the handle holds from HIP at the end of the call */
   int32_t products_compacted;/* products written as kept blocks only (large products on one stream) */
   int32_t pair_panels;       /* panels of block rows whose pair lists were built one at a time */
+  double flops_leaf_gemm_reduced;   /* the part of flops_leaf_gemm with FP32 / BF16 inputs */
+  double seconds_leaf_gemm_reduced; /* the part of seconds_leaf_gemm in those launches (timing = 1) */
+  int64_t leaf_gemm_launches_reduced; /* the part of leaf_gemm_launches with FP32 / BF16 inputs */
 } lif_info;
 
 /* Fills *o with the defaults: m = 4, tau = 0, FP64, paper stopping rule,
@@ -216,6 +219,22 @@ lif_status lif_get_Z(lif_handle h, int64_t* nnzb, int32_t* brow, int32_t* bcol, 
  * error measure), against the truncated S the handle factorized; formed by
  * panels of block rows (opts.residual_panel_rows), never stored whole. */
 lif_status lif_residual(lif_handle h, double* out);
+
+/* ||I - Z^T S Z||_F of the handle's Z against another S of the same n and b
+ * (Table 1's error measure; for example the matrix before the block
+ * truncation the handle applied at creation, since the table does not say
+ * which S its residuals use), FP64, untruncated, by panels of block rows as
+ * lif_residual.  S may be host or device blocks (device blocks are read in
+ * place, not copied); its pattern need not be symmetric.  LIF_ERR_STATE
+ * before a factorization. */
+lif_status lif_residual_against(lif_handle h, const lif_blocks* S, double* out);
+
+/* Replaces the handle's options (S, its truncation and the memory pool
+ * stay): opts.tau and opts.mem_cap_bytes must equal the handle's, the rest
+ * is validated as in lif_create.  Lets one handle, its S and its warm memory
+ * pool serve runs in several precisions or stopping rules.  Drops the
+ * checkpoints and any kept derivative; the current Z stays. */
+lif_status lif_set_opts(lif_handle h, const lif_opts* o);
 
 /* C = op(A) op(B) truncated at tau: the block-sparse product of Sec. 4 with
  * the leaf truncation of Sec. 5, on the handle's stream and memory.  op is

@@ -145,6 +145,29 @@ lif_status guarded(lif_handle h, F&& f) {
   }
 }
 
+// The options of a handle from the caller's struct (the cap is the pool's).
+void copy_opts(lif_handle h, const lif_opts& o) {
+  Opts& p = h->opts;
+  p.m = o.m;
+  p.tau = o.tau;
+  p.prec = o.prec;
+  p.stop = o.stop;
+  p.tol = o.tol;
+  p.max_iter = o.max_iter;
+  p.base_rows = o.base_rows;
+  p.start = o.start;
+  p.start_value = o.start_value;
+  p.checkpoint = o.checkpoint != 0;
+  p.presize = o.presize;
+  p.refinement = o.refinement;
+  p.prec_switch = o.prec_switch;
+  p.sym_delta = o.sym_delta != 0;
+  p.residual_panel_rows = o.residual_panel_rows;
+  p.update_panel_rows = o.update_panel_rows;
+  h->ctx.stream = static_cast<hipStream_t>(o.stream);
+  h->ctx.timing = o.timing != 0;
+}
+
 void fill_info(lif_handle h, const RunInfo& ri, double seconds, lif_info* info) {
   if (!info) return;
   h->ctx.flush_timing();
@@ -171,6 +194,9 @@ void fill_info(lif_handle h, const RunInfo& ri, double seconds, lif_info* info) 
   info->n_norms = (int32_t)std::min<size_t>(64, ri.norms_top.size());
   for (int k = 0; k < info->n_norms; ++k) info->norms[k] = ri.norms_top[k];
   info->iterations_redone = h->ctx.stats.redone;
+  info->flops_leaf_gemm_reduced = h->ctx.stats.flops_lowp;
+  info->seconds_leaf_gemm_reduced = h->ctx.stats.gemm_ms_lowp * 1e-3;
+  info->leaf_gemm_launches_reduced = h->ctx.stats.gemm_launches_lowp;
 }
 
 void reset_stats(lif_handle h) {
@@ -244,33 +270,15 @@ lif_status lif_create(const lif_blocks* S, const lif_opts* o, lif_handle* out) {
     check_blocks(S, true, "S");
     LIF_REQUIRE(o->base_rows >= S->b, LIF_ERR_INVALID, "opts.base_rows must be >= b");
     h = new lif_handle_s(o->mem_cap_bytes);
-    Opts& p = h->opts;
-    p.m = o->m;
-    p.tau = o->tau;
-    p.prec = o->prec;
-    p.stop = o->stop;
-    p.tol = o->tol;
-    p.max_iter = o->max_iter;
-    p.base_rows = o->base_rows;
-    p.start = o->start;
-    p.start_value = o->start_value;
-    p.checkpoint = o->checkpoint != 0;
-    p.presize = o->presize;
-    p.refinement = o->refinement;
-    p.prec_switch = o->prec_switch;
-    p.sym_delta = o->sym_delta != 0;
-    p.residual_panel_rows = o->residual_panel_rows;
-    p.update_panel_rows = o->update_panel_rows;
+    copy_opts(h, *o);
     Ctx& c = h->ctx;
-    c.stream = static_cast<hipStream_t>(o->stream);
     c.pool = &h->pool;
-    c.timing = o->timing != 0;
     c.b = S->b;
     c.n = S->n;
     c.nb = (int)((S->n + S->b - 1) / S->b);
     Bsr S0 = bsr_from_blocks(c, *S);
     DBuf<double> nrm = block_norms(c, S0);
-    h->S = truncate(c, std::move(S0), nrm.get(), p.tau);
+    h->S = truncate(c, std::move(S0), nrm.get(), h->opts.tau);
     exact_nnzb(c, h->S);
   } catch (const Error& e) {
     g_create_error = e.what();
@@ -367,6 +375,46 @@ lif_status lif_residual(lif_handle h, double* out) {
     *out = residual(h->ctx, h->S, h->Z, h->opts.residual_panel_rows);
     h->ctx.flush_timing();
     h->ctx.stats = keep;
+  });
+}
+
+lif_status lif_residual_against(lif_handle h, const lif_blocks* S, double* out) {
+  if (!h) return LIF_ERR_INVALID;
+  return guarded(h, [&] {
+    LIF_REQUIRE(out != nullptr, LIF_ERR_INVALID, "out is null");
+    LIF_REQUIRE(h->has_Z, LIF_ERR_STATE, "no factor yet: call lif_refine or lif_localized first");
+    check_blocks(S, false, "S");
+    LIF_REQUIRE(S->n == h->S.n && S->b == h->S.b, LIF_ERR_INVALID, "S must have the n and b of the handle");
+    const Stats keep = h->ctx.stats;
+    double r = 0.0;
+    {
+      // device blocks are read in place; host blocks are copied once
+      Bsr Sx = S->on_device ? bsr_view_blocks(h->ctx, *S) : bsr_from_blocks(h->ctx, *S);
+      r = residual(h->ctx, Sx, h->Z, h->opts.residual_panel_rows);
+      h->ctx.sync();
+    }
+    *out = r;
+    h->ctx.flush_timing();
+    h->ctx.stats = keep;
+  });
+}
+
+lif_status lif_set_opts(lif_handle h, const lif_opts* o) {
+  if (!h) return LIF_ERR_INVALID;
+  return guarded(h, [&] {
+    LIF_REQUIRE(o != nullptr, LIF_ERR_INVALID, "null options");
+    validate_opts(*o);
+    LIF_REQUIRE(o->tau == h->opts.tau, LIF_ERR_INVALID,
+                "opts.tau cannot change: S was truncated with the handle's threshold");
+    LIF_REQUIRE(o->mem_cap_bytes == h->pool.cap(), LIF_ERR_INVALID, "opts.mem_cap_bytes cannot change");
+    LIF_REQUIRE(o->base_rows >= h->S.b, LIF_ERR_INVALID, "opts.base_rows must be >= b");
+    h->ctx.sync();
+    h->ctx.flush_timing();
+    copy_opts(h, *o);
+    // checkpoints and a kept derivative belong to the previous options' run
+    h->ck.clear();
+    h->dS = Bsr();
+    h->has_dS = false;
   });
 }
 

@@ -233,6 +233,8 @@ struct Stats {
   int64_t products = 0;
   int64_t gemm_launches = 0;
   double gemm_ms = 0;
+  double gemm_ms_lowp = 0;        // part of gemm_ms spent in FP32/BF16-input launches
+  int64_t gemm_launches_lowp = 0;
   int redone = 0;  // presized iterations redone with exact sizes
   int cpl = 0;           // longest chain of dependent tasks so far (Bsr::cpl)
   int cpl_products = 0;  // products on it
@@ -314,6 +316,7 @@ struct Ctx {
   DBuf<int> lb_fail;
   // events around leaf-GEMM launches (timing mode), resolved at flush_timing()
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+  std::vector<char> ev_lowp;  // per pending pair: a reduced-precision launch
   std::vector<hipEvent_t> ev_free;
 
   hipEvent_t take_event();

@@ -203,14 +203,17 @@ hipEvent_t Ctx::take_event() {
 void Ctx::flush_timing() {
   if (ev_pending.empty()) return;
   LIF_HIP(hipStreamSynchronize(stream));
-  for (auto& pr : ev_pending) {
+  for (size_t i = 0; i < ev_pending.size(); ++i) {
+    auto& pr = ev_pending[i];
     float ms = 0.f;
     LIF_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
     stats.gemm_ms += ms;
+    if (i < ev_lowp.size() && ev_lowp[i]) stats.gemm_ms_lowp += ms;
     ev_free.push_back(pr.first);
     ev_free.push_back(pr.second);
   }
   ev_pending.clear();
+  ev_lowp.clear();
 }
 
 void launch_gather_bytes(hipStream_t stream, const void* const* src, const unsigned* bytes, int count, void* dst);

@@ -30,7 +30,7 @@ _STATUS_NAMES = {1: "LIF_ERR_INVALID", 2: "LIF_ERR_NOT_PD", 3: "LIF_ERR_NO_CONVE
 
 EXPORTED = ("lif_opts_default", "lif_create", "lif_refine", "lif_localized", "lif_rinch", "lif_get_Z", "lif_residual",
             "lif_multiply", "lif_multiply_add", "lif_multiply_noalloc", "lif_backward", "lif_destroy",
-            "lif_last_error")
+            "lif_last_error", "lif_residual_against", "lif_set_opts")
 
 
 class LifError(RuntimeError):
@@ -60,7 +60,8 @@ class Info(ctypes.Structure):
                 ("n_norms", c_int32), ("norms", c_double * 64), ("iterations_redone", c_int32),
                 ("cpl_tasks", c_int32), ("cpl_products", c_int32), ("iterations_reduced", c_int32),
                 ("mem_peak_bytes", c_uint64), ("mem_reserved_bytes", c_uint64), ("products_compacted", c_int32),
-                ("pair_panels", c_int32)]
+                ("pair_panels", c_int32), ("flops_leaf_gemm_reduced", c_double),
+                ("seconds_leaf_gemm_reduced", c_double), ("leaf_gemm_launches_reduced", c_int64)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "norms"}
@@ -86,6 +87,8 @@ def load() -> ctypes.CDLL:
     lib.lif_rinch.argtypes = [c_void_p, POINTER(Info)]
     lib.lif_get_Z.argtypes = [c_void_p, POINTER(c_int64), c_void_p, c_void_p, c_void_p, c_int32]
     lib.lif_residual.argtypes = [c_void_p, POINTER(c_double)]
+    lib.lif_residual_against.argtypes = [c_void_p, POINTER(Blocks), POINTER(c_double)]
+    lib.lif_set_opts.argtypes = [c_void_p, POINTER(Opts)]
     lib.lif_multiply.argtypes = [c_void_p, POINTER(Blocks), c_int32, POINTER(Blocks), c_int32, c_double,
                                  POINTER(c_int64), c_void_p, c_void_p, c_void_p, c_int32, POINTER(c_int64)]
     lib.lif_multiply_add.argtypes = [c_void_p, POINTER(Blocks), c_int32, POINTER(Blocks), c_int32, c_double,
@@ -258,6 +261,25 @@ class Factorization:
         out = c_double(0.0)
         self._check(load().lif_residual(self._h, byref(out)))
         return out.value
+
+    def residual_against(self, S) -> float:
+        """||I - Z^T S Z||_F of the handle's Z against another S (for example
+        the matrix before the block truncation applied at creation)."""
+        out = c_double(0.0)
+        st, keep = _marshal(S)
+        self._check(load().lif_residual_against(self._h, byref(st), byref(out)))
+        del keep
+        return out.value
+
+    def set_opts(self, **opts):
+        """Changes options of the handle (not tau or mem_cap_bytes): the same
+        S and warm memory pool serve the next factorization."""
+        o = Opts()
+        ctypes.memmove(byref(o), byref(self._opts), ctypes.sizeof(Opts))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        self._check(load().lif_set_opts(self._h, byref(o)))
+        self._opts = o
 
     def multiply(self, A, transA: bool, B, transB: bool, tau: float = 0.0, upper: bool = False,
                  alpha: float = 1.0, D=None, gamma: float = 0.0):
