@@ -11,7 +11,11 @@ Plain, slow, dense numpy implementations of what the GPU path computes:
 * ``adjoint``: the reverse sweep of refinement and LIF for L = tr(G^T Z) and
   dense references for it;
 * ``blocks``: single output blocks of a block-sparse product, for sampled
-  checks at sizes the dense oracle cannot hold.
+  checks at sizes the dense oracle cannot hold;
+* ``blocked``: the same IRSI, LIF and RINCH steps on block lists, for sizes
+  the dense oracle cannot hold; its products run in ``bsmm.c`` (plain C
+  with OpenMP over output rows, built by ``build.py`` into ``libbsmm.so``)
+  when that is built, else in a Python loop, the two pinned to each other.
 
 Only tests, the smoke check and the benchmark's CPU-baseline leg may import
 this package.  It shares no code with the HIP library and never calls it.

@@ -15,12 +15,17 @@ sizes both can run).
 """
 from __future__ import annotations
 
+import ctypes
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
 
 from . import refinement as R
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbsmm.so")
+_lib = None
 
 
 @dataclass
@@ -82,8 +87,68 @@ def transpose(A: BM) -> BM:
     return BM(A.n, A.b, {(j, i): v.T.copy() for (i, j), v in A.blocks.items()})
 
 
+def _clib():
+    """The oracle's C block product (``bsmm.c``, built by ``oracle/build.py``),
+    or None when it is not built."""
+    global _lib
+    if _lib is None and os.path.exists(_LIB_PATH):
+        lib = ctypes.CDLL(_LIB_PATH)
+        p = ctypes.c_void_p
+        lib.bsmm_pattern.argtypes = [ctypes.c_int64, p, p, p, p, p]
+        lib.bsmm_values.argtypes = [ctypes.c_int64, ctypes.c_int32, p, p, p, p, p, p, p, p, p, p]
+        _lib = lib
+    return _lib
+
+
+def _csr(A: BM):
+    """(row pointers int64, columns int32, values (nnzb, b, b)) in (row, col) order."""
+    keys = sorted(A.blocks)
+    nb = A.nb
+    rows = np.fromiter((k[0] for k in keys), np.int64, len(keys))
+    cols = np.fromiter((k[1] for k in keys), np.int32, len(keys))
+    rp = np.zeros(nb + 1, np.int64)
+    np.cumsum(np.bincount(rows, minlength=nb), out=rp[1:])
+    vals = np.empty((len(keys), A.b, A.b))
+    for e, k in enumerate(keys):
+        vals[e] = A.blocks[k]
+    return rp, cols, vals
+
+
 def mult(A: BM, B: BM, tau: float) -> BM:
-    """trunc_tau(A B): output block (i, j) = sum over k ascending of A_ik B_kj."""
+    """trunc_tau(A B): output block (i, j) = sum over k ascending of A_ik B_kj.
+    Runs the oracle's C product when it is built (rows of the output on
+    several threads), else the loop of ``mult_py``; the two are pinned to
+    each other and to dense products by tests."""
+    lib = _clib()
+    if lib is None:
+        return mult_py(A, B, tau)
+    nb, b = A.nb, A.b
+    arp, acol, avals = _csr(A)
+    brp, bcol, bvals = _csr(B)
+    cnt = np.zeros(nb, np.int64)
+    ptr = lambda x: x.ctypes.data  # noqa: E731
+    if lib.bsmm_pattern(nb, ptr(arp), ptr(acol), ptr(brp), ptr(bcol), ptr(cnt)) != 0:
+        raise MemoryError("bsmm_pattern")
+    crp = np.zeros(nb + 1, np.int64)
+    np.cumsum(cnt, out=crp[1:])
+    nc = int(crp[-1])
+    ccol = np.empty(nc, np.int32)
+    cvals = np.empty((nc, b, b))
+    cnorm = np.empty(nc)
+    if lib.bsmm_values(nb, b, ptr(arp), ptr(acol), ptr(avals), ptr(brp), ptr(bcol), ptr(bvals), ptr(crp),
+                       ptr(ccol), ptr(cvals), ptr(cnorm)) != 0:
+        raise MemoryError("bsmm_values")
+    keep = np.ones(nc, bool) if tau <= 0.0 else cnorm >= tau
+    crow = np.repeat(np.arange(nb), np.diff(crp))
+    out = {}
+    for e in np.nonzero(keep)[0].tolist():
+        out[(int(crow[e]), int(ccol[e]))] = cvals[e]
+    return BM(A.n, A.b, out)
+
+
+def mult_py(A: BM, B: BM, tau: float) -> BM:
+    """trunc_tau(A B): output block (i, j) = sum over k ascending of A_ik B_kj
+    (plain Python loop over block products)."""
     brows = B.rows()
     out = {}
     for i, ks in sorted(A.rows().items()):

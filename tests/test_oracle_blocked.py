@@ -63,3 +63,61 @@ def test_blocked_lif_chain_matches_dense():
     assert np.array_equal(OB.to_dense(OB.transpose(Zb)), OB.to_dense(Zb).T)
     I = OB.identity(S.n, 64, 2.0)
     assert np.array_equal(OB.to_dense(I), 2.0 * np.eye(S.n))
+
+
+# ----------------------------------------------------------------------------
+# the oracle's C block product (oracle/bsmm.c) against the Python loop and
+# dense numpy products
+# ----------------------------------------------------------------------------
+
+def _random_bm(n, b, density, seed, spread=3.0):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nb = (n + b - 1) // b
+    A = OB.BM(n, b)
+    for i in range(nb):
+        for j in range(nb):
+            if rng.random() < density:
+                v = rng.standard_normal((b, b)) * 10.0 ** (-spread * rng.random())
+                v[max(0, n - i * b):, :] = 0.0
+                v[:, max(0, n - j * b):] = 0.0
+                A.blocks[(i, j)] = v
+    return A
+
+
+def _check_c_product(mult):
+    for n, b, seed in ((7 * 8 + 5, 8, 1), (5 * 32 + 11, 32, 2)):
+        A = _random_bm(n, b, 0.45, 10 + seed)
+        B = _random_bm(n, b, 0.4, 20 + seed)
+        full = OB.to_dense(A) @ OB.to_dense(B)
+        nrm = R.block_norms(full, b)
+        srt = np.sort(nrm[nrm > 0])
+        tau = float(np.sqrt(srt[len(srt) // 2 - 1] * srt[len(srt) // 2]))   # no norm near tau
+        for t in (0.0, tau):
+            C = mult(A, B, t)
+            P = OB.mult_py(A, B, t)
+            if set(C.blocks) != set(P.blocks):
+                return False
+            ref = R.truncate(full, b, t)
+            if np.max(np.abs(OB.to_dense(C) - ref)) > 1e-13 * np.max(np.abs(ref)):
+                return False
+            if max(np.max(np.abs(C.blocks[k] - P.blocks[k])) for k in C.blocks) > 1e-13 * np.max(np.abs(ref)):
+                return False
+    return True
+
+
+def test_c_block_product_matches_python_loop_and_dense():
+    if OB._clib() is None:
+        pytest.skip("oracle/libbsmm.so not built (oracle/build.py)")
+    assert _check_c_product(OB.mult)
+
+
+def test_planted_c_product_layout_mistake_is_caught(monkeypatch):
+    if OB._clib() is None:
+        pytest.skip("oracle/libbsmm.so not built (oracle/build.py)")
+    good = OB._csr
+
+    def transposed_blocks(A):
+        rp, cols, vals = good(A)
+        return rp, cols, np.ascontiguousarray(vals.transpose(0, 2, 1))
+    monkeypatch.setattr(OB, "_csr", transposed_blocks)
+    assert not _check_c_product(OB.mult)
