@@ -145,7 +145,7 @@ WATER_VARIANTS = {
 PEAK_TFLOPS = {"FP64": 78.6, "MIXED_FP32": 157.3, "MIXED_BF16": 2500.0}
 
 
-def water_comparison(lif, count, which=("fp64_sym", "bf16_schedule_sym"), z_diff=True):
+def water_comparison(lif, count, which=("fp64_sym", "bf16_schedule_sym"), z_diff=True, residuals=True):
     """FP64 against the scheduled reduced-precision corrections on a water
     cluster (tau = 1e-8, b = 64, LIF to 4096-row leaves, paper stop): the
     metric's comparison, on the compute-bound products where reduced
@@ -183,8 +183,8 @@ def water_comparison(lif, count, which=("fp64_sym", "bf16_schedule_sym"), z_diff
         info = f.localized()
         torch.cuda.synchronize()
         s = time.perf_counter() - t0
-        res = f.residual()
-        res_u = f.residual_against(Sd)
+        res = f.residual() if residuals else None
+        res_u = f.residual_against(Sd) if residuals else None
         r = {"s_per_factorization": s, "residual": res, "residual_untruncated_S": res_u,
              "iterations_total": info["iterations_total"], "iterations_reduced": info["iterations_reduced"],
              "iterations_redone": info["iterations_redone"], "nnzb_Z": info["nnzb_Z"],
@@ -192,6 +192,8 @@ def water_comparison(lif, count, which=("fp64_sym", "bf16_schedule_sym"), z_diff
              "products_compacted": info["products_compacted"], "pair_panels": info["pair_panels"]}
         fl, sec = info["flops_leaf_gemm"], info["seconds_leaf_gemm"]
         flr, secr = info["flops_leaf_gemm_reduced"], info["seconds_leaf_gemm_reduced"]
+        r["leaf_gemm_seconds"] = sec
+        r["leaf_gemm_reduced_seconds"] = secr
         if sec - secr > 0:
             r["leaf_gemm_fp64_tflops"] = (fl - flr) / (sec - secr) / 1e12
             r["leaf_gemm_fp64_frac_of_peak"] = r["leaf_gemm_fp64_tflops"] / PEAK_TFLOPS["FP64"]
@@ -211,7 +213,7 @@ def water_comparison(lif, count, which=("fp64_sym", "bf16_schedule_sym"), z_diff
             if z_diff and Zref is not None:
                 r["rel_diff_vs_fp64_Z"] = rel_diff(f.get_Z(), Zref)
         out[name] = r
-        print(f"# water-{count} {name}: {s:.2f} s, residual {res:.3e} (untruncated S {res_u:.3e})",
+        print(f"# water-{count} {name}: {s:.2f} s, residual {res} (untruncated S {res_u})",
               file=sys.stderr, flush=True)
     f.close()
     del Zref
@@ -296,7 +298,8 @@ def main():
         from paper_1901_07993_amd import lif as lifmod
         lifmod.load()
         assert torch.cuda.is_available(), "bench.py needs a GPU"
-        print(json.dumps({"water": water_comparison(lifmod, args.water_count, tuple(args.water_only.split(",")))}),
+        print(json.dumps({"water": water_comparison(lifmod, args.water_count, tuple(args.water_only.split(",")),
+                                                    z_diff=not args.no_residual, residuals=not args.no_residual)}),
               flush=True)
         return
     if args.cpl_sweep:
