@@ -86,11 +86,13 @@ def traffic(fetch: str, write: str, out: str, kernel: str, copy_mib: float, cmd:
         f.write("\n")
 
 
-def mfma(counters: str, trace: str, out: str, kernel: str, peak_tflops: float, cmd: str) -> None:
+def mfma(counters: str, trace: str, out: str, kernel: str, peak_tflops: float, cmd: str,
+         flops_counter: str = "MfmaFlopsF64") -> None:
     """MFMA busy fraction and MFMA flop rate of one kernel from a counter run
     that also traced the kernels (durations by dispatch id): the derived
     counters MfmaUtil (MFMA busy cycles over active cycles and SIMDs, in %)
-    and MfmaFlopsF64 (512 flops per MFMA op), weighted by dispatch time."""
+    and MfmaFlopsF64 / MfmaFlopsF32 / MfmaFlopsBF16 (512 flops per MFMA op
+    of that type), weighted by dispatch time."""
     dur = {}
     for r in csv.DictReader(open(trace)):
         if _short(r["Kernel_Name"]).startswith(kernel):
@@ -102,16 +104,17 @@ def mfma(counters: str, trace: str, out: str, kernel: str, peak_tflops: float, c
         d = int(r["Dispatch_Id"])
         if r["Counter_Name"] == "MfmaUtil":
             util[d] = util.get(d, 0.0) + float(r["Counter_Value"])
-        elif r["Counter_Name"] == "MfmaFlopsF64":
+        elif r["Counter_Name"] == flops_counter:
             flops[d] = flops.get(d, 0.0) + float(r["Counter_Value"])
     ids = sorted(set(util) & set(flops) & set(dur))
     t = sum(dur[i] for i in ids)
     res = {"kernel": kernel, "command": cmd, "dispatches": len(ids), "kernel_seconds": t / 1e9,
+           "flops_counter": flops_counter,
            "mfma_util_pct_time_weighted": sum(util[i] * dur[i] for i in ids) / t if t else None,
-           "mfma_f64_flops": sum(flops[i] for i in ids),
-           "mfma_f64_tflops": sum(flops[i] for i in ids) / (t / 1e9) / 1e12 if t else None,
+           "mfma_flops": sum(flops[i] for i in ids),
+           "mfma_tflops": sum(flops[i] for i in ids) / (t / 1e9) / 1e12 if t else None,
            "peak_tflops": peak_tflops}
-    res["frac_of_peak"] = res["mfma_f64_tflops"] / peak_tflops if res["mfma_f64_tflops"] else None
+    res["frac_of_peak"] = res["mfma_tflops"] / peak_tflops if res["mfma_tflops"] else None
     with open(out, "w") as f:
         json.dump(res, f, indent=1)
         f.write("\n")
@@ -194,6 +197,7 @@ def main() -> None:
     m.add_argument("--kernel", required=True)
     m.add_argument("--peak-tflops", type=float, required=True)
     m.add_argument("--cmd", required=True)
+    m.add_argument("--flops-counter", default="MfmaFlopsF64")
     a = ap.parse_args()
     if a.what == "stats":
         stats(a.trace, a.out, a.title, a.cmd)
@@ -202,7 +206,7 @@ def main() -> None:
     elif a.what == "hbm":
         hbm(a.trace, a.fetch, a.write, a.out, a.copy_mib, a.peak_gbps, a.title, a.cmd)
     else:
-        mfma(a.counters, a.trace, a.out, a.kernel, a.peak_tflops, a.cmd)
+        mfma(a.counters, a.trace, a.out, a.kernel, a.peak_tflops, a.cmd, a.flops_counter)
 
 
 if __name__ == "__main__":
