@@ -328,12 +328,20 @@ def main():
         res = None if args.no_residual else f.residual()
         res_u = None if args.no_residual else f.residual_against(Sd)
         Z = None if args.no_residual else f.get_Z()
+        run.detail = None
+        if prec == lif.FP64:
+            # after the timed steps: three more with every leaf factorization
+            # and symbolic phase timed as well (more events per step, so not
+            # part of the headline), for their rooflines
+            f.set_opts(timing=2)
+            run.detail = [f.localized() for _ in range(3)]
         f.close()
         run.res_u = res_u
         return (t1 - t0) / args.steps, infos, res, Z
 
     step_s, infos, res, Z64 = run(lif.FP64, lif.STOP_PAPER, 1e-10)
     res_u64 = run.res_u
+    detail64 = run.detail
     ms = step_s * 1e3
     flops = sum(i["flops_leaf_gemm"] for i in infos)
     gemm_s = sum(i["seconds_leaf_gemm"] for i in infos)
@@ -394,6 +402,23 @@ def main():
                               "cpl_tasks": inf_v["cpl_tasks"], "cpl_products": inf_v["cpl_products"],
                               "iterations_top": inf_v["iterations_top"],
                               "iterations_total": inf_v["iterations_total"], "nnzb_Z": inf_v["nnzb_Z"]}
+    rooflines = []
+    if detail64:
+        d = detail64
+        lf, ls = sum(i["flops_leaf_factorization"] for i in d), sum(i["seconds_leaf_factorization"] for i in d)
+        sb, ss = sum(i["bytes_symbolic"] for i in d), sum(i["seconds_symbolic"] for i in d)
+        nl = sum(i["symbolic_launches"] for i in d)
+        if ls > 0:
+            rooflines.append({"kernel": "k_potrf + k_step + k_trinv (batched leaf inverse Cholesky, one interval per "
+                                        "factorization: the serial steps with the inverse's columns beside them)",
+                              "bound": "mfma", "achieved": lf / ls / 1e12, "peak": PEAK_FP64_MFMA_TFLOPS,
+                              "unit": "TFLOP/s", "frac": lf / ls / 1e12 / PEAK_FP64_MFMA_TFLOPS,
+                              "flops_per_factorization": lf / len(d), "seconds_per_factorization": ls / len(d)})
+        if ss > 0:
+            rooflines.append({"kernel": "k_symbolic_* + k_scan_pair* (symbolic phases of every product)",
+                              "bound": "hbm", "achieved": sb / ss / 1e9, "peak": PEAK_HBM_BPS / 1e9, "unit": "GB/s",
+                              "frac": sb / ss / PEAK_HBM_BPS, "bytes_per_factorization": sb / len(d),
+                              "seconds_per_factorization": ss / len(d), "launches_per_factorization": nl / len(d)})
     water = None
     if not args.no_water:
         water = water_comparison(lif, args.water_count)
@@ -430,6 +455,7 @@ def main():
         "rinch": rinch,
         "variants": variants,
         "water": water,
+        "rooflines_other_kernels": rooflines,
         "roofline": {"bound": "mfma", "kernel": "k_numeric_f64 (leaf GEMM, v_mfma_f64_16x16x4f64)",
                      "achieved": achieved, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_MFMA_TFLOPS,

@@ -99,7 +99,8 @@ typedef struct {
                            * iterations on one stream with buffers freed early, products
                            * written as kept blocks only, the residual's panels */
   void* stream;           /* hipStream_t for all work (NULL = null stream) */
-  int32_t timing;         /* 1: time every leaf-GEMM launch with HIP events */
+  int32_t timing;         /* 1: time every leaf-GEMM launch with HIP events; 2: also the leaf
+                           * factorizations and the symbolic phases (lif_info) */
   int32_t presize;        /* 1: from the second iteration of a refinement on, size each
                            * product from the previous iteration's counts (with a
                            * margin) instead of reading its counts back; an iteration
@@ -158,6 +159,16 @@ typedef struct {
   double flops_leaf_gemm_reduced;   /* the part of flops_leaf_gemm with FP32 / BF16 inputs */
   double seconds_leaf_gemm_reduced; /* the part of seconds_leaf_gemm in those launches (timing = 1) */
   int64_t leaf_gemm_launches_reduced; /* the part of leaf_gemm_launches with FP32 / BF16 inputs */
+  double seconds_leaf_factorization;  /* timing = 2: the batched leaf factorizations (all steps and the
+                                       * inverse's columns on the second stream), summed over the call */
+  double flops_leaf_factorization;    /* their algorithmic flops: the band-limited Cholesky (diagonal
+                                       * tiles, panels, trailing updates), the panel products V and the
+                                       * inverse's tile products, b^3 or 2 b^3 each as counted */
+  double seconds_symbolic;            /* timing = 2: the symbolic phases (counts, scans, fills) */
+  double bytes_symbolic;              /* their algorithmic bytes: 20 per block product (a column index
+                                       * read, a 16-byte pair written), 12 per output block, the row
+                                       * pointers */
+  int64_t symbolic_launches;          /* timed symbolic launches */
 } lif_info;
 
 /* Fills *o with the defaults: m = 4, tau = 0, FP64, paper stopping rule,

@@ -46,6 +46,7 @@ void validate_opts(const lif_opts& o) {
   LIF_REQUIRE(o.sym_delta == 0 || o.sym_delta == 1, LIF_ERR_INVALID, "opts.sym_delta must be 0 or 1");
   LIF_REQUIRE(o.residual_panel_rows >= 0, LIF_ERR_INVALID, "opts.residual_panel_rows must be >= 0");
   LIF_REQUIRE(o.update_panel_rows >= 0, LIF_ERR_INVALID, "opts.update_panel_rows must be >= 0");
+  LIF_REQUIRE(o.timing >= 0 && o.timing <= 2, LIF_ERR_INVALID, "opts.timing must be 0, 1 or 2");
   if (o.start == LIF_START_INV_SQRT_LMAX || o.start == LIF_START_GIVEN)
     LIF_REQUIRE(std::isfinite(o.start_value) && o.start_value > 0.0, LIF_ERR_INVALID,
                 "opts.start_value must be > 0 for this start");
@@ -166,6 +167,7 @@ void copy_opts(lif_handle h, const lif_opts& o) {
   p.update_panel_rows = o.update_panel_rows;
   h->ctx.stream = static_cast<hipStream_t>(o.stream);
   h->ctx.timing = o.timing != 0;
+  h->ctx.timing_level = o.timing;
 }
 
 void fill_info(lif_handle h, const RunInfo& ri, double seconds, lif_info* info) {
@@ -197,6 +199,11 @@ void fill_info(lif_handle h, const RunInfo& ri, double seconds, lif_info* info) 
   info->flops_leaf_gemm_reduced = h->ctx.stats.flops_lowp;
   info->seconds_leaf_gemm_reduced = h->ctx.stats.gemm_ms_lowp * 1e-3;
   info->leaf_gemm_launches_reduced = h->ctx.stats.gemm_launches_lowp;
+  info->seconds_leaf_factorization = h->ctx.stats.leaf_ms * 1e-3;
+  info->flops_leaf_factorization = h->ctx.stats.leaf_flops;
+  info->seconds_symbolic = h->ctx.stats.sym_ms * 1e-3;
+  info->bytes_symbolic = h->ctx.stats.sym_bytes;
+  info->symbolic_launches = h->ctx.stats.sym_launches;
 }
 
 void reset_stats(lif_handle h) {

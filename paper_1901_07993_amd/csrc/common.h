@@ -235,6 +235,14 @@ struct Stats {
   double gemm_ms = 0;
   double gemm_ms_lowp = 0;        // part of gemm_ms spent in FP32/BF16-input launches
   int64_t gemm_launches_lowp = 0;
+  // timing level 2: the leaf factorizations and the symbolic phases, with the
+  // algorithmic work of each -- the band-limited factorization's and the
+  // dense inverse's flops; the symbolic phase's bytes (each block product
+  // reads one column index of B and writes a 16-byte pair, each output block
+  // a column index and a segment start; the row pointers)
+  double leaf_ms = 0, leaf_flops = 0;
+  double sym_ms = 0, sym_bytes = 0;
+  int64_t leaf_launches = 0, sym_launches = 0;
   int redone = 0;  // presized iterations redone with exact sizes
   int cpl = 0;           // longest chain of dependent tasks so far (Bsr::cpl)
   int cpl_products = 0;  // products on it
@@ -317,6 +325,16 @@ struct Ctx {
   // events around leaf-GEMM launches (timing mode), resolved at flush_timing()
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
   std::vector<char> ev_lowp;  // per pending pair: a reduced-precision launch
+  // per pending pair: what it timed (Timed::Gemm, Leaf or Symbolic)
+  std::vector<char> ev_cat;
+  enum Timed { Gemm = 0, Leaf = 1, Symbolic = 2 };
+  // 1: every leaf-GEMM launch is timed; 2: also the leaf factorizations and
+  // the symbolic phases (more events per step; for per-kernel rooflines)
+  int timing_level = 0;
+  // an event recorded on the current stream when timing is at least `level`
+  hipEvent_t timed_begin(int level);
+  // closes the interval opened by timed_begin (a null begin: nothing)
+  void timed_end(hipEvent_t e0, Timed what);
   std::vector<hipEvent_t> ev_free;
 
   hipEvent_t take_event();
@@ -353,6 +371,11 @@ struct Ctx {
 // LIF_VERBOSE set in the environment: one line per refinement iteration and
 // per large product on stderr (sizes, memory), for following long runs.
 bool verbose();
+
+// The symbolic phase's algorithmic bytes of one product (Stats::sym_bytes).
+inline void count_symbolic(Ctx& c, int64_t nnzc, int64_t pairs, int nb) {
+  c.stats.sym_bytes += 20.0 * (double)pairs + 12.0 * (double)nnzc + 8.0 * (double)(nb + 1);
+}
 
 // Launches within the scope go to stream s.
 struct StreamScope {

@@ -488,6 +488,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
           seen.push_back(ex ? c.spec.exact[i] : std::array<int64_t, 2>{sz[2 * i], sz[2 * i + 1]});
           const double fl = 2.0 * (double)S.b * S.b * S.b * (double)seen.back()[1];
           c.stats.products += seen.back()[1];
+          count_symbolic(c, seen.back()[0], seen.back()[1], nb);
           c.stats.flops += fl;
           if (pprec[i] != LIF_FP64) c.stats.flops_lowp += fl;
         }
@@ -722,6 +723,27 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
   // the later (serial, small) factorization steps.
   hipStream_t side = c.side_stream();
   hipStream_t main_stream = c.stream;
+  {
+    // algorithmic flops of the band-limited factorization and the inverse:
+    // per tile column k of a leaf with m = min(band, nbb - k - 1) tiles
+    // beside the diagonal in the band: the diagonal tile's Cholesky and
+    // inverse (b^3/3 each), the panel (m triangular-by-full products, b^3
+    // each), the trailing update (m (m + 1) / 2 tile products, 2 b^3 each),
+    // the tiles V of that column (min(band, k), b^3 each); then every tile
+    // (i, j > i) of the inverse sums min(j - i, band) tile products
+    const double b3 = (double)b * b * b;
+    double fl = 0.0;
+    for (int s = 0; s < nbase; ++s) {
+      const int nbb = nbbv[s];
+      for (int k = 0; k < nbb; ++k) {
+        const double m = std::min(band, nbb - k - 1);
+        fl += 2.0 * b3 / 3.0 + m * b3 + m * (m + 1.0) * b3 + std::min(band, k) * b3;
+        for (int i = 0; i < k; ++i) fl += 2.0 * b3 * std::min(k - i, band);
+      }
+    }
+    c.stats.leaf_flops += fl;
+  }
+  hipEvent_t leaf_t0 = c.timed_begin(2);
   // step 0's diagonal tile; every later one is factorized by the step before
   // (the workgroup of the last update it receives)
   launch_potrf(c, 0, nbase, d_nbb.get(), d_blk0.get(), d_tile0.get(), b, U.get(), zs->get(), nz.get(), d_err.get());
@@ -747,6 +769,7 @@ Bsr leaf_inverse_cholesky(Ctx& c, const Bsr& S, const std::vector<std::pair<int6
     LIF_HIP(hipEventRecord(ev, side));
     LIF_HIP(hipStreamWaitEvent(main_stream, ev, 0));
   }
+  c.timed_end(leaf_t0, Ctx::Leaf);  // the steps and the inverse's columns on the second stream
   launch_chol_pad(c, nbase, d_nbb.get(), d_rows.get(), d_tile0.get(), b, zs->get(), 0.0);
   std::vector<int> err(nbase);
   c.d2h(err.data(), d_err.get(), nbase * sizeof(int));
@@ -960,6 +983,7 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck)
             if (i < c.spec.exact.size() && c.spec.exact[i][0] >= 0) seen[i] = c.spec.exact[i];  // sized exactly
             const double fl = 2.0 * (double)S.b * S.b * S.b * (double)seen[i][1];
             c.stats.products += seen[i][1];
+            count_symbolic(c, seen[i][0], seen[i][1], nb);
             c.stats.flops += fl;
           }
         }

@@ -470,6 +470,7 @@ Bsr spgemm_body(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau
     }
     if (exact_slot < 0) {  // a slot's statistics are counted once its sequence is kept
       c.stats.products += P;
+      count_symbolic(c, nnzc, P, nb);
       const double fl = 2.0 * (double)C.b * C.b * C.b * (double)P;
       c.stats.flops += fl;
       if (prec != LIF_FP64) c.stats.flops_lowp += fl;

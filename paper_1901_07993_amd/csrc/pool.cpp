@@ -200,20 +200,47 @@ hipEvent_t Ctx::take_event() {
   return e;
 }
 
+hipEvent_t Ctx::timed_begin(int level) {
+  if (timing_level < level) return nullptr;
+  hipEvent_t e = take_event();
+  LIF_HIP(hipEventRecord(e, stream));
+  return e;
+}
+
+void Ctx::timed_end(hipEvent_t e0, Timed what) {
+  if (!e0) return;
+  hipEvent_t e1 = take_event();
+  LIF_HIP(hipEventRecord(e1, stream));
+  ev_pending.emplace_back(e0, e1);
+  ev_lowp.push_back(0);
+  ev_cat.push_back((char)what);
+  if (what == Leaf) ++stats.leaf_launches;
+  if (what == Symbolic) ++stats.sym_launches;
+}
+
 void Ctx::flush_timing() {
   if (ev_pending.empty()) return;
   LIF_HIP(hipStreamSynchronize(stream));
+  if (side) LIF_HIP(hipStreamSynchronize(side));  // events of the second stream as well
   for (size_t i = 0; i < ev_pending.size(); ++i) {
     auto& pr = ev_pending[i];
     float ms = 0.f;
     LIF_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
-    stats.gemm_ms += ms;
-    if (i < ev_lowp.size() && ev_lowp[i]) stats.gemm_ms_lowp += ms;
+    const int cat = i < ev_cat.size() ? ev_cat[i] : Gemm;
+    if (cat == Leaf) {
+      stats.leaf_ms += ms;
+    } else if (cat == Symbolic) {
+      stats.sym_ms += ms;
+    } else {
+      stats.gemm_ms += ms;
+      if (i < ev_lowp.size() && ev_lowp[i]) stats.gemm_ms_lowp += ms;
+    }
     ev_free.push_back(pr.first);
     ev_free.push_back(pr.second);
   }
   ev_pending.clear();
   ev_lowp.clear();
+  ev_cat.clear();
 }
 
 void launch_gather_bytes(hipStream_t stream, const void* const* src, const unsigned* bytes, int count, void* dst);

@@ -111,15 +111,19 @@ void launch_gather_bytes(hipStream_t stream, const void* const* src, const unsig
 }
 
 void scan_exclusive_pair(Ctx& c, const int* in32, int* out32, const int64_t* in64, int64_t* out64, int count) {
+  hipEvent_t t0 = c.timed_begin(2);  // part of the symbolic phase
   hipLaunchKernelGGL(k_scan_pair, dim3(2), dim3(kScanThreads), 0, c.stream, in32, out32, in64, out64, count);
   LIF_HIP(hipGetLastError());
+  c.timed_end(t0, Ctx::Symbolic);
 }
 
 void scan_exclusive_pair_capped(Ctx& c, const int* in32, int* out32, const int64_t* in64, int64_t* out64, int count,
                                 int64_t cap32, int64_t cap64, int64_t* sizes, int* overflow) {
+  hipEvent_t t0 = c.timed_begin(2);  // part of the symbolic phase
   hipLaunchKernelGGL(k_scan_pair_capped, dim3(1), dim3(kScanThreads), 0, c.stream, in32, out32, in64, out64, count,
                      cap32, cap64, sizes, overflow);
   LIF_HIP(hipGetLastError());
+  c.timed_end(t0, Ctx::Symbolic);
 }
 
 void scan_exclusive_i32(Ctx& c, const int* in, int* out, int count) {

@@ -700,9 +700,11 @@ void launch_symbolic_count(Ctx& c, const int* arp, const int* acol, const int* a
                            const int* dcol, int nb, int* cnt_c, int64_t* cnt_p, bool upper) {
   allow_lds((const void*)k_symbolic_count, symbolic_lds_bytes(nb, false));
   const Holes h{ahole, aidx, bhole, bidx};
+  hipEvent_t t0 = c.timed_begin(2);
   hipLaunchKernelGGL(k_symbolic_count, dim3(nb), dim3(kSymWG), symbolic_lds_bytes(nb, false), c.stream, arp, acol,
                      brp, bcol, h, drp, dcol, nb, upper, cnt_c, cnt_p);
   LIF_HIP(hipGetLastError());
+  c.timed_end(t0, Ctx::Symbolic);
 }
 
 void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* aidx, const int* brp, const int* bcol,
@@ -711,12 +713,14 @@ void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* ai
                           int64_t* seg, BlockPair* pairs, BlkOut dsrc, bool upper, int row0, int rows) {
   if (rows < 0) rows = nb - row0;
   LIF_REQUIRE(row0 >= 0 && rows >= 1 && row0 + rows <= nb, LIF_ERR_INVALID, "symbolic fill: row range");
+  hipEvent_t t0 = c.timed_begin(2);
   if (masked_fill_lds_bytes(nb) <= kMaskedFillLds) {
     allow_lds((const void*)k_symbolic_fill_masked<false>, masked_fill_lds_bytes(nb));
     hipLaunchKernelGGL(k_symbolic_fill_masked<false>, dim3(rows), dim3(kSymWG), masked_fill_lds_bytes(nb), c.stream,
                        arp, acol, aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb, upper,
                        const_cast<int*>(crp), prp, ccol, seg, pairs, dsrc, OnePass{}, row0);
     LIF_HIP(hipGetLastError());
+    c.timed_end(t0, Ctx::Symbolic);
     return;
   }
   allow_lds((const void*)k_symbolic_fill, symbolic_lds_bytes(nb, true));
@@ -724,6 +728,7 @@ void launch_symbolic_fill(Ctx& c, const int* arp, const int* acol, const int* ai
                      aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb, upper, crp, prp, ccol,
                      seg, pairs, dsrc, row0);
   LIF_HIP(hipGetLastError());
+  c.timed_end(t0, Ctx::Symbolic);
 }
 
 bool symbolic_onepass_fits(int nb) { return masked_fill_lds_bytes(nb) <= kMaskedFillLds; }
@@ -740,10 +745,12 @@ void launch_symbolic_onepass(Ctx& c, const int* arp, const int* acol, const int*
   op.sizes = sizes;
   op.overflow = overflow;
   allow_lds((const void*)k_symbolic_fill_masked<true>, masked_fill_lds_bytes(nb));
+  hipEvent_t t0 = c.timed_begin(2);
   hipLaunchKernelGGL(k_symbolic_fill_masked<true>, dim3(nb), dim3(kSymWG), masked_fill_lds_bytes(nb), c.stream, arp,
                      acol, aidx, brp, bcol, bidx, ablk, bblk, a_holes, b_holes, drp, dcol, dblk, nb, upper, crp,
                      nullptr, ccol, seg, pairs, dsrc, op, 0);
   LIF_HIP(hipGetLastError());
+  c.timed_end(t0, Ctx::Symbolic);
 }
 
 void launch_numeric(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg, const BlockPair* pairs,
@@ -766,6 +773,7 @@ void launch_numeric(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg, cons
     LIF_HIP(hipEventRecord(e1, c.stream));
     c.ev_pending.emplace_back(e0, e1);
     c.ev_lowp.push_back(prec != LIF_FP64 ? 1 : 0);
+    c.ev_cat.push_back(Ctx::Gemm);
   }
   c.stats.gemm_launches += 1;
   if (prec != LIF_FP64) c.stats.gemm_launches_lowp += 1;

@@ -61,7 +61,9 @@ class Info(ctypes.Structure):
                 ("cpl_tasks", c_int32), ("cpl_products", c_int32), ("iterations_reduced", c_int32),
                 ("mem_peak_bytes", c_uint64), ("mem_reserved_bytes", c_uint64), ("products_compacted", c_int32),
                 ("pair_panels", c_int32), ("flops_leaf_gemm_reduced", c_double),
-                ("seconds_leaf_gemm_reduced", c_double), ("leaf_gemm_launches_reduced", c_int64)]
+                ("seconds_leaf_gemm_reduced", c_double), ("leaf_gemm_launches_reduced", c_int64),
+                ("seconds_leaf_factorization", c_double), ("flops_leaf_factorization", c_double),
+                ("seconds_symbolic", c_double), ("bytes_symbolic", c_double), ("symbolic_launches", c_int64)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "norms"}

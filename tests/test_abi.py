@@ -37,7 +37,7 @@ def test_exports_every_declared_symbol():
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lif.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lif_blocks),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lif_blocks),'
                    ' sizeof(lif_opts), sizeof(lif_info), offsetof(lif_opts, stream), offsetof(lif_info, norms),'
                    ' offsetof(lif_blocks, on_device), offsetof(lif_opts, presize),'
                    ' offsetof(lif_info, iterations_redone), offsetof(lif_opts, refinement),'
@@ -45,7 +45,8 @@ def test_struct_layout_matches_header(tmp_path):
                    ' offsetof(lif_info, iterations_reduced), offsetof(lif_info, mem_reserved_bytes),'
                    ' offsetof(lif_opts, sym_delta), offsetof(lif_opts, residual_panel_rows),'
                    ' offsetof(lif_info, pair_panels), offsetof(lif_opts, update_panel_rows),'
-                   ' offsetof(lif_info, leaf_gemm_launches_reduced)); return 0;}\n')
+                   ' offsetof(lif_info, leaf_gemm_launches_reduced), offsetof(lif_info, symbolic_launches));'
+                   ' return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
@@ -54,7 +55,8 @@ def test_struct_layout_matches_header(tmp_path):
             lif.Info.iterations_redone.offset, lif.Opts.refinement.offset, lif.Info.cpl_products.offset,
             lif.Opts.prec_switch.offset, lif.Info.iterations_reduced.offset, lif.Info.mem_reserved_bytes.offset,
             lif.Opts.sym_delta.offset, lif.Opts.residual_panel_rows.offset, lif.Info.pair_panels.offset,
-            lif.Opts.update_panel_rows.offset, lif.Info.leaf_gemm_launches_reduced.offset]
+            lif.Opts.update_panel_rows.offset, lif.Info.leaf_gemm_launches_reduced.offset,
+            lif.Info.symbolic_launches.offset]
     assert got == want
 
 
@@ -100,7 +102,8 @@ def test_nonzero_padding_rejected():
                                      ("max_iter", 0), ("base_rows", 16), ("start", 9),
                                      ("presize", 3), ("presize", -1), ("refinement", 2),
                                      ("refinement", -1), ("prec_switch", -1.0), ("prec_switch", float("nan")),
-                                     ("sym_delta", 2), ("residual_panel_rows", -1), ("update_panel_rows", -1)])
+                                     ("sym_delta", 2), ("residual_panel_rows", -1), ("update_panel_rows", -1),
+                                     ("timing", 3)])
 def test_invalid_options_rejected(opt, val):
     S = _blocks(64, 64, [0], [0], np.eye(64)[None])
     with pytest.raises(lif.LifError) as ei:
