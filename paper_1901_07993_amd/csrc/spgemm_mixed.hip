@@ -45,6 +45,12 @@ __device__ inline int64_t xcd_remap_m(int64_t wg, int64_t total) {
   return x * q + (x < r ? x : r) + l;
 }
 
+// output blocks per workgroup of the BF16 product (1: one block per workgroup)
+#ifndef LIF_BF16_GROUP
+#define LIF_BF16_GROUP 4
+#endif
+constexpr int kBf16Group = LIF_BF16_GROUP;
+
 template <int B>
 struct MixCfg {
   static constexpr int WAVES = (B / 32) * (B / 32);
@@ -184,6 +190,101 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16(const int64
   epilogue<B, LIF_MIXED_BF16, OUT_LP>(acc, rb, cb, l16, kq, lane, wave, blk, C, Cp, red, norms, epi);
 }
 
+// BF16 with operand sharing: a workgroup computes G consecutive output blocks
+// (in the output's block order), walking their G lists of block products
+// together.  At each step it takes the smallest A block pointer among the
+// lists' next products, loads that block's fragments once, and runs the
+// products of every list whose next product has that A block (an A block
+// shared by several outputs of a row is read once instead of G times).  Each
+// list is still consumed in its own order, with the same MFMA sequence per
+// output block as k_numeric_bf16, so the blocks are bitwise the same; only
+// the sharing depends on the A blocks of a row lying at increasing addresses
+// (true for the input-precision copies, stored in block order).
+template <int B, bool OUT_LP, int G>
+__global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16_group(const int64_t* __restrict__ seg,
+                                                                           const BlockPair* __restrict__ pairs,
+                                                                           const int* __restrict__ live,
+                                                                           double* __restrict__ C, BlkOut Cp,
+                                                                           double* __restrict__ norms,
+                                                                           Epilogue epi, int64_t nblocks) {
+  constexpr int KS = B / 32;
+  __shared__ double red[MixCfg<B>::WAVES + 1];
+  // the output blocks of the launch: *live, else all nblocks (the grid has
+  // one workgroup per G of them, so it does not count them); none for a
+  // voided product, whose row pointers workgroup 0 clears
+  int64_t nlive;
+  if (epi.poison && *epi.poison) {
+    if (blockIdx.x == 0)
+      for (int r = threadIdx.x; r <= epi.nrows; r += blockDim.x) epi.rows[r] = 0;
+    nlive = 0;
+  } else {
+    nlive = live ? min((int64_t)*live, nblocks) : nblocks;
+  }
+  const int64_t ngroups = (nlive + G - 1) / G;
+  if ((int64_t)blockIdx.x >= ngroups) return;
+  const int64_t e0 = xcd_remap_m(blockIdx.x, ngroups) * G;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rb = 32 * (wave / (B / 32)), cb = 32 * (wave % (B / 32));
+  const int l16 = lane & 15, kq = lane >> 4;
+  v4f acc[G][2][2];
+  int64_t pp[G], pe[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const bool in = e0 + g < nlive;
+    pp[g] = in ? seg[e0 + g] : 0;
+    pe[g] = in ? seg[e0 + g + 1] : 0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[g][a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+  }
+  for (;;) {
+    uintptr_t amin = ~uintptr_t(0);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (pp[g] < pe[g]) amin = min(amin, reinterpret_cast<uintptr_t>(pairs[pp[g]].a));
+    if (amin == ~uintptr_t(0)) break;
+    const unsigned short* a = reinterpret_cast<const unsigned short*>(amin);
+    v8bf af[KS][2];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+        af[ks][t] = *gptr(reinterpret_cast<const v8bf*>(a + (rb + 16 * t + l16) * B + 32 * ks + 8 * kq));
+    // the B fragments of every list taking this A block, then their MFMAs
+    v8bf bf[G][KS][2];
+    bool take[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      take[g] = pp[g] < pe[g] && reinterpret_cast<uintptr_t>(pairs[pp[g]].a) == amin;
+      if (take[g]) {
+        const unsigned short* bt = reinterpret_cast<const unsigned short*>(pairs[pp[g]].b);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+          for (int t = 0; t < 2; ++t)
+            bf[g][ks][t] = *gptr(reinterpret_cast<const v8bf*>(bt + (cb + 16 * t + l16) * B + 32 * ks + 8 * kq));
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (take[g]) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          acc[g][0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][0], bf[g][ks][0], acc[g][0][0], 0, 0, 0);
+          acc[g][0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][0], bf[g][ks][1], acc[g][0][1], 0, 0, 0);
+          acc[g][1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][1], bf[g][ks][0], acc[g][1][0], 0, 0, 0);
+          acc[g][1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][1], bf[g][ks][1], acc[g][1][1], 0, 0, 0);
+        }
+        ++pp[g];
+      }
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+    if (e0 + g < nlive)
+      epilogue<B, LIF_MIXED_BF16, OUT_LP>(acc[g], rb, cb, l16, kq, lane, wave, e0 + g, C, Cp, red, norms, epi);
+}
+
 template <int B, bool OUT_LP>
 __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(const int64_t* __restrict__ seg,
                                                                     const BlockPair* __restrict__ pairs,
@@ -290,6 +391,14 @@ void launch_mixed_b(Ctx& c, int prec, const int64_t* seg, const BlockPair* pairs
       hipLaunchKernelGGL((k_numeric_f32<B, true>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms, epi);
     else
       hipLaunchKernelGGL((k_numeric_f32<B, false>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms, epi);
+  } else if (kBf16Group > 1) {
+    const dim3 ggrid((unsigned)((nnzc + kBf16Group - 1) / kBf16Group));
+    if (out_lp)
+      hipLaunchKernelGGL((k_numeric_bf16_group<B, true, kBf16Group>), ggrid, block, 0, c.stream, seg, pairs, live, C,
+                         Cp, norms, epi, nnzc);
+    else
+      hipLaunchKernelGGL((k_numeric_bf16_group<B, false, kBf16Group>), ggrid, block, 0, c.stream, seg, pairs, live,
+                         C, Cp, norms, epi, nnzc);
   } else {
     if (out_lp)
       hipLaunchKernelGGL((k_numeric_bf16<B, true>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms, epi);
