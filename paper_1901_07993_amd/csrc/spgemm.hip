@@ -651,10 +651,140 @@ __global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64(const int64
   numeric_epilogue<B, TA, TB, HAS_D>(acc, f, blk, C, Cp, norms, epi, d, red);
 }
 
+// The same with operand sharing for large products: a workgroup computes G
+// consecutive output blocks, walking their lists of block products together
+// -- at each step the smallest A block pointer among the lists' next products
+// is loaded (and staged) once and the products of every list whose next
+// product has that A block run against it.  Each list is consumed in its own
+// order with the MFMA sequence of k_numeric_f64, so every block is bitwise
+// the same; A blocks stored in block order (as sums, products and compaction
+// leave them) are shared between the outputs of a row.
+template <int B, bool TA, bool TB, bool HAS_D, int G>
+__global__ __launch_bounds__(TileCfg<B>::THREADS) void k_numeric_f64_group(const int64_t* __restrict__ seg,
+                                                                              const BlockPair* __restrict__ pairs,
+                                                                              const int* __restrict__ live,
+                                                                              double* __restrict__ C, BlkOut Cp,
+                                                                              double* __restrict__ norms,
+                                                                              Epilogue epi, int64_t nblocks) {
+  using Cfg = TileCfg<B>;
+  constexpr bool A_LDS = !TA, B_LDS = TB;
+  constexpr int KS = B / 4;
+  __shared__ __attribute__((aligned(16))) double As[A_LDS ? Cfg::LDS_DOUBLES : 2];
+  __shared__ __attribute__((aligned(16))) double Bs[B_LDS ? Cfg::LDS_DOUBLES : 2];
+  __shared__ double red[Cfg::WAVES + 1];
+  // the output blocks of the launch: *live, else all nblocks (the grid has
+  // one workgroup per G of them); none for a voided product, whose row
+  // pointers workgroup 0 clears
+  int64_t nlive;
+  if (epi.poison && *epi.poison) {
+    if (blockIdx.x == 0)
+      for (int r = threadIdx.x; r <= epi.nrows; r += blockDim.x) epi.rows[r] = 0;
+    nlive = 0;
+  } else {
+    nlive = live ? min((int64_t)*live, nblocks) : nblocks;
+  }
+  const int64_t ngroups = (nlive + G - 1) / G;
+  if ((int64_t)blockIdx.x >= ngroups) return;
+  const int64_t e0 = xcd_remap(blockIdx.x, ngroups) * G;
+  const Frag f = frag_coords<B>();
+  v4d acc[G][2][2];
+  int64_t pp[G], pe[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const bool in = e0 + g < nlive;
+    pp[g] = in ? seg[e0 + g] : 0;
+    pe[g] = in ? seg[e0 + g + 1] : 0;
+    acc_zero(acc[g]);
+  }
+  bool staged = false;  // LDS holds tiles that MFMAs of the workgroup may still read
+  for (;;) {
+    uintptr_t amin = ~uintptr_t(0);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (pp[g] < pe[g]) amin = min(amin, reinterpret_cast<uintptr_t>(pairs[pp[g]].a));
+    if (amin == ~uintptr_t(0)) break;
+    const double* pa = reinterpret_cast<const double*>(amin);
+    v2d ad[KS];
+    if (A_LDS) {
+      v2d ra[Cfg::V2];
+      tile_load<B>(pa, ra);
+      if (staged) __syncthreads();
+      tile_store<B>(As, ra, true);
+      __syncthreads();
+      staged = true;
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk)
+        ad[kk] = *gptr(reinterpret_cast<const v2d*>(pa + (4 * kk + f.kq) * B + f.rb + 2 * f.l16));
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      // uniform over the workgroup: the lists and their heads are shared
+      if (!(pp[g] < pe[g] && reinterpret_cast<uintptr_t>(pairs[pp[g]].a) == amin)) continue;
+      const double* pb = pairs[pp[g]].b;
+      v2d bd[KS];
+      if (B_LDS) {
+        v2d rbv[Cfg::V2];
+        tile_load<B>(pb, rbv);
+        if (staged) __syncthreads();
+        tile_store<B>(Bs, rbv, true);
+        __syncthreads();
+        staged = true;
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk)
+          bd[kk] = *gptr(reinterpret_cast<const v2d*>(pb + (4 * kk + f.kq) * B + f.cb + 2 * f.l16));
+      }
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) {
+        const int k = 4 * kk + f.kq;
+        constexpr int LD = Cfg::LD;
+        const double a0 = A_LDS ? As[(f.rb + f.l16) * LD + k] : ad[kk].x;
+        const double a1 = A_LDS ? As[(f.rb + 16 + f.l16) * LD + k] : ad[kk].y;
+        const double b0 = B_LDS ? Bs[(f.cb + f.l16) * LD + k] : bd[kk].x;
+        const double b1 = B_LDS ? Bs[(f.cb + 16 + f.l16) * LD + k] : bd[kk].y;
+        acc[g][0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[g][0][0], 0, 0, 0);
+        acc[g][0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[g][0][1], 0, 0, 0);
+        acc[g][1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[g][1][0], 0, 0, 0);
+        acc[g][1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[g][1][1], 0, 0, 0);
+      }
+      ++pp[g];
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+    if (e0 + g < nlive) {
+      double d[2][2][4];
+      if (HAS_D) load_d<B, TA, TB>(f, epi.dsrc[e0 + g], d);
+      numeric_epilogue<B, TA, TB, HAS_D>(acc[g], f, e0 + g, C, Cp, norms, epi, d, red);
+    }
+}
+
+// outputs per workgroup of the FP64 product on large products (1: one
+// each).  Two: 4 % less time on the FP64 factorizations of the water
+// clusters; four leaves one workgroup per SIMD and is 17 % slower.
+#ifndef LIF_F64_GROUP
+#define LIF_F64_GROUP 2
+#endif
+constexpr int kF64Group = LIF_F64_GROUP;
+// products with at least this many output blocks use the grouped kernel
+constexpr int64_t kF64GroupMin = 16384;
+
 template <int B, bool TA, bool TB>
 void launch_numeric_t(Ctx& c, dim3 grid, const int64_t* seg, const BlockPair* pairs, const int* live, double* C,
                       BlkOut Cp, double* norms, const Epilogue& epi) {
   const dim3 block(TileCfg<B>::THREADS);
+  const int64_t nnzc = grid.x;
+  if (kF64Group > 1 && nnzc >= kF64GroupMin) {
+    const dim3 ggrid((unsigned)((nnzc + kF64Group - 1) / kF64Group));
+    if (epi.dsrc)
+      hipLaunchKernelGGL((k_numeric_f64_group<B, TA, TB, true, kF64Group>), ggrid, block, 0, c.stream, seg, pairs,
+                         live, C, Cp, norms, epi, nnzc);
+    else
+      hipLaunchKernelGGL((k_numeric_f64_group<B, TA, TB, false, kF64Group>), ggrid, block, 0, c.stream, seg, pairs,
+                         live, C, Cp, norms, epi, nnzc);
+    return;
+  }
   if (epi.dsrc)
     hipLaunchKernelGGL((k_numeric_f64<B, TA, TB, true>), grid, block, 0, c.stream, seg, pairs, live, C, Cp, norms,
                        epi);
