@@ -212,7 +212,7 @@ def upper_blocks(A: np.ndarray, b: int, strict: bool = False) -> np.ndarray:
 
 
 def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_iter=100, info=None,
-                         prec="fp64", prec_switch=0.0, sym_delta=False):
+                         prec="fp64", prec_switch=0.0, sym_delta=False, update_prec="fp64", trace=None):
     """Localized iterative refinement (eq. refinement_local; Alg. 2 repeat loop).
 
     Each iteration, with T_k the Horner terms of sum_{k=1}^m b_k delta^k:
@@ -237,6 +237,16 @@ def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_
     ``sym_delta``: delta is symmetric in exact arithmetic, so only its upper
     block triangle is updated (the blocks (I, J), J >= I, of the two
     truncated products) and the strictly upper part is mirrored below.
+    ``update_prec`` (with ``prec_switch`` > 0): the delta-update products of
+    the reduced iterations (S M, Z'^T SM, SM^T Z) in that input precision
+    too.  delta then no longer tracks I - Z^T S Z to FP64 accuracy, so when
+    the schedule moves to FP64 it is formed again from its definition,
+    delta = I - trunc(trunc(Z^T S) Z) in FP64 (mirrored like an update with
+    ``sym_delta``); its norm replaces the last recorded one, which the
+    stopping rule then compares against.
+    ``trace`` (tests): called as trace(k, event, Z, delta) with event
+    "recomputed" (delta formed again before iteration k) or "updated" (Z and
+    delta after iteration k).
     Returns (Z, RefineInfo).
     """
     info = info if info is not None else RefineInfo()
@@ -246,11 +256,24 @@ def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_
     Z, delta = Z0.copy(), delta0.copy()
     if not np.any(delta):
         return Z, info
+    assert update_prec == "fp64" or prec_switch > 0.0, "a reduced delta update needs the precision schedule"
     e_prev = None
     e_cur = float(np.sqrt(np.sum(delta * delta)))
+    stale = False  # delta carries the rounding of reduced-precision updates
     for k in range(1, max_iter + 1):
         reduced = prec != "fp64" and (prec_switch == 0.0 or e_cur > prec_switch)
         p = prec if reduced else "fp64"
+        if stale and not reduced:
+            delta = I - mult(mult(Z.T, S, b, tau), Z, b, tau)
+            if sym_delta:
+                U = upper_blocks(delta, b)
+                delta = U + upper_blocks(U, b, strict=True).T
+            e_cur = float(np.sqrt(np.sum(delta * delta)))
+            info.norms[-1] = e_cur
+            e_prev = e_cur
+            stale = False
+            if trace:
+                trace(k, "recomputed", Z, delta)
         if m == 1:
             q = bk[1] * delta
         elif p == "fp64":
@@ -267,14 +290,18 @@ def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_
             q = X
         M = mult(Z, q, b, tau, p)
         Z_new = Z + M
-        SM = mult(S, M, b, tau)
-        X1 = mult(Z_new.T, SM, b, tau)
-        X2 = mult(SM.T, Z, b, tau)
+        pu = update_prec if reduced else "fp64"
+        SM = mult(S, M, b, tau, pu)
+        X1 = mult(Z_new.T, SM, b, tau, pu)
+        X2 = mult(SM.T, Z, b, tau, pu)
+        stale = pu != "fp64"
         delta = delta - X1 - X2
         if sym_delta:
             U = upper_blocks(delta, b)
             delta = U + upper_blocks(U, b, strict=True).T
         Z = Z_new
+        if trace:
+            trace(k, "updated", Z, delta)
         e = float(np.sqrt(np.sum(delta * delta)))
         info.norms.append(e)
         info.reduced.append(reduced)
@@ -328,7 +355,7 @@ def nonlocal_refinement(S, Z0, b, tau, m=4, iterations=None, stop="paper", tol=0
 
 def irsi(S, b, tau, m=4, start="sqrt2_over_gersh", start_value=None, stop="paper", tol=0.0,
          max_iter=100, truncate_input=True, prec="fp64", refinement="local", prec_switch=0.0,
-         sym_delta=False):
+         sym_delta=False, update_prec="fp64"):
     """Iterative refinement from a scaled identity (IRSI, Sec. 2.2):
     Z_0 = c I, delta_0 = I - c^2 S (a scaling, no product), then localized
     refinement.  With ``refinement="nonlocal"`` the regular form of
@@ -346,7 +373,7 @@ def irsi(S, b, tau, m=4, start="sqrt2_over_gersh", start_value=None, stop="paper
     assert refinement == "local", refinement
     delta0 = np.eye(n) - (c * c) * St
     Z, info = localized_refinement(St, Z0, delta0, b, tau, m, stop, tol, max_iter, prec=prec,
-                                   prec_switch=prec_switch, sym_delta=sym_delta)
+                                   prec_switch=prec_switch, sym_delta=sym_delta, update_prec=update_prec)
     return Z, info, c
 
 
@@ -373,7 +400,7 @@ def lif_plan(n: int, b: int, base_rows: int) -> LifNode:
 
 
 def lif(S, b, tau, m=4, base_rows=4096, stop="paper", tol=0.0, max_iter=100, truncate_input=True,
-        plan=None, prec="fp64", refinement="local", prec_switch=0.0, sym_delta=False):
+        plan=None, prec="fp64", refinement="local", prec_switch=0.0, sym_delta=False, update_prec="fp64"):
     """Localized inverse factorization (Alg. 2) with an inverse Cholesky leaf.
 
     For a node with children A (leading rows) and C:
@@ -416,7 +443,7 @@ def lif(S, b, tau, m=4, base_rows=4096, stop="paper", tol=0.0, max_iter=100, tru
         node.delta0_norm2 = float(np.linalg.norm(delta0, 2)) if rows <= 4000 else float("nan")
         node.info = RefineInfo()
         Z, _ = localized_refinement(Sn, Z0, delta0, b, tau, m, stop, tol, max_iter, node.info, prec=prec,
-                                    prec_switch=prec_switch, sym_delta=sym_delta)
+                                    prec_switch=prec_switch, sym_delta=sym_delta, update_prec=update_prec)
         return Z
 
     return rec(plan), plan
