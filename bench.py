@@ -137,15 +137,19 @@ def time_method(lif, Sd, tau, meth, steps, **kw):
 
 
 WATER_VARIANTS = {
-    # name: (precision, precision switch, symmetric delta update)
-    "fp64": ("FP64", 0.0, 0), "fp64_sym": ("FP64", 0.0, 1),
-    "fp32_schedule": ("MIXED_FP32", 1e-2, 0), "bf16_schedule": ("MIXED_BF16", 1e-2, 0),
-    "fp32_schedule_sym": ("MIXED_FP32", 1e-2, 1), "bf16_schedule_sym": ("MIXED_BF16", 1e-2, 1),
+    # name: (precision, precision switch, symmetric delta update, inputs of
+    # the delta update in reduced iterations)
+    "fp64": ("FP64", 0.0, 0, "FP64"), "fp64_sym": ("FP64", 0.0, 1, "FP64"),
+    "fp32_schedule": ("MIXED_FP32", 1e-2, 0, "FP64"), "bf16_schedule": ("MIXED_BF16", 1e-2, 0, "FP64"),
+    "fp32_schedule_sym": ("MIXED_FP32", 1e-2, 1, "FP64"), "bf16_schedule_sym": ("MIXED_BF16", 1e-2, 1, "FP64"),
+    "bf16_schedule_sym_f32update": ("MIXED_BF16", 1e-2, 1, "MIXED_FP32"),
+    "fp32_schedule_sym_f32update": ("MIXED_FP32", 1e-2, 1, "MIXED_FP32"),
 }
 PEAK_TFLOPS = {"FP64": 78.6, "MIXED_FP32": 157.3, "MIXED_BF16": 2500.0}
 
 
-def water_comparison(lif, count, which=("fp64_sym", "bf16_schedule_sym"), z_diff=True, residuals=True):
+def water_comparison(lif, count, which=("fp64_sym", "bf16_schedule_sym", "bf16_schedule_sym_f32update"),
+                     z_diff=True, residuals=True):
     """FP64 against the scheduled reduced-precision corrections on a water
     cluster (tau = 1e-8, b = 64, LIF to 4096-row leaves, paper stop): the
     metric's comparison, on the compute-bound products where reduced
@@ -155,7 +159,8 @@ def water_comparison(lif, count, which=("fp64_sym", "bf16_schedule_sym"), z_diff
     residual against the truncated S that was factorized and against S
     before that truncation (Table 1 leaves open which one it used), node
     iterations, the leaf-GEMM rate of each precision on its own, the memory
-    peak and, for reduced runs, ||Z - Z_fp64||_F / ||Z_fp64||_F."""
+    peak and, for reduced runs, ||Z - Z_fp64||_F / ||Z_fp64||_F.  A variant
+    that fails (out of memory, say) is reported with its error."""
     import torch
     from gen import config_matrix
     print(f"# generating water-{count}", file=sys.stderr, flush=True)
@@ -169,18 +174,23 @@ def water_comparison(lif, count, which=("fp64_sym", "bf16_schedule_sym"), z_diff
            "device_memory_gib": torch.cuda.get_device_properties(0).total_memory / 2 ** 30}
     first = WATER_VARIANTS[which[0]]
     f = lif.Factorization(Sd, tau=cfg["tau"], base_rows=4096, prec=getattr(lif, first[0]), prec_switch=first[1],
-                          sym_delta=first[2], timing=1)
+                          sym_delta=first[2], update_prec=getattr(lif, first[3]), timing=1)
     f.localized()
     torch.cuda.synchronize()
     print(f"# water-{count} warm-up done", file=sys.stderr, flush=True)
     t64 = {}
     Zref = None
     for name in which:
-        pname, sw, sym = WATER_VARIANTS[name]
-        f.set_opts(prec=getattr(lif, pname), prec_switch=sw, sym_delta=sym)
+        pname, sw, sym, upd = WATER_VARIANTS[name]
+        f.set_opts(prec=getattr(lif, pname), prec_switch=sw, sym_delta=sym, update_prec=getattr(lif, upd))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        info = f.localized()
+        try:
+            info = f.localized()
+        except lif.LifError as e:
+            out[name] = {"error": str(e)}
+            print(f"# water-{count} {name}: {e}", file=sys.stderr, flush=True)
+            continue
         torch.cuda.synchronize()
         s = time.perf_counter() - t0
         res = f.residual() if residuals else None
@@ -197,10 +207,18 @@ def water_comparison(lif, count, which=("fp64_sym", "bf16_schedule_sym"), z_diff
         if sec - secr > 0:
             r["leaf_gemm_fp64_tflops"] = (fl - flr) / (sec - secr) / 1e12
             r["leaf_gemm_fp64_frac_of_peak"] = r["leaf_gemm_fp64_tflops"] / PEAK_TFLOPS["FP64"]
-        if secr > 0:
-            r["leaf_gemm_reduced_tflops"] = flr / secr / 1e12
-            r["leaf_gemm_reduced_frac_of_peak"] = r["leaf_gemm_reduced_tflops"] / PEAK_TFLOPS[pname]
-            r["leaf_gemm_reduced_launches"] = info["leaf_gemm_launches_reduced"]
+        # the reduced launches by input precision (with update_prec the
+        # delta update's FP32 products join the correction's BF16 ones)
+        fl32, sec32 = info["flops_leaf_gemm_fp32"], info["seconds_leaf_gemm_fp32"]
+        n32 = info["leaf_gemm_launches_fp32"]
+        nred = info["leaf_gemm_launches_reduced"]
+        for tag, p_fl, p_sec, p_n, peak in (("bf16", flr - fl32, secr - sec32, nred - n32, "MIXED_BF16"),
+                                            ("fp32", fl32, sec32, n32, "MIXED_FP32")):
+            if p_n > 0 and p_sec > 0:
+                r[f"leaf_gemm_{tag}_seconds"] = p_sec
+                r[f"leaf_gemm_{tag}_tflops"] = p_fl / p_sec / 1e12
+                r[f"leaf_gemm_{tag}_frac_of_peak"] = r[f"leaf_gemm_{tag}_tflops"] / PEAK_TFLOPS[peak]
+                r[f"leaf_gemm_{tag}_launches"] = p_n
         if pname == "FP64":
             t64[sym] = s
             if z_diff and Zref is None:

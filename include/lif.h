@@ -128,6 +128,14 @@ typedef struct {
                            * large part of the device memory, sized so that the two products of a
                            * panel take at most 1/32 of it), so that neither product is ever
                            * held whole; the result is the same bit for bit */
+  int32_t update_prec;    /* inputs of the delta-update products (S M, Z_{k+1}^T (S M), (S M)^T Z_k of
+                           * eq. refinement_local) in a problem's reduced iterations under the precision
+                           * schedule: LIF_FP64 (default) or LIF_MIXED_FP32 (FP32 inputs, FP32
+                           * accumulation).  delta then carries FP32 rounding, so when a problem's
+                           * schedule moves to FP64 its delta is formed again from its definition,
+                           * I - trunc(Z^T trunc(S Z)) in FP64 (Sec. 2.2; mirrored with sym_delta), and
+                           * its norm replaces the last recorded one.  LIF_MIXED_FP32 needs a reduced
+                           * prec with prec_switch > 0 and checkpoint = 0 */
 } lif_opts;
 
 typedef struct {
@@ -169,6 +177,9 @@ typedef struct {
                                        * read, a 16-byte pair written), 12 per output block, the row
                                        * pointers */
   int64_t symbolic_launches;          /* timed symbolic launches */
+  double flops_leaf_gemm_fp32;        /* the part of flops_leaf_gemm_reduced with FP32 inputs */
+  double seconds_leaf_gemm_fp32;      /* the part of seconds_leaf_gemm_reduced in those launches */
+  int64_t leaf_gemm_launches_fp32;    /* the part of leaf_gemm_launches_reduced with FP32 inputs */
 } lif_info;
 
 /* Fills *o with the defaults: m = 4, tau = 0, FP64, paper stopping rule,

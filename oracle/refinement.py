@@ -241,9 +241,10 @@ def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_
     the reduced iterations (S M, Z'^T SM, SM^T Z) in that input precision
     too.  delta then no longer tracks I - Z^T S Z to FP64 accuracy, so when
     the schedule moves to FP64 it is formed again from its definition,
-    delta = I - trunc(trunc(Z^T S) Z) in FP64 (mirrored like an update with
-    ``sym_delta``); its norm replaces the last recorded one, which the
-    stopping rule then compares against.
+    delta = I - trunc(Z^T trunc(S Z)) in FP64 (S Z first, as the update
+    forms S M; mirrored like an update with ``sym_delta``); its norm
+    replaces the last recorded one, which the stopping rule then compares
+    against.
     ``trace`` (tests): called as trace(k, event, Z, delta) with event
     "recomputed" (delta formed again before iteration k) or "updated" (Z and
     delta after iteration k).
@@ -264,7 +265,7 @@ def localized_refinement(S, Z0, delta0, b, tau, m=4, stop="paper", tol=0.0, max_
         reduced = prec != "fp64" and (prec_switch == 0.0 or e_cur > prec_switch)
         p = prec if reduced else "fp64"
         if stale and not reduced:
-            delta = I - mult(mult(Z.T, S, b, tau), Z, b, tau)
+            delta = I - mult(Z.T, mult(S, Z, b, tau), b, tau)
             if sym_delta:
                 U = upper_blocks(delta, b)
                 delta = U + upper_blocks(U, b, strict=True).T

@@ -47,6 +47,13 @@ void validate_opts(const lif_opts& o) {
   LIF_REQUIRE(o.residual_panel_rows >= 0, LIF_ERR_INVALID, "opts.residual_panel_rows must be >= 0");
   LIF_REQUIRE(o.update_panel_rows >= 0, LIF_ERR_INVALID, "opts.update_panel_rows must be >= 0");
   LIF_REQUIRE(o.timing >= 0 && o.timing <= 2, LIF_ERR_INVALID, "opts.timing must be 0, 1 or 2");
+  LIF_REQUIRE(o.update_prec == LIF_FP64 || o.update_prec == LIF_MIXED_FP32, LIF_ERR_INVALID,
+              "opts.update_prec must be LIF_FP64 or LIF_MIXED_FP32");
+  if (o.update_prec != LIF_FP64) {
+    LIF_REQUIRE(o.prec != LIF_FP64 && o.prec_switch > 0.0, LIF_ERR_INVALID,
+                "opts.update_prec = LIF_MIXED_FP32 needs a reduced prec with prec_switch > 0");
+    LIF_REQUIRE(o.checkpoint == 0, LIF_ERR_INVALID, "opts.update_prec = LIF_MIXED_FP32 needs checkpoint = 0");
+  }
   if (o.start == LIF_START_INV_SQRT_LMAX || o.start == LIF_START_GIVEN)
     LIF_REQUIRE(std::isfinite(o.start_value) && o.start_value > 0.0, LIF_ERR_INVALID,
                 "opts.start_value must be > 0 for this start");
@@ -165,6 +172,7 @@ void copy_opts(lif_handle h, const lif_opts& o) {
   p.sym_delta = o.sym_delta != 0;
   p.residual_panel_rows = o.residual_panel_rows;
   p.update_panel_rows = o.update_panel_rows;
+  p.update_prec = o.update_prec;
   h->ctx.stream = static_cast<hipStream_t>(o.stream);
   h->ctx.timing = o.timing != 0;
   h->ctx.timing_level = o.timing;
@@ -199,6 +207,9 @@ void fill_info(lif_handle h, const RunInfo& ri, double seconds, lif_info* info) 
   info->flops_leaf_gemm_reduced = h->ctx.stats.flops_lowp;
   info->seconds_leaf_gemm_reduced = h->ctx.stats.gemm_ms_lowp * 1e-3;
   info->leaf_gemm_launches_reduced = h->ctx.stats.gemm_launches_lowp;
+  info->flops_leaf_gemm_fp32 = h->ctx.stats.flops_f32;
+  info->seconds_leaf_gemm_fp32 = h->ctx.stats.gemm_ms_f32 * 1e-3;
+  info->leaf_gemm_launches_fp32 = h->ctx.stats.gemm_launches_f32;
   info->seconds_leaf_factorization = h->ctx.stats.leaf_ms * 1e-3;
   info->flops_leaf_factorization = h->ctx.stats.leaf_flops;
   info->seconds_symbolic = h->ctx.stats.sym_ms * 1e-3;
@@ -261,6 +272,7 @@ lif_status lif_opts_default(lif_opts* o) {
   o->sym_delta = 0;
   o->residual_panel_rows = 0;
   o->update_panel_rows = 0;
+  o->update_prec = LIF_FP64;
   return LIF_OK;
 }
 

@@ -235,6 +235,8 @@ struct Stats {
   double gemm_ms = 0;
   double gemm_ms_lowp = 0;        // part of gemm_ms spent in FP32/BF16-input launches
   int64_t gemm_launches_lowp = 0;
+  double flops_f32 = 0, gemm_ms_f32 = 0;  // the FP32-input part of the three above
+  int64_t gemm_launches_f32 = 0;
   // timing level 2: the leaf factorizations and the symbolic phases, with the
   // algorithmic work of each -- the band-limited factorization's and the
   // dense inverse's flops; the symbolic phase's bytes (each block product
@@ -324,7 +326,7 @@ struct Ctx {
   DBuf<int> lb_fail;
   // events around leaf-GEMM launches (timing mode), resolved at flush_timing()
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
-  std::vector<char> ev_lowp;  // per pending pair: a reduced-precision launch
+  std::vector<char> ev_lowp;  // per pending pair: the input precision of the launch (LIF_FP64 = 0: FP64)
   // per pending pair: what it timed (Timed::Gemm, Leaf or Symbolic)
   std::vector<char> ev_cat;
   enum Timed { Gemm = 0, Leaf = 1, Symbolic = 2 };

@@ -157,13 +157,8 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
   // delta_{k+1} from delta_k and the two products: the full difference, or
   // with a symmetric delta the difference on the upper block triangle (the
   // products hold only those blocks) with its strictly upper part mirrored
-  auto delta_update = [&](const Bsr& X1, const Bsr& X2) {
-    if (!o.sym_delta) return axpby3(c, 1.0, &delta, -1.0, &X1, -1.0, &X2);
-    Bsr U;
-    {
-      Bsr dU = filter(c, delta, d_iota.get(), d_iota.get(), 3);
-      U = axpby3(c, 1.0, &dU, -1.0, &X1, -1.0, &X2);
-    }
+  // the upper block triangle of U with its strictly upper part mirrored below
+  auto mirror_upper = [&](const Bsr& U) {
     Bsr L;
     {
       Bsr SU = filter(c, U, d_iota1.get(), d_iota.get(), 3);
@@ -171,6 +166,16 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
     }
     return axpby(c, 1.0, &U, 1.0, &L, 0.0, nullptr);
   };
+  auto delta_update_from = [&](const Bsr& d0, const Bsr& X1, const Bsr& X2) {
+    if (!o.sym_delta) return axpby3(c, 1.0, &d0, -1.0, &X1, -1.0, &X2);
+    Bsr U;
+    {
+      Bsr dU = filter(c, d0, d_iota.get(), d_iota.get(), 3);
+      U = axpby3(c, 1.0, &dU, -1.0, &X1, -1.0, &X2);
+    }
+    return mirror_upper(U);
+  };
+  auto delta_update = [&](const Bsr& X1, const Bsr& X2) { return delta_update_from(delta, X1, X2); };
   // The update on large problems, formed by panels of block rows so that
   // neither product is ever held whole: rows [p0, p1) of Z_{k+1}^T (S M) take
   // Z_{k+1}'s block columns in [p0, p1), rows of (S M)^T Z_k the same columns
@@ -179,7 +184,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
   // whole update.  The panels' row sets are disjoint: joining them moves
   // pointers only, and like the assembly of submatrices it is not a task.
   DBuf<int> d_pzero, d_plab, d_piota;
-  auto delta_update_panels = [&](const Bsr& SM, const Bsr& Zk, const Bsr& Zn, int rows) {
+  auto delta_update_panels = [&](const Bsr& d0, const Bsr& SM, const Bsr& Zk, const Bsr& Zn, int rows, int pu) {
     if (!d_pzero.get()) {
       d_pzero = DBuf<int>(c.pool, nb);
       d_plab = DBuf<int>(c.pool, nb);
@@ -197,11 +202,11 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       Bsr X1, X2;
       {
         Bsr Zc = filter(c, Zn, d_pzero.get(), d_plab.get(), 0);
-        X1 = spgemm(c, Zc, true, SM, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, true, false, o.sym_delta);
+        X1 = spgemm(c, Zc, true, SM, false, o.tau, pu, 1.0, nullptr, 0.0, true, false, o.sym_delta);
       }
       {
         Bsr Sc = filter(c, SM, d_pzero.get(), d_plab.get(), 0);
-        X2 = spgemm(c, Sc, true, Zk, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, true, false, o.sym_delta);
+        X2 = spgemm(c, Sc, true, Zk, false, o.tau, pu, 1.0, nullptr, 0.0, true, false, o.sym_delta);
       }
       Bsr dP;
       if (o.sym_delta) {
@@ -209,9 +214,9 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
         launch_fill_i32(c, d_piota.get(), -1, nb);
         LIF_HIP(hipMemcpyAsync(d_piota.get() + p0, d_iota.get() + p0, (size_t)(p1 - p0) * sizeof(int),
                                hipMemcpyDeviceToDevice, c.stream));
-        dP = filter(c, delta, d_piota.get(), d_iota.get(), 3);
+        dP = filter(c, d0, d_piota.get(), d_iota.get(), 3);
       } else {
-        dP = filter(c, delta, d_plab.get(), nullptr, 2);
+        dP = filter(c, d0, d_plab.get(), nullptr, 2);
       }
       Bsr part = axpby3(c, 1.0, &dP, -1.0, &X1, -1.0, &X2);
       if (part.cpl > part_cpl || (part.cpl == part_cpl && part.cpl_products > part_prod)) {
@@ -231,14 +236,98 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
     acc.cpl = part_cpl;
     acc.cpl_products = part_prod;
     if (!o.sym_delta) return acc;
-    Bsr L;
-    {
-      Bsr SU = filter(c, acc, d_iota1.get(), d_iota.get(), 3);
-      L = transpose(c, SU);
-    }
-    return axpby(c, 1.0, &acc, 1.0, &L, 0.0, nullptr);
+    return mirror_upper(acc);
   };
   const bool up = o.sym_delta;
+  // The input-precision copies the update's products made of Z_k and Z_{k+1}
+  // (transposed operands) have no other reader: on one stream their memory
+  // is given back as soon as the products are queued.
+  auto drop_update_copies = [&](const Bsr& Zk, const Bsr& Zn, int pu) {
+    if (pu == LIF_FP64) return;
+    Zk.lp[1] = Bsr::Shadow();
+    Zn.lp[1] = Bsr::Shadow();
+  };
+  // d0 - Z_{k+1}^T (S Mp) - (S Mp)^T Z_k with the products in precision pu,
+  // on one stream, by panels when large (the correction Mp may be that of
+  // some of the problems only: the others' rows of d0 pass unchanged)
+  auto update_pass = [&](const Bsr& d0, const Bsr& Mp, const Bsr& Zk, const Bsr& Zn, bool planned_it, int pu) {
+    const bool lp = pu != LIF_FP64;  // S M's input-precision copy, read by both products
+    Bsr SM = spgemm(c, S, false, Mp, false, o.tau, pu, 1.0, nullptr, 0.0, true, lp);
+    int prow = o.update_panel_rows;
+    if (prow == 0 && !planned_it) {
+      const double upd = (o.sym_delta ? 1.0 : 2.0) * (double)d0.bound() * S.b * S.b * sizeof(double);
+      const double dev = (double)c.device_bytes();
+      if (upd > dev / 16.0) {
+        const int np = (int)std::ceil(upd / (dev / 32.0));
+        prow = (nb + np - 1) / np;
+      }
+    }
+    Bsr d1;
+    if (prow > 0 && prow < nb) {
+      d1 = delta_update_panels(d0, SM, Zk, Zn, prow, pu);
+    } else {
+      Bsr X2 = spgemm(c, SM, true, Zk, false, o.tau, pu, 1.0, nullptr, 0.0, true, false, up);
+      Bsr X1 = spgemm(c, Zn, true, SM, false, o.tau, pu, 1.0, nullptr, 0.0, true, false, up);
+      SM = Bsr();
+      d1 = delta_update_from(d0, X1, X2);
+    }
+    drop_update_copies(Zk, Zn, pu);
+    return d1;
+  };
+  // Reduced delta update (update_prec): per problem, whether its delta
+  // carries the rounding of reduced-precision updates.  When the schedule
+  // moves a problem to FP64, its delta is formed again from the definition,
+  // I - trunc(Z^T trunc(S Z)) (Sec. 2.2; S Z first, as the update forms S M,
+  // and with a symmetric delta only the upper block triangle of the second
+  // product; the problems share no block, so this runs on their rows of Z),
+  // and its norm replaces the last recorded one.
+  const bool red_update = o.update_prec != LIF_FP64 && o.prec != LIF_FP64 && !regular;
+  std::vector<char> stale(nn, 0);
+  std::vector<int> lab_sw(nb), lab_keep(nb);  // host sources of async copies: live to the end
+  std::vector<unsigned char> on_sw(nb);
+  DBuf<int> d_lab_sw, d_lab_keep;
+  DBuf<unsigned char> d_on_sw;
+  auto recompute_delta = [&](const std::vector<char>& sw) {
+    for (int i = 0; i < nb; ++i) {
+      lab_sw[i] = lab_keep[i] = -1;
+      on_sw[i] = 0;
+    }
+    for (int s = 0; s < nn; ++s)
+      for (int i = bt.rlo[s]; i < bt.rhi[s]; ++i) {
+        (sw[s] ? lab_sw : lab_keep)[i] = s;
+        on_sw[i] = sw[s] ? 1 : 0;
+      }
+    if (!d_lab_sw.get()) {
+      d_lab_sw = DBuf<int>(c.pool, nb);
+      d_lab_keep = DBuf<int>(c.pool, nb);
+      d_on_sw = DBuf<unsigned char>(c.pool, nb);
+    }
+    h2d(c, d_lab_sw.get(), lab_sw.data(), nb);
+    h2d(c, d_lab_keep.get(), lab_keep.data(), nb);
+    h2d(c, d_on_sw.get(), on_sw.data(), nb);
+    Bsr dn;
+    {
+      Bsr Zs = filter(c, Z, d_lab_sw.get(), nullptr, 2);
+      Bsr V;
+      {
+        Bsr SZ = spgemm(c, S, false, Zs, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, true);
+        V = spgemm(c, Zs, true, SZ, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, true, false, o.sym_delta);
+      }
+      dn = axpby(c, -1.0, &V, 0.0, nullptr, 1.0, d_on_sw.get());
+    }
+    if (o.sym_delta) dn = mirror_upper(dn);
+    Bsr keep = filter(c, delta, d_lab_keep.get(), nullptr, 2);
+    delta = axpby(c, 1.0, &keep, 1.0, &dn, 0.0, nullptr);
+    const std::vector<double> ss = node_sumsq(c, delta, d_rlo.get(), d_rhi.get(), nn);
+    for (int s = 0; s < nn; ++s) {
+      if (!sw[s]) continue;
+      NodeState& ns = st[s];
+      const double e = std::sqrt(ss[s]);
+      ns.e_cur = ns.e_prev = ns.e = e;
+      if (!ns.norms.empty()) ns.norms.back() = e;
+      stale[s] = 0;
+    }
+  };
   if (!c.spec.sizes.get()) {
     c.spec.sizes = DBuf<int64_t>(c.pool, 2 * Ctx::Spec::kSlots);
     c.spec.overflow = DBuf<int>(c.pool, 1);
@@ -287,6 +376,21 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       h2d(c, d_lab_red.get(), lab_red.data(), nb);
       h2d(c, d_lab_full.get(), lab_full.data(), nb);
     }
+    // problems whose schedule moves to FP64 after reduced updates
+    if (red_update) {
+      std::vector<char> sw(nn, 0);
+      bool any = false;
+      for (int s = 0; s < nn; ++s) {
+        sw[s] = st[s].active && stale[s] && !red[s];
+        any = any || sw[s];
+      }
+      if (any) recompute_delta(sw);
+    }
+    // the delta update's inputs: FP32 (update_prec) for the problems in a
+    // reduced iteration; with some problems in each precision the update
+    // runs in two passes, each on its problems' part of M
+    const int pu_all = (red_update && n_red > 0 && !split) ? o.update_prec : LIF_FP64;
+    const bool upd_split = red_update && split;
     // One iteration.  After the first, every product is sized from the
     // previous iteration's counts (with a margin) instead of reading its
     // counts back; the counts and an overflow flag come back with the norms.
@@ -389,13 +493,12 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
         }
         return spgemm(c, Z, false, q, false, o.tau, p, 1.0, nullptr, 0.0, kHoles);
       };
-      Bsr M;
+      Bsr M, MR, MF;
       if (!split) {
         M = correction(da, prec_it);
       } else {
         // problems above the switch in reduced precision, the others in
         // FP64; Z is block diagonal, so the two parts of M share no row
-        Bsr MR, MF;
         {
           Bsr dR = filter(c, delta, d_lab_red.get(), nullptr, 2);
           MR = correction(dR, o.prec);
@@ -405,12 +508,27 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
           MF = correction(dF, LIF_FP64);
         }
         M = axpby(c, 1.0, &MR, 1.0, &MF, 0.0, nullptr);
+        if (!upd_split) {
+          MR = Bsr();
+          MF = Bsr();
+        }
       }
       // delta_{k+1} = delta_k - Z_{k+1}^T (S M) - (S M)^T Z_k   (M^T S = (S M)^T)
-      if (big) {
+      if (upd_split) {
+        // the reduced problems' update with FP32 inputs, then the others' in
+        // FP64: no problem has blocks in the other pass's products, so each
+        // gets its own update (its rows pass the other sum unchanged)
+        defer.release();
+        Znew = axpby(c, 1.0, &Z, 1.0, &M, 0.0, nullptr);
+        M = Bsr();
+        Bsr d1 = update_pass(delta, MR, Z, Znew, planned, o.update_prec);
+        MR = Bsr();
+        dnew = update_pass(d1, MF, Z, Znew, planned, LIF_FP64);
+        MF = Bsr();
+      } else if (big) {
         // large products fill the GPU by themselves: one stream, and every
         // operand is released as soon as its last reader is queued
-        Bsr SM = spgemm(c, S, false, M, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles);
+        Bsr SM = spgemm(c, S, false, M, false, o.tau, pu_all, 1.0, nullptr, 0.0, kHoles, pu_all != LIF_FP64);
         Znew = axpby(c, 1.0, &Z, 1.0, &M, 0.0, nullptr);
         M = Bsr();
         // panels of the update: as asked, or when its two products (about
@@ -425,14 +543,15 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
           }
         }
         if (prow > 0 && prow < nb) {
-          dnew = delta_update_panels(SM, Z, Znew, prow);
+          dnew = delta_update_panels(delta, SM, Z, Znew, prow, pu_all);
           SM = Bsr();
         } else {
-          Bsr X2 = spgemm(c, SM, true, Z, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles, false, up);
-          Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles, false, up);
+          Bsr X2 = spgemm(c, SM, true, Z, false, o.tau, pu_all, 1.0, nullptr, 0.0, kHoles, false, up);
+          Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau, pu_all, 1.0, nullptr, 0.0, kHoles, false, up);
           SM = Bsr();
           dnew = delta_update(X1, X2);
         }
+        drop_update_copies(Z, Znew, pu_all);
       } else {
       // S M and then (S M)^T Z_k run on the side stream while Z + M and then
       // Z_{k+1}^T (S M) run on the main one; buffers freed meanwhile are
@@ -442,15 +561,15 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       Bsr SM, X2;
       {
         StreamScope on_side(c, side_s);
-        SM = spgemm(c, S, false, M, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles);
+        SM = spgemm(c, S, false, M, false, o.tau, pu_all, 1.0, nullptr, 0.0, kHoles, pu_all != LIF_FP64);
       }
       Znew = axpby(c, 1.0, &Z, 1.0, &M, 0.0, nullptr);
       c.stream_after(main_s, side_s);  // S M is complete
       {
         StreamScope on_side(c, side_s);
-        X2 = spgemm(c, SM, true, Z, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles, false, up);
+        X2 = spgemm(c, SM, true, Z, false, o.tau, pu_all, 1.0, nullptr, 0.0, kHoles, false, up);
       }
-      Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau, LIF_FP64, 1.0, nullptr, 0.0, kHoles, false, up);
+      Bsr X1 = spgemm(c, Znew, true, SM, false, o.tau, pu_all, 1.0, nullptr, 0.0, kHoles, false, up);
       c.stream_after(main_s, side_s);  // (S M)^T Z_k is complete
       M = Bsr();
       SM = Bsr();
@@ -491,6 +610,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
           count_symbolic(c, seen.back()[0], seen.back()[1], nb);
           c.stats.flops += fl;
           if (pprec[i] != LIF_FP64) c.stats.flops_lowp += fl;
+          if (pprec[i] == LIF_MIXED_FP32) c.stats.flops_f32 += fl;
         }
       }
       // margins: output counts move little between iterations, block-product
@@ -533,6 +653,7 @@ void refine_batch(Ctx& c, const Bsr& S, Bsr& Z, Bsr delta, const Batch& bt, cons
       ns.iterations = k;
       ns.norms.push_back(e);
       if (red[s]) ++ns.reduced;
+      stale[s] = red_update && red[s];
       const bool tested = !(o.prec_switch > 0.0 && red[s]);
       const Step d = stop_decision(k, e, ns.e_prev, ns.has_prev, o.m, o.stop, o.tol, &ns.stagnated, tested);
       ns.e_cur = e;

@@ -24,6 +24,7 @@ struct Opts {
   bool sym_delta = false;    // update delta's upper block triangle and mirror it
   int residual_panel_rows = 0;  // block rows of I - Z^T S Z formed at once (0: automatic)
   int update_panel_rows = 0;    // block rows of the delta update formed at once (0: automatic)
+  int update_prec = 0;          // inputs of the delta update in reduced iterations (LIF_FP64 / LIF_MIXED_FP32)
 };
 
 // One node of the split tree: scalar rows [lo, hi), lo a multiple of b.

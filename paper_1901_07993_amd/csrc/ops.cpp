@@ -474,6 +474,7 @@ Bsr spgemm_body(Ctx& c, const Bsr& A, bool ta, const Bsr& B, bool tb, double tau
       const double fl = 2.0 * (double)C.b * C.b * C.b * (double)P;
       c.stats.flops += fl;
       if (prec != LIF_FP64) c.stats.flops_lowp += fl;
+      if (prec == LIF_MIXED_FP32) c.stats.flops_f32 += fl;
     }
   }
   const double dev = (double)c.device_bytes(), pair_bytes = (double)P * sizeof(BlockPair);

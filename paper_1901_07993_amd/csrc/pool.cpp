@@ -212,7 +212,7 @@ void Ctx::timed_end(hipEvent_t e0, Timed what) {
   hipEvent_t e1 = take_event();
   LIF_HIP(hipEventRecord(e1, stream));
   ev_pending.emplace_back(e0, e1);
-  ev_lowp.push_back(0);
+  ev_lowp.push_back(LIF_FP64);
   ev_cat.push_back((char)what);
   if (what == Leaf) ++stats.leaf_launches;
   if (what == Symbolic) ++stats.sym_launches;
@@ -233,7 +233,9 @@ void Ctx::flush_timing() {
       stats.sym_ms += ms;
     } else {
       stats.gemm_ms += ms;
-      if (i < ev_lowp.size() && ev_lowp[i]) stats.gemm_ms_lowp += ms;
+      const int p = i < ev_lowp.size() ? ev_lowp[i] : LIF_FP64;
+      if (p != LIF_FP64) stats.gemm_ms_lowp += ms;
+      if (p == LIF_MIXED_FP32) stats.gemm_ms_f32 += ms;
     }
     ev_free.push_back(pr.first);
     ev_free.push_back(pr.second);

@@ -902,11 +902,12 @@ void launch_numeric(Ctx& c, int prec, bool ta, bool tb, const int64_t* seg, cons
   if (c.timing) {
     LIF_HIP(hipEventRecord(e1, c.stream));
     c.ev_pending.emplace_back(e0, e1);
-    c.ev_lowp.push_back(prec != LIF_FP64 ? 1 : 0);
+    c.ev_lowp.push_back((char)prec);
     c.ev_cat.push_back(Ctx::Gemm);
   }
   c.stats.gemm_launches += 1;
   if (prec != LIF_FP64) c.stats.gemm_launches_lowp += 1;
+  if (prec == LIF_MIXED_FP32) c.stats.gemm_launches_f32 += 1;
 }
 
 }  // namespace lif

@@ -49,7 +49,8 @@ class Opts(ctypes.Structure):
                 ("max_iter", c_int32), ("base_rows", c_int64), ("start", c_int32), ("start_value", c_double),
                 ("checkpoint", c_int32), ("mem_cap_bytes", c_uint64), ("stream", c_void_p), ("timing", c_int32),
                 ("presize", c_int32), ("refinement", c_int32), ("prec_switch", c_double),
-                ("sym_delta", c_int32), ("residual_panel_rows", c_int32), ("update_panel_rows", c_int32)]
+                ("sym_delta", c_int32), ("residual_panel_rows", c_int32), ("update_panel_rows", c_int32),
+                ("update_prec", c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -63,7 +64,9 @@ class Info(ctypes.Structure):
                 ("pair_panels", c_int32), ("flops_leaf_gemm_reduced", c_double),
                 ("seconds_leaf_gemm_reduced", c_double), ("leaf_gemm_launches_reduced", c_int64),
                 ("seconds_leaf_factorization", c_double), ("flops_leaf_factorization", c_double),
-                ("seconds_symbolic", c_double), ("bytes_symbolic", c_double), ("symbolic_launches", c_int64)]
+                ("seconds_symbolic", c_double), ("bytes_symbolic", c_double), ("symbolic_launches", c_int64),
+                ("flops_leaf_gemm_fp32", c_double), ("seconds_leaf_gemm_fp32", c_double),
+                ("leaf_gemm_launches_fp32", c_int64)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "norms"}
@@ -192,7 +195,8 @@ class Factorization:
 
     Keyword options mirror ``lif_opts``: m, tau, prec, stop, tol, max_iter,
     base_rows, start, start_value, checkpoint, mem_cap_bytes, timing, presize,
-    refinement, prec_switch, sym_delta, residual_panel_rows, update_panel_rows.
+    refinement, prec_switch, sym_delta, residual_panel_rows, update_panel_rows,
+    update_prec.
     """
 
     def __init__(self, S, **opts):

@@ -37,7 +37,7 @@ def test_exports_every_declared_symbol():
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lif.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lif_blocks),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lif_blocks),'
                    ' sizeof(lif_opts), sizeof(lif_info), offsetof(lif_opts, stream), offsetof(lif_info, norms),'
                    ' offsetof(lif_blocks, on_device), offsetof(lif_opts, presize),'
                    ' offsetof(lif_info, iterations_redone), offsetof(lif_opts, refinement),'
@@ -45,7 +45,8 @@ def test_struct_layout_matches_header(tmp_path):
                    ' offsetof(lif_info, iterations_reduced), offsetof(lif_info, mem_reserved_bytes),'
                    ' offsetof(lif_opts, sym_delta), offsetof(lif_opts, residual_panel_rows),'
                    ' offsetof(lif_info, pair_panels), offsetof(lif_opts, update_panel_rows),'
-                   ' offsetof(lif_info, leaf_gemm_launches_reduced), offsetof(lif_info, symbolic_launches));'
+                   ' offsetof(lif_info, leaf_gemm_launches_reduced), offsetof(lif_info, symbolic_launches),'
+                   ' offsetof(lif_opts, update_prec), offsetof(lif_info, leaf_gemm_launches_fp32));'
                    ' return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
@@ -56,7 +57,7 @@ def test_struct_layout_matches_header(tmp_path):
             lif.Opts.prec_switch.offset, lif.Info.iterations_reduced.offset, lif.Info.mem_reserved_bytes.offset,
             lif.Opts.sym_delta.offset, lif.Opts.residual_panel_rows.offset, lif.Info.pair_panels.offset,
             lif.Opts.update_panel_rows.offset, lif.Info.leaf_gemm_launches_reduced.offset,
-            lif.Info.symbolic_launches.offset]
+            lif.Info.symbolic_launches.offset, lif.Opts.update_prec.offset, lif.Info.leaf_gemm_launches_fp32.offset]
     assert got == want
 
 
@@ -64,7 +65,7 @@ def test_default_options():
     o = lif.default_opts()
     assert (o.m, o.tau, o.prec, o.stop, o.max_iter, o.base_rows) == (4, 0.0, 0, 0, 100, 4096)
     assert o.tol == 1e-10 and o.timing == 0 and o.presize == 1 and o.refinement == 0 and o.prec_switch == 0.0
-    assert o.sym_delta == 0 and o.residual_panel_rows == 0 and o.update_panel_rows == 0
+    assert o.sym_delta == 0 and o.residual_panel_rows == 0 and o.update_panel_rows == 0 and o.update_prec == 0
 
 
 def _blocks(n, b, rows, cols, vals=None):
@@ -103,7 +104,9 @@ def test_nonzero_padding_rejected():
                                      ("presize", 3), ("presize", -1), ("refinement", 2),
                                      ("refinement", -1), ("prec_switch", -1.0), ("prec_switch", float("nan")),
                                      ("sym_delta", 2), ("residual_panel_rows", -1), ("update_panel_rows", -1),
-                                     ("timing", 3)])
+                                     ("timing", 3), ("update_prec", 2), ("update_prec", -1),
+                                     # a reduced update needs the schedule (and a reduced prec)
+                                     ("update_prec", 1)])
 def test_invalid_options_rejected(opt, val):
     S = _blocks(64, 64, [0], [0], np.eye(64)[None])
     with pytest.raises(lif.LifError) as ei:
@@ -116,3 +119,12 @@ def test_nonlocal_refinement_needs_fp64():
     with pytest.raises(lif.LifError) as ei:
         lif.Factorization(S, refinement=lif.REFINE_NONLOCAL, prec=lif.MIXED_BF16)
     assert ei.value.status == lif.ERR_INVALID and "needs prec" in str(ei.value)
+
+
+@pytest.mark.parametrize("extra", [dict(prec=0, prec_switch=1e-2), dict(prec=2, prec_switch=0.0),
+                                   dict(prec=2, prec_switch=1e-2, checkpoint=1)])
+def test_reduced_update_needs_schedule_without_checkpoints(extra):
+    S = _blocks(64, 64, [0], [0], np.eye(64)[None])
+    with pytest.raises(lif.LifError) as ei:
+        lif.Factorization(S, update_prec=lif.MIXED_FP32, **extra)
+    assert ei.value.status == lif.ERR_INVALID and "update_prec" in str(ei.value)

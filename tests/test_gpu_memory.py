@@ -43,7 +43,8 @@ def _run(S, cap, **opts):
     return info, Z, res
 
 
-@pytest.mark.parametrize("variant", ["fp64", "fp64_sym", "bf16_schedule_sym", "chain_fp64"])
+@pytest.mark.parametrize("variant", ["fp64", "fp64_sym", "bf16_schedule_sym", "chain_fp64",
+                                     "bf16_schedule_sym_f32update"])
 def test_capped_run_matches_uncapped(variant):
     if variant.startswith("chain"):
         # several problems per level, sparse products (a few block products
@@ -54,10 +55,12 @@ def test_capped_run_matches_uncapped(variant):
         c_, e_ = water_cluster(300, 17)
         S = overlap_blocks(c_, e_, 32)             # n = 2100, b = 32, 66 block rows
         opts = dict(tau=1e-6, base_rows=512)
-    if variant in ("fp64_sym", "bf16_schedule_sym"):
+    if "sym" in variant:
         opts["sym_delta"] = 1
-    if variant.startswith("bf16"):
+    if "bf16" in variant:
         opts.update(prec=lif.MIXED_BF16, prec_switch=1e-2)
+    if "f32update" in variant:
+        opts["update_prec"] = lif.MIXED_FP32
     say(f"case memory cap water-300 n={S.n} {variant}")
     i0, Z0, r0 = _run(S, 0, **opts)
     peak = int(i0["mem_peak_bytes"])
@@ -122,7 +125,8 @@ def test_residual_by_panels_irsi_exact():
 
 
 @pytest.mark.parametrize("variant,rows", [("fp64", 1), ("fp64", 7), ("fp64_sym", 5), ("bf16_schedule_sym", 13),
-                                          ("irsi_fp64", 9), ("chain_fp64", 4)])
+                                          ("irsi_fp64", 9), ("chain_fp64", 4),
+                                          ("bf16_schedule_sym_f32update", 13), ("chain_bf16_schedule_f32update", 4)])
 def test_delta_update_by_panels_matches_whole(variant, rows):
     # the delta update formed `rows` block rows at a time (neither product
     # held whole) gives the same factor bit for bit
@@ -135,8 +139,10 @@ def test_delta_update_by_panels_matches_whole(variant, rows):
         opts = dict(tau=1e-6, base_rows=512)
     if "sym" in variant:
         opts["sym_delta"] = 1
-    if variant.startswith("bf16"):
+    if "bf16" in variant:
         opts.update(prec=lif.MIXED_BF16, prec_switch=1e-2)
+    if "f32update" in variant:
+        opts["update_prec"] = lif.MIXED_FP32
     say(f"case delta update by panels of {rows} block rows, {variant}, n={S.n}")
 
     def run(**extra):

@@ -201,3 +201,98 @@ def test_schedule_lif_chain_split_batches(prec):
     assert res <= 2 * res64 + 1e-12
     say(f"  rel diff vs oracle {rel(Z, Zm):.3e}")
     assert rel(Z, Zm) <= S.n * 2.0 ** -24
+
+
+# ----------------------------------------------------------------------------
+# reduced delta update (update_prec): the update products with FP32 inputs in
+# reduced iterations, delta formed again from its definition in FP64 when the
+# schedule moves a problem to FP64.  Against the oracle's same reading: the
+# switch decisions and the final factor within the FP32 accumulation bound.
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("sym", [0, 1])
+def test_reduced_update_irsi_water100(prec, sym):
+    S, _ = config_matrix(0)
+    D = blocks_to_dense(S)
+    lam = float(np.linalg.eigvalsh(D)[-1])
+    say(f"case reduced update irsi water-100 {prec} sym {sym}")
+    with lif.Factorization(dev(S), prec=PREC[prec], prec_switch=1e-2, start=lif.START_INV_SQRT_LMAX,
+                           start_value=lam, update_prec=lif.MIXED_FP32, sym_delta=sym) as f:
+        info = f.refine()
+        Z = blocks_to_dense(f.get_Z())
+        res = f.residual()
+    Zm, im, _ = R.irsi(D, 32, 0.0, start="inv_sqrt_lmax", start_value=lam, prec=prec, prec_switch=1e-2,
+                       sym_delta=bool(sym), update_prec="fp32")
+    say(f"  gpu iterations {info['iterations_top']} reduced {info['iterations_reduced']}, oracle "
+        f"{im.iterations} reduced {sum(im.reduced)}; norms {info['norms']} / {im.norms}")
+    assert info["iterations_reduced"] == sum(im.reduced)
+    assert abs(info["iterations_top"] - im.iterations) <= 1
+    # the recorded norms (the one before the switch replaced by the
+    # recomputed delta's) agree down to the FP64 floor, within the FP32
+    # accumulation bound of the products that formed them: n 2^-24 times the
+    # size of the correction, which the previous norm bounds (the last
+    # reduced one is mostly that rounding: measured 5e-6 against 8e-6)
+    prev = float(np.linalg.norm(np.eye(S.n) - D / lam))
+    for g, o in zip(info["norms"], im.norms):
+        if o > 1e-10:
+            assert abs(g - o) <= 1e-6 * o + S.n * 2.0 ** -24 * prev
+        prev = o
+    # the refinement wins the accuracy back: the FP64 floor, tracked exactly
+    assert res <= 1e-12 and abs(res - info["delta_tracked"]) <= 1e-12
+    say(f"  rel diff vs oracle {rel(Z, Zm):.3e}")
+    assert rel(Z, Zm) <= S.n * 2.0 ** -24
+
+
+@pytest.mark.parametrize("sym", [0, 1])
+def test_reduced_update_lif_chain_split_batches(sym):
+    # several problems per level, split between the precisions in some
+    # iterations: the update then runs in two passes
+    S, cfg = config_matrix(1, count=150)   # n = 3000 chain, b = 64
+    D = blocks_to_dense(S)
+    tau = 1e-10
+    say(f"case reduced update lif chain n={S.n} bf16 sym {sym}")
+    with lif.Factorization(dev(S), tau=tau, base_rows=512, sym_delta=sym) as f:
+        f.localized()
+        res64 = f.residual()
+    with lif.Factorization(dev(S), tau=tau, base_rows=512, prec=lif.MIXED_BF16, prec_switch=1e-2,
+                           update_prec=lif.MIXED_FP32, sym_delta=sym) as f:
+        info = f.localized()
+        Z = blocks_to_dense(f.get_Z())
+        res = f.residual()
+    Zm, plan = R.lif(D, 64, tau, base_rows=512, prec="bf16", prec_switch=1e-2, sym_delta=bool(sym),
+                     update_prec="fp32")
+    nodes = []
+
+    def walk(nd):
+        if nd.children:
+            nodes.append(nd.info)
+            walk(nd.children[0])
+            walk(nd.children[1])
+
+    walk(plan)
+    red = sum(sum(i.reduced) for i in nodes)
+    say(f"  gpu total {info['iterations_total']} reduced {info['iterations_reduced']}, oracle total "
+        f"{sum(i.iterations for i in nodes)} reduced {red}; residual {res:.3e} (fp64 {res64:.3e})")
+    assert info["iterations_reduced"] == red
+    assert abs(info["iterations_total"] - sum(i.iterations for i in nodes)) <= len(nodes)
+    assert res <= 2 * res64 + 1e-12
+    say(f"  rel diff vs oracle {rel(Z, Zm):.3e}")
+    assert rel(Z, Zm) <= S.n * 2.0 ** -24
+
+
+def test_reduced_update_lif_water150():
+    c_, e_ = water_cluster(150, 7)
+    S = overlap_blocks(c_, e_, 64)
+    D = blocks_to_dense(S)
+    say("case reduced update lif water-150 bf16 sym")
+    with lif.Factorization(dev(S), base_rows=320, prec=lif.MIXED_BF16, prec_switch=1e-2,
+                           update_prec=lif.MIXED_FP32, sym_delta=1) as f:
+        info = f.localized()
+        Z = blocks_to_dense(f.get_Z())
+        res = f.residual()
+    Zm, _ = R.lif(D, 64, 0.0, base_rows=320, prec="bf16", prec_switch=1e-2, sym_delta=True, update_prec="fp32")
+    say(f"  residual {res:.3e}, reduced {info['iterations_reduced']}, rel diff vs oracle {rel(Z, Zm):.3e}")
+    assert info["iterations_reduced"] > 0
+    assert res <= 1e-12
+    assert rel(Z, Zm) <= S.n * 2.0 ** -24
