@@ -1,8 +1,10 @@
 """Summaries of rocprofv3 CSV output for the committed profiles.
 
-    python -m paper_1901_07993_amd.prof_summary stats TRACE.csv OUT.md --title T --cmd C
+    python -m paper_1901_07993_amd.prof_summary stats TRACE.csv OUT.md --title T --cmd C [--group P ...]
         per-kernel totals of the last factorization in a kernel trace (a
-        factorization starts at its k_chol_scatter launch), plus the span
+        factorization starts at its k_chol_scatter launch), plus the span;
+        each --group P adds the totals of all kernels whose names start
+        with P (e.g. every variant of the numeric kernel)
     python -m paper_1901_07993_amd.prof_summary traffic FETCH.csv WRITE.csv OUT.json \
             --kernel k_numeric_f64 --copy-mib N --cmd C [--hash H]
         HBM bytes per dispatch of one kernel from FETCH_SIZE / WRITE_SIZE
@@ -26,7 +28,7 @@ def _short(name: str) -> str:
     return name.replace("lif::(anonymous namespace)::", "").split("(")[0].replace("void ", "")
 
 
-def stats(trace: str, out: str, title: str, cmd: str) -> None:
+def stats(trace: str, out: str, title: str, cmd: str, groups=()) -> None:
     rows = list(csv.DictReader(open(trace)))
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
     starts = [i for i, r in enumerate(rows) if "k_chol_scatter" in r["Kernel_Name"]]
@@ -48,6 +50,12 @@ def stats(trace: str, out: str, title: str, cmd: str) -> None:
         f.write("| kernel | calls | total ms | avg us | % of summed |\n|---|---:|---:|---:|---:|\n")
         for n, (c, d) in sorted(agg.items(), key=lambda x: -x[1][1]):
             f.write(f"| `{n}` | {c} | {d / 1e6:.3f} | {d / c / 1e3:.1f} | {100 * d / busy:.1f} |\n")
+        for g in groups:
+            c = sum(v[0] for n, v in agg.items() if n.startswith(g))
+            d = sum(v[1] for n, v in agg.items() if n.startswith(g))
+            if c:
+                f.write(f"\nAll `{g}*` kernels together: {c} calls, {d / 1e6:.3f} ms, average "
+                        f"{d / c / 1e3:.1f} us per call, {100 * d / busy:.1f} % of the summed time.\n")
 
 
 def _counter(path: str, name: str):
@@ -173,6 +181,7 @@ def main() -> None:
     s.add_argument("out")
     s.add_argument("--title", required=True)
     s.add_argument("--cmd", required=True)
+    s.add_argument("--group", action="append", default=[])
     t = sub.add_parser("traffic")
     t.add_argument("fetch")
     t.add_argument("write")
@@ -200,7 +209,7 @@ def main() -> None:
     m.add_argument("--flops-counter", default="MfmaFlopsF64")
     a = ap.parse_args()
     if a.what == "stats":
-        stats(a.trace, a.out, a.title, a.cmd)
+        stats(a.trace, a.out, a.title, a.cmd, a.group)
     elif a.what == "traffic":
         traffic(a.fetch, a.write, a.out, a.kernel, a.copy_mib, a.cmd, a.hash)
     elif a.what == "hbm":
