@@ -239,6 +239,62 @@ def water_comparison(lif, count, which=("fp64_sym", "bf16_schedule_sym", "bf16_s
     return out
 
 
+def fit_sweep(lif, counts, variant):
+    """The largest water cluster that one GPU factorizes (the survey's
+    largest single-GPU case: tau = 1e-8, b = 64, LIF to 4096-row leaves,
+    by default FP32 corrections under the schedule): one factorization per
+    size, in increasing order, until one does not fit in the device memory
+    (reported with its error).  Per size: seconds (first factorization on
+    its handle, so including the memory pool's hipMalloc calls), memory
+    peak, blocks of Z, node iterations, the residual and each precision's
+    leaf-GEMM rate; the untruncated residual after it (its own error, if
+    it does not fit, does not end the sweep)."""
+    import torch
+    from gen import config_matrix
+    pname, sw, sym, upd = WATER_VARIANTS[variant]
+    rows = []
+    for count in counts:
+        print(f"# generating water-{count}", file=sys.stderr, flush=True)
+        S, cfg = config_matrix(2, count=count)
+        Sd = type("DevBlocks", (), dict(n=S.n, b=S.b, brow=torch.from_numpy(S.brow).cuda(),
+                                        bcol=torch.from_numpy(S.bcol).cuda(), vals=torch.from_numpy(S.vals).cuda()))
+        row = {"count": count, "n": S.n, "nnzb_S": int(S.nnzb)}
+        del S
+        f = lif.Factorization(Sd, tau=cfg["tau"], base_rows=4096, prec=getattr(lif, pname), prec_switch=sw,
+                              sym_delta=sym, update_prec=getattr(lif, upd), timing=1)
+        try:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = f.localized()
+            torch.cuda.synchronize()
+            row.update(fits=True, s_per_factorization=time.perf_counter() - t0,
+                       mem_peak_gib=info["mem_peak_bytes"] / 2 ** 30, nnzb_Z=info["nnzb_Z"],
+                       iterations_total=info["iterations_total"], iterations_reduced=info["iterations_reduced"])
+            fl, sec = info["flops_leaf_gemm"], info["seconds_leaf_gemm"]
+            flr, secr = info["flops_leaf_gemm_reduced"], info["seconds_leaf_gemm_reduced"]
+            if sec - secr > 0:
+                row["leaf_gemm_fp64_tflops"] = (fl - flr) / (sec - secr) / 1e12
+            if secr > 0:
+                row[f"leaf_gemm_{pname.split('_')[-1].lower()}_tflops"] = flr / secr / 1e12
+                row["leaf_gemm_reduced_frac_of_peak"] = flr / secr / 1e12 / PEAK_TFLOPS[pname]
+        except lif.LifError as e:
+            row.update(fits=False, error=str(e))
+        if row["fits"]:
+            try:
+                row["residual"] = f.residual()
+            except lif.LifError as e:
+                row["residual_error"] = str(e)
+        f.close()
+        del Sd
+        torch.cuda.empty_cache()
+        rows.append(row)
+        print(f"# water-{count}: {row}", file=sys.stderr, flush=True)
+        if not row["fits"]:
+            break
+    return {"fit_sweep": rows, "variant": variant, "device_memory_gib":
+            torch.cuda.get_device_properties(0).total_memory / 2 ** 30, "data": "synthetic"}
+
+
 def cpl_sweep(counts, steps):
     """Critical-path task counts (the one-GPU shadow of Sec. 3) and times of
     the four methods on chains of the given lengths."""
@@ -283,11 +339,17 @@ def main():
                     help="molecules of that water cluster (20000 = the n = 140000 workload)")
     ap.add_argument("--water-only", type=str, default="",
                     help="comma-separated subset of fp64,fp64_sym,fp32_schedule,bf16_schedule,"
-                         "fp32_schedule_sym,bf16_schedule_sym: run only the water "
+                         "fp32_schedule_sym,bf16_schedule_sym,bf16_schedule_sym_f32update,"
+                         "fp32_schedule_sym_f32update: run only the water "
                          "comparison with these (one JSON line) and exit")
     ap.add_argument("--cpl-sweep", type=str, default="",
                     help="comma-separated chain lengths: print critical-path task counts and times of "
                          "LIF, RINCH, IRSI and the regular-form recursion per size (one JSON line) and exit")
+    ap.add_argument("--fit-sweep", type=str, default="",
+                    help="comma-separated water-cluster sizes (molecules), increasing: factorize each once "
+                         "until one does not fit in the device memory (one JSON line) and exit")
+    ap.add_argument("--fit-variant", type=str, default="fp32_schedule_sym",
+                    help="precision variant of --fit-sweep (a name of the water comparison)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device to device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -318,6 +380,12 @@ def main():
         assert torch.cuda.is_available(), "bench.py needs a GPU"
         print(json.dumps({"water": water_comparison(lifmod, args.water_count, tuple(args.water_only.split(",")),
                                                     z_diff=not args.no_residual, residuals=not args.no_residual)}),
+              flush=True)
+        return
+    if args.fit_sweep:
+        from paper_1901_07993_amd import lif as lifmod
+        lifmod.load()
+        print(json.dumps(fit_sweep(lifmod, [int(x) for x in args.fit_sweep.split(",")], args.fit_variant)),
               flush=True)
         return
     if args.cpl_sweep:

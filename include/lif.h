@@ -118,10 +118,11 @@ typedef struct {
   int32_t sym_delta;      /* 1: delta (symmetric in exact arithmetic) is updated on its upper block triangle
                            * only, the update's two products forming just those blocks, and the strictly
                            * upper part is mirrored below (localized refinement); 0: the full update */
-  int32_t residual_panel_rows; /* lif_residual forms I - Z^T S Z this many block rows at a time (>= 0;
-                           * 0: panels of at most min(8 GiB, 1/16 of the device memory the
-                           * handle may use) of dense block rows, the whole matrix when it
-                           * fits), bounding its memory by Z, S Z and one panel */
+  int32_t residual_panel_rows; /* lif_residual forms I - Z^T (S Z) this many block columns at a time
+                           * (>= 0; 0: panels of at most min(8 GiB, 1/16 of the device memory the
+                           * handle may use) of dense block columns, the whole matrix when it
+                           * fits), each panel from S Z's same columns, bounding its memory by Z
+                           * and one panel of S Z and of the result */
   int32_t update_panel_rows; /* localized refinement on large problems: the two products of the delta
                            * update and their difference are formed this many block rows at a time
                            * (>= 0; 0: automatic -- panels only on iterations whose buffers fill a
@@ -239,13 +240,13 @@ lif_status lif_get_Z(lif_handle h, int64_t* nnzb, int32_t* brow, int32_t* bcol, 
 
 /* ||I - Z^T S Z||_F of the handle's Z in FP64 with no truncation (Table 1's
  * error measure), against the truncated S the handle factorized; formed by
- * panels of block rows (opts.residual_panel_rows), never stored whole. */
+ * panels of block columns (opts.residual_panel_rows), never stored whole. */
 lif_status lif_residual(lif_handle h, double* out);
 
 /* ||I - Z^T S Z||_F of the handle's Z against another S of the same n and b
  * (Table 1's error measure; for example the matrix before the block
  * truncation the handle applied at creation, since the table does not say
- * which S its residuals use), FP64, untruncated, by panels of block rows as
+ * which S its residuals use), FP64, untruncated, by panels of block columns as
  * lif_residual.  S may be host or device blocks (device blocks are read in
  * place, not copied); its pattern need not be symmetric.  LIF_ERR_STATE
  * before a factorization. */

@@ -1162,15 +1162,18 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck)
 
 double residual(Ctx& c, const Bsr& S, const Bsr& Z, int panel_rows) {
   // R = I - Z^T (S Z), untruncated, with ||R||_F^2 summed over panels of
-  // R's block rows: rows [p0, p1) of R take only Z's block columns in
-  // [p0, p1).  Automatic panels: one, unless R could take more than
+  // R's block columns: columns [p0, p1) of R are Z^T (S Z_p), Z_p the block
+  // columns of Z in [p0, p1), so neither S Z nor R is ever held whole (each
+  // block is the whole product's: the same block products in the same
+  // order).  Automatic panels: one, unless R could take more than
   // min(8 GiB, 1/16 of the device memory the handle may use).
   const double kPanelBytes = std::min(8.0 * double(1u << 30), (double)c.device_bytes() / 16.0);
   const int nb = S.nb;
-  const double row_bytes = (double)nb * S.b * S.b * sizeof(double);  // a dense block row of R
+  const double row_bytes = (double)nb * S.b * S.b * sizeof(double);  // a dense block column of R
   const int rows = panel_rows > 0 ? std::min(panel_rows, nb)
                                   : (int)std::max(1.0, std::min((double)nb, std::floor(kPanelBytes / row_bytes)));
-  Bsr SZ = spgemm(c, S, false, Z, false, 0.0);
+  Bsr SZ;
+  if (rows >= nb) SZ = spgemm(c, S, false, Z, false, 0.0);
   // host sources of asynchronous copies, rewritten only after the
   // read-back that ends each panel
   std::vector<int> zeros(nb, 0), clab(nb), lo(1), hi(1);
@@ -1179,12 +1182,12 @@ double residual(Ctx& c, const Bsr& S, const Bsr& Z, int panel_rows) {
   DBuf<unsigned char> d_on(c.pool, nb);
   h2d(c, d_zeros.get(), zeros.data(), nb);
   double ss = 0.0;
+  lo[0] = 0;
+  hi[0] = nb;
+  h2d(c, d_lo.get(), lo.data(), 1);
+  h2d(c, d_hi.get(), hi.data(), 1);
   for (int p0 = 0; p0 < nb; p0 += rows) {
     const int p1 = std::min(nb, p0 + rows);
-    lo[0] = p0;
-    hi[0] = p1;
-    h2d(c, d_lo.get(), lo.data(), 1);
-    h2d(c, d_hi.get(), hi.data(), 1);
     Bsr R;
     if (rows >= nb) {
       Bsr ZSZ = spgemm(c, Z, true, SZ, false, 0.0);
@@ -1196,9 +1199,16 @@ double residual(Ctx& c, const Bsr& S, const Bsr& Z, int panel_rows) {
       }
       h2d(c, d_clab.get(), clab.data(), nb);
       h2d(c, d_on.get(), on.data(), nb);
-      Bsr Zp = filter(c, Z, d_zeros.get(), d_clab.get(), 0);
-      Bsr P = spgemm(c, Zp, true, SZ, false, 0.0);
-      Zp = Bsr();
+      Bsr P;
+      {
+        Bsr SZp;
+        {
+          Bsr Zp = filter(c, Z, d_zeros.get(), d_clab.get(), 0);
+          SZp = spgemm(c, S, false, Zp, false, 0.0);
+        }
+        P = spgemm(c, Z, true, SZp, false, 0.0);
+      }
+      // the identity's blocks (j, j) with j in the panel
       R = axpby(c, -1.0, &P, 0.0, nullptr, 1.0, d_on.get());
     }
     ss += node_sumsq(c, R, d_lo.get(), d_hi.get(), 1)[0];

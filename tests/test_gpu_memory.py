@@ -6,7 +6,7 @@ GPU's memory):
 * products written as kept blocks only, in chunks, each chunk's store cut to
   its kept blocks (the untruncated product is never held), their pair lists
   built one panel of block rows at a time;
-* the true residual formed by panels of block rows.
+* the true residual formed by panels of block columns.
 
 None of them changes a value: a capped factorization gives Z bit for bit
 and the same iteration counts as an uncapped one (FP64, symmetric delta
@@ -99,7 +99,7 @@ def test_capped_run_matches_uncapped(variant):
 def test_residual_by_panels(rows):
     c_, e_ = water_cluster(300, 17)
     S = overlap_blocks(c_, e_, 32)                 # 66 block rows: panels of 1, 5 (ragged), 21, all
-    say(f"case residual panels of {rows} block rows")
+    say(f"case residual panels of {rows} block columns")
     with lif.Factorization(dev(S), tau=1e-6, base_rows=512) as f:
         f.localized()
         whole = f.residual()
