@@ -775,7 +775,12 @@ void launch_numeric_t(Ctx& c, dim3 grid, const int64_t* seg, const BlockPair* pa
                       BlkOut Cp, double* norms, const Epilogue& epi) {
   const dim3 block(TileCfg<B>::THREADS);
   const int64_t nnzc = grid.x;
-  if (kF64Group > 1 && nnzc >= kF64GroupMin) {
+  // op(A) = A^T keeps one output block per workgroup: its A fragments come
+  // straight from memory, and with two outputs' accumulators beside them
+  // the grouped form leaves one workgroup per SIMD (measured: 4.6 % more
+  // time for the BF16 schedule on water-10 000, where these products are
+  // most of the FP64 work; FP64 alone unchanged)
+  if (kF64Group > 1 && nnzc >= kF64GroupMin && !TA) {
     const dim3 ggrid((unsigned)((nnzc + kF64Group - 1) / kF64Group));
     if (epi.dsrc)
       hipLaunchKernelGGL((k_numeric_f64_group<B, TA, TB, true, kF64Group>), ggrid, block, 0, c.stream, seg, pairs,
