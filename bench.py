@@ -145,16 +145,21 @@ WATER_VARIANTS = {
     "bf16_schedule_sym_f32update": ("MIXED_BF16", 1e-2, 1, "MIXED_FP32"),
     "fp32_schedule_sym_f32update": ("MIXED_FP32", 1e-2, 1, "MIXED_FP32"),
 }
+# the same with IRSI instead of LIF (the method of the small water workload,
+# from Z_0 = I / sqrt(beta), beta the Gershgorin bound): "irsi_" + a name above
+for _k, _v in list(WATER_VARIANTS.items()):
+    WATER_VARIANTS["irsi_" + _k] = _v
 PEAK_TFLOPS = {"FP64": 78.6, "MIXED_FP32": 157.3, "MIXED_BF16": 2500.0}
 
 
-def water_comparison(lif, count, which=("fp64_sym", "bf16_schedule_sym", "bf16_schedule_sym_f32update"),
+def water_comparison(lif, count, which=("fp64_sym", "bf16_schedule_sym", "irsi_fp64_sym", "irsi_bf16_schedule_sym"),
                      z_diff=True, residuals=True):
     """FP64 against the scheduled reduced-precision corrections on a water
     cluster (tau = 1e-8, b = 64, LIF to 4096-row leaves, paper stop): the
     metric's comparison, on the compute-bound products where reduced
     precision pays.  One handle holds S and its memory pool for all runs
-    (lif_set_opts between them): one untimed warm-up, then one timed
+    (lif_set_opts between them): one untimed warm-up per method (LIF, and
+    IRSI from c = 1 / sqrt(beta) for the "irsi_" variants), then one timed
     factorization per variant.  Reported per run: seconds, the untruncated
     residual against the truncated S that was factorized and against S
     before that truncation (Table 1 leaves open which one it used), node
@@ -168,25 +173,41 @@ def water_comparison(lif, count, which=("fp64_sym", "bf16_schedule_sym", "bf16_s
     Sd = type("DevBlocks", (), dict(n=S.n, b=S.b, brow=torch.from_numpy(S.brow).cuda(),
                                     bcol=torch.from_numpy(S.bcol).cuda(), vals=torch.from_numpy(S.vals).cuda()))
     out = {"workload": f"water-{count}: {count} molecules x 7 s-Gaussians, n={S.n}, b=64, tau={cfg['tau']}, "
-                       f"LIF to 4096-row leaves, m=4, paper stop", "n": S.n, "nnzb_S": int(S.nnzb),
+                       f"LIF to 4096-row leaves, and IRSI from I / sqrt(beta) (\"irsi_\" variants), m=4, "
+                       f"paper stop", "n": S.n, "nnzb_S": int(S.nnzb),
            "tau_floor_note": "with per-block truncation at tau = 1e-8 the residual settles near 1e-5 (the floor); "
                              "the 1e-10 target is the tau = 0 runs' gate",
            "device_memory_gib": torch.cuda.get_device_properties(0).total_memory / 2 ** 30}
     first = WATER_VARIANTS[which[0]]
     f = lif.Factorization(Sd, tau=cfg["tau"], base_rows=4096, prec=getattr(lif, first[0]), prec_switch=first[1],
-                          sym_delta=first[2], update_prec=getattr(lif, first[3]), timing=1)
-    f.localized()
+                          sym_delta=first[2], update_prec=getattr(lif, first[3]), start=lif.START_INV_SQRT_GERSH,
+                          timing=1)
+    warm = set()
+    for name in which:
+        irsi = name.startswith("irsi_")
+        if irsi in warm:
+            continue
+        warm.add(irsi)
+        pname, sw, sym, upd = WATER_VARIANTS[name]
+        f.set_opts(prec=getattr(lif, pname), prec_switch=sw, sym_delta=sym, update_prec=getattr(lif, upd),
+                   start=lif.START_INV_SQRT_GERSH)
+        try:
+            f.refine() if irsi else f.localized()
+        except lif.LifError as e:
+            print(f"# water-{count} warm-up of {name}: {e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     print(f"# water-{count} warm-up done", file=sys.stderr, flush=True)
-    t64 = {}
-    Zref = None
+    t64 = {}   # FP64 seconds by (method, symmetric delta)
+    Zref = {}  # FP64 factor by method
     for name in which:
         pname, sw, sym, upd = WATER_VARIANTS[name]
-        f.set_opts(prec=getattr(lif, pname), prec_switch=sw, sym_delta=sym, update_prec=getattr(lif, upd))
+        irsi = name.startswith("irsi_")
+        f.set_opts(prec=getattr(lif, pname), prec_switch=sw, sym_delta=sym, update_prec=getattr(lif, upd),
+                   start=lif.START_INV_SQRT_GERSH)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
-            info = f.localized()
+            info = f.refine() if irsi else f.localized()
         except lif.LifError as e:
             out[name] = {"error": str(e)}
             print(f"# water-{count} {name}: {e}", file=sys.stderr, flush=True)
@@ -199,6 +220,7 @@ def water_comparison(lif, count, which=("fp64_sym", "bf16_schedule_sym", "bf16_s
              "iterations_total": info["iterations_total"], "iterations_reduced": info["iterations_reduced"],
              "iterations_redone": info["iterations_redone"], "nnzb_Z": info["nnzb_Z"],
              "mem_peak_gib": info["mem_peak_bytes"] / 2 ** 30, "sym_delta": sym,
+             "method": "irsi" if irsi else "lif",
              "products_compacted": info["products_compacted"], "pair_panels": info["pair_panels"]}
         fl, sec = info["flops_leaf_gemm"], info["seconds_leaf_gemm"]
         flr, secr = info["flops_leaf_gemm_reduced"], info["seconds_leaf_gemm_reduced"]
@@ -220,16 +242,16 @@ def water_comparison(lif, count, which=("fp64_sym", "bf16_schedule_sym", "bf16_s
                 r[f"leaf_gemm_{tag}_frac_of_peak"] = r[f"leaf_gemm_{tag}_tflops"] / PEAK_TFLOPS[peak]
                 r[f"leaf_gemm_{tag}_launches"] = p_n
         if pname == "FP64":
-            t64[sym] = s
-            if z_diff and Zref is None:
-                Zref = f.get_Z()
+            t64[(irsi, sym)] = s
+            if z_diff and irsi not in Zref:
+                Zref[irsi] = f.get_Z()
         else:
-            if sym in t64:
-                r["speedup_vs_fp64_same_update"] = t64[sym] / s
-            if 0 in t64:
-                r["speedup_vs_fp64"] = t64[0] / s
-            if z_diff and Zref is not None:
-                r["rel_diff_vs_fp64_Z"] = rel_diff(f.get_Z(), Zref)
+            if (irsi, sym) in t64:
+                r["speedup_vs_fp64_same_update"] = t64[(irsi, sym)] / s
+            if (irsi, 0) in t64:
+                r["speedup_vs_fp64"] = t64[(irsi, 0)] / s
+            if z_diff and irsi in Zref:
+                r["rel_diff_vs_fp64_Z"] = rel_diff(f.get_Z(), Zref[irsi])
         out[name] = r
         print(f"# water-{count} {name}: {s:.2f} s, residual {res} (untruncated S {res_u})",
               file=sys.stderr, flush=True)
