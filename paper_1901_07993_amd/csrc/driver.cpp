@@ -1162,11 +1162,12 @@ Bsr run_lif(Ctx& c, const Bsr& S, const Opts& o, RunInfo& info, Checkpoints* ck)
 
 double residual(Ctx& c, const Bsr& S, const Bsr& Z, int panel_rows) {
   // R = I - Z^T (S Z), untruncated, with ||R||_F^2 summed over panels of
-  // R's block columns: columns [p0, p1) of R are Z^T (S Z_p), Z_p the block
-  // columns of Z in [p0, p1), so neither S Z nor R is ever held whole (each
-  // block is the whole product's: the same block products in the same
-  // order).  Automatic panels: one, unless R could take more than
-  // min(8 GiB, 1/16 of the device memory the handle may use).
+  // R's block columns: columns [p0, p1) of R, taken as the rows of their
+  // transpose (S Z_p)^T Z, Z_p the block columns of Z in [p0, p1), so neither
+  // S Z nor R is ever held whole and the transposed operand is the panel's
+  // S Z_p, not Z (a transpose has the Frobenius norm of its matrix).
+  // Automatic panels: one, unless R could take more than min(8 GiB, 1/16 of
+  // the device memory the handle may use).
   const double kPanelBytes = std::min(8.0 * double(1u << 30), (double)c.device_bytes() / 16.0);
   const int nb = S.nb;
   const double row_bytes = (double)nb * S.b * S.b * sizeof(double);  // a dense block column of R
@@ -1206,7 +1207,7 @@ double residual(Ctx& c, const Bsr& S, const Bsr& Z, int panel_rows) {
           Bsr Zp = filter(c, Z, d_zeros.get(), d_clab.get(), 0);
           SZp = spgemm(c, S, false, Zp, false, 0.0);
         }
-        P = spgemm(c, Z, true, SZp, false, 0.0);
+        P = spgemm(c, SZp, true, Z, false, 0.0);
       }
       // the identity's blocks (j, j) with j in the panel
       R = axpby(c, -1.0, &P, 0.0, nullptr, 1.0, d_on.get());
