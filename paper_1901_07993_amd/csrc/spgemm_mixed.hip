@@ -7,9 +7,12 @@
 // through FP32, both rounded to nearest even), made once per matrix by
 // k_make_shadow or written by the product that created the matrix.  The
 // copies hold op(A)'s blocks row-major and op(B)'s blocks transposed, so
-// that every MFMA fragment below is one 16-byte global load of consecutive
-// k (no LDS staging): a quarter of the FP64 operand bytes for BF16, half for
-// FP32.  The products of one output block accumulate in FP32 MFMA
+// that every MFMA fragment below is one 16-byte read of consecutive k: a
+// quarter of the FP64 operand bytes for BF16, half for FP32.  The FP32
+// product stages both tiles of a block product in LDS once per workgroup
+// (each fragment row is read by two of its four waves) and loads the next
+// pair's tiles while it multiplies; the BF16 product does the same with a
+// merge step's A tile and the B tiles of the output blocks taking it.  The products of one output block accumulate in FP32 MFMA
 // registers; the block is written back as FP64 with its FP64 Frobenius norm
 // (and, when asked, as the transposed reduced-precision copy the next
 // product reads).
@@ -45,9 +48,12 @@ __device__ inline int64_t xcd_remap_m(int64_t wg, int64_t total) {
   return x * q + (x < r ? x : r) + l;
 }
 
-// output blocks per workgroup of the BF16 product (1: one block per workgroup)
+// output blocks per workgroup of the BF16 product (1: one block per
+// workgroup, fragments straight from global memory).  With the tiles staged
+// in LDS, water-10 000's BF16 part ran at 323 / 329 / 292 / 164 TFLOP/s for
+// 1, 2, 4 and 8 (8 leaves one workgroup per SIMD).
 #ifndef LIF_BF16_GROUP
-#define LIF_BF16_GROUP 4
+#define LIF_BF16_GROUP 2
 #endif
 constexpr int kBf16Group = LIF_BF16_GROUP;
 
@@ -238,46 +244,88 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_bf16_group(const
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[g][a][b] = v4f{0.f, 0.f, 0.f, 0.f};
   }
-  for (;;) {
-    uintptr_t amin = ~uintptr_t(0);
+  // one merge step's A tile and the B tiles of the lists taking it staged in
+  // LDS once per workgroup (padded rows: the 16 rows a fragment read touches
+  // fall in different banks); the next step's tiles are loaded into
+  // registers while the current one is multiplied
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  constexpr int LDP = B + 8;                                  // bf16 per padded row
+  constexpr int NV = B * B / 8 / MixCfg<B>::THREADS;          // 16-byte pieces per thread per tile
+  __shared__ __attribute__((aligned(16))) unsigned short As[B * LDP];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[G][B * LDP];
+  v4u sa[NV], sb[G][NV];
+  uintptr_t amin = 0, anext = 0;
+  bool take[G], tnext[G];
+  // the next merge step from the lists' heads: the smallest A block and the
+  // lists whose head has it (uniform over the workgroup)
+  auto plan = [&](uintptr_t& am, bool (&tk)[G]) {
+    am = ~uintptr_t(0);
 #pragma unroll
     for (int g = 0; g < G; ++g)
-      if (pp[g] < pe[g]) amin = min(amin, reinterpret_cast<uintptr_t>(pairs[pp[g]].a));
-    if (amin == ~uintptr_t(0)) break;
-    const unsigned short* a = reinterpret_cast<const unsigned short*>(amin);
+      if (pp[g] < pe[g]) am = min(am, reinterpret_cast<uintptr_t>(pairs[pp[g]].a));
+#pragma unroll
+    for (int g = 0; g < G; ++g) tk[g] = pp[g] < pe[g] && reinterpret_cast<uintptr_t>(pairs[pp[g]].a) == am;
+    return am != ~uintptr_t(0);
+  };
+  auto gload = [&](uintptr_t am, const bool (&tk)[G]) {
+    const v4u* a = reinterpret_cast<const v4u*>(am);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sa[v] = *gptr(a + threadIdx.x + v * MixCfg<B>::THREADS);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (tk[g]) {
+        const v4u* bt = reinterpret_cast<const v4u*>(pairs[pp[g]].b);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sb[g][v] = *gptr(bt + threadIdx.x + v * MixCfg<B>::THREADS);
+      }
+  };
+  bool have = plan(amin, take);
+  if (have) gload(amin, take);
+  while (have) {
+    __syncthreads();  // the previous step's fragment reads are done
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int q = 8 * ((int)threadIdx.x + v * MixCfg<B>::THREADS);
+      *reinterpret_cast<v4u*>(&As[(q / B) * LDP + q % B]) = sa[v];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        if (take[g]) *reinterpret_cast<v4u*>(&Bs[g][(q / B) * LDP + q % B]) = sb[g][v];
+    }
+    __syncthreads();
     v8bf af[KS][2];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int t = 0; t < 2; ++t)
-        af[ks][t] = *gptr(reinterpret_cast<const v8bf*>(a + (rb + 16 * t + l16) * B + 32 * ks + 8 * kq));
-    // the B fragments of every list taking this A block, then their MFMAs
-    v8bf bf[G][KS][2];
-    bool take[G];
+        af[ks][t] = *reinterpret_cast<const v8bf*>(&As[(rb + 16 * t + l16) * LDP + 32 * ks + 8 * kq]);
+    // the lists' heads advance before the next step is planned; take[]
+    // still names this step's lists
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      take[g] = pp[g] < pe[g] && reinterpret_cast<uintptr_t>(pairs[pp[g]].a) == amin;
+    for (int g = 0; g < G; ++g)
+      if (take[g]) ++pp[g];
+    const bool hn = plan(anext, tnext);
+    if (hn) gload(anext, tnext);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
       if (take[g]) {
-        const unsigned short* bt = reinterpret_cast<const unsigned short*>(pairs[pp[g]].b);
+        v8bf bf[KS][2];
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
           for (int t = 0; t < 2; ++t)
-            bf[g][ks][t] = *gptr(reinterpret_cast<const v8bf*>(bt + (cb + 16 * t + l16) * B + 32 * ks + 8 * kq));
-      }
-    }
-#pragma unroll
-    for (int g = 0; g < G; ++g)
-      if (take[g]) {
+            bf[ks][t] = *reinterpret_cast<const v8bf*>(&Bs[g][(cb + 16 * t + l16) * LDP + 32 * ks + 8 * kq]);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-          acc[g][0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][0], bf[g][ks][0], acc[g][0][0], 0, 0, 0);
-          acc[g][0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][0], bf[g][ks][1], acc[g][0][1], 0, 0, 0);
-          acc[g][1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][1], bf[g][ks][0], acc[g][1][0], 0, 0, 0);
-          acc[g][1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][1], bf[g][ks][1], acc[g][1][1], 0, 0, 0);
+          acc[g][0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][0], bf[ks][0], acc[g][0][0], 0, 0, 0);
+          acc[g][0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][0], bf[ks][1], acc[g][0][1], 0, 0, 0);
+          acc[g][1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][1], bf[ks][0], acc[g][1][0], 0, 0, 0);
+          acc[g][1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks][1], bf[ks][1], acc[g][1][1], 0, 0, 0);
         }
-        ++pp[g];
       }
+    have = hn;
+    amin = anext;
+#pragma unroll
+    for (int g = 0; g < G; ++g) take[g] = tnext[g];
   }
 #pragma unroll
   for (int g = 0; g < G; ++g)
@@ -305,19 +353,44 @@ __global__ __launch_bounds__(MixCfg<B>::THREADS) void k_numeric_f32(const int64_
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int64_t p = p0; p < p1; ++p) {
+  // both tiles staged once per workgroup in LDS (padded rows: the 16 rows a
+  // fragment read touches fall in different banks); the next pair's tiles
+  // are loaded into registers while the current one is multiplied
+  constexpr int LDP = B + 4;
+  constexpr int NV = B * B / 4 / MixCfg<B>::THREADS;
+  __shared__ __attribute__((aligned(16))) float As[B * LDP];
+  __shared__ __attribute__((aligned(16))) float Bs[B * LDP];
+  v4f sa[NV], sb[NV];
+  auto gload = [&](int64_t p) {
     const BlockPair pr = pairs[p];
-    const float* a = reinterpret_cast<const float*>(pr.a);
-    const float* bt = reinterpret_cast<const float*>(pr.b);
+    const v4f* a = reinterpret_cast<const v4f*>(pr.a);
+    const v4f* bt = reinterpret_cast<const v4f*>(pr.b);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      sa[v] = *gptr(a + threadIdx.x + v * MixCfg<B>::THREADS);
+      sb[v] = *gptr(bt + threadIdx.x + v * MixCfg<B>::THREADS);
+    }
+  };
+  if (p0 < p1) gload(p0);
+  for (int64_t p = p0; p < p1; ++p) {
+    if (p > p0) __syncthreads();  // the previous pair's fragment reads are done
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int q = 4 * ((int)threadIdx.x + v * MixCfg<B>::THREADS);
+      *reinterpret_cast<v4f*>(&As[(q / B) * LDP + q % B]) = sa[v];
+      *reinterpret_cast<v4f*>(&Bs[(q / B) * LDP + q % B]) = sb[v];
+    }
+    __syncthreads();
     v4f af[KB][2], bf[KB][2];
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         const int k0 = 16 * kb + 4 * kq;
-        af[kb][t] = *gptr(reinterpret_cast<const v4f*>(a + (rb + 16 * t + l16) * B + k0));
-        bf[kb][t] = *gptr(reinterpret_cast<const v4f*>(bt + (cb + 16 * t + l16) * B + k0));
+        af[kb][t] = *reinterpret_cast<const v4f*>(&As[(rb + 16 * t + l16) * LDP + k0]);
+        bf[kb][t] = *reinterpret_cast<const v4f*>(&Bs[(cb + 16 * t + l16) * LDP + k0]);
       }
+    if (p + 1 < p1) gload(p + 1);
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
