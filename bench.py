@@ -9,9 +9,14 @@ matrices are not available).
 
 A step is one complete lif_localized call on the resident S (the handle is
 created, S uploaded and truncated, before the timed region).  Output: one
-JSON line.
+JSON line, which also carries the FP32 / BF16 schedules on the chain, RINCH,
+IRSI and the regular-form recursion on the same S, the per-kernel rooflines of
+the leaf factorization and the symbolic phases, the FP64-against-BF16
+comparison on the 20,000-molecule water cluster, and the CPU oracle's time.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline]
+    python bench.py --water-only fp64_sym,bf16_schedule_sym [--water-count N]
+    python bench.py --fit-sweep 30000,35000,40000     (largest cluster that fits)
 """
 from __future__ import annotations
 
@@ -155,16 +160,17 @@ PEAK_TFLOPS = {"FP64": 78.6, "MIXED_FP32": 157.3, "MIXED_BF16": 2500.0}
 def water_comparison(lif, count, which=("fp64_sym", "bf16_schedule_sym", "irsi_fp64_sym", "irsi_bf16_schedule_sym"),
                      z_diff=True, residuals=True):
     """FP64 against the scheduled reduced-precision corrections on a water
-    cluster (tau = 1e-8, b = 64, LIF to 4096-row leaves, paper stop): the
-    metric's comparison, on the compute-bound products where reduced
-    precision pays.  One handle holds S and its memory pool for all runs
+    cluster (tau = 1e-8, b = 64, paper stop; LIF to 4096-row leaves, and
+    IRSI for the "irsi_" variants): the metric's comparison, on the
+    compute-bound products where reduced precision pays.  One handle holds S and its memory pool for all runs
     (lif_set_opts between them): one untimed warm-up per method (LIF, and
     IRSI from c = 1 / sqrt(beta) for the "irsi_" variants), then one timed
     factorization per variant.  Reported per run: seconds, the untruncated
-    residual against the truncated S that was factorized and against S
-    before that truncation (Table 1 leaves open which one it used), node
-    iterations, the leaf-GEMM rate of each precision on its own, the memory
-    peak and, for reduced runs, ||Z - Z_fp64||_F / ||Z_fp64||_F.  A variant
+    residual against the truncated S that was factorized and, for the FP64
+    runs, against S before that truncation (Table 1 leaves open which one it
+    used), node iterations, the leaf-GEMM rate of each precision on its own,
+    the memory peak and, for reduced runs, ||Z - Z_fp64||_F / ||Z_fp64||_F
+    against the same method's FP64 factor.  A variant
     that fails (out of memory, say) is reported with its error."""
     import torch
     from gen import config_matrix
