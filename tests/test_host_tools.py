@@ -52,9 +52,12 @@ def test_profile_summaries(tmp_path):
     _counters(fe, "FETCH_SIZE", 1000.0)
     _counters(wr, "WRITE_SIZE", 500.0)
     # stats: the last factorization only (3 kernels from the second k_chol_scatter)
-    PS.stats(str(tr), str(tmp_path / "s.md"), "T", "C")
+    PS.stats(str(tr), str(tmp_path / "s.md"), "T", "C", groups=("k_numeric_f64", "k_none"))
     text = (tmp_path / "s.md").read_text()
     assert "3 kernels" in text and "| `k_numeric_f64<64, false, false, true>` | 2 | 0.004 |" in text
+    # a group's totals: 2 calls of 2 us each, 4 of the 4.1 us summed; an empty group is left out
+    assert "All `k_numeric_f64*` kernels together: 2 calls, 0.004 ms, average 2.0 us per call, 97.6 %" in text
+    assert "k_none" not in text
     # traffic: counts scaled by the probe's factor 2 (4 MiB counted as 2 MiB)
     PS.traffic(str(fe), str(wr), str(tmp_path / "x.json"), "k_numeric_f64", 4.0, "C", "h")
     t = json.load(open(tmp_path / "x.json"))
